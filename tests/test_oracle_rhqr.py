@@ -1,0 +1,200 @@
+"""Pins of the oracle's RHVector, left/right-looking RHQR, Householder QR and
+recRHQR against LAPACK (via scipy) and against identities the paper proves:
+
+* Thm. 3.1 (simultaneous factorizations): RHQR of W sketched is Householder
+  QR of Psi W, so (R, S, beta) equal LAPACK's geqrf (R, V, tau) of Psi W and T
+  equals geqrt's T.
+* Prop. 3.2: (Psi U)^t Psi U = T^-1 + T^-t, i.e. T = (sut(S^tS) + diag(S^tS)/2)^-1.
+* Alg. 4 output: W = (I - U T S^t Psi)[R; 0], and Psi Q has orthonormal columns.
+* Psi = I: RHQR is Householder QR of W (numpy.linalg.qr's R, U^tU = T^-1+T^-t).
+* Sec. 3.3: ut(T^t S^t Z) = -T U_1^t R, and recRHQR reproduces RHQR's U.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+from scipy.linalg import lapack
+
+from oracle import rhqr, sketch, metrics
+from paper_2405_10923_amd.inputs import test_matrix as make_w
+
+
+def _psi_dense(sk):
+    I = np.eye(sk.n)
+    return sketch.rh_sketch(I, sk)
+
+
+def _woodbury_T(S):
+    G = S.T @ S
+    return np.linalg.inv(np.triu(G, 1) + 0.5 * np.diag(np.diag(G)))
+
+
+@pytest.mark.parametrize("j", [0, 3])
+def test_rh_vector_equals_dlarfg(j):
+    rng = np.random.default_rng(j)
+    n, m, l = 256, 8, 32
+    sk = sketch.Sketch(sketch.SRHT, n, m, l, seed=1)
+    w = rng.standard_normal(n)
+    y = sketch.rh_sketch(w, sk)
+    for sign in (1.0, -1.0):
+        w2 = w.copy()
+        w2[j] = sign * abs(w2[j])
+        y2 = y.copy()
+        y2[j] = w2[j]
+        u, s, sigma, rho, beta, alpha, ok = rhqr.rh_vector(w2, y2, j, "B")
+        # dlarfg(n, alpha, x): H (alpha; x) = (beta; 0), H = I - tau v v^t, v = (1; x_out)
+        bet, xout, tau = lapack.dlarfg(len(y2) - j, y2[j], y2[j + 1:].copy())
+        assert np.isclose(-sigma * rho, bet, rtol=1e-15, atol=0)
+        assert np.isclose(beta, tau, rtol=1e-15, atol=0)
+        assert s[j] == 1.0 and np.all(s[:j] == 0)
+        assert np.allclose(s[j + 1:], xout, rtol=1e-14, atol=0)
+        # u and s are consistent: s = RHSketch(u)
+        assert np.allclose(sketch.rh_sketch(u, sk), s, rtol=0, atol=1e-14 * np.linalg.norm(s))
+        assert np.isclose(2.0 / np.sum(s * s), beta, rtol=1e-14)
+
+
+def test_rh_vector_scaling_a():
+    rng = np.random.default_rng(0)
+    n, m, l = 128, 4, 16
+    sk = sketch.Sketch(sketch.SRHT, n, m, l, seed=3)
+    w = rng.standard_normal(n)
+    y = sketch.rh_sketch(w, sk)
+    u, s, sigma, rho, beta, alpha, ok = rhqr.rh_vector(w, y, 1, "A")
+    assert beta == 1.0 and np.isclose(np.sum(s * s), 2.0, rtol=1e-15)
+    uB, sB, *_ = rhqr.rh_vector(w, y, 1, "B")
+    # same reflector direction (Prop. 3.1, item 1: P(lambda z) = P(z))
+    assert np.allclose(u / u[1], uB, rtol=1e-14, atol=1e-16)
+
+
+@pytest.mark.parametrize("kind", [sketch.SRHT, sketch.GAUSS])
+def test_rhqr_left_equals_lapack_qr_of_sketch(kind):
+    n, m, l = 600, 12, 48
+    W = make_w(n, m, 2, seed=4)
+    sk = sketch.Sketch(kind, n, m, l, seed=7)
+    out = rhqr.rhqr_left(W, sk)
+    Z = sketch.rh_sketch(W, sk)
+    (qr, tau), _ = scipy.linalg.qr(Z, mode="raw")
+    V = np.tril(qr[:, :m], -1)
+    V[np.arange(m), np.arange(m)] = 1.0
+    Rl = np.triu(qr[:m, :m])
+    sc = np.max(np.abs(Rl))
+    assert np.allclose(out["R"], Rl, rtol=0, atol=1e-13 * sc)        # signs included
+    assert np.allclose(out["S"], V, rtol=0, atol=1e-12)
+    assert np.allclose(out["beta"], tau, rtol=1e-12, atol=0)
+    # T against LAPACK's compact-WY T (geqrt, one block)
+    _, Tg, _ = lapack.dgeqrt(m, Z)
+    assert np.allclose(out["T"], Tg, rtol=0, atol=1e-12)
+    # Woodbury identity of Prop. 3.2
+    assert np.allclose(out["T"], _woodbury_T(out["S"]), rtol=0, atol=1e-11)
+
+
+def test_rhqr_left_compact_form_and_sketch_orthogonality():
+    n, m, l = 700, 10, 40
+    W = make_w(n, m, 6, seed=5)
+    sk = sketch.Sketch(sketch.SRHT, n, m, l, seed=2)
+    out = rhqr.rhqr_left(W, sk)
+    U, S, T, R = out["U"], out["S"], out["T"], out["R"]
+    Psi = _psi_dense(sk)
+    assert np.allclose(S, Psi @ U, rtol=0, atol=1e-13)                 # S = Psi U
+    E = np.zeros((n, m))
+    E[:m] = R
+    Wrec = E - U @ (T @ (S.T @ (Psi @ E)))                              # (I - U T S^t Psi)[R;0]
+    assert np.linalg.norm(W - Wrec) <= 1e-14 * np.linalg.norm(W) * m
+    Q = rhqr.thin_q(U, T, m)
+    assert metrics.fact_error(W, Q, R) < 1e-14
+    assert metrics.orth_error(Psi @ Q) < 1e-13
+    assert np.allclose(np.triu(U[:m]), np.eye(m))                      # U_1 unit lower
+
+
+def test_identity_sketch_is_householder_qr():
+    n, m = 80, 9
+    W = make_w(n, m, 3, seed=6)
+    sk = sketch.Sketch(sketch.IDENTITY, n, m, 0)
+    out = rhqr.rhqr_left(W, sk)
+    _, Rn = np.linalg.qr(W)
+    assert np.allclose(out["R"], Rn, rtol=0, atol=1e-13)
+    U, T = out["U"], out["T"]
+    Ti = np.linalg.inv(T)
+    assert np.allclose(U.T @ U, Ti + Ti.T, rtol=0, atol=1e-11)
+    Q = rhqr.thin_q(U, T, m)
+    assert np.allclose(Q.T @ Q, np.eye(m), atol=1e-14)
+
+
+def test_hqr_equals_lapack():
+    Z = np.random.default_rng(8).standard_normal((70, 12))
+    V, T, R = rhqr.hqr(Z)
+    (qr, tau), _ = scipy.linalg.qr(Z, mode="raw")
+    assert np.allclose(R, np.triu(qr[:12, :12]), rtol=0, atol=1e-13)
+    assert np.allclose(np.tril(V[:, :12], -1), np.tril(qr, -1)[:, :12], atol=1e-13)
+    _, Tg, _ = lapack.dgeqrt(12, Z)
+    assert np.allclose(T, Tg, atol=1e-13)
+
+
+def test_right_and_left_looking_agree():
+    n, m, l = 500, 8, 32
+    W = make_w(n, m, 2, seed=9)
+    sk = sketch.Sketch(sketch.SRHT, n, m, l, seed=4)
+    a = rhqr.rhqr_left(W, sk)
+    b = rhqr.rhqr_right(W, sk)
+    assert np.allclose(a["U"], b["U"], rtol=0, atol=1e-12)
+    assert np.allclose(a["R"], b["R"], rtol=0, atol=1e-12 * np.abs(a["R"]).max())
+    assert np.allclose(a["S"], b["S"], rtol=0, atol=1e-12)
+
+
+def test_rec_rhqr_identities():
+    n, m, l = 800, 10, 40
+    W = make_w(n, m, 2, seed=10)
+    sk = sketch.Sketch(sketch.SRHT, n, m, l, seed=5)
+    rec = rhqr.rec_rhqr(W, sk, "M")
+    left = rhqr.rhqr_left(W, sk)
+    U1 = rec["S"][:m]
+    M_closed = -rec["T"] @ U1.T @ rec["R"]                     # Sec. 3.3
+    assert np.allclose(rec["M"], M_closed, rtol=0, atol=1e-13 * np.abs(M_closed).max())
+    assert np.allclose(np.diag(rec["M"]), left["alpha"], rtol=1e-12)  # alpha_j on the diagonal
+    assert np.allclose(rec["U"], left["U"], rtol=0, atol=1e-11)
+    assert np.allclose(rec["Q"], rhqr.thin_q(left["U"], left["T"], m), atol=1e-11)
+    chol = rhqr.rec_rhqr(W, sk, "R")
+    assert np.allclose(chol["Q"], rec["Q"], atol=1e-10)
+    assert metrics.fact_error(W, rec["Q"], rec["R"]) < 1e-14
+
+
+def test_ill_conditioned_bounds():
+    # Thm. factoerror / conditionnumberQ: accuracy independent of cond(W)
+    n, m, l = 2000, 24, 96
+    W = make_w(n, m, 12, seed=11)
+    sk = sketch.Sketch(sketch.SRHT, n, m, l, seed=6)
+    out = rhqr.rhqr_left(W, sk)
+    Q = rhqr.thin_q(out["U"], out["T"], m)
+    PsiQ = sketch.rh_sketch(Q, sk)
+    assert metrics.fact_error(W, Q, out["R"]) < 1e-14
+    assert metrics.orth_error(PsiQ) < 1e-13
+    eps = metrics.embedding_distortion(lambda X: sketch.rh_sketch(X, sk), Q)
+    assert metrics.cond(Q) <= (1 + eps) / (1 - eps) * (1 + 1e-10)
+
+
+def test_rank_deficient_gives_identity_reflector():
+    n, m, l = 300, 5, 20
+    W = make_w(n, m, 1, seed=12)
+    W[:, 3] = W[:, 1]                          # duplicate column
+    W[:, 3] += 0.0
+    sk = sketch.Sketch(sketch.SRHT, n, m, l, seed=1)
+    out = rhqr.rhqr_left(W, sk)
+    # the duplicated column is eliminated exactly only in exact arithmetic; in
+    # floating point it leaves a rounding-size residual.  Force an exact zero:
+    W0 = W.copy()
+    W0[:, 2] = 0.0
+    out0 = rhqr.rhqr_left(W0[:, :3], sketch.Sketch(sketch.SRHT, n, 3, l, seed=1))
+    assert out0["info"] == 3 and out0["R"][2, 2] == 0.0 and out0["T"][2, 2] == 0.0
+    assert np.abs(out["R"][3, 3]) < 1e-12 * np.abs(out["R"][0, 0])
+
+
+def test_column_scale_equivariance():
+    # Prop. 3.1 item 1 (P(lambda z) = P(z)): scaling columns by powers of two
+    # scales R's columns and leaves U, S, T unchanged, exactly.
+    n, m, l = 400, 6, 24
+    W = make_w(n, m, 4, seed=13)
+    d = 2.0 ** np.array([3, -5, 0, 7, -2, 1])
+    sk = sketch.Sketch(sketch.SRHT, n, m, l, seed=2)
+    a = rhqr.rhqr_left(W, sk)
+    b = rhqr.rhqr_left(W * d, sk)
+    assert np.array_equal(a["U"], b["U"]) and np.array_equal(a["T"], b["T"])
+    assert np.array_equal(a["R"] * d, b["R"])
