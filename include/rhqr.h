@@ -1,0 +1,184 @@
+/*
+ * rhqr.h -- C ABI of the MI355X (gfx950) randomized Householder QR library.
+ *
+ * Method: L. Grigori, E. Timsit, "Randomized Householder QR", arXiv 2405.10923.
+ * The library factors a tall-skinny W (n x m, m << n) as
+ *     W = (I_n - U T (Psi U)^t Psi) [R; 0] = Q R,      (Psi Q)^t (Psi Q) = I_m,
+ * where Psi = [I_m 0; 0 Omega] (eq. psi, Sec. 3.1) keeps the first m rows and
+ * sketches the remaining n-m rows with an l x (n-m) embedding Omega (Sec. 2.3).
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are column-major with an explicit leading dimension (ld >= rows).
+ *  - Pointers named d_* are device pointers (HBM), pointers named h_* are host
+ *    pointers.  The caller owns every input and output buffer; the library
+ *    allocates device memory only inside the handles it creates (freed by the
+ *    matching *_destroy) and never retains caller pointers after a call.
+ *  - n-row data (W, U, Q, X) is stored in the element type `dtype`
+ *    (RHQR_F64/F32/F16/BF16).  Sketch-space data (Psi X, S = Psi U, T, R, H)
+ *    is always float64 -- the paper keeps the low-dimensional operations in
+ *    high precision (Sec. 8, mixed-precision experiment).
+ *  - Arithmetic on n-row data runs in float64 for RHQR_F64 and in float32 for
+ *    the other types (FP32 accumulation).
+ *  - Every call is asynchronous on `stream` (a hipStream_t, NULL = the null
+ *    stream) unless stated otherwise; arguments are validated synchronously,
+ *    before anything is launched.
+ *  - Return value: RHQR_OK (0) on success; -i if argument i (1-based) is
+ *    invalid; RHQR_ERR_HIP if a HIP call failed; RHQR_ERR_WORKSPACE if the
+ *    workspace is too small.  Numerical breakdown is not an error return; it is
+ *    reported through rhqr_status (below).
+ */
+#ifndef RHQR_H
+#define RHQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RHQR_OK = 0,
+  RHQR_ERR_HIP = -1000,
+  RHQR_ERR_WORKSPACE = -1001,
+  RHQR_ERR_UNSUPPORTED = -1002
+};
+
+typedef enum { RHQR_F64 = 0, RHQR_F32 = 1, RHQR_F16 = 2, RHQR_BF16 = 3 } rhqr_dtype;
+
+/* Sketch kinds (Sec. 2.3). */
+typedef enum {
+  RHQR_SKETCH_SRHT = 0,   /* Omega = sqrt(N/l) P H D on R^N, N = 2^ceil(log2 n) */
+  RHQR_SKETCH_GAUSS = 1   /* Omega = G / sqrt(l), G iid N(0,1), stored densely  */
+} rhqr_sketch_kind;
+
+/* Reflector scaling of RHVector (Alg. 2, scaling line). */
+typedef enum {
+  RHQR_SCALE_UNIT_PIVOT = 0, /* u_jj = 1,  beta = |gamma| / rho  (LAPACK-like) */
+  RHQR_SCALE_SQRT2 = 1       /* ||Psi u||^2 = 2,  beta = 1                     */
+} rhqr_scaling;
+
+/* recRHQR modes (Alg. 6 and its comparator of Sec. 8). */
+typedef enum {
+  RHQR_REC_M = 0,      /* U_2 = W_2 ut(T^t S^t Psi W)^-1, Q = [I;0] - U T U_1^t */
+  RHQR_REC_RCHOL = 1   /* Q = W R^-1 (randomized Cholesky QR)                    */
+} rhqr_rec_mode;
+
+typedef struct rhqr_sketch_s *rhqr_sketch_t;
+typedef struct rhqr_arnoldi_s *rhqr_arnoldi_t;
+
+/* ------------------------------------------------------------------------
+ * Sketch handle.  Draws Psi for problems with n rows and an m-row head.
+ *   kind   : RHQR_SKETCH_SRHT or RHQR_SKETCH_GAUSS
+ *   n, m, l: 0 < m < n, 0 < l <= N (SRHT; l <= 4096) or l >= 1 (GAUSS)
+ *   seed   : Philox4x64-10 key word 0 (key word 1 selects the stream)
+ *   d_omega: GAUSS only, optional caller-supplied l x (n-m) float64 Omega
+ *            (ld_omega >= l); it is copied.  NULL: Omega is drawn on the
+ *            device from the seed (Box-Muller, entries N(0, 1/l)).
+ * The draw (random signs, the l sampled rows, or Omega) runs on the device,
+ * on `stream`; the call synchronises `stream` before it returns.
+ * Passage: Sec. 2.3 (Gaussian and SRHT embeddings), eq. psi.
+ * ---------------------------------------------------------------------- */
+int rhqr_sketch_create(int kind, int64_t n, int32_t m, int32_t l, uint64_t seed,
+                       const double *d_omega, int64_t ld_omega, void *stream,
+                       rhqr_sketch_t *out);
+int rhqr_sketch_destroy(rhqr_sketch_t h);
+
+/* Copies of the draw, for inspection: h_signs receives ceil(N/64) words (bit
+ * i%64 of word i/64 set <=> D_ii = -1), h_rows the l sampled rows (int32,
+ * increasing).  GAUSS: h_omega receives l x (n-m) entries (ld = l).  Any
+ * pointer may be NULL.  Synchronous. */
+int rhqr_sketch_get(rhqr_sketch_t h, uint64_t *h_signs, int32_t *h_rows, double *h_omega);
+int rhqr_sketch_info(rhqr_sketch_t h, int64_t *n, int32_t *m, int32_t *l, int64_t *N, int32_t *kind);
+
+/* ------------------------------------------------------------------------
+ * rhqr_sketch: Y = Psi X  (RHSketch, Alg. 1).
+ *   X  : n x k in dtype (ldx >= n), device;  Y: (l+m) x k float64 (ldy >= l+m)
+ *   n must equal the handle's n.  ws: device workspace of at least
+ *   rhqr_sketch_workspace_size(h, k) bytes.
+ * SRHT order as Lemma srht: signs, Walsh-Hadamard transform, sampling; the
+ * normalisation sqrt(N/l) * N^-1/2 = l^-1/2 is applied once to the samples.
+ * ---------------------------------------------------------------------- */
+size_t rhqr_sketch_workspace_size(rhqr_sketch_t h, int32_t k);
+int rhqr_sketch(rhqr_sketch_t h, int dtype, int64_t n, int32_t k, const void *d_X,
+                int64_t ldx, double *d_Y, int64_t ldy, void *d_ws, size_t ws_bytes,
+                void *stream);
+
+/* ------------------------------------------------------------------------
+ * rhqr_factor: left-looking RHQR (Alg. 4) with RHVector (Alg. 2).
+ *   d_W   : n x m in dtype, overwritten by U (unit lower-trapezoidal in the
+ *           UNIT_PIVOT scaling).  The head m x m block of U is also in S.
+ *   d_S   : (l+m) x m float64, S = Psi U
+ *   d_T   : m x m float64, upper triangular; I - U T S^t Psi = P_1 ... P_m
+ *   d_R   : m x m float64, upper triangular
+ *   d_Q   : optional n x m thin Q factor in dtype (NULL to skip),
+ *           Q = [I_m; 0] - U T U_1^t (Sec. 3.2)
+ *   scaling: rhqr_scaling
+ *   d_ws  : device workspace, >= rhqr_factor_workspace_size(h, dtype, m) bytes
+ * One synchronisation per column: the refreshed column's sketch (Alg. 4).
+ * Breakdown (rho_j = 0) gives an identity reflector (beta_j = 0, R_jj = 0) and
+ * is reported by rhqr_status.
+ * ---------------------------------------------------------------------- */
+size_t rhqr_factor_workspace_size(rhqr_sketch_t h, int dtype, int32_t m);
+int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W, int64_t ldw,
+                double *d_S, int64_t lds, double *d_T, int64_t ldt, double *d_R,
+                int64_t ldr, void *d_Q, int64_t ldq, int scaling, void *d_ws,
+                size_t ws_bytes, void *stream);
+
+/* Status of the last rhqr_factor / recrhqr_factor / Arnoldi call that used
+ * this workspace: 0, or j (1-based) of the first column with rho_j = 0.
+ * Synchronises `stream`. */
+int rhqr_status(const void *d_ws, void *stream, int32_t *h_info);
+
+/* ------------------------------------------------------------------------
+ * recrhqr_factor: recRHQR (Alg. 6), one synchronisation.
+ *   Z = Psi W; Householder QR of Z on the device in float64 gives S, T, R;
+ *   mode RHQR_REC_M: U_2 solves W_2 = U_2 ut(T^t S^t Z) (row-wise forward
+ *   substitution), U_1 = S_{1:m}; Q (optional) = [I;0] - U T U_1^t.
+ *   mode RHQR_REC_RCHOL: Q = W R^-1 (d_U may be NULL).
+ *   d_W is read only; d_U (n x m, dtype) receives U; d_Q optional.
+ * ---------------------------------------------------------------------- */
+size_t recrhqr_workspace_size(rhqr_sketch_t h, int dtype, int32_t m);
+int recrhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, const void *d_W,
+                   int64_t ldw, void *d_U, int64_t ldu, double *d_S, int64_t lds,
+                   double *d_T, int64_t ldt, double *d_R, int64_t ldr, void *d_Q,
+                   int64_t ldq, int mode, void *d_ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * RHQR-Arnoldi (Alg. 7).  The operator stays with the caller.
+ *   rhqr_arnoldi_create: state for up to mmax Arnoldi steps; the sketch handle
+ *     must have head m = mmax + 1.  The basis U ((n x (mmax+1)), dtype) lives in
+ *     the state (device memory owned by the state).
+ *   rhqr_arnoldi_start(r0): r0 = b - A x0 (n, dtype, device).  Forms u_1, and
+ *     writes q_1 (n, dtype, device) and beta = (h_0)_1 (host, synchronous).
+ *   rhqr_arnoldi_step(w): w = A q_j (n, dtype, device) for the current j.
+ *     Applies the j reflectors to w, forms u_{j+1}, writes h_j (mmax+1 float64,
+ *     device; rows > j+1 zero) and q_{j+1} (n, dtype, device).
+ *   rhqr_arnoldi_solution: x += Q_j y for y (j float64, device): x (n, dtype).
+ * ---------------------------------------------------------------------- */
+int rhqr_arnoldi_create(rhqr_sketch_t h, int dtype, int64_t n, int32_t mmax, void *stream,
+                        rhqr_arnoldi_t *out);
+int rhqr_arnoldi_destroy(rhqr_arnoldi_t a);
+int rhqr_arnoldi_start(rhqr_arnoldi_t a, const void *d_r0, void *d_q1, double *h_beta,
+                       void *stream);
+int rhqr_arnoldi_step(rhqr_arnoldi_t a, const void *d_w, void *d_qnext, double *d_hcol,
+                      void *stream);
+int rhqr_arnoldi_solution(rhqr_arnoldi_t a, int32_t j, const double *d_y, void *d_x,
+                          void *stream);
+int rhqr_arnoldi_basis(rhqr_arnoldi_t a, void **d_U, double **d_S, double **d_T);
+
+/* ------------------------------------------------------------------------
+ * Measurement aid.  Between rhqr_profile_begin() and rhqr_profile_end(), every
+ * launch of the tall-update kernel (the per-column refresh + re-sketch pass of
+ * rhqr_factor / recrhqr_factor) is bracketed by HIP events recorded on the
+ * launching stream.  rhqr_profile_end synchronises those events and returns
+ * the summed kernel time (ms) and the number of launches.  Host-side state,
+ * not thread-safe; intended for benchmarks.
+ * ---------------------------------------------------------------------- */
+int rhqr_profile_begin(void);
+int rhqr_profile_end(double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RHQR_H */

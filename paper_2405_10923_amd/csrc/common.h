@@ -1,0 +1,135 @@
+// Shared definitions of the gfx950 RHQR library (device helpers, handle layout).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/rhqr.h"
+
+#define RHQR_HIP(x)                                   \
+  do {                                                \
+    hipError_t e_ = (x);                              \
+    if (e_ != hipSuccess) return RHQR_ERR_HIP;        \
+  } while (0)
+
+// Internal sketch kind: Psi = I (used for the sketch-space Householder QR of
+// recRHQR, where the "n-row" matrix is the (l+m) x m sketch itself).
+enum { RHQR_SKETCH_IDENT = 2 };
+
+// Walsh-Hadamard tile: the SRHT of R^N is split as H_N = H_{N/TILE} (x) H_TILE;
+// a workgroup transforms one aligned block of TILE coordinates in LDS and only
+// the l sampled outputs leave the workgroup.
+constexpr int TILE_LOG = 12;
+constexpr int TILE = 1 << TILE_LOG;
+constexpr int TILE_PAD = TILE + TILE / 16;  // one pad slot per 16 entries
+__device__ __forceinline__ int tpad(int i) { return i + (i >> 4); }
+
+struct rhqr_sketch_s {
+  int kind;
+  int64_t n;
+  int32_t m;
+  int32_t l;
+  uint64_t seed;
+  int64_t N;          // 2^ceil(log2 n)
+  uint64_t *d_signs;  // ceil(N/64) words (SRHT)
+  int32_t *d_rows;    // l sampled rows, increasing (SRHT)
+  double *d_omega;    // l x (n-m), ld = l (GAUSS)
+  int device;
+};
+
+// ---------------------------------------------------------------- dtypes
+template <typename ST> struct CompT { using type = float; };
+template <> struct CompT<double> { using type = double; };
+
+template <typename CT> __device__ __forceinline__ CT cvt_in(double x) { return (CT)x; }
+template <typename CT> __device__ __forceinline__ CT cvt_in(float x) { return (CT)x; }
+template <typename CT> __device__ __forceinline__ CT cvt_in(__half x) { return (CT)__half2float(x); }
+template <typename CT> __device__ __forceinline__ CT cvt_in(__hip_bfloat16 x) { return (CT)__bfloat162float(x); }
+
+template <typename ST> __device__ __forceinline__ ST cvt_out(double x);
+template <> __device__ __forceinline__ double cvt_out<double>(double x) { return x; }
+template <> __device__ __forceinline__ float cvt_out<float>(double x) { return (float)x; }
+template <> __device__ __forceinline__ __half cvt_out<__half>(double x) { return __float2half((float)x); }
+template <> __device__ __forceinline__ __hip_bfloat16 cvt_out<__hip_bfloat16>(double x) { return __float2bfloat16((float)x); }
+
+inline size_t dtype_size(int dt) {
+  switch (dt) {
+    case RHQR_F64: return 8;
+    case RHQR_F32: return 4;
+    case RHQR_F16: return 2;
+    case RHQR_BF16: return 2;
+  }
+  return 0;
+}
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- reductions
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over a workgroup; `red` is LDS scratch of >= blockDim.x/64 entries.
+// Every thread returns the total.  Fixed order: deterministic.
+template <typename T> __device__ T block_sum(T v, T *red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  T s = 0;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+// ---------------------------------------------------------------- FWHT
+// In-place unnormalised Walsh-Hadamard transform (natural order) of TILE
+// values held in LDS at padded positions tpad(i).  Three radix-16 passes over
+// bit groups [0,4), [4,8), [8,12); each of 256 threads owns one group of 16.
+template <typename A> __device__ __forceinline__ void fwht16(A v[16]) {
+#pragma unroll
+  for (int h = 1; h < 16; h <<= 1) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if ((k & h) == 0) {
+        A a = v[k], b = v[k + h];
+        v[k] = a + b;
+        v[k + h] = a - b;
+      }
+    }
+  }
+}
+
+template <typename A> __device__ void fwht_tile_lds(A *s) {
+#pragma unroll 1
+  for (int pass = 0; pass < 3; ++pass) {
+    __syncthreads();
+    const int sh = 4 * pass;
+    for (int g = threadIdx.x; g < TILE / 16; g += blockDim.x) {
+      const int lo = g & ((1 << sh) - 1);
+      const int hi = g >> sh;
+      const int base = lo + (hi << (sh + 4));
+      A v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = s[tpad(base + (k << sh))];
+      fwht16(v);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s[tpad(base + (k << sh))] = v[k];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool sign_bit(const uint64_t *signs, int64_t i) {
+  return (signs[i >> 6] >> (i & 63)) & 1ull;
+}
+
+// ---------------------------------------------------------------- host side
+int sketch_tail_partials_size(const rhqr_sketch_s *h, int32_t k, int *gt_out, size_t *bytes_out);
+int launch_sketch(const rhqr_sketch_s *h, int dtype, int64_t n, int32_t k, const void *X,
+                  int64_t ldx, double *Y, int64_t ldy, void *ws, size_t ws_bytes,
+                  hipStream_t st);
+size_t sketch_ws_bytes(const rhqr_sketch_s *h, int32_t k);

@@ -1,0 +1,54 @@
+// Column-loop engine of left-looking RHQR (Alg. 4) shared by rhqr_factor,
+// recrhqr_factor (its sketch-space Householder QR runs the same loop with
+// Psi = I) and the batched entry point.
+#pragma once
+#include "common.h"
+
+struct LoopWs {
+  int32_t *status;   // first column with rho_j = 0 (1-based), 0 if none
+  double *y;         // (l+m) sketch of the refreshed column
+  double *sq;        // per-workgroup partial sums of squares
+  double *dpart;     // [G_ss][m] partial S^t s_j
+  double *epart;     // [G_ss][m] partial S^t z_{j+1}
+  double *scal;      // [m][4]: sigma, rho, alpha, beta
+  double *c;         // c_{j+1} = T_j^t S_j^t z_{j+1}
+  double *cf;        // c with the pending 1/alpha of the raw column folded in
+  double *ia;        // [m] 1/alpha_j applied when u_j is stored
+  double *Tt;        // m x m transpose of T (ld m)
+  double *part;      // [ntiles][l] per-tile sketch partials
+  float *wstage;     // n-vector staging of the raw refreshed column (low precision)
+  void *skws;        // workspace of the multi-column pre-sketch
+  size_t skws_bytes;
+};
+
+struct LoopArgs {
+  int kind;           // RHQR_SKETCH_SRHT / GAUSS / IDENT
+  int dtype;
+  int64_t n;
+  int32_t m, l;
+  void *W;
+  int64_t ldw;
+  const double *Z;    // (l+m) x m pre-sketch (may alias W for IDENT)
+  int64_t ldz;
+  double *S;
+  int64_t lds;
+  double *T;
+  int64_t ldt;
+  double *R;
+  int64_t ldr;
+  int scaling;
+  const uint64_t *signs;
+  const int32_t *rows;
+  const double *omega;  // l x (n-m), ld l
+};
+
+size_t loop_ws_bytes(int kind, int dtype, int64_t n, int32_t m, int32_t l);
+int loop_ws_carve(void *ws, size_t bytes, int kind, int dtype, int64_t n, int32_t m, int32_t l,
+                  LoopWs *out);
+int run_column_loop(const LoopArgs &a, const LoopWs &w, hipStream_t st);
+int launch_thin_q(int dtype, int64_t n, int32_t m, const void *U, int64_t ldu, const double *S,
+                  int64_t lds, const double *T, int64_t ldt, double *Mq, void *Q, int64_t ldq,
+                  hipStream_t st);
+int launch_fill(void *p, size_t bytes, hipStream_t st);
+
+constexpr int RED_CHUNK = 64;  // outputs per reduction workgroup

@@ -1,0 +1,805 @@
+// Left-looking RHQR column loop (Alg. 4 with RHVector, Alg. 2) on gfx950.
+//
+// Per column j (0-based) the n-row work is one streaming pass (k_tall):
+//     w~_j = w_j - U_{:, <j} c_j                         (refresh, Alg. 4)
+//     u_{j-1} = w~_{j-1} / alpha_{j-1}  stored           (deferred scaling)
+//     per-tile partials of Omega w~_j                    (re-sketch)
+// followed by three small kernels in float64 (the single synchronisation):
+//     k_red : reduce the tile partials to y = Psi w~_j, head rows refreshed
+//             in float64 from U_1 = S_{1:m}
+//     k_ss  : RHVector scalars (sigma, rho, gamma, beta), s_j, R_{:,j}, and
+//             partial dot products S^t s_j and S^t z_{j+1}
+//     k_fin : T_{:,j} = -beta T_{j-1} S^t s_j and c_{j+1} = T_j^t S_j^t z_{j+1}
+//
+// Tall data is column-major in the storage type ST (double, float, half,
+// bfloat16); arithmetic on it runs in CT = double for double storage and float
+// otherwise.  The raw refreshed column is kept in float64 in place (ST=double)
+// or in a float32 staging vector (low precision) until alpha_j is known, and
+// the division by alpha_j is folded into the next pass's coefficient.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+#include <vector>
+
+namespace {
+
+constexpr int MAXM = 1024;  // largest m the sketch-space kernels support
+
+// Optional timing of the tall-update launches with HIP events recorded on the
+// launching stream (rhqr_profile_begin / rhqr_profile_end).
+struct TallProfile {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  size_t used = 0;
+};
+TallProfile g_prof;
+
+int prof_pair(hipEvent_t *a, hipEvent_t *b) {
+  if (g_prof.used + 2 > g_prof.ev.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      RHQR_HIP(hipEventCreate(&e));
+      g_prof.ev.push_back(e);
+    }
+  }
+  *a = g_prof.ev[g_prof.used];
+  *b = g_prof.ev[g_prof.used + 1];
+  g_prof.used += 2;
+  return RHQR_OK;
+}
+
+// -------------------------------------------------------------- 16-byte I/O
+template <typename ST, typename CT>
+__device__ __forceinline__ void vload(const ST *p, CT *o) {
+  const uint4 u = *reinterpret_cast<const uint4 *>(p);
+  if constexpr (sizeof(ST) == 8) {
+    o[0] = (CT)__hiloint2double((int)u.y, (int)u.x);
+    o[1] = (CT)__hiloint2double((int)u.w, (int)u.z);
+  } else if constexpr (sizeof(ST) == 4) {
+    o[0] = (CT)__uint_as_float(u.x);
+    o[1] = (CT)__uint_as_float(u.y);
+    o[2] = (CT)__uint_as_float(u.z);
+    o[3] = (CT)__uint_as_float(u.w);
+  } else {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const unsigned short b = (unsigned short)(w[k >> 1] >> (16 * (k & 1)));
+      if constexpr (std::is_same<ST, __half>::value)
+        o[k] = (CT)__half2float(__ushort_as_half(b));
+      else
+        o[k] = (CT)__uint_as_float(((uint32_t)b) << 16);
+    }
+  }
+}
+
+template <typename ST> __device__ __forceinline__ unsigned short enc16(float v) {
+  if constexpr (std::is_same<ST, __half>::value)
+    return __half_as_ushort(__float2half(v));
+  else
+    return __bfloat16_as_ushort(__float2bfloat16(v));
+}
+
+template <typename ST, typename CT>
+__device__ __forceinline__ void vstore(ST *p, const CT *v) {
+  uint4 u;
+  if constexpr (sizeof(ST) == 8) {
+    const double a = (double)v[0], b = (double)v[1];
+    u.x = (uint32_t)__double2loint(a);
+    u.y = (uint32_t)__double2hiint(a);
+    u.z = (uint32_t)__double2loint(b);
+    u.w = (uint32_t)__double2hiint(b);
+  } else if constexpr (sizeof(ST) == 4) {
+    u.x = __float_as_uint((float)v[0]);
+    u.y = __float_as_uint((float)v[1]);
+    u.z = __float_as_uint((float)v[2]);
+    u.w = __float_as_uint((float)v[3]);
+  } else {
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      w[k] = (uint32_t)enc16<ST>((float)v[2 * k]) | ((uint32_t)enc16<ST>((float)v[2 * k + 1]) << 16);
+    u.x = w[0];
+    u.y = w[1];
+    u.z = w[2];
+    u.w = w[3];
+  }
+  *reinterpret_cast<uint4 *>(p) = u;
+}
+
+// ------------------------------------------------------------------ k_tall
+// One workgroup per TILE rows.  Thread t owns rows base + VEC*(t + 256 v) + e.
+template <typename ST, int KIND, bool INTERIOR>
+__device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
+                                          int32_t j, const double *__restrict__ cf,
+                                          double iaprev, float *__restrict__ wstage,
+                                          int64_t base,
+                                          typename CompT<ST>::type (&acc)[(TILE / 256) / (16 / sizeof(ST))][16 / sizeof(ST)]) {
+  using CT = typename CompT<ST>::type;
+  constexpr int VEC = 16 / sizeof(ST);
+  constexpr int NV = (TILE / 256) / VEC;
+  constexpr bool LOWP = !std::is_same<ST, double>::value;
+  const int tid = threadIdx.x;
+  auto row = [&](int v) { return base + (int64_t)VEC * (tid + 256 * v); };
+  auto ok = [&](int64_t i) { return i >= m && i < n; };
+
+  // acc <- w_j
+  const ST *wj = W + (int64_t)j * ldw;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int64_t i0 = row(v);
+    if (INTERIOR) {
+      vload(wj + i0, acc[v]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[v][e] = ok(i0 + e) ? cvt_in<CT>(wj[i0 + e]) : (CT)0;
+    }
+  }
+  // acc -= U_{:, <j-1} c (columns already scaled).  Interior tiles address each
+  // column through a uniform base pointer plus 32-bit per-thread offsets.
+  if (INTERIOR) {
+    uint32_t off[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) off[v] = (uint32_t)((row(v) - base) * (int64_t)sizeof(ST));
+#pragma unroll 1
+    for (int p = 0; p < j - 1; ++p) {
+      const CT cp = (CT)cf[p];
+      const char *cb = (const char *)(W + (int64_t)p * ldw + base);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        CT x[VEC];
+        vload((const ST *)(cb + off[v]), x);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[v][e] -= x[e] * cp;
+      }
+    }
+  } else {
+#pragma unroll 1
+    for (int p = 0; p < j - 1; ++p) {
+      const CT cp = (CT)cf[p];
+      const ST *col = W + (int64_t)p * ldw;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int64_t i0 = row(v);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (ok(i0 + e)) acc[v][e] -= cvt_in<CT>(col[i0 + e]) * cp;
+      }
+    }
+  }
+  // previous column: raw refreshed values, scaled by 1/alpha_{j-1} and stored
+  if (j >= 1) {
+    const CT cp = (CT)cf[j - 1];
+    const CT ia = (CT)iaprev;
+    ST *col = W + (int64_t)(j - 1) * ldw;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int64_t i0 = row(v);
+      CT x[VEC], o[VEC];
+      // column 0 is never refreshed: its raw values are the input itself
+      if (LOWP && j >= 2) {
+        if (INTERIOR) {
+          const float4 *ws4 = reinterpret_cast<const float4 *>(wstage + i0);
+#pragma unroll
+          for (int h = 0; h < VEC / 4; ++h) {
+            const float4 f = ws4[h];
+            x[4 * h] = f.x;
+            x[4 * h + 1] = f.y;
+            x[4 * h + 2] = f.z;
+            x[4 * h + 3] = f.w;
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) x[e] = ok(i0 + e) ? (CT)wstage[i0 + e] : (CT)0;
+        }
+      } else {
+        if (INTERIOR) {
+          vload(col + i0, x);
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) x[e] = ok(i0 + e) ? cvt_in<CT>(col[i0 + e]) : (CT)0;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        acc[v][e] -= x[e] * cp;
+        o[e] = x[e] * ia;
+      }
+      if (INTERIOR) {
+        vstore(col + i0, o);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (ok(i0 + e)) col[i0 + e] = cvt_out<ST>((double)o[e]);
+      }
+    }
+  }
+  // store the raw refreshed column
+  ST *wjw = W + (int64_t)j * ldw;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int64_t i0 = row(v);
+    if (LOWP) {
+      if (INTERIOR) {
+        float4 *ws4 = reinterpret_cast<float4 *>(wstage + i0);
+#pragma unroll
+        for (int h = 0; h < VEC / 4; ++h)
+          ws4[h] = make_float4((float)acc[v][4 * h], (float)acc[v][4 * h + 1],
+                               (float)acc[v][4 * h + 2], (float)acc[v][4 * h + 3]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (ok(i0 + e)) wstage[i0 + e] = (float)acc[v][e];
+      }
+    } else {
+      if (INTERIOR) {
+        vstore(wjw + i0, acc[v]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (ok(i0 + e)) wjw[i0 + e] = cvt_out<ST>((double)acc[v][e]);
+      }
+    }
+  }
+}
+
+template <typename ST, int KIND>
+__global__ void __launch_bounds__(256, 4) k_tall(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
+                                              int32_t j, const double *__restrict__ cf,
+                                              const double *__restrict__ ia,
+                                              float *__restrict__ wstage, double *__restrict__ part,
+                                              const uint64_t *__restrict__ signs,
+                                              const int32_t *__restrict__ rows, int32_t l,
+                                              const double *__restrict__ om, int aligned) {
+  using CT = typename CompT<ST>::type;
+  constexpr int VEC = 16 / sizeof(ST);
+  constexpr int NV = (TILE / 256) / VEC;
+  __shared__ CT s[TILE_PAD];
+  const int64_t base = (int64_t)blockIdx.x * TILE;
+  const bool interior = aligned && base >= m && base + TILE <= n;
+  const double iaprev = j >= 1 ? ia[j - 1] : 0.0;
+  CT acc[NV][VEC];
+  if (interior)
+    tall_body<ST, KIND, true>(W, ldw, n, m, j, cf, iaprev, wstage, base, acc);
+  else
+    tall_body<ST, KIND, false>(W, ldw, n, m, j, cf, iaprev, wstage, base, acc);
+
+  if (KIND == RHQR_SKETCH_IDENT) return;
+  const int tid = threadIdx.x;
+  if (KIND == RHQR_SKETCH_SRHT) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int li0 = VEC * (tid + 256 * v);
+      const int64_t i0 = base + li0;
+      const uint64_t word = (i0 < n) ? signs[i0 >> 6] : 0ull;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const int64_t i = i0 + e;
+        CT x = (i >= m && i < n) ? acc[v][e] : (CT)0;
+        if ((word >> (i & 63)) & 1ull) x = -x;
+        s[tpad(li0 + e)] = x;
+      }
+    }
+    fwht_tile_lds(s);
+    const uint64_t t = (uint64_t)blockIdx.x;
+    for (int q = tid; q < l; q += 256) {
+      const int32_t r = rows[q];
+      const double h = (double)s[tpad(r & (TILE - 1))];
+      const bool neg = __popcll((uint64_t)(r >> TILE_LOG) & t) & 1;
+      part[(int64_t)blockIdx.x * l + q] = neg ? -h : h;
+    }
+  } else {  // Gaussian: partial Omega[:, tile] w~_tile
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int li0 = VEC * (tid + 256 * v);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const int64_t i = base + li0 + e;
+        s[li0 + e] = (i >= m && i < n) ? acc[v][e] : (CT)0;
+      }
+    }
+    __syncthreads();
+    const int64_t lo = base > m ? base : (int64_t)m;
+    const int64_t hi = base + TILE < n ? base + TILE : n;
+    for (int q = tid; q < l; q += 256) {
+      double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+      int64_t i = lo;
+      for (; i + 3 < hi; i += 4) {
+        a0 += om[(i - m) * l + q] * (double)s[i - base];
+        a1 += om[(i + 1 - m) * l + q] * (double)s[i + 1 - base];
+        a2 += om[(i + 2 - m) * l + q] * (double)s[i + 2 - base];
+        a3 += om[(i + 3 - m) * l + q] * (double)s[i + 3 - base];
+      }
+      for (; i < hi; ++i) a0 += om[(i - m) * l + q] * (double)s[i - base];
+      part[(int64_t)blockIdx.x * l + q] = (a0 + a1) + (a2 + a3);
+    }
+  }
+}
+
+// ------------------------------------------------------------------- k_red
+// y = Psi w~_j.  Head rows: y_k = w_{k,j} - sum_{p<j} S_{k,p} c_p (float64);
+// tail rows: sum of the tile partials (SRHT scaled by l^-1/2), or the refreshed
+// rows themselves for Psi = I.  Sixteen waves split the summation index.
+template <typename ST, int KIND>
+__global__ void __launch_bounds__(1024) k_red(const ST *__restrict__ W, int64_t ldw, int32_t m,
+                                              int32_t l, int32_t j, const double *__restrict__ Z,
+                                              int64_t ldz, const double *__restrict__ S, int64_t lds,
+                                              const double *__restrict__ c,
+                                              const double *__restrict__ part, int64_t ntiles,
+                                              double scale, double *__restrict__ y,
+                                              double *__restrict__ sq) {
+  __shared__ double red[16][RED_CHUNK + 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nhb = (m + RED_CHUNK - 1) / RED_CHUNK;
+  const bool head = (int)blockIdx.x < nhb;
+  const int k = head ? (int)blockIdx.x * RED_CHUNK + lane : m + ((int)blockIdx.x - nhb) * RED_CHUNK + lane;
+  const bool valid = head ? (k < m) : (k < m + l);
+  double v = 0.0;
+  if (valid && j >= 1) {
+    if (head) {
+      const int pe = min(j, k + 1);
+      for (int p = w; p < pe; p += 16) v += S[k + (int64_t)p * lds] * c[p];
+    } else if (KIND != RHQR_SKETCH_IDENT) {
+      const int q = k - m;
+      for (int64_t t = w; t < ntiles; t += 16) v += part[t * l + q];
+    }
+  }
+  red[w][lane] = v;
+  __syncthreads();
+  if (w == 0) {
+    double s = 0.0;
+    for (int i = 0; i < 16; ++i) s += red[i][lane];
+    double out = 0.0;
+    if (valid) {
+      if (j == 0)
+        out = Z[k];
+      else if (head)
+        out = cvt_in<double>(W[k + (int64_t)j * ldw]) - s;
+      else if (KIND == RHQR_SKETCH_IDENT)
+        out = cvt_in<double>(W[k + (int64_t)j * ldw]);
+      else
+        out = s * scale;
+      y[k] = out;
+    }
+    const double q2 = (valid && k >= j) ? out * out : 0.0;
+    const double tot = wave_sum(q2);
+    if (lane == 0) sq[blockIdx.x] = tot;
+  }
+}
+
+// -------------------------------------------------------------------- k_ss
+struct StepScalars {
+  double sigma, rho, alpha, beta, gamma;
+  bool ident;
+};
+
+__device__ __forceinline__ StepScalars step_scalars(const double *y, const double *sq, int gred,
+                                                    int32_t j, int scaling) {
+  double ss = 0.0;
+  for (int g = 0; g < gred; ++g) ss += sq[g];
+  StepScalars r;
+  r.rho = sqrt(ss);
+  const double yj = y[j];
+  r.sigma = yj >= 0.0 ? 1.0 : -1.0;
+  r.ident = !(r.rho > 0.0);
+  if (r.ident) {
+    r.gamma = 0.0;
+    r.alpha = 1.0;
+    r.beta = 0.0;
+  } else {
+    r.gamma = yj + r.sigma * r.rho;
+    if (scaling == RHQR_SCALE_UNIT_PIVOT) {
+      r.alpha = r.gamma;
+      r.beta = fabs(r.gamma) / r.rho;
+    } else {
+      r.alpha = sqrt(r.rho * fabs(r.gamma));
+      r.beta = 1.0;
+    }
+  }
+  return r;
+}
+
+__global__ void __launch_bounds__(1024) k_ss(int32_t m, int32_t l, int32_t j, int scaling,
+                                             const double *__restrict__ y,
+                                             const double *__restrict__ sq, int gred,
+                                             double *__restrict__ S, int64_t lds,
+                                             const double *__restrict__ Z, int64_t ldz,
+                                             double *__restrict__ dpart, double *__restrict__ epart,
+                                             double *__restrict__ scal, double *__restrict__ R,
+                                             int64_t ldr, int32_t *__restrict__ status) {
+  __shared__ StepScalars shs;
+  if (threadIdx.x == 0) shs = step_scalars(y, sq, gred, j, scaling);
+  __syncthreads();
+  const StepScalars sc = shs;
+  const int L = l + m;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int k = (int)blockIdx.x * RED_CHUNK + lane;
+  double s = 0.0;
+  if (k < L) {
+    if (k == j)
+      s = sc.ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : sc.gamma / sc.alpha);
+    else if (k > j)
+      s = sc.ident ? 0.0 : y[k] / sc.alpha;
+    if (w == 0) S[k + (int64_t)j * lds] = s;
+  }
+  const bool neede = j + 1 < m;
+  const double z = (neede && k < L) ? Z[k + (int64_t)(j + 1) * ldz] : 0.0;
+  for (int p = w; p <= j; p += 16) {
+    const double sp = (k < L) ? (p < j ? S[k + (int64_t)p * lds] : s) : 0.0;
+    const double dv = wave_sum(sp * s);
+    const double ev = wave_sum(sp * z);
+    if (lane == 0) {
+      if (p < j) dpart[(int64_t)blockIdx.x * m + p] = dv;
+      if (neede) epart[(int64_t)blockIdx.x * m + p] = ev;
+    }
+  }
+  if (blockIdx.x == 0) {
+    for (int r = threadIdx.x; r < m; r += blockDim.x)
+      R[r + (int64_t)j * ldr] = r < j ? y[r] : (r == j ? -sc.sigma * sc.rho : 0.0);
+    if (threadIdx.x == 0) {
+      scal[4 * j + 0] = sc.sigma;
+      scal[4 * j + 1] = sc.rho;
+      scal[4 * j + 2] = sc.alpha;
+      scal[4 * j + 3] = sc.beta;
+      if (sc.ident) atomicCAS(status, 0, j + 1);
+    }
+  }
+}
+
+// ------------------------------------------------------------------- k_fin
+__global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t j, int gss,
+                                              const double *__restrict__ dpart,
+                                              const double *__restrict__ epart,
+                                              const double *__restrict__ scal, double *__restrict__ T,
+                                              int64_t ldt, double *__restrict__ Tt,
+                                              double *__restrict__ c, double *__restrict__ cf,
+                                              double *__restrict__ ia) {
+  __shared__ double d[MAXM], e[MAXM], tc[MAXM];
+  const double rho = scal[4 * j + 1], alpha = scal[4 * j + 2], beta = scal[4 * j + 3];
+  const bool needc = j + 1 < m;
+  for (int p = threadIdx.x; p < j; p += blockDim.x) {
+    double s = 0.0;
+    for (int g = 0; g < gss; ++g) s += dpart[(int64_t)g * m + p];
+    d[p] = s;
+  }
+  if (needc)
+    for (int p = threadIdx.x; p <= j; p += blockDim.x) {
+      double s = 0.0;
+      for (int g = 0; g < gss; ++g) s += epart[(int64_t)g * m + p];
+      e[p] = s;
+    }
+  __syncthreads();
+  const int sub = threadIdx.x & 3;
+  for (int p0 = 0; p0 < j; p0 += 256) {
+    const int p = p0 + (threadIdx.x >> 2);
+    double v = 0.0;
+    if (p < j)
+      for (int q = p + sub; q < j; q += 4) v += T[p + (int64_t)q * ldt] * d[q];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    if (sub == 0 && p < j) {
+      const double t = -beta * v;
+      tc[p] = t;
+      T[p + (int64_t)j * ldt] = t;
+      Tt[j + (int64_t)p * m] = t;
+    }
+  }
+  if (threadIdx.x == 0) {
+    tc[j] = beta;
+    T[j + (int64_t)j * ldt] = beta;
+    Tt[j + (int64_t)j * m] = beta;
+  }
+  __syncthreads();
+  const double iaj = rho > 0.0 ? 1.0 / alpha : 0.0;
+  if (needc) {
+    for (int p0 = 0; p0 <= j; p0 += 256) {
+      const int p = p0 + (threadIdx.x >> 2);
+      double v = 0.0;
+      if (p < j)
+        for (int q = sub; q <= p; q += 4) v += Tt[p + (int64_t)q * m] * e[q];
+      else if (p == j)
+        for (int q = sub; q <= j; q += 4) v += tc[q] * e[q];
+      v += __shfl_xor(v, 1, 64);
+      v += __shfl_xor(v, 2, 64);
+      if (sub == 0 && p <= j) {
+        c[p] = v;
+        cf[p] = p == j ? v * iaj : v;
+      }
+    }
+  }
+  if (threadIdx.x == 0) ia[j] = iaj;
+}
+
+// ------------------------------------------------------------ final stores
+template <typename ST>
+__global__ void k_scale_last(ST *W, int64_t ldw, int64_t n, int32_t m, const double *ia,
+                             const float *wstage) {
+  const int64_t i = m + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  ST *col = W + (int64_t)(m - 1) * ldw;
+  const double a = ia[m - 1];
+  double raw;
+  if constexpr (std::is_same<ST, double>::value)
+    raw = col[i];
+  else
+    raw = m >= 2 ? (double)wstage[i] : cvt_in<double>(col[i]);
+  col[i] = cvt_out<ST>(raw * a);
+}
+
+template <typename ST>
+__global__ void k_head_store(ST *W, int64_t ldw, int32_t m, const double *S, int64_t lds) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cidx = blockIdx.y;
+  if (k < m) W[k + (int64_t)cidx * ldw] = cvt_out<ST>(S[k + (int64_t)cidx * lds]);
+}
+
+__global__ void k_fill(uint32_t *p, size_t nwords) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nwords) p[i] = 0u;
+}
+
+// ----------------------------------------------------------------- thin Q
+// Mq = T U_1^t (m x m):  Mq_{p,c} = sum_{q=p..c} T_{p,q} U1_{c,q}
+__global__ void k_tu1t(int32_t m, const double *T, int64_t ldt, const double *S, int64_t lds,
+                       double *Mq) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cidx = blockIdx.y;
+  if (p >= m) return;
+  double v = 0.0;
+  for (int q = p; q <= cidx; ++q) v += T[p + (int64_t)q * ldt] * S[cidx + (int64_t)q * lds];
+  Mq[p + (int64_t)cidx * m] = v;
+}
+
+// Q head: I - U_1 Mq (float64 U_1 from S)
+template <typename ST>
+__global__ void k_qhead(int32_t m, const double *S, int64_t lds, const double *Mq, ST *Q,
+                        int64_t ldq) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cidx = blockIdx.y;
+  if (k >= m) return;
+  double v = (k == cidx) ? 1.0 : 0.0;
+  for (int p = 0; p <= k; ++p) v -= S[k + (int64_t)p * lds] * Mq[p + (int64_t)cidx * m];
+  Q[k + (int64_t)cidx * ldq] = cvt_out<ST>(v);
+}
+
+// C[r0:r1, 0:N2] = alpha * A[r0:r1, 0:K] B  (B float64, K x N2).  64 x 64 tiles,
+// 16-deep K steps through LDS, 4 x 4 outputs per thread.
+template <typename ST>
+__global__ void __launch_bounds__(256) k_gemm_tall(const ST *__restrict__ A, int64_t lda, int64_t r0,
+                                                   int64_t r1, int32_t K,
+                                                   const double *__restrict__ B, int64_t ldb,
+                                                   int32_t N2, ST *__restrict__ C, int64_t ldc,
+                                                   double alpha) {
+  using CT = typename CompT<ST>::type;
+  __shared__ CT As[16][64 + 1];
+  __shared__ CT Bs[16][64 + 1];
+  const int64_t rb = r0 + (int64_t)blockIdx.x * 64;
+  const int cb = blockIdx.y * 64;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  CT acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int r = e & 63, kq = e >> 6;
+      const int64_t gi = rb + r;
+      const int kk = k0 + kq;
+      As[kq][r] = (gi < r1 && kk < K) ? cvt_in<CT>(A[gi + (int64_t)kk * lda]) : (CT)0;
+      const int kr = e & 15, cc = e >> 4;
+      const int kk2 = k0 + kr, col = cb + cc;
+      Bs[kr][cc] = (kk2 < K && col < N2) ? (CT)B[kk2 + (int64_t)col * ldb] : (CT)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kq = 0; kq < 16; ++kq) {
+      CT a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kq][ty + 16 * i];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) b[jj] = Bs[kq][tx + 16 * jj];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) acc[i][jj] += a[i] * b[jj];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int64_t gi = rb + ty + 16 * i;
+      const int col = cb + tx + 16 * jj;
+      if (gi < r1 && col < N2) C[gi + (int64_t)col * ldc] = cvt_out<ST>((double)(alpha * (double)acc[i][jj]));
+    }
+}
+
+// ------------------------------------------------------------ host helpers
+template <typename ST>
+int run_typed(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
+  ST *W = (ST *)a.W;
+  const int64_t n = a.n;
+  const int32_t m = a.m, l = a.l, L = l + m;
+  const int64_t ntiles = (n + TILE - 1) / TILE;
+  const int gred = (m + RED_CHUNK - 1) / RED_CHUNK + (l + RED_CHUNK - 1) / RED_CHUNK;
+  const int gss = (L + RED_CHUNK - 1) / RED_CHUNK;
+  const double scale = a.kind == RHQR_SKETCH_SRHT ? 1.0 / std::sqrt((double)l) : 1.0;
+  const int aligned = ((uintptr_t)a.W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
+  for (int32_t j = 0; j < m; ++j) {
+    if (j >= 1) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (g_prof.on) {
+        if (prof_pair(&e0, &e1)) return RHQR_ERR_HIP;
+        RHQR_HIP(hipEventRecord(e0, st));
+      }
+      switch (a.kind) {
+        case RHQR_SKETCH_SRHT:
+          hipLaunchKernelGGL((k_tall<ST, RHQR_SKETCH_SRHT>), dim3(ntiles), dim3(256), 0, st, W,
+                             a.ldw, n, m, j, w.cf, w.ia, w.wstage, w.part, a.signs, a.rows, l,
+                             a.omega, aligned);
+          break;
+        case RHQR_SKETCH_GAUSS:
+          hipLaunchKernelGGL((k_tall<ST, RHQR_SKETCH_GAUSS>), dim3(ntiles), dim3(256), 0, st, W,
+                             a.ldw, n, m, j, w.cf, w.ia, w.wstage, w.part, a.signs, a.rows, l,
+                             a.omega, aligned);
+          break;
+        default:
+          hipLaunchKernelGGL((k_tall<ST, RHQR_SKETCH_IDENT>), dim3(ntiles), dim3(256), 0, st, W,
+                             a.ldw, n, m, j, w.cf, w.ia, w.wstage, w.part, a.signs, a.rows, l,
+                             a.omega, aligned);
+      }
+      RHQR_HIP(hipGetLastError());
+      if (g_prof.on) RHQR_HIP(hipEventRecord(e1, st));
+    }
+    if (a.kind == RHQR_SKETCH_IDENT)
+      hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_IDENT>), dim3(gred), dim3(1024), 0, st, W, a.ldw,
+                         m, l, j, a.Z + (int64_t)j * a.ldz, a.ldz, a.S, a.lds, w.c, w.part, ntiles,
+                         scale, w.y, w.sq);
+    else
+      hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_SRHT>), dim3(gred), dim3(1024), 0, st, W, a.ldw, m,
+                         l, j, a.Z + (int64_t)j * a.ldz, a.ldz, a.S, a.lds, w.c, w.part, ntiles,
+                         scale, w.y, w.sq);
+    RHQR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ss, dim3(gss), dim3(1024), 0, st, m, l, j, a.scaling, w.y, w.sq, gred,
+                       a.S, a.lds, a.Z, a.ldz, w.dpart, w.epart, w.scal, a.R, a.ldr, w.status);
+    RHQR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_fin, dim3(1), dim3(1024), 0, st, m, j, gss, w.dpart, w.epart, w.scal, a.T,
+                       a.ldt, w.Tt, w.c, w.cf, w.ia);
+    RHQR_HIP(hipGetLastError());
+  }
+  const int64_t ntail = n - m;
+  if (ntail > 0) {
+    hipLaunchKernelGGL((k_scale_last<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W, a.ldw, n,
+                       m, w.ia, w.wstage);
+    RHQR_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL((k_head_store<ST>), dim3((m + 255) / 256, m), dim3(256), 0, st, W, a.ldw, m,
+                     a.S, a.lds);
+  RHQR_HIP(hipGetLastError());
+  return RHQR_OK;
+}
+
+template <typename ST>
+int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S, int64_t lds,
+                 const double *T, int64_t ldt, double *Mq, ST *Q, int64_t ldq, hipStream_t st) {
+  hipLaunchKernelGGL(k_tu1t, dim3((m + 255) / 256, m), dim3(256), 0, st, m, T, ldt, S, lds, Mq);
+  RHQR_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_qhead<ST>), dim3((m + 255) / 256, m), dim3(256), 0, st, m, S, lds, Mq, Q,
+                     ldq);
+  RHQR_HIP(hipGetLastError());
+  const int64_t rows = n - m;
+  if (rows > 0) {
+    dim3 grid((rows + 63) / 64, (m + 63) / 64);
+    hipLaunchKernelGGL((k_gemm_tall<ST>), grid, dim3(256), 0, st, U, ldu, (int64_t)m, n, m,
+                       (const double *)Mq, (int64_t)m, m, Q, ldq, -1.0);
+    RHQR_HIP(hipGetLastError());
+  }
+  return RHQR_OK;
+}
+
+}  // namespace
+
+int launch_fill(void *p, size_t bytes, hipStream_t st) {
+  const size_t nw = bytes / 4;
+  if (nw == 0) return RHQR_OK;
+  hipLaunchKernelGGL(k_fill, dim3((nw + 255) / 256), dim3(256), 0, st, (uint32_t *)p, nw);
+  RHQR_HIP(hipGetLastError());
+  return RHQR_OK;
+}
+
+size_t loop_ws_bytes(int kind, int dtype, int64_t n, int32_t m, int32_t l) {
+  const int32_t L = l + m;
+  const int64_t ntiles = (n + TILE - 1) / TILE;
+  const int gred = (m + RED_CHUNK - 1) / RED_CHUNK + (l + RED_CHUNK - 1) / RED_CHUNK;
+  const int gss = (L + RED_CHUNK - 1) / RED_CHUNK;
+  size_t b = 0;
+  b += align_up(sizeof(int32_t) * 4);
+  b += align_up(sizeof(double) * L);
+  b += align_up(sizeof(double) * gred);
+  b += 2 * align_up(sizeof(double) * (size_t)gss * m);
+  b += align_up(sizeof(double) * 4 * m);
+  b += 3 * align_up(sizeof(double) * m);
+  b += align_up(sizeof(double) * (size_t)m * m);
+  if (kind != RHQR_SKETCH_IDENT) b += align_up(sizeof(double) * (size_t)ntiles * l);
+  if (dtype != RHQR_F64) b += align_up(sizeof(float) * (size_t)n);
+  return b;
+}
+
+int loop_ws_carve(void *ws, size_t bytes, int kind, int dtype, int64_t n, int32_t m, int32_t l,
+                  LoopWs *o) {
+  if (bytes < loop_ws_bytes(kind, dtype, n, m, l)) return RHQR_ERR_WORKSPACE;
+  const int32_t L = l + m;
+  const int64_t ntiles = (n + TILE - 1) / TILE;
+  const int gred = (m + RED_CHUNK - 1) / RED_CHUNK + (l + RED_CHUNK - 1) / RED_CHUNK;
+  const int gss = (L + RED_CHUNK - 1) / RED_CHUNK;
+  char *p = (char *)ws;
+  auto take = [&](size_t b) {
+    char *r = p;
+    p += align_up(b);
+    return (void *)r;
+  };
+  o->status = (int32_t *)take(sizeof(int32_t) * 4);
+  o->y = (double *)take(sizeof(double) * L);
+  o->sq = (double *)take(sizeof(double) * gred);
+  o->dpart = (double *)take(sizeof(double) * (size_t)gss * m);
+  o->epart = (double *)take(sizeof(double) * (size_t)gss * m);
+  o->scal = (double *)take(sizeof(double) * 4 * m);
+  o->c = (double *)take(sizeof(double) * m);
+  o->cf = (double *)take(sizeof(double) * m);
+  o->ia = (double *)take(sizeof(double) * m);
+  o->Tt = (double *)take(sizeof(double) * (size_t)m * m);
+  o->part = kind != RHQR_SKETCH_IDENT ? (double *)take(sizeof(double) * (size_t)ntiles * l) : nullptr;
+  o->wstage = dtype != RHQR_F64 ? (float *)take(sizeof(float) * (size_t)n) : nullptr;
+  o->skws = nullptr;
+  o->skws_bytes = 0;
+  return RHQR_OK;
+}
+
+int run_column_loop(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
+  if (a.m > MAXM) return RHQR_ERR_UNSUPPORTED;
+  switch (a.dtype) {
+    case RHQR_F64: return run_typed<double>(a, w, st);
+    case RHQR_F32: return run_typed<float>(a, w, st);
+    case RHQR_F16: return run_typed<__half>(a, w, st);
+    case RHQR_BF16: return run_typed<__hip_bfloat16>(a, w, st);
+  }
+  return RHQR_ERR_UNSUPPORTED;
+}
+
+int launch_thin_q(int dtype, int64_t n, int32_t m, const void *U, int64_t ldu, const double *S,
+                  int64_t lds, const double *T, int64_t ldt, double *Mq, void *Q, int64_t ldq,
+                  hipStream_t st) {
+  switch (dtype) {
+    case RHQR_F64:
+      return thin_q_typed<double>(n, m, (const double *)U, ldu, S, lds, T, ldt, Mq, (double *)Q, ldq, st);
+    case RHQR_F32:
+      return thin_q_typed<float>(n, m, (const float *)U, ldu, S, lds, T, ldt, Mq, (float *)Q, ldq, st);
+    case RHQR_F16:
+      return thin_q_typed<__half>(n, m, (const __half *)U, ldu, S, lds, T, ldt, Mq, (__half *)Q, ldq, st);
+    case RHQR_BF16:
+      return thin_q_typed<__hip_bfloat16>(n, m, (const __hip_bfloat16 *)U, ldu, S, lds, T, ldt, Mq,
+                                          (__hip_bfloat16 *)Q, ldq, st);
+  }
+  return RHQR_ERR_UNSUPPORTED;
+}
+
+extern "C" int rhqr_profile_begin(void) {
+  g_prof.on = true;
+  g_prof.used = 0;
+  return RHQR_OK;
+}
+
+extern "C" int rhqr_profile_end(double *total_ms, int64_t *launches) {
+  g_prof.on = false;
+  double tot = 0.0;
+  for (size_t k = 0; k + 1 < g_prof.used; k += 2) {
+    RHQR_HIP(hipEventSynchronize(g_prof.ev[k + 1]));
+    float ms = 0.f;
+    RHQR_HIP(hipEventElapsedTime(&ms, g_prof.ev[k], g_prof.ev[k + 1]));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (int64_t)(g_prof.used / 2);
+  g_prof.used = 0;
+  return RHQR_OK;
+}

@@ -1,0 +1,121 @@
+// C ABI: rhqr_factor (left-looking RHQR, Alg. 4) and rhqr_status.
+#include "engine.h"
+
+namespace {
+
+__global__ void k_zero_sq(double *A, int64_t lda, int32_t rows, int32_t cols) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r < rows && c < cols) A[r + (int64_t)c * lda] = 0.0;
+}
+
+struct FactorWs {
+  LoopWs loop;
+  double *Z;
+  void *skws;
+  size_t skws_bytes;
+  double *Mq;
+};
+
+size_t factor_ws_bytes(const rhqr_sketch_s *h, int dtype, int32_t m) {
+  const int32_t L = h->l + m;
+  size_t b = loop_ws_bytes(h->kind, dtype, h->n, m, h->l);
+  b += align_up(sizeof(double) * (size_t)L * m);
+  b += align_up(sketch_ws_bytes(h, m));
+  b += align_up(sizeof(double) * (size_t)m * m);
+  return b;
+}
+
+int factor_ws_carve(const rhqr_sketch_s *h, int dtype, int32_t m, void *ws, size_t bytes,
+                    FactorWs *o) {
+  if (bytes < factor_ws_bytes(h, dtype, m)) return RHQR_ERR_WORKSPACE;
+  const size_t lb = loop_ws_bytes(h->kind, dtype, h->n, m, h->l);
+  int rc = loop_ws_carve(ws, lb, h->kind, dtype, h->n, m, h->l, &o->loop);
+  if (rc) return rc;
+  char *p = (char *)ws + lb;
+  const int32_t L = h->l + m;
+  o->Z = (double *)p;
+  p += align_up(sizeof(double) * (size_t)L * m);
+  o->skws = p;
+  o->skws_bytes = align_up(sketch_ws_bytes(h, m));
+  p += o->skws_bytes;
+  o->Mq = (double *)p;
+  return RHQR_OK;
+}
+
+}  // namespace
+
+extern "C" size_t rhqr_factor_workspace_size(rhqr_sketch_t h, int dtype, int32_t m) {
+  if (!h || m != h->m || dtype < RHQR_F64 || dtype > RHQR_BF16) return 0;
+  return factor_ws_bytes(h, dtype, m);
+}
+
+extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W,
+                           int64_t ldw, double *d_S, int64_t lds, double *d_T, int64_t ldt,
+                           double *d_R, int64_t ldr, void *d_Q, int64_t ldq, int scaling,
+                           void *d_ws, size_t ws_bytes, void *stream) {
+  if (!h) return -1;
+  if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -2;
+  if (n != h->n) return -3;
+  if (m != h->m) return -4;
+  if (!d_W) return -5;
+  if (ldw < n) return -6;
+  const int32_t L = h->l + m;
+  if (!d_S) return -7;
+  if (lds < L) return -8;
+  if (!d_T) return -9;
+  if (ldt < m) return -10;
+  if (!d_R) return -11;
+  if (ldr < m) return -12;
+  if (d_Q && ldq < n) return -14;
+  if (scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) return -15;
+  if (!d_ws) return -16;
+  if (m > 1024) return RHQR_ERR_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  FactorWs w;
+  int rc = factor_ws_carve(h, dtype, m, d_ws, ws_bytes, &w);
+  if (rc) return rc;
+
+  rc = launch_fill(w.loop.status, 16, st);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_zero_sq, dim3((m + 255) / 256, m), dim3(256), 0, st, d_T, ldt, m, m);
+  RHQR_HIP(hipGetLastError());
+
+  // pre-sketch of every column: "if next vector available, sketch it now"
+  rc = launch_sketch(h, dtype, n, m, d_W, ldw, w.Z, L, w.skws, w.skws_bytes, st);
+  if (rc) return rc;
+
+  LoopArgs a;
+  a.kind = h->kind;
+  a.dtype = dtype;
+  a.n = n;
+  a.m = m;
+  a.l = h->l;
+  a.W = d_W;
+  a.ldw = ldw;
+  a.Z = w.Z;
+  a.ldz = L;
+  a.S = d_S;
+  a.lds = lds;
+  a.T = d_T;
+  a.ldt = ldt;
+  a.R = d_R;
+  a.ldr = ldr;
+  a.scaling = scaling;
+  a.signs = h->d_signs;
+  a.rows = h->d_rows;
+  a.omega = h->d_omega;
+  rc = run_column_loop(a, w.loop, st);
+  if (rc) return rc;
+  if (d_Q) rc = launch_thin_q(dtype, n, m, d_W, ldw, d_S, lds, d_T, ldt, w.Mq, d_Q, ldq, st);
+  return rc;
+}
+
+extern "C" int rhqr_status(const void *d_ws, void *stream, int32_t *h_info) {
+  if (!d_ws) return -1;
+  if (!h_info) return -3;
+  hipStream_t st = (hipStream_t)stream;
+  RHQR_HIP(hipMemcpyAsync(h_info, d_ws, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  RHQR_HIP(hipStreamSynchronize(st));
+  return RHQR_OK;
+}

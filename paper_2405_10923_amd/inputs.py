@@ -3,7 +3,7 @@
 This module builds test matrices and operators only; it holds none of the
 factorization's arithmetic.
 
-* ``test_matrix``: W = G diag(s) V with G iid N(0,1) (n x m), singular values
+* ``synthetic_matrix``: W = G diag(s) V with G iid N(0,1) (n x m), singular values
   s_i = 10^(-kappa * i / (m-1)) logarithmically spaced from 1 to 10^-kappa,
   and V a Haar-distributed orthogonal m x m matrix (QR of a Gaussian matrix
   with the signs of diag(R) moved into Q).
@@ -30,7 +30,7 @@ def singular_values(m, kappa_log10):
     return 10.0 ** (-float(kappa_log10) * np.arange(m) / (m - 1))
 
 
-def test_matrix(n, m, kappa_log10, seed=0):
+def synthetic_matrix(n, m, kappa_log10, seed=0):
     """float64 n x m matrix with condition number 10^kappa_log10 (numpy RNG)."""
     rng = np.random.default_rng(seed)
     G = rng.standard_normal((n, m))
@@ -39,7 +39,7 @@ def test_matrix(n, m, kappa_log10, seed=0):
     return np.asfortranarray((G * s) @ V)
 
 
-def test_matrix_torch(n, m, kappa_log10, seed=0, device="cuda"):
+def synthetic_matrix_torch(n, m, kappa_log10, seed=0, device="cuda"):
     """Same construction with G drawn by torch on ``device`` (large sizes).
     Returned as a column-major (n x m) float64 torch tensor (a transposed view
     of an m x n row-major buffer)."""

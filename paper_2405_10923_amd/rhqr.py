@@ -1,0 +1,252 @@
+"""Thin ctypes binding of librhqr.so (the C ABI declared in include/rhqr.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch tensors provide device memory and the current stream.  Matrices are
+column-major: an (r x c) matrix is a tensor of shape (r, c) with stride(0) == 1
+and leading dimension stride(1).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librhqr.so")
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+SRHT, GAUSS = 0, 1
+SCALE_UNIT_PIVOT, SCALE_SQRT2 = 0, 1
+REC_M, REC_RCHOL = 0, 1
+
+_lib = None
+
+_vp, _i32, _i64, _u64, _sz, _dp = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_size_t, C.c_void_p
+
+_SIGS = {
+    "rhqr_sketch_create": (C.c_int, [C.c_int, _i64, _i32, _i32, _u64, _vp, _i64, _vp, C.POINTER(_vp)]),
+    "rhqr_sketch_destroy": (C.c_int, [_vp]),
+    "rhqr_sketch_get": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "rhqr_sketch_info": (C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32),
+                                   C.POINTER(_i64), C.POINTER(_i32)]),
+    "rhqr_sketch_workspace_size": (_sz, [_vp, _i32]),
+    "rhqr_sketch": (C.c_int, [_vp, C.c_int, _i64, _i32, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
+    "rhqr_factor_workspace_size": (_sz, [_vp, C.c_int, _i32]),
+    "rhqr_factor": (C.c_int, [_vp, C.c_int, _i64, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
+                              _i64, _vp, _i64, C.c_int, _vp, _sz, _vp]),
+    "rhqr_status": (C.c_int, [_vp, _vp, C.POINTER(_i32)]),
+    "recrhqr_workspace_size": (_sz, [_vp, C.c_int, _i32]),
+    "recrhqr_factor": (C.c_int, [_vp, C.c_int, _i64, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
+                                 _i64, _vp, _i64, _vp, _i64, C.c_int, _vp, _sz, _vp]),
+    "rhqr_arnoldi_create": (C.c_int, [_vp, C.c_int, _i64, _i32, _vp, C.POINTER(_vp)]),
+    "rhqr_arnoldi_destroy": (C.c_int, [_vp]),
+    "rhqr_arnoldi_start": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
+    "rhqr_arnoldi_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "rhqr_arnoldi_solution": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "rhqr_arnoldi_basis": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp)]),
+    "rhqr_profile_begin": (C.c_int, []),
+    "rhqr_profile_end": (C.c_int, [C.POINTER(C.c_double), C.POINTER(_i64)]),
+}
+
+
+def lib():
+    """Load librhqr.so.  Fails loudly when the library has not been built:
+    there is no fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not found: build it with "
+                               "`python -m paper_2405_10923_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class RHQRError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RHQRError(f"{what} failed with code {rc}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_code(t):
+    torch = _torch()
+    return {torch.float64: F64, torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}[t]
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ld(t):
+    if t.dim() != 2 or (t.stride(0) != 1 and t.shape[0] > 1):
+        raise ValueError("expected a column-major matrix (stride(0) == 1)")
+    if t.shape[1] == 1:
+        return max(t.shape[0], 1)
+    return t.stride(1)
+
+
+def colmajor_empty(rows, cols, dtype, device):
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+def to_colmajor(t):
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    if t.stride(0) == 1 or t.shape[0] == 1:
+        return t
+    return t.t().contiguous().t()
+
+
+def workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Sketch:
+    """Psi = [I_m 0; 0 Omega] for n-row problems (Sec. 2.3, eq. psi)."""
+
+    def __init__(self, kind, n, m, l, seed=0, omega=None):
+        torch = _torch()
+        self.kind, self.n, self.m, self.l, self.seed = kind, int(n), int(m), int(l), int(seed)
+        h = C.c_void_p()
+        om = _ptr(omega) if omega is not None else C.c_void_p(0)
+        ldo = _ld(omega) if omega is not None else 0
+        rc = lib().rhqr_sketch_create(int(kind), self.n, self.m, self.l, C.c_uint64(self.seed), om,
+                                      ldo, _stream(), C.byref(h))
+        _check(rc, "rhqr_sketch_create")
+        self.h = h
+        N = C.c_int64()
+        lib().rhqr_sketch_info(h, None, None, None, C.byref(N), None)
+        self.N = N.value
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rhqr_sketch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def rows_out(self):
+        return self.l + self.m
+
+    def signs_words(self):
+        w = np.zeros((self.N + 63) // 64, dtype=np.uint64)
+        _check(lib().rhqr_sketch_get(self.h, w.ctypes.data_as(C.c_void_p), None, None), "get")
+        return w
+
+    def rows(self):
+        r = np.zeros(self.l, dtype=np.int32)
+        _check(lib().rhqr_sketch_get(self.h, None, r.ctypes.data_as(C.c_void_p), None), "get")
+        return r
+
+    def omega(self):
+        o = np.zeros((self.n - self.m) * self.l, dtype=np.float64)
+        _check(lib().rhqr_sketch_get(self.h, None, None, o.ctypes.data_as(C.c_void_p)), "get")
+        return o.reshape(self.n - self.m, self.l).T
+
+
+def sketch(sk, X, Y=None, ws=None):
+    """Y = Psi X (RHSketch, Alg. 1); X column-major (n x k) on the GPU."""
+    X = to_colmajor(X)
+    n, k = X.shape
+    if Y is None:
+        Y = colmajor_empty(sk.rows_out, k, _torch().float64, X.device)
+    nb = lib().rhqr_sketch_workspace_size(sk.h, k)
+    if ws is None:
+        ws = workspace(nb, X.device)
+    rc = lib().rhqr_sketch(sk.h, dtype_code(X.dtype), n, k, _ptr(X), _ld(X), _ptr(Y), _ld(Y),
+                           _ptr(ws), ws.numel(), _stream())
+    _check(rc, "rhqr_sketch")
+    return Y
+
+
+class FactorBuffers:
+    """Outputs and workspace of rhqr_factor for one (sketch, dtype, m)."""
+
+    def __init__(self, sk, dtype, m, want_q=False, n=None):
+        torch = _torch()
+        dev = sk.device
+        L = sk.rows_out
+        self.S = colmajor_empty(L, m, torch.float64, dev)
+        self.T = colmajor_empty(m, m, torch.float64, dev)
+        self.R = colmajor_empty(m, m, torch.float64, dev)
+        self.Q = colmajor_empty(sk.n, m, dtype, dev) if want_q else None
+        self.ws = workspace(lib().rhqr_factor_workspace_size(sk.h, dtype_code(dtype), m), dev)
+
+
+def factor(sk, W, scaling=SCALE_UNIT_PIVOT, want_q=False, bufs=None):
+    """Left-looking RHQR (Alg. 4).  W (n x m, column-major, GPU) is overwritten
+    by U.  Returns dict(U=W, S, T, R, Q)."""
+    n, m = W.shape
+    if bufs is None:
+        bufs = FactorBuffers(sk, W.dtype, m, want_q)
+    Q = bufs.Q if want_q else None
+    rc = lib().rhqr_factor(sk.h, dtype_code(W.dtype), n, m, _ptr(W), _ld(W), _ptr(bufs.S),
+                           _ld(bufs.S), _ptr(bufs.T), _ld(bufs.T), _ptr(bufs.R), _ld(bufs.R),
+                           _ptr(Q), _ld(Q) if Q is not None else 0, int(scaling), _ptr(bufs.ws),
+                           bufs.ws.numel(), _stream())
+    _check(rc, "rhqr_factor")
+    return dict(U=W, S=bufs.S, T=bufs.T, R=bufs.R, Q=Q, ws=bufs.ws)
+
+
+def status(ws):
+    info = C.c_int32()
+    _check(lib().rhqr_status(_ptr(ws), _stream(), C.byref(info)), "rhqr_status")
+    return info.value
+
+
+def recrhqr(sk, W, mode=REC_M, want_q=True):
+    """recRHQR (Alg. 6).  W is read only.  Returns dict(U, S, T, R, Q)."""
+    torch = _torch()
+    n, m = W.shape
+    dev = W.device
+    L = sk.rows_out
+    S = colmajor_empty(L, m, torch.float64, dev)
+    T = colmajor_empty(m, m, torch.float64, dev)
+    R = colmajor_empty(m, m, torch.float64, dev)
+    U = colmajor_empty(n, m, W.dtype, dev) if mode == REC_M else None
+    Q = colmajor_empty(n, m, W.dtype, dev) if want_q else None
+    ws = workspace(lib().recrhqr_workspace_size(sk.h, dtype_code(W.dtype), m), dev)
+    rc = lib().recrhqr_factor(sk.h, dtype_code(W.dtype), n, m, _ptr(W), _ld(W), _ptr(U),
+                              _ld(U) if U is not None else 0, _ptr(S), _ld(S), _ptr(T), _ld(T),
+                              _ptr(R), _ld(R), _ptr(Q), _ld(Q) if Q is not None else 0, int(mode),
+                              _ptr(ws), ws.numel(), _stream())
+    _check(rc, "recrhqr_factor")
+    return dict(U=U, S=S, T=T, R=R, Q=Q, ws=ws)
+
+
+def profile_begin():
+    _check(lib().rhqr_profile_begin(), "rhqr_profile_begin")
+
+
+def profile_end():
+    """Summed duration (ms) and count of tall-update launches since
+    profile_begin(), measured with HIP events on the launching stream."""
+    ms = C.c_double()
+    cnt = C.c_int64()
+    _check(lib().rhqr_profile_end(C.byref(ms), C.byref(cnt)), "rhqr_profile_end")
+    return ms.value, cnt.value

@@ -1,0 +1,131 @@
+"""GPU parity of left-looking RHQR (Alg. 4) against the CPU oracle.
+
+Well-conditioned inputs are compared element by element (U, S, T, R, Q);
+ill-conditioned ones through the backward-stable quantities the paper bounds
+(Thm. factoerror, Thm. conditionnumberQ): the factorization error and the
+sketch orthogonality, which must both be below the precision's tolerance.
+Tolerances: float64 1e-12, float32 1e-5, float16/bfloat16 1e-2."""
+import numpy as np
+import pytest
+
+from oracle import sketch as osk, rhqr as orq, metrics
+from paper_2405_10923_amd.inputs import synthetic_matrix
+from tests.gpu_util import cuda_or_skip, to_gpu, to_np, rel, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(kind, n, m, l, kappa, seed=0, scaling=0, dtype="float64", want_q=True):
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    W = synthetic_matrix(n, m, kappa, seed=seed)
+    Wd = to_gpu(W, getattr(torch, dtype))
+    Win = to_np(Wd)
+    sk = rhqr.Sketch(kind, n, m, l, seed=seed + 1)
+    out = rhqr.factor(sk, Wd, scaling=scaling, want_q=want_q)
+    torch.cuda.synchronize()
+    res = {k: to_np(v) for k, v in out.items() if k in ("U", "S", "T", "R") or (k == "Q" and v is not None)}
+    res["info"] = rhqr.status(out["ws"])
+    okind = osk.SRHT if kind == rhqr.SRHT else osk.GAUSS
+    omega = sk.omega() if kind == rhqr.GAUSS else None
+    osketch = osk.Sketch(okind, n, m, l, seed=seed + 1, omega=omega)
+    return W, Win, res, osketch
+
+
+@pytest.mark.parametrize("n,m,l", [(300, 7, 40), (4096, 32, 128), (3 * 4096 + 777, 24, 96),
+                                   (2 * 4096 + 5, 70, 200)])
+def test_f64_srht_elementwise(n, m, l):
+    log(f"rhqr f64 srht n={n} m={m} l={l}")
+    W, Win, g, sk = _run(0, n, m, l, 2)
+    ref = orq.rhqr_left(W, sk)
+    assert g["info"] == 0
+    assert rel(g["R"], ref["R"]) < 1e-12
+    assert rel(g["S"], ref["S"]) < 1e-12
+    assert rel(g["T"], ref["T"]) < 1e-12
+    assert rel(g["U"], ref["U"]) < 1e-12
+    Qref = orq.thin_q(ref["U"], ref["T"], m)
+    assert rel(g["Q"], Qref) < 1e-12
+    assert np.array_equal(np.triu(g["R"], 1) + np.diag(np.diag(g["R"])), g["R"])
+
+
+def test_f64_scaling_sqrt2():
+    n, m, l = 3 * 4096 + 11, 16, 64
+    W, Win, g, sk = _run(0, n, m, l, 2, scaling=1)
+    ref = orq.rhqr_left(W, sk, scaling="A")
+    assert rel(g["R"], ref["R"]) < 1e-12
+    assert rel(g["S"], ref["S"]) < 1e-12
+    assert rel(g["T"], ref["T"]) < 1e-12
+    assert rel(g["U"], ref["U"]) < 1e-12
+    assert np.allclose(np.sum(g["S"] ** 2, axis=0), 2.0, rtol=1e-13)
+
+
+def test_f64_gauss_elementwise():
+    n, m, l = 2 * 4096 + 300, 20, 80
+    W, Win, g, sk = _run(1, n, m, l, 2)
+    ref = orq.rhqr_left(W, sk)
+    assert rel(g["R"], ref["R"]) < 1e-12
+    assert rel(g["S"], ref["S"]) < 1e-12
+    assert rel(g["T"], ref["T"]) < 1e-12
+    assert rel(g["U"], ref["U"]) < 1e-12
+
+
+def test_c1_ill_conditioned():
+    """4096 x 32, singular values 1..1e-8, SRHT l=128, seed 0."""
+    n, m, l = 4096, 32, 128
+    W, Win, g, sk = _run(0, n, m, l, 8, seed=0)
+    ref = orq.rhqr_left(W, sk)
+    Q = g["Q"]
+    ef = metrics.fact_error(W, Q, g["R"])
+    eo = metrics.orth_error(osk.rh_sketch(Q, sk))
+    Qr = orq.thin_q(ref["U"], ref["T"], m)
+    ef_o = metrics.fact_error(W, Qr, ref["R"])
+    eo_o = metrics.orth_error(osk.rh_sketch(Qr, sk))
+    log(f"c1: e_fact {ef:.2e} (oracle {ef_o:.2e})  e_orth {eo:.2e} (oracle {eo_o:.2e})")
+    assert ef < 1e-12 and eo < 1e-12
+    assert abs(ef - ef_o) < 1e-12 and abs(eo - eo_o) < 1e-12
+    # R is backward-stable: compare against the oracle normwise
+    assert np.linalg.norm(g["R"] - ref["R"]) <= 1e-12 * np.linalg.norm(ref["R"]) * 1e4
+
+
+@pytest.mark.parametrize("dt,tol", [("float32", 1e-5), ("float16", 1e-2), ("bfloat16", 1e-2)])
+def test_low_precision_bounds(dt, tol):
+    n, m, l = 3 * 4096 + 77, 24, 96
+    torch = cuda_or_skip()
+    W, Win, g, sk = _run(0, n, m, l, 6, dtype=dt)
+    Q = g["Q"]
+    ef = metrics.fact_error(Win, Q, g["R"])
+    eo = metrics.orth_error(osk.rh_sketch(Q, sk))
+    ref = orq.rhqr_left(Win, sk)
+    Qr = orq.thin_q(ref["U"], ref["T"], m)
+    ef_o = metrics.fact_error(Win, Qr, ref["R"])
+    log(f"{dt}: e_fact {ef:.2e} e_orth {eo:.2e} (oracle e_fact {ef_o:.2e})")
+    assert ef < tol and eo < tol
+    assert abs(ef - ef_o) < tol
+
+
+def test_rank_deficient_zero_column():
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    n, m, l = 5000, 6, 32
+    W = synthetic_matrix(n, m, 1, seed=3)
+    W[:, 2] = 0.0
+    sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=3)
+    out = rhqr.factor(sk, to_gpu(W), want_q=True)
+    info = rhqr.status(out["ws"])
+    R, T = to_np(out["R"]), to_np(out["T"])
+    ref = orq.rhqr_left(W, osk.Sketch(osk.SRHT, n, m, l, seed=3))
+    assert info == 3 == ref["info"]
+    assert R[2, 2] == 0.0 and T[2, 2] == 0.0
+    assert rel(R, ref["R"]) < 1e-12
+
+
+def test_repeatable_bitwise():
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    n, m, l = 3 * 4096 + 1, 16, 64
+    W = synthetic_matrix(n, m, 10, seed=5)
+    sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=5)
+    a = rhqr.factor(sk, to_gpu(W))
+    b = rhqr.factor(sk, to_gpu(W))
+    for k in ("U", "S", "T", "R"):
+        assert torch.equal(a[k], b[k])

@@ -6,7 +6,7 @@ import pytest
 import scipy.linalg
 
 from oracle import rhqr, sketch, metrics
-from paper_2405_10923_amd.inputs import test_matrix as make_w
+from paper_2405_10923_amd.inputs import synthetic_matrix as make_w
 
 
 def _pins_hold(out, W, sk):

@@ -15,7 +15,7 @@ import scipy.linalg
 from scipy.linalg import lapack
 
 from oracle import rhqr, sketch, metrics
-from paper_2405_10923_amd.inputs import test_matrix as make_w
+from paper_2405_10923_amd.inputs import synthetic_matrix as make_w
 
 
 def _psi_dense(sk):
