@@ -6,6 +6,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <type_traits>
+
 #include "../../include/rhqr.h"
 
 #define RHQR_HIP(x)                                   \
@@ -65,6 +67,77 @@ inline size_t dtype_size(int dt) {
 }
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// -------------------------------------------------------------- 16-byte I/O
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// 16-byte load decoded to CT; NT selects a non-temporal (streaming) load.
+template <typename ST, typename CT, bool NT = false>
+__device__ __forceinline__ void vload(const ST *p, CT *o) {
+  u32x4 uv;
+  if constexpr (NT)
+    uv = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+  else
+    uv = *reinterpret_cast<const u32x4 *>(p);
+  uint4 u;
+  u.x = uv.x;
+  u.y = uv.y;
+  u.z = uv.z;
+  u.w = uv.w;
+  if constexpr (sizeof(ST) == 8) {
+    o[0] = (CT)__hiloint2double((int)u.y, (int)u.x);
+    o[1] = (CT)__hiloint2double((int)u.w, (int)u.z);
+  } else if constexpr (sizeof(ST) == 4) {
+    o[0] = (CT)__uint_as_float(u.x);
+    o[1] = (CT)__uint_as_float(u.y);
+    o[2] = (CT)__uint_as_float(u.z);
+    o[3] = (CT)__uint_as_float(u.w);
+  } else {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const unsigned short b = (unsigned short)(w[k >> 1] >> (16 * (k & 1)));
+      if constexpr (std::is_same<ST, __half>::value)
+        o[k] = (CT)__half2float(__ushort_as_half(b));
+      else
+        o[k] = (CT)__uint_as_float(((uint32_t)b) << 16);
+    }
+  }
+}
+
+template <typename ST> __device__ __forceinline__ unsigned short enc16(float v) {
+  if constexpr (std::is_same<ST, __half>::value)
+    return __half_as_ushort(__float2half(v));
+  else
+    return __bfloat16_as_ushort(__float2bfloat16(v));
+}
+
+template <typename ST, typename CT>
+__device__ __forceinline__ void vstore(ST *p, const CT *v) {
+  uint4 u;
+  if constexpr (sizeof(ST) == 8) {
+    const double a = (double)v[0], b = (double)v[1];
+    u.x = (uint32_t)__double2loint(a);
+    u.y = (uint32_t)__double2hiint(a);
+    u.z = (uint32_t)__double2loint(b);
+    u.w = (uint32_t)__double2hiint(b);
+  } else if constexpr (sizeof(ST) == 4) {
+    u.x = __float_as_uint((float)v[0]);
+    u.y = __float_as_uint((float)v[1]);
+    u.z = __float_as_uint((float)v[2]);
+    u.w = __float_as_uint((float)v[3]);
+  } else {
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      w[k] = (uint32_t)enc16<ST>((float)v[2 * k]) | ((uint32_t)enc16<ST>((float)v[2 * k + 1]) << 16);
+    u.x = w[0];
+    u.y = w[1];
+    u.z = w[2];
+    u.w = w[3];
+  }
+  *reinterpret_cast<uint4 *>(p) = u;
+}
 
 // ---------------------------------------------------------------- reductions
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {

@@ -6,6 +6,7 @@
 
 struct LoopWs {
   int32_t *status;   // first column with rho_j = 0 (1-based), 0 if none
+  uint32_t *counter; // arrival counter of the last-workgroup step (zero between calls)
   double *y;         // (l+m) sketch of the refreshed column
   double *sq;        // per-workgroup partial sums of squares
   double *dpart;     // [G_ss][m] partial S^t s_j

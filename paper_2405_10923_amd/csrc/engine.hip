@@ -26,6 +26,7 @@
 namespace {
 
 constexpr int MAXM = 1024;  // largest m the sketch-space kernels support
+constexpr int TALL_TPB = 1024;  // threads per tall workgroup
 
 // Optional timing of the tall-update launches with HIP events recorded on the
 // launching stream (rhqr_profile_begin / rhqr_profile_end).
@@ -50,109 +51,71 @@ int prof_pair(hipEvent_t *a, hipEvent_t *b) {
   return RHQR_OK;
 }
 
-// -------------------------------------------------------------- 16-byte I/O
-template <typename ST, typename CT>
-__device__ __forceinline__ void vload(const ST *p, CT *o) {
-  const uint4 u = *reinterpret_cast<const uint4 *>(p);
-  if constexpr (sizeof(ST) == 8) {
-    o[0] = (CT)__hiloint2double((int)u.y, (int)u.x);
-    o[1] = (CT)__hiloint2double((int)u.w, (int)u.z);
-  } else if constexpr (sizeof(ST) == 4) {
-    o[0] = (CT)__uint_as_float(u.x);
-    o[1] = (CT)__uint_as_float(u.y);
-    o[2] = (CT)__uint_as_float(u.z);
-    o[3] = (CT)__uint_as_float(u.w);
-  } else {
-    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const unsigned short b = (unsigned short)(w[k >> 1] >> (16 * (k & 1)));
-      if constexpr (std::is_same<ST, __half>::value)
-        o[k] = (CT)__half2float(__ushort_as_half(b));
-      else
-        o[k] = (CT)__uint_as_float(((uint32_t)b) << 16);
-    }
-  }
-}
-
-template <typename ST> __device__ __forceinline__ unsigned short enc16(float v) {
-  if constexpr (std::is_same<ST, __half>::value)
-    return __half_as_ushort(__float2half(v));
-  else
-    return __bfloat16_as_ushort(__float2bfloat16(v));
-}
-
-template <typename ST, typename CT>
-__device__ __forceinline__ void vstore(ST *p, const CT *v) {
-  uint4 u;
-  if constexpr (sizeof(ST) == 8) {
-    const double a = (double)v[0], b = (double)v[1];
-    u.x = (uint32_t)__double2loint(a);
-    u.y = (uint32_t)__double2hiint(a);
-    u.z = (uint32_t)__double2loint(b);
-    u.w = (uint32_t)__double2hiint(b);
-  } else if constexpr (sizeof(ST) == 4) {
-    u.x = __float_as_uint((float)v[0]);
-    u.y = __float_as_uint((float)v[1]);
-    u.z = __float_as_uint((float)v[2]);
-    u.w = __float_as_uint((float)v[3]);
-  } else {
-    uint32_t w[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      w[k] = (uint32_t)enc16<ST>((float)v[2 * k]) | ((uint32_t)enc16<ST>((float)v[2 * k + 1]) << 16);
-    u.x = w[0];
-    u.y = w[1];
-    u.z = w[2];
-    u.w = w[3];
-  }
-  *reinterpret_cast<uint4 *>(p) = u;
-}
-
 // ------------------------------------------------------------------ k_tall
-// One workgroup per TILE rows.  Thread t owns rows base + VEC*(t + 256 v) + e.
-template <typename ST, int KIND, bool INTERIOR>
+// One workgroup per TILE rows; thread t owns rows base + VEC*(t + 256 v) + e.
+// FAST: every 16-byte vector of the tile is in bounds and aligned; head rows
+// (i < m) are loaded with the vector but excluded from the update by value, so
+// they keep their input values (head rows of W are refreshed in float64 from
+// U_1 = S_{1:m} by the reduction kernel).  !FAST: guarded element accesses
+// (ragged last tile or unaligned storage).
+template <typename ST, bool FAST, int NV>
 __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
                                           int32_t j, const double *__restrict__ cf,
                                           double iaprev, float *__restrict__ wstage,
                                           int64_t base,
-                                          typename CompT<ST>::type (&acc)[(TILE / 256) / (16 / sizeof(ST))][16 / sizeof(ST)]) {
+                                          typename CompT<ST>::type (&acc)[NV][16 / sizeof(ST)]) {
   using CT = typename CompT<ST>::type;
   constexpr int VEC = 16 / sizeof(ST);
-  constexpr int NV = (TILE / 256) / VEC;
   constexpr bool LOWP = !std::is_same<ST, double>::value;
   const int tid = threadIdx.x;
-  auto row = [&](int v) { return base + (int64_t)VEC * (tid + 256 * v); };
+  auto row = [&](int v) { return base + (int64_t)VEC * (tid + TALL_TPB * v); };
   auto ok = [&](int64_t i) { return i >= m && i < n; };
+  const bool head = base < m;  // uniform: the tile holds head rows
+
+  uint32_t off[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) off[v] = (uint32_t)((row(v) - base) * (int64_t)sizeof(ST));
 
   // acc <- w_j
   const ST *wj = W + (int64_t)j * ldw;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int64_t i0 = row(v);
-    if (INTERIOR) {
+    if (FAST) {
       vload(wj + i0, acc[v]);
     } else {
 #pragma unroll
       for (int e = 0; e < VEC; ++e) acc[v][e] = ok(i0 + e) ? cvt_in<CT>(wj[i0 + e]) : (CT)0;
     }
   }
-  // acc -= U_{:, <j-1} c (columns already scaled).  Interior tiles address each
-  // column through a uniform base pointer plus 32-bit per-thread offsets.
-  if (INTERIOR) {
-    uint32_t off[NV];
+  // acc -= U_{:, <j-1} c  (stored columns, already scaled)
+  if (FAST) {
+    if (!head) {
+#pragma unroll 2
+      for (int p = 0; p < j - 1; ++p) {
+        const CT cp = (CT)cf[p];
+        const char *cb = (const char *)(W + (int64_t)p * ldw + base);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) off[v] = (uint32_t)((row(v) - base) * (int64_t)sizeof(ST));
+        for (int v = 0; v < NV; ++v) {
+          CT x[VEC];
+          vload<ST, CT, true>((const ST *)(cb + off[v]), x);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[v][e] -= x[e] * cp;
+        }
+      }
+    } else {
 #pragma unroll 1
-    for (int p = 0; p < j - 1; ++p) {
-      const CT cp = (CT)cf[p];
-      const char *cb = (const char *)(W + (int64_t)p * ldw + base);
+      for (int p = 0; p < j - 1; ++p) {
+        const CT cp = (CT)cf[p];
+        const char *cb = (const char *)(W + (int64_t)p * ldw + base);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        CT x[VEC];
-        vload((const ST *)(cb + off[v]), x);
+        for (int v = 0; v < NV; ++v) {
+          const int64_t i0 = row(v);
+          CT x[VEC];
+          vload<ST, CT, true>((const ST *)(cb + off[v]), x);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[v][e] -= x[e] * cp;
+          for (int e = 0; e < VEC; ++e) acc[v][e] -= (i0 + e >= m) ? x[e] * cp : (CT)0;
+        }
       }
     }
   } else {
@@ -169,18 +132,19 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
       }
     }
   }
-  // previous column: raw refreshed values, scaled by 1/alpha_{j-1} and stored
+  // previous column: raw refreshed values, used, then stored scaled by
+  // 1/alpha_{j-1}.  Column 0 is never refreshed: its raw values are the input.
   if (j >= 1) {
     const CT cp = (CT)cf[j - 1];
     const CT ia = (CT)iaprev;
     ST *col = W + (int64_t)(j - 1) * ldw;
+    const bool from_stage = LOWP && j >= 2;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int64_t i0 = row(v);
       CT x[VEC], o[VEC];
-      // column 0 is never refreshed: its raw values are the input itself
-      if (LOWP && j >= 2) {
-        if (INTERIOR) {
+      if (FAST) {
+        if (from_stage) {
           const float4 *ws4 = reinterpret_cast<const float4 *>(wstage + i0);
 #pragma unroll
           for (int h = 0; h < VEC / 4; ++h) {
@@ -191,38 +155,33 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
             x[4 * h + 3] = f.w;
           }
         } else {
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) x[e] = ok(i0 + e) ? (CT)wstage[i0 + e] : (CT)0;
-        }
-      } else {
-        if (INTERIOR) {
           vload(col + i0, x);
-        } else {
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) x[e] = ok(i0 + e) ? cvt_in<CT>(col[i0 + e]) : (CT)0;
         }
-      }
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        acc[v][e] -= x[e] * cp;
-        o[e] = x[e] * ia;
-      }
-      if (INTERIOR) {
-        vstore(col + i0, o);
+        for (int e = 0; e < VEC; ++e) {
+          if (i0 + e >= m) acc[v][e] -= x[e] * cp;
+          o[e] = x[e] * ia;
+        }
+        vstore(col + i0, o);  // head rows are rewritten from S at the end
       } else {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          if (ok(i0 + e)) col[i0 + e] = cvt_out<ST>((double)o[e]);
+        for (int e = 0; e < VEC; ++e) {
+          if (ok(i0 + e)) {
+            x[e] = from_stage ? (CT)wstage[i0 + e] : cvt_in<CT>(col[i0 + e]);
+            acc[v][e] -= x[e] * cp;
+            col[i0 + e] = cvt_out<ST>((double)(x[e] * ia));
+          }
+        }
       }
     }
   }
-  // store the raw refreshed column
+  // store the raw refreshed column (float64: in place; otherwise: staging)
   ST *wjw = W + (int64_t)j * ldw;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int64_t i0 = row(v);
     if (LOWP) {
-      if (INTERIOR) {
+      if (FAST) {
         float4 *ws4 = reinterpret_cast<float4 *>(wstage + i0);
 #pragma unroll
         for (int h = 0; h < VEC / 4; ++h)
@@ -234,8 +193,8 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
           if (ok(i0 + e)) wstage[i0 + e] = (float)acc[v][e];
       }
     } else {
-      if (INTERIOR) {
-        vstore(wjw + i0, acc[v]);
+      if (FAST) {
+        vstore(wjw + i0, acc[v]);  // head rows hold their unchanged input values
       } else {
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
@@ -245,33 +204,62 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
   }
 }
 
-template <typename ST, int KIND>
-__global__ void __launch_bounds__(256, 4) k_tall(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
-                                              int32_t j, const double *__restrict__ cf,
-                                              const double *__restrict__ ia,
-                                              float *__restrict__ wstage, double *__restrict__ part,
-                                              const uint64_t *__restrict__ signs,
-                                              const int32_t *__restrict__ rows, int32_t l,
-                                              const double *__restrict__ om, int aligned) {
+// A tall workgroup covers TPW consecutive transform tiles (TPW * TILE rows),
+// so the per-column partials shrink by TPW.
+
+template <typename A, int TPW> __device__ void fwht_tiles_lds(A *s) {
+#pragma unroll 1
+  for (int pass = 0; pass < 3; ++pass) {
+    __syncthreads();
+    const int sh = 4 * pass;
+    for (int gg = threadIdx.x; gg < (TILE / 16) * TPW; gg += blockDim.x) {
+      A *st = s + (gg >> 8) * TILE_PAD;
+      const int g = gg & 255;
+      const int lo = g & ((1 << sh) - 1);
+      const int hi = g >> sh;
+      const int base = lo + (hi << (sh + 4));
+      A v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = st[tpad(base + (k << sh))];
+      fwht16(v);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) st[tpad(base + (k << sh))] = v[k];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename ST, int KIND, int TPW>
+__global__ void __launch_bounds__(TALL_TPB) k_tall(ST *__restrict__ W, int64_t ldw, int64_t n,
+                                                   int32_t m, int32_t j,
+                                                   const double *__restrict__ cf,
+                                                   const double *__restrict__ ia,
+                                                   float *__restrict__ wstage,
+                                                   double *__restrict__ part,
+                                                   const uint64_t *__restrict__ signs,
+                                                   const int32_t *__restrict__ rows, int32_t l,
+                                                   const double *__restrict__ om, int aligned) {
   using CT = typename CompT<ST>::type;
   constexpr int VEC = 16 / sizeof(ST);
-  constexpr int NV = (TILE / 256) / VEC;
-  __shared__ CT s[TILE_PAD];
-  const int64_t base = (int64_t)blockIdx.x * TILE;
-  const bool interior = aligned && base >= m && base + TILE <= n;
+  constexpr int ROWS = TILE * TPW;
+  constexpr int NV = ROWS / (TALL_TPB * VEC);
+  static_assert(NV >= 1, "tile too small for the vector width");
+  __shared__ CT s[TPW * TILE_PAD];
+  const int64_t base = (int64_t)blockIdx.x * ROWS;
+  const bool fast = aligned && base + ROWS <= n;
   const double iaprev = j >= 1 ? ia[j - 1] : 0.0;
   CT acc[NV][VEC];
-  if (interior)
-    tall_body<ST, KIND, true>(W, ldw, n, m, j, cf, iaprev, wstage, base, acc);
+  if (fast)
+    tall_body<ST, true, NV>(W, ldw, n, m, j, cf, iaprev, wstage, base, acc);
   else
-    tall_body<ST, KIND, false>(W, ldw, n, m, j, cf, iaprev, wstage, base, acc);
+    tall_body<ST, false, NV>(W, ldw, n, m, j, cf, iaprev, wstage, base, acc);
 
   if (KIND == RHQR_SKETCH_IDENT) return;
   const int tid = threadIdx.x;
   if (KIND == RHQR_SKETCH_SRHT) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int li0 = VEC * (tid + 256 * v);
+      const int li0 = VEC * (tid + TALL_TPB * v);
       const int64_t i0 = base + li0;
       const uint64_t word = (i0 < n) ? signs[i0 >> 6] : 0ull;
 #pragma unroll
@@ -279,55 +267,70 @@ __global__ void __launch_bounds__(256, 4) k_tall(ST *__restrict__ W, int64_t ldw
         const int64_t i = i0 + e;
         CT x = (i >= m && i < n) ? acc[v][e] : (CT)0;
         if ((word >> (i & 63)) & 1ull) x = -x;
-        s[tpad(li0 + e)] = x;
+        const int li = li0 + e;
+        s[(li >> TILE_LOG) * TILE_PAD + tpad(li & (TILE - 1))] = x;
       }
     }
-    fwht_tile_lds(s);
-    const uint64_t t = (uint64_t)blockIdx.x;
-    for (int q = tid; q < l; q += 256) {
+    fwht_tiles_lds<CT, TPW>(s);
+    const uint64_t t0 = (uint64_t)blockIdx.x * TPW;
+    for (int q = tid; q < l; q += TALL_TPB) {
       const int32_t r = rows[q];
-      const double h = (double)s[tpad(r & (TILE - 1))];
-      const bool neg = __popcll((uint64_t)(r >> TILE_LOG) & t) & 1;
-      part[(int64_t)blockIdx.x * l + q] = neg ? -h : h;
+      const int r2 = tpad(r & (TILE - 1));
+      const uint64_t r1 = (uint64_t)(r >> TILE_LOG);
+      double h = 0.0;
+#pragma unroll
+      for (int tt = 0; tt < TPW; ++tt) {
+        const double x = (double)s[tt * TILE_PAD + r2];
+        h += (__popcll(r1 & (t0 + tt)) & 1) ? -x : x;
+      }
+      part[(int64_t)blockIdx.x * l + q] = h;
     }
-  } else {  // Gaussian: partial Omega[:, tile] w~_tile
+  } else {  // Gaussian: partial Omega[:, rows] w~_rows, four row groups per sample
+    __shared__ double red[KIND == RHQR_SKETCH_GAUSS ? 1024 : 1];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int li0 = VEC * (tid + 256 * v);
+      const int li0 = VEC * (tid + TALL_TPB * v);
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         const int64_t i = base + li0 + e;
         s[li0 + e] = (i >= m && i < n) ? acc[v][e] : (CT)0;
       }
     }
-    __syncthreads();
     const int64_t lo = base > m ? base : (int64_t)m;
-    const int64_t hi = base + TILE < n ? base + TILE : n;
-    for (int q = tid; q < l; q += 256) {
-      double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-      int64_t i = lo;
-      for (; i + 3 < hi; i += 4) {
-        a0 += om[(i - m) * l + q] * (double)s[i - base];
-        a1 += om[(i + 1 - m) * l + q] * (double)s[i + 1 - base];
-        a2 += om[(i + 2 - m) * l + q] * (double)s[i + 2 - base];
-        a3 += om[(i + 3 - m) * l + q] * (double)s[i + 3 - base];
+    const int64_t hi = base + ROWS < n ? base + ROWS : n;
+    const int g = tid >> 8;
+    for (int q0 = 0; q0 < l; q0 += 256) {
+      __syncthreads();
+      const int q = q0 + (tid & 255);
+      double a0 = 0, a1 = 0;
+      if (q < l) {
+        int64_t i = lo + g;
+        for (; i + 4 < hi; i += 8) {
+          a0 += om[(i - m) * l + q] * (double)s[i - base];
+          a1 += om[(i + 4 - m) * l + q] * (double)s[i + 4 - base];
+        }
+        for (; i < hi; i += 4) a0 += om[(i - m) * l + q] * (double)s[i - base];
       }
-      for (; i < hi; ++i) a0 += om[(i - m) * l + q] * (double)s[i - base];
-      part[(int64_t)blockIdx.x * l + q] = (a0 + a1) + (a2 + a3);
+      red[g * 256 + (tid & 255)] = a0 + a1;
+      __syncthreads();
+      if (g == 0 && q < l)
+        part[(int64_t)blockIdx.x * l + q] =
+            (red[tid] + red[256 + tid]) + (red[512 + tid] + red[768 + tid]);
     }
   }
 }
 
 // ------------------------------------------------------------------- k_red
 // y = Psi w~_j.  Head rows: y_k = w_{k,j} - sum_{p<j} S_{k,p} c_p (float64);
-// tail rows: sum of the tile partials (SRHT scaled by l^-1/2), or the refreshed
-// rows themselves for Psi = I.  Sixteen waves split the summation index.
+// tail rows: sum of the per-workgroup partials (SRHT scaled by l^-1/2), or the
+// refreshed rows themselves for Psi = I.  Sixteen waves split the summation
+// index; each lane keeps four independent partial sums.
 template <typename ST, int KIND>
 __global__ void __launch_bounds__(1024) k_red(const ST *__restrict__ W, int64_t ldw, int32_t m,
                                               int32_t l, int32_t j, const double *__restrict__ Z,
                                               int64_t ldz, const double *__restrict__ S, int64_t lds,
                                               const double *__restrict__ c,
-                                              const double *__restrict__ part, int64_t ntiles,
+                                              const double *__restrict__ part, int64_t nparts,
                                               double scale, double *__restrict__ y,
                                               double *__restrict__ sq) {
   __shared__ double red[16][RED_CHUNK + 1];
@@ -336,17 +339,31 @@ __global__ void __launch_bounds__(1024) k_red(const ST *__restrict__ W, int64_t 
   const bool head = (int)blockIdx.x < nhb;
   const int k = head ? (int)blockIdx.x * RED_CHUNK + lane : m + ((int)blockIdx.x - nhb) * RED_CHUNK + lane;
   const bool valid = head ? (k < m) : (k < m + l);
-  double v = 0.0;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
   if (valid && j >= 1) {
     if (head) {
       const int pe = min(j, k + 1);
-      for (int p = w; p < pe; p += 16) v += S[k + (int64_t)p * lds] * c[p];
+      int p = w;
+      for (; p + 48 < pe; p += 64) {
+        v0 += S[k + (int64_t)p * lds] * c[p];
+        v1 += S[k + (int64_t)(p + 16) * lds] * c[p + 16];
+        v2 += S[k + (int64_t)(p + 32) * lds] * c[p + 32];
+        v3 += S[k + (int64_t)(p + 48) * lds] * c[p + 48];
+      }
+      for (; p < pe; p += 16) v0 += S[k + (int64_t)p * lds] * c[p];
     } else if (KIND != RHQR_SKETCH_IDENT) {
-      const int q = k - m;
-      for (int64_t t = w; t < ntiles; t += 16) v += part[t * l + q];
+      const double *pq = part + (k - m);
+      int64_t t = w;
+      for (; t + 48 < nparts; t += 64) {
+        v0 += pq[t * l];
+        v1 += pq[(t + 16) * l];
+        v2 += pq[(t + 32) * l];
+        v3 += pq[(t + 48) * l];
+      }
+      for (; t < nparts; t += 16) v0 += pq[t * l];
     }
   }
-  red[w][lane] = v;
+  red[w][lane] = (v0 + v1) + (v2 + v3);
   __syncthreads();
   if (w == 0) {
     double s = 0.0;
@@ -372,7 +389,7 @@ __global__ void __launch_bounds__(1024) k_red(const ST *__restrict__ W, int64_t 
 // -------------------------------------------------------------------- k_ss
 struct StepScalars {
   double sigma, rho, alpha, beta, gamma;
-  bool ident;
+  int ident;
 };
 
 __device__ __forceinline__ StepScalars step_scalars(const double *y, const double *sq, int gred,
@@ -401,6 +418,10 @@ __device__ __forceinline__ StepScalars step_scalars(const double *y, const doubl
   return r;
 }
 
+// RHVector (Alg. 2) on the sketch y: scalars, s_j = S_{:,j}, R_{:,j}, and the
+// partial dot products of this workgroup's RED_CHUNK rows: S_{:,p}^t s_j
+// (p < j) and S_{:,p}^t z_{j+1} (p <= j).  One wave per p; the S loads of
+// eight p's are issued before their reductions.
 __global__ void __launch_bounds__(1024) k_ss(int32_t m, int32_t l, int32_t j, int scaling,
                                              const double *__restrict__ y,
                                              const double *__restrict__ sq, int gred,
@@ -416,8 +437,9 @@ __global__ void __launch_bounds__(1024) k_ss(int32_t m, int32_t l, int32_t j, in
   const int L = l + m;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int k = (int)blockIdx.x * RED_CHUNK + lane;
+  const bool kv = k < L;
   double s = 0.0;
-  if (k < L) {
+  if (kv) {
     if (k == j)
       s = sc.ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : sc.gamma / sc.alpha);
     else if (k > j)
@@ -425,14 +447,25 @@ __global__ void __launch_bounds__(1024) k_ss(int32_t m, int32_t l, int32_t j, in
     if (w == 0) S[k + (int64_t)j * lds] = s;
   }
   const bool neede = j + 1 < m;
-  const double z = (neede && k < L) ? Z[k + (int64_t)(j + 1) * ldz] : 0.0;
-  for (int p = w; p <= j; p += 16) {
-    const double sp = (k < L) ? (p < j ? S[k + (int64_t)p * lds] : s) : 0.0;
-    const double dv = wave_sum(sp * s);
-    const double ev = wave_sum(sp * z);
-    if (lane == 0) {
-      if (p < j) dpart[(int64_t)blockIdx.x * m + p] = dv;
-      if (neede) epart[(int64_t)blockIdx.x * m + p] = ev;
+  const double z = (neede && kv) ? Z[k + (int64_t)(j + 1) * ldz] : 0.0;
+  for (int p0 = w; p0 <= j; p0 += 16 * 8) {
+    double sp[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int p = p0 + 16 * b;
+      sp[b] = (kv && p <= j) ? (p < j ? S[k + (int64_t)p * lds] : s) : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int p = p0 + 16 * b;
+      if (p <= j) {  // uniform across the wave
+        const double dv = wave_sum(sp[b] * s);
+        const double ev = neede ? wave_sum(sp[b] * z) : 0.0;
+        if (lane == 0) {
+          if (p < j) dpart[(int64_t)blockIdx.x * m + p] = dv;
+          if (neede) epart[(int64_t)blockIdx.x * m + p] = ev;
+        }
+      }
     }
   }
   if (blockIdx.x == 0) {
@@ -449,67 +482,99 @@ __global__ void __launch_bounds__(1024) k_ss(int32_t m, int32_t l, int32_t j, in
 }
 
 // ------------------------------------------------------------------- k_fin
+// T_{p,j} = -beta (T_{j-1} d)_p and c_{j+1,p} = (T_{j-1}^t e)_p for p < j,
+// d = S^t s_j, e = S^t z_{j+1} (reduced from the k_ss partials), one wave per
+// p, FIN_P values of p per workgroup.  T_{j,j} = beta.  The workgroup that
+// finishes last (device-scope counter) forms the last coefficient
+// c_{j+1,j} = beta (e_j - d . c_{:j}) and the folded copy cf used by the next
+// tall pass (the raw column j is divided by alpha_j there).
+constexpr int FIN_P = 16;
+
 __global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t j, int gss,
                                               const double *__restrict__ dpart,
                                               const double *__restrict__ epart,
                                               const double *__restrict__ scal, double *__restrict__ T,
                                               int64_t ldt, double *__restrict__ Tt,
                                               double *__restrict__ c, double *__restrict__ cf,
-                                              double *__restrict__ ia) {
-  __shared__ double d[MAXM], e[MAXM], tc[MAXM];
+                                              double *__restrict__ ia, uint32_t *__restrict__ counter) {
+  __shared__ double d[MAXM], e[MAXM];
+  __shared__ int last;
   const double rho = scal[4 * j + 1], alpha = scal[4 * j + 2], beta = scal[4 * j + 3];
   const bool needc = j + 1 < m;
-  for (int p = threadIdx.x; p < j; p += blockDim.x) {
-    double s = 0.0;
-    for (int g = 0; g < gss; ++g) s += dpart[(int64_t)g * m + p];
-    d[p] = s;
-  }
-  if (needc)
-    for (int p = threadIdx.x; p <= j; p += blockDim.x) {
-      double s = 0.0;
-      for (int g = 0; g < gss; ++g) s += epart[(int64_t)g * m + p];
-      e[p] = s;
-    }
-  __syncthreads();
-  const int sub = threadIdx.x & 3;
-  for (int p0 = 0; p0 < j; p0 += 256) {
-    const int p = p0 + (threadIdx.x >> 2);
-    double v = 0.0;
-    if (p < j)
-      for (int q = p + sub; q < j; q += 4) v += T[p + (int64_t)q * ldt] * d[q];
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    if (sub == 0 && p < j) {
-      const double t = -beta * v;
-      tc[p] = t;
-      T[p + (int64_t)j * ldt] = t;
-      Tt[j + (int64_t)p * m] = t;
-    }
-  }
-  if (threadIdx.x == 0) {
-    tc[j] = beta;
-    T[j + (int64_t)j * ldt] = beta;
-    Tt[j + (int64_t)j * m] = beta;
-  }
-  __syncthreads();
-  const double iaj = rho > 0.0 ? 1.0 / alpha : 0.0;
-  if (needc) {
-    for (int p0 = 0; p0 <= j; p0 += 256) {
-      const int p = p0 + (threadIdx.x >> 2);
-      double v = 0.0;
-      if (p < j)
-        for (int q = sub; q <= p; q += 4) v += Tt[p + (int64_t)q * m] * e[q];
-      else if (p == j)
-        for (int q = sub; q <= j; q += 4) v += tc[q] * e[q];
-      v += __shfl_xor(v, 1, 64);
-      v += __shfl_xor(v, 2, 64);
-      if (sub == 0 && p <= j) {
-        c[p] = v;
-        cf[p] = p == j ? v * iaj : v;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // reduce the partial dot products: 64 indices x 16 group lanes per pass
+  {
+    const int pl = threadIdx.x >> 4, gl = threadIdx.x & 15;
+    const int np = needc ? j + 1 : j;
+    for (int p0 = 0; p0 < np; p0 += 64) {
+      const int p = p0 + pl;
+      double dv = 0.0, ev = 0.0;
+      if (p < np) {
+        for (int g = gl; g < gss; g += 16) {
+          if (p < j) dv += dpart[(int64_t)g * m + p];
+          if (needc) ev += epart[(int64_t)g * m + p];
+        }
+      }
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        dv += __shfl_xor(dv, o, 64);
+        ev += __shfl_xor(ev, o, 64);
+      }
+      if (gl == 0 && p < np) {
+        d[p] = dv;
+        e[p] = ev;
       }
     }
   }
-  if (threadIdx.x == 0) ia[j] = iaj;
+  __syncthreads();
+  const int p = (int)blockIdx.x * FIN_P + w;
+  if (w < FIN_P && p < j) {
+    double td = 0.0, te = 0.0;
+    for (int q = p + lane; q < j; q += 64) td += Tt[q + (int64_t)p * m] * d[q];  // T_{p,q}
+    if (needc)
+      for (int q = lane; q <= p; q += 64) te += T[q + (int64_t)p * ldt] * e[q];  // T_{q,p}
+    td = wave_sum(td);
+    te = wave_sum(te);
+    if (lane == 0) {
+      const double t = -beta * td;
+      T[p + (int64_t)j * ldt] = t;
+      Tt[j + (int64_t)p * m] = t;
+      if (needc) {
+        c[p] = te;
+        cf[p] = te;
+      }
+    }
+  }
+  // last workgroup: diagonal, last coefficient, 1/alpha_j
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const double iaj = rho > 0.0 ? 1.0 / alpha : 0.0;
+  if (w == 0) {
+    double dc = 0.0;
+    if (needc)
+      for (int q = lane; q < j; q += 64) {
+        // written by other workgroups of this launch: device-coherent load
+        const unsigned long long bits = __hip_atomic_load(
+            reinterpret_cast<unsigned long long *>(c + q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        dc += d[q] * __longlong_as_double((long long)bits);
+      }
+    dc = wave_sum(dc);
+    if (lane == 0) {
+      T[j + (int64_t)j * ldt] = beta;
+      Tt[j + (int64_t)j * m] = beta;
+      if (needc) {
+        const double cj = beta * (e[j] - dc);
+        c[j] = cj;
+        cf[j] = cj * iaj;
+      }
+      ia[j] = iaj;
+      *counter = 0u;
+    }
+  }
 }
 
 // ------------------------------------------------------------ final stores
@@ -615,12 +680,43 @@ __global__ void __launch_bounds__(256) k_gemm_tall(const ST *__restrict__ A, int
 }
 
 // ------------------------------------------------------------ host helpers
+// Tiles per tall workgroup: about one workgroup per compute unit, at least
+// two tiles for 2-byte types (16-byte loads need 8 rows per thread).
+inline int tall_tpw(int64_t n, size_t elt) {
+  const int64_t ntiles = (n + TILE - 1) / TILE;
+  int tpw = ntiles >= 1024 ? 4 : ntiles >= 512 ? 2 : 1;
+  if (elt == 2 && tpw < 2) tpw = 2;
+  return tpw;
+}
+
+template <typename ST, int KIND, int TPW>
+void launch_tall(const LoopArgs &a, const LoopWs &w, int32_t j, int aligned, hipStream_t st) {
+  const int64_t rows = (int64_t)TILE * TPW;
+  const int64_t g = (a.n + rows - 1) / rows;
+  hipLaunchKernelGGL((k_tall<ST, KIND, TPW>), dim3(g), dim3(TALL_TPB), 0, st, (ST *)a.W, a.ldw, a.n,
+                     a.m, j, w.cf, w.ia, w.wstage, w.part, a.signs, a.rows, a.l, a.omega, aligned);
+}
+
+template <typename ST, int KIND>
+void launch_tall_k(const LoopArgs &a, const LoopWs &w, int32_t j, int aligned, int tpw,
+                   hipStream_t st) {
+  if constexpr (sizeof(ST) == 2) {
+    if (tpw == 4) launch_tall<ST, KIND, 4>(a, w, j, aligned, st);
+    else launch_tall<ST, KIND, 2>(a, w, j, aligned, st);
+  } else {
+    if (tpw == 4) launch_tall<ST, KIND, 4>(a, w, j, aligned, st);
+    else if (tpw == 2) launch_tall<ST, KIND, 2>(a, w, j, aligned, st);
+    else launch_tall<ST, KIND, 1>(a, w, j, aligned, st);
+  }
+}
+
 template <typename ST>
 int run_typed(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
   ST *W = (ST *)a.W;
   const int64_t n = a.n;
   const int32_t m = a.m, l = a.l, L = l + m;
-  const int64_t ntiles = (n + TILE - 1) / TILE;
+  const int tpw = tall_tpw(n, sizeof(ST));
+  const int64_t nparts = (n + (int64_t)TILE * tpw - 1) / ((int64_t)TILE * tpw);
   const int gred = (m + RED_CHUNK - 1) / RED_CHUNK + (l + RED_CHUNK - 1) / RED_CHUNK;
   const int gss = (L + RED_CHUNK - 1) / RED_CHUNK;
   const double scale = a.kind == RHQR_SKETCH_SRHT ? 1.0 / std::sqrt((double)l) : 1.0;
@@ -633,38 +729,28 @@ int run_typed(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
         RHQR_HIP(hipEventRecord(e0, st));
       }
       switch (a.kind) {
-        case RHQR_SKETCH_SRHT:
-          hipLaunchKernelGGL((k_tall<ST, RHQR_SKETCH_SRHT>), dim3(ntiles), dim3(256), 0, st, W,
-                             a.ldw, n, m, j, w.cf, w.ia, w.wstage, w.part, a.signs, a.rows, l,
-                             a.omega, aligned);
-          break;
-        case RHQR_SKETCH_GAUSS:
-          hipLaunchKernelGGL((k_tall<ST, RHQR_SKETCH_GAUSS>), dim3(ntiles), dim3(256), 0, st, W,
-                             a.ldw, n, m, j, w.cf, w.ia, w.wstage, w.part, a.signs, a.rows, l,
-                             a.omega, aligned);
-          break;
-        default:
-          hipLaunchKernelGGL((k_tall<ST, RHQR_SKETCH_IDENT>), dim3(ntiles), dim3(256), 0, st, W,
-                             a.ldw, n, m, j, w.cf, w.ia, w.wstage, w.part, a.signs, a.rows, l,
-                             a.omega, aligned);
+        case RHQR_SKETCH_SRHT: launch_tall_k<ST, RHQR_SKETCH_SRHT>(a, w, j, aligned, tpw, st); break;
+        case RHQR_SKETCH_GAUSS: launch_tall_k<ST, RHQR_SKETCH_GAUSS>(a, w, j, aligned, tpw, st); break;
+        default: launch_tall_k<ST, RHQR_SKETCH_IDENT>(a, w, j, aligned, tpw, st);
       }
       RHQR_HIP(hipGetLastError());
       if (g_prof.on) RHQR_HIP(hipEventRecord(e1, st));
     }
     if (a.kind == RHQR_SKETCH_IDENT)
       hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_IDENT>), dim3(gred), dim3(1024), 0, st, W, a.ldw,
-                         m, l, j, a.Z + (int64_t)j * a.ldz, a.ldz, a.S, a.lds, w.c, w.part, ntiles,
+                         m, l, j, a.Z + (int64_t)j * a.ldz, a.ldz, a.S, a.lds, w.c, w.part, nparts,
                          scale, w.y, w.sq);
     else
       hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_SRHT>), dim3(gred), dim3(1024), 0, st, W, a.ldw, m,
-                         l, j, a.Z + (int64_t)j * a.ldz, a.ldz, a.S, a.lds, w.c, w.part, ntiles,
+                         l, j, a.Z + (int64_t)j * a.ldz, a.ldz, a.S, a.lds, w.c, w.part, nparts,
                          scale, w.y, w.sq);
     RHQR_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_ss, dim3(gss), dim3(1024), 0, st, m, l, j, a.scaling, w.y, w.sq, gred,
                        a.S, a.lds, a.Z, a.ldz, w.dpart, w.epart, w.scal, a.R, a.ldr, w.status);
     RHQR_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_fin, dim3(1), dim3(1024), 0, st, m, j, gss, w.dpart, w.epart, w.scal, a.T,
-                       a.ldt, w.Tt, w.c, w.cf, w.ia);
+    const int gfin = j > 0 ? (j + FIN_P - 1) / FIN_P : 1;
+    hipLaunchKernelGGL(k_fin, dim3(gfin), dim3(1024), 0, st, m, j, gss, w.dpart, w.epart, w.scal,
+                       a.T, a.ldt, w.Tt, w.c, w.cf, w.ia, w.counter);
     RHQR_HIP(hipGetLastError());
   }
   const int64_t ntail = n - m;
@@ -739,6 +825,7 @@ int loop_ws_carve(void *ws, size_t bytes, int kind, int dtype, int64_t n, int32_
     return (void *)r;
   };
   o->status = (int32_t *)take(sizeof(int32_t) * 4);
+  o->counter = (uint32_t *)(o->status + 2);
   o->y = (double *)take(sizeof(double) * L);
   o->sq = (double *)take(sizeof(double) * gred);
   o->dpart = (double *)take(sizeof(double) * (size_t)gss * m);

@@ -140,32 +140,70 @@ __global__ void k_gauss(double *om, int64_t count, uint64_t seed, double inv_sqr
 // ------------------------------------------------------------ RHSketch, SRHT
 // Grid (gt, k): workgroup (g, c) transforms tiles t = g, g+gt, ... of column c
 // and accumulates its contribution to each of the l samples; part[c][g][q].
+// The next tile's loads are issued before the current tile's transform.
 template <typename ST, typename AT>
+__device__ __forceinline__ void load_tile(const ST *__restrict__ x, int64_t base, int64_t n,
+                                          int32_t m, bool fast,
+                                          AT (&o)[(TILE / 256) / (16 / sizeof(ST))][16 / sizeof(ST)]) {
+  constexpr int VEC = 16 / sizeof(ST);
+  constexpr int NV = (TILE / 256) / VEC;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int64_t i0 = base + (int64_t)VEC * (threadIdx.x + 256 * v);
+    if (fast) {
+      vload<ST, AT, true>(x + i0, o[v]);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+        if (i0 + e < m) o[v][e] = (AT)0;
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const int64_t i = i0 + e;
+        o[v][e] = (i >= m && i < n) ? cvt_in<AT>(x[i]) : (AT)0;
+      }
+    }
+  }
+}
+
+template <typename ST, typename AT, int QA>
 __global__ void __launch_bounds__(256) k_srht_cols(const ST *__restrict__ X, int64_t ldx, int64_t n,
                                                    int32_t m, int32_t l, int64_t ntiles, int gt,
                                                    const uint64_t *__restrict__ signs,
                                                    const int32_t *__restrict__ rows,
-                                                   double *__restrict__ part) {
+                                                   double *__restrict__ part, int aligned) {
+  constexpr int VEC = 16 / sizeof(ST);
+  constexpr int NV = (TILE / 256) / VEC;
   __shared__ AT s[TILE_PAD];
-  constexpr int QA = TILE / 256;  // l <= TILE
   const int c = blockIdx.y;
   const ST *x = X + (int64_t)c * ldx;
   double acc[QA];
 #pragma unroll
   for (int a = 0; a < QA; ++a) acc[a] = 0.0;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gt) {
+  AT cur[NV][VEC], nxt[NV][VEC];
+  int64_t t = blockIdx.x;
+  if (t < ntiles) {
+    const int64_t base = t << TILE_LOG;
+    load_tile<ST, AT>(x, base, n, m, aligned && base + TILE <= n, cur);
+  }
+  for (; t < ntiles; t += gt) {
     const int64_t base = t << TILE_LOG;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < TILE / 256; ++r) {
-      const int li = threadIdx.x + 256 * r;
-      const int64_t i = base + li;
-      AT v = 0;
-      if (i >= m && i < n) {
-        v = cvt_in<AT>(x[i]);
-        if (sign_bit(signs, i)) v = -v;
+    for (int v = 0; v < NV; ++v) {
+      const int li0 = VEC * (threadIdx.x + 256 * v);
+      const int64_t i0 = base + li0;
+      const uint64_t word = i0 < n ? signs[i0 >> 6] : 0ull;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        AT val = cur[v][e];
+        if ((word >> ((i0 + e) & 63)) & 1ull) val = -val;
+        s[tpad(li0 + e)] = val;
       }
-      s[tpad(li)] = v;
+    }
+    const int64_t tn = t + gt;
+    if (tn < ntiles) {
+      const int64_t bn = tn << TILE_LOG;
+      load_tile<ST, AT>(x, bn, n, m, aligned && bn + TILE <= n, nxt);
     }
     fwht_tile_lds(s);
 #pragma unroll
@@ -178,6 +216,10 @@ __global__ void __launch_bounds__(256) k_srht_cols(const ST *__restrict__ X, int
         acc[a] += neg ? -(double)h : (double)h;
       }
     }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) cur[v][e] = nxt[v][e];
   }
 #pragma unroll
   for (int a = 0; a < QA; ++a) {
@@ -270,8 +312,20 @@ int launch_typed(const rhqr_sketch_s *h, int64_t n, int32_t k, const ST *X, int6
   sketch_tail_partials_size(h, k, &gt, &need);
   if (h->kind == RHQR_SKETCH_SRHT) {
     const int64_t ntiles = (n + TILE - 1) / TILE;
-    hipLaunchKernelGGL((k_srht_cols<ST, CT>), dim3(gt, k), dim3(256), 0, st, X, ldx, n, m, l,
-                       ntiles, gt, h->d_signs, h->d_rows, part);
+    const int aligned = ((uintptr_t)X % 16 == 0) && ((ldx * (int64_t)sizeof(ST)) % 16 == 0);
+    // samples per thread: ceil(l / 256), rounded up to a power of two
+    const int qa = l <= 256 ? 1 : l <= 512 ? 2 : l <= 1024 ? 4 : l <= 2048 ? 8 : 16;
+#define RHQR_SRHT_COLS(Q)                                                                        \
+  hipLaunchKernelGGL((k_srht_cols<ST, CT, Q>), dim3(gt, k), dim3(256), 0, st, X, ldx, n, m, l,   \
+                     ntiles, gt, h->d_signs, h->d_rows, part, aligned)
+    switch (qa) {
+      case 1: RHQR_SRHT_COLS(1); break;
+      case 2: RHQR_SRHT_COLS(2); break;
+      case 4: RHQR_SRHT_COLS(4); break;
+      case 8: RHQR_SRHT_COLS(8); break;
+      default: RHQR_SRHT_COLS(16); break;
+    }
+#undef RHQR_SRHT_COLS
     RHQR_HIP(hipGetLastError());
     hipLaunchKernelGGL((k_sketch_finish<ST>), dim3((m + l + 255) / 256, k), dim3(256), 0, st, X,
                        ldx, m, l, gt, part, 1.0 / std::sqrt((double)l), Y, ldy);
