@@ -33,6 +33,10 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#ifndef RHQR_API
+#define RHQR_API __attribute__((visibility("default")))
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -79,17 +83,17 @@ typedef struct rhqr_arnoldi_s *rhqr_arnoldi_t;
  * on `stream`; the call synchronises `stream` before it returns.
  * Passage: Sec. 2.3 (Gaussian and SRHT embeddings), eq. psi.
  * ---------------------------------------------------------------------- */
-int rhqr_sketch_create(int kind, int64_t n, int32_t m, int32_t l, uint64_t seed,
+RHQR_API int rhqr_sketch_create(int kind, int64_t n, int32_t m, int32_t l, uint64_t seed,
                        const double *d_omega, int64_t ld_omega, void *stream,
                        rhqr_sketch_t *out);
-int rhqr_sketch_destroy(rhqr_sketch_t h);
+RHQR_API int rhqr_sketch_destroy(rhqr_sketch_t h);
 
 /* Copies of the draw, for inspection: h_signs receives ceil(N/64) words (bit
  * i%64 of word i/64 set <=> D_ii = -1), h_rows the l sampled rows (int32,
  * increasing).  GAUSS: h_omega receives l x (n-m) entries (ld = l).  Any
  * pointer may be NULL.  Synchronous. */
-int rhqr_sketch_get(rhqr_sketch_t h, uint64_t *h_signs, int32_t *h_rows, double *h_omega);
-int rhqr_sketch_info(rhqr_sketch_t h, int64_t *n, int32_t *m, int32_t *l, int64_t *N, int32_t *kind);
+RHQR_API int rhqr_sketch_get(rhqr_sketch_t h, uint64_t *h_signs, int32_t *h_rows, double *h_omega);
+RHQR_API int rhqr_sketch_info(rhqr_sketch_t h, int64_t *n, int32_t *m, int32_t *l, int64_t *N, int32_t *kind);
 
 /* ------------------------------------------------------------------------
  * rhqr_sketch: Y = Psi X  (RHSketch, Alg. 1).
@@ -99,8 +103,8 @@ int rhqr_sketch_info(rhqr_sketch_t h, int64_t *n, int32_t *m, int32_t *l, int64_
  * SRHT order as Lemma srht: signs, Walsh-Hadamard transform, sampling; the
  * normalisation sqrt(N/l) * N^-1/2 = l^-1/2 is applied once to the samples.
  * ---------------------------------------------------------------------- */
-size_t rhqr_sketch_workspace_size(rhqr_sketch_t h, int32_t k);
-int rhqr_sketch(rhqr_sketch_t h, int dtype, int64_t n, int32_t k, const void *d_X,
+RHQR_API size_t rhqr_sketch_workspace_size(rhqr_sketch_t h, int32_t k);
+RHQR_API int rhqr_sketch(rhqr_sketch_t h, int dtype, int64_t n, int32_t k, const void *d_X,
                 int64_t ldx, double *d_Y, int64_t ldy, void *d_ws, size_t ws_bytes,
                 void *stream);
 
@@ -119,8 +123,8 @@ int rhqr_sketch(rhqr_sketch_t h, int dtype, int64_t n, int32_t k, const void *d_
  * Breakdown (rho_j = 0) gives an identity reflector (beta_j = 0, R_jj = 0) and
  * is reported by rhqr_status.
  * ---------------------------------------------------------------------- */
-size_t rhqr_factor_workspace_size(rhqr_sketch_t h, int dtype, int32_t m);
-int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W, int64_t ldw,
+RHQR_API size_t rhqr_factor_workspace_size(rhqr_sketch_t h, int dtype, int32_t m);
+RHQR_API int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W, int64_t ldw,
                 double *d_S, int64_t lds, double *d_T, int64_t ldt, double *d_R,
                 int64_t ldr, void *d_Q, int64_t ldq, int scaling, void *d_ws,
                 size_t ws_bytes, void *stream);
@@ -128,7 +132,7 @@ int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W, int
 /* Status of the last rhqr_factor / recrhqr_factor / Arnoldi call that used
  * this workspace: 0, or j (1-based) of the first column with rho_j = 0.
  * Synchronises `stream`. */
-int rhqr_status(const void *d_ws, void *stream, int32_t *h_info);
+RHQR_API int rhqr_status(const void *d_ws, void *stream, int32_t *h_info);
 
 /* ------------------------------------------------------------------------
  * recrhqr_factor: recRHQR (Alg. 6), one synchronisation.
@@ -138,34 +142,47 @@ int rhqr_status(const void *d_ws, void *stream, int32_t *h_info);
  *   mode RHQR_REC_RCHOL: Q = W R^-1 (d_U may be NULL).
  *   d_W is read only; d_U (n x m, dtype) receives U; d_Q optional.
  * ---------------------------------------------------------------------- */
-size_t recrhqr_workspace_size(rhqr_sketch_t h, int dtype, int32_t m);
-int recrhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, const void *d_W,
+RHQR_API size_t recrhqr_workspace_size(rhqr_sketch_t h, int dtype, int32_t m);
+RHQR_API int recrhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, const void *d_W,
                    int64_t ldw, void *d_U, int64_t ldu, double *d_S, int64_t lds,
                    double *d_T, int64_t ldt, double *d_R, int64_t ldr, void *d_Q,
                    int64_t ldq, int mode, void *d_ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
- * RHQR-Arnoldi (Alg. 7).  The operator stays with the caller.
+ * RHQR-Arnoldi (Alg. 7, Sec. 5).  The operator stays with the caller.
  *   rhqr_arnoldi_create: state for up to mmax Arnoldi steps; the sketch handle
- *     must have head m = mmax + 1.  The basis U ((n x (mmax+1)), dtype) lives in
- *     the state (device memory owned by the state).
- *   rhqr_arnoldi_start(r0): r0 = b - A x0 (n, dtype, device).  Forms u_1, and
- *     writes q_1 (n, dtype, device) and beta = (h_0)_1 (host, synchronous).
+ *     must have head m = mmax + 1 (the loop forms mmax + 1 reflectors).  The
+ *     state owns its device memory (basis U, n x (mmax+1) in dtype, S, T, H).
+ *   rhqr_arnoldi_start(r0): r0 = b - A x0 (n, dtype, device).  Forms u_1 from
+ *     r0 and its sketch, writes q_1 (n, dtype, device) and, on the host,
+ *     beta = (h_0)_1 = -sigma_1 rho_1 so that r0 = beta q_1.  Synchronous.
  *   rhqr_arnoldi_step(w): w = A q_j (n, dtype, device) for the current j.
- *     Applies the j reflectors to w, forms u_{j+1}, writes h_j (mmax+1 float64,
- *     device; rows > j+1 zero) and q_{j+1} (n, dtype, device).
- *   rhqr_arnoldi_solution: x += Q_j y for y (j float64, device): x (n, dtype).
+ *     Sketches w, refreshes it with the j reflectors (w - U T^t S^t Psi w),
+ *     re-sketches, forms u_{j+1}, writes h_j ((mmax+1) float64, device; rows
+ *     > j+1 are zero) and q_{j+1} (n, dtype, device; NULL to skip).  Returns
+ *     -1 once mmax steps have been taken.
+ *   rhqr_arnoldi_solution(j, y): x += Q_j y (y: j float64 values, device;
+ *     x: n, dtype, device), 1 <= j <= number of steps taken.
+ *   rhqr_arnoldi_basis: device pointers of U (tail rows; the head rows of the
+ *     Householder vectors are the head rows of S), S ((l+mmax+1) x (mmax+1),
+ *     ld l+mmax+1) and T ((mmax+1) x (mmax+1), ld mmax+1).  The most recent
+ *     column of U is stored before its division by alpha.
+ * rhqr_spmv_csr: y = A x for A in CSR (row pointers int64, column indices
+ *   int32, values float64; n rows), x and y in dtype, float64 accumulation.
+ *   Device pointers; asynchronous.
  * ---------------------------------------------------------------------- */
-int rhqr_arnoldi_create(rhqr_sketch_t h, int dtype, int64_t n, int32_t mmax, void *stream,
+RHQR_API int rhqr_arnoldi_create(rhqr_sketch_t h, int dtype, int64_t n, int32_t mmax, void *stream,
                         rhqr_arnoldi_t *out);
-int rhqr_arnoldi_destroy(rhqr_arnoldi_t a);
-int rhqr_arnoldi_start(rhqr_arnoldi_t a, const void *d_r0, void *d_q1, double *h_beta,
+RHQR_API int rhqr_arnoldi_destroy(rhqr_arnoldi_t a);
+RHQR_API int rhqr_arnoldi_start(rhqr_arnoldi_t a, const void *d_r0, void *d_q1, double *h_beta,
                        void *stream);
-int rhqr_arnoldi_step(rhqr_arnoldi_t a, const void *d_w, void *d_qnext, double *d_hcol,
+RHQR_API int rhqr_arnoldi_step(rhqr_arnoldi_t a, const void *d_w, void *d_qnext, double *d_hcol,
                       void *stream);
-int rhqr_arnoldi_solution(rhqr_arnoldi_t a, int32_t j, const double *d_y, void *d_x,
+RHQR_API int rhqr_arnoldi_solution(rhqr_arnoldi_t a, int32_t j, const double *d_y, void *d_x,
                           void *stream);
-int rhqr_arnoldi_basis(rhqr_arnoldi_t a, void **d_U, double **d_S, double **d_T);
+RHQR_API int rhqr_arnoldi_basis(rhqr_arnoldi_t a, void **d_U, double **d_S, double **d_T);
+RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int32_t *d_idx,
+                  const double *d_val, const void *d_x, void *d_y, void *stream);
 
 /* ------------------------------------------------------------------------
  * Measurement aid.  Between rhqr_profile_begin() and rhqr_profile_end(), every
@@ -175,8 +192,8 @@ int rhqr_arnoldi_basis(rhqr_arnoldi_t a, void **d_U, double **d_S, double **d_T)
  * the summed kernel time (ms) and the number of launches.  Host-side state,
  * not thread-safe; intended for benchmarks.
  * ---------------------------------------------------------------------- */
-int rhqr_profile_begin(void);
-int rhqr_profile_end(double *total_ms, int64_t *launches);
+RHQR_API int rhqr_profile_begin(void);
+RHQR_API int rhqr_profile_end(double *total_ms, int64_t *launches);
 
 #ifdef __cplusplus
 }

@@ -47,6 +47,11 @@ size_t loop_ws_bytes(int kind, int dtype, int64_t n, int32_t m, int32_t l);
 int loop_ws_carve(void *ws, size_t bytes, int kind, int dtype, int64_t n, int32_t m, int32_t l,
                   LoopWs *out);
 int run_column_loop(const LoopArgs &a, const LoopWs &w, hipStream_t st);
+// single-column pieces of the loop (used by the Arnoldi process):
+// the tall refresh + re-sketch pass of column j (j >= 1), and the float64 step
+// (reduction, RHVector, T column; c_{j+1} when next != 0, from Z_{:, j+1}).
+int engine_tall(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st);
+int engine_step(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st);
 int launch_thin_q(int dtype, int64_t n, int32_t m, const void *U, int64_t ldu, const double *S,
                   int64_t lds, const double *T, int64_t ldt, double *Mq, void *Q, int64_t ldq,
                   hipStream_t st);

@@ -422,7 +422,7 @@ __device__ __forceinline__ StepScalars step_scalars(const double *y, const doubl
 // partial dot products of this workgroup's RED_CHUNK rows: S_{:,p}^t s_j
 // (p < j) and S_{:,p}^t z_{j+1} (p <= j).  One wave per p; the S loads of
 // eight p's are issued before their reductions.
-__global__ void __launch_bounds__(1024) k_ss(int32_t m, int32_t l, int32_t j, int scaling,
+__global__ void __launch_bounds__(1024) k_ss(int32_t m, int32_t l, int32_t j, int next, int scaling,
                                              const double *__restrict__ y,
                                              const double *__restrict__ sq, int gred,
                                              double *__restrict__ S, int64_t lds,
@@ -446,7 +446,7 @@ __global__ void __launch_bounds__(1024) k_ss(int32_t m, int32_t l, int32_t j, in
       s = sc.ident ? 0.0 : y[k] / sc.alpha;
     if (w == 0) S[k + (int64_t)j * lds] = s;
   }
-  const bool neede = j + 1 < m;
+  const bool neede = next != 0;
   const double z = (neede && kv) ? Z[k + (int64_t)(j + 1) * ldz] : 0.0;
   for (int p0 = w; p0 <= j; p0 += 16 * 8) {
     double sp[8];
@@ -490,7 +490,7 @@ __global__ void __launch_bounds__(1024) k_ss(int32_t m, int32_t l, int32_t j, in
 // tall pass (the raw column j is divided by alpha_j there).
 constexpr int FIN_P = 16;
 
-__global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t j, int gss,
+__global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t j, int next, int gss,
                                               const double *__restrict__ dpart,
                                               const double *__restrict__ epart,
                                               const double *__restrict__ scal, double *__restrict__ T,
@@ -500,7 +500,7 @@ __global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t j, int gss,
   __shared__ double d[MAXM], e[MAXM];
   __shared__ int last;
   const double rho = scal[4 * j + 1], alpha = scal[4 * j + 2], beta = scal[4 * j + 3];
-  const bool needc = j + 1 < m;
+  const bool needc = next != 0;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   // reduce the partial dot products: 64 indices x 16 group lanes per pass
   {
@@ -711,7 +711,26 @@ void launch_tall_k(const LoopArgs &a, const LoopWs &w, int32_t j, int aligned, i
 }
 
 template <typename ST>
-int run_typed(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
+int tall_typed(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st) {
+  const int tpw = tall_tpw(a.n, sizeof(ST));
+  const int aligned = ((uintptr_t)a.W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (g_prof.on) {
+    if (prof_pair(&e0, &e1)) return RHQR_ERR_HIP;
+    RHQR_HIP(hipEventRecord(e0, st));
+  }
+  switch (a.kind) {
+    case RHQR_SKETCH_SRHT: launch_tall_k<ST, RHQR_SKETCH_SRHT>(a, w, j, aligned, tpw, st); break;
+    case RHQR_SKETCH_GAUSS: launch_tall_k<ST, RHQR_SKETCH_GAUSS>(a, w, j, aligned, tpw, st); break;
+    default: launch_tall_k<ST, RHQR_SKETCH_IDENT>(a, w, j, aligned, tpw, st);
+  }
+  RHQR_HIP(hipGetLastError());
+  if (g_prof.on) RHQR_HIP(hipEventRecord(e1, st));
+  return RHQR_OK;
+}
+
+template <typename ST>
+int step_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st) {
   ST *W = (ST *)a.W;
   const int64_t n = a.n;
   const int32_t m = a.m, l = a.l, L = l + m;
@@ -720,49 +739,51 @@ int run_typed(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
   const int gred = (m + RED_CHUNK - 1) / RED_CHUNK + (l + RED_CHUNK - 1) / RED_CHUNK;
   const int gss = (L + RED_CHUNK - 1) / RED_CHUNK;
   const double scale = a.kind == RHQR_SKETCH_SRHT ? 1.0 / std::sqrt((double)l) : 1.0;
-  const int aligned = ((uintptr_t)a.W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
-  for (int32_t j = 0; j < m; ++j) {
-    if (j >= 1) {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (g_prof.on) {
-        if (prof_pair(&e0, &e1)) return RHQR_ERR_HIP;
-        RHQR_HIP(hipEventRecord(e0, st));
-      }
-      switch (a.kind) {
-        case RHQR_SKETCH_SRHT: launch_tall_k<ST, RHQR_SKETCH_SRHT>(a, w, j, aligned, tpw, st); break;
-        case RHQR_SKETCH_GAUSS: launch_tall_k<ST, RHQR_SKETCH_GAUSS>(a, w, j, aligned, tpw, st); break;
-        default: launch_tall_k<ST, RHQR_SKETCH_IDENT>(a, w, j, aligned, tpw, st);
-      }
-      RHQR_HIP(hipGetLastError());
-      if (g_prof.on) RHQR_HIP(hipEventRecord(e1, st));
-    }
-    if (a.kind == RHQR_SKETCH_IDENT)
-      hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_IDENT>), dim3(gred), dim3(1024), 0, st, W, a.ldw,
-                         m, l, j, a.Z + (int64_t)j * a.ldz, a.ldz, a.S, a.lds, w.c, w.part, nparts,
-                         scale, w.y, w.sq);
-    else
-      hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_SRHT>), dim3(gred), dim3(1024), 0, st, W, a.ldw, m,
-                         l, j, a.Z + (int64_t)j * a.ldz, a.ldz, a.S, a.lds, w.c, w.part, nparts,
-                         scale, w.y, w.sq);
-    RHQR_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_ss, dim3(gss), dim3(1024), 0, st, m, l, j, a.scaling, w.y, w.sq, gred,
-                       a.S, a.lds, a.Z, a.ldz, w.dpart, w.epart, w.scal, a.R, a.ldr, w.status);
-    RHQR_HIP(hipGetLastError());
-    const int gfin = j > 0 ? (j + FIN_P - 1) / FIN_P : 1;
-    hipLaunchKernelGGL(k_fin, dim3(gfin), dim3(1024), 0, st, m, j, gss, w.dpart, w.epart, w.scal,
-                       a.T, a.ldt, w.Tt, w.c, w.cf, w.ia, w.counter);
-    RHQR_HIP(hipGetLastError());
-  }
-  const int64_t ntail = n - m;
-  if (ntail > 0) {
-    hipLaunchKernelGGL((k_scale_last<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W, a.ldw, n,
-                       m, w.ia, w.wstage);
-    RHQR_HIP(hipGetLastError());
-  }
-  hipLaunchKernelGGL((k_head_store<ST>), dim3((m + 255) / 256, m), dim3(256), 0, st, W, a.ldw, m,
-                     a.S, a.lds);
+  if (a.kind == RHQR_SKETCH_IDENT)
+    hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_IDENT>), dim3(gred), dim3(1024), 0, st, W, a.ldw, m,
+                       l, j, a.Z + (int64_t)j * a.ldz, a.ldz, a.S, a.lds, w.c, w.part, nparts,
+                       scale, w.y, w.sq);
+  else
+    hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_SRHT>), dim3(gred), dim3(1024), 0, st, W, a.ldw, m,
+                       l, j, a.Z + (int64_t)j * a.ldz, a.ldz, a.S, a.lds, w.c, w.part, nparts,
+                       scale, w.y, w.sq);
+  RHQR_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_ss, dim3(gss), dim3(1024), 0, st, m, l, j, next, a.scaling, w.y, w.sq, gred,
+                     a.S, a.lds, a.Z, a.ldz, w.dpart, w.epart, w.scal, a.R, a.ldr, w.status);
+  RHQR_HIP(hipGetLastError());
+  const int gfin = j > 0 ? (j + FIN_P - 1) / FIN_P : 1;
+  hipLaunchKernelGGL(k_fin, dim3(gfin), dim3(1024), 0, st, m, j, next, gss, w.dpart, w.epart,
+                     w.scal, a.T, a.ldt, w.Tt, w.c, w.cf, w.ia, w.counter);
   RHQR_HIP(hipGetLastError());
   return RHQR_OK;
+}
+
+template <typename ST>
+int finish_typed(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
+  ST *W = (ST *)a.W;
+  const int64_t ntail = a.n - a.m;
+  if (ntail > 0) {
+    hipLaunchKernelGGL((k_scale_last<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W, a.ldw,
+                       a.n, a.m, w.ia, w.wstage);
+    RHQR_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL((k_head_store<ST>), dim3((a.m + 255) / 256, a.m), dim3(256), 0, st, W, a.ldw,
+                     a.m, a.S, a.lds);
+  RHQR_HIP(hipGetLastError());
+  return RHQR_OK;
+}
+
+template <typename ST>
+int run_typed(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
+  for (int32_t j = 0; j < a.m; ++j) {
+    if (j >= 1) {
+      const int rc = tall_typed<ST>(a, w, j, st);
+      if (rc) return rc;
+    }
+    const int rc = step_typed<ST>(a, w, j, j + 1 < a.m, st);
+    if (rc) return rc;
+  }
+  return finish_typed<ST>(a, w, st);
 }
 
 template <typename ST>
@@ -840,6 +861,24 @@ int loop_ws_carve(void *ws, size_t bytes, int kind, int dtype, int64_t n, int32_
   o->skws = nullptr;
   o->skws_bytes = 0;
   return RHQR_OK;
+}
+
+#define RHQR_DISPATCH(dt, expr)                                        \
+  switch (dt) {                                                        \
+    case RHQR_F64: { using ST = double; return expr; }                 \
+    case RHQR_F32: { using ST = float; return expr; }                  \
+    case RHQR_F16: { using ST = __half; return expr; }                 \
+    case RHQR_BF16: { using ST = __hip_bfloat16; return expr; }        \
+  }                                                                    \
+  return RHQR_ERR_UNSUPPORTED;
+
+int engine_tall(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st) {
+  RHQR_DISPATCH(a.dtype, tall_typed<ST>(a, w, j, st))
+}
+
+int engine_step(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st) {
+  if (a.m > MAXM) return RHQR_ERR_UNSUPPORTED;
+  RHQR_DISPATCH(a.dtype, step_typed<ST>(a, w, j, next, st))
 }
 
 int run_column_loop(const LoopArgs &a, const LoopWs &w, hipStream_t st) {

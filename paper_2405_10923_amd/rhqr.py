@@ -43,6 +43,7 @@ _SIGS = {
     "rhqr_arnoldi_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "rhqr_arnoldi_solution": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "rhqr_arnoldi_basis": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp)]),
+    "rhqr_spmv_csr": (C.c_int, [C.c_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rhqr_profile_begin": (C.c_int, []),
     "rhqr_profile_end": (C.c_int, [C.POINTER(C.c_double), C.POINTER(_i64)]),
 }
@@ -250,3 +251,105 @@ def profile_end():
     cnt = C.c_int64()
     _check(lib().rhqr_profile_end(C.byref(ms), C.byref(cnt)), "rhqr_profile_end")
     return ms.value, cnt.value
+
+
+class CSR:
+    """A float64 CSR matrix on the GPU (row pointers int64, indices int32)."""
+
+    def __init__(self, indptr, indices, values, n, device=None):
+        torch = _torch()
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        self.n = int(n)
+        self.ptr = torch.as_tensor(np.asarray(indptr, dtype=np.int64), device=dev)
+        self.idx = torch.as_tensor(np.asarray(indices, dtype=np.int32), device=dev)
+        self.val = torch.as_tensor(np.asarray(values, dtype=np.float64), device=dev)
+
+    def matvec(self, x, y=None):
+        torch = _torch()
+        if y is None:
+            y = torch.empty_like(x)
+        rc = lib().rhqr_spmv_csr(dtype_code(x.dtype), self.n, _ptr(self.ptr), _ptr(self.idx),
+                                 _ptr(self.val), _ptr(x), _ptr(y), _stream())
+        _check(rc, "rhqr_spmv_csr")
+        return y
+
+
+class Arnoldi:
+    """RHQR-Arnoldi (Alg. 7) state: up to ``mmax`` steps; the sketch must have
+    head m = mmax + 1."""
+
+    def __init__(self, sk, dtype, mmax):
+        h = C.c_void_p()
+        rc = lib().rhqr_arnoldi_create(sk.h, dtype_code(dtype), sk.n, int(mmax), _stream(),
+                                       C.byref(h))
+        _check(rc, "rhqr_arnoldi_create")
+        self.h, self.sk, self.dtype, self.mmax = h, sk, dtype, int(mmax)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rhqr_arnoldi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def start(self, r0, q1):
+        beta = C.c_double()
+        _check(lib().rhqr_arnoldi_start(self.h, _ptr(r0), _ptr(q1), C.byref(beta), _stream()),
+               "rhqr_arnoldi_start")
+        return beta.value
+
+    def step(self, w, qnext, hcol):
+        _check(lib().rhqr_arnoldi_step(self.h, _ptr(w), _ptr(qnext), _ptr(hcol), _stream()),
+               "rhqr_arnoldi_step")
+
+    def solution(self, j, y, x):
+        _check(lib().rhqr_arnoldi_solution(self.h, int(j), _ptr(y), _ptr(x), _stream()),
+               "rhqr_arnoldi_solution")
+
+
+def gmres(A, b, sk, m, dtype, tol=1e-6, max_cycles=1000, x0=None, callback=None):
+    """Restarted RHQR-GMRES(m) (Alg. 8): Krylov basis in ``dtype`` on the GPU,
+    Hessenberg least squares in float64 on the host, true residual recomputed
+    in float64 at every restart.  Returns (x float64, list of relative
+    residuals, total Arnoldi steps)."""
+    torch = _torch()
+    dev = b.device
+    n = A.n
+    x = torch.zeros(n, dtype=torch.float64, device=dev) if x0 is None else x0.clone()
+    nb = float(torch.linalg.norm(b))
+    arn = Arnoldi(sk, dtype, m)
+    Hcols = torch.zeros((m, m + 1), dtype=torch.float64, device=dev)
+    qa = torch.empty(n, dtype=dtype, device=dev)
+    qb = torch.empty(n, dtype=dtype, device=dev)
+    w = torch.empty(n, dtype=dtype, device=dev)
+    hist, steps = [], 0
+    for _ in range(max_cycles):
+        r = b - A.matvec(x)
+        rel = float(torch.linalg.norm(r)) / nb
+        if hist and rel <= tol:
+            break
+        beta = arn.start(r.to(dtype), qa)
+        for j in range(m):
+            A.matvec(qa, w)
+            arn.step(w, qb, Hcols[j])
+            qa, qb = qb, qa
+        steps += m
+        H = Hcols.t().cpu().numpy()          # (m+1) x m
+        rhs = np.zeros(m + 1)
+        rhs[0] = beta
+        y = np.linalg.lstsq(H, rhs, rcond=None)[0]
+        dx = torch.zeros(n, dtype=dtype, device=dev)
+        arn.solution(m, torch.from_numpy(y).to(dev), dx)
+        x += dx.to(torch.float64)
+        rel = float(torch.linalg.norm(b - A.matvec(x))) / nb
+        hist.append(rel)
+        if callback:
+            callback(len(hist), rel)
+        if rel <= tol:
+            break
+    arn.close()
+    return x, hist, steps

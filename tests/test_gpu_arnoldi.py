@@ -1,0 +1,77 @@
+"""GPU parity of RHQR-Arnoldi (Alg. 7) and restarted RHQR-GMRES (Alg. 8)
+against the CPU oracle on a convection-diffusion operator."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import sketch as osk, arnoldi as oarn
+from paper_2405_10923_amd.inputs import convdiff_csr
+from tests.gpu_util import cuda_or_skip, to_np, rel, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(nx, m, l, seed=3, dtype="float64"):
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    ptr, idx, val, n = convdiff_csr(nx)
+    A = rhqr.CSR(ptr, idx, val, n)
+    Acpu = sp.csr_matrix((val, idx, ptr), shape=(n, n))
+    sk = rhqr.Sketch(rhqr.SRHT, n, m + 1, l, seed=seed)
+    osketch = osk.Sketch(osk.SRHT, n, m + 1, l, seed=seed)
+    return torch, rhqr, A, Acpu, n, sk, osketch
+
+
+@pytest.mark.parametrize("nx,m,l", [(40, 20, 80), (70, 30, 120)])
+def test_arnoldi_matches_oracle(nx, m, l):
+    torch, rhqr, A, Acpu, n, sk, osketch = _setup(nx, m, l)
+    log(f"arnoldi n={n} m={m} l={l}")
+    r0 = np.random.default_rng(0).standard_normal(n)
+    ref = oarn.rhqr_arnoldi(Acpu, r0, osketch, m)
+    arn = rhqr.Arnoldi(sk, torch.float64, m)
+    q = torch.empty(n, dtype=torch.float64, device="cuda")
+    qn = torch.empty_like(q)
+    w = torch.empty_like(q)
+    H = torch.zeros((m, m + 1), dtype=torch.float64, device="cuda")
+    beta = arn.start(torch.from_numpy(r0).cuda(), q)
+    assert abs(beta - ref["h0"][0]) <= 1e-13 * abs(ref["h0"][0])
+    Q = [to_np(q).ravel()]
+    for j in range(m):
+        A.matvec(q, w)
+        arn.step(w, qn, H[j])
+        q, qn = qn, q
+        Q.append(to_np(q).ravel())
+    Hg = to_np(H).T
+    Qg = np.stack(Q, axis=1)
+    assert rel(Hg, ref["H"]) < 1e-12
+    assert rel(Qg, ref["Q"]) < 1e-12
+    # Arnoldi relation with the GPU's own outputs
+    lhs = Acpu @ Qg[:, :m]
+    assert np.linalg.norm(lhs - Qg @ Hg) <= 1e-12 * np.linalg.norm(lhs)
+    # x += Q_m y
+    y = np.random.default_rng(1).standard_normal(m)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    arn.solution(m, torch.from_numpy(y).cuda(), x)
+    assert rel(to_np(x).ravel(), Qg[:, :m] @ y) < 1e-12
+
+
+def test_gmres_matches_oracle_history():
+    torch, rhqr, A, Acpu, n, sk, osketch = _setup(48, 24, 96, seed=5)
+    b = np.ones(n)
+    x_ref, hist_ref = oarn.rhqr_gmres(Acpu, b, osketch, 24, tol=1e-8, max_cycles=30)
+    x, hist, steps = rhqr.gmres(A, torch.from_numpy(b).cuda(), sk, 24, torch.float64, tol=1e-8,
+                                max_cycles=30)
+    log(f"gmres cycles gpu {len(hist)} oracle {len(hist_ref)}; final {hist[-1]:.2e} {hist_ref[-1]:.2e}")
+    assert len(hist) == len(hist_ref)
+    for a, r in zip(hist, hist_ref):
+        assert abs(a - r) <= 1e-6 * r + 1e-13
+    assert rel(to_np(x).ravel(), x_ref) < 1e-8
+
+
+@pytest.mark.parametrize("dt", ["float32", "float16"])
+def test_gmres_low_precision_basis_converges(dt):
+    torch, rhqr, A, Acpu, n, sk, osketch = _setup(48, 24, 96, seed=5)
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    x, hist, steps = rhqr.gmres(A, b, sk, 24, getattr(torch, dt), tol=1e-6, max_cycles=200)
+    log(f"gmres {dt}: cycles {len(hist)} final {hist[-1]:.2e}")
+    assert hist[-1] <= 1e-6
