@@ -3,17 +3,24 @@
 
 Workload: W = G diag(s) V, G iid N(0,1), singular values logspaced 1..1e-14,
 V Haar-orthogonal; SRHT sketch with l = 1024, seed 0.  One step is one
-rhqr_factor call: pre-sketch Psi W, the 256-column loop (refresh + re-sketch
-pass, float64 sketch-space step), outputs U (in place of W), S, T, R.  The
-input is restored from a pristine copy between steps, outside the timed
-events.  Mixed precision (n-row data in float32 / float16 / bfloat16 with
-float32 accumulation; unit-max column scaling before rounding) is timed on
-the same workload and gated on ||W~ - QR||/||W~|| <= 1e-2 and
-||(Psi Q)^t Psi Q - I||_2 <= 1e-2.
+rhqr_factor call: pre-sketch Psi W, the 256-column loop (refresh + re-sketch,
+float64 sketch-space step with one synchronisation per column), outputs U (in
+place of W), S, T, R.  The input is restored from a pristine copy between
+steps, outside the timed events.
 
-value = B_alg / t for float64, B_alg = 8 (n-m) [m(m-1)/2 + 3m] bytes (the
-paper's algorithm: U_{j-1} read by the refresh of column j, plus the
-pre-sketch read, the column read and the u_j write).
+Schedules: "blocked" (panels of 16 columns: the earlier reflectors are applied
+to a whole panel by one tall product, the default) and "column" (every
+refresh reads all earlier reflectors, Alg. 4 as written).  Mixed precision
+(n-row data in float32 / float16 / bfloat16, float32 accumulation, unit-max
+column scaling before rounding) runs the same workload and is gated on
+||W~ - QR||/||W~|| <= 1e-2 and ||(Psi Q)^t Psi Q - I||_2 <= 1e-2.
+
+value = B_alg / t of the float64 factorization, B_alg = 8 (n-m) [m(m-1)/2 + 3m]
+bytes: the traffic of the column-by-column algorithm (U_{j-1} read by the
+refresh of column j, the pre-sketch read, the column read, the u_j write).
+For the blocked schedule this is an effective rate: it moves fewer bytes, and
+the roofline object reports the dominant kernel against its own algorithmic
+bytes per launch.
 
 Prints ONE JSON line.
 """
@@ -29,30 +36,47 @@ if ROOT not in sys.path:
 
 METRIC = "RHQR GB/s (% HBM roofline), mixed vs FP64 at ||W-QR||/||W|| <= 1e-2"
 HBM_PEAK_GBS = 8000.0
+TILE = 4096
 
 
 def b_alg(n, m, b):
     return b * (n - m) * (m * (m - 1) / 2 + 3 * m)
 
 
-def tall_bytes_per_launch_avg(n, m, l, b):
-    """Algorithmic bytes of the refresh + re-sketch kernel, averaged over its
-    m-1 launches: launch j reads the j-1 stored columns of U, the raw column
-    j-1 and w_j, writes u_{j-1} and the raw refreshed column j (j+3 columns of
-    n-m rows), reads the sign bits and writes one l-vector of partials per
-    4096-row tile."""
-    ntiles = (n + 4095) // 4096
+def _nparts(n, es):
+    ntiles = (n + TILE - 1) // TILE
+    tpw = 4 if ntiles >= 1024 else 2 if ntiles >= 512 else 1
+    if es == 2 and tpw < 2:
+        tpw = 2
+    return (n + TILE * tpw - 1) // (TILE * tpw)
+
+
+def kernel_bytes(n, m, l, es, panel):
+    """Algorithmic bytes of one factorization's launches of (a) the refresh +
+    re-sketch kernel and (b) the panel-update kernel.  Launch j of (a) reads the
+    stored columns it applies (all earlier ones, or the panel's), the raw column
+    j-1 and w_j, writes u_{j-1} and the raw refreshed column, reads the sign
+    bits and writes one l-vector of partials per workgroup.  Launch J of (b)
+    reads the J earlier columns and the panel's nb columns and writes them."""
     N = 1 << (n - 1).bit_length()
-    tot = 0.0
+    tail = (n - m) * es
+    side = _nparts(n, es) * l * 8 + N / 8
+    tall = 0.0
     for j in range(1, m):
-        tot += (j + 3) * b * (n - m) + ntiles * l * 8 + N / 8
-    return tot / (m - 1)
+        J = (j // panel) * panel if panel >= 2 else 0
+        cols = (j - J + 3) if j > J else 2
+        tall += cols * tail + side
+    pan = 0.0
+    if panel >= 2:
+        for J in range(panel, m, panel):
+            nb = min(panel, m - J)
+            pan += (J + 2 * nb) * tail
+    return tall, pan
 
 
-def cpu_baseline(n, l, kappa, ncols=8, seed=0):
-    """The CPU oracle, untuned, on a bounded sample: the first ``ncols``
-    columns of the workload's matrix shape (n rows), head m = ncols."""
-    import numpy as np
+def cpu_baseline(n, l, kappa, ncols, seed=0):
+    """The CPU oracle, untuned, on a bounded sample: a float64 left-looking
+    RHQR of the first ``ncols`` columns' shape (n rows, head m = ncols)."""
     from oracle import sketch as osk, rhqr as orq
     from paper_2405_10923_amd.inputs import synthetic_matrix
     try:
@@ -65,104 +89,138 @@ def cpu_baseline(n, l, kappa, ncols=8, seed=0):
     sk = osk.Sketch(osk.SRHT, n, ncols, l, seed=seed)
     orq.rhqr_left(W, sk)
     dt = time.perf_counter() - t0
-    gbs = b_alg(n, ncols, 8) / dt / 1e9
-    return {"value": gbs, "unit": "GB/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"float64 left-looking RHQR of a {n} x {ncols} slice of the workload "
-                      f"(SRHT l={l}, head {ncols}), sketch draw included; {dt:.1f} s"}
+    return {"value": round(b_alg(n, ncols, 8) / dt / 1e9, 3), "unit": "GB/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": f"float64 left-looking RHQR of a {n} x {ncols} matrix of the workload's "
+                      f"construction (SRHT l={l}, head {ncols}), sketch draw included, "
+                      f"B_alg of that shape over {dt:.1f} s"}
+
+
+def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, steps, warmup, profile):
+    import numpy as np
+    dev = W64.device
+    es = torch.finfo(dt).bits // 8
+    if dt == torch.float64:
+        Wsrc = W64
+    else:
+        d = W64.abs().amax(dim=0)
+        Wsrc = torch.empty((m, n), dtype=dt, device=dev).t()
+        Wsrc.copy_(W64 / d)
+    Ww = torch.empty((m, n), dtype=dt, device=dev).t()
+    bufs = rhqr.FactorBuffers(sk, dt, m, want_q=False)
+    for _ in range(warmup):
+        Ww.copy_(Wsrc)
+        rhqr.factor(sk, Ww, bufs=bufs, panel=panel)
+    torch.cuda.synchronize()
+    if profile:
+        rhqr.profile_begin()
+    evs = []
+    for _ in range(steps):
+        Ww.copy_(Wsrc)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rhqr.factor(sk, Ww, bufs=bufs, panel=panel)
+        e1.record()
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    step_ms = float(np.mean([a.elapsed_time(c) for a, c in evs]))
+    roof = None
+    if profile:
+        (tall_ms, tall_n), (pan_ms, pan_n) = rhqr.profile_end()
+        tb, pb = kernel_bytes(n, m, l, es, panel)
+        kern = []
+        if tall_n:
+            ach = tb * steps / (tall_ms * 1e-3) / 1e9
+            kern.append({"kernel": "k_tall (refresh + re-sketch pass)", "ms_total": tall_ms,
+                         "launches": tall_n, "avg_launch_ms": tall_ms / tall_n,
+                         "alg_bytes_per_launch": tb * steps / tall_n, "achieved": ach})
+        if pan_n:
+            ach = pb * steps / (pan_ms * 1e-3) / 1e9
+            kern.append({"kernel": "k_panel (panel update)", "ms_total": pan_ms,
+                         "launches": pan_n, "avg_launch_ms": pan_ms / pan_n,
+                         "alg_bytes_per_launch": pb * steps / pan_n, "achieved": ach})
+        kern.sort(key=lambda k: -k["ms_total"])
+        top = kern[0]
+        roof = {"bound": "hbm", "achieved": round(top["achieved"], 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(top["achieved"] / HBM_PEAK_GBS, 4),
+                "traffic": None, "kernel": top["kernel"],
+                "avg_launch_ms": round(top["avg_launch_ms"], 4), "launches": top["launches"],
+                "alg_bytes_per_launch": round(top["alg_bytes_per_launch"]),
+                "share_of_step": round(top["ms_total"] / steps / step_ms, 3),
+                "other_kernels": [{k: (round(v, 4) if isinstance(v, float) else v)
+                                   for k, v in o.items()} for o in kern[1:]]}
+    # accuracy of one more factorization with Q (untimed)
+    Ww.copy_(Wsrc)
+    bq = rhqr.FactorBuffers(sk, dt, m, want_q=True)
+    out = rhqr.factor(sk, Ww, want_q=True, bufs=bq, panel=panel)
+    Q, R = out["Q"], out["R"]
+    Wt = Wsrc.to(torch.float64)
+    ef = float(torch.linalg.norm(Wt - Q.to(torch.float64) @ R) / torch.linalg.norm(Wt))
+    Y = rhqr.sketch(sk, Q)
+    G = (Y.t() @ Y).cpu().numpy()
+    eo = float(np.linalg.norm(G - np.eye(m), 2))
+    info = rhqr.status(out["ws"])
+    del bq, out, Q, Y, Wt, Ww, Wsrc, bufs
+    torch.cuda.empty_cache()
+    gbs = b_alg(n, m, es) / (step_ms * 1e-3) / 1e9
+    res = {"ms_per_step": round(step_ms, 3), "GBps_alg": round(gbs, 1),
+           "factorizations_per_s": round(1000.0 / step_ms, 3), "e_fact": ef, "e_orth": eo,
+           "info": info}
+    return res, roof
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1 << 22)
     ap.add_argument("--m", type=int, default=256)
     ap.add_argument("--l", type=int, default=1024)
     ap.add_argument("--kappa", type=float, default=14.0)
     ap.add_argument("--dtypes", default="float64,float32,float16,bfloat16")
+    ap.add_argument("--panel", type=int, default=16,
+                    help="panel width of the blocked schedule (0: column by column)")
+    ap.add_argument("--no-column", action="store_true",
+                    help="skip the column-by-column float64 reference schedule")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-cols", type=int, default=8)
+    ap.add_argument("--cpu-cols", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "row-sharded design is described but not built.", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): the row-sharded "
+              "multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_2405_10923_amd import rhqr
     from paper_2405_10923_amd.inputs import synthetic_matrix_torch
 
     n, m, l, kappa = args.n, args.m, args.l, args.kappa
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(0)
     print(f"# workload n={n} m={m} l={l} cond=1e{kappa:g}", file=sys.stderr, flush=True)
     W64 = synthetic_matrix_torch(n, m, kappa, seed=0, device="cuda")
     sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=0)
-    res = {}
-    roof = None
+    res, roof = {}, None
     for name in args.dtypes.split(","):
         dt = getattr(torch, name)
-        b = torch.finfo(dt).bits // 8
-        if dt == torch.float64:
-            Wsrc = W64
-            d = None
-        else:
-            d = W64.abs().amax(dim=0)
-            Wsrc = torch.empty((m, n), dtype=dt, device=dev).t()
-            Wsrc.copy_(W64 / d)
-        Ww = torch.empty((m, n), dtype=dt, device=dev).t()
-        bufs = rhqr.FactorBuffers(sk, dt, m, want_q=False)
-        for _ in range(args.warmup):
-            Ww.copy_(Wsrc)
-            rhqr.factor(sk, Ww, bufs=bufs)
-        torch.cuda.synchronize()
-        prof = dt == torch.float64
-        if prof:
-            rhqr.profile_begin()
-        evs = []
-        for _ in range(args.steps):
-            Ww.copy_(Wsrc)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            rhqr.factor(sk, Ww, bufs=bufs)
-            e1.record()
-            evs.append((e0, e1))
-        torch.cuda.synchronize()
-        ms = [a.elapsed_time(c) for a, c in evs]
-        step_ms = float(np.mean(ms))
-        if prof:
-            tall_ms, launches = rhqr.profile_end()
-            avg_ms = tall_ms / max(launches, 1)
-            avg_bytes = tall_bytes_per_launch_avg(n, m, l, b)
-            ach = avg_bytes / (avg_ms * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": "k_tall<double,SRHT> (refresh + re-sketch pass)",
-                    "avg_launch_ms": round(avg_ms, 4), "launches": launches,
-                    "alg_bytes_per_launch": avg_bytes}
-        # accuracy of one more factorization with Q (untimed)
-        Ww.copy_(Wsrc)
-        bq = rhqr.FactorBuffers(sk, dt, m, want_q=True)
-        out = rhqr.factor(sk, Ww, want_q=True, bufs=bq)
-        Q, R = out["Q"], out["R"]
-        Wt = Wsrc.to(torch.float64)
-        ef = float(torch.linalg.norm(Wt - Q.to(torch.float64) @ R) / torch.linalg.norm(Wt))
-        Y = rhqr.sketch(sk, Q)
-        G = (Y.t() @ Y).cpu().numpy()
-        eo = float(np.linalg.norm(G - np.eye(m), 2))
-        info = rhqr.status(out["ws"])
-        del bq, out, Q, Y, Wt
-        gbs = b_alg(n, m, b) / (step_ms * 1e-3) / 1e9
-        res[name] = {"ms_per_step": round(step_ms, 3), "GBps_alg": round(gbs, 1),
-                     "hbm_frac_alg": round(gbs / HBM_PEAK_GBS, 4), "e_fact": ef, "e_orth": eo,
-                     "info": info, "factorizations_per_s": round(1000.0 / step_ms, 3)}
-        print(f"# {name}: {step_ms:.2f} ms/step  {gbs:.0f} GB/s(alg)  e_fact {ef:.2e} "
-              f"e_orth {eo:.2e}", file=sys.stderr, flush=True)
-        del Ww, Wsrc, bufs
-        torch.cuda.empty_cache()
+        r, rf = run_case(rhqr, torch, sk, W64, n, m, l, dt, args.panel, args.steps, args.warmup,
+                         profile=(dt == torch.float64))
+        res[name] = r
+        if rf is not None:
+            roof = rf
+        print(f"# {name} panel={args.panel}: {r['ms_per_step']:.2f} ms/step "
+              f"{r['GBps_alg']:.0f} GB/s(alg)  e_fact {r['e_fact']:.2e} e_orth {r['e_orth']:.2e}",
+              file=sys.stderr, flush=True)
+    column = None
+    if not args.no_column and args.panel >= 2:
+        column, croof = run_case(rhqr, torch, sk, W64, n, m, l, torch.float64, 0,
+                                 max(2, args.steps // 2), 1, profile=True)
+        column["roofline"] = croof
+        column["hbm_frac_alg"] = round(column["GBps_alg"] / HBM_PEAK_GBS, 4)
+        print(f"# float64 column-by-column: {column['ms_per_step']:.2f} ms/step "
+              f"{column['GBps_alg']:.0f} GB/s(alg) = {column['hbm_frac_alg']:.1%} of HBM",
+              file=sys.stderr, flush=True)
 
     f64 = res.get("float64")
     mixed = {}
@@ -175,6 +233,7 @@ def main():
         v["meets_1e-2"] = bool(v["e_fact"] <= 1e-2 and v["e_orth"] <= 1e-2)
         mixed[k] = v
     head = f64 if f64 else next(iter(res.values()))
+    sched = f"blocked, panels of {args.panel}" if args.panel >= 2 else "column by column"
     line = {
         "metric": METRIC,
         "value": head["GBps_alg"],
@@ -190,14 +249,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"RHQR left-looking, W {n}x{m} cond 1e{kappa:g} "
                                f"(G diag(s) V), SRHT l={l}, seed 0",
-                   "n": n, "m": m, "l": l, "sketch": "srht",
-                   "e_fact": head["e_fact"], "e_orth": head["e_orth"],
-                   "hbm_frac_alg": head["hbm_frac_alg"]},
+                   "n": n, "m": m, "l": l, "sketch": "srht", "schedule": sched,
+                   "value_is": "B_alg / time (bytes of the column-by-column algorithm)",
+                   "factorizations_per_s": head["factorizations_per_s"],
+                   "e_fact": head["e_fact"], "e_orth": head["e_orth"]},
         "roofline": roof,
         "mixed": mixed,
     }
+    if column is not None:
+        line["column_by_column_f64"] = column
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(n, l, kappa, ncols=args.cpu_cols)
+        line["cpu_baseline"] = cpu_baseline(n, l, kappa, args.cpu_cols)
     print(json.dumps(line), flush=True)
 
 

@@ -117,7 +117,14 @@ RHQR_API int rhqr_sketch(rhqr_sketch_t h, int dtype, int64_t n, int32_t k, const
  *   d_R   : m x m float64, upper triangular
  *   d_Q   : optional n x m thin Q factor in dtype (NULL to skip),
  *           Q = [I_m; 0] - U T U_1^t (Sec. 3.2)
- *   scaling: rhqr_scaling
+ *   opts  : bits 0-7 rhqr_scaling; bits 8-15 panel width b (0 or 1: the
+ *           column-by-column schedule of Alg. 4, every refresh reads all
+ *           earlier reflectors; 2 <= b <= 32: before each panel of b columns
+ *           the earlier reflectors are applied to the whole panel at once by a
+ *           tall matrix product with C = T^t S^t Psi W_panel (the block form of
+ *           Alg. 5 / Prop. 3.2), the columns inside a panel are refreshed as in
+ *           Alg. 4 with the panel's own reflectors).  Same factorization in
+ *           exact arithmetic; the one synchronisation per column is kept.
  *   d_ws  : device workspace, >= rhqr_factor_workspace_size(h, dtype, m) bytes
  * One synchronisation per column: the refreshed column's sketch (Alg. 4).
  * Breakdown (rho_j = 0) gives an identity reflector (beta_j = 0, R_jj = 0) and
@@ -126,7 +133,7 @@ RHQR_API int rhqr_sketch(rhqr_sketch_t h, int dtype, int64_t n, int32_t k, const
 RHQR_API size_t rhqr_factor_workspace_size(rhqr_sketch_t h, int dtype, int32_t m);
 RHQR_API int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W, int64_t ldw,
                 double *d_S, int64_t lds, double *d_T, int64_t ldt, double *d_R,
-                int64_t ldr, void *d_Q, int64_t ldq, int scaling, void *d_ws,
+                int64_t ldr, void *d_Q, int64_t ldq, int opts, void *d_ws,
                 size_t ws_bytes, void *stream);
 
 /* Status of the last rhqr_factor / recrhqr_factor / Arnoldi call that used
@@ -186,14 +193,17 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
 
 /* ------------------------------------------------------------------------
  * Measurement aid.  Between rhqr_profile_begin() and rhqr_profile_end(), every
- * launch of the tall-update kernel (the per-column refresh + re-sketch pass of
- * rhqr_factor / recrhqr_factor) is bracketed by HIP events recorded on the
- * launching stream.  rhqr_profile_end synchronises those events and returns
- * the summed kernel time (ms) and the number of launches.  Host-side state,
- * not thread-safe; intended for benchmarks.
+ * launch of the tall kernels of rhqr_factor / recrhqr_factor / the Arnoldi
+ * step is bracketed by HIP events recorded on the launching stream: the
+ * per-column refresh + re-sketch pass, and the panel update of the blocked
+ * schedule.  rhqr_profile_end synchronises those events and returns, for each
+ * of the two kernels, the summed kernel time (ms) and the number of launches
+ * (NULL pointers are skipped).  Host-side state, not thread-safe; intended for
+ * benchmarks.
  * ---------------------------------------------------------------------- */
 RHQR_API int rhqr_profile_begin(void);
-RHQR_API int rhqr_profile_end(double *total_ms, int64_t *launches);
+RHQR_API int rhqr_profile_end(double *tall_ms, int64_t *tall_launches, double *panel_ms,
+                              int64_t *panel_launches);
 
 #ifdef __cplusplus
 }

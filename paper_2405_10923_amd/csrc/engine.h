@@ -9,8 +9,9 @@ struct LoopWs {
   uint32_t *counter; // arrival counter of the last-workgroup step (zero between calls)
   double *y;         // (l+m) sketch of the refreshed column
   double *sq;        // per-workgroup partial sums of squares
-  double *dpart;     // [G_ss][m] partial S^t s_j
-  double *epart;     // [G_ss][m] partial S^t z_{j+1}
+  double *dpart;     // [G_red][m] partial S^t y (masked to rows >= j)
+  double *epart;     // [G_red][m] partial S^t z_{j+1}
+  double *ypart;     // [G_red] partial y^t z_{j+1}
   double *scal;      // [m][4]: sigma, rho, alpha, beta
   double *c;         // c_{j+1} = T_j^t S_j^t z_{j+1}
   double *cf;        // c with the pending 1/alpha of the raw column folded in
@@ -52,6 +53,10 @@ int run_column_loop(const LoopArgs &a, const LoopWs &w, hipStream_t st);
 // (reduction, RHVector, T column; c_{j+1} when next != 0, from Z_{:, j+1}).
 int engine_tall(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st);
 int engine_step(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st);
+// blocked schedule: panels of `panel` (<= 32) columns; C and G are float64
+// scratch of m x panel entries each
+int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, double *C, double *G,
+                            hipStream_t st);
 int launch_thin_q(int dtype, int64_t n, int32_t m, const void *U, int64_t ldu, const double *S,
                   int64_t lds, const double *T, int64_t ldt, double *Mq, void *Q, int64_t ldq,
                   hipStream_t st);

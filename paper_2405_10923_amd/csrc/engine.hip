@@ -28,16 +28,18 @@ namespace {
 constexpr int MAXM = 1024;  // largest m the sketch-space kernels support
 constexpr int TALL_TPB = 1024;  // threads per tall workgroup
 
-// Optional timing of the tall-update launches with HIP events recorded on the
-// launching stream (rhqr_profile_begin / rhqr_profile_end).
+// Optional timing of the tall kernels with HIP events recorded on the
+// launching stream (rhqr_profile_begin / rhqr_profile_end): class 0 = the
+// refresh + re-sketch pass, class 1 = the panel update of the blocked schedule.
 struct TallProfile {
   bool on = false;
-  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  std::vector<hipEvent_t> ev;   // pairs (start, stop)
+  std::vector<int> cls;         // class of each pair
   size_t used = 0;
 };
 TallProfile g_prof;
 
-int prof_pair(hipEvent_t *a, hipEvent_t *b) {
+int prof_pair(hipEvent_t *a, hipEvent_t *b, int cls) {
   if (g_prof.used + 2 > g_prof.ev.size()) {
     for (int k = 0; k < 2; ++k) {
       hipEvent_t e;
@@ -45,8 +47,10 @@ int prof_pair(hipEvent_t *a, hipEvent_t *b) {
       g_prof.ev.push_back(e);
     }
   }
+  if (g_prof.cls.size() < g_prof.ev.size() / 2) g_prof.cls.resize(g_prof.ev.size() / 2);
   *a = g_prof.ev[g_prof.used];
   *b = g_prof.ev[g_prof.used + 1];
+  g_prof.cls[g_prof.used / 2] = cls;
   g_prof.used += 2;
   return RHQR_OK;
 }
@@ -60,7 +64,8 @@ int prof_pair(hipEvent_t *a, hipEvent_t *b) {
 // (ragged last tile or unaligned storage).
 template <typename ST, bool FAST, int NV>
 __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
-                                          int32_t j, const double *__restrict__ cf,
+                                          int32_t j, int32_t p0, bool prev,
+                                          const double *__restrict__ cf,
                                           double iaprev, float *__restrict__ wstage,
                                           int64_t base,
                                           typename CompT<ST>::type (&acc)[NV][16 / sizeof(ST)]) {
@@ -92,7 +97,7 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
   if (FAST) {
     if (!head) {
 #pragma unroll 2
-      for (int p = 0; p < j - 1; ++p) {
+      for (int p = p0; p < j - 1; ++p) {
         const CT cp = (CT)cf[p];
         const char *cb = (const char *)(W + (int64_t)p * ldw + base);
 #pragma unroll
@@ -105,7 +110,7 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
       }
     } else {
 #pragma unroll 1
-      for (int p = 0; p < j - 1; ++p) {
+      for (int p = p0; p < j - 1; ++p) {
         const CT cp = (CT)cf[p];
         const char *cb = (const char *)(W + (int64_t)p * ldw + base);
 #pragma unroll
@@ -120,7 +125,7 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
     }
   } else {
 #pragma unroll 1
-    for (int p = 0; p < j - 1; ++p) {
+    for (int p = p0; p < j - 1; ++p) {
       const CT cp = (CT)cf[p];
       const ST *col = W + (int64_t)p * ldw;
 #pragma unroll
@@ -134,7 +139,9 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
   }
   // previous column: raw refreshed values, used, then stored scaled by
   // 1/alpha_{j-1}.  Column 0 is never refreshed: its raw values are the input.
-  if (j >= 1) {
+  // (prev == false: column j-1 was already stored scaled and applied by the
+  // panel update of the blocked schedule.)
+  if (j >= 1 && prev) {
     const CT cp = (CT)cf[j - 1];
     const CT ia = (CT)iaprev;
     ST *col = W + (int64_t)(j - 1) * ldw;
@@ -231,7 +238,7 @@ template <typename A, int TPW> __device__ void fwht_tiles_lds(A *s) {
 
 template <typename ST, int KIND, int TPW>
 __global__ void __launch_bounds__(TALL_TPB) k_tall(ST *__restrict__ W, int64_t ldw, int64_t n,
-                                                   int32_t m, int32_t j,
+                                                   int32_t m, int32_t j, int32_t p0,
                                                    const double *__restrict__ cf,
                                                    const double *__restrict__ ia,
                                                    float *__restrict__ wstage,
@@ -247,12 +254,13 @@ __global__ void __launch_bounds__(TALL_TPB) k_tall(ST *__restrict__ W, int64_t l
   __shared__ CT s[TPW * TILE_PAD];
   const int64_t base = (int64_t)blockIdx.x * ROWS;
   const bool fast = aligned && base + ROWS <= n;
-  const double iaprev = j >= 1 ? ia[j - 1] : 0.0;
+  const bool prev = j - 1 >= p0;
+  const double iaprev = (j >= 1 && prev) ? ia[j - 1] : 0.0;
   CT acc[NV][VEC];
   if (fast)
-    tall_body<ST, true, NV>(W, ldw, n, m, j, cf, iaprev, wstage, base, acc);
+    tall_body<ST, true, NV>(W, ldw, n, m, j, p0, prev, cf, iaprev, wstage, base, acc);
   else
-    tall_body<ST, false, NV>(W, ldw, n, m, j, cf, iaprev, wstage, base, acc);
+    tall_body<ST, false, NV>(W, ldw, n, m, j, p0, prev, cf, iaprev, wstage, base, acc);
 
   if (KIND == RHQR_SKETCH_IDENT) return;
   const int tid = threadIdx.x;
@@ -321,19 +329,29 @@ __global__ void __launch_bounds__(TALL_TPB) k_tall(ST *__restrict__ W, int64_t l
 }
 
 // ------------------------------------------------------------------- k_red
-// y = Psi w~_j.  Head rows: y_k = w_{k,j} - sum_{p<j} S_{k,p} c_p (float64);
-// tail rows: sum of the per-workgroup partials (SRHT scaled by l^-1/2), or the
-// refreshed rows themselves for Psi = I.  Sixteen waves split the summation
-// index; each lane keeps four independent partial sums.
+// One workgroup per RED_CHUNK rows of the (l+m) sketch space (head chunks
+// first).  Forms y = Psi w~_j on its rows: head rows y_k = w_{k,j} - sum_{p<j}
+// S_{k,p} c_p (float64), tail rows the sum of the per-workgroup sketch
+// partials (SRHT scaled by l^-1/2), or the refreshed rows themselves for
+// Psi = I.  Then, on its rows, the partial sums that RHVector and the T/c
+// updates need, with y masked to rows k >= j (no cancellation against the
+// already-eliminated entries):
+//   sq     = sum y_k^2                       (rho^2)
+//   dpart_p = sum S_{k,p} y_k      (p < j)   (S^t s_j up to the pivot term)
+//   epart_p = sum S_{k,p} z_k      (p < j)   (S^t z_{j+1}, z the next pre-sketch)
+//   ypart   = sum y_k z_k                    (s_j^t z_{j+1} up to the pivot term)
 template <typename ST, int KIND>
 __global__ void __launch_bounds__(1024) k_red(const ST *__restrict__ W, int64_t ldw, int32_t m,
-                                              int32_t l, int32_t j, const double *__restrict__ Z,
-                                              int64_t ldz, const double *__restrict__ S, int64_t lds,
+                                              int32_t l, int32_t j, int next,
+                                              const double *__restrict__ Z, int64_t ldz,
+                                              const double *__restrict__ S, int64_t lds,
                                               const double *__restrict__ c,
                                               const double *__restrict__ part, int64_t nparts,
                                               double scale, double *__restrict__ y,
-                                              double *__restrict__ sq) {
+                                              double *__restrict__ sq, double *__restrict__ dpart,
+                                              double *__restrict__ epart, double *__restrict__ ypart) {
   __shared__ double red[16][RED_CHUNK + 1];
+  __shared__ double yl[RED_CHUNK];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nhb = (m + RED_CHUNK - 1) / RED_CHUNK;
   const bool head = (int)blockIdx.x < nhb;
@@ -371,7 +389,7 @@ __global__ void __launch_bounds__(1024) k_red(const ST *__restrict__ W, int64_t 
     double out = 0.0;
     if (valid) {
       if (j == 0)
-        out = Z[k];
+        out = Z[k];  // column 0 of the pre-sketch
       else if (head)
         out = cvt_in<double>(W[k + (int64_t)j * ldw]) - s;
       else if (KIND == RHQR_SKETCH_IDENT)
@@ -380,22 +398,51 @@ __global__ void __launch_bounds__(1024) k_red(const ST *__restrict__ W, int64_t 
         out = s * scale;
       y[k] = out;
     }
-    const double q2 = (valid && k >= j) ? out * out : 0.0;
-    const double tot = wave_sum(q2);
+    const double ym = (valid && k >= j) ? out : 0.0;
+    yl[lane] = ym;
+    const double tot = wave_sum(ym * ym);
     if (lane == 0) sq[blockIdx.x] = tot;
+  }
+  __syncthreads();
+  const double ym = yl[lane];
+  const double z = (next && valid) ? Z[k + (int64_t)(j + 1) * ldz] : 0.0;
+  if (next && w == 0) {
+    const double yz = wave_sum(ym * z);
+    if (lane == 0) ypart[blockIdx.x] = yz;
+  }
+  // partial dot products with the earlier columns of S, one wave per p;
+  // eight p's loads are issued before their reductions
+  for (int p0 = w; p0 < j; p0 += 16 * 8) {
+    double sp[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int p = p0 + 16 * b;
+      sp[b] = (valid && p < j) ? S[k + (int64_t)p * lds] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int p = p0 + 16 * b;
+      if (p < j) {  // uniform across the wave
+        const double dv = wave_sum(sp[b] * ym);
+        const double ev = next ? wave_sum(sp[b] * z) : 0.0;
+        if (lane == 0) {
+          dpart[(int64_t)blockIdx.x * m + p] = dv;
+          if (next) epart[(int64_t)blockIdx.x * m + p] = ev;
+        }
+      }
+    }
   }
 }
 
-// -------------------------------------------------------------------- k_ss
+// -------------------------------------------------------------------- scalars
 struct StepScalars {
   double sigma, rho, alpha, beta, gamma;
   int ident;
 };
 
-__device__ __forceinline__ StepScalars step_scalars(const double *y, const double *sq, int gred,
-                                                    int32_t j, int scaling) {
-  double ss = 0.0;
-  for (int g = 0; g < gred; ++g) ss += sq[g];
+// ss: the sum of the partial sums of squares (rho^2)
+__device__ __forceinline__ StepScalars step_scalars(const double *y, double ss, int32_t j,
+                                                    int scaling) {
   StepScalars r;
   r.rho = sqrt(ss);
   const double yj = y[j];
@@ -418,59 +465,69 @@ __device__ __forceinline__ StepScalars step_scalars(const double *y, const doubl
   return r;
 }
 
-// RHVector (Alg. 2) on the sketch y: scalars, s_j = S_{:,j}, R_{:,j}, and the
-// partial dot products of this workgroup's RED_CHUNK rows: S_{:,p}^t s_j
-// (p < j) and S_{:,p}^t z_{j+1} (p <= j).  One wave per p; the S loads of
-// eight p's are issued before their reductions.
-__global__ void __launch_bounds__(1024) k_ss(int32_t m, int32_t l, int32_t j, int next, int scaling,
-                                             const double *__restrict__ y,
-                                             const double *__restrict__ sq, int gred,
-                                             double *__restrict__ S, int64_t lds,
-                                             const double *__restrict__ Z, int64_t ldz,
-                                             double *__restrict__ dpart, double *__restrict__ epart,
-                                             double *__restrict__ scal, double *__restrict__ R,
-                                             int64_t ldr, int32_t *__restrict__ status) {
+// ------------------------------------------------------------------- k_fin
+// RHVector (Alg. 2) and the T / c updates of Alg. 4 for column j, float64:
+//   scalars sigma, rho, gamma, alpha, beta from the partial sums of squares;
+//   s_j = ((0; y_{j:}) + sigma rho e_j) / alpha  -> S_{:, j};  R_{:, j};
+//   d = S^t s_j,  e = S^t z_{j+1}  (from the k_red partials plus the pivot term);
+//   T_{p,j} = -beta (T_{j-1} d)_p,  c_{j+1,p} = (T_{j-1}^t e)_p  for p < j,
+// one wave per p, FIN_P values of p per workgroup; T_{j,j} = beta.  The
+// workgroup that finishes last (device-scope counter) forms the last
+// coefficient c_{j+1,j} = beta (e_j - d . c_{:j}) and the folded copy cf used by
+// the next tall pass (the raw column j is divided by alpha_j there).
+constexpr int FIN_P = 16;
+
+__global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t l, int32_t j, int next,
+                                              int scaling, int gred,
+                                              const double *__restrict__ y,
+                                              const double *__restrict__ sq,
+                                              const double *__restrict__ dpart,
+                                              const double *__restrict__ epart,
+                                              const double *__restrict__ ypart,
+                                              const double *__restrict__ Z, int64_t ldz,
+                                              double *__restrict__ S, int64_t lds,
+                                              double *__restrict__ T, int64_t ldt,
+                                              double *__restrict__ Tt, double *__restrict__ R,
+                                              int64_t ldr, double *__restrict__ scal,
+                                              double *__restrict__ c, double *__restrict__ cf,
+                                              double *__restrict__ ia, int32_t *__restrict__ status,
+                                              uint32_t *__restrict__ counter) {
+  __shared__ double d[MAXM], e[MAXM];
   __shared__ StepScalars shs;
-  if (threadIdx.x == 0) shs = step_scalars(y, sq, gred, j, scaling);
+  __shared__ double yzs;
+  __shared__ int last;
+  if (threadIdx.x < 64) {
+    // wave 0 sums the partials in a fixed order (lane-strided, then a tree)
+    double ss = 0.0, yz = 0.0;
+    for (int g = threadIdx.x; g < gred; g += 64) {
+      ss += sq[g];
+      if (next) yz += ypart[g];
+    }
+    ss = wave_sum(ss);
+    yz = wave_sum(yz);
+    if (threadIdx.x == 0) {
+      shs = step_scalars(y, ss, j, scaling);
+      yzs = yz;
+    }
+  }
   __syncthreads();
   const StepScalars sc = shs;
-  const int L = l + m;
+  const double sr = sc.sigma * sc.rho;
+  const bool needc = next != 0;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int k = (int)blockIdx.x * RED_CHUNK + lane;
-  const bool kv = k < L;
-  double s = 0.0;
-  if (kv) {
+  const int L = l + m;
+  // s_j into S_{:, j} (grid-stride over the l+m rows)
+  for (int k = (int)blockIdx.x * blockDim.x + threadIdx.x; k < L; k += gridDim.x * blockDim.x) {
+    double s = 0.0;
     if (k == j)
       s = sc.ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : sc.gamma / sc.alpha);
     else if (k > j)
       s = sc.ident ? 0.0 : y[k] / sc.alpha;
-    if (w == 0) S[k + (int64_t)j * lds] = s;
-  }
-  const bool neede = next != 0;
-  const double z = (neede && kv) ? Z[k + (int64_t)(j + 1) * ldz] : 0.0;
-  for (int p0 = w; p0 <= j; p0 += 16 * 8) {
-    double sp[8];
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int p = p0 + 16 * b;
-      sp[b] = (kv && p <= j) ? (p < j ? S[k + (int64_t)p * lds] : s) : 0.0;
-    }
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int p = p0 + 16 * b;
-      if (p <= j) {  // uniform across the wave
-        const double dv = wave_sum(sp[b] * s);
-        const double ev = neede ? wave_sum(sp[b] * z) : 0.0;
-        if (lane == 0) {
-          if (p < j) dpart[(int64_t)blockIdx.x * m + p] = dv;
-          if (neede) epart[(int64_t)blockIdx.x * m + p] = ev;
-        }
-      }
-    }
+    S[k + (int64_t)j * lds] = s;
   }
   if (blockIdx.x == 0) {
     for (int r = threadIdx.x; r < m; r += blockDim.x)
-      R[r + (int64_t)j * ldr] = r < j ? y[r] : (r == j ? -sc.sigma * sc.rho : 0.0);
+      R[r + (int64_t)j * ldr] = r < j ? y[r] : (r == j ? -sr : 0.0);
     if (threadIdx.x == 0) {
       scal[4 * j + 0] = sc.sigma;
       scal[4 * j + 1] = sc.rho;
@@ -479,39 +536,15 @@ __global__ void __launch_bounds__(1024) k_ss(int32_t m, int32_t l, int32_t j, in
       if (sc.ident) atomicCAS(status, 0, j + 1);
     }
   }
-}
-
-// ------------------------------------------------------------------- k_fin
-// T_{p,j} = -beta (T_{j-1} d)_p and c_{j+1,p} = (T_{j-1}^t e)_p for p < j,
-// d = S^t s_j, e = S^t z_{j+1} (reduced from the k_ss partials), one wave per
-// p, FIN_P values of p per workgroup.  T_{j,j} = beta.  The workgroup that
-// finishes last (device-scope counter) forms the last coefficient
-// c_{j+1,j} = beta (e_j - d . c_{:j}) and the folded copy cf used by the next
-// tall pass (the raw column j is divided by alpha_j there).
-constexpr int FIN_P = 16;
-
-__global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t j, int next, int gss,
-                                              const double *__restrict__ dpart,
-                                              const double *__restrict__ epart,
-                                              const double *__restrict__ scal, double *__restrict__ T,
-                                              int64_t ldt, double *__restrict__ Tt,
-                                              double *__restrict__ c, double *__restrict__ cf,
-                                              double *__restrict__ ia, uint32_t *__restrict__ counter) {
-  __shared__ double d[MAXM], e[MAXM];
-  __shared__ int last;
-  const double rho = scal[4 * j + 1], alpha = scal[4 * j + 2], beta = scal[4 * j + 3];
-  const bool needc = next != 0;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   // reduce the partial dot products: 64 indices x 16 group lanes per pass
   {
     const int pl = threadIdx.x >> 4, gl = threadIdx.x & 15;
-    const int np = needc ? j + 1 : j;
-    for (int p0 = 0; p0 < np; p0 += 64) {
+    for (int p0 = 0; p0 < j; p0 += 64) {
       const int p = p0 + pl;
       double dv = 0.0, ev = 0.0;
-      if (p < np) {
-        for (int g = gl; g < gss; g += 16) {
-          if (p < j) dv += dpart[(int64_t)g * m + p];
+      if (p < j) {
+        for (int g = gl; g < gred; g += 16) {
+          dv += dpart[(int64_t)g * m + p];
           if (needc) ev += epart[(int64_t)g * m + p];
         }
       }
@@ -520,13 +553,19 @@ __global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t j, int next, in
         dv += __shfl_xor(dv, o, 64);
         ev += __shfl_xor(ev, o, 64);
       }
-      if (gl == 0 && p < np) {
-        d[p] = dv;
+      if (gl == 0 && p < j) {
+        const double sjp = S[j + (int64_t)p * lds];  // row j of an earlier column
+        d[p] = sc.ident ? sjp : (dv + sr * sjp) / sc.alpha;
         e[p] = ev;
       }
     }
+    if (threadIdx.x == 0 && needc) {
+      const double zj = Z[j + (int64_t)(j + 1) * ldz];
+      e[j] = sc.ident ? zj : (yzs + sr * zj) / sc.alpha;
+    }
   }
   __syncthreads();
+  const double beta = sc.beta;
   const int p = (int)blockIdx.x * FIN_P + w;
   if (w < FIN_P && p < j) {
     double td = 0.0, te = 0.0;
@@ -552,7 +591,7 @@ __global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t j, int next, in
   __syncthreads();
   if (!last) return;
   __threadfence();
-  const double iaj = rho > 0.0 ? 1.0 / alpha : 0.0;
+  const double iaj = sc.ident ? 0.0 : 1.0 / sc.alpha;
   if (w == 0) {
     double dc = 0.0;
     if (needc)
@@ -578,18 +617,21 @@ __global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t j, int next, in
 }
 
 // ------------------------------------------------------------ final stores
+// Store column cidx (tail rows) as u = raw / alpha: raw values are in place
+// (float64), in the float32 staging vector (low precision, cidx >= 1), or the
+// input column itself (cidx == 0).
 template <typename ST>
-__global__ void k_scale_last(ST *W, int64_t ldw, int64_t n, int32_t m, const double *ia,
-                             const float *wstage) {
+__global__ void k_scale_col(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t cidx,
+                            const double *ia, const float *wstage) {
   const int64_t i = m + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  ST *col = W + (int64_t)(m - 1) * ldw;
-  const double a = ia[m - 1];
+  ST *col = W + (int64_t)cidx * ldw;
+  const double a = ia[cidx];
   double raw;
   if constexpr (std::is_same<ST, double>::value)
     raw = col[i];
   else
-    raw = m >= 2 ? (double)wstage[i] : cvt_in<double>(col[i]);
+    raw = cidx >= 1 ? (double)wstage[i] : cvt_in<double>(col[i]);
   col[i] = cvt_out<ST>(raw * a);
 }
 
@@ -690,39 +732,41 @@ inline int tall_tpw(int64_t n, size_t elt) {
 }
 
 template <typename ST, int KIND, int TPW>
-void launch_tall(const LoopArgs &a, const LoopWs &w, int32_t j, int aligned, hipStream_t st) {
+void launch_tall(const LoopArgs &a, const LoopWs &w, int32_t j, int32_t p0, int aligned,
+                 hipStream_t st) {
   const int64_t rows = (int64_t)TILE * TPW;
   const int64_t g = (a.n + rows - 1) / rows;
   hipLaunchKernelGGL((k_tall<ST, KIND, TPW>), dim3(g), dim3(TALL_TPB), 0, st, (ST *)a.W, a.ldw, a.n,
-                     a.m, j, w.cf, w.ia, w.wstage, w.part, a.signs, a.rows, a.l, a.omega, aligned);
+                     a.m, j, p0, w.cf, w.ia, w.wstage, w.part, a.signs, a.rows, a.l, a.omega,
+                     aligned);
 }
 
 template <typename ST, int KIND>
-void launch_tall_k(const LoopArgs &a, const LoopWs &w, int32_t j, int aligned, int tpw,
+void launch_tall_k(const LoopArgs &a, const LoopWs &w, int32_t j, int32_t p0, int aligned, int tpw,
                    hipStream_t st) {
   if constexpr (sizeof(ST) == 2) {
-    if (tpw == 4) launch_tall<ST, KIND, 4>(a, w, j, aligned, st);
-    else launch_tall<ST, KIND, 2>(a, w, j, aligned, st);
+    if (tpw == 4) launch_tall<ST, KIND, 4>(a, w, j, p0, aligned, st);
+    else launch_tall<ST, KIND, 2>(a, w, j, p0, aligned, st);
   } else {
-    if (tpw == 4) launch_tall<ST, KIND, 4>(a, w, j, aligned, st);
-    else if (tpw == 2) launch_tall<ST, KIND, 2>(a, w, j, aligned, st);
-    else launch_tall<ST, KIND, 1>(a, w, j, aligned, st);
+    if (tpw == 4) launch_tall<ST, KIND, 4>(a, w, j, p0, aligned, st);
+    else if (tpw == 2) launch_tall<ST, KIND, 2>(a, w, j, p0, aligned, st);
+    else launch_tall<ST, KIND, 1>(a, w, j, p0, aligned, st);
   }
 }
 
 template <typename ST>
-int tall_typed(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st) {
+int tall_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int32_t p0, hipStream_t st) {
   const int tpw = tall_tpw(a.n, sizeof(ST));
   const int aligned = ((uintptr_t)a.W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_prof.on) {
-    if (prof_pair(&e0, &e1)) return RHQR_ERR_HIP;
+    if (prof_pair(&e0, &e1, 0)) return RHQR_ERR_HIP;
     RHQR_HIP(hipEventRecord(e0, st));
   }
   switch (a.kind) {
-    case RHQR_SKETCH_SRHT: launch_tall_k<ST, RHQR_SKETCH_SRHT>(a, w, j, aligned, tpw, st); break;
-    case RHQR_SKETCH_GAUSS: launch_tall_k<ST, RHQR_SKETCH_GAUSS>(a, w, j, aligned, tpw, st); break;
-    default: launch_tall_k<ST, RHQR_SKETCH_IDENT>(a, w, j, aligned, tpw, st);
+    case RHQR_SKETCH_SRHT: launch_tall_k<ST, RHQR_SKETCH_SRHT>(a, w, j, p0, aligned, tpw, st); break;
+    case RHQR_SKETCH_GAUSS: launch_tall_k<ST, RHQR_SKETCH_GAUSS>(a, w, j, p0, aligned, tpw, st); break;
+    default: launch_tall_k<ST, RHQR_SKETCH_IDENT>(a, w, j, p0, aligned, tpw, st);
   }
   RHQR_HIP(hipGetLastError());
   if (g_prof.on) RHQR_HIP(hipEventRecord(e1, st));
@@ -733,27 +777,24 @@ template <typename ST>
 int step_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st) {
   ST *W = (ST *)a.W;
   const int64_t n = a.n;
-  const int32_t m = a.m, l = a.l, L = l + m;
+  const int32_t m = a.m, l = a.l;
   const int tpw = tall_tpw(n, sizeof(ST));
   const int64_t nparts = (n + (int64_t)TILE * tpw - 1) / ((int64_t)TILE * tpw);
   const int gred = (m + RED_CHUNK - 1) / RED_CHUNK + (l + RED_CHUNK - 1) / RED_CHUNK;
-  const int gss = (L + RED_CHUNK - 1) / RED_CHUNK;
   const double scale = a.kind == RHQR_SKETCH_SRHT ? 1.0 / std::sqrt((double)l) : 1.0;
   if (a.kind == RHQR_SKETCH_IDENT)
     hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_IDENT>), dim3(gred), dim3(1024), 0, st, W, a.ldw, m,
-                       l, j, a.Z + (int64_t)j * a.ldz, a.ldz, a.S, a.lds, w.c, w.part, nparts,
-                       scale, w.y, w.sq);
+                       l, j, next, a.Z, a.ldz, a.S, a.lds, w.c, w.part,
+                       nparts, scale, w.y, w.sq, w.dpart, w.epart, w.ypart);
   else
     hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_SRHT>), dim3(gred), dim3(1024), 0, st, W, a.ldw, m,
-                       l, j, a.Z + (int64_t)j * a.ldz, a.ldz, a.S, a.lds, w.c, w.part, nparts,
-                       scale, w.y, w.sq);
-  RHQR_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_ss, dim3(gss), dim3(1024), 0, st, m, l, j, next, a.scaling, w.y, w.sq, gred,
-                     a.S, a.lds, a.Z, a.ldz, w.dpart, w.epart, w.scal, a.R, a.ldr, w.status);
+                       l, j, next, a.Z, a.ldz, a.S, a.lds, w.c, w.part,
+                       nparts, scale, w.y, w.sq, w.dpart, w.epart, w.ypart);
   RHQR_HIP(hipGetLastError());
   const int gfin = j > 0 ? (j + FIN_P - 1) / FIN_P : 1;
-  hipLaunchKernelGGL(k_fin, dim3(gfin), dim3(1024), 0, st, m, j, next, gss, w.dpart, w.epart,
-                     w.scal, a.T, a.ldt, w.Tt, w.c, w.cf, w.ia, w.counter);
+  hipLaunchKernelGGL(k_fin, dim3(gfin), dim3(1024), 0, st, m, l, j, next, a.scaling, gred, w.y,
+                     w.sq, w.dpart, w.epart, w.ypart, a.Z, a.ldz, a.S, a.lds, a.T, a.ldt, w.Tt,
+                     a.R, a.ldr, w.scal, w.c, w.cf, w.ia, w.status, w.counter);
   RHQR_HIP(hipGetLastError());
   return RHQR_OK;
 }
@@ -763,8 +804,8 @@ int finish_typed(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
   ST *W = (ST *)a.W;
   const int64_t ntail = a.n - a.m;
   if (ntail > 0) {
-    hipLaunchKernelGGL((k_scale_last<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W, a.ldw,
-                       a.n, a.m, w.ia, w.wstage);
+    hipLaunchKernelGGL((k_scale_col<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W, a.ldw,
+                       a.n, a.m, a.m - 1, w.ia, w.wstage);
     RHQR_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL((k_head_store<ST>), dim3((a.m + 255) / 256, a.m), dim3(256), 0, st, W, a.ldw,
@@ -777,11 +818,214 @@ template <typename ST>
 int run_typed(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
   for (int32_t j = 0; j < a.m; ++j) {
     if (j >= 1) {
-      const int rc = tall_typed<ST>(a, w, j, st);
+      const int rc = tall_typed<ST>(a, w, j, 0, st);
       if (rc) return rc;
     }
     const int rc = step_typed<ST>(a, w, j, j + 1 < a.m, st);
     if (rc) return rc;
+  }
+  return finish_typed<ST>(a, w, st);
+}
+
+// ---------------------------------------------------------- blocked schedule
+// Panels of PB columns (block form of the column loop, Alg. 5 with the compact
+// form of Prop. 3.2): before the panel starting at column J is processed, the
+// J earlier reflectors are applied to all of its columns at once,
+//     W_{:, J:J+nb} -= U_{:, <J} C,   C = T_{<J}^t S_{<J}^t Z_{:, J:J+nb},
+// which is exact because rows p < J of c_j = T^t S^t z_j only involve
+// T_{<J}; inside the panel each column is refreshed with the reflectors
+// J..j-1 only.  U_{:, <J} is then read once per panel instead of once per
+// column.
+
+// G = S_{:, <J}^t Z_{:, J:J+nb} (J x nb, ld J), one wave per entry
+__global__ void __launch_bounds__(1024) k_pgram(int32_t L, int32_t J, int32_t nb,
+                                                const double *__restrict__ S, int64_t lds,
+                                                const double *__restrict__ Z, int64_t ldz,
+                                                double *__restrict__ G) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 16 + w;
+  if (e >= (int64_t)J * nb) return;
+  const int p = (int)(e % J), jj = (int)(e / J);
+  const double *sp = S + (int64_t)p * lds;
+  const double *zp = Z + (int64_t)(J + jj) * ldz;
+  double v = 0.0;
+  for (int k = lane; k < L; k += 64) v += sp[k] * zp[k];
+  v = wave_sum(v);
+  if (lane == 0) G[p + (int64_t)jj * J] = v;
+}
+
+// C = T_{<J}^t G: C_{p,jj} = sum_{q <= p} T_{q,p} G_{q,jj}
+__global__ void k_ptri(int32_t J, int32_t nb, const double *__restrict__ T, int64_t ldt,
+                       const double *__restrict__ G, double *__restrict__ C) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int jj = blockIdx.y;
+  if (p >= J || jj >= nb) return;
+  double v = 0.0;
+  for (int q = 0; q <= p; ++q) v += T[q + (int64_t)p * ldt] * G[q + (int64_t)jj * J];
+  C[p + (int64_t)jj * J] = v;
+}
+
+// W[m:n, J:J+nb] -= U[m:n, 0:J] C.  Each thread streams VEC consecutive rows
+// of U (one 16-byte load per column) against all NBC panel columns, whose
+// coefficients sit in LDS (broadcast reads); U is read exactly once.
+constexpr int PANEL_TPB = 256;
+
+template <typename ST, int NBC>
+__global__ void __launch_bounds__(PANEL_TPB) k_panel(ST *__restrict__ W, int64_t ldw, int64_t n,
+                                                     int32_t m, int32_t J, int32_t nb,
+                                                     const double *__restrict__ C, int aligned) {
+  using CT = typename CompT<ST>::type;
+  constexpr int VEC = sizeof(ST) == 8 ? 2 : 4;   // rows per thread
+  constexpr int KC = 64;  // panel coefficients staged KC rows at a time
+  __shared__ CT Cs[KC][NBC];
+  const int64_t mb = m - (m % VEC);  // aligned start; head rows < m are not written
+  const int64_t r0 = mb + ((int64_t)blockIdx.x * PANEL_TPB + threadIdx.x) * VEC;
+  const bool live = r0 < n;
+  const bool full = aligned && r0 + VEC <= n && (r0 % VEC) == 0;
+  CT acc[VEC][NBC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e)
+#pragma unroll
+    for (int c = 0; c < NBC; ++c) acc[e][c] = (CT)0;
+  for (int k0 = 0; k0 < J; k0 += KC) {
+    const int kn = J - k0 < KC ? J - k0 : KC;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kn * NBC; e += PANEL_TPB) {
+      const int k = e / NBC, c = e % NBC;
+      Cs[k][c] = c < nb ? (CT)C[k0 + k + (int64_t)c * J] : (CT)0;
+    }
+    __syncthreads();
+    if (!live) continue;
+    int k = 0;
+    if (full) {
+      // four columns' loads issued before their products
+      for (; k + 4 <= kn; k += 4) {
+        CT xs[4][VEC];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const ST *col = W + (int64_t)(k0 + k + u) * ldw + r0;
+          if constexpr (sizeof(ST) >= 4) {
+            vload<ST, CT, true>(col, xs[u]);
+          } else {
+            const uint2 uu = *reinterpret_cast<const uint2 *>(col);
+            const uint32_t wd[2] = {uu.x, uu.y};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const unsigned short bits = (unsigned short)(wd[e >> 1] >> (16 * (e & 1)));
+              if constexpr (std::is_same<ST, __half>::value)
+                xs[u][e] = (CT)__half2float(__ushort_as_half(bits));
+              else
+                xs[u][e] = (CT)__uint_as_float(((uint32_t)bits) << 16);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < NBC; ++c) {
+            const CT ck = Cs[k + u][c];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[e][c] += xs[u][e] * ck;
+          }
+      }
+    }
+    for (; k < kn; ++k) {
+      const ST *col = W + (int64_t)(k0 + k) * ldw + r0;
+      CT x[VEC];
+      if (full) {
+        if constexpr (sizeof(ST) >= 4) {
+          vload<ST, CT, true>(col, x);
+        } else {
+          const uint2 u = *reinterpret_cast<const uint2 *>(col);
+          const uint32_t wd[2] = {u.x, u.y};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const unsigned short bits = (unsigned short)(wd[e >> 1] >> (16 * (e & 1)));
+            if constexpr (std::is_same<ST, __half>::value)
+              x[e] = (CT)__half2float(__ushort_as_half(bits));
+            else
+              x[e] = (CT)__uint_as_float(((uint32_t)bits) << 16);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) x[e] = r0 + e < n ? cvt_in<CT>(col[e]) : (CT)0;
+      }
+#pragma unroll
+      for (int c = 0; c < NBC; ++c) {
+        const CT ck = Cs[k][c];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e][c] += x[e] * ck;
+      }
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int c = 0; c < NBC; ++c) {
+    if (c >= nb) break;
+    ST *wc = W + (int64_t)(J + c) * ldw + r0;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+      if (r0 + e < n && r0 + e >= m) wc[e] = cvt_out<ST>((double)(cvt_in<CT>(wc[e]) - acc[e][c]));
+  }
+}
+
+template <typename ST>
+void launch_panel(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t J, int32_t nb, const double *C,
+                  hipStream_t st) {
+  constexpr int VEC = sizeof(ST) == 8 ? 2 : 4;
+  const int aligned = ((uintptr_t)W % 16 == 0) && ((ldw * (int64_t)sizeof(ST)) % 16 == 0);
+  const int64_t threads = (n - (m - m % VEC) + VEC - 1) / VEC;
+  const dim3 grid((unsigned)((threads + PANEL_TPB - 1) / PANEL_TPB));
+  if (nb <= 8)
+    hipLaunchKernelGGL((k_panel<ST, 8>), grid, dim3(PANEL_TPB), 0, st, W, ldw, n, m, J, nb, C, aligned);
+  else if (nb <= 16)
+    hipLaunchKernelGGL((k_panel<ST, 16>), grid, dim3(PANEL_TPB), 0, st, W, ldw, n, m, J, nb, C, aligned);
+  else
+    hipLaunchKernelGGL((k_panel<ST, 32>), grid, dim3(PANEL_TPB), 0, st, W, ldw, n, m, J, nb, C, aligned);
+}
+
+template <typename ST>
+int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, double *C, double *G,
+                      hipStream_t st) {
+  ST *W = (ST *)a.W;
+  const int32_t m = a.m, L = a.l + a.m;
+  const int64_t ntail = a.n - m;
+  for (int32_t J = 0; J < m; J += panel) {
+    const int32_t nb = m - J < panel ? m - J : panel;
+    if (J > 0) {
+      // store u_{J-1}, then apply the J earlier reflectors to the panel
+      if (ntail > 0) {
+        hipLaunchKernelGGL((k_scale_col<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W,
+                           a.ldw, a.n, m, J - 1, w.ia, w.wstage);
+        RHQR_HIP(hipGetLastError());
+      }
+      const int64_t ne = (int64_t)J * nb;
+      hipLaunchKernelGGL(k_pgram, dim3((ne + 15) / 16), dim3(1024), 0, st, L, J, nb, a.S, a.lds,
+                         a.Z, a.ldz, G);
+      RHQR_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_ptri, dim3((J + 255) / 256, nb), dim3(256), 0, st, J, nb, a.T, a.ldt, G,
+                         C);
+      RHQR_HIP(hipGetLastError());
+      if (ntail > 0) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (g_prof.on) {
+          if (prof_pair(&e0, &e1, 1)) return RHQR_ERR_HIP;
+          RHQR_HIP(hipEventRecord(e0, st));
+        }
+        launch_panel<ST>(W, a.ldw, a.n, m, J, nb, (const double *)C, st);
+        RHQR_HIP(hipGetLastError());
+        if (g_prof.on) RHQR_HIP(hipEventRecord(e1, st));
+      }
+    }
+    for (int32_t j = J; j < J + nb; ++j) {
+      if (j >= 1) {
+        const int rc = tall_typed<ST>(a, w, j, J, st);
+        if (rc) return rc;
+      }
+      const int rc = step_typed<ST>(a, w, j, j + 1 < m, st);
+      if (rc) return rc;
+    }
   }
   return finish_typed<ST>(a, w, st);
 }
@@ -823,7 +1067,8 @@ size_t loop_ws_bytes(int kind, int dtype, int64_t n, int32_t m, int32_t l) {
   b += align_up(sizeof(int32_t) * 4);
   b += align_up(sizeof(double) * L);
   b += align_up(sizeof(double) * gred);
-  b += 2 * align_up(sizeof(double) * (size_t)gss * m);
+  b += 2 * align_up(sizeof(double) * (size_t)gred * m);
+  b += align_up(sizeof(double) * gred);
   b += align_up(sizeof(double) * 4 * m);
   b += 3 * align_up(sizeof(double) * m);
   b += align_up(sizeof(double) * (size_t)m * m);
@@ -849,8 +1094,9 @@ int loop_ws_carve(void *ws, size_t bytes, int kind, int dtype, int64_t n, int32_
   o->counter = (uint32_t *)(o->status + 2);
   o->y = (double *)take(sizeof(double) * L);
   o->sq = (double *)take(sizeof(double) * gred);
-  o->dpart = (double *)take(sizeof(double) * (size_t)gss * m);
-  o->epart = (double *)take(sizeof(double) * (size_t)gss * m);
+  o->dpart = (double *)take(sizeof(double) * (size_t)gred * m);
+  o->epart = (double *)take(sizeof(double) * (size_t)gred * m);
+  o->ypart = (double *)take(sizeof(double) * gred);
   o->scal = (double *)take(sizeof(double) * 4 * m);
   o->c = (double *)take(sizeof(double) * m);
   o->cf = (double *)take(sizeof(double) * m);
@@ -873,7 +1119,13 @@ int loop_ws_carve(void *ws, size_t bytes, int kind, int dtype, int64_t n, int32_
   return RHQR_ERR_UNSUPPORTED;
 
 int engine_tall(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st) {
-  RHQR_DISPATCH(a.dtype, tall_typed<ST>(a, w, j, st))
+  RHQR_DISPATCH(a.dtype, tall_typed<ST>(a, w, j, 0, st))
+}
+
+int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, double *C, double *G,
+                            hipStream_t st) {
+  if (a.m > MAXM) return RHQR_ERR_UNSUPPORTED;
+  RHQR_DISPATCH(a.dtype, run_blocked_typed<ST>(a, w, panel, C, G, st))
 }
 
 int engine_step(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st) {
@@ -915,17 +1167,23 @@ extern "C" int rhqr_profile_begin(void) {
   return RHQR_OK;
 }
 
-extern "C" int rhqr_profile_end(double *total_ms, int64_t *launches) {
+extern "C" int rhqr_profile_end(double *tall_ms, int64_t *tall_launches, double *panel_ms,
+                                int64_t *panel_launches) {
   g_prof.on = false;
-  double tot = 0.0;
+  double tot[2] = {0.0, 0.0};
+  int64_t cnt[2] = {0, 0};
   for (size_t k = 0; k + 1 < g_prof.used; k += 2) {
     RHQR_HIP(hipEventSynchronize(g_prof.ev[k + 1]));
     float ms = 0.f;
     RHQR_HIP(hipEventElapsedTime(&ms, g_prof.ev[k], g_prof.ev[k + 1]));
-    tot += ms;
+    const int c = g_prof.cls[k / 2] ? 1 : 0;
+    tot[c] += ms;
+    cnt[c] += 1;
   }
-  if (total_ms) *total_ms = tot;
-  if (launches) *launches = (int64_t)(g_prof.used / 2);
+  if (tall_ms) *tall_ms = tot[0];
+  if (tall_launches) *tall_launches = cnt[0];
+  if (panel_ms) *panel_ms = tot[1];
+  if (panel_launches) *panel_launches = cnt[1];
   g_prof.used = 0;
   return RHQR_OK;
 }

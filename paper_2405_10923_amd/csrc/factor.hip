@@ -15,6 +15,7 @@ struct FactorWs {
   void *skws;
   size_t skws_bytes;
   double *Mq;
+  double *C, *G;  // panel coefficients (blocked schedule), m x 32 each
 };
 
 size_t factor_ws_bytes(const rhqr_sketch_s *h, int dtype, int32_t m) {
@@ -23,6 +24,7 @@ size_t factor_ws_bytes(const rhqr_sketch_s *h, int dtype, int32_t m) {
   b += align_up(sizeof(double) * (size_t)L * m);
   b += align_up(sketch_ws_bytes(h, m));
   b += align_up(sizeof(double) * (size_t)m * m);
+  b += 2 * align_up(sizeof(double) * (size_t)m * 32);
   return b;
 }
 
@@ -40,6 +42,10 @@ int factor_ws_carve(const rhqr_sketch_s *h, int dtype, int32_t m, void *ws, size
   o->skws_bytes = align_up(sketch_ws_bytes(h, m));
   p += o->skws_bytes;
   o->Mq = (double *)p;
+  p += align_up(sizeof(double) * (size_t)m * m);
+  o->C = (double *)p;
+  p += align_up(sizeof(double) * (size_t)m * 32);
+  o->G = (double *)p;
   return RHQR_OK;
 }
 
@@ -52,8 +58,10 @@ extern "C" size_t rhqr_factor_workspace_size(rhqr_sketch_t h, int dtype, int32_t
 
 extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W,
                            int64_t ldw, double *d_S, int64_t lds, double *d_T, int64_t ldt,
-                           double *d_R, int64_t ldr, void *d_Q, int64_t ldq, int scaling,
+                           double *d_R, int64_t ldr, void *d_Q, int64_t ldq, int opts,
                            void *d_ws, size_t ws_bytes, void *stream) {
+  const int scaling = opts & 0xff;
+  const int panel = (opts >> 8) & 0xff;
   if (!h) return -1;
   if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -2;
   if (n != h->n) return -3;
@@ -68,7 +76,9 @@ extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, voi
   if (!d_R) return -11;
   if (ldr < m) return -12;
   if (d_Q && ldq < n) return -14;
-  if (scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) return -15;
+  if ((scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) || panel > 32 ||
+      (opts >> 16) != 0)
+    return -15;
   if (!d_ws) return -16;
   if (m > 1024) return RHQR_ERR_UNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
@@ -105,7 +115,8 @@ extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, voi
   a.signs = h->d_signs;
   a.rows = h->d_rows;
   a.omega = h->d_omega;
-  rc = run_column_loop(a, w.loop, st);
+  rc = panel >= 2 ? run_column_loop_blocked(a, w.loop, panel, w.C, w.G, st)
+                  : run_column_loop(a, w.loop, st);
   if (rc) return rc;
   if (d_Q) rc = launch_thin_q(dtype, n, m, d_W, ldw, d_S, lds, d_T, ldt, w.Mq, d_Q, ldq, st);
   return rc;

@@ -165,65 +165,94 @@ __device__ __forceinline__ void load_tile(const ST *__restrict__ x, int64_t base
   }
 }
 
+// 1024 threads transform two consecutive tiles (2 TILE rows) per step; two
+// workgroups per compute unit overlap one's loads with the other's transform.
+constexpr int SK_TPB = 1024, SK_TPW = 2;
+
+template <typename A> __device__ void fwht_two_tiles(A *s) {
+#pragma unroll 1
+  for (int pass = 0; pass < 3; ++pass) {
+    __syncthreads();
+    const int sh = 4 * pass;
+    const int gg = threadIdx.x;
+    if (gg < (TILE / 16) * SK_TPW) {
+      A *st = s + (gg >> 8) * TILE_PAD;
+      const int g = gg & 255;
+      const int lo = g & ((1 << sh) - 1);
+      const int hi = g >> sh;
+      const int base = lo + (hi << (sh + 4));
+      A v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = st[tpad(base + (k << sh))];
+      fwht16(v);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) st[tpad(base + (k << sh))] = v[k];
+    }
+  }
+  __syncthreads();
+}
+
 template <typename ST, typename AT, int QA>
-__global__ void __launch_bounds__(256) k_srht_cols(const ST *__restrict__ X, int64_t ldx, int64_t n,
-                                                   int32_t m, int32_t l, int64_t ntiles, int gt,
-                                                   const uint64_t *__restrict__ signs,
-                                                   const int32_t *__restrict__ rows,
-                                                   double *__restrict__ part, int aligned) {
+__global__ void __launch_bounds__(SK_TPB) k_srht_cols(const ST *__restrict__ X, int64_t ldx, int64_t n,
+                                                      int32_t m, int32_t l, int64_t ngroups, int gt,
+                                                      const uint64_t *__restrict__ signs,
+                                                      const int32_t *__restrict__ rows,
+                                                      double *__restrict__ part, int aligned) {
   constexpr int VEC = 16 / sizeof(ST);
-  constexpr int NV = (TILE / 256) / VEC;
-  __shared__ AT s[TILE_PAD];
+  constexpr int ROWS = TILE * SK_TPW;
+  constexpr int NV = ROWS / (SK_TPB * VEC);
+  static_assert(NV >= 1, "tile too small for the vector width");
+  __shared__ AT s[SK_TPW * TILE_PAD];
   const int c = blockIdx.y;
   const ST *x = X + (int64_t)c * ldx;
   double acc[QA];
 #pragma unroll
   for (int a = 0; a < QA; ++a) acc[a] = 0.0;
-  AT cur[NV][VEC], nxt[NV][VEC];
-  int64_t t = blockIdx.x;
-  if (t < ntiles) {
-    const int64_t base = t << TILE_LOG;
-    load_tile<ST, AT>(x, base, n, m, aligned && base + TILE <= n, cur);
-  }
-  for (; t < ntiles; t += gt) {
-    const int64_t base = t << TILE_LOG;
+  for (int64_t g = blockIdx.x; g < ngroups; g += gt) {
+    const int64_t base = g * ROWS;
+    const bool fast = aligned && base + ROWS <= n;
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int li0 = VEC * (threadIdx.x + 256 * v);
+      const int li0 = VEC * (threadIdx.x + SK_TPB * v);
       const int64_t i0 = base + li0;
+      AT xv[VEC];
+      if (fast) {
+        vload<ST, AT, true>(x + i0, xv);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) xv[e] = (i0 + e < n) ? cvt_in<AT>(x[i0 + e]) : (AT)0;
+      }
       const uint64_t word = i0 < n ? signs[i0 >> 6] : 0ull;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
-        AT val = cur[v][e];
-        if ((word >> ((i0 + e) & 63)) & 1ull) val = -val;
-        s[tpad(li0 + e)] = val;
+        const int64_t i = i0 + e;
+        AT val = (i >= m && i < n) ? xv[e] : (AT)0;
+        if ((word >> (i & 63)) & 1ull) val = -val;
+        const int li = li0 + e;
+        s[(li >> TILE_LOG) * TILE_PAD + tpad(li & (TILE - 1))] = val;
       }
     }
-    const int64_t tn = t + gt;
-    if (tn < ntiles) {
-      const int64_t bn = tn << TILE_LOG;
-      load_tile<ST, AT>(x, bn, n, m, aligned && bn + TILE <= n, nxt);
-    }
-    fwht_tile_lds(s);
+    fwht_two_tiles(s);
+    const uint64_t t0 = (uint64_t)g * SK_TPW;
 #pragma unroll
     for (int a = 0; a < QA; ++a) {
-      const int q = threadIdx.x + 256 * a;
+      const int q = threadIdx.x + SK_TPB * a;
       if (q < l) {
         const int32_t r = rows[q];
-        const AT h = s[tpad(r & (TILE - 1))];
-        const bool neg = __popcll((uint64_t)(r >> TILE_LOG) & (uint64_t)t) & 1;
-        acc[a] += neg ? -(double)h : (double)h;
+        const int r2 = tpad(r & (TILE - 1));
+        const uint64_t r1 = (uint64_t)(r >> TILE_LOG);
+#pragma unroll
+        for (int tt = 0; tt < SK_TPW; ++tt) {
+          const double h = (double)s[tt * TILE_PAD + r2];
+          acc[a] += (__popcll(r1 & (t0 + tt)) & 1) ? -h : h;
+        }
       }
     }
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) cur[v][e] = nxt[v][e];
   }
 #pragma unroll
   for (int a = 0; a < QA; ++a) {
-    const int q = threadIdx.x + 256 * a;
+    const int q = threadIdx.x + SK_TPB * a;
     if (q < l) part[((int64_t)c * gt + blockIdx.x) * l + q] = acc[a];
   }
 }
@@ -313,17 +342,16 @@ int launch_typed(const rhqr_sketch_s *h, int64_t n, int32_t k, const ST *X, int6
   if (h->kind == RHQR_SKETCH_SRHT) {
     const int64_t ntiles = (n + TILE - 1) / TILE;
     const int aligned = ((uintptr_t)X % 16 == 0) && ((ldx * (int64_t)sizeof(ST)) % 16 == 0);
-    // samples per thread: ceil(l / 256), rounded up to a power of two
-    const int qa = l <= 256 ? 1 : l <= 512 ? 2 : l <= 1024 ? 4 : l <= 2048 ? 8 : 16;
-#define RHQR_SRHT_COLS(Q)                                                                        \
-  hipLaunchKernelGGL((k_srht_cols<ST, CT, Q>), dim3(gt, k), dim3(256), 0, st, X, ldx, n, m, l,   \
-                     ntiles, gt, h->d_signs, h->d_rows, part, aligned)
+    const int64_t ngroups = (n + (int64_t)TILE * SK_TPW - 1) / ((int64_t)TILE * SK_TPW);
+    // samples per thread: ceil(l / 1024)
+    const int qa = l <= 1024 ? 1 : l <= 2048 ? 2 : 4;
+#define RHQR_SRHT_COLS(Q)                                                                       \
+  hipLaunchKernelGGL((k_srht_cols<ST, CT, Q>), dim3(gt, k), dim3(SK_TPB), 0, st, X, ldx, n, m, \
+                     l, ngroups, gt, h->d_signs, h->d_rows, part, aligned)
     switch (qa) {
       case 1: RHQR_SRHT_COLS(1); break;
       case 2: RHQR_SRHT_COLS(2); break;
-      case 4: RHQR_SRHT_COLS(4); break;
-      case 8: RHQR_SRHT_COLS(8); break;
-      default: RHQR_SRHT_COLS(16); break;
+      default: RHQR_SRHT_COLS(4); break;
     }
 #undef RHQR_SRHT_COLS
     RHQR_HIP(hipGetLastError());
@@ -349,9 +377,9 @@ int launch_typed(const rhqr_sketch_s *h, int64_t n, int32_t k, const ST *X, int6
 int sketch_tail_partials_size(const rhqr_sketch_s *h, int32_t k, int *gt_out, size_t *bytes_out) {
   int gt;
   if (h->kind == RHQR_SKETCH_SRHT) {
-    const int64_t ntiles = (h->n + TILE - 1) / TILE;
-    const int64_t target = std::max<int64_t>(1, 4096 / std::max<int32_t>(k, 1));
-    gt = (int)std::min<int64_t>(ntiles, target);
+    const int64_t ngroups = (h->n + (int64_t)TILE * 2 - 1) / ((int64_t)TILE * 2);
+    const int64_t target = std::max<int64_t>(1, 1024 / std::max<int32_t>(k, 1));
+    gt = (int)std::min<int64_t>(ngroups, target);
   } else {
     const int64_t ntail = h->n - h->m;
     const int64_t tiles = (int64_t)((h->l + GB - 1) / GB) * ((k + GB - 1) / GB);

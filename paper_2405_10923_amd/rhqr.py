@@ -45,7 +45,8 @@ _SIGS = {
     "rhqr_arnoldi_basis": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp)]),
     "rhqr_spmv_csr": (C.c_int, [C.c_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rhqr_profile_begin": (C.c_int, []),
-    "rhqr_profile_end": (C.c_int, [C.POINTER(C.c_double), C.POINTER(_i64)]),
+    "rhqr_profile_end": (C.c_int, [C.POINTER(C.c_double), C.POINTER(_i64),
+                                   C.POINTER(C.c_double), C.POINTER(_i64)]),
 }
 
 
@@ -199,16 +200,18 @@ class FactorBuffers:
         self.ws = workspace(lib().rhqr_factor_workspace_size(sk.h, dtype_code(dtype), m), dev)
 
 
-def factor(sk, W, scaling=SCALE_UNIT_PIVOT, want_q=False, bufs=None):
+def factor(sk, W, scaling=SCALE_UNIT_PIVOT, want_q=False, bufs=None, panel=0):
     """Left-looking RHQR (Alg. 4).  W (n x m, column-major, GPU) is overwritten
-    by U.  Returns dict(U=W, S, T, R, Q)."""
+    by U.  ``panel`` >= 2 selects the blocked schedule (panels of that many
+    columns).  Returns dict(U=W, S, T, R, Q)."""
     n, m = W.shape
     if bufs is None:
         bufs = FactorBuffers(sk, W.dtype, m, want_q)
     Q = bufs.Q if want_q else None
     rc = lib().rhqr_factor(sk.h, dtype_code(W.dtype), n, m, _ptr(W), _ld(W), _ptr(bufs.S),
                            _ld(bufs.S), _ptr(bufs.T), _ld(bufs.T), _ptr(bufs.R), _ld(bufs.R),
-                           _ptr(Q), _ld(Q) if Q is not None else 0, int(scaling), _ptr(bufs.ws),
+                           _ptr(Q), _ld(Q) if Q is not None else 0,
+                           int(scaling) | (int(panel) << 8), _ptr(bufs.ws),
                            bufs.ws.numel(), _stream())
     _check(rc, "rhqr_factor")
     return dict(U=W, S=bufs.S, T=bufs.T, R=bufs.R, Q=Q, ws=bufs.ws)
@@ -245,12 +248,14 @@ def profile_begin():
 
 
 def profile_end():
-    """Summed duration (ms) and count of tall-update launches since
-    profile_begin(), measured with HIP events on the launching stream."""
-    ms = C.c_double()
-    cnt = C.c_int64()
-    _check(lib().rhqr_profile_end(C.byref(ms), C.byref(cnt)), "rhqr_profile_end")
-    return ms.value, cnt.value
+    """Summed duration (ms) and launch count of the refresh + re-sketch kernel
+    and of the panel-update kernel since profile_begin(), measured with HIP
+    events on the launching stream: ((tall_ms, tall_n), (panel_ms, panel_n))."""
+    ms0, ms1 = C.c_double(), C.c_double()
+    n0, n1 = C.c_int64(), C.c_int64()
+    _check(lib().rhqr_profile_end(C.byref(ms0), C.byref(n0), C.byref(ms1), C.byref(n1)),
+           "rhqr_profile_end")
+    return (ms0.value, n0.value), (ms1.value, n1.value)
 
 
 class CSR:

@@ -15,14 +15,14 @@ from tests.gpu_util import cuda_or_skip, to_gpu, to_np, rel, log
 pytestmark = pytest.mark.gpu
 
 
-def _run(kind, n, m, l, kappa, seed=0, scaling=0, dtype="float64", want_q=True):
+def _run(kind, n, m, l, kappa, seed=0, scaling=0, dtype="float64", want_q=True, panel=0):
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
     W = synthetic_matrix(n, m, kappa, seed=seed)
     Wd = to_gpu(W, getattr(torch, dtype))
     Win = to_np(Wd)
     sk = rhqr.Sketch(kind, n, m, l, seed=seed + 1)
-    out = rhqr.factor(sk, Wd, scaling=scaling, want_q=want_q)
+    out = rhqr.factor(sk, Wd, scaling=scaling, want_q=want_q, panel=panel)
     torch.cuda.synchronize()
     res = {k: to_np(v) for k, v in out.items() if k in ("U", "S", "T", "R") or (k == "Q" and v is not None)}
     res["info"] = rhqr.status(out["ws"])
@@ -32,11 +32,12 @@ def _run(kind, n, m, l, kappa, seed=0, scaling=0, dtype="float64", want_q=True):
     return W, Win, res, osketch
 
 
+@pytest.mark.parametrize("panel", [0, 16, 5])
 @pytest.mark.parametrize("n,m,l", [(300, 7, 40), (4096, 32, 128), (3 * 4096 + 777, 24, 96),
                                    (2 * 4096 + 5, 70, 200)])
-def test_f64_srht_elementwise(n, m, l):
-    log(f"rhqr f64 srht n={n} m={m} l={l}")
-    W, Win, g, sk = _run(0, n, m, l, 2)
+def test_f64_srht_elementwise(n, m, l, panel):
+    log(f"rhqr f64 srht n={n} m={m} l={l} panel={panel}")
+    W, Win, g, sk = _run(0, n, m, l, 2, panel=panel)
     ref = orq.rhqr_left(W, sk)
     assert g["info"] == 0
     assert rel(g["R"], ref["R"]) < 1e-12
@@ -59,9 +60,10 @@ def test_f64_scaling_sqrt2():
     assert np.allclose(np.sum(g["S"] ** 2, axis=0), 2.0, rtol=1e-13)
 
 
-def test_f64_gauss_elementwise():
+@pytest.mark.parametrize("panel", [0, 8])
+def test_f64_gauss_elementwise(panel):
     n, m, l = 2 * 4096 + 300, 20, 80
-    W, Win, g, sk = _run(1, n, m, l, 2)
+    W, Win, g, sk = _run(1, n, m, l, 2, panel=panel)
     ref = orq.rhqr_left(W, sk)
     assert rel(g["R"], ref["R"]) < 1e-12
     assert rel(g["S"], ref["S"]) < 1e-12
@@ -69,10 +71,11 @@ def test_f64_gauss_elementwise():
     assert rel(g["U"], ref["U"]) < 1e-12
 
 
-def test_c1_ill_conditioned():
+@pytest.mark.parametrize("panel", [0, 8])
+def test_c1_ill_conditioned(panel):
     """4096 x 32, singular values 1..1e-8, SRHT l=128, seed 0."""
     n, m, l = 4096, 32, 128
-    W, Win, g, sk = _run(0, n, m, l, 8, seed=0)
+    W, Win, g, sk = _run(0, n, m, l, 8, seed=0, panel=panel)
     ref = orq.rhqr_left(W, sk)
     Q = g["Q"]
     ef = metrics.fact_error(W, Q, g["R"])
@@ -87,11 +90,12 @@ def test_c1_ill_conditioned():
     assert np.linalg.norm(g["R"] - ref["R"]) <= 1e-12 * np.linalg.norm(ref["R"]) * 1e4
 
 
+@pytest.mark.parametrize("panel", [0, 8])
 @pytest.mark.parametrize("dt,tol", [("float32", 1e-5), ("float16", 1e-2), ("bfloat16", 1e-2)])
-def test_low_precision_bounds(dt, tol):
+def test_low_precision_bounds(dt, tol, panel):
     n, m, l = 3 * 4096 + 77, 24, 96
     torch = cuda_or_skip()
-    W, Win, g, sk = _run(0, n, m, l, 6, dtype=dt)
+    W, Win, g, sk = _run(0, n, m, l, 6, dtype=dt, panel=panel)
     Q = g["Q"]
     ef = metrics.fact_error(Win, Q, g["R"])
     eo = metrics.orth_error(osk.rh_sketch(Q, sk))
