@@ -72,8 +72,32 @@ inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // 16-byte load decoded to CT; NT selects a non-temporal (streaming) load.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 template <typename ST, typename CT, bool NT = false>
 __device__ __forceinline__ void vload(const ST *p, CT *o) {
+  if constexpr (sizeof(ST) == 8) {
+    f64x2 d;
+    if constexpr (NT)
+      d = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p));
+    else
+      d = *reinterpret_cast<const f64x2 *>(p);
+    o[0] = (CT)d.x;
+    o[1] = (CT)d.y;
+    return;
+  } else if constexpr (std::is_same<ST, float>::value) {
+    f32x4 f;
+    if constexpr (NT)
+      f = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
+    else
+      f = *reinterpret_cast<const f32x4 *>(p);
+    o[0] = (CT)f.x;
+    o[1] = (CT)f.y;
+    o[2] = (CT)f.z;
+    o[3] = (CT)f.w;
+    return;
+  }
   u32x4 uv;
   if constexpr (NT)
     uv = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));

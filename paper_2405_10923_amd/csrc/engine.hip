@@ -96,7 +96,7 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
   // acc -= U_{:, <j-1} c  (stored columns, already scaled)
   if (FAST) {
     if (!head) {
-#pragma unroll 2
+#pragma unroll 1
       for (int p = p0; p < j - 1; ++p) {
         const CT cp = (CT)cf[p];
         const char *cb = (const char *)(W + (int64_t)p * ldw + base);
@@ -854,15 +854,18 @@ __global__ void __launch_bounds__(1024) k_pgram(int32_t L, int32_t J, int32_t nb
   if (lane == 0) G[p + (int64_t)jj * J] = v;
 }
 
-// C = T_{<J}^t G: C_{p,jj} = sum_{q <= p} T_{q,p} G_{q,jj}
-__global__ void k_ptri(int32_t J, int32_t nb, const double *__restrict__ T, int64_t ldt,
-                       const double *__restrict__ G, double *__restrict__ C) {
+// C = T_{<J}^t G: C_{p,jj} = sum_{q <= p} T_{q,p} G_{q,jj}, stored row-major (J x nb)
+// rows padded to pw >= nb entries (zeros beyond nb): the pw coefficients of
+// column p are contiguous and read unconditionally by the panel kernel
+__global__ void k_ptri(int32_t J, int32_t nb, int32_t pw, const double *__restrict__ T,
+                       int64_t ldt, const double *__restrict__ G, double *__restrict__ C) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int jj = blockIdx.y;
-  if (p >= J || jj >= nb) return;
+  if (p >= J || jj >= pw) return;
   double v = 0.0;
-  for (int q = 0; q <= p; ++q) v += T[q + (int64_t)p * ldt] * G[q + (int64_t)jj * J];
-  C[p + (int64_t)jj * J] = v;
+  if (jj < nb)
+    for (int q = 0; q <= p; ++q) v += T[q + (int64_t)p * ldt] * G[q + (int64_t)jj * J];
+  C[(int64_t)p * pw + jj] = v;
 }
 
 // W[m:n, J:J+nb] -= U[m:n, 0:J] C.  Each thread streams VEC consecutive rows
@@ -870,96 +873,89 @@ __global__ void k_ptri(int32_t J, int32_t nb, const double *__restrict__ T, int6
 // coefficients sit in LDS (broadcast reads); U is read exactly once.
 constexpr int PANEL_TPB = 256;
 
+template <typename ST, typename CT, int VEC>
+__device__ __forceinline__ void panel_load(const ST *p, CT *x) {
+  if constexpr (sizeof(ST) * VEC == 16) {
+    vload<ST, CT, true>(p, x);
+  } else {  // 8 bytes: four 2-byte values
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 u = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+    const uint32_t wd[2] = {u.x, u.y};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const unsigned short bits = (unsigned short)(wd[e >> 1] >> (16 * (e & 1)));
+      if constexpr (std::is_same<ST, __half>::value)
+        x[e] = (CT)__half2float(__ushort_as_half(bits));
+      else
+        x[e] = (CT)__uint_as_float(((uint32_t)bits) << 16);
+    }
+  }
+}
+
 template <typename ST, int NBC>
 __global__ void __launch_bounds__(PANEL_TPB) k_panel(ST *__restrict__ W, int64_t ldw, int64_t n,
                                                      int32_t m, int32_t J, int32_t nb,
-                                                     const double *__restrict__ C, int aligned) {
+                                                     const double *__restrict__ Ct, int aligned) {
   using CT = typename CompT<ST>::type;
   constexpr int VEC = sizeof(ST) == 8 ? 2 : 4;   // rows per thread
-  constexpr int KC = 64;  // panel coefficients staged KC rows at a time
-  __shared__ CT Cs[KC][NBC];
   const int64_t mb = m - (m % VEC);  // aligned start; head rows < m are not written
-  const int64_t r0 = mb + ((int64_t)blockIdx.x * PANEL_TPB + threadIdx.x) * VEC;
-  const bool live = r0 < n;
-  const bool full = aligned && r0 + VEC <= n && (r0 % VEC) == 0;
+  const int64_t rb = mb + (int64_t)blockIdx.x * PANEL_TPB * VEC;  // first row of the workgroup
+  const int64_t r0 = rb + (int64_t)threadIdx.x * VEC;
+  if (r0 >= n) return;
+  // uniform: every thread's vector is in bounds and aligned
+  const bool fast = aligned && rb + (int64_t)PANEL_TPB * VEC <= n;
+  const uint32_t off = (uint32_t)(threadIdx.x * VEC * sizeof(ST));
   CT acc[VEC][NBC];
 #pragma unroll
   for (int e = 0; e < VEC; ++e)
 #pragma unroll
     for (int c = 0; c < NBC; ++c) acc[e][c] = (CT)0;
-  for (int k0 = 0; k0 < J; k0 += KC) {
-    const int kn = J - k0 < KC ? J - k0 : KC;
-    __syncthreads();
-    for (int e = threadIdx.x; e < kn * NBC; e += PANEL_TPB) {
-      const int k = e / NBC, c = e % NBC;
-      Cs[k][c] = c < nb ? (CT)C[k0 + k + (int64_t)c * J] : (CT)0;
-    }
-    __syncthreads();
-    if (!live) continue;
+  // coefficients of column k: Ct[k * NBC + c], zero beyond nb (uniform
+  // addresses: scalar loads)
+  auto coef = [&](int k, int c) -> CT { return (CT)Ct[(int64_t)k * NBC + c]; };
+  if (fast) {
     int k = 0;
-    if (full) {
-      // four columns' loads issued before their products
-      for (; k + 4 <= kn; k += 4) {
-        CT xs[4][VEC];
+    for (; k + 4 <= J; k += 4) {
+      CT xs[4][VEC];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const ST *col = W + (int64_t)(k0 + k + u) * ldw + r0;
-          if constexpr (sizeof(ST) >= 4) {
-            vload<ST, CT, true>(col, xs[u]);
-          } else {
-            const uint2 uu = *reinterpret_cast<const uint2 *>(col);
-            const uint32_t wd[2] = {uu.x, uu.y};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const unsigned short bits = (unsigned short)(wd[e >> 1] >> (16 * (e & 1)));
-              if constexpr (std::is_same<ST, __half>::value)
-                xs[u][e] = (CT)__half2float(__ushort_as_half(bits));
-              else
-                xs[u][e] = (CT)__uint_as_float(((uint32_t)bits) << 16);
-            }
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int c = 0; c < NBC; ++c) {
-            const CT ck = Cs[k + u][c];
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[e][c] += xs[u][e] * ck;
-          }
+      for (int u = 0; u < 4; ++u) {
+        const char *cb = (const char *)(W + (int64_t)(k + u) * ldw + rb);  // uniform
+        panel_load<ST, CT, VEC>((const ST *)(cb + off), xs[u]);
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < NBC; ++c) {
+          const CT ck = coef(k + u, c);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[e][c] += xs[u][e] * ck;
+        }
     }
-    for (; k < kn; ++k) {
-      const ST *col = W + (int64_t)(k0 + k) * ldw + r0;
+    for (; k < J; ++k) {
+      const char *cb = (const char *)(W + (int64_t)k * ldw + rb);
       CT x[VEC];
-      if (full) {
-        if constexpr (sizeof(ST) >= 4) {
-          vload<ST, CT, true>(col, x);
-        } else {
-          const uint2 u = *reinterpret_cast<const uint2 *>(col);
-          const uint32_t wd[2] = {u.x, u.y};
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const unsigned short bits = (unsigned short)(wd[e >> 1] >> (16 * (e & 1)));
-            if constexpr (std::is_same<ST, __half>::value)
-              x[e] = (CT)__half2float(__ushort_as_half(bits));
-            else
-              x[e] = (CT)__uint_as_float(((uint32_t)bits) << 16);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) x[e] = r0 + e < n ? cvt_in<CT>(col[e]) : (CT)0;
-      }
+      panel_load<ST, CT, VEC>((const ST *)(cb + off), x);
 #pragma unroll
       for (int c = 0; c < NBC; ++c) {
-        const CT ck = Cs[k][c];
+        const CT ck = coef(k, c);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e][c] += x[e] * ck;
+      }
+    }
+  } else {
+    for (int k = 0; k < J; ++k) {
+      const ST *col = W + (int64_t)k * ldw + r0;
+      CT x[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) x[e] = r0 + e < n ? cvt_in<CT>(col[e]) : (CT)0;
+#pragma unroll
+      for (int c = 0; c < NBC; ++c) {
+        const CT ck = coef(k, c);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e][c] += x[e] * ck;
       }
     }
   }
-  if (!live) return;
 #pragma unroll
   for (int c = 0; c < NBC; ++c) {
     if (c >= nb) break;
@@ -969,6 +965,8 @@ __global__ void __launch_bounds__(PANEL_TPB) k_panel(ST *__restrict__ W, int64_t
       if (r0 + e < n && r0 + e >= m) wc[e] = cvt_out<ST>((double)(cvt_in<CT>(wc[e]) - acc[e][c]));
   }
 }
+
+inline int panel_width(int nb) { return nb <= 8 ? 8 : nb <= 16 ? 16 : 32; }
 
 template <typename ST>
 void launch_panel(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t J, int32_t nb, const double *C,
@@ -1004,8 +1002,9 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, double *C, 
       hipLaunchKernelGGL(k_pgram, dim3((ne + 15) / 16), dim3(1024), 0, st, L, J, nb, a.S, a.lds,
                          a.Z, a.ldz, G);
       RHQR_HIP(hipGetLastError());
-      hipLaunchKernelGGL(k_ptri, dim3((J + 255) / 256, nb), dim3(256), 0, st, J, nb, a.T, a.ldt, G,
-                         C);
+      const int pw = panel_width(nb);
+      hipLaunchKernelGGL(k_ptri, dim3((J + 255) / 256, pw), dim3(256), 0, st, J, nb, pw, a.T,
+                         a.ldt, G, C);
       RHQR_HIP(hipGetLastError());
       if (ntail > 0) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
