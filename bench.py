@@ -186,6 +186,9 @@ def main():
                     help="skip the column-by-column float64 reference schedule")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=32)
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
+                    help="first copy a GIB-sized buffer three times (a plain copy kernel of "
+                         "known traffic, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}): the row-sharded "
@@ -198,6 +201,16 @@ def main():
 
     n, m, l, kappa = args.n, args.m, args.l, args.kappa
     torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        nb = int(args.copy_probe * (1 << 30)) // 4
+        src = torch.ones(nb, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy probe: {nb * 4} bytes read and written per copy", file=sys.stderr,
+              flush=True)
+        del src, dst
     print(f"# workload n={n} m={m} l={l} cond=1e{kappa:g}", file=sys.stderr, flush=True)
     W64 = synthetic_matrix_torch(n, m, kappa, seed=0, device="cuda")
     sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=0)

@@ -872,6 +872,7 @@ __global__ void k_ptri(int32_t J, int32_t nb, int32_t pw, const double *__restri
 // of U (one 16-byte load per column) against all NBC panel columns, whose
 // coefficients sit in LDS (broadcast reads); U is read exactly once.
 constexpr int PANEL_TPB = 256;
+constexpr int PANEL_KB = 8;  // columns of U whose loads are in flight together
 
 template <typename ST, typename CT, int VEC>
 __device__ __forceinline__ void panel_load(const ST *p, CT *x) {
@@ -889,6 +890,19 @@ __device__ __forceinline__ void panel_load(const ST *p, CT *x) {
       else
         x[e] = (CT)__uint_as_float(((uint32_t)bits) << 16);
     }
+  }
+}
+
+template <typename ST, typename CT, int VEC>
+__device__ __forceinline__ void panel_store(ST *p, const CT *x) {
+  if constexpr (sizeof(ST) * VEC == 16) {
+    vstore<ST, CT>(p, x);
+  } else {  // 8 bytes: four 2-byte values
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    u32x2 u;
+    u.x = (uint32_t)enc16<ST>((float)x[0]) | ((uint32_t)enc16<ST>((float)x[1]) << 16);
+    u.y = (uint32_t)enc16<ST>((float)x[2]) | ((uint32_t)enc16<ST>((float)x[3]) << 16);
+    *reinterpret_cast<u32x2 *>(p) = u;
   }
 }
 
@@ -915,15 +929,18 @@ __global__ void __launch_bounds__(PANEL_TPB) k_panel(ST *__restrict__ W, int64_t
   auto coef = [&](int k, int c) -> CT { return (CT)Ct[(int64_t)k * NBC + c]; };
   if (fast) {
     int k = 0;
-    for (; k + 4 <= J; k += 4) {
-      CT xs[4][VEC];
+    for (; k + PANEL_KB <= J; k += PANEL_KB) {
+      CT xs[PANEL_KB][VEC];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < PANEL_KB; ++u) {
         const char *cb = (const char *)(W + (int64_t)(k + u) * ldw + rb);  // uniform
         panel_load<ST, CT, VEC>((const ST *)(cb + off), xs[u]);
       }
+      // keep the PANEL_KB loads issued together ahead of the arithmetic (the
+      // scheduler otherwise sinks each load to its first use)
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < PANEL_KB; ++u)
 #pragma unroll
         for (int c = 0; c < NBC; ++c) {
           const CT ck = coef(k + u, c);
@@ -956,13 +973,31 @@ __global__ void __launch_bounds__(PANEL_TPB) k_panel(ST *__restrict__ W, int64_t
       }
     }
   }
+  if (fast && r0 >= m) {
+    // whole-vector read-modify-write: partial stores would cost extra HBM
+    // write and fetch traffic
+#pragma unroll
+    for (int c = 0; c < NBC; ++c) {
+      if (c < nb) {  // uniform; a break here would stop the unrolling
+        ST *wc = W + (int64_t)(J + c) * ldw + r0;
+        CT x[VEC];
+        panel_load<ST, CT, VEC>(wc, x);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) x[e] -= acc[e][c];
+        panel_store<ST, CT, VEC>(wc, x);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < NBC; ++c) {
-    if (c >= nb) break;
-    ST *wc = W + (int64_t)(J + c) * ldw + r0;
+    if (c < nb) {
+      ST *wc = W + (int64_t)(J + c) * ldw + r0;
 #pragma unroll
-    for (int e = 0; e < VEC; ++e)
-      if (r0 + e < n && r0 + e >= m) wc[e] = cvt_out<ST>((double)(cvt_in<CT>(wc[e]) - acc[e][c]));
+      for (int e = 0; e < VEC; ++e)
+        if (r0 + e < n && r0 + e >= m)
+          wc[e] = cvt_out<ST>((double)(cvt_in<CT>(wc[e]) - acc[e][c]));
+    }
   }
 }
 
