@@ -249,6 +249,7 @@ extern "C" int rhqr_arnoldi_create(rhqr_sketch_t h, int dtype, int64_t n, int32_
   la.signs = h->d_signs;
   la.rows = h->d_rows;
   la.omega = h->d_omega;
+  la.defer = 0;  // launch_coef forms every coefficient of c
   int rc = launch_fill(a->lw.status, 16, st);
   if (!rc) {
     hipLaunchKernelGGL(k_zero, dim3(((int64_t)kh * kh + 255) / 256), dim3(256), 0, st, a->T,

@@ -28,6 +28,14 @@ constexpr int TILE = 1 << TILE_LOG;
 constexpr int TILE_PAD = TILE + TILE / 16;  // one pad slot per 16 entries
 __device__ __forceinline__ int tpad(int i) { return i + (i >> 4); }
 
+// Workgroup barrier that orders LDS accesses only: global loads issued before
+// it stay in flight (a full __syncthreads waits for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 struct rhqr_sketch_s {
   int kind;
   int64_t n;
@@ -164,9 +172,31 @@ __device__ __forceinline__ void vstore(ST *p, const CT *v) {
 }
 
 // ---------------------------------------------------------------- reductions
+// Wavefront sum with DPP row moves (butterflies inside each 16-lane row) and
+// four lane reads across the rows; every lane receives the same total, summed
+// in a fixed order.  All 64 lanes must be active.
+template <int CTRL> __device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_read(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double lane_read(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  v += dpp_mov<0x140>(v);  // row_mirror: every lane holds its row's sum
+  return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
 // Sum over a workgroup; `red` is LDS scratch of >= blockDim.x/64 entries.

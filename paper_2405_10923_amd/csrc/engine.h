@@ -6,7 +6,8 @@
 
 struct LoopWs {
   int32_t *status;   // first column with rho_j = 0 (1-based), 0 if none
-  uint32_t *counter; // arrival counter of the last-workgroup step (zero between calls)
+  double *dcpart;    // [m / 16] per-workgroup sums of d_p c_p (deferred last coefficient)
+  double *fs;        // beta_j and e_j of the deferred last coefficient
   double *y;         // (l+m) sketch of the refreshed column
   double *sq;        // per-workgroup partial sums of squares
   double *dpart;     // [G_red][m] partial S^t y (masked to rows >= j)
@@ -42,6 +43,7 @@ struct LoopArgs {
   const uint64_t *signs;
   const int32_t *rows;
   const double *omega;  // l x (n-m), ld l
+  int defer;          // the step of column j-1 left c_{j-1} to be finished by column j
 };
 
 size_t loop_ws_bytes(int kind, int dtype, int64_t n, int32_t m, int32_t l);

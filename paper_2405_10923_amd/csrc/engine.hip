@@ -55,6 +55,26 @@ int prof_pair(hipEvent_t *a, hipEvent_t *b, int cls) {
   return RHQR_OK;
 }
 
+// workgroups of the float64 step of column j (FIN_P values of p each)
+constexpr int FIN_P = 16;
+inline int fin_groups(int32_t j) { return j > 0 ? (j + FIN_P - 1) / FIN_P : 1; }
+
+// ------------------------------------------------------ deferred c_{j-1}
+// The last coefficient of c_j = T_{j-1}^t S_{j-1}^t z_j is
+//     c_{j-1} = beta_{j-1} (e_{j-1} - sum_{p < j-1} d_p c_p)
+// (d = S^t s_{j-1}, e = S^t z_j).  The step of column j-1 leaves beta and e_{j-1}
+// in fs[0..1] and per-workgroup partial sums of d_p c_p in dcpart[0..gfin); the
+// consumers (the next reduction and tall pass) finish it themselves, so the
+// step needs no cross-workgroup hand-off.  Called by whole waves; fixed order.
+__device__ __forceinline__ double deferred_c(const double *__restrict__ fs,
+                                             const double *__restrict__ dcpart, int gfin) {
+  const int lane = threadIdx.x & 63;
+  double v = 0.0;
+  for (int g = lane; g < gfin; g += 64) v += dcpart[g];
+  v = wave_sum(v);
+  return fs[0] * (fs[1] - v);
+}
+
 // ------------------------------------------------------------------ k_tall
 // One workgroup per TILE rows; thread t owns rows base + VEC*(t + 256 v) + e.
 // FAST: every 16-byte vector of the tile is in bounds and aligned; head rows
@@ -65,7 +85,7 @@ int prof_pair(hipEvent_t *a, hipEvent_t *b, int cls) {
 template <typename ST, bool FAST, int NV>
 __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
                                           int32_t j, int32_t p0, bool prev,
-                                          const double *__restrict__ cf,
+                                          const double *__restrict__ cf, double cprev,
                                           double iaprev, float *__restrict__ wstage,
                                           int64_t base,
                                           typename CompT<ST>::type (&acc)[NV][16 / sizeof(ST)]) {
@@ -142,7 +162,7 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
   // (prev == false: column j-1 was already stored scaled and applied by the
   // panel update of the blocked schedule.)
   if (j >= 1 && prev) {
-    const CT cp = (CT)cf[j - 1];
+    const CT cp = (CT)cprev;
     const CT ia = (CT)iaprev;
     ST *col = W + (int64_t)(j - 1) * ldw;
     const bool from_stage = LOWP && j >= 2;
@@ -245,7 +265,10 @@ __global__ void __launch_bounds__(TALL_TPB) k_tall(ST *__restrict__ W, int64_t l
                                                    double *__restrict__ part,
                                                    const uint64_t *__restrict__ signs,
                                                    const int32_t *__restrict__ rows, int32_t l,
-                                                   const double *__restrict__ om, int aligned) {
+                                                   const double *__restrict__ om, int aligned,
+                                                   int defer, int gfin,
+                                                   const double *__restrict__ fs,
+                                                   const double *__restrict__ dcpart) {
   using CT = typename CompT<ST>::type;
   constexpr int VEC = 16 / sizeof(ST);
   constexpr int ROWS = TILE * TPW;
@@ -255,12 +278,17 @@ __global__ void __launch_bounds__(TALL_TPB) k_tall(ST *__restrict__ W, int64_t l
   const int64_t base = (int64_t)blockIdx.x * ROWS;
   const bool fast = aligned && base + ROWS <= n;
   const bool prev = j - 1 >= p0;
-  const double iaprev = (j >= 1 && prev) ? ia[j - 1] : 0.0;
+  // coefficient of the raw previous column: c_{j-1} / alpha_{j-1}
+  double iaprev = 0.0, cprev = 0.0;
+  if (j >= 1 && prev) {
+    iaprev = ia[j - 1];
+    cprev = defer ? deferred_c(fs, dcpart, gfin) * iaprev : cf[j - 1];
+  }
   CT acc[NV][VEC];
   if (fast)
-    tall_body<ST, true, NV>(W, ldw, n, m, j, p0, prev, cf, iaprev, wstage, base, acc);
+    tall_body<ST, true, NV>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, wstage, base, acc);
   else
-    tall_body<ST, false, NV>(W, ldw, n, m, j, p0, prev, cf, iaprev, wstage, base, acc);
+    tall_body<ST, false, NV>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, wstage, base, acc);
 
   if (KIND == RHQR_SKETCH_IDENT) return;
   const int tid = threadIdx.x;
@@ -340,12 +368,18 @@ __global__ void __launch_bounds__(TALL_TPB) k_tall(ST *__restrict__ W, int64_t l
 //   dpart_p = sum S_{k,p} y_k      (p < j)   (S^t s_j up to the pivot term)
 //   epart_p = sum S_{k,p} z_k      (p < j)   (S^t z_{j+1}, z the next pre-sketch)
 //   ypart   = sum y_k z_k                    (s_j^t z_{j+1} up to the pivot term)
+// Every load that does not depend on y (the S entries of the dot products, z,
+// the partials) is issued before the first wait.
+constexpr int RED_NP = 16;  // per-lane loads issued together
+
 template <typename ST, int KIND>
 __global__ void __launch_bounds__(1024) k_red(const ST *__restrict__ W, int64_t ldw, int32_t m,
                                               int32_t l, int32_t j, int next,
                                               const double *__restrict__ Z, int64_t ldz,
                                               const double *__restrict__ S, int64_t lds,
-                                              const double *__restrict__ c,
+                                              const double *__restrict__ c, int defer, int gfin,
+                                              const double *__restrict__ fs,
+                                              const double *__restrict__ dcpart,
                                               const double *__restrict__ part, int64_t nparts,
                                               double scale, double *__restrict__ y,
                                               double *__restrict__ sq, double *__restrict__ dpart,
@@ -357,31 +391,48 @@ __global__ void __launch_bounds__(1024) k_red(const ST *__restrict__ W, int64_t 
   const bool head = (int)blockIdx.x < nhb;
   const int k = head ? (int)blockIdx.x * RED_CHUNK + lane : m + ((int)blockIdx.x - nhb) * RED_CHUNK + lane;
   const bool valid = head ? (k < m) : (k < m + l);
-  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-  if (valid && j >= 1) {
+  // S entries of the first RED_NP dot products of this wave, and z
+  double sp[RED_NP];
+#pragma unroll
+  for (int b = 0; b < RED_NP; ++b) {
+    const int p = w + 16 * b;
+    sp[b] = (valid && p < j) ? S[k + (int64_t)p * lds] : 0.0;
+  }
+  const double z = (next && valid) ? Z[k + (int64_t)(j + 1) * ldz] : 0.0;
+  double v = 0.0;
+  if (j >= 1) {
     if (head) {
-      const int pe = min(j, k + 1);
-      int p = w;
-      for (; p + 48 < pe; p += 64) {
-        v0 += S[k + (int64_t)p * lds] * c[p];
-        v1 += S[k + (int64_t)(p + 16) * lds] * c[p + 16];
-        v2 += S[k + (int64_t)(p + 32) * lds] * c[p + 32];
-        v3 += S[k + (int64_t)(p + 48) * lds] * c[p + 48];
+      const double clast = defer ? deferred_c(fs, dcpart, gfin) : 0.0;
+      const int pe = valid ? min(j, k + 1) : 0;
+      for (int p0 = w; p0 < pe; p0 += 16 * RED_NP) {
+        double t[RED_NP];
+#pragma unroll
+        for (int b = 0; b < RED_NP; ++b) {
+          const int p = p0 + 16 * b;
+          t[b] = 0.0;
+          if (p < pe) {
+            const double cp = (defer && p == j - 1) ? clast : c[p];
+            t[b] = S[k + (int64_t)p * lds] * cp;
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < RED_NP; ++b) v += t[b];
       }
-      for (; p < pe; p += 16) v0 += S[k + (int64_t)p * lds] * c[p];
-    } else if (KIND != RHQR_SKETCH_IDENT) {
+    } else if (KIND != RHQR_SKETCH_IDENT && valid) {
       const double *pq = part + (k - m);
-      int64_t t = w;
-      for (; t + 48 < nparts; t += 64) {
-        v0 += pq[t * l];
-        v1 += pq[(t + 16) * l];
-        v2 += pq[(t + 32) * l];
-        v3 += pq[(t + 48) * l];
+      for (int64_t t0 = w; t0 < nparts; t0 += 16 * RED_NP) {
+        double t[RED_NP];
+#pragma unroll
+        for (int b = 0; b < RED_NP; ++b) {
+          const int64_t tt = t0 + 16 * b;
+          t[b] = tt < nparts ? pq[tt * l] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < RED_NP; ++b) v += t[b];
       }
-      for (; t < nparts; t += 16) v0 += pq[t * l];
     }
   }
-  red[w][lane] = (v0 + v1) + (v2 + v3);
+  red[w][lane] = v;
   __syncthreads();
   if (w == 0) {
     double s = 0.0;
@@ -401,26 +452,25 @@ __global__ void __launch_bounds__(1024) k_red(const ST *__restrict__ W, int64_t 
     const double ym = (valid && k >= j) ? out : 0.0;
     yl[lane] = ym;
     const double tot = wave_sum(ym * ym);
-    if (lane == 0) sq[blockIdx.x] = tot;
+    const double yz = next ? wave_sum(ym * z) : 0.0;
+    if (lane == 0) {
+      sq[blockIdx.x] = tot;
+      if (next) ypart[blockIdx.x] = yz;
+    }
   }
   __syncthreads();
   const double ym = yl[lane];
-  const double z = (next && valid) ? Z[k + (int64_t)(j + 1) * ldz] : 0.0;
-  if (next && w == 0) {
-    const double yz = wave_sum(ym * z);
-    if (lane == 0) ypart[blockIdx.x] = yz;
-  }
-  // partial dot products with the earlier columns of S, one wave per p;
-  // eight p's loads are issued before their reductions
-  for (int p0 = w; p0 < j; p0 += 16 * 8) {
-    double sp[8];
+  // partial dot products with the earlier columns of S, one wave per p
+  for (int p0 = w; p0 < j; p0 += 16 * RED_NP) {
+    if (p0 > w) {  // columns beyond the prefetched ones (j > 16 RED_NP)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int p = p0 + 16 * b;
-      sp[b] = (valid && p < j) ? S[k + (int64_t)p * lds] : 0.0;
+      for (int b = 0; b < RED_NP; ++b) {
+        const int p = p0 + 16 * b;
+        sp[b] = (valid && p < j) ? S[k + (int64_t)p * lds] : 0.0;
+      }
     }
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < RED_NP; ++b) {
       const int p = p0 + 16 * b;
       if (p < j) {  // uniform across the wave
         const double dv = wave_sum(sp[b] * ym);
@@ -471,11 +521,12 @@ __device__ __forceinline__ StepScalars step_scalars(const double *y, double ss, 
 //   s_j = ((0; y_{j:}) + sigma rho e_j) / alpha  -> S_{:, j};  R_{:, j};
 //   d = S^t s_j,  e = S^t z_{j+1}  (from the k_red partials plus the pivot term);
 //   T_{p,j} = -beta (T_{j-1} d)_p,  c_{j+1,p} = (T_{j-1}^t e)_p  for p < j,
-// one wave per p, FIN_P values of p per workgroup; T_{j,j} = beta.  The
-// workgroup that finishes last (device-scope counter) forms the last
-// coefficient c_{j+1,j} = beta (e_j - d . c_{:j}) and the folded copy cf used by
-// the next tall pass (the raw column j is divided by alpha_j there).
-constexpr int FIN_P = 16;
+// one wave per p, FIN_P values of p per workgroup; T_{j,j} = beta.  The last
+// coefficient c_{j+1,j} is left to its consumers (deferred_c): workgroup g
+// writes sum_{p in g} d_p c_{j+1,p} to dcpart[g], workgroup 0 writes beta and
+// e_j to fs.  The partial sums, the rows of T and the pivot row of S are all
+// loaded before the first wait.
+constexpr int FIN_NQ = 4;  // T entries per lane loaded together
 
 __global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t l, int32_t j, int next,
                                               int scaling, int gred,
@@ -491,21 +542,44 @@ __global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t l, int32_t j, i
                                               int64_t ldr, double *__restrict__ scal,
                                               double *__restrict__ c, double *__restrict__ cf,
                                               double *__restrict__ ia, int32_t *__restrict__ status,
-                                              uint32_t *__restrict__ counter) {
-  __shared__ double d[MAXM], e[MAXM];
+                                              double *__restrict__ dcpart, double *__restrict__ fs) {
+  __shared__ double d[MAXM], e[MAXM + 1];
+  __shared__ double wdc[16];
   __shared__ StepScalars shs;
   __shared__ double yzs;
-  __shared__ int last;
-  if (threadIdx.x < 64) {
-    // wave 0 sums the partials in a fixed order (lane-strided, then a tree)
+  const bool needc = next != 0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p = (int)blockIdx.x * FIN_P + w;  // this wave's index (p < j)
+  // ---- loads that need nothing computed here
+  // this wave's row of T (T_{p,q}, q in [p, j): from the transposed copy) and
+  // column of T (T_{q,p}, q <= p)
+  double tr[FIN_NQ], tc[FIN_NQ];
+  const bool pw = w < FIN_P && p < j;
+#pragma unroll
+  for (int i = 0; i < FIN_NQ; ++i) {
+    const int qr = p + lane + 64 * i, qc = lane + 64 * i;
+    tr[i] = (pw && qr < j) ? Tt[qr + (int64_t)p * m] : 0.0;
+    tc[i] = (pw && needc && qc <= p) ? T[qc + (int64_t)p * ldt] : 0.0;
+  }
+  // thread q: the partial dot products d_q, e_q and the pivot-row entry S_{j,q}
+  const int q = threadIdx.x;
+  double dv = 0.0, ev = 0.0, sjq = 0.0;
+  if (q < j) {
+    sjq = S[j + (int64_t)q * lds];
+    for (int g = 0; g < gred; ++g) {
+      dv += dpart[(int64_t)g * m + q];
+      if (needc) ev += epart[(int64_t)g * m + q];
+    }
+  }
+  if (w == 0) {
     double ss = 0.0, yz = 0.0;
-    for (int g = threadIdx.x; g < gred; g += 64) {
+    for (int g = lane; g < gred; g += 64) {
       ss += sq[g];
-      if (next) yz += ypart[g];
+      if (needc) yz += ypart[g];
     }
     ss = wave_sum(ss);
     yz = wave_sum(yz);
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
       shs = step_scalars(y, ss, j, scaling);
       yzs = yz;
     }
@@ -513,10 +587,16 @@ __global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t l, int32_t j, i
   __syncthreads();
   const StepScalars sc = shs;
   const double sr = sc.sigma * sc.rho;
-  const bool needc = next != 0;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int L = l + m;
+  if (q < j) {
+    d[q] = sc.ident ? sjq : (dv + sr * sjq) / sc.alpha;
+    e[q] = ev;
+  }
+  if (q == j && needc) {
+    const double zj = Z[j + (int64_t)(j + 1) * ldz];
+    e[j] = sc.ident ? zj : (yzs + sr * zj) / sc.alpha;
+  }
   // s_j into S_{:, j} (grid-stride over the l+m rows)
+  const int L = l + m;
   for (int k = (int)blockIdx.x * blockDim.x + threadIdx.x; k < L; k += gridDim.x * blockDim.x) {
     double s = 0.0;
     if (k == j)
@@ -525,55 +605,24 @@ __global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t l, int32_t j, i
       s = sc.ident ? 0.0 : y[k] / sc.alpha;
     S[k + (int64_t)j * lds] = s;
   }
-  if (blockIdx.x == 0) {
-    for (int r = threadIdx.x; r < m; r += blockDim.x)
-      R[r + (int64_t)j * ldr] = r < j ? y[r] : (r == j ? -sr : 0.0);
-    if (threadIdx.x == 0) {
-      scal[4 * j + 0] = sc.sigma;
-      scal[4 * j + 1] = sc.rho;
-      scal[4 * j + 2] = sc.alpha;
-      scal[4 * j + 3] = sc.beta;
-      if (sc.ident) atomicCAS(status, 0, j + 1);
-    }
-  }
-  // reduce the partial dot products: 64 indices x 16 group lanes per pass
-  {
-    const int pl = threadIdx.x >> 4, gl = threadIdx.x & 15;
-    for (int p0 = 0; p0 < j; p0 += 64) {
-      const int p = p0 + pl;
-      double dv = 0.0, ev = 0.0;
-      if (p < j) {
-        for (int g = gl; g < gred; g += 16) {
-          dv += dpart[(int64_t)g * m + p];
-          if (needc) ev += epart[(int64_t)g * m + p];
-        }
-      }
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) {
-        dv += __shfl_xor(dv, o, 64);
-        ev += __shfl_xor(ev, o, 64);
-      }
-      if (gl == 0 && p < j) {
-        const double sjp = S[j + (int64_t)p * lds];  // row j of an earlier column
-        d[p] = sc.ident ? sjp : (dv + sr * sjp) / sc.alpha;
-        e[p] = ev;
-      }
-    }
-    if (threadIdx.x == 0 && needc) {
-      const double zj = Z[j + (int64_t)(j + 1) * ldz];
-      e[j] = sc.ident ? zj : (yzs + sr * zj) / sc.alpha;
-    }
-  }
   __syncthreads();
   const double beta = sc.beta;
-  const int p = (int)blockIdx.x * FIN_P + w;
-  if (w < FIN_P && p < j) {
+  double dcw = 0.0;
+  if (pw) {
     double td = 0.0, te = 0.0;
-    for (int q = p + lane; q < j; q += 64) td += Tt[q + (int64_t)p * m] * d[q];  // T_{p,q}
+#pragma unroll
+    for (int i = 0; i < FIN_NQ; ++i) {
+      const int qr = p + lane + 64 * i, qc = lane + 64 * i;
+      if (qr < j) td += tr[i] * d[qr];
+      if (needc && qc <= p) te += tc[i] * e[qc];
+    }
+    // rows beyond the prefetched ones (j > 64 FIN_NQ)
+    for (int qr = p + lane + 64 * FIN_NQ; qr < j; qr += 64) td += Tt[qr + (int64_t)p * m] * d[qr];
     if (needc)
-      for (int q = lane; q <= p; q += 64) te += T[q + (int64_t)p * ldt] * e[q];  // T_{q,p}
+      for (int qc = lane + 64 * FIN_NQ; qc <= p; qc += 64) te += T[qc + (int64_t)p * ldt] * e[qc];
     td = wave_sum(td);
     te = wave_sum(te);
+    dcw = d[p] * te;
     if (lane == 0) {
       const double t = -beta * td;
       T[p + (int64_t)j * ldt] = t;
@@ -584,36 +633,32 @@ __global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t l, int32_t j, i
       }
     }
   }
-  // last workgroup: diagonal, last coefficient, 1/alpha_j
-  __threadfence();
+  if (lane == 0 && w < 16) wdc[w] = dcw;
   __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const double iaj = sc.ident ? 0.0 : 1.0 / sc.alpha;
-  if (w == 0) {
-    double dc = 0.0;
-    if (needc)
-      for (int q = lane; q < j; q += 64) {
-        // written by other workgroups of this launch: device-coherent load
-        const unsigned long long bits = __hip_atomic_load(
-            reinterpret_cast<unsigned long long *>(c + q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        dc += d[q] * __longlong_as_double((long long)bits);
-      }
-    dc = wave_sum(dc);
-    if (lane == 0) {
+  if (threadIdx.x == 0) {
+    if (needc) {
+      double s = 0.0;
+      for (int i = 0; i < 16; ++i) s += wdc[i];
+      dcpart[blockIdx.x] = s;
+    }
+    if (blockIdx.x == 0) {
       T[j + (int64_t)j * ldt] = beta;
       Tt[j + (int64_t)j * m] = beta;
+      ia[j] = sc.ident ? 0.0 : 1.0 / sc.alpha;
       if (needc) {
-        const double cj = beta * (e[j] - dc);
-        c[j] = cj;
-        cf[j] = cj * iaj;
+        fs[0] = beta;
+        fs[1] = e[j];
       }
-      ia[j] = iaj;
-      *counter = 0u;
+      scal[4 * j + 0] = sc.sigma;
+      scal[4 * j + 1] = sc.rho;
+      scal[4 * j + 2] = sc.alpha;
+      scal[4 * j + 3] = sc.beta;
+      if (sc.ident) atomicCAS(status, 0, j + 1);
     }
   }
+  if (blockIdx.x == 0)
+    for (int r = threadIdx.x; r < m; r += blockDim.x)
+      R[r + (int64_t)j * ldr] = r < j ? y[r] : (r == j ? -sr : 0.0);
 }
 
 // ------------------------------------------------------------ final stores
@@ -736,9 +781,11 @@ void launch_tall(const LoopArgs &a, const LoopWs &w, int32_t j, int32_t p0, int 
                  hipStream_t st) {
   const int64_t rows = (int64_t)TILE * TPW;
   const int64_t g = (a.n + rows - 1) / rows;
+  const int defer = a.defer && j >= 1;
+  const int gfin = fin_groups(j - 1);
   hipLaunchKernelGGL((k_tall<ST, KIND, TPW>), dim3(g), dim3(TALL_TPB), 0, st, (ST *)a.W, a.ldw, a.n,
                      a.m, j, p0, w.cf, w.ia, w.wstage, w.part, a.signs, a.rows, a.l, a.omega,
-                     aligned);
+                     aligned, defer, gfin, w.fs, w.dcpart);
 }
 
 template <typename ST, int KIND>
@@ -782,19 +829,20 @@ int step_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStrea
   const int64_t nparts = (n + (int64_t)TILE * tpw - 1) / ((int64_t)TILE * tpw);
   const int gred = (m + RED_CHUNK - 1) / RED_CHUNK + (l + RED_CHUNK - 1) / RED_CHUNK;
   const double scale = a.kind == RHQR_SKETCH_SRHT ? 1.0 / std::sqrt((double)l) : 1.0;
+  const int defer = a.defer && j >= 1;
+  const int gprev = fin_groups(j - 1);
   if (a.kind == RHQR_SKETCH_IDENT)
     hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_IDENT>), dim3(gred), dim3(1024), 0, st, W, a.ldw, m,
-                       l, j, next, a.Z, a.ldz, a.S, a.lds, w.c, w.part,
-                       nparts, scale, w.y, w.sq, w.dpart, w.epart, w.ypart);
+                       l, j, next, a.Z, a.ldz, a.S, a.lds, w.c, defer, gprev, w.fs, w.dcpart,
+                       w.part, nparts, scale, w.y, w.sq, w.dpart, w.epart, w.ypart);
   else
     hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_SRHT>), dim3(gred), dim3(1024), 0, st, W, a.ldw, m,
-                       l, j, next, a.Z, a.ldz, a.S, a.lds, w.c, w.part,
-                       nparts, scale, w.y, w.sq, w.dpart, w.epart, w.ypart);
+                       l, j, next, a.Z, a.ldz, a.S, a.lds, w.c, defer, gprev, w.fs, w.dcpart,
+                       w.part, nparts, scale, w.y, w.sq, w.dpart, w.epart, w.ypart);
   RHQR_HIP(hipGetLastError());
-  const int gfin = j > 0 ? (j + FIN_P - 1) / FIN_P : 1;
-  hipLaunchKernelGGL(k_fin, dim3(gfin), dim3(1024), 0, st, m, l, j, next, a.scaling, gred, w.y,
-                     w.sq, w.dpart, w.epart, w.ypart, a.Z, a.ldz, a.S, a.lds, a.T, a.ldt, w.Tt,
-                     a.R, a.ldr, w.scal, w.c, w.cf, w.ia, w.status, w.counter);
+  hipLaunchKernelGGL(k_fin, dim3(fin_groups(j)), dim3(1024), 0, st, m, l, j, next, a.scaling, gred,
+                     w.y, w.sq, w.dpart, w.epart, w.ypart, a.Z, a.ldz, a.S, a.lds, a.T, a.ldt,
+                     w.Tt, a.R, a.ldr, w.scal, w.c, w.cf, w.ia, w.status, w.dcpart, w.fs);
   RHQR_HIP(hipGetLastError());
   return RHQR_OK;
 }
@@ -1099,6 +1147,8 @@ size_t loop_ws_bytes(int kind, int dtype, int64_t n, int32_t m, int32_t l) {
   const int gss = (L + RED_CHUNK - 1) / RED_CHUNK;
   size_t b = 0;
   b += align_up(sizeof(int32_t) * 4);
+  b += align_up(sizeof(double) * (MAXM / FIN_P));
+  b += align_up(sizeof(double) * 4);
   b += align_up(sizeof(double) * L);
   b += align_up(sizeof(double) * gred);
   b += 2 * align_up(sizeof(double) * (size_t)gred * m);
@@ -1125,7 +1175,8 @@ int loop_ws_carve(void *ws, size_t bytes, int kind, int dtype, int64_t n, int32_
     return (void *)r;
   };
   o->status = (int32_t *)take(sizeof(int32_t) * 4);
-  o->counter = (uint32_t *)(o->status + 2);
+  o->dcpart = (double *)take(sizeof(double) * (MAXM / FIN_P));
+  o->fs = (double *)take(sizeof(double) * 4);
   o->y = (double *)take(sizeof(double) * L);
   o->sq = (double *)take(sizeof(double) * gred);
   o->dpart = (double *)take(sizeof(double) * (size_t)gred * m);

@@ -115,6 +115,7 @@ extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, voi
   a.signs = h->d_signs;
   a.rows = h->d_rows;
   a.omega = h->d_omega;
+  a.defer = 1;
   rc = panel >= 2 ? run_column_loop_blocked(a, w.loop, panel, w.C, w.G, st)
                   : run_column_loop(a, w.loop, st);
   if (rc) return rc;

@@ -224,6 +224,7 @@ int sketch_space_hqr(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, d
   a.signs = nullptr;
   a.rows = nullptr;
   a.omega = nullptr;
+  a.defer = 1;
   return run_column_loop(a, w, st);
 }
 

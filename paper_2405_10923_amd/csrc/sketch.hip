@@ -172,7 +172,7 @@ constexpr int SK_TPB = 1024, SK_TPW = 2;
 template <typename A> __device__ void fwht_two_tiles(A *s) {
 #pragma unroll 1
   for (int pass = 0; pass < 3; ++pass) {
-    __syncthreads();
+    lds_barrier();
     const int sh = 4 * pass;
     const int gg = threadIdx.x;
     if (gg < (TILE / 16) * SK_TPW) {
@@ -189,9 +189,13 @@ template <typename A> __device__ void fwht_two_tiles(A *s) {
       for (int k = 0; k < 16; ++k) st[tpad(base + (k << sh))] = v[k];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
+// Each workgroup walks the row groups g = blockIdx.x, blockIdx.x + gt, ... of
+// column blockIdx.y; the loads of group g + gt are issued before the transform
+// of group g (LDS-only barriers keep them in flight), so HBM reads overlap the
+// in-LDS butterflies.
 template <typename ST, typename AT, int QA>
 __global__ void __launch_bounds__(SK_TPB) k_srht_cols(const ST *__restrict__ X, int64_t ldx, int64_t n,
                                                       int32_t m, int32_t l, int64_t ngroups, int gt,
@@ -208,31 +212,42 @@ __global__ void __launch_bounds__(SK_TPB) k_srht_cols(const ST *__restrict__ X, 
   double acc[QA];
 #pragma unroll
   for (int a = 0; a < QA; ++a) acc[a] = 0.0;
-  for (int64_t g = blockIdx.x; g < ngroups; g += gt) {
+  AT xv[NV][VEC];
+  uint64_t wd[NV];
+  auto fetch = [&](int64_t g) {
     const int64_t base = g * ROWS;
     const bool fast = aligned && base + ROWS <= n;
-    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int64_t i0 = base + VEC * (threadIdx.x + SK_TPB * v);
+      if (fast) {
+        vload<ST, AT, true>(x + i0, xv[v]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) xv[v][e] = (i0 + e < n) ? cvt_in<AT>(x[i0 + e]) : (AT)0;
+      }
+      wd[v] = i0 < n ? signs[i0 >> 6] : 0ull;
+    }
+  };
+  int64_t g = blockIdx.x;
+  if (g < ngroups) fetch(g);
+  for (; g < ngroups; g += gt) {
+    const int64_t base = g * ROWS;
+    lds_barrier();  // the previous group's samples have been read
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int li0 = VEC * (threadIdx.x + SK_TPB * v);
       const int64_t i0 = base + li0;
-      AT xv[VEC];
-      if (fast) {
-        vload<ST, AT, true>(x + i0, xv);
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) xv[e] = (i0 + e < n) ? cvt_in<AT>(x[i0 + e]) : (AT)0;
-      }
-      const uint64_t word = i0 < n ? signs[i0 >> 6] : 0ull;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         const int64_t i = i0 + e;
-        AT val = (i >= m && i < n) ? xv[e] : (AT)0;
-        if ((word >> (i & 63)) & 1ull) val = -val;
+        AT val = (i >= m && i < n) ? xv[v][e] : (AT)0;
+        if ((wd[v] >> (i & 63)) & 1ull) val = -val;
         const int li = li0 + e;
         s[(li >> TILE_LOG) * TILE_PAD + tpad(li & (TILE - 1))] = val;
       }
     }
+    if (g + gt < ngroups) fetch(g + gt);
     fwht_two_tiles(s);
     const uint64_t t0 = (uint64_t)g * SK_TPW;
 #pragma unroll
