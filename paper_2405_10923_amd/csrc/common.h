@@ -137,6 +137,34 @@ __device__ __forceinline__ void vload(const ST *p, CT *o) {
   }
 }
 
+// Raw 16-byte non-temporal load and its decoding, for loops that issue a batch
+// of loads before converting any of them.
+__device__ __forceinline__ u32x4 vraw_nt(const void *p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+}
+template <typename ST, typename CT>
+__device__ __forceinline__ void vdecode(const u32x4 u, CT *o) {
+  if constexpr (sizeof(ST) == 8) {
+    o[0] = (CT)__hiloint2double((int)u.y, (int)u.x);
+    o[1] = (CT)__hiloint2double((int)u.w, (int)u.z);
+  } else if constexpr (sizeof(ST) == 4) {
+    o[0] = (CT)__uint_as_float(u.x);
+    o[1] = (CT)__uint_as_float(u.y);
+    o[2] = (CT)__uint_as_float(u.z);
+    o[3] = (CT)__uint_as_float(u.w);
+  } else {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const unsigned short b = (unsigned short)(w[k >> 1] >> (16 * (k & 1)));
+      if constexpr (std::is_same<ST, __half>::value)
+        o[k] = (CT)__half2float(__ushort_as_half(b));
+      else
+        o[k] = (CT)__uint_as_float(((uint32_t)b) << 16);
+    }
+  }
+}
+
 template <typename ST> __device__ __forceinline__ unsigned short enc16(float v) {
   if constexpr (std::is_same<ST, __half>::value)
     return __half_as_ushort(__float2half(v));

@@ -116,8 +116,35 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
   // acc -= U_{:, <j-1} c  (stored columns, already scaled)
   if (FAST) {
     if (!head) {
+      // UF columns per step so that UF * NV 16-byte loads are in flight
+      constexpr int UF = NV >= 8 ? 1 : 8 / NV;
+      int p = p0;
+      if constexpr (UF > 1) {
 #pragma unroll 1
-      for (int p = p0; p < j - 1; ++p) {
+        for (; p + UF <= j - 1; p += UF) {
+          u32x4 raw[UF][NV];
+#pragma unroll
+          for (int u = 0; u < UF; ++u) {
+            const char *cb = (const char *)(W + (int64_t)(p + u) * ldw + base);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) raw[u][v] = vraw_nt(cb + off[v]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < UF; ++u) {
+            const CT cp = (CT)cf[p + u];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              CT x[VEC];
+              vdecode<ST, CT>(raw[u][v], x);
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) acc[v][e] -= x[e] * cp;
+            }
+          }
+        }
+      }
+#pragma unroll 1
+      for (; p < j - 1; ++p) {
         const CT cp = (CT)cf[p];
         const char *cb = (const char *)(W + (int64_t)p * ldw + base);
 #pragma unroll
@@ -278,6 +305,17 @@ __global__ void __launch_bounds__(TALL_TPB) k_tall(ST *__restrict__ W, int64_t l
   const int64_t base = (int64_t)blockIdx.x * ROWS;
   const bool fast = aligned && base + ROWS <= n;
   const bool prev = j - 1 >= p0;
+  // SRHT: the workgroup's sign words and the first sample row, loaded now and
+  // used after the streaming pass
+  constexpr int NSW = ROWS / 64;
+  __shared__ uint64_t sgn[KIND == RHQR_SKETCH_SRHT ? NSW : 1];
+  uint64_t sw = 0;
+  int32_t rq = 0;
+  if (KIND == RHQR_SKETCH_SRHT) {
+    const int64_t wi = base / 64 + threadIdx.x;
+    if (threadIdx.x < NSW && wi * 64 < n) sw = signs[wi];
+    if ((int)threadIdx.x < l) rq = rows[threadIdx.x];
+  }
   // coefficient of the raw previous column: c_{j-1} / alpha_{j-1}
   double iaprev = 0.0, cprev = 0.0;
   if (j >= 1 && prev) {
@@ -293,11 +331,13 @@ __global__ void __launch_bounds__(TALL_TPB) k_tall(ST *__restrict__ W, int64_t l
   if (KIND == RHQR_SKETCH_IDENT) return;
   const int tid = threadIdx.x;
   if (KIND == RHQR_SKETCH_SRHT) {
+    if (tid < NSW) sgn[tid] = sw;
+    lds_barrier();
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int li0 = VEC * (tid + TALL_TPB * v);
       const int64_t i0 = base + li0;
-      const uint64_t word = (i0 < n) ? signs[i0 >> 6] : 0ull;
+      const uint64_t word = sgn[li0 >> 6];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         const int64_t i = i0 + e;
@@ -310,7 +350,7 @@ __global__ void __launch_bounds__(TALL_TPB) k_tall(ST *__restrict__ W, int64_t l
     fwht_tiles_lds<CT, TPW>(s);
     const uint64_t t0 = (uint64_t)blockIdx.x * TPW;
     for (int q = tid; q < l; q += TALL_TPB) {
-      const int32_t r = rows[q];
+      const int32_t r = q == tid ? rq : rows[q];
       const int r2 = tpad(r & (TILE - 1));
       const uint64_t r1 = (uint64_t)(r >> TILE_LOG);
       double h = 0.0;
