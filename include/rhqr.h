@@ -192,6 +192,55 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
                   const double *d_val, const void *d_x, void *d_y, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Batched left-looking RHQR: `count` independent factorizations (Alg. 4 with
+ * RHVector, Alg. 2), each with its own n, m, l (taken from its SRHT sketch
+ * handle), W, S, T and R as in rhqr_factor, all in one element type.
+ *   rhqr_problem: sketch (SRHT handle with the problem's n, head m and l),
+ *     d_W (n x m in dtype, ld >= n; overwritten by U), d_S ((l+m) x m float64),
+ *     d_T, d_R (m x m float64).  Device pointers, owned by the caller.
+ *   rhqr_batch_workspace_size: device workspace bytes for the batch (0 if a
+ *     problem is invalid).
+ *   rhqr_batch_create: validates the problems (m <= 1024, l <= 4096, leading
+ *     dimensions), lays the descriptors and per-problem scratch out in the
+ *     caller's workspace d_ws (kept by the batch until rhqr_batch_destroy: the
+ *     caller must keep it alive), uploads them on `stream` and synchronises.
+ *     opts: bits 0-7 rhqr_scaling; other bits must be 0 (column schedule).
+ *     Returns -1 for an invalid problem array, -3 bad dtype, -4 bad opts,
+ *     -5 null workspace, RHQR_ERR_WORKSPACE if ws_bytes is too small.
+ *   rhqr_batch_factor: factors every problem of the batch.  The work is a
+ *     fixed sequence of kernel launches (no allocation, no host
+ *     synchronisation, no memset): per column index j one refresh + re-sketch
+ *     launch, one reduction and one float64 step over the problems with
+ *     m_p > j.  use_graph != 0: the sequence is captured once into a hipGraph
+ *     (on the batch's own stream) and the graph is launched on `stream`; later
+ *     calls replay it.  Each problem's U, S, T, R equal those of rhqr_factor
+ *     with the column schedule (same device code, same reduction orders).
+ *   rhqr_batch_status: h_info[i] (host, count entries, caller order) = the
+ *     first column of problem i with rho_j = 0 (1-based), or 0.  Synchronous.
+ * Not in the paper as such: the paper factors one matrix at a time; the batch
+ * applies Alg. 4 to each problem independently.
+ * ---------------------------------------------------------------------- */
+typedef struct rhqr_problem {
+  rhqr_sketch_t sketch;
+  void *d_W;
+  int64_t ldw;
+  double *d_S;
+  int64_t lds;
+  double *d_T;
+  int64_t ldt;
+  double *d_R;
+  int64_t ldr;
+} rhqr_problem;
+typedef struct rhqr_batch_s *rhqr_batch_t;
+
+RHQR_API size_t rhqr_batch_workspace_size(const rhqr_problem *probs, int32_t count, int dtype);
+RHQR_API int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int dtype, int opts,
+                               void *d_ws, size_t ws_bytes, void *stream, rhqr_batch_t *out);
+RHQR_API int rhqr_batch_factor(rhqr_batch_t b, int use_graph, void *stream);
+RHQR_API int rhqr_batch_status(rhqr_batch_t b, void *stream, int32_t *h_info);
+RHQR_API int rhqr_batch_destroy(rhqr_batch_t b);
+
+/* ------------------------------------------------------------------------
  * Measurement aid.  Between rhqr_profile_begin() and rhqr_profile_end(), every
  * launch of the tall kernels of rhqr_factor / recrhqr_factor / the Arnoldi
  * step is bracketed by HIP events recorded on the launching stream: the

@@ -1,0 +1,442 @@
+// Batched left-looking RHQR (Alg. 4 with RHVector, Alg. 2): many independent
+// problems, each with its own W (n_p x m_p), SRHT sketch and outputs, factored
+// by one fixed sequence of launches that allocates nothing, synchronises with
+// nothing on the host and can be captured once in a hipGraph and replayed.
+//
+// Problems are ordered by decreasing m, so the problems still active at column
+// j (m_p > j) are a prefix of that order.  Per column j the sequence is one
+// tall launch, one reduction launch and one step launch over all active
+// problems; every workgroup finds its (problem, local block) in a block map
+// built at creation, then runs exactly the single-problem device code
+// (colstep.h, sketch_dev.h) on that problem's descriptor.  A problem's result
+// is therefore bitwise the one rhqr_factor (column schedule) gives it.
+#include "colstep.h"
+#include "sketch_dev.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+namespace {
+
+struct BlockMap {
+  int32_t p, local;
+};
+
+// pre-sketch of one problem's m columns
+struct SketchJob {
+  const void *X;
+  int64_t ldx, n;
+  int32_t m, l;
+  int64_t ngroups;
+  int32_t gt, aligned;
+  const uint64_t *signs;
+  const int32_t *rows;
+  double *part;
+  double *Z;
+  int64_t ldz;
+  double scale;
+};
+
+__global__ void kb_init(const ColProblem *__restrict__ P) {
+  const ColProblem &Q = P[blockIdx.x];
+  const int32_t m = Q.m;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x)
+    Q.T[(e % m) + (int64_t)(e / m) * Q.ldt] = 0.0;
+  if (threadIdx.x < 4) Q.status[threadIdx.x] = 0;
+}
+
+template <typename ST, typename AT, int QA>
+__global__ void __launch_bounds__(SK_TPB) kb_srht_cols(const SketchJob *__restrict__ J,
+                                                       const BlockMap *__restrict__ map) {
+  const BlockMap b = map[blockIdx.x];
+  const SketchJob &s = J[b.p];
+  srht_cols_block<ST, AT, QA>((const ST *)s.X, s.ldx, s.n, s.m, s.l, s.ngroups, s.gt, s.signs,
+                              s.rows, s.part, s.aligned, b.local % s.gt, b.local / s.gt);
+}
+
+template <typename ST>
+__global__ void kb_sketch_finish(const SketchJob *__restrict__ J, const BlockMap *__restrict__ cmap) {
+  const BlockMap b = cmap[blockIdx.x];
+  const SketchJob &s = J[b.p];
+  sketch_finish_one<ST>((const ST *)s.X, s.ldx, s.m, s.l, s.gt, s.part, s.scale, s.Z, s.ldz,
+                        blockIdx.y * blockDim.x + threadIdx.x, b.local);
+}
+
+template <typename ST, int TPW>
+__global__ void __launch_bounds__(TALL_TPB) kb_tall(const ColProblem *__restrict__ P,
+                                                    const BlockMap *__restrict__ map, int32_t j) {
+  const BlockMap b = map[blockIdx.x];
+  tall_block<ST, RHQR_SKETCH_SRHT, TPW>(P[b.p], j, 0, b.local);
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(1024) kb_red(const ColProblem *__restrict__ P,
+                                               const BlockMap *__restrict__ map, int32_t j) {
+  const BlockMap b = map[blockIdx.x];
+  const ColProblem &Q = P[b.p];
+  red_block<ST, RHQR_SKETCH_SRHT>(Q, j, j + 1 < Q.m, b.local);
+}
+
+__global__ void __launch_bounds__(1024) kb_fin(const ColProblem *__restrict__ P, int32_t j, int fg) {
+  const int p = blockIdx.x / fg, local = blockIdx.x % fg;
+  const ColProblem &Q = P[p];
+  fin_block(Q, j, j + 1 < Q.m, local, fg);
+}
+
+// last column stored as u = raw / alpha, head block of U written from S
+template <typename ST>
+__global__ void kb_finish(const ColProblem *__restrict__ P) {
+  const ColProblem &Q = P[blockIdx.x];
+  ST *W = (ST *)Q.W;
+  const int32_t m = Q.m, cidx = m - 1;
+  const double a = Q.ia[cidx];
+  ST *col = W + (int64_t)cidx * Q.ldw;
+  const int64_t stride = (int64_t)gridDim.y * blockDim.x;
+  for (int64_t i = m + (int64_t)blockIdx.y * blockDim.x + threadIdx.x; i < Q.n; i += stride) {
+    double raw;
+    if constexpr (std::is_same<ST, double>::value)
+      raw = col[i];
+    else
+      raw = cidx >= 1 ? (double)Q.wstage[i] : cvt_in<double>(col[i]);
+    col[i] = cvt_out<ST>(raw * a);
+  }
+  for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < (int64_t)m * m; e += stride) {
+    const int k = (int)(e % m), c = (int)(e / m);
+    W[k + (int64_t)c * Q.ldw] = cvt_out<ST>(Q.S[k + (int64_t)c * Q.lds]);
+  }
+}
+
+constexpr int FINISH_CH = 64;  // workgroups per problem in kb_finish
+
+// tall workgroups cover TPW transform tiles: two for 2-byte types (16-byte
+// loads need eight rows per thread), one otherwise
+inline int batch_tpw(int dtype) { return dtype_size(dtype) == 2 ? 2 : 1; }
+
+struct Layout {
+  // sorted order and per-problem geometry
+  std::vector<int32_t> order;
+  std::vector<int64_t> nparts, gred, gt, ngroups;
+  // prefix sums over the sorted problems
+  std::vector<int64_t> tall_start, red_start, sk_start, col_start;
+  size_t head_bytes = 0, total = 0;
+  std::vector<size_t> off;  // per sorted problem: start of its region
+  size_t off_probs = 0, off_jobs = 0, off_tall = 0, off_red = 0, off_sk = 0, off_col = 0;
+};
+
+size_t problem_bytes(const rhqr_sketch_s *h, int dtype) {
+  const int32_t m = h->m, L = h->l + h->m;
+  int gt;
+  size_t skb;
+  sketch_tail_partials_size(h, m, &gt, &skb);
+  return align_up(loop_ws_bytes(h->kind, dtype, h->n, m, h->l)) +
+         align_up(sizeof(double) * (size_t)L * m) + align_up(skb);
+}
+
+int plan(const rhqr_problem *probs, int32_t count, int dtype, Layout *o) {
+  const int tpw = batch_tpw(dtype);
+  o->order.resize(count);
+  std::iota(o->order.begin(), o->order.end(), 0);
+  std::stable_sort(o->order.begin(), o->order.end(), [&](int a, int b) {
+    return probs[a].sketch->m > probs[b].sketch->m;
+  });
+  o->nparts.resize(count);
+  o->gred.resize(count);
+  o->gt.resize(count);
+  o->ngroups.resize(count);
+  o->tall_start.assign(count + 1, 0);
+  o->red_start.assign(count + 1, 0);
+  o->sk_start.assign(count + 1, 0);
+  o->col_start.assign(count + 1, 0);
+  for (int s = 0; s < count; ++s) {
+    const rhqr_sketch_s *h = probs[o->order[s]].sketch;
+    int gt;
+    size_t skb;
+    sketch_tail_partials_size(h, h->m, &gt, &skb);
+    o->nparts[s] = (h->n + (int64_t)TILE * tpw - 1) / ((int64_t)TILE * tpw);
+    o->gred[s] = (h->m + RED_CHUNK - 1) / RED_CHUNK + (h->l + RED_CHUNK - 1) / RED_CHUNK;
+    o->gt[s] = gt;
+    o->ngroups[s] = (h->n + (int64_t)TILE * SK_TPW - 1) / ((int64_t)TILE * SK_TPW);
+    o->tall_start[s + 1] = o->tall_start[s] + o->nparts[s];
+    o->red_start[s + 1] = o->red_start[s] + o->gred[s];
+    o->sk_start[s + 1] = o->sk_start[s] + (int64_t)h->m * gt;
+    o->col_start[s + 1] = o->col_start[s] + h->m;
+  }
+  if (o->tall_start[count] > INT32_MAX || o->sk_start[count] > INT32_MAX) return RHQR_ERR_UNSUPPORTED;
+  size_t b = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = b;
+    b += align_up(bytes);
+    return r;
+  };
+  o->off_probs = take(sizeof(ColProblem) * count);
+  o->off_jobs = take(sizeof(SketchJob) * count);
+  o->off_tall = take(sizeof(BlockMap) * o->tall_start[count]);
+  o->off_red = take(sizeof(BlockMap) * o->red_start[count]);
+  o->off_sk = take(sizeof(BlockMap) * o->sk_start[count]);
+  o->off_col = take(sizeof(BlockMap) * o->col_start[count]);
+  o->head_bytes = b;
+  o->off.resize(count);
+  for (int s = 0; s < count; ++s) o->off[s] = take(problem_bytes(probs[o->order[s]].sketch, dtype));
+  o->total = b;
+  return RHQR_OK;
+}
+
+int check_problems(const rhqr_problem *probs, int32_t count, int dtype) {
+  if (!probs || count < 1) return -1;
+  if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -3;
+  for (int32_t i = 0; i < count; ++i) {
+    const rhqr_problem &q = probs[i];
+    const rhqr_sketch_s *h = q.sketch;
+    if (!h || h->kind != RHQR_SKETCH_SRHT) return -1;
+    if (h->m > MAXM || h->l > 4096) return -1;
+    if (!q.d_W || q.ldw < h->n) return -1;
+    if (!q.d_S || q.lds < h->l + h->m) return -1;
+    if (!q.d_T || q.ldt < h->m) return -1;
+    if (!q.d_R || q.ldr < h->m) return -1;
+  }
+  return RHQR_OK;
+}
+
+}  // namespace
+
+struct rhqr_batch_s {
+  int dtype = 0, count = 0, maxm = 0, tpw = 1, qa = 1, maxL = 0;
+  std::vector<int32_t> order;     // sorted position -> caller index
+  std::vector<int32_t> ms;        // m of each sorted problem (decreasing)
+  std::vector<int64_t> tall_start, red_start;
+  int64_t sk_blocks = 0, cols = 0;
+  std::vector<ColProblem> hp;     // host copy of the descriptors (sorted)
+  ColProblem *d_probs = nullptr;
+  SketchJob *d_jobs = nullptr;
+  BlockMap *d_tall = nullptr, *d_red = nullptr, *d_sk = nullptr, *d_col = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// active problems at column j: m_p > j (a prefix of the sorted order)
+int active(const rhqr_batch_s *b, int32_t j) {
+  return (int)(std::partition_point(b->ms.begin(), b->ms.end(), [j](int32_t m) { return m > j; }) -
+               b->ms.begin());
+}
+
+template <typename ST>
+int enqueue_typed(rhqr_batch_s *b, hipStream_t st) {
+  using AT = typename CompT<ST>::type;
+  hipLaunchKernelGGL(kb_init, dim3(b->count), dim3(256), 0, st, b->d_probs);
+  RHQR_HIP(hipGetLastError());
+  switch (b->qa) {
+    case 1:
+      hipLaunchKernelGGL((kb_srht_cols<ST, AT, 1>), dim3(b->sk_blocks), dim3(SK_TPB), 0, st, b->d_jobs, b->d_sk);
+      break;
+    case 2:
+      hipLaunchKernelGGL((kb_srht_cols<ST, AT, 2>), dim3(b->sk_blocks), dim3(SK_TPB), 0, st, b->d_jobs, b->d_sk);
+      break;
+    default:
+      hipLaunchKernelGGL((kb_srht_cols<ST, AT, 4>), dim3(b->sk_blocks), dim3(SK_TPB), 0, st, b->d_jobs, b->d_sk);
+  }
+  RHQR_HIP(hipGetLastError());
+  hipLaunchKernelGGL((kb_sketch_finish<ST>), dim3(b->cols, (b->maxL + 255) / 256), dim3(256), 0, st,
+                     b->d_jobs, b->d_col);
+  RHQR_HIP(hipGetLastError());
+  for (int32_t j = 0; j < b->maxm; ++j) {
+    const int a = active(b, j);
+    if (j >= 1) {
+      constexpr int TPW = sizeof(ST) == 2 ? 2 : 1;  // = batch_tpw(dtype)
+      hipLaunchKernelGGL((kb_tall<ST, TPW>), dim3(b->tall_start[a]), dim3(TALL_TPB), 0, st,
+                         b->d_probs, b->d_tall, j);
+      RHQR_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL((kb_red<ST>), dim3(b->red_start[a]), dim3(1024), 0, st, b->d_probs, b->d_red, j);
+    RHQR_HIP(hipGetLastError());
+    const int fg = fin_groups(j);
+    hipLaunchKernelGGL(kb_fin, dim3(a * fg), dim3(1024), 0, st, b->d_probs, j, fg);
+    RHQR_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL((kb_finish<ST>), dim3(b->count, FINISH_CH), dim3(256), 0, st, b->d_probs);
+  RHQR_HIP(hipGetLastError());
+  return RHQR_OK;
+}
+
+int enqueue(rhqr_batch_s *b, hipStream_t st) {
+  switch (b->dtype) {
+    case RHQR_F64: return enqueue_typed<double>(b, st);
+    case RHQR_F32: return enqueue_typed<float>(b, st);
+    case RHQR_F16: return enqueue_typed<__half>(b, st);
+    case RHQR_BF16: return enqueue_typed<__hip_bfloat16>(b, st);
+  }
+  return RHQR_ERR_UNSUPPORTED;
+}
+
+}  // namespace
+
+extern "C" size_t rhqr_batch_workspace_size(const rhqr_problem *probs, int32_t count, int dtype) {
+  if (check_problems(probs, count, dtype)) return 0;
+  Layout L;
+  if (plan(probs, count, dtype, &L)) return 0;
+  return L.total;
+}
+
+extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int dtype, int opts,
+                                 void *d_ws, size_t ws_bytes, void *stream, rhqr_batch_t *out) {
+  int rc = check_problems(probs, count, dtype);
+  if (rc) return rc;
+  const int scaling = opts & 0xff;
+  if ((scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) || (opts >> 8) != 0)
+    return -4;
+  if (!d_ws) return -5;
+  if (!out) return -8;
+  Layout L;
+  rc = plan(probs, count, dtype, &L);
+  if (rc) return rc;
+  if (ws_bytes < L.total) return RHQR_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  char *ws = (char *)d_ws;
+  const int tpw = batch_tpw(dtype);
+  const size_t es = dtype_size(dtype);
+
+  rhqr_batch_s *b = new rhqr_batch_s();
+  b->dtype = dtype;
+  b->count = count;
+  b->tpw = tpw;
+  b->order = L.order;
+  b->tall_start = L.tall_start;
+  b->red_start = L.red_start;
+  b->sk_blocks = L.sk_start[count];
+  b->cols = L.col_start[count];
+  std::vector<SketchJob> jobs(count);
+  std::vector<BlockMap> tall_map(L.tall_start[count]), red_map(L.red_start[count]),
+      sk_map(L.sk_start[count]), col_map(L.col_start[count]);
+  b->hp.resize(count);
+  for (int s = 0; s < count; ++s) {
+    const rhqr_problem &q = probs[L.order[s]];
+    const rhqr_sketch_s *h = q.sketch;
+    const int32_t m = h->m, Lr = h->l + h->m;
+    b->ms.push_back(m);
+    b->maxm = std::max(b->maxm, m);
+    b->maxL = std::max(b->maxL, Lr);
+    b->qa = std::max(b->qa, h->l <= 1024 ? 1 : h->l <= 2048 ? 2 : 4);
+    char *region = ws + L.off[s];
+    const size_t lb = loop_ws_bytes(h->kind, dtype, h->n, m, h->l);
+    LoopWs lw;
+    rc = loop_ws_carve(region, lb, h->kind, dtype, h->n, m, h->l, &lw);
+    if (rc) {
+      delete b;
+      return rc;
+    }
+    double *Z = (double *)(region + align_up(lb));
+    double *skpart = (double *)(region + align_up(lb) + align_up(sizeof(double) * (size_t)Lr * m));
+    LoopArgs a;
+    a.kind = h->kind;
+    a.dtype = dtype;
+    a.n = h->n;
+    a.m = m;
+    a.l = h->l;
+    a.W = q.d_W;
+    a.ldw = q.ldw;
+    a.Z = Z;
+    a.ldz = Lr;
+    a.S = q.d_S;
+    a.lds = q.lds;
+    a.T = q.d_T;
+    a.ldt = q.ldt;
+    a.R = q.d_R;
+    a.ldr = q.ldr;
+    a.scaling = scaling;
+    a.signs = h->d_signs;
+    a.rows = h->d_rows;
+    a.omega = nullptr;
+    a.defer = 1;
+    b->hp[s] = make_col_problem(a, lw, tpw);
+    SketchJob &jb = jobs[s];
+    jb.X = q.d_W;
+    jb.ldx = q.ldw;
+    jb.n = h->n;
+    jb.m = m;
+    jb.l = h->l;
+    jb.ngroups = L.ngroups[s];
+    jb.gt = (int32_t)L.gt[s];
+    jb.aligned = ((uintptr_t)q.d_W % 16 == 0) && ((q.ldw * (int64_t)es) % 16 == 0);
+    jb.signs = h->d_signs;
+    jb.rows = h->d_rows;
+    jb.part = skpart;
+    jb.Z = Z;
+    jb.ldz = Lr;
+    jb.scale = 1.0 / std::sqrt((double)h->l);
+    for (int64_t k = 0; k < L.nparts[s]; ++k) tall_map[L.tall_start[s] + k] = {s, (int32_t)k};
+    for (int64_t k = 0; k < L.gred[s]; ++k) red_map[L.red_start[s] + k] = {s, (int32_t)k};
+    for (int64_t k = 0; k < (int64_t)m * L.gt[s]; ++k) sk_map[L.sk_start[s] + k] = {s, (int32_t)k};
+    for (int32_t k = 0; k < m; ++k) col_map[L.col_start[s] + k] = {s, k};
+  }
+  b->d_probs = (ColProblem *)(ws + L.off_probs);
+  b->d_jobs = (SketchJob *)(ws + L.off_jobs);
+  b->d_tall = (BlockMap *)(ws + L.off_tall);
+  b->d_red = (BlockMap *)(ws + L.off_red);
+  b->d_sk = (BlockMap *)(ws + L.off_sk);
+  b->d_col = (BlockMap *)(ws + L.off_col);
+  auto up = [&](void *dst, const void *src, size_t bytes) -> int {
+    if (bytes == 0) return RHQR_OK;
+    RHQR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    return RHQR_OK;
+  };
+  rc = up(b->d_probs, b->hp.data(), sizeof(ColProblem) * count);
+  if (!rc) rc = up(b->d_jobs, jobs.data(), sizeof(SketchJob) * count);
+  if (!rc) rc = up(b->d_tall, tall_map.data(), sizeof(BlockMap) * tall_map.size());
+  if (!rc) rc = up(b->d_red, red_map.data(), sizeof(BlockMap) * red_map.size());
+  if (!rc) rc = up(b->d_sk, sk_map.data(), sizeof(BlockMap) * sk_map.size());
+  if (!rc) rc = up(b->d_col, col_map.data(), sizeof(BlockMap) * col_map.size());
+  if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = RHQR_ERR_HIP;
+  if (!rc && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) rc = RHQR_ERR_HIP;
+  if (rc) {
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return RHQR_OK;
+}
+
+extern "C" int rhqr_batch_factor(rhqr_batch_t b, int use_graph, void *stream) {
+  if (!b) return -1;
+  hipStream_t st = (hipStream_t)stream;
+  if (!use_graph) return enqueue(b, st);
+  if (!b->exec) {
+    RHQR_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue(b, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->cap, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    RHQR_HIP(ec);
+    b->graph = g;
+    RHQR_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  RHQR_HIP(hipGraphLaunch(b->exec, st));
+  return RHQR_OK;
+}
+
+extern "C" int rhqr_batch_status(rhqr_batch_t b, void *stream, int32_t *h_info) {
+  if (!b) return -1;
+  if (!h_info) return -3;
+  hipStream_t st = (hipStream_t)stream;
+  for (int s = 0; s < b->count; ++s)
+    RHQR_HIP(hipMemcpyAsync(h_info + b->order[s], b->hp[s].status, sizeof(int32_t),
+                            hipMemcpyDeviceToHost, st));
+  RHQR_HIP(hipStreamSynchronize(st));
+  return RHQR_OK;
+}
+
+extern "C" int rhqr_batch_destroy(rhqr_batch_t b) {
+  if (!b) return -1;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+  return RHQR_OK;
+}

@@ -46,6 +46,37 @@ struct LoopArgs {
   int defer;          // the step of column j-1 left c_{j-1} to be finished by column j
 };
 
+// Everything the per-column kernels read about one problem: its data, its
+// sketch and its slice of the loop workspace.  Passed by value to the
+// single-problem kernels; the batched kernels read an array of them from
+// device memory.
+struct ColProblem {
+  void *W;
+  int64_t ldw, n;
+  int32_t m, l;
+  const double *Z;
+  int64_t ldz;
+  double *S;
+  int64_t lds;
+  double *T;
+  int64_t ldt;
+  double *R;
+  int64_t ldr;
+  const uint64_t *signs;
+  const int32_t *rows;
+  const double *omega;
+  double scale;        // l^-1/2 for the SRHT tile partials, 1 otherwise
+  int64_t nparts;      // tall workgroups (= partial sketches per column)
+  int32_t gred;        // reduction workgroups
+  int32_t scaling, defer, aligned;
+  double *part, *y, *sq, *dpart, *epart, *ypart, *scal, *c, *cf, *ia, *Tt, *dcpart, *fs;
+  float *wstage;
+  int32_t *status;
+};
+
+// descriptor of (a, w) for tall workgroups of tpw transform tiles
+ColProblem make_col_problem(const LoopArgs &a, const LoopWs &w, int tpw);
+
 size_t loop_ws_bytes(int kind, int dtype, int64_t n, int32_t m, int32_t l);
 int loop_ws_carve(void *ws, size_t bytes, int kind, int dtype, int64_t n, int32_t m, int32_t l,
                   LoopWs *out);

@@ -16,7 +16,7 @@
 // otherwise.  The raw refreshed column is kept in float64 in place (ST=double)
 // or in a float32 staging vector (low precision) until alpha_j is known, and
 // the division by alpha_j is folded into the next pass's coefficient.
-#include "engine.h"
+#include "colstep.h"
 
 #include <algorithm>
 #include <cmath>
@@ -25,8 +25,6 @@
 
 namespace {
 
-constexpr int MAXM = 1024;  // largest m the sketch-space kernels support
-constexpr int TALL_TPB = 1024;  // threads per tall workgroup
 
 // Optional timing of the tall kernels with HIP events recorded on the
 // launching stream (rhqr_profile_begin / rhqr_profile_end): class 0 = the
@@ -55,650 +53,19 @@ int prof_pair(hipEvent_t *a, hipEvent_t *b, int cls) {
   return RHQR_OK;
 }
 
-// workgroups of the float64 step of column j (FIN_P values of p each)
-constexpr int FIN_P = 16;
-inline int fin_groups(int32_t j) { return j > 0 ? (j + FIN_P - 1) / FIN_P : 1; }
-
-// ------------------------------------------------------ deferred c_{j-1}
-// The last coefficient of c_j = T_{j-1}^t S_{j-1}^t z_j is
-//     c_{j-1} = beta_{j-1} (e_{j-1} - sum_{p < j-1} d_p c_p)
-// (d = S^t s_{j-1}, e = S^t z_j).  The step of column j-1 leaves beta and e_{j-1}
-// in fs[0..1] and per-workgroup partial sums of d_p c_p in dcpart[0..gfin); the
-// consumers (the next reduction and tall pass) finish it themselves, so the
-// step needs no cross-workgroup hand-off.  Called by whole waves; fixed order.
-__device__ __forceinline__ double deferred_c(const double *__restrict__ fs,
-                                             const double *__restrict__ dcpart, int gfin) {
-  const int lane = threadIdx.x & 63;
-  double v = 0.0;
-  for (int g = lane; g < gfin; g += 64) v += dcpart[g];
-  v = wave_sum(v);
-  return fs[0] * (fs[1] - v);
-}
-
-// ------------------------------------------------------------------ k_tall
-// One workgroup per TILE rows; thread t owns rows base + VEC*(t + 256 v) + e.
-// FAST: every 16-byte vector of the tile is in bounds and aligned; head rows
-// (i < m) are loaded with the vector but excluded from the update by value, so
-// they keep their input values (head rows of W are refreshed in float64 from
-// U_1 = S_{1:m} by the reduction kernel).  !FAST: guarded element accesses
-// (ragged last tile or unaligned storage).
-template <typename ST, bool FAST, int NV>
-__device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
-                                          int32_t j, int32_t p0, bool prev,
-                                          const double *__restrict__ cf, double cprev,
-                                          double iaprev, float *__restrict__ wstage,
-                                          int64_t base,
-                                          typename CompT<ST>::type (&acc)[NV][16 / sizeof(ST)]) {
-  using CT = typename CompT<ST>::type;
-  constexpr int VEC = 16 / sizeof(ST);
-  constexpr bool LOWP = !std::is_same<ST, double>::value;
-  const int tid = threadIdx.x;
-  auto row = [&](int v) { return base + (int64_t)VEC * (tid + TALL_TPB * v); };
-  auto ok = [&](int64_t i) { return i >= m && i < n; };
-  const bool head = base < m;  // uniform: the tile holds head rows
-
-  uint32_t off[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) off[v] = (uint32_t)((row(v) - base) * (int64_t)sizeof(ST));
-
-  // acc <- w_j
-  const ST *wj = W + (int64_t)j * ldw;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const int64_t i0 = row(v);
-    if (FAST) {
-      vload(wj + i0, acc[v]);
-    } else {
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) acc[v][e] = ok(i0 + e) ? cvt_in<CT>(wj[i0 + e]) : (CT)0;
-    }
-  }
-  // acc -= U_{:, <j-1} c  (stored columns, already scaled)
-  if (FAST) {
-    if (!head) {
-      // UF columns per step so that UF * NV 16-byte loads are in flight
-      constexpr int UF = NV >= 8 ? 1 : 8 / NV;
-      int p = p0;
-      if constexpr (UF > 1) {
-#pragma unroll 1
-        for (; p + UF <= j - 1; p += UF) {
-          u32x4 raw[UF][NV];
-#pragma unroll
-          for (int u = 0; u < UF; ++u) {
-            const char *cb = (const char *)(W + (int64_t)(p + u) * ldw + base);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) raw[u][v] = vraw_nt(cb + off[v]);
-          }
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int u = 0; u < UF; ++u) {
-            const CT cp = (CT)cf[p + u];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-              CT x[VEC];
-              vdecode<ST, CT>(raw[u][v], x);
-#pragma unroll
-              for (int e = 0; e < VEC; ++e) acc[v][e] -= x[e] * cp;
-            }
-          }
-        }
-      }
-#pragma unroll 1
-      for (; p < j - 1; ++p) {
-        const CT cp = (CT)cf[p];
-        const char *cb = (const char *)(W + (int64_t)p * ldw + base);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          CT x[VEC];
-          vload<ST, CT, true>((const ST *)(cb + off[v]), x);
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) acc[v][e] -= x[e] * cp;
-        }
-      }
-    } else {
-#pragma unroll 1
-      for (int p = p0; p < j - 1; ++p) {
-        const CT cp = (CT)cf[p];
-        const char *cb = (const char *)(W + (int64_t)p * ldw + base);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const int64_t i0 = row(v);
-          CT x[VEC];
-          vload<ST, CT, true>((const ST *)(cb + off[v]), x);
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) acc[v][e] -= (i0 + e >= m) ? x[e] * cp : (CT)0;
-        }
-      }
-    }
-  } else {
-#pragma unroll 1
-    for (int p = p0; p < j - 1; ++p) {
-      const CT cp = (CT)cf[p];
-      const ST *col = W + (int64_t)p * ldw;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int64_t i0 = row(v);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          if (ok(i0 + e)) acc[v][e] -= cvt_in<CT>(col[i0 + e]) * cp;
-      }
-    }
-  }
-  // previous column: raw refreshed values, used, then stored scaled by
-  // 1/alpha_{j-1}.  Column 0 is never refreshed: its raw values are the input.
-  // (prev == false: column j-1 was already stored scaled and applied by the
-  // panel update of the blocked schedule.)
-  if (j >= 1 && prev) {
-    const CT cp = (CT)cprev;
-    const CT ia = (CT)iaprev;
-    ST *col = W + (int64_t)(j - 1) * ldw;
-    const bool from_stage = LOWP && j >= 2;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int64_t i0 = row(v);
-      CT x[VEC], o[VEC];
-      if (FAST) {
-        if (from_stage) {
-          const float4 *ws4 = reinterpret_cast<const float4 *>(wstage + i0);
-#pragma unroll
-          for (int h = 0; h < VEC / 4; ++h) {
-            const float4 f = ws4[h];
-            x[4 * h] = f.x;
-            x[4 * h + 1] = f.y;
-            x[4 * h + 2] = f.z;
-            x[4 * h + 3] = f.w;
-          }
-        } else {
-          vload(col + i0, x);
-        }
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-          if (i0 + e >= m) acc[v][e] -= x[e] * cp;
-          o[e] = x[e] * ia;
-        }
-        vstore(col + i0, o);  // head rows are rewritten from S at the end
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-          if (ok(i0 + e)) {
-            x[e] = from_stage ? (CT)wstage[i0 + e] : cvt_in<CT>(col[i0 + e]);
-            acc[v][e] -= x[e] * cp;
-            col[i0 + e] = cvt_out<ST>((double)(x[e] * ia));
-          }
-        }
-      }
-    }
-  }
-  // store the raw refreshed column (float64: in place; otherwise: staging)
-  ST *wjw = W + (int64_t)j * ldw;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const int64_t i0 = row(v);
-    if (LOWP) {
-      if (FAST) {
-        float4 *ws4 = reinterpret_cast<float4 *>(wstage + i0);
-#pragma unroll
-        for (int h = 0; h < VEC / 4; ++h)
-          ws4[h] = make_float4((float)acc[v][4 * h], (float)acc[v][4 * h + 1],
-                               (float)acc[v][4 * h + 2], (float)acc[v][4 * h + 3]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          if (ok(i0 + e)) wstage[i0 + e] = (float)acc[v][e];
-      }
-    } else {
-      if (FAST) {
-        vstore(wjw + i0, acc[v]);  // head rows hold their unchanged input values
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          if (ok(i0 + e)) wjw[i0 + e] = cvt_out<ST>((double)acc[v][e]);
-      }
-    }
-  }
-}
-
-// A tall workgroup covers TPW consecutive transform tiles (TPW * TILE rows),
-// so the per-column partials shrink by TPW.
-
-template <typename A, int TPW> __device__ void fwht_tiles_lds(A *s) {
-#pragma unroll 1
-  for (int pass = 0; pass < 3; ++pass) {
-    __syncthreads();
-    const int sh = 4 * pass;
-    for (int gg = threadIdx.x; gg < (TILE / 16) * TPW; gg += blockDim.x) {
-      A *st = s + (gg >> 8) * TILE_PAD;
-      const int g = gg & 255;
-      const int lo = g & ((1 << sh) - 1);
-      const int hi = g >> sh;
-      const int base = lo + (hi << (sh + 4));
-      A v[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = st[tpad(base + (k << sh))];
-      fwht16(v);
-#pragma unroll
-      for (int k = 0; k < 16; ++k) st[tpad(base + (k << sh))] = v[k];
-    }
-  }
-  __syncthreads();
-}
-
+// ----------------------------------------------------- single-problem kernels
 template <typename ST, int KIND, int TPW>
-__global__ void __launch_bounds__(TALL_TPB) k_tall(ST *__restrict__ W, int64_t ldw, int64_t n,
-                                                   int32_t m, int32_t j, int32_t p0,
-                                                   const double *__restrict__ cf,
-                                                   const double *__restrict__ ia,
-                                                   float *__restrict__ wstage,
-                                                   double *__restrict__ part,
-                                                   const uint64_t *__restrict__ signs,
-                                                   const int32_t *__restrict__ rows, int32_t l,
-                                                   const double *__restrict__ om, int aligned,
-                                                   int defer, int gfin,
-                                                   const double *__restrict__ fs,
-                                                   const double *__restrict__ dcpart) {
-  using CT = typename CompT<ST>::type;
-  constexpr int VEC = 16 / sizeof(ST);
-  constexpr int ROWS = TILE * TPW;
-  constexpr int NV = ROWS / (TALL_TPB * VEC);
-  static_assert(NV >= 1, "tile too small for the vector width");
-  __shared__ CT s[TPW * TILE_PAD];
-  const int64_t base = (int64_t)blockIdx.x * ROWS;
-  const bool fast = aligned && base + ROWS <= n;
-  const bool prev = j - 1 >= p0;
-  // SRHT: the workgroup's sign words and the first sample row, loaded now and
-  // used after the streaming pass
-  constexpr int NSW = ROWS / 64;
-  __shared__ uint64_t sgn[KIND == RHQR_SKETCH_SRHT ? NSW : 1];
-  uint64_t sw = 0;
-  int32_t rq = 0;
-  if (KIND == RHQR_SKETCH_SRHT) {
-    const int64_t wi = base / 64 + threadIdx.x;
-    if (threadIdx.x < NSW && wi * 64 < n) sw = signs[wi];
-    if ((int)threadIdx.x < l) rq = rows[threadIdx.x];
-  }
-  // coefficient of the raw previous column: c_{j-1} / alpha_{j-1}
-  double iaprev = 0.0, cprev = 0.0;
-  if (j >= 1 && prev) {
-    iaprev = ia[j - 1];
-    cprev = defer ? deferred_c(fs, dcpart, gfin) * iaprev : cf[j - 1];
-  }
-  CT acc[NV][VEC];
-  if (fast)
-    tall_body<ST, true, NV>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, wstage, base, acc);
-  else
-    tall_body<ST, false, NV>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, wstage, base, acc);
-
-  if (KIND == RHQR_SKETCH_IDENT) return;
-  const int tid = threadIdx.x;
-  if (KIND == RHQR_SKETCH_SRHT) {
-    if (tid < NSW) sgn[tid] = sw;
-    lds_barrier();
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int li0 = VEC * (tid + TALL_TPB * v);
-      const int64_t i0 = base + li0;
-      const uint64_t word = sgn[li0 >> 6];
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const int64_t i = i0 + e;
-        CT x = (i >= m && i < n) ? acc[v][e] : (CT)0;
-        if ((word >> (i & 63)) & 1ull) x = -x;
-        const int li = li0 + e;
-        s[(li >> TILE_LOG) * TILE_PAD + tpad(li & (TILE - 1))] = x;
-      }
-    }
-    fwht_tiles_lds<CT, TPW>(s);
-    const uint64_t t0 = (uint64_t)blockIdx.x * TPW;
-    for (int q = tid; q < l; q += TALL_TPB) {
-      const int32_t r = q == tid ? rq : rows[q];
-      const int r2 = tpad(r & (TILE - 1));
-      const uint64_t r1 = (uint64_t)(r >> TILE_LOG);
-      double h = 0.0;
-#pragma unroll
-      for (int tt = 0; tt < TPW; ++tt) {
-        const double x = (double)s[tt * TILE_PAD + r2];
-        h += (__popcll(r1 & (t0 + tt)) & 1) ? -x : x;
-      }
-      part[(int64_t)blockIdx.x * l + q] = h;
-    }
-  } else {  // Gaussian: partial Omega[:, rows] w~_rows, four row groups per sample
-    __shared__ double red[KIND == RHQR_SKETCH_GAUSS ? 1024 : 1];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int li0 = VEC * (tid + TALL_TPB * v);
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const int64_t i = base + li0 + e;
-        s[li0 + e] = (i >= m && i < n) ? acc[v][e] : (CT)0;
-      }
-    }
-    const int64_t lo = base > m ? base : (int64_t)m;
-    const int64_t hi = base + ROWS < n ? base + ROWS : n;
-    const int g = tid >> 8;
-    for (int q0 = 0; q0 < l; q0 += 256) {
-      __syncthreads();
-      const int q = q0 + (tid & 255);
-      double a0 = 0, a1 = 0;
-      if (q < l) {
-        int64_t i = lo + g;
-        for (; i + 4 < hi; i += 8) {
-          a0 += om[(i - m) * l + q] * (double)s[i - base];
-          a1 += om[(i + 4 - m) * l + q] * (double)s[i + 4 - base];
-        }
-        for (; i < hi; i += 4) a0 += om[(i - m) * l + q] * (double)s[i - base];
-      }
-      red[g * 256 + (tid & 255)] = a0 + a1;
-      __syncthreads();
-      if (g == 0 && q < l)
-        part[(int64_t)blockIdx.x * l + q] =
-            (red[tid] + red[256 + tid]) + (red[512 + tid] + red[768 + tid]);
-    }
-  }
+__global__ void __launch_bounds__(TALL_TPB) k_tall(const ColProblem P, int32_t j, int32_t p0) {
+  tall_block<ST, KIND, TPW>(P, j, p0, blockIdx.x);
 }
-
-// ------------------------------------------------------------------- k_red
-// One workgroup per RED_CHUNK rows of the (l+m) sketch space (head chunks
-// first).  Forms y = Psi w~_j on its rows: head rows y_k = w_{k,j} - sum_{p<j}
-// S_{k,p} c_p (float64), tail rows the sum of the per-workgroup sketch
-// partials (SRHT scaled by l^-1/2), or the refreshed rows themselves for
-// Psi = I.  Then, on its rows, the partial sums that RHVector and the T/c
-// updates need, with y masked to rows k >= j (no cancellation against the
-// already-eliminated entries):
-//   sq     = sum y_k^2                       (rho^2)
-//   dpart_p = sum S_{k,p} y_k      (p < j)   (S^t s_j up to the pivot term)
-//   epart_p = sum S_{k,p} z_k      (p < j)   (S^t z_{j+1}, z the next pre-sketch)
-//   ypart   = sum y_k z_k                    (s_j^t z_{j+1} up to the pivot term)
-// Every load that does not depend on y (the S entries of the dot products, z,
-// the partials) is issued before the first wait.
-constexpr int RED_NP = 16;  // per-lane loads issued together
 
 template <typename ST, int KIND>
-__global__ void __launch_bounds__(1024) k_red(const ST *__restrict__ W, int64_t ldw, int32_t m,
-                                              int32_t l, int32_t j, int next,
-                                              const double *__restrict__ Z, int64_t ldz,
-                                              const double *__restrict__ S, int64_t lds,
-                                              const double *__restrict__ c, int defer, int gfin,
-                                              const double *__restrict__ fs,
-                                              const double *__restrict__ dcpart,
-                                              const double *__restrict__ part, int64_t nparts,
-                                              double scale, double *__restrict__ y,
-                                              double *__restrict__ sq, double *__restrict__ dpart,
-                                              double *__restrict__ epart, double *__restrict__ ypart) {
-  __shared__ double red[16][RED_CHUNK + 1];
-  __shared__ double yl[RED_CHUNK];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int nhb = (m + RED_CHUNK - 1) / RED_CHUNK;
-  const bool head = (int)blockIdx.x < nhb;
-  const int k = head ? (int)blockIdx.x * RED_CHUNK + lane : m + ((int)blockIdx.x - nhb) * RED_CHUNK + lane;
-  const bool valid = head ? (k < m) : (k < m + l);
-  // S entries of the first RED_NP dot products of this wave, and z
-  double sp[RED_NP];
-#pragma unroll
-  for (int b = 0; b < RED_NP; ++b) {
-    const int p = w + 16 * b;
-    sp[b] = (valid && p < j) ? S[k + (int64_t)p * lds] : 0.0;
-  }
-  const double z = (next && valid) ? Z[k + (int64_t)(j + 1) * ldz] : 0.0;
-  double v = 0.0;
-  if (j >= 1) {
-    if (head) {
-      const double clast = defer ? deferred_c(fs, dcpart, gfin) : 0.0;
-      const int pe = valid ? min(j, k + 1) : 0;
-      for (int p0 = w; p0 < pe; p0 += 16 * RED_NP) {
-        double t[RED_NP];
-#pragma unroll
-        for (int b = 0; b < RED_NP; ++b) {
-          const int p = p0 + 16 * b;
-          t[b] = 0.0;
-          if (p < pe) {
-            const double cp = (defer && p == j - 1) ? clast : c[p];
-            t[b] = S[k + (int64_t)p * lds] * cp;
-          }
-        }
-#pragma unroll
-        for (int b = 0; b < RED_NP; ++b) v += t[b];
-      }
-    } else if (KIND != RHQR_SKETCH_IDENT && valid) {
-      const double *pq = part + (k - m);
-      for (int64_t t0 = w; t0 < nparts; t0 += 16 * RED_NP) {
-        double t[RED_NP];
-#pragma unroll
-        for (int b = 0; b < RED_NP; ++b) {
-          const int64_t tt = t0 + 16 * b;
-          t[b] = tt < nparts ? pq[tt * l] : 0.0;
-        }
-#pragma unroll
-        for (int b = 0; b < RED_NP; ++b) v += t[b];
-      }
-    }
-  }
-  red[w][lane] = v;
-  __syncthreads();
-  if (w == 0) {
-    double s = 0.0;
-    for (int i = 0; i < 16; ++i) s += red[i][lane];
-    double out = 0.0;
-    if (valid) {
-      if (j == 0)
-        out = Z[k];  // column 0 of the pre-sketch
-      else if (head)
-        out = cvt_in<double>(W[k + (int64_t)j * ldw]) - s;
-      else if (KIND == RHQR_SKETCH_IDENT)
-        out = cvt_in<double>(W[k + (int64_t)j * ldw]);
-      else
-        out = s * scale;
-      y[k] = out;
-    }
-    const double ym = (valid && k >= j) ? out : 0.0;
-    yl[lane] = ym;
-    const double tot = wave_sum(ym * ym);
-    const double yz = next ? wave_sum(ym * z) : 0.0;
-    if (lane == 0) {
-      sq[blockIdx.x] = tot;
-      if (next) ypart[blockIdx.x] = yz;
-    }
-  }
-  __syncthreads();
-  const double ym = yl[lane];
-  // partial dot products with the earlier columns of S, one wave per p
-  for (int p0 = w; p0 < j; p0 += 16 * RED_NP) {
-    if (p0 > w) {  // columns beyond the prefetched ones (j > 16 RED_NP)
-#pragma unroll
-      for (int b = 0; b < RED_NP; ++b) {
-        const int p = p0 + 16 * b;
-        sp[b] = (valid && p < j) ? S[k + (int64_t)p * lds] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < RED_NP; ++b) {
-      const int p = p0 + 16 * b;
-      if (p < j) {  // uniform across the wave
-        const double dv = wave_sum(sp[b] * ym);
-        const double ev = next ? wave_sum(sp[b] * z) : 0.0;
-        if (lane == 0) {
-          dpart[(int64_t)blockIdx.x * m + p] = dv;
-          if (next) epart[(int64_t)blockIdx.x * m + p] = ev;
-        }
-      }
-    }
-  }
+__global__ void __launch_bounds__(1024) k_red(const ColProblem P, int32_t j, int next) {
+  red_block<ST, KIND>(P, j, next, blockIdx.x);
 }
 
-// -------------------------------------------------------------------- scalars
-struct StepScalars {
-  double sigma, rho, alpha, beta, gamma;
-  int ident;
-};
-
-// ss: the sum of the partial sums of squares (rho^2)
-__device__ __forceinline__ StepScalars step_scalars(const double *y, double ss, int32_t j,
-                                                    int scaling) {
-  StepScalars r;
-  r.rho = sqrt(ss);
-  const double yj = y[j];
-  r.sigma = yj >= 0.0 ? 1.0 : -1.0;
-  r.ident = !(r.rho > 0.0);
-  if (r.ident) {
-    r.gamma = 0.0;
-    r.alpha = 1.0;
-    r.beta = 0.0;
-  } else {
-    r.gamma = yj + r.sigma * r.rho;
-    if (scaling == RHQR_SCALE_UNIT_PIVOT) {
-      r.alpha = r.gamma;
-      r.beta = fabs(r.gamma) / r.rho;
-    } else {
-      r.alpha = sqrt(r.rho * fabs(r.gamma));
-      r.beta = 1.0;
-    }
-  }
-  return r;
-}
-
-// ------------------------------------------------------------------- k_fin
-// RHVector (Alg. 2) and the T / c updates of Alg. 4 for column j, float64:
-//   scalars sigma, rho, gamma, alpha, beta from the partial sums of squares;
-//   s_j = ((0; y_{j:}) + sigma rho e_j) / alpha  -> S_{:, j};  R_{:, j};
-//   d = S^t s_j,  e = S^t z_{j+1}  (from the k_red partials plus the pivot term);
-//   T_{p,j} = -beta (T_{j-1} d)_p,  c_{j+1,p} = (T_{j-1}^t e)_p  for p < j,
-// one wave per p, FIN_P values of p per workgroup; T_{j,j} = beta.  The last
-// coefficient c_{j+1,j} is left to its consumers (deferred_c): workgroup g
-// writes sum_{p in g} d_p c_{j+1,p} to dcpart[g], workgroup 0 writes beta and
-// e_j to fs.  The partial sums, the rows of T and the pivot row of S are all
-// loaded before the first wait.
-constexpr int FIN_NQ = 4;  // T entries per lane loaded together
-
-__global__ void __launch_bounds__(1024) k_fin(int32_t m, int32_t l, int32_t j, int next,
-                                              int scaling, int gred,
-                                              const double *__restrict__ y,
-                                              const double *__restrict__ sq,
-                                              const double *__restrict__ dpart,
-                                              const double *__restrict__ epart,
-                                              const double *__restrict__ ypart,
-                                              const double *__restrict__ Z, int64_t ldz,
-                                              double *__restrict__ S, int64_t lds,
-                                              double *__restrict__ T, int64_t ldt,
-                                              double *__restrict__ Tt, double *__restrict__ R,
-                                              int64_t ldr, double *__restrict__ scal,
-                                              double *__restrict__ c, double *__restrict__ cf,
-                                              double *__restrict__ ia, int32_t *__restrict__ status,
-                                              double *__restrict__ dcpart, double *__restrict__ fs) {
-  __shared__ double d[MAXM], e[MAXM + 1];
-  __shared__ double wdc[16];
-  __shared__ StepScalars shs;
-  __shared__ double yzs;
-  const bool needc = next != 0;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int p = (int)blockIdx.x * FIN_P + w;  // this wave's index (p < j)
-  // ---- loads that need nothing computed here
-  // this wave's row of T (T_{p,q}, q in [p, j): from the transposed copy) and
-  // column of T (T_{q,p}, q <= p)
-  double tr[FIN_NQ], tc[FIN_NQ];
-  const bool pw = w < FIN_P && p < j;
-#pragma unroll
-  for (int i = 0; i < FIN_NQ; ++i) {
-    const int qr = p + lane + 64 * i, qc = lane + 64 * i;
-    tr[i] = (pw && qr < j) ? Tt[qr + (int64_t)p * m] : 0.0;
-    tc[i] = (pw && needc && qc <= p) ? T[qc + (int64_t)p * ldt] : 0.0;
-  }
-  // thread q: the partial dot products d_q, e_q and the pivot-row entry S_{j,q}
-  const int q = threadIdx.x;
-  double dv = 0.0, ev = 0.0, sjq = 0.0;
-  if (q < j) {
-    sjq = S[j + (int64_t)q * lds];
-    for (int g = 0; g < gred; ++g) {
-      dv += dpart[(int64_t)g * m + q];
-      if (needc) ev += epart[(int64_t)g * m + q];
-    }
-  }
-  if (w == 0) {
-    double ss = 0.0, yz = 0.0;
-    for (int g = lane; g < gred; g += 64) {
-      ss += sq[g];
-      if (needc) yz += ypart[g];
-    }
-    ss = wave_sum(ss);
-    yz = wave_sum(yz);
-    if (lane == 0) {
-      shs = step_scalars(y, ss, j, scaling);
-      yzs = yz;
-    }
-  }
-  __syncthreads();
-  const StepScalars sc = shs;
-  const double sr = sc.sigma * sc.rho;
-  if (q < j) {
-    d[q] = sc.ident ? sjq : (dv + sr * sjq) / sc.alpha;
-    e[q] = ev;
-  }
-  if (q == j && needc) {
-    const double zj = Z[j + (int64_t)(j + 1) * ldz];
-    e[j] = sc.ident ? zj : (yzs + sr * zj) / sc.alpha;
-  }
-  // s_j into S_{:, j} (grid-stride over the l+m rows)
-  const int L = l + m;
-  for (int k = (int)blockIdx.x * blockDim.x + threadIdx.x; k < L; k += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    if (k == j)
-      s = sc.ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : sc.gamma / sc.alpha);
-    else if (k > j)
-      s = sc.ident ? 0.0 : y[k] / sc.alpha;
-    S[k + (int64_t)j * lds] = s;
-  }
-  __syncthreads();
-  const double beta = sc.beta;
-  double dcw = 0.0;
-  if (pw) {
-    double td = 0.0, te = 0.0;
-#pragma unroll
-    for (int i = 0; i < FIN_NQ; ++i) {
-      const int qr = p + lane + 64 * i, qc = lane + 64 * i;
-      if (qr < j) td += tr[i] * d[qr];
-      if (needc && qc <= p) te += tc[i] * e[qc];
-    }
-    // rows beyond the prefetched ones (j > 64 FIN_NQ)
-    for (int qr = p + lane + 64 * FIN_NQ; qr < j; qr += 64) td += Tt[qr + (int64_t)p * m] * d[qr];
-    if (needc)
-      for (int qc = lane + 64 * FIN_NQ; qc <= p; qc += 64) te += T[qc + (int64_t)p * ldt] * e[qc];
-    td = wave_sum(td);
-    te = wave_sum(te);
-    dcw = d[p] * te;
-    if (lane == 0) {
-      const double t = -beta * td;
-      T[p + (int64_t)j * ldt] = t;
-      Tt[j + (int64_t)p * m] = t;
-      if (needc) {
-        c[p] = te;
-        cf[p] = te;
-      }
-    }
-  }
-  if (lane == 0 && w < 16) wdc[w] = dcw;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (needc) {
-      double s = 0.0;
-      for (int i = 0; i < 16; ++i) s += wdc[i];
-      dcpart[blockIdx.x] = s;
-    }
-    if (blockIdx.x == 0) {
-      T[j + (int64_t)j * ldt] = beta;
-      Tt[j + (int64_t)j * m] = beta;
-      ia[j] = sc.ident ? 0.0 : 1.0 / sc.alpha;
-      if (needc) {
-        fs[0] = beta;
-        fs[1] = e[j];
-      }
-      scal[4 * j + 0] = sc.sigma;
-      scal[4 * j + 1] = sc.rho;
-      scal[4 * j + 2] = sc.alpha;
-      scal[4 * j + 3] = sc.beta;
-      if (sc.ident) atomicCAS(status, 0, j + 1);
-    }
-  }
-  if (blockIdx.x == 0)
-    for (int r = threadIdx.x; r < m; r += blockDim.x)
-      R[r + (int64_t)j * ldr] = r < j ? y[r] : (r == j ? -sr : 0.0);
+__global__ void __launch_bounds__(1024) k_fin(const ColProblem P, int32_t j, int next) {
+  fin_block(P, j, next, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------ final stores
@@ -817,43 +184,37 @@ inline int tall_tpw(int64_t n, size_t elt) {
 }
 
 template <typename ST, int KIND, int TPW>
-void launch_tall(const LoopArgs &a, const LoopWs &w, int32_t j, int32_t p0, int aligned,
-                 hipStream_t st) {
+void launch_tall(const ColProblem &P, int32_t j, int32_t p0, hipStream_t st) {
   const int64_t rows = (int64_t)TILE * TPW;
-  const int64_t g = (a.n + rows - 1) / rows;
-  const int defer = a.defer && j >= 1;
-  const int gfin = fin_groups(j - 1);
-  hipLaunchKernelGGL((k_tall<ST, KIND, TPW>), dim3(g), dim3(TALL_TPB), 0, st, (ST *)a.W, a.ldw, a.n,
-                     a.m, j, p0, w.cf, w.ia, w.wstage, w.part, a.signs, a.rows, a.l, a.omega,
-                     aligned, defer, gfin, w.fs, w.dcpart);
+  const int64_t g = (P.n + rows - 1) / rows;
+  hipLaunchKernelGGL((k_tall<ST, KIND, TPW>), dim3(g), dim3(TALL_TPB), 0, st, P, j, p0);
 }
 
 template <typename ST, int KIND>
-void launch_tall_k(const LoopArgs &a, const LoopWs &w, int32_t j, int32_t p0, int aligned, int tpw,
-                   hipStream_t st) {
+void launch_tall_k(const ColProblem &P, int32_t j, int32_t p0, int tpw, hipStream_t st) {
   if constexpr (sizeof(ST) == 2) {
-    if (tpw == 4) launch_tall<ST, KIND, 4>(a, w, j, p0, aligned, st);
-    else launch_tall<ST, KIND, 2>(a, w, j, p0, aligned, st);
+    if (tpw == 4) launch_tall<ST, KIND, 4>(P, j, p0, st);
+    else launch_tall<ST, KIND, 2>(P, j, p0, st);
   } else {
-    if (tpw == 4) launch_tall<ST, KIND, 4>(a, w, j, p0, aligned, st);
-    else if (tpw == 2) launch_tall<ST, KIND, 2>(a, w, j, p0, aligned, st);
-    else launch_tall<ST, KIND, 1>(a, w, j, p0, aligned, st);
+    if (tpw == 4) launch_tall<ST, KIND, 4>(P, j, p0, st);
+    else if (tpw == 2) launch_tall<ST, KIND, 2>(P, j, p0, st);
+    else launch_tall<ST, KIND, 1>(P, j, p0, st);
   }
 }
 
 template <typename ST>
 int tall_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int32_t p0, hipStream_t st) {
   const int tpw = tall_tpw(a.n, sizeof(ST));
-  const int aligned = ((uintptr_t)a.W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
+  const ColProblem P = make_col_problem(a, w, tpw);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_prof.on) {
     if (prof_pair(&e0, &e1, 0)) return RHQR_ERR_HIP;
     RHQR_HIP(hipEventRecord(e0, st));
   }
   switch (a.kind) {
-    case RHQR_SKETCH_SRHT: launch_tall_k<ST, RHQR_SKETCH_SRHT>(a, w, j, p0, aligned, tpw, st); break;
-    case RHQR_SKETCH_GAUSS: launch_tall_k<ST, RHQR_SKETCH_GAUSS>(a, w, j, p0, aligned, tpw, st); break;
-    default: launch_tall_k<ST, RHQR_SKETCH_IDENT>(a, w, j, p0, aligned, tpw, st);
+    case RHQR_SKETCH_SRHT: launch_tall_k<ST, RHQR_SKETCH_SRHT>(P, j, p0, tpw, st); break;
+    case RHQR_SKETCH_GAUSS: launch_tall_k<ST, RHQR_SKETCH_GAUSS>(P, j, p0, tpw, st); break;
+    default: launch_tall_k<ST, RHQR_SKETCH_IDENT>(P, j, p0, tpw, st);
   }
   RHQR_HIP(hipGetLastError());
   if (g_prof.on) RHQR_HIP(hipEventRecord(e1, st));
@@ -862,27 +223,13 @@ int tall_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int32_t p0, hipStr
 
 template <typename ST>
 int step_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st) {
-  ST *W = (ST *)a.W;
-  const int64_t n = a.n;
-  const int32_t m = a.m, l = a.l;
-  const int tpw = tall_tpw(n, sizeof(ST));
-  const int64_t nparts = (n + (int64_t)TILE * tpw - 1) / ((int64_t)TILE * tpw);
-  const int gred = (m + RED_CHUNK - 1) / RED_CHUNK + (l + RED_CHUNK - 1) / RED_CHUNK;
-  const double scale = a.kind == RHQR_SKETCH_SRHT ? 1.0 / std::sqrt((double)l) : 1.0;
-  const int defer = a.defer && j >= 1;
-  const int gprev = fin_groups(j - 1);
+  const ColProblem P = make_col_problem(a, w, tall_tpw(a.n, sizeof(ST)));
   if (a.kind == RHQR_SKETCH_IDENT)
-    hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_IDENT>), dim3(gred), dim3(1024), 0, st, W, a.ldw, m,
-                       l, j, next, a.Z, a.ldz, a.S, a.lds, w.c, defer, gprev, w.fs, w.dcpart,
-                       w.part, nparts, scale, w.y, w.sq, w.dpart, w.epart, w.ypart);
+    hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_IDENT>), dim3(P.gred), dim3(1024), 0, st, P, j, next);
   else
-    hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_SRHT>), dim3(gred), dim3(1024), 0, st, W, a.ldw, m,
-                       l, j, next, a.Z, a.ldz, a.S, a.lds, w.c, defer, gprev, w.fs, w.dcpart,
-                       w.part, nparts, scale, w.y, w.sq, w.dpart, w.epart, w.ypart);
+    hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_SRHT>), dim3(P.gred), dim3(1024), 0, st, P, j, next);
   RHQR_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_fin, dim3(fin_groups(j)), dim3(1024), 0, st, m, l, j, next, a.scaling, gred,
-                     w.y, w.sq, w.dpart, w.epart, w.ypart, a.Z, a.ldz, a.S, a.lds, a.T, a.ldt,
-                     w.Tt, a.R, a.ldr, w.scal, w.c, w.cf, w.ia, w.status, w.dcpart, w.fs);
+  hipLaunchKernelGGL(k_fin, dim3(fin_groups(j)), dim3(1024), 0, st, P, j, next);
   RHQR_HIP(hipGetLastError());
   return RHQR_OK;
 }
@@ -1171,6 +518,49 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
 }
 
 }  // namespace
+
+ColProblem make_col_problem(const LoopArgs &a, const LoopWs &w, int tpw) {
+  ColProblem P;
+  const size_t es = dtype_size(a.dtype);
+  P.W = a.W;
+  P.ldw = a.ldw;
+  P.n = a.n;
+  P.m = a.m;
+  P.l = a.l;
+  P.Z = a.Z;
+  P.ldz = a.ldz;
+  P.S = a.S;
+  P.lds = a.lds;
+  P.T = a.T;
+  P.ldt = a.ldt;
+  P.R = a.R;
+  P.ldr = a.ldr;
+  P.signs = a.signs;
+  P.rows = a.rows;
+  P.omega = a.omega;
+  P.scale = a.kind == RHQR_SKETCH_SRHT ? 1.0 / std::sqrt((double)a.l) : 1.0;
+  P.nparts = (a.n + (int64_t)TILE * tpw - 1) / ((int64_t)TILE * tpw);
+  P.gred = (a.m + RED_CHUNK - 1) / RED_CHUNK + (a.l + RED_CHUNK - 1) / RED_CHUNK;
+  P.scaling = a.scaling;
+  P.defer = a.defer;
+  P.aligned = ((uintptr_t)a.W % 16 == 0) && ((a.ldw * (int64_t)es) % 16 == 0);
+  P.part = w.part;
+  P.y = w.y;
+  P.sq = w.sq;
+  P.dpart = w.dpart;
+  P.epart = w.epart;
+  P.ypart = w.ypart;
+  P.scal = w.scal;
+  P.c = w.c;
+  P.cf = w.cf;
+  P.ia = w.ia;
+  P.Tt = w.Tt;
+  P.dcpart = w.dcpart;
+  P.fs = w.fs;
+  P.wstage = w.wstage;
+  P.status = w.status;
+  return P;
+}
 
 int launch_fill(void *p, size_t bytes, hipStream_t st) {
   const size_t nw = bytes / 4;

@@ -44,6 +44,11 @@ _SIGS = {
     "rhqr_arnoldi_solution": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "rhqr_arnoldi_basis": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp)]),
     "rhqr_spmv_csr": (C.c_int, [C.c_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rhqr_batch_workspace_size": (_sz, [_vp, _i32, C.c_int]),
+    "rhqr_batch_create": (C.c_int, [_vp, _i32, C.c_int, C.c_int, _vp, _sz, _vp, C.POINTER(_vp)]),
+    "rhqr_batch_factor": (C.c_int, [_vp, C.c_int, _vp]),
+    "rhqr_batch_status": (C.c_int, [_vp, _vp, _vp]),
+    "rhqr_batch_destroy": (C.c_int, [_vp]),
     "rhqr_profile_begin": (C.c_int, []),
     "rhqr_profile_end": (C.c_int, [C.POINTER(C.c_double), C.POINTER(_i64),
                                    C.POINTER(C.c_double), C.POINTER(_i64)]),
@@ -241,6 +246,71 @@ def recrhqr(sk, W, mode=REC_M, want_q=True):
                               _ptr(ws), ws.numel(), _stream())
     _check(rc, "recrhqr_factor")
     return dict(U=U, S=S, T=T, R=R, Q=Q, ws=ws)
+
+
+class _Problem(C.Structure):
+    _fields_ = [("sketch", _vp), ("d_W", _vp), ("ldw", _i64), ("d_S", _vp), ("lds", _i64),
+                ("d_T", _vp), ("ldt", _i64), ("d_R", _vp), ("ldr", _i64)]
+
+
+class Batch:
+    """Batched left-looking RHQR (rhqr_batch_*): ``problems`` is a list of
+    (Sketch, W) pairs, W (n x m, column-major, GPU, one dtype for the batch)
+    overwritten by U.  Allocates S, T, R per problem and the batch workspace;
+    ``factor(graph)`` runs the whole batch (as a replayed hipGraph when
+    ``graph`` is true).  ``outputs[i]`` = dict(U, S, T, R) in caller order."""
+
+    def __init__(self, problems, scaling=SCALE_UNIT_PIVOT):
+        torch = _torch()
+        self._lib = lib()
+        self.problems = list(problems)
+        dt = self.problems[0][1].dtype
+        self.dtype = dt
+        arr = (_Problem * len(self.problems))()
+        self.outputs = []
+        for i, (sk, W) in enumerate(self.problems):
+            n, m = W.shape
+            if W.dtype != dt or n != sk.n or m != sk.m:
+                raise ValueError(f"problem {i}: W does not match its sketch or the batch dtype")
+            dev = W.device
+            S = colmajor_empty(sk.rows_out, m, torch.float64, dev)
+            T = colmajor_empty(m, m, torch.float64, dev)
+            R = colmajor_empty(m, m, torch.float64, dev)
+            self.outputs.append(dict(U=W, S=S, T=T, R=R))
+            arr[i] = _Problem(sk.h.value, W.data_ptr(), _ld(W), S.data_ptr(), _ld(S), T.data_ptr(),
+                              _ld(T), R.data_ptr(), _ld(R))
+        self._arr = arr
+        code = dtype_code(dt)
+        nb = self._lib.rhqr_batch_workspace_size(arr, len(arr), code)
+        if nb == 0:
+            raise RHQRError("rhqr_batch_workspace_size rejected the problems")
+        self.ws = workspace(nb, self.problems[0][1].device)
+        h = C.c_void_p()
+        _check(self._lib.rhqr_batch_create(arr, len(arr), code, int(scaling), _ptr(self.ws),
+                                           self.ws.numel(), _stream(), C.byref(h)),
+               "rhqr_batch_create")
+        self.h = h
+
+    def factor(self, graph=False):
+        _check(self._lib.rhqr_batch_factor(self.h, 1 if graph else 0, _stream()),
+               "rhqr_batch_factor")
+        return self.outputs
+
+    def status(self):
+        info = (C.c_int32 * len(self.problems))()
+        _check(self._lib.rhqr_batch_status(self.h, _stream(), info), "rhqr_batch_status")
+        return list(info)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.rhqr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_begin():
