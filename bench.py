@@ -175,6 +175,95 @@ def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, steps, warmup, profile):
     return res, roof
 
 
+def batched_workload(count, seed=0):
+    """The batched workload: ``count`` problems, n = 2^k with k uniform in
+    {14..18}, m uniform in [16, 128], cond log-uniform in 1e2..1e12, SRHT
+    l = 4m with a per-problem sketch seed."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        k = int(rng.integers(14, 19))
+        m = int(rng.integers(16, 129))
+        kap = float(rng.uniform(2.0, 12.0))
+        out.append((1 << k, m, 4 * m, kap, seed * 100003 + i))
+    return out
+
+
+def run_batched(rhqr, torch, count, steps, warmup, dtype_name="float32"):
+    """Factor the whole batch per step (one hipGraph launch); value = sum of the
+    problems' B_alg over the step time."""
+    import numpy as np
+    from paper_2405_10923_amd.inputs import synthetic_matrix_torch
+    dt = getattr(torch, dtype_name)
+    es = torch.finfo(dt).bits // 8
+    shapes = batched_workload(count)
+    src, work, sks = [], [], []
+    for n, m, l, kap, sd in shapes:
+        W64 = synthetic_matrix_torch(n, m, kap, seed=sd, device="cuda")
+        d = W64.abs().amax(dim=0)
+        Ws = torch.empty((m, n), dtype=dt, device="cuda").t()
+        Ws.copy_(W64 / d)   # unit-max column scaling, rounded to the storage type
+        del W64
+        src.append(Ws)
+        work.append(Ws.clone())
+        sks.append(rhqr.Sketch(rhqr.SRHT, n, m, l, seed=sd))
+    b = rhqr.Batch(list(zip(sks, work)))
+    bytes_alg = sum(b_alg(n, m, es) for n, m, _, _, _ in shapes)
+
+    def restore():
+        for s_, w_ in zip(src, work):
+            w_.copy_(s_)
+
+    for _ in range(warmup):
+        restore()
+        b.factor(graph=True)
+    torch.cuda.synchronize()
+    evs = []
+    for _ in range(steps):
+        restore()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.factor(graph=True)
+        e1.record()
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(c) for a, c in evs]))
+    info = b.status()
+    # accuracy of the largest-m problem of the batch (untimed, thin Q by torch)
+    i = int(np.argmax([m for _, m, _, _, _ in shapes]))
+    n, m, l, kap, sd = shapes[i]
+    o = b.outputs[i]
+    U = o["U"].to(torch.float64)   # head block written from S = Psi U
+    T = o["T"]
+    Q = -U @ (T @ U[:m].t())       # Q = [I; 0] - U T U_1^t (Sec. 3.2)
+    Q[:m] += torch.eye(m, dtype=torch.float64, device="cuda")
+    Wt = src[i].to(torch.float64)
+    ef = float(torch.linalg.norm(Wt - Q @ o["R"]) / torch.linalg.norm(Wt))
+    Qs = to_colmajor_dt(Q, dt)
+    Y = rhqr.sketch(sks[i], Qs)
+    eo = float(np.linalg.norm((Y.t() @ Y).cpu().numpy() - np.eye(m), 2))
+    b.close()
+    del src, work
+    torch.cuda.empty_cache()
+    gbs = bytes_alg / (ms * 1e-3) / 1e9
+    return {"problems": count, "dtype": dtype_name, "ms_per_batch": round(ms, 3),
+            "factorizations_per_s": round(count * 1000.0 / ms, 1),
+            "GBps_alg": round(gbs, 1), "hbm_frac_alg": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_alg": bytes_alg, "launch": "one hipGraph replay per batch",
+            "breakdowns": int(sum(1 for v in info if v)),
+            "largest_m_problem": {"n": n, "m": m, "cond": f"1e{kap:.1f}", "e_fact": ef,
+                                  "e_orth": eo}}
+
+
+def to_colmajor_dt(A, dt):
+    import torch
+    out = torch.empty((A.shape[1], A.shape[0]), dtype=dt, device=A.device).t()
+    out.copy_(A)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +280,8 @@ def main():
                     help="skip the column-by-column float64 reference schedule")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=32)
+    ap.add_argument("--batch-count", type=int, default=512,
+                    help="problems of the batched float32 workload (0: skip it)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="first copy a GIB-sized buffer three times (a plain copy kernel of "
                          "known traffic, to scale hardware byte counters)")
@@ -240,6 +331,16 @@ def main():
               f"{column['GBps_alg']:.0f} GB/s(alg) = {column['hbm_frac_alg']:.1%} of HBM",
               file=sys.stderr, flush=True)
 
+    batched = None
+    if args.batch_count > 0:
+        del W64
+        torch.cuda.empty_cache()
+        batched = run_batched(rhqr, torch, args.batch_count, args.steps, args.warmup)
+        print(f"# batched float32 x{args.batch_count}: {batched['ms_per_batch']:.2f} ms/batch "
+              f"{batched['GBps_alg']:.0f} GB/s(alg) = {batched['hbm_frac_alg']:.1%} of HBM, "
+              f"largest-m e_fact {batched['largest_m_problem']['e_fact']:.2e}",
+              file=sys.stderr, flush=True)
+
     f64 = res.get("float64")
     mixed = {}
     for k, v in res.items():
@@ -276,6 +377,8 @@ def main():
     }
     if column is not None:
         line["column_by_column_f64"] = column
+    if batched is not None:
+        line["batched_f32"] = batched
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n, l, kappa, args.cpu_cols)
     print(json.dumps(line), flush=True)
