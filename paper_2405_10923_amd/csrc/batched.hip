@@ -64,19 +64,23 @@ __global__ void kb_sketch_finish(const SketchJob *__restrict__ J, const BlockMap
                         blockIdx.y * blockDim.x + threadIdx.x, b.local);
 }
 
+// 256-thread tall workgroups: several per compute unit, so one workgroup's
+// transform overlaps the others' streaming (the problems are small)
+constexpr int BATCH_TPB = 256;
+
 template <typename ST, int TPW>
-__global__ void __launch_bounds__(TALL_TPB) kb_tall(const ColProblem *__restrict__ P,
-                                                    const BlockMap *__restrict__ map, int32_t j) {
+__global__ void __launch_bounds__(BATCH_TPB) kb_tall(const ColProblem *__restrict__ P,
+                                                     const BlockMap *__restrict__ map, int32_t j) {
   const BlockMap b = map[blockIdx.x];
-  tall_block<ST, RHQR_SKETCH_SRHT, TPW>(P[b.p], j, 0, b.local);
+  tall_block<ST, RHQR_SKETCH_SRHT, TPW, BATCH_TPB>(P[b.p], j, 0, b.local);
 }
 
 template <typename ST>
-__global__ void __launch_bounds__(1024) kb_red(const ColProblem *__restrict__ P,
-                                               const BlockMap *__restrict__ map, int32_t j) {
+__global__ void __launch_bounds__(256) kb_red(const ColProblem *__restrict__ P,
+                                              const BlockMap *__restrict__ map, int32_t j) {
   const BlockMap b = map[blockIdx.x];
   const ColProblem &Q = P[b.p];
-  red_block<ST, RHQR_SKETCH_SRHT>(Q, j, j + 1 < Q.m, b.local);
+  red_block<ST, RHQR_SKETCH_SRHT, 4>(Q, j, j + 1 < Q.m, b.local);
 }
 
 __global__ void __launch_bounds__(1024) kb_fin(const ColProblem *__restrict__ P, int32_t j, int fg) {
@@ -247,11 +251,11 @@ int enqueue_typed(rhqr_batch_s *b, hipStream_t st) {
     const int a = active(b, j);
     if (j >= 1) {
       constexpr int TPW = sizeof(ST) == 2 ? 2 : 1;  // = batch_tpw(dtype)
-      hipLaunchKernelGGL((kb_tall<ST, TPW>), dim3(b->tall_start[a]), dim3(TALL_TPB), 0, st,
+      hipLaunchKernelGGL((kb_tall<ST, TPW>), dim3(b->tall_start[a]), dim3(BATCH_TPB), 0, st,
                          b->d_probs, b->d_tall, j);
       RHQR_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL((kb_red<ST>), dim3(b->red_start[a]), dim3(1024), 0, st, b->d_probs, b->d_red, j);
+    hipLaunchKernelGGL((kb_red<ST>), dim3(b->red_start[a]), dim3(256), 0, st, b->d_probs, b->d_red, j);
     RHQR_HIP(hipGetLastError());
     const int fg = fin_groups(j);
     hipLaunchKernelGGL(kb_fin, dim3(a * fg), dim3(1024), 0, st, b->d_probs, j, fg);

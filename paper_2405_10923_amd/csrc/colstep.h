@@ -40,7 +40,7 @@ __device__ __forceinline__ double deferred_c(const double *__restrict__ fs,
 // they keep their input values (head rows of W are refreshed in float64 from
 // U_1 = S_{1:m} by the reduction kernel).  !FAST: guarded element accesses
 // (ragged last tile or unaligned storage).
-template <typename ST, bool FAST, int NV>
+template <typename ST, bool FAST, int NV, int TPB>
 __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
                                           int32_t j, int32_t p0, bool prev,
                                           const double *__restrict__ cf, double cprev,
@@ -51,7 +51,7 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
   constexpr int VEC = 16 / sizeof(ST);
   constexpr bool LOWP = !std::is_same<ST, double>::value;
   const int tid = threadIdx.x;
-  auto row = [&](int v) { return base + (int64_t)VEC * (tid + TALL_TPB * v); };
+  auto row = [&](int v) { return base + (int64_t)VEC * (tid + TPB * v); };
   auto ok = [&](int64_t i) { return i >= m && i < n; };
   const bool head = base < m;  // uniform: the tile holds head rows
 
@@ -241,8 +241,13 @@ template <typename A, int TPW> __device__ void fwht_tiles_lds(A *s) {
   __syncthreads();
 }
 
-template <typename ST, int KIND, int TPW>
+// TPB threads per workgroup: 1024 (one workgroup per compute unit on large
+// problems) or 256 (several workgroups per compute unit, for the many small
+// problems of a batch).  The result does not depend on TPB: every row is
+// refreshed alone and the in-LDS transform runs the same butterflies.
+template <typename ST, int KIND, int TPW, int TPB = TALL_TPB>
 __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32_t p0, int bid) {
+  static_assert(KIND != RHQR_SKETCH_GAUSS || TPB == 1024, "the Gaussian tail assumes 1024 threads");
   ST *__restrict__ W = (ST *)P.W;
   const int64_t ldw = P.ldw, n = P.n;
   const int32_t m = P.m, l = P.l;
@@ -261,7 +266,7 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
   using CT = typename CompT<ST>::type;
   constexpr int VEC = 16 / sizeof(ST);
   constexpr int ROWS = TILE * TPW;
-  constexpr int NV = ROWS / (TALL_TPB * VEC);
+  constexpr int NV = ROWS / (TPB * VEC);
   static_assert(NV >= 1, "tile too small for the vector width");
   __shared__ CT s[TPW * TILE_PAD];
   const int64_t base = (int64_t)bid * ROWS;
@@ -286,9 +291,9 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
   }
   CT acc[NV][VEC];
   if (fast)
-    tall_body<ST, true, NV>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, wstage, base, acc);
+    tall_body<ST, true, NV, TPB>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, wstage, base, acc);
   else
-    tall_body<ST, false, NV>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, wstage, base, acc);
+    tall_body<ST, false, NV, TPB>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, wstage, base, acc);
 
   if (KIND == RHQR_SKETCH_IDENT) return;
   const int tid = threadIdx.x;
@@ -297,7 +302,7 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
     lds_barrier();
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int li0 = VEC * (tid + TALL_TPB * v);
+      const int li0 = VEC * (tid + TPB * v);
       const int64_t i0 = base + li0;
       const uint64_t word = sgn[li0 >> 6];
 #pragma unroll
@@ -311,7 +316,7 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
     }
     fwht_tiles_lds<CT, TPW>(s);
     const uint64_t t0 = (uint64_t)bid * TPW;
-    for (int q = tid; q < l; q += TALL_TPB) {
+    for (int q = tid; q < l; q += TPB) {
       const int32_t r = q == tid ? rq : rows[q];
       const int r2 = tpad(r & (TILE - 1));
       const uint64_t r1 = (uint64_t)(r >> TILE_LOG);
@@ -327,7 +332,7 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
     __shared__ double red[KIND == RHQR_SKETCH_GAUSS ? 1024 : 1];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int li0 = VEC * (tid + TALL_TPB * v);
+      const int li0 = VEC * (tid + TPB * v);
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         const int64_t i = base + li0 + e;
@@ -374,8 +379,13 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
 // the partials) is issued before the first wait.
 constexpr int RED_NP = 16;  // per-lane loads issued together
 
-template <typename ST, int KIND>
+// RW waves per workgroup (16 with 1024 threads, 4 with 256).  The row sums
+// are formed in 16 fixed groups (element t of a row's sum belongs to group
+// t mod 16, each group summed in increasing t, then the groups in order), so
+// the result does not depend on RW.
+template <typename ST, int KIND, int RW = 16>
 __device__ __forceinline__ void red_block(const ColProblem &P, int32_t j, int next, int bid) {
+  static_assert(16 % RW == 0, "RW must divide 16");
   const ST *__restrict__ W = (const ST *)P.W;
   const int64_t ldw = P.ldw;
   const int32_t m = P.m, l = P.l;
@@ -407,44 +417,48 @@ __device__ __forceinline__ void red_block(const ColProblem &P, int32_t j, int ne
   double sp[RED_NP];
 #pragma unroll
   for (int b = 0; b < RED_NP; ++b) {
-    const int p = w + 16 * b;
+    const int p = w + RW * b;
     sp[b] = (valid && p < j) ? S[k + (int64_t)p * lds] : 0.0;
   }
   const double z = (next && valid) ? Z[k + (int64_t)(j + 1) * ldz] : 0.0;
-  double v = 0.0;
-  if (j >= 1) {
-    if (head) {
-      const double clast = defer ? deferred_c(fs, dcpart, gfin) : 0.0;
-      const int pe = valid ? min(j, k + 1) : 0;
-      for (int p0 = w; p0 < pe; p0 += 16 * RED_NP) {
-        double t[RED_NP];
+  const double clast = (j >= 1 && head && defer) ? deferred_c(fs, dcpart, gfin) : 0.0;
 #pragma unroll
-        for (int b = 0; b < RED_NP; ++b) {
-          const int p = p0 + 16 * b;
-          t[b] = 0.0;
-          if (p < pe) {
-            const double cp = (defer && p == j - 1) ? clast : c[p];
-            t[b] = S[k + (int64_t)p * lds] * cp;
+  for (int gi = 0; gi < 16 / RW; ++gi) {
+    const int g = w + RW * gi;  // this group's elements: g, g + 16, g + 32, ...
+    double v = 0.0;
+    if (j >= 1) {
+      if (head) {
+        const int pe = valid ? min(j, k + 1) : 0;
+        for (int p0 = g; p0 < pe; p0 += 16 * RED_NP) {
+          double t[RED_NP];
+#pragma unroll
+          for (int b = 0; b < RED_NP; ++b) {
+            const int p = p0 + 16 * b;
+            t[b] = 0.0;
+            if (p < pe) {
+              const double cp = (defer && p == j - 1) ? clast : c[p];
+              t[b] = S[k + (int64_t)p * lds] * cp;
+            }
           }
+#pragma unroll
+          for (int b = 0; b < RED_NP; ++b) v += t[b];
         }
+      } else if (KIND != RHQR_SKETCH_IDENT && valid) {
+        const double *pq = part + (k - m);
+        for (int64_t t0 = g; t0 < nparts; t0 += 16 * RED_NP) {
+          double t[RED_NP];
 #pragma unroll
-        for (int b = 0; b < RED_NP; ++b) v += t[b];
-      }
-    } else if (KIND != RHQR_SKETCH_IDENT && valid) {
-      const double *pq = part + (k - m);
-      for (int64_t t0 = w; t0 < nparts; t0 += 16 * RED_NP) {
-        double t[RED_NP];
+          for (int b = 0; b < RED_NP; ++b) {
+            const int64_t tt = t0 + 16 * b;
+            t[b] = tt < nparts ? pq[tt * l] : 0.0;
+          }
 #pragma unroll
-        for (int b = 0; b < RED_NP; ++b) {
-          const int64_t tt = t0 + 16 * b;
-          t[b] = tt < nparts ? pq[tt * l] : 0.0;
+          for (int b = 0; b < RED_NP; ++b) v += t[b];
         }
-#pragma unroll
-        for (int b = 0; b < RED_NP; ++b) v += t[b];
       }
     }
+    red[g][lane] = v;
   }
-  red[w][lane] = v;
   __syncthreads();
   if (w == 0) {
     double s = 0.0;
@@ -473,17 +487,17 @@ __device__ __forceinline__ void red_block(const ColProblem &P, int32_t j, int ne
   __syncthreads();
   const double ym = yl[lane];
   // partial dot products with the earlier columns of S, one wave per p
-  for (int p0 = w; p0 < j; p0 += 16 * RED_NP) {
-    if (p0 > w) {  // columns beyond the prefetched ones (j > 16 RED_NP)
+  for (int p0 = w; p0 < j; p0 += RW * RED_NP) {
+    if (p0 > w) {  // columns beyond the prefetched ones (j > RW RED_NP)
 #pragma unroll
       for (int b = 0; b < RED_NP; ++b) {
-        const int p = p0 + 16 * b;
+        const int p = p0 + RW * b;
         sp[b] = (valid && p < j) ? S[k + (int64_t)p * lds] : 0.0;
       }
     }
 #pragma unroll
     for (int b = 0; b < RED_NP; ++b) {
-      const int p = p0 + 16 * b;
+      const int p = p0 + RW * b;
       if (p < j) {  // uniform across the wave
         const double dv = wave_sum(sp[b] * ym);
         const double ev = next ? wave_sum(sp[b] * z) : 0.0;
