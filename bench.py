@@ -25,6 +25,7 @@ bytes per launch.
 Prints ONE JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -37,6 +38,41 @@ if ROOT not in sys.path:
 METRIC = "RHQR GB/s (% HBM roofline), mixed vs FP64 at ||W-QR||/||W|| <= 1e-2"
 HBM_PEAK_GBS = 8000.0
 TILE = 4096
+
+
+# HBM traffic per launch measured with rocprofv3 byte counters (FETCH_SIZE and
+# WRITE_SIZE runs, scaled by a plain copy of known size), committed as text;
+# used only while the kernel sources still hash to the recorded digest.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3.md")
+KERNEL_SOURCES = ["common.h", "engine.h", "colstep.h", "engine.hip"]
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2405_10923_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key):
+    """Bytes per launch of kernel ``key`` ("k_panel" or "k_tall_column") from
+    TRAFFIC_FILE, or None if absent or taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    vals = {}
+    for ln in lines:
+        parts = ln.strip().strip("`").split()
+        if len(parts) == 2 and parts[0] == "source-digest:":
+            vals["digest"] = parts[1]
+        elif len(parts) == 3 and parts[0] == "traffic":
+            vals[parts[1].rstrip(":")] = int(parts[2])
+    if vals.get("digest") != source_digest():
+        return None
+    return vals.get(key)
 
 
 def b_alg(n, m, b):
@@ -147,9 +183,12 @@ def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, steps, warmup, profile):
                          "alg_bytes_per_launch": pb * steps / pan_n, "achieved": ach})
         kern.sort(key=lambda k: -k["ms_total"])
         top = kern[0]
+        tkey = ("k_panel" if top["kernel"].startswith("k_panel") else
+                "k_tall_column" if panel < 2 else "k_tall_blocked")
+        traffic = measured_traffic(tkey) if es == 8 else None
         roof = {"bound": "hbm", "achieved": round(top["achieved"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(top["achieved"] / HBM_PEAK_GBS, 4),
-                "traffic": None, "kernel": top["kernel"],
+                "traffic": traffic, "kernel": top["kernel"],
                 "avg_launch_ms": round(top["avg_launch_ms"], 4), "launches": top["launches"],
                 "alg_bytes_per_launch": round(top["alg_bytes_per_launch"]),
                 "share_of_step": round(top["ms_total"] / steps / step_ms, 3),
@@ -285,7 +324,12 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="first copy a GIB-sized buffer three times (a plain copy kernel of "
                          "known traffic, to scale hardware byte counters)")
+    ap.add_argument("--print-digest", action="store_true",
+                    help="print the digest of the kernel sources and exit")
     args = ap.parse_args()
+    if args.print_digest:
+        print(source_digest())
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}): the row-sharded "
               "multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
