@@ -243,7 +243,7 @@ RHQR_API int rhqr_batch_destroy(rhqr_batch_t b);
 /* ------------------------------------------------------------------------
  * Measurement aid.  Between rhqr_profile_begin() and rhqr_profile_end(), every
  * launch of the tall kernels of rhqr_factor / recrhqr_factor / the Arnoldi
- * step is bracketed by HIP events recorded on the launching stream: the
+ * step records a start and an end HIP event from its own dispatch: the
  * per-column refresh + re-sketch pass, and the panel update of the blocked
  * schedule.  rhqr_profile_end synchronises those events and returns, for each
  * of the two kernels, the summed kernel time (ms) and the number of launches

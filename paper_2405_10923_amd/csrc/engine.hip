@@ -18,6 +18,8 @@
 // the division by alpha_j is folded into the next pass's coefficient.
 #include "colstep.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
@@ -26,9 +28,10 @@
 namespace {
 
 
-// Optional timing of the tall kernels with HIP events recorded on the
-// launching stream (rhqr_profile_begin / rhqr_profile_end): class 0 = the
-// refresh + re-sketch pass, class 1 = the panel update of the blocked schedule.
+// Optional timing of the tall kernels (rhqr_profile_begin / rhqr_profile_end):
+// the dispatch itself records a start and an end event (hipExtLaunchKernel),
+// so the measured time is the kernel's own.  Class 0 = the refresh +
+// re-sketch pass, class 1 = the panel update of the blocked schedule.
 struct TallProfile {
   bool on = false;
   std::vector<hipEvent_t> ev;   // pairs (start, stop)
@@ -183,22 +186,30 @@ inline int tall_tpw(int64_t n, size_t elt) {
   return tpw;
 }
 
+// e0/e1 non-null: the dispatch itself records the two events (start and end
+// of the kernel), as the profiling interface requires
 template <typename ST, int KIND, int TPW>
-void launch_tall(const ColProblem &P, int32_t j, int32_t p0, hipStream_t st) {
+void launch_tall(const ColProblem &P, int32_t j, int32_t p0, hipStream_t st, hipEvent_t e0,
+                 hipEvent_t e1) {
   const int64_t rows = (int64_t)TILE * TPW;
   const int64_t g = (P.n + rows - 1) / rows;
-  hipLaunchKernelGGL((k_tall<ST, KIND, TPW>), dim3(g), dim3(TALL_TPB), 0, st, P, j, p0);
+  if (e0)
+    hipExtLaunchKernelGGL((k_tall<ST, KIND, TPW>), dim3(g), dim3(TALL_TPB), 0, st, e0, e1, 0, P, j,
+                          p0);
+  else
+    hipLaunchKernelGGL((k_tall<ST, KIND, TPW>), dim3(g), dim3(TALL_TPB), 0, st, P, j, p0);
 }
 
 template <typename ST, int KIND>
-void launch_tall_k(const ColProblem &P, int32_t j, int32_t p0, int tpw, hipStream_t st) {
+void launch_tall_k(const ColProblem &P, int32_t j, int32_t p0, int tpw, hipStream_t st,
+                   hipEvent_t e0, hipEvent_t e1) {
   if constexpr (sizeof(ST) == 2) {
-    if (tpw == 4) launch_tall<ST, KIND, 4>(P, j, p0, st);
-    else launch_tall<ST, KIND, 2>(P, j, p0, st);
+    if (tpw == 4) launch_tall<ST, KIND, 4>(P, j, p0, st, e0, e1);
+    else launch_tall<ST, KIND, 2>(P, j, p0, st, e0, e1);
   } else {
-    if (tpw == 4) launch_tall<ST, KIND, 4>(P, j, p0, st);
-    else if (tpw == 2) launch_tall<ST, KIND, 2>(P, j, p0, st);
-    else launch_tall<ST, KIND, 1>(P, j, p0, st);
+    if (tpw == 4) launch_tall<ST, KIND, 4>(P, j, p0, st, e0, e1);
+    else if (tpw == 2) launch_tall<ST, KIND, 2>(P, j, p0, st, e0, e1);
+    else launch_tall<ST, KIND, 1>(P, j, p0, st, e0, e1);
   }
 }
 
@@ -207,17 +218,13 @@ int tall_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int32_t p0, hipStr
   const int tpw = tall_tpw(a.n, sizeof(ST));
   const ColProblem P = make_col_problem(a, w, tpw);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (g_prof.on) {
-    if (prof_pair(&e0, &e1, 0)) return RHQR_ERR_HIP;
-    RHQR_HIP(hipEventRecord(e0, st));
-  }
+  if (g_prof.on && prof_pair(&e0, &e1, 0)) return RHQR_ERR_HIP;
   switch (a.kind) {
-    case RHQR_SKETCH_SRHT: launch_tall_k<ST, RHQR_SKETCH_SRHT>(P, j, p0, tpw, st); break;
-    case RHQR_SKETCH_GAUSS: launch_tall_k<ST, RHQR_SKETCH_GAUSS>(P, j, p0, tpw, st); break;
-    default: launch_tall_k<ST, RHQR_SKETCH_IDENT>(P, j, p0, tpw, st);
+    case RHQR_SKETCH_SRHT: launch_tall_k<ST, RHQR_SKETCH_SRHT>(P, j, p0, tpw, st, e0, e1); break;
+    case RHQR_SKETCH_GAUSS: launch_tall_k<ST, RHQR_SKETCH_GAUSS>(P, j, p0, tpw, st, e0, e1); break;
+    default: launch_tall_k<ST, RHQR_SKETCH_IDENT>(P, j, p0, tpw, st, e0, e1);
   }
   RHQR_HIP(hipGetLastError());
-  if (g_prof.on) RHQR_HIP(hipEventRecord(e1, st));
   return RHQR_OK;
 }
 
@@ -438,19 +445,31 @@ __global__ void __launch_bounds__(PANEL_TPB) k_panel(ST *__restrict__ W, int64_t
 
 inline int panel_width(int nb) { return nb <= 8 ? 8 : nb <= 16 ? 16 : 32; }
 
+template <typename ST, int NBC>
+void launch_panel_w(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t J, int32_t nb,
+                    const double *C, int aligned, dim3 grid, hipStream_t st, hipEvent_t e0,
+                    hipEvent_t e1) {
+  if (e0)
+    hipExtLaunchKernelGGL((k_panel<ST, NBC>), grid, dim3(PANEL_TPB), 0, st, e0, e1, 0, W, ldw, n, m,
+                          J, nb, C, aligned);
+  else
+    hipLaunchKernelGGL((k_panel<ST, NBC>), grid, dim3(PANEL_TPB), 0, st, W, ldw, n, m, J, nb, C,
+                       aligned);
+}
+
 template <typename ST>
 void launch_panel(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t J, int32_t nb, const double *C,
-                  hipStream_t st) {
+                  hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   constexpr int VEC = sizeof(ST) == 8 ? 2 : 4;
   const int aligned = ((uintptr_t)W % 16 == 0) && ((ldw * (int64_t)sizeof(ST)) % 16 == 0);
   const int64_t threads = (n - (m - m % VEC) + VEC - 1) / VEC;
   const dim3 grid((unsigned)((threads + PANEL_TPB - 1) / PANEL_TPB));
   if (nb <= 8)
-    hipLaunchKernelGGL((k_panel<ST, 8>), grid, dim3(PANEL_TPB), 0, st, W, ldw, n, m, J, nb, C, aligned);
+    launch_panel_w<ST, 8>(W, ldw, n, m, J, nb, C, aligned, grid, st, e0, e1);
   else if (nb <= 16)
-    hipLaunchKernelGGL((k_panel<ST, 16>), grid, dim3(PANEL_TPB), 0, st, W, ldw, n, m, J, nb, C, aligned);
+    launch_panel_w<ST, 16>(W, ldw, n, m, J, nb, C, aligned, grid, st, e0, e1);
   else
-    hipLaunchKernelGGL((k_panel<ST, 32>), grid, dim3(PANEL_TPB), 0, st, W, ldw, n, m, J, nb, C, aligned);
+    launch_panel_w<ST, 32>(W, ldw, n, m, J, nb, C, aligned, grid, st, e0, e1);
 }
 
 template <typename ST>
@@ -478,13 +497,9 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, double *C, 
       RHQR_HIP(hipGetLastError());
       if (ntail > 0) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (g_prof.on) {
-          if (prof_pair(&e0, &e1, 1)) return RHQR_ERR_HIP;
-          RHQR_HIP(hipEventRecord(e0, st));
-        }
-        launch_panel<ST>(W, a.ldw, a.n, m, J, nb, (const double *)C, st);
+        if (g_prof.on && prof_pair(&e0, &e1, 1)) return RHQR_ERR_HIP;
+        launch_panel<ST>(W, a.ldw, a.n, m, J, nb, (const double *)C, st, e0, e1);
         RHQR_HIP(hipGetLastError());
-        if (g_prof.on) RHQR_HIP(hipEventRecord(e1, st));
       }
     }
     for (int32_t j = J; j < J + nb; ++j) {

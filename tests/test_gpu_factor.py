@@ -21,14 +21,15 @@ def _run(kind, n, m, l, kappa, seed=0, scaling=0, dtype="float64", want_q=True, 
     W = synthetic_matrix(n, m, kappa, seed=seed)
     Wd = to_gpu(W, getattr(torch, dtype))
     Win = to_np(Wd)
-    sk = rhqr.Sketch(kind, n, m, l, seed=seed + 1)
+    okind = osk.SRHT if kind == rhqr.SRHT else osk.GAUSS
+    osketch = osk.Sketch(okind, n, m, l, seed=seed + 1)
+    # Gaussian: the oracle's Omega (its own Philox draw) is handed to the GPU
+    om = to_gpu(osketch.omega) if kind == rhqr.GAUSS else None
+    sk = rhqr.Sketch(kind, n, m, l, seed=seed + 1, omega=om)
     out = rhqr.factor(sk, Wd, scaling=scaling, want_q=want_q, panel=panel)
     torch.cuda.synchronize()
     res = {k: to_np(v) for k, v in out.items() if k in ("U", "S", "T", "R") or (k == "Q" and v is not None)}
     res["info"] = rhqr.status(out["ws"])
-    okind = osk.SRHT if kind == rhqr.SRHT else osk.GAUSS
-    omega = sk.omega() if kind == rhqr.GAUSS else None
-    osketch = osk.Sketch(okind, n, m, l, seed=seed + 1, omega=omega)
     return W, Win, res, osketch
 
 

@@ -1,0 +1,159 @@
+"""GPU parity at the workloads' full sizes.
+
+At these sizes the oracle cannot run the whole factorization in seconds, so
+the checks are (a) outputs the oracle computes one by one: sketches of sampled
+columns of the input and of U, taken with the oracle's own Psi; and (b)
+properties that hold at any size, evaluated in float64 with plain torch
+products (no library kernel is involved in a check):
+
+* S = Psi U (sampled columns, oracle sketch);
+* Psi W = (I - S T S^t) [R; 0] (sampled columns, oracle sketch; the compact
+  form of Prop. 3.2 under Psi);
+* ||W - Q R|| / ||W|| <= tol with Q = [I; 0] - U T U_1^t (Sec. 3.2) formed by
+  torch from the returned U, T;
+* ||(Psi Q)^t Psi Q - I||_2 <= tol with Psi Q = [I; 0] - S T U_1^t;
+* recRHQR: M = -T U_1^t R and the row-wise substitution W_2 = U_2 M on sampled
+  columns, backward error within the tolerance.
+
+Workloads: W = G diag(s) V with singular values 1..1e-12 (2^20 x 128, SRHT and
+Gaussian l = 512) and 1..1e-14 (2^22 x 256, SRHT l = 1024, panels of 16: the
+configuration bench.py times).  float64 tolerance 1e-12."""
+import numpy as np
+import pytest
+
+from oracle import sketch as osk
+from tests.gpu_util import cuda_or_skip, to_np, rel, log
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _gen(torch, n, m, kappa, seed):
+    from paper_2405_10923_amd.inputs import synthetic_matrix_torch
+    return synthetic_matrix_torch(n, m, kappa, seed=seed, device="cuda")
+
+
+def _gauss_omega(l, cols, seed):
+    """Gaussian Omega (entries N(0, 1/l)) drawn by the test from numpy's
+    generator and handed to both sides."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((cols, l)).T / np.sqrt(l)  # l x cols, column-major
+
+
+def _checks(torch, W, U, S, T, R, osketch, m, cols, what):
+    dev = W.device
+    I = torch.eye(m, dtype=torch.float64, device=dev)
+    # thin Q and the factorization error (torch, float64)
+    U1 = U[:m]
+    Q = -U @ (T @ U1.t())
+    Q[:m] += I
+    ef = float(torch.linalg.norm(W - Q @ R) / torch.linalg.norm(W))
+    del Q
+    # sketch orthogonality from the sketch-space factors
+    L = S.shape[0]
+    PQ = -S @ (T @ U1.t())
+    PQ[:m] += I
+    G = (PQ.t() @ PQ).cpu().numpy()
+    eo = float(np.linalg.norm(G - np.eye(m), 2))
+    log(f"{what}: e_fact {ef:.2e} e_orth {eo:.2e}")
+    assert ef <= TOL and eo <= TOL
+    # sampled columns against the oracle's Psi
+    Sn, Tn, Rn = to_np(S), to_np(T), to_np(R)
+    for j in cols:
+        u = to_np(U[:, j:j + 1])
+        su = osk.rh_sketch(u, osketch)[:, 0]
+        assert rel(Sn[:, j], su) < TOL, (what, "S = Psi U", j)
+        w = to_np(W[:, j:j + 1])
+        z = osk.rh_sketch(w, osketch)[:, 0]
+        rj = np.zeros(L)
+        rj[:m] = Rn[:, j]
+        cz = rj - Sn @ (Tn @ (Sn.T @ rj))
+        assert np.linalg.norm(cz - z) <= TOL * np.linalg.norm(z), (what, "Psi W", j)
+
+
+@pytest.mark.parametrize("kind", ["srht", "gauss"])
+@pytest.mark.parametrize("panel", [16, 0])
+def test_c2_f64_rhqr_fullsize(kind, panel):
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    n, m, l = 1 << 20, 128, 512
+    log(f"c2 rhqr {kind} panel={panel}: W {n} x {m} cond 1e12, l={l}")
+    W0 = _gen(torch, n, m, 12, seed=0)
+    if kind == "srht":
+        osketch = osk.Sketch(osk.SRHT, n, m, l, seed=0)
+        sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=0)
+    else:
+        om = _gauss_omega(l, n - m, seed=2)
+        osketch = osk.Sketch(osk.GAUSS, n, m, l, seed=0, omega=om)
+        omd = torch.from_numpy(np.ascontiguousarray(om.T)).cuda().t()  # l x (n-m), ld l
+        sk = rhqr.Sketch(rhqr.GAUSS, n, m, l, seed=0, omega=omd)
+        del omd
+    Wd = W0.clone()
+    out = rhqr.factor(sk, Wd, panel=panel)
+    torch.cuda.synchronize()
+    assert rhqr.status(out["ws"]) == 0
+    _checks(torch, W0, out["U"], out["S"], out["T"], out["R"], osketch, m, (0, 1, 63, 127),
+            f"c2 {kind} panel={panel}")
+
+
+@pytest.mark.parametrize("mode", ["M", "RCHOL"])
+def test_c2_f64_recrhqr_fullsize(mode):
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    n, m, l = 1 << 20, 128, 512
+    log(f"c2 recrhqr {mode}: W {n} x {m} cond 1e12, SRHT l={l}")
+    W = _gen(torch, n, m, 12, seed=0)
+    sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=0)
+    osketch = osk.Sketch(osk.SRHT, n, m, l, seed=0)
+    out = rhqr.recrhqr(sk, W, mode=rhqr.REC_M if mode == "M" else rhqr.REC_RCHOL, want_q=True)
+    torch.cuda.synchronize()
+    S, T, R, Q = out["S"], out["T"], out["R"], out["Q"]
+    Sn, Tn, Rn = to_np(S), to_np(T), to_np(R)
+    # R and S: Householder QR of the sketch, whose columns the oracle forms
+    for j in (0, 64, 127):
+        z = osk.rh_sketch(to_np(W[:, j:j + 1]), osketch)[:, 0]
+        rj = np.zeros(S.shape[0])
+        rj[:m] = Rn[:, j]
+        cz = rj - Sn @ (Tn @ (Sn.T @ rj))
+        assert np.linalg.norm(cz - z) <= TOL * np.linalg.norm(z), ("Psi W", j)
+    ef = float(torch.linalg.norm(W - Q @ R) / torch.linalg.norm(W))
+    log(f"  e_fact {ef:.2e}")
+    assert ef <= TOL
+    if mode == "M":
+        U = out["U"]
+        U1 = to_np(U[:m])
+        M = -Tn @ U1.T @ Rn
+        # row-wise substitution W_2 = U_2 M on sampled columns: backward error
+        for j in (0, 31, 127):
+            w2 = to_np(W[m:, j:j + 1])[:, 0]
+            u2 = to_np(U[m:, :j + 1])
+            res = w2 - u2 @ M[:j + 1, j]
+            scale = np.abs(u2) @ np.abs(M[:j + 1, j])
+            assert np.max(np.abs(res) / np.maximum(scale, 1e-300)) <= 64 * (j + 1) * 2.0 ** -53, j
+    else:
+        # Q_2 = W_2 R^-1: Q_2 R = W_2 on sampled columns
+        for j in (0, 31, 127):
+            w2 = to_np(W[m:, j:j + 1])[:, 0]
+            q2 = to_np(Q[m:, :j + 1])
+            res = w2 - q2 @ Rn[:j + 1, j]
+            scale = np.abs(q2) @ np.abs(Rn[:j + 1, j])
+            assert np.max(np.abs(res) / np.maximum(scale, 1e-300)) <= 64 * (j + 1) * 2.0 ** -53, j
+
+
+def test_c3_f64_blocked_fullsize():
+    """2^22 x 256, cond 1e14, SRHT l = 1024, panels of 16: the benchmark's
+    float64 configuration."""
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    n, m, l = 1 << 22, 256, 1024
+    log(f"c3 rhqr f64 blocked: W {n} x {m} cond 1e14, l={l}")
+    W0 = _gen(torch, n, m, 14, seed=0)
+    sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=0)
+    osketch = osk.Sketch(osk.SRHT, n, m, l, seed=0)
+    Wd = W0.clone()
+    out = rhqr.factor(sk, Wd, panel=16)
+    torch.cuda.synchronize()
+    assert rhqr.status(out["ws"]) == 0
+    _checks(torch, W0, out["U"], out["S"], out["T"], out["R"], osketch, m, (0, 1, 128, 255),
+            "c3 f64 panel=16")

@@ -16,13 +16,15 @@ def _rec(n, m, l, kappa, mode, dtype="float64", seed=0, kind=0):
     from paper_2405_10923_amd import rhqr
     W = synthetic_matrix(n, m, kappa, seed=seed)
     Wd = to_gpu(W, getattr(torch, dtype))
-    sk = rhqr.Sketch(kind, n, m, l, seed=seed + 3)
+    okind = osk.SRHT if kind == rhqr.SRHT else osk.GAUSS
+    osketch = osk.Sketch(okind, n, m, l, seed=seed + 3)
+    # Gaussian: the oracle's Omega (its own Philox draw) is handed to the GPU
+    om = to_gpu(osketch.omega) if kind == rhqr.GAUSS else None
+    sk = rhqr.Sketch(kind, n, m, l, seed=seed + 3, omega=om)
     out = rhqr.recrhqr(sk, Wd, mode=mode, want_q=True)
     torch.cuda.synchronize()
     g = {k: (to_np(v) if v is not None else None) for k, v in out.items() if k != "ws"}
-    okind = osk.SRHT if kind == rhqr.SRHT else osk.GAUSS
-    om = sk.omega() if kind == rhqr.GAUSS else None
-    return W, to_np(Wd), g, osk.Sketch(okind, n, m, l, seed=seed + 3, omega=om)
+    return W, to_np(Wd), g, osketch
 
 
 @pytest.mark.parametrize("n,m,l", [(300, 7, 40), (3 * 4096 + 777, 24, 96), (2 * 4096 + 5, 70, 200)])

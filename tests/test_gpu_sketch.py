@@ -82,8 +82,8 @@ def test_gauss_sketch_f64():
     from paper_2405_10923_amd import rhqr
     n, m, l, k = 9000, 12, 80, 70
     X = np.random.default_rng(3).standard_normal((n, k))
-    sk = rhqr.Sketch(rhqr.GAUSS, n, m, l, seed=6)
-    om = sk.omega()
+    om = osk.gaussian_omega(6, l, n - m)  # the oracle's draw, handed to the GPU
+    sk = rhqr.Sketch(rhqr.GAUSS, n, m, l, seed=6, omega=to_gpu(om))
     Y = to_np(rhqr.sketch(sk, to_gpu(X)))
     ref = np.concatenate([X[:m], om @ X[m:]])
     for c in range(k):
