@@ -87,9 +87,11 @@ int run_column_loop(const LoopArgs &a, const LoopWs &w, hipStream_t st);
 int engine_tall(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st);
 int engine_step(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st);
 // blocked schedule: panels of `panel` (<= 32) columns; C and G are float64
-// scratch of m x panel entries each
+// scratch of m x 32 entries each, mf panel_mfma_bytes(m) bytes
 int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, double *C, double *G,
-                            hipStream_t st);
+                            void *mf, hipStream_t st);
+// scratch of the matrix-core panel update (split coefficients and scales)
+size_t panel_mfma_bytes(int32_t m);
 int launch_thin_q(int dtype, int64_t n, int32_t m, const void *U, int64_t ldu, const double *S,
                   int64_t lds, const double *T, int64_t ldt, double *Mq, void *Q, int64_t ldq,
                   hipStream_t st);

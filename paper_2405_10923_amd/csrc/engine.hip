@@ -443,6 +443,206 @@ __global__ void __launch_bounds__(PANEL_TPB) k_panel(ST *__restrict__ W, int64_t
   }
 }
 
+// ------------------------------------------- panel update on matrix cores
+// 2-byte storage, nb <= 16: W[m:n, J:J+nb] -= U[m:n, 0:J] C on float32 MFMA
+// (v_mfma_f32_16x16x16 f16 / bf16).  C (float64) is scaled per column by a
+// power of two s_j (max |C_{:,j}| / s_j in (1/2, 1]) and split into two
+// storage-type parts, C / s = hi + lo, so the coefficients keep about 22
+// (f16) or 16 (bf16) bits; the products accumulate in float32 as on the
+// vector path.  Each wave owns 64 rows: it loads 32 columns of U with 16-byte
+// row-contiguous loads, transposes them through its own LDS slice (the MFMA
+// operand needs 4 consecutive columns per lane) and issues the next chunk's
+// loads before the current chunk's products.
+constexpr int PM_ROWS = 64;                // rows per wave
+constexpr int PM_KC = 32;                  // columns of U per chunk
+constexpr int PM_RS = PM_ROWS + 8;         // LDS stride (elements) of one column slice
+constexpr int PM_WAVES = 4;
+
+typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
+typedef short s16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+template <typename ST> __device__ __forceinline__ float dec16(unsigned short b) {
+  if constexpr (std::is_same<ST, __half>::value)
+    return __half2float(__ushort_as_half(b));
+  else
+    return __uint_as_float(((uint32_t)b) << 16);
+}
+
+// Scales and split coefficients in the MFMA B-operand order: for column group
+// g (columns 4g..4g+3 of U, i.e. rows of C) and panel column j, the four
+// values sit at B[(g * 16 + j) * 4 + t].  Rows k >= J and columns j >= nb are
+// zero; Kp = J rounded up to PM_KC.  One workgroup of 16 waves.
+template <typename ST>
+__global__ void __launch_bounds__(1024) k_pconv(int32_t J, int32_t nb, int32_t pw, int32_t Kp,
+                                               const double *__restrict__ Ct,
+                                               unsigned short *__restrict__ Bh,
+                                               unsigned short *__restrict__ Bl,
+                                               float *__restrict__ scale) {
+  __shared__ float sc[16];
+  const int lane = threadIdx.x & 63, j = threadIdx.x >> 6;  // wave j: panel column j
+  double mx = 0.0;
+  if (j < nb)
+    for (int k = lane; k < J; k += 64) mx = fmax(mx, fabs(Ct[(int64_t)k * pw + j]));
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if (lane == 0) {
+    int e = 0;
+    if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [1/2, 1)
+    sc[j] = ldexpf(1.0f, e);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < Kp * 16; idx += blockDim.x) {
+    const int k = idx >> 4, jj = idx & 15;
+    double v = 0.0;
+    if (k < J && jj < nb) v = Ct[(int64_t)k * pw + jj] / (double)sc[jj];
+    const unsigned short h = enc16<ST>((float)v);
+    const unsigned short lo = enc16<ST>((float)(v - (double)dec16<ST>(h)));
+    const int o = (((k >> 2) * 16 + jj) << 2) + (k & 3);
+    Bh[o] = h;
+    Bl[o] = lo;
+  }
+  if (threadIdx.x < 16) scale[threadIdx.x] = sc[threadIdx.x];
+}
+
+template <typename ST>
+__device__ __forceinline__ f32x4_t mfma16(const unsigned short (&a)[4], const uint2 b,
+                                         f32x4_t acc) {
+  if constexpr (std::is_same<ST, __half>::value) {
+    f16x4_t av, bv;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) av[t] = __builtin_bit_cast(_Float16, a[t]);
+    bv[0] = __builtin_bit_cast(_Float16, (unsigned short)(b.x & 0xffff));
+    bv[1] = __builtin_bit_cast(_Float16, (unsigned short)(b.x >> 16));
+    bv[2] = __builtin_bit_cast(_Float16, (unsigned short)(b.y & 0xffff));
+    bv[3] = __builtin_bit_cast(_Float16, (unsigned short)(b.y >> 16));
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(av, bv, acc, 0, 0, 0);
+  } else {
+    s16x4_t av, bv;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) av[t] = (short)a[t];
+    bv[0] = (short)(b.x & 0xffff);
+    bv[1] = (short)(b.x >> 16);
+    bv[2] = (short)(b.y & 0xffff);
+    bv[3] = (short)(b.y >> 16);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+  }
+}
+
+// One wave's 64 rows.  FULL: all rows in bounds and 16-byte aligned; the
+// column index of the loads is clamped to J - 1 (finite values, multiplied by
+// the zero padding of B), so the loads carry no condition.  !FULL (the last,
+// ragged wave): guarded element loads.
+template <typename ST, bool FULL>
+__device__ __forceinline__ void panel_mfma_wave(ST *__restrict__ W, int64_t ldw, int64_t n,
+                                                int32_t J, const unsigned short *__restrict__ Bh,
+                                                const unsigned short *__restrict__ Bl,
+                                                unsigned short *sl, int64_t rb,
+                                                f32x4_t (&acc)[4]) {
+  const int lane = threadIdx.x & 63;
+  // load lane: column lc (+ 8 r), rows rb + lr .. + 7
+  const int lc = lane >> 3, lr = (lane & 7) * 8;
+  u32x4 buf[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = k0 + lc + 8 * r;
+      if constexpr (FULL) {
+        const int kc = k < J ? k : J - 1;
+        buf[r] = vraw_nt(W + (int64_t)kc * ldw + rb + lr);
+      } else {
+        const ST *src = W + (int64_t)k * ldw + rb + lr;
+        unsigned short e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          e[q] = (k < J && rb + lr + q < n) ? __builtin_bit_cast(unsigned short, src[q]) : 0;
+        buf[r] = u32x4{(uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2] | ((uint32_t)e[3] << 16),
+                       (uint32_t)e[4] | ((uint32_t)e[5] << 16), (uint32_t)e[6] | ((uint32_t)e[7] << 16)};
+      }
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < J; k0 += PM_KC) {
+    // transpose the chunk into this wave's LDS slice: column k at sl[k * PM_RS + row]
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      *reinterpret_cast<u32x4 *>(sl + (lc + 8 * r) * PM_RS + lr) = buf[r];
+    // this chunk's coefficients, loaded before the next chunk's columns so
+    // that waiting for them does not wait for those (loads complete in order)
+    uint2 bh[PM_KC / 16], bl[PM_KC / 16];
+#pragma unroll
+    for (int kk = 0; kk < PM_KC / 16; ++kk) {
+      const int g = (k0 >> 2) + kk * 4 + (lane >> 4);  // column group of this lane
+      bh[kk] = *reinterpret_cast<const uint2 *>(Bh + ((g * 16 + (lane & 15)) << 2));
+      bl[kk] = *reinterpret_cast<const uint2 *>(Bl + ((g * 16 + (lane & 15)) << 2));
+    }
+    // next chunk's columns, in flight during the products (FULL: always, with
+    // clamped columns after the last chunk, so the loop has no branch and the
+    // waits for the coefficients count the prefetch exactly)
+    if (FULL || k0 + PM_KC < J) fetch(k0 + PM_KC);
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
+#pragma unroll
+    for (int kk = 0; kk < PM_KC / 16; ++kk) {
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        unsigned short a[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          a[t] = sl[(kk * 16 + 4 * (lane >> 4) + t) * PM_RS + mb * 16 + (lane & 15)];
+        acc[mb] = mfma16<ST>(a, bh[kk], acc[mb]);
+        acc[mb] = mfma16<ST>(a, bl[kk], acc[mb]);
+      }
+    }
+  }
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(PM_WAVES * 64) k_panel_mfma(
+    ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m, int32_t J, int32_t nb,
+    const unsigned short *__restrict__ Bh, const unsigned short *__restrict__ Bl,
+    const float *__restrict__ scale, int aligned) {
+  __shared__ unsigned short lds[PM_WAVES][PM_KC * PM_RS];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t mb0 = m - (m % 8);
+  const int64_t rb = mb0 + ((int64_t)blockIdx.x * PM_WAVES + w) * PM_ROWS;  // wave's first row
+  if (rb >= n) return;  // whole wave beyond the last row (uniform)
+  const bool full = aligned && rb + PM_ROWS <= n;
+  f32x4_t acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  if (full)
+    panel_mfma_wave<ST, true>(W, ldw, n, J, Bh, Bl, lds[w], rb, acc);
+  else
+    panel_mfma_wave<ST, false>(W, ldw, n, J, Bh, Bl, lds[w], rb, acc);
+  // acc[mb][t] = (U C / s)[row rb + 16 mb + 4 (lane / 16) + t][panel column lane % 16]
+  const int j = lane & 15;
+  if (j >= nb) return;
+  const float sj = scale[j];
+  ST *col = W + (int64_t)(J + j) * ldw;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const int64_t r0 = rb + mb * 16 + 4 * (lane >> 4);
+    if (full && r0 >= m) {
+      const uint2 old = *reinterpret_cast<const uint2 *>(col + r0);
+      const uint32_t wd[2] = {old.x, old.y};
+      uint32_t nw[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float x0 = dec16<ST>((unsigned short)(wd[h] & 0xffff)) - sj * acc[mb][2 * h];
+        const float x1 = dec16<ST>((unsigned short)(wd[h] >> 16)) - sj * acc[mb][2 * h + 1];
+        nw[h] = (uint32_t)enc16<ST>(x0) | ((uint32_t)enc16<ST>(x1) << 16);
+      }
+      *reinterpret_cast<uint2 *>(col + r0) = uint2{nw[0], nw[1]};
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t r = r0 + t;
+        if (r >= m && r < n)
+          col[r] = cvt_out<ST>((double)(cvt_in<float>(col[r]) - sj * acc[mb][t]));
+      }
+    }
+  }
+}
+
 inline int panel_width(int nb) { return nb <= 8 ? 8 : nb <= 16 ? 16 : 32; }
 
 template <typename ST, int NBC>
@@ -472,9 +672,13 @@ void launch_panel(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t J, int32_t n
     launch_panel_w<ST, 32>(W, ldw, n, m, J, nb, C, aligned, grid, st, e0, e1);
 }
 
+// 2-byte storage with panels of at most 16 columns: the panel update runs on
+// matrix cores (k_panel_mfma); otherwise on the vector units (k_panel)
+template <typename ST> constexpr bool panel_on_mfma() { return sizeof(ST) == 2; }
+
 template <typename ST>
 int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, double *C, double *G,
-                      hipStream_t st) {
+                      void *mf, hipStream_t st) {
   ST *W = (ST *)a.W;
   const int32_t m = a.m, L = a.l + a.m;
   const int64_t ntail = a.n - m;
@@ -498,7 +702,30 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, double *C, 
       if (ntail > 0) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (g_prof.on && prof_pair(&e0, &e1, 1)) return RHQR_ERR_HIP;
-        launch_panel<ST>(W, a.ldw, a.n, m, J, nb, (const double *)C, st, e0, e1);
+        bool on_mfma = false;
+        if constexpr (panel_on_mfma<ST>()) on_mfma = nb <= 16;
+        if constexpr (panel_on_mfma<ST>()) if (on_mfma) {
+          const int Kp = (J + PM_KC - 1) / PM_KC * PM_KC;
+          unsigned short *Bh = (unsigned short *)mf;
+          unsigned short *Bl = Bh + (size_t)Kp * 16;
+          float *sc = (float *)(Bl + (size_t)Kp * 16);
+          hipLaunchKernelGGL((k_pconv<ST>), dim3(1), dim3(1024), 0, st, J, nb, pw, Kp,
+                             (const double *)C, Bh, Bl, sc);
+          RHQR_HIP(hipGetLastError());
+          const int64_t mb0 = m - (m % 8);
+          const int64_t waves = (a.n - mb0 + PM_ROWS - 1) / PM_ROWS;
+          const dim3 grid((unsigned)((waves + PM_WAVES - 1) / PM_WAVES));
+          const int aligned = ((uintptr_t)W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
+          if (e0)
+            hipExtLaunchKernelGGL((k_panel_mfma<ST>), grid, dim3(PM_WAVES * 64), 0, st, e0, e1, 0,
+                                  W, a.ldw, a.n, m, J, nb, (const unsigned short *)Bh,
+                                  (const unsigned short *)Bl, (const float *)sc, aligned);
+          else
+            hipLaunchKernelGGL((k_panel_mfma<ST>), grid, dim3(PM_WAVES * 64), 0, st, W, a.ldw,
+                               a.n, m, J, nb, (const unsigned short *)Bh,
+                               (const unsigned short *)Bl, (const float *)sc, aligned);
+        }
+        if (!on_mfma) launch_panel<ST>(W, a.ldw, a.n, m, J, nb, (const double *)C, st, e0, e1);
         RHQR_HIP(hipGetLastError());
       }
     }
@@ -652,10 +879,15 @@ int engine_tall(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st) {
   RHQR_DISPATCH(a.dtype, tall_typed<ST>(a, w, j, 0, st))
 }
 
+size_t panel_mfma_bytes(int32_t m) {
+  const size_t Kp = (size_t)(m + PM_KC - 1) / PM_KC * PM_KC;
+  return align_up(2 * Kp * 16 * sizeof(unsigned short) + 16 * sizeof(float));
+}
+
 int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, double *C, double *G,
-                            hipStream_t st) {
+                            void *mf, hipStream_t st) {
   if (a.m > MAXM) return RHQR_ERR_UNSUPPORTED;
-  RHQR_DISPATCH(a.dtype, run_blocked_typed<ST>(a, w, panel, C, G, st))
+  RHQR_DISPATCH(a.dtype, run_blocked_typed<ST>(a, w, panel, C, G, mf, st))
 }
 
 int engine_step(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st) {

@@ -91,7 +91,7 @@ def test_c1_ill_conditioned(panel):
     assert np.linalg.norm(g["R"] - ref["R"]) <= 1e-12 * np.linalg.norm(ref["R"]) * 1e4
 
 
-@pytest.mark.parametrize("panel", [0, 8])
+@pytest.mark.parametrize("panel", [0, 8, 16])
 @pytest.mark.parametrize("dt,tol", [("float32", 1e-5), ("float16", 1e-2), ("bfloat16", 1e-2)])
 def test_low_precision_bounds(dt, tol, panel):
     n, m, l = 3 * 4096 + 77, 24, 96
