@@ -296,6 +296,105 @@ def run_batched(rhqr, torch, count, steps, warmup, dtype_name="float32"):
                                   "e_orth": eo}}
 
 
+def _time(torch, fn, steps, warmup, before=None):
+    """Mean ms of fn() over ``steps`` runs bracketed by CUDA events, after
+    ``warmup`` runs; ``before`` (untimed) runs ahead of every call."""
+    import numpy as np
+    for _ in range(warmup):
+        if before:
+            before()
+        fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(steps):
+        if before:
+            before()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        out.append((e0, e1))
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in out]))
+
+
+def run_thin_q(rhqr, torch, sk, W64, m, steps):
+    """Thin Q = [I; 0] - U T U_1^t (Sec. 3.2) after a float64 factorization:
+    time of the factorization with Q minus the time without."""
+    W = torch.empty_like(W64.t()).t()
+    bq = rhqr.FactorBuffers(sk, torch.float64, m, want_q=True)
+    restore = lambda: W.copy_(W64)
+    t_q = _time(torch, lambda: rhqr.factor(sk, W, want_q=True, bufs=bq, panel=16), steps, 1, restore)
+    t_n = _time(torch, lambda: rhqr.factor(sk, W, want_q=False, bufs=bq, panel=16), steps, 1, restore)
+    n = W64.shape[0]
+    ms = t_q - t_n
+    byts = 2 * 8 * (n - m) * m
+    flops = 2.0 * (n - m) * m * m
+    del W, bq
+    torch.cuda.empty_cache()
+    return {"workload": f"Q of a {n} x {m} float64 factorization", "ms": round(ms, 3),
+            "GBps": round(byts / (ms * 1e-3) / 1e9, 1), "TFLOPs": round(flops / (ms * 1e-3) / 1e12, 2),
+            "bound": "fp64 (AI = m/8 flop/B)", "frac_fp64_peak": round(flops / (ms * 1e-3) / 78.6e12, 4)}
+
+
+def run_c2(rhqr, torch, steps):
+    """2^20 x 128, cond 1e12, float64: RHQR with the SRHT and the Gaussian
+    sketch (l = 512, blocked schedule) and recRHQR (SRHT)."""
+    from paper_2405_10923_amd.inputs import synthetic_matrix_torch
+    n, m, l = 1 << 20, 128, 512
+    W0 = synthetic_matrix_torch(n, m, 12, seed=0, device="cuda")
+    W = torch.empty_like(W0.t()).t()
+    restore = lambda: W.copy_(W0)
+    out = {"workload": f"W {n} x {m} cond 1e12 float64, l = {l}"}
+    for kind, name in ((rhqr.SRHT, "rhqr_srht"), (rhqr.GAUSS, "rhqr_gauss")):
+        sk = rhqr.Sketch(kind, n, m, l, seed=0)
+        bufs = rhqr.FactorBuffers(sk, torch.float64, m)
+        ms = _time(torch, lambda: rhqr.factor(sk, W, bufs=bufs, panel=16), steps, 1, restore)
+        ent = {"ms": round(ms, 3), "GBps_alg": round(b_alg(n, m, 8) / (ms * 1e-3) / 1e9, 1)}
+        if kind == rhqr.GAUSS:
+            # the Gaussian sketch re-reads Omega (l x (n-m) float64) in every column's pass
+            ent["omega_bytes_per_column"] = 8 * l * (n - m)
+            Y = torch.empty((m, l + m), dtype=torch.float64, device="cuda").t()
+            ws = rhqr.workspace(rhqr.lib().rhqr_sketch_workspace_size(sk.h, m), "cuda")
+            msk = _time(torch, lambda: rhqr.sketch(sk, W0, Y, ws), steps, 1)
+            fl = 2.0 * l * (n - m) * m
+            ent["presketch_ms"] = round(msk, 3)
+            ent["presketch_TFLOPs"] = round(fl / (msk * 1e-3) / 1e12, 2)
+            del Y, ws
+        out[name] = ent
+        del bufs, sk
+        torch.cuda.empty_cache()
+    sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=0)
+    ms = _time(torch, lambda: rhqr.recrhqr(sk, W0, want_q=False), steps, 1)
+    out["recrhqr_srht"] = {"ms": round(ms, 3),
+                           "GBps": round(8.0 * 3 * (n - m) * m / (ms * 1e-3) / 1e9, 1),
+                           "bytes": "sketch read + W_2 read + U_2 write"}
+    del W, W0, sk
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_gmres_c5(rhqr, torch, max_cycles=200):
+    """RHQR-GMRES(100) on the 2048 x 2048 convection-diffusion operator (CSR
+    float64), rhs of ones, SRHT l = 400, float32 basis, to 1e-6."""
+    import numpy as np
+    from paper_2405_10923_amd.inputs import convdiff_csr
+    ptr, idx, val, n = convdiff_csr(2048)
+    A = rhqr.CSR(ptr, idx, val, n)
+    sk = rhqr.Sketch(rhqr.SRHT, n, 101, 400, seed=0)
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, hist, steps = rhqr.gmres(A, b, sk, 100, torch.float32, tol=1e-6, max_cycles=max_cycles)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": f"convection-diffusion 2048^2 (n = {n}), GMRES(100), SRHT l = 400, float32 basis",
+            "cycles": len(hist), "arnoldi_steps": steps, "final_rel_residual": hist[-1],
+            "seconds": round(dt, 3), "ms_per_cycle": round(1000 * dt / len(hist), 2),
+            "converged": bool(hist[-1] <= 1e-6)}
+
+
 def to_colmajor_dt(A, dt):
     import torch
     out = torch.empty((A.shape[1], A.shape[0]), dtype=dt, device=A.device).t()
@@ -319,6 +418,8 @@ def main():
                     help="skip the column-by-column float64 reference schedule")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=32)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the secondary measurements (thin Q, 2^20 x 128, GMRES)")
     ap.add_argument("--batch-count", type=int, default=512,
                     help="problems of the batched float32 workload (0: skip it)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
@@ -375,6 +476,10 @@ def main():
               f"{column['GBps_alg']:.0f} GB/s(alg) = {column['hbm_frac_alg']:.1%} of HBM",
               file=sys.stderr, flush=True)
 
+    extra = None
+    if not args.no_extra:
+        extra = {"thin_q_f64": run_thin_q(rhqr, torch, sk, W64, m, max(2, args.steps // 2))}
+        print(f"# thin Q float64: {extra['thin_q_f64']['ms']:.2f} ms", file=sys.stderr, flush=True)
     batched = None
     if args.batch_count > 0:
         del W64
@@ -384,6 +489,13 @@ def main():
               f"{batched['GBps_alg']:.0f} GB/s(alg) = {batched['hbm_frac_alg']:.1%} of HBM, "
               f"largest-m e_fact {batched['largest_m_problem']['e_fact']:.2e}",
               file=sys.stderr, flush=True)
+
+    if extra is not None:
+        torch.cuda.empty_cache()
+        extra["c2_f64"] = run_c2(rhqr, torch, max(2, args.steps // 2))
+        print(f"# 2^20 x 128: {json.dumps(extra['c2_f64'])}", file=sys.stderr, flush=True)
+        extra["gmres_c5"] = run_gmres_c5(rhqr, torch)
+        print(f"# GMRES c5: {json.dumps(extra['gmres_c5'])}", file=sys.stderr, flush=True)
 
     f64 = res.get("float64")
     mixed = {}
@@ -423,6 +535,8 @@ def main():
         line["column_by_column_f64"] = column
     if batched is not None:
         line["batched_f32"] = batched
+    if extra is not None:
+        line["secondary"] = extra
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n, l, kappa, args.cpu_cols)
     print(json.dumps(line), flush=True)
