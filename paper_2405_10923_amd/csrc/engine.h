@@ -96,5 +96,14 @@ int launch_thin_q(int dtype, int64_t n, int32_t m, const void *U, int64_t ldu, c
                   int64_t lds, const double *T, int64_t ldt, double *Mq, void *Q, int64_t ldq,
                   hipStream_t st);
 int launch_fill(void *p, size_t bytes, hipStream_t st);
+// X M = B for `rows` rows (B, X n-row data in dtype, column-major; M upper
+// triangular m x m float64): blocked forward substitution (recRHQR, Alg. 6).
+// coef: trsm_coef_bytes(m) bytes of scratch; stage: trsm_stage_bytes(...)
+// bytes (a float32 copy of X, 2-byte types only; may be NULL otherwise).
+size_t trsm_coef_bytes(int32_t m);
+size_t trsm_stage_bytes(int dtype, int64_t rows, int32_t m);
+int launch_trsm_blocked(int dtype, const void *B, int64_t ldb, int64_t rows, int32_t m,
+                        const double *M, int64_t ldm, void *X, int64_t ldx, double *coef,
+                        float *stage, hipStream_t st);
 
 constexpr int RED_CHUNK = 64;  // outputs per reduction workgroup

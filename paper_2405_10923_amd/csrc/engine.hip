@@ -443,6 +443,160 @@ __global__ void __launch_bounds__(PANEL_TPB) k_panel(ST *__restrict__ W, int64_t
   }
 }
 
+// --------------------------------------------------------- blocked TRSM
+// X M = B for n-row B, X (column-major, storage type) and M upper triangular
+// (float64), in column blocks of TRSM_NB: for the block starting at J,
+//   X_{:, J:J+nb} = (B_{:, J:J+nb} - X_{:, <J} M_{<J, J:J+nb}) M_{J:J+nb, J:J+nb}^{-1}.
+// One launch per block: the product streams the solved columns X_{:, <J}
+// exactly as the panel update does (eight column loads in flight), then every
+// row solves its nb x nb triangle by forward substitution in registers and
+// the block is written once.  Rows are independent, so each row's result is
+// its own substitution, in float64 (float32 for low precision).
+constexpr int TRSM_NB = 16;
+
+// Ct[k * 16 + c] = M[k, J + c] (k < J), Md[p * 16 + c] = M[J + p, J + c]
+// (upper triangle of the diagonal block); zero padding beyond nb, ones on the
+// padded diagonal.
+__global__ void k_trsm_coef(int32_t J, int32_t nb, const double *__restrict__ M, int64_t ldm,
+                            double *__restrict__ Ct, double *__restrict__ Md) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (k < J) Ct[(int64_t)k * TRSM_NB + c] = c < nb ? M[k + (int64_t)(J + c) * ldm] : 0.0;
+  if (k < TRSM_NB) {
+    double v = 0.0;
+    if (k < nb && c < nb && k <= c) v = M[J + k + (int64_t)(J + c) * ldm];
+    if (k == c && c >= nb) v = 1.0;
+    Md[k * TRSM_NB + c] = v;
+  }
+}
+
+// 2-byte storage: the solved columns are also kept in a float32 copy (stage,
+// ld = rows) and the product reads that copy, so the substitution carries
+// float32 unknowns from block to block as it does inside a block.
+template <typename ST>
+__global__ void __launch_bounds__(PANEL_TPB) k_trsm_blk(const ST *__restrict__ B, int64_t ldb,
+                                                        ST *__restrict__ X, int64_t ldx,
+                                                        float *__restrict__ stage,
+                                                        int64_t rows, int32_t J, int32_t nb,
+                                                        const double *__restrict__ Ct,
+                                                        const double *__restrict__ Md,
+                                                        int aligned) {
+  using CT = typename CompT<ST>::type;
+  constexpr bool STG = sizeof(ST) == 2;
+  using LT = typename std::conditional<STG, float, ST>::type;  // type the product reads
+  constexpr int VEC = sizeof(ST) == 8 ? 2 : 4;
+  const int64_t lsg = (rows + 3) & ~(int64_t)3;  // leading dimension of the float32 copy
+  const LT *Xr = STG ? (const LT *)stage : (const LT *)X;
+  const int64_t ldr = STG ? lsg : ldx;
+  constexpr int NBC = TRSM_NB;
+  const int64_t rb = (int64_t)blockIdx.x * PANEL_TPB * VEC;
+  const int64_t r0 = rb + (int64_t)threadIdx.x * VEC;
+  if (r0 >= rows) return;
+  const bool fast = aligned && rb + (int64_t)PANEL_TPB * VEC <= rows;  // uniform
+  const uint32_t off = (uint32_t)(threadIdx.x * VEC * sizeof(ST));
+  CT acc[VEC][NBC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e)
+#pragma unroll
+    for (int c = 0; c < NBC; ++c) acc[e][c] = (CT)0;
+  auto coef = [&](int k, int c) -> CT { return (CT)Ct[(int64_t)k * NBC + c]; };
+  const uint32_t offr = (uint32_t)(threadIdx.x * VEC * sizeof(LT));
+  if (fast) {
+    int k = 0;
+    for (; k + PANEL_KB <= J; k += PANEL_KB) {
+      CT xs[PANEL_KB][VEC];
+#pragma unroll
+      for (int u = 0; u < PANEL_KB; ++u) {
+        const char *cb = (const char *)(Xr + (int64_t)(k + u) * ldr + rb);  // uniform
+        panel_load<LT, CT, VEC>((const LT *)(cb + offr), xs[u]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < PANEL_KB; ++u)
+#pragma unroll
+        for (int c = 0; c < NBC; ++c) {
+          const CT ck = coef(k + u, c);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[e][c] += xs[u][e] * ck;
+        }
+    }
+    for (; k < J; ++k) {
+      const char *cb = (const char *)(Xr + (int64_t)k * ldr + rb);
+      CT xv[VEC];
+      panel_load<LT, CT, VEC>((const LT *)(cb + offr), xv);
+#pragma unroll
+      for (int c = 0; c < NBC; ++c) {
+        const CT ck = coef(k, c);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e][c] += xv[e] * ck;
+      }
+    }
+  } else {
+    for (int k = 0; k < J; ++k) {
+      const LT *col = Xr + (int64_t)k * ldr + r0;
+      CT xv[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) xv[e] = r0 + e < rows ? cvt_in<CT>(col[e]) : (CT)0;
+#pragma unroll
+      for (int c = 0; c < NBC; ++c) {
+        const CT ck = coef(k, c);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e][c] += xv[e] * ck;
+      }
+    }
+  }
+  // right-hand side of the block, then the block's forward substitution
+#pragma unroll
+  for (int c = 0; c < NBC; ++c) {
+    if (c < nb) {
+      const ST *bc = B + (int64_t)(J + c) * ldb + r0;
+      CT bv[VEC];
+      if (fast) {
+        panel_load<ST, CT, VEC>(bc, bv);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) bv[e] = r0 + e < rows ? cvt_in<CT>(bc[e]) : (CT)0;
+      }
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e][c] = bv[e] - acc[e][c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NBC; ++c) {
+#pragma unroll
+    for (int p = 0; p < c; ++p) {
+      const CT mpc = (CT)Md[p * NBC + c];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e][c] -= acc[e][p] * mpc;
+    }
+    const CT d = (CT)Md[c * NBC + c];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e][c] = acc[e][c] / d;
+  }
+#pragma unroll
+  for (int c = 0; c < NBC; ++c) {
+    if (c < nb) {
+      ST *xc = X + (int64_t)(J + c) * ldx + r0;
+      CT xv[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) xv[e] = acc[e][c];
+      if (fast) {
+        panel_store<ST, CT, VEC>(xc, xv);
+        if constexpr (STG)
+          *reinterpret_cast<float4 *>(stage + (int64_t)(J + c) * lsg + r0) =
+              make_float4(xv[0], xv[1], xv[2], xv[3]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (r0 + e < rows) {
+            xc[e] = cvt_out<ST>((double)xv[e]);
+            if constexpr (STG) stage[(int64_t)(J + c) * lsg + r0 + e] = (float)xv[e];
+          }
+      }
+    }
+  }
+}
+
 // ------------------------------------------- panel update on matrix cores
 // 2-byte storage, nb <= 16: W[m:n, J:J+nb] -= U[m:n, 0:J] C on float32 MFMA
 // (v_mfma_f32_16x16x16 f16 / bf16).  C (float64) is scaled per column by a
@@ -759,7 +913,59 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
   return RHQR_OK;
 }
 
+template <typename ST>
+int trsm_blocked_typed(const ST *B, int64_t ldb, int64_t rows, int32_t m, const double *M,
+                       int64_t ldm, ST *X, int64_t ldx, double *coef, float *stage,
+                       hipStream_t st) {
+  if (rows <= 0) return RHQR_OK;
+  constexpr int VEC = sizeof(ST) == 8 ? 2 : 4;
+  if (sizeof(ST) == 2 && !stage) return RHQR_ERR_WORKSPACE;
+  const int aligned = ((uintptr_t)B % 16 == 0) && ((uintptr_t)X % 16 == 0) &&
+                      ((ldb * (int64_t)sizeof(ST)) % 16 == 0) &&
+                      ((ldx * (int64_t)sizeof(ST)) % 16 == 0) &&
+                      (sizeof(ST) != 2 || (uintptr_t)stage % 16 == 0);
+  double *Ct = coef, *Md = coef + (size_t)m * TRSM_NB;
+  const dim3 grid((unsigned)((rows + (int64_t)PANEL_TPB * VEC - 1) / ((int64_t)PANEL_TPB * VEC)));
+  for (int32_t J = 0; J < m; J += TRSM_NB) {
+    const int32_t nb = m - J < TRSM_NB ? m - J : TRSM_NB;
+    const int kmax = J > TRSM_NB ? J : TRSM_NB;
+    hipLaunchKernelGGL(k_trsm_coef, dim3((kmax + 255) / 256, TRSM_NB), dim3(256), 0, st, J, nb, M,
+                       ldm, Ct, Md);
+    RHQR_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_trsm_blk<ST>), grid, dim3(PANEL_TPB), 0, st, B, ldb, X, ldx, stage, rows,
+                       J, nb, (const double *)Ct, (const double *)Md, aligned);
+    RHQR_HIP(hipGetLastError());
+  }
+  return RHQR_OK;
+}
+
 }  // namespace
+
+size_t trsm_coef_bytes(int32_t m) { return align_up(sizeof(double) * ((size_t)m * TRSM_NB + 256)); }
+
+size_t trsm_stage_bytes(int dtype, int64_t rows, int32_t m) {
+  return dtype_size(dtype) == 2 ? align_up(sizeof(float) * (size_t)((rows + 3) & ~(int64_t)3) * m) : 0;
+}
+
+int launch_trsm_blocked(int dtype, const void *B, int64_t ldb, int64_t rows, int32_t m,
+                        const double *M, int64_t ldm, void *X, int64_t ldx, double *coef,
+                        float *stage, hipStream_t st) {
+  switch (dtype) {
+    case RHQR_F64:
+      return trsm_blocked_typed<double>((const double *)B, ldb, rows, m, M, ldm, (double *)X, ldx,
+                                        coef, stage, st);
+    case RHQR_F32:
+      return trsm_blocked_typed<float>((const float *)B, ldb, rows, m, M, ldm, (float *)X, ldx,
+                                       coef, stage, st);
+    case RHQR_F16:
+      return trsm_blocked_typed<__half>((const __half *)B, ldb, rows, m, M, ldm, (__half *)X, ldx,
+                                        coef, stage, st);
+    case RHQR_BF16:
+      return trsm_blocked_typed<__hip_bfloat16>((const __hip_bfloat16 *)B, ldb, rows, m, M, ldm,
+                                                (__hip_bfloat16 *)X, ldx, coef, stage, st);
+  }
+  return RHQR_ERR_UNSUPPORTED;
+}
 
 ColProblem make_col_problem(const LoopArgs &a, const LoopWs &w, int tpw) {
   ColProblem P;
