@@ -204,7 +204,9 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
  *     dimensions), lays the descriptors and per-problem scratch out in the
  *     caller's workspace d_ws (kept by the batch until rhqr_batch_destroy: the
  *     caller must keep it alive), uploads them on `stream` and synchronises.
- *     opts: bits 0-7 rhqr_scaling; other bits must be 0 (column schedule).
+ *     opts: bits 0-7 rhqr_scaling; bits 8-15 panel width: 0 (column
+ *     schedule) or 16 (blocked schedule as in rhqr_factor, the panel update
+ *     on the vector units); other bits 0.
  *     Returns -1 for an invalid problem array, -3 bad dtype, -4 bad opts,
  *     -5 null workspace, RHQR_ERR_WORKSPACE if ws_bytes is too small.
  *   rhqr_batch_factor: factors every problem of the batch.  The work is a
@@ -214,7 +216,9 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
  *     m_p > j.  use_graph != 0: the sequence is captured once into a hipGraph
  *     (on the batch's own stream) and the graph is launched on `stream`; later
  *     calls replay it.  Each problem's U, S, T, R equal those of rhqr_factor
- *     with the column schedule (same device code, same reduction orders).
+ *     with the same schedule (same device code, same reduction orders;
+ *     except 2-byte storage with panels, whose single-problem panel update
+ *     runs on matrix cores).
  *   rhqr_batch_status: h_info[i] (host, count entries, caller order) = the
  *     first column of problem i with rho_j = 0 (1-based), or 0.  Synchronous.
  * Not in the paper as such: the paper factors one matrix at a time; the batch

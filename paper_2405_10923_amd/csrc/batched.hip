@@ -70,9 +70,10 @@ constexpr int BATCH_TPB = 256;
 
 template <typename ST, int TPW>
 __global__ void __launch_bounds__(BATCH_TPB) kb_tall(const ColProblem *__restrict__ P,
-                                                     const BlockMap *__restrict__ map, int32_t j) {
+                                                     const BlockMap *__restrict__ map, int32_t j,
+                                                     int32_t p0) {
   const BlockMap b = map[blockIdx.x];
-  tall_block<ST, RHQR_SKETCH_SRHT, TPW, BATCH_TPB>(P[b.p], j, 0, b.local);
+  tall_block<ST, RHQR_SKETCH_SRHT, TPW, BATCH_TPB>(P[b.p], j, p0, b.local);
 }
 
 template <typename ST>
@@ -87,6 +88,52 @@ __global__ void __launch_bounds__(1024) kb_fin(const ColProblem *__restrict__ P,
   const int p = blockIdx.x / fg, local = blockIdx.x % fg;
   const ColProblem &Q = P[p];
   fin_block(Q, j, j + 1 < Q.m, local, fg);
+}
+
+// ---- blocked schedule (panels of BATCH_PB columns), per problem as in the
+// single-problem path: store u_{J-1}, G = S_{<J}^t Z_panel, C = T^t G, then
+// W_panel -= U_{<J} C.
+constexpr int BATCH_PB = 16;
+constexpr int SCALE_CH = 64;  // workgroups per problem in kb_scale_col
+
+template <typename ST>
+__global__ void kb_scale_col(const ColProblem *__restrict__ P, int32_t cidx) {
+  const ColProblem &Q = P[blockIdx.x];
+  ST *col = (ST *)Q.W + (int64_t)cidx * Q.ldw;
+  const double a = Q.ia[cidx];
+  const int64_t stride = (int64_t)gridDim.y * blockDim.x;
+  for (int64_t i = Q.m + (int64_t)blockIdx.y * blockDim.x + threadIdx.x; i < Q.n; i += stride) {
+    double raw;
+    if constexpr (std::is_same<ST, double>::value)
+      raw = col[i];
+    else
+      raw = cidx >= 1 ? (double)Q.wstage[i] : cvt_in<double>(col[i]);
+    col[i] = cvt_out<ST>(raw * a);
+  }
+}
+
+__global__ void __launch_bounds__(1024) kb_pgram(const ColProblem *__restrict__ P, int32_t J,
+                                                 int per) {
+  const int p = blockIdx.x / per, local = blockIdx.x % per;
+  const ColProblem &Q = P[p];
+  const int32_t nb = Q.m - J < BATCH_PB ? Q.m - J : BATCH_PB;
+  pgram_block(Q.l + Q.m, J, nb, Q.S, Q.lds, Q.Z, Q.ldz, Q.G, local);
+}
+
+__global__ void kb_ptri(const ColProblem *__restrict__ P, int32_t J, int per) {
+  const int p = blockIdx.x / per, local = blockIdx.x % per;
+  const ColProblem &Q = P[p];
+  const int32_t nb = Q.m - J < BATCH_PB ? Q.m - J : BATCH_PB;
+  ptri_entry(J, nb, BATCH_PB, Q.T, Q.ldt, Q.G, Q.C, local * blockDim.x + threadIdx.x, blockIdx.y);
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(PANEL_TPB) kb_panel(const ColProblem *__restrict__ P,
+                                                      const BlockMap *__restrict__ map, int32_t J) {
+  const BlockMap b = map[blockIdx.x];
+  const ColProblem &Q = P[b.p];
+  const int32_t nb = Q.m - J < BATCH_PB ? Q.m - J : BATCH_PB;
+  panel_block<ST, BATCH_PB>((ST *)Q.W, Q.ldw, Q.n, Q.m, J, nb, Q.C, Q.aligned, b.local);
 }
 
 // last column stored as u = raw / alpha, head block of U written from S
@@ -121,12 +168,13 @@ inline int batch_tpw(int dtype) { return dtype_size(dtype) == 2 ? 2 : 1; }
 struct Layout {
   // sorted order and per-problem geometry
   std::vector<int32_t> order;
-  std::vector<int64_t> nparts, gred, gt, ngroups;
+  std::vector<int64_t> nparts, gred, gt, ngroups, npanel;
   // prefix sums over the sorted problems
-  std::vector<int64_t> tall_start, red_start, sk_start, col_start;
+  std::vector<int64_t> tall_start, red_start, sk_start, col_start, pan_start;
   size_t head_bytes = 0, total = 0;
   std::vector<size_t> off;  // per sorted problem: start of its region
-  size_t off_probs = 0, off_jobs = 0, off_tall = 0, off_red = 0, off_sk = 0, off_col = 0;
+  size_t off_probs = 0, off_jobs = 0, off_tall = 0, off_red = 0, off_sk = 0, off_col = 0,
+         off_pan = 0;
 };
 
 size_t problem_bytes(const rhqr_sketch_s *h, int dtype) {
@@ -135,7 +183,15 @@ size_t problem_bytes(const rhqr_sketch_s *h, int dtype) {
   size_t skb;
   sketch_tail_partials_size(h, m, &gt, &skb);
   return align_up(loop_ws_bytes(h->kind, dtype, h->n, m, h->l)) +
-         align_up(sizeof(double) * (size_t)L * m) + align_up(skb);
+         align_up(sizeof(double) * (size_t)L * m) + align_up(skb) +
+         2 * align_up(sizeof(double) * (size_t)m * BATCH_PB);
+}
+
+// panel-update workgroups of one problem (rows from m rounded down to VEC)
+int64_t panel_groups(int64_t n, int32_t m, int dtype) {
+  const int vec = dtype_size(dtype) == 8 ? 2 : 4;
+  const int64_t mb0 = m - (m % vec);
+  return (n - mb0 + (int64_t)PANEL_TPB * vec - 1) / ((int64_t)PANEL_TPB * vec);
 }
 
 int plan(const rhqr_problem *probs, int32_t count, int dtype, Layout *o) {
@@ -149,6 +205,8 @@ int plan(const rhqr_problem *probs, int32_t count, int dtype, Layout *o) {
   o->gred.resize(count);
   o->gt.resize(count);
   o->ngroups.resize(count);
+  o->npanel.resize(count);
+  o->pan_start.assign(count + 1, 0);
   o->tall_start.assign(count + 1, 0);
   o->red_start.assign(count + 1, 0);
   o->sk_start.assign(count + 1, 0);
@@ -166,8 +224,12 @@ int plan(const rhqr_problem *probs, int32_t count, int dtype, Layout *o) {
     o->red_start[s + 1] = o->red_start[s] + o->gred[s];
     o->sk_start[s + 1] = o->sk_start[s] + (int64_t)h->m * gt;
     o->col_start[s + 1] = o->col_start[s] + h->m;
+    o->npanel[s] = panel_groups(h->n, h->m, dtype);
+    o->pan_start[s + 1] = o->pan_start[s] + o->npanel[s];
   }
-  if (o->tall_start[count] > INT32_MAX || o->sk_start[count] > INT32_MAX) return RHQR_ERR_UNSUPPORTED;
+  if (o->tall_start[count] > INT32_MAX || o->sk_start[count] > INT32_MAX ||
+      o->pan_start[count] > INT32_MAX)
+    return RHQR_ERR_UNSUPPORTED;
   size_t b = 0;
   auto take = [&](size_t bytes) {
     const size_t r = b;
@@ -180,6 +242,7 @@ int plan(const rhqr_problem *probs, int32_t count, int dtype, Layout *o) {
   o->off_red = take(sizeof(BlockMap) * o->red_start[count]);
   o->off_sk = take(sizeof(BlockMap) * o->sk_start[count]);
   o->off_col = take(sizeof(BlockMap) * o->col_start[count]);
+  o->off_pan = take(sizeof(BlockMap) * o->pan_start[count]);
   o->head_bytes = b;
   o->off.resize(count);
   for (int s = 0; s < count; ++s) o->off[s] = take(problem_bytes(probs[o->order[s]].sketch, dtype));
@@ -207,14 +270,16 @@ int check_problems(const rhqr_problem *probs, int32_t count, int dtype) {
 
 struct rhqr_batch_s {
   int dtype = 0, count = 0, maxm = 0, tpw = 1, qa = 1, maxL = 0;
+  int panel = 0;                  // 0: column schedule, BATCH_PB: blocked
   std::vector<int32_t> order;     // sorted position -> caller index
   std::vector<int32_t> ms;        // m of each sorted problem (decreasing)
-  std::vector<int64_t> tall_start, red_start;
+  std::vector<int64_t> tall_start, red_start, pan_start;
   int64_t sk_blocks = 0, cols = 0;
   std::vector<ColProblem> hp;     // host copy of the descriptors (sorted)
   ColProblem *d_probs = nullptr;
   SketchJob *d_jobs = nullptr;
-  BlockMap *d_tall = nullptr, *d_red = nullptr, *d_sk = nullptr, *d_col = nullptr;
+  BlockMap *d_tall = nullptr, *d_red = nullptr, *d_sk = nullptr, *d_col = nullptr,
+           *d_pan = nullptr;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -247,19 +312,39 @@ int enqueue_typed(rhqr_batch_s *b, hipStream_t st) {
   hipLaunchKernelGGL((kb_sketch_finish<ST>), dim3(b->cols, (b->maxL + 255) / 256), dim3(256), 0, st,
                      b->d_jobs, b->d_col);
   RHQR_HIP(hipGetLastError());
-  for (int32_t j = 0; j < b->maxm; ++j) {
-    const int a = active(b, j);
-    if (j >= 1) {
-      constexpr int TPW = sizeof(ST) == 2 ? 2 : 1;  // = batch_tpw(dtype)
-      hipLaunchKernelGGL((kb_tall<ST, TPW>), dim3(b->tall_start[a]), dim3(BATCH_TPB), 0, st,
-                         b->d_probs, b->d_tall, j);
+  const int pb = b->panel >= 2 ? b->panel : b->maxm;  // column schedule: one panel
+  for (int32_t J = 0; J < b->maxm; J += pb) {
+    if (J > 0) {
+      // store u_{J-1}, then apply the J earlier reflectors to every active panel
+      const int a = active(b, J);
+      hipLaunchKernelGGL((kb_scale_col<ST>), dim3(a, SCALE_CH), dim3(256), 0, st, b->d_probs, J - 1);
+      RHQR_HIP(hipGetLastError());
+      const int pg = (J * BATCH_PB + 15) / 16;
+      hipLaunchKernelGGL(kb_pgram, dim3(a * pg), dim3(1024), 0, st, b->d_probs, J, pg);
+      RHQR_HIP(hipGetLastError());
+      const int pt = (J + 255) / 256;
+      hipLaunchKernelGGL(kb_ptri, dim3(a * pt, BATCH_PB), dim3(256), 0, st, b->d_probs, J, pt);
+      RHQR_HIP(hipGetLastError());
+      hipLaunchKernelGGL((kb_panel<ST>), dim3(b->pan_start[a]), dim3(PANEL_TPB), 0, st, b->d_probs,
+                         b->d_pan, J);
       RHQR_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL((kb_red<ST>), dim3(b->red_start[a]), dim3(256), 0, st, b->d_probs, b->d_red, j);
-    RHQR_HIP(hipGetLastError());
-    const int fg = fin_groups(j);
-    hipLaunchKernelGGL(kb_fin, dim3(a * fg), dim3(1024), 0, st, b->d_probs, j, fg);
-    RHQR_HIP(hipGetLastError());
+    const int32_t jend = J + pb < b->maxm ? J + pb : b->maxm;
+    for (int32_t j = J; j < jend; ++j) {
+      const int a = active(b, j);
+      if (j >= 1) {
+        constexpr int TPW = sizeof(ST) == 2 ? 2 : 1;  // = batch_tpw(dtype)
+        hipLaunchKernelGGL((kb_tall<ST, TPW>), dim3(b->tall_start[a]), dim3(BATCH_TPB), 0, st,
+                           b->d_probs, b->d_tall, j, J);
+        RHQR_HIP(hipGetLastError());
+      }
+      hipLaunchKernelGGL((kb_red<ST>), dim3(b->red_start[a]), dim3(256), 0, st, b->d_probs,
+                         b->d_red, j);
+      RHQR_HIP(hipGetLastError());
+      const int fg = fin_groups(j);
+      hipLaunchKernelGGL(kb_fin, dim3(a * fg), dim3(1024), 0, st, b->d_probs, j, fg);
+      RHQR_HIP(hipGetLastError());
+    }
   }
   hipLaunchKernelGGL((kb_finish<ST>), dim3(b->count, FINISH_CH), dim3(256), 0, st, b->d_probs);
   RHQR_HIP(hipGetLastError());
@@ -290,7 +375,9 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
   int rc = check_problems(probs, count, dtype);
   if (rc) return rc;
   const int scaling = opts & 0xff;
-  if ((scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) || (opts >> 8) != 0)
+  const int panel = (opts >> 8) & 0xff;
+  if ((scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) ||
+      (panel != 0 && panel != BATCH_PB) || (opts >> 16) != 0)
     return -4;
   if (!d_ws) return -5;
   if (!out) return -8;
@@ -307,6 +394,8 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
   b->dtype = dtype;
   b->count = count;
   b->tpw = tpw;
+  b->panel = panel;
+  b->pan_start = L.pan_start;
   b->order = L.order;
   b->tall_start = L.tall_start;
   b->red_start = L.red_start;
@@ -314,7 +403,7 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
   b->cols = L.col_start[count];
   std::vector<SketchJob> jobs(count);
   std::vector<BlockMap> tall_map(L.tall_start[count]), red_map(L.red_start[count]),
-      sk_map(L.sk_start[count]), col_map(L.col_start[count]);
+      sk_map(L.sk_start[count]), col_map(L.col_start[count]), pan_map(L.pan_start[count]);
   b->hp.resize(count);
   for (int s = 0; s < count; ++s) {
     const rhqr_problem &q = probs[L.order[s]];
@@ -334,6 +423,11 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
     }
     double *Z = (double *)(region + align_up(lb));
     double *skpart = (double *)(region + align_up(lb) + align_up(sizeof(double) * (size_t)Lr * m));
+    int gt0;
+    size_t skb0;
+    sketch_tail_partials_size(h, m, &gt0, &skb0);
+    double *Cc = (double *)((char *)skpart + align_up(skb0));
+    double *Gc = (double *)((char *)Cc + align_up(sizeof(double) * (size_t)m * BATCH_PB));
     LoopArgs a;
     a.kind = h->kind;
     a.dtype = dtype;
@@ -356,6 +450,8 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
     a.omega = nullptr;
     a.defer = 1;
     b->hp[s] = make_col_problem(a, lw, tpw);
+    b->hp[s].C = Cc;
+    b->hp[s].G = Gc;
     SketchJob &jb = jobs[s];
     jb.X = q.d_W;
     jb.ldx = q.ldw;
@@ -375,6 +471,7 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
     for (int64_t k = 0; k < L.gred[s]; ++k) red_map[L.red_start[s] + k] = {s, (int32_t)k};
     for (int64_t k = 0; k < (int64_t)m * L.gt[s]; ++k) sk_map[L.sk_start[s] + k] = {s, (int32_t)k};
     for (int32_t k = 0; k < m; ++k) col_map[L.col_start[s] + k] = {s, k};
+    for (int64_t k = 0; k < L.npanel[s]; ++k) pan_map[L.pan_start[s] + k] = {s, (int32_t)k};
   }
   b->d_probs = (ColProblem *)(ws + L.off_probs);
   b->d_jobs = (SketchJob *)(ws + L.off_jobs);
@@ -382,6 +479,7 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
   b->d_red = (BlockMap *)(ws + L.off_red);
   b->d_sk = (BlockMap *)(ws + L.off_sk);
   b->d_col = (BlockMap *)(ws + L.off_col);
+  b->d_pan = (BlockMap *)(ws + L.off_pan);
   auto up = [&](void *dst, const void *src, size_t bytes) -> int {
     if (bytes == 0) return RHQR_OK;
     RHQR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
@@ -393,6 +491,7 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
   if (!rc) rc = up(b->d_red, red_map.data(), sizeof(BlockMap) * red_map.size());
   if (!rc) rc = up(b->d_sk, sk_map.data(), sizeof(BlockMap) * sk_map.size());
   if (!rc) rc = up(b->d_col, col_map.data(), sizeof(BlockMap) * col_map.size());
+  if (!rc) rc = up(b->d_pan, pan_map.data(), sizeof(BlockMap) * pan_map.size());
   if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = RHQR_ERR_HIP;
   if (!rc && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) rc = RHQR_ERR_HIP;
   if (rc) {

@@ -698,4 +698,179 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
 }
 
 
+// ---------------------------------------------------------- blocked schedule
+// Panels of PB columns (block form of the column loop, Alg. 5 with the compact
+// form of Prop. 3.2): before the panel starting at column J is processed, the
+// J earlier reflectors are applied to all of its columns at once,
+//     W_{:, J:J+nb} -= U_{:, <J} C,   C = T_{<J}^t S_{<J}^t Z_{:, J:J+nb},
+// which is exact because rows p < J of c_j = T^t S^t z_j only involve
+// T_{<J}; inside the panel each column is refreshed with the reflectors
+// J..j-1 only.  U_{:, <J} is then read once per panel instead of once per
+// column.
+
+// G = S_{:, <J}^t Z_{:, J:J+nb} (J x nb, ld J), one wave per entry
+__device__ __forceinline__ void pgram_block(int32_t L, int32_t J, int32_t nb,
+                                            const double *__restrict__ S, int64_t lds,
+                                            const double *__restrict__ Z, int64_t ldz,
+                                            double *__restrict__ G, int bid) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t e = (int64_t)bid * 16 + w;
+  if (e >= (int64_t)J * nb) return;
+  const int p = (int)(e % J), jj = (int)(e / J);
+  const double *sp = S + (int64_t)p * lds;
+  const double *zp = Z + (int64_t)(J + jj) * ldz;
+  double v = 0.0;
+  for (int k = lane; k < L; k += 64) v += sp[k] * zp[k];
+  v = wave_sum(v);
+  if (lane == 0) G[p + (int64_t)jj * J] = v;
+}
+
+// C = T_{<J}^t G: C_{p,jj} = sum_{q <= p} T_{q,p} G_{q,jj}, stored row-major (J x nb)
+// rows padded to pw >= nb entries (zeros beyond nb): the pw coefficients of
+// column p are contiguous and read unconditionally by the panel kernel
+__device__ __forceinline__ void ptri_entry(int32_t J, int32_t nb, int32_t pw,
+                                           const double *__restrict__ T, int64_t ldt,
+                                           const double *__restrict__ G, double *__restrict__ C,
+                                           int p, int jj) {
+  if (p >= J || jj >= pw) return;
+  double v = 0.0;
+  if (jj < nb)
+    for (int q = 0; q <= p; ++q) v += T[q + (int64_t)p * ldt] * G[q + (int64_t)jj * J];
+  C[(int64_t)p * pw + jj] = v;
+}
+
+// W[m:n, J:J+nb] -= U[m:n, 0:J] C.  Each thread streams VEC consecutive rows
+// of U (one 16-byte load per column) against all NBC panel columns, whose
+// coefficients sit in LDS (broadcast reads); U is read exactly once.
+constexpr int PANEL_TPB = 256;
+constexpr int PANEL_KB = 8;  // columns of U whose loads are in flight together
+
+template <typename ST, typename CT, int VEC>
+__device__ __forceinline__ void panel_load(const ST *p, CT *x) {
+  if constexpr (sizeof(ST) * VEC == 16) {
+    vload<ST, CT, true>(p, x);
+  } else {  // 8 bytes: four 2-byte values
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 u = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+    const uint32_t wd[2] = {u.x, u.y};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const unsigned short bits = (unsigned short)(wd[e >> 1] >> (16 * (e & 1)));
+      if constexpr (std::is_same<ST, __half>::value)
+        x[e] = (CT)__half2float(__ushort_as_half(bits));
+      else
+        x[e] = (CT)__uint_as_float(((uint32_t)bits) << 16);
+    }
+  }
+}
+
+template <typename ST, typename CT, int VEC>
+__device__ __forceinline__ void panel_store(ST *p, const CT *x) {
+  if constexpr (sizeof(ST) * VEC == 16) {
+    vstore<ST, CT>(p, x);
+  } else {  // 8 bytes: four 2-byte values
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    u32x2 u;
+    u.x = (uint32_t)enc16<ST>((float)x[0]) | ((uint32_t)enc16<ST>((float)x[1]) << 16);
+    u.y = (uint32_t)enc16<ST>((float)x[2]) | ((uint32_t)enc16<ST>((float)x[3]) << 16);
+    *reinterpret_cast<u32x2 *>(p) = u;
+  }
+}
+
+template <typename ST, int NBC>
+__device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
+                                            int32_t J, int32_t nb, const double *__restrict__ Ct,
+                                            int aligned, int bid) {
+  using CT = typename CompT<ST>::type;
+  constexpr int VEC = sizeof(ST) == 8 ? 2 : 4;   // rows per thread
+  const int64_t mb = m - (m % VEC);  // aligned start; head rows < m are not written
+  const int64_t rb = mb + (int64_t)bid * PANEL_TPB * VEC;  // first row of the workgroup
+  const int64_t r0 = rb + (int64_t)threadIdx.x * VEC;
+  if (r0 >= n) return;
+  // uniform: every thread's vector is in bounds and aligned
+  const bool fast = aligned && rb + (int64_t)PANEL_TPB * VEC <= n;
+  const uint32_t off = (uint32_t)(threadIdx.x * VEC * sizeof(ST));
+  CT acc[VEC][NBC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e)
+#pragma unroll
+    for (int c = 0; c < NBC; ++c) acc[e][c] = (CT)0;
+  // coefficients of column k: Ct[k * NBC + c], zero beyond nb (uniform
+  // addresses: scalar loads)
+  auto coef = [&](int k, int c) -> CT { return (CT)Ct[(int64_t)k * NBC + c]; };
+  if (fast) {
+    int k = 0;
+    for (; k + PANEL_KB <= J; k += PANEL_KB) {
+      CT xs[PANEL_KB][VEC];
+#pragma unroll
+      for (int u = 0; u < PANEL_KB; ++u) {
+        const char *cb = (const char *)(W + (int64_t)(k + u) * ldw + rb);  // uniform
+        panel_load<ST, CT, VEC>((const ST *)(cb + off), xs[u]);
+      }
+      // keep the PANEL_KB loads issued together ahead of the arithmetic (the
+      // scheduler otherwise sinks each load to its first use)
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < PANEL_KB; ++u)
+#pragma unroll
+        for (int c = 0; c < NBC; ++c) {
+          const CT ck = coef(k + u, c);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[e][c] += xs[u][e] * ck;
+        }
+    }
+    for (; k < J; ++k) {
+      const char *cb = (const char *)(W + (int64_t)k * ldw + rb);
+      CT x[VEC];
+      panel_load<ST, CT, VEC>((const ST *)(cb + off), x);
+#pragma unroll
+      for (int c = 0; c < NBC; ++c) {
+        const CT ck = coef(k, c);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e][c] += x[e] * ck;
+      }
+    }
+  } else {
+    for (int k = 0; k < J; ++k) {
+      const ST *col = W + (int64_t)k * ldw + r0;
+      CT x[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) x[e] = r0 + e < n ? cvt_in<CT>(col[e]) : (CT)0;
+#pragma unroll
+      for (int c = 0; c < NBC; ++c) {
+        const CT ck = coef(k, c);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e][c] += x[e] * ck;
+      }
+    }
+  }
+  if (fast && r0 >= m) {
+    // whole-vector read-modify-write: partial stores would cost extra HBM
+    // write and fetch traffic
+#pragma unroll
+    for (int c = 0; c < NBC; ++c) {
+      if (c < nb) {  // uniform; a break here would stop the unrolling
+        ST *wc = W + (int64_t)(J + c) * ldw + r0;
+        CT x[VEC];
+        panel_load<ST, CT, VEC>(wc, x);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) x[e] -= acc[e][c];
+        panel_store<ST, CT, VEC>(wc, x);
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < NBC; ++c) {
+    if (c < nb) {
+      ST *wc = W + (int64_t)(J + c) * ldw + r0;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+        if (r0 + e < n && r0 + e >= m)
+          wc[e] = cvt_out<ST>((double)(cvt_in<CT>(wc[e]) - acc[e][c]));
+    }
+  }
+}
+
+
 }  // namespace

@@ -72,6 +72,7 @@ struct ColProblem {
   double *part, *y, *sq, *dpart, *epart, *ypart, *scal, *c, *cf, *ia, *Tt, *dcpart, *fs;
   float *wstage;
   int32_t *status;
+  double *C, *G;       // panel coefficients of the blocked schedule (batched path)
 };
 
 // descriptor of (a, w) for tall workgroups of tpw transform tiles

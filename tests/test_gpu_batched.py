@@ -31,33 +31,51 @@ def _inputs(torch, dt, kappa=3.0, shapes=SHAPES):
     return probs
 
 
+@pytest.mark.parametrize("panel", [0, 16])
 @pytest.mark.parametrize("dt", ["float64", "float32", "float16", "bfloat16"])
-def test_batch_bitwise_equals_single(dt):
+def test_batch_bitwise_equals_single(dt, panel):
+    """Same schedule, same device code: bitwise equal.  (2-byte storage with
+    panels: the single-problem path updates panels on matrix cores with split
+    coefficients, the batch on the vector units; elementwise agreement then
+    means nothing at the storage precision, so both are held to the
+    factorization bounds instead.)"""
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
     tdt = getattr(torch, dt)
     probs = _inputs(torch, tdt)
-    log(f"batch {dt}: {len(probs)} problems")
+    log(f"batch {dt} panel={panel}: {len(probs)} problems")
     batch_in = [(sk, to_gpu(W, tdt)) for W, sk, _ in probs]
-    b = rhqr.Batch(batch_in)
+    b = rhqr.Batch(batch_in, panel=panel)
     outs = b.factor()
     torch.cuda.synchronize()
     assert b.status() == [0] * len(probs)
+    exact = not (panel and tdt in (torch.float16, torch.bfloat16))
     for (W, sk, shp), o in zip(probs, outs):
         log(f"  single {shp}")
         Wd = to_gpu(W, tdt)
-        ref = rhqr.factor(sk, Wd, panel=0)
+        ref = rhqr.factor(sk, Wd, panel=panel)
         torch.cuda.synchronize()
-        for k in ("U", "S", "T", "R"):
-            assert torch.equal(o[k], ref[k]), (shp, k)
+        if exact:
+            for k in ("U", "S", "T", "R"):
+                assert torch.equal(o[k], ref[k]), (shp, k)
+        else:
+            n, m, l, seed = shp
+            Win = to_np(to_gpu(W, tdt))  # the rounded input
+            osketch = osk.Sketch(osk.SRHT, n, m, l, seed=seed + 100)
+            for out in (o, ref):
+                Q = orq.thin_q(to_np(out["U"]), to_np(out["T"]), m)
+                ef = metrics.fact_error(Win, Q, to_np(out["R"]))
+                eo = metrics.orth_error(osk.rh_sketch(Q, osketch))
+                assert ef < 1e-2 and eo < 1e-2, (shp, ef, eo)
     b.close()
 
 
-def test_batch_f64_matches_oracle():
+@pytest.mark.parametrize("panel", [0, 16])
+def test_batch_f64_matches_oracle(panel):
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
     probs = _inputs(torch, torch.float64, kappa=2.0)
-    b = rhqr.Batch([(sk, to_gpu(W)) for W, sk, _ in probs])
+    b = rhqr.Batch([(sk, to_gpu(W)) for W, sk, _ in probs], panel=panel)
     outs = b.factor()
     torch.cuda.synchronize()
     for (W, sk, (n, m, l, seed)), o in zip(probs, outs):
@@ -68,13 +86,14 @@ def test_batch_f64_matches_oracle():
     b.close()
 
 
-def test_batch_graph_replays_match_eager():
+@pytest.mark.parametrize("panel", [0, 16])
+def test_batch_graph_replays_match_eager(panel):
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
     probs = _inputs(torch, torch.float32)
     src = [to_gpu(W, torch.float32) for W, _, _ in probs]
     work = [s.clone() for s in src]
-    b = rhqr.Batch([(sk, w) for (_, sk, _), w in zip(probs, work)])
+    b = rhqr.Batch([(sk, w) for (_, sk, _), w in zip(probs, work)], panel=panel)
     eager = [{k: v.clone() for k, v in o.items()} for o in b.factor(graph=False)]
     torch.cuda.synchronize()
     for rep in range(3):
@@ -124,7 +143,8 @@ def test_batch_c4_shapes_fp32_bounds():
         W = synthetic_matrix(n, m, kap, seed=seed)
         probs.append((W, rhqr.Sketch(rhqr.SRHT, n, m, l, seed=seed)))
     d = [np.abs(W).max(axis=0) for W, _ in probs]
-    b = rhqr.Batch([(sk, to_gpu(W / dd, torch.float32)) for (W, sk), dd in zip(probs, d)])
+    b = rhqr.Batch([(sk, to_gpu(W / dd, torch.float32)) for (W, sk), dd in zip(probs, d)],
+                   panel=16)
     outs = b.factor(graph=True)
     torch.cuda.synchronize()
     assert b.status() == [0] * len(probs)

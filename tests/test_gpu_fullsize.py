@@ -157,3 +157,28 @@ def test_c3_f64_blocked_fullsize():
     assert rhqr.status(out["ws"]) == 0
     _checks(torch, W0, out["U"], out["S"], out["T"], out["R"], osketch, m, (0, 1, 128, 255),
             "c3 f64 panel=16")
+
+
+@pytest.mark.parametrize("dt", ["float32", "float16"])
+def test_c5_gmres_fullsize(dt):
+    """RHQR-GMRES(100) on the 2048 x 2048 convection-diffusion operator
+    (n = 4,194,304), rhs of ones, SRHT l = 400: the true relative residual,
+    recomputed here on the CPU with scipy from the returned x, reaches 1e-6;
+    the float32 / float16 basis needs at most a few more cycles than the
+    float64 one."""
+    torch = cuda_or_skip()
+    import scipy.sparse as sp
+    from paper_2405_10923_amd import rhqr
+    from paper_2405_10923_amd.inputs import convdiff_csr
+    ptr, idx, val, n = convdiff_csr(2048)
+    A = rhqr.CSR(ptr, idx, val, n)
+    Acpu = sp.csr_matrix((val, idx, ptr), shape=(n, n))
+    sk = rhqr.Sketch(rhqr.SRHT, n, 101, 400, seed=0)
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    x64, h64, _ = rhqr.gmres(A, b, sk, 100, torch.float64, tol=1e-6, max_cycles=150)
+    x, h, _ = rhqr.gmres(A, b, sk, 100, getattr(torch, dt), tol=1e-6, max_cycles=150)
+    xn = to_np(x).ravel()
+    res = np.linalg.norm(np.ones(n) - Acpu @ xn) / np.sqrt(n)
+    log(f"c5 gmres {dt}: {len(h)} cycles (float64 basis {len(h64)}), true residual {res:.2e}")
+    assert res <= 1e-6
+    assert len(h) <= len(h64) + 10
