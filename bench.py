@@ -322,23 +322,37 @@ def _time(torch, fn, steps, warmup, before=None):
     return float(np.mean([a.elapsed_time(b) for a, b in out]))
 
 
-def run_thin_q(rhqr, torch, sk, W64, m, steps):
-    """Thin Q = [I; 0] - U T U_1^t (Sec. 3.2) after a float64 factorization:
-    time of the factorization with Q minus the time without."""
-    W = torch.empty_like(W64.t()).t()
-    bq = rhqr.FactorBuffers(sk, torch.float64, m, want_q=True)
-    restore = lambda: W.copy_(W64)
+def run_thin_q(rhqr, torch, sk, W64, m, steps, dt=None):
+    """Thin Q = [I; 0] - U T U_1^t (Sec. 3.2) after a factorization: time of
+    the factorization with Q minus the time without."""
+    dt = dt or torch.float64
+    if dt == torch.float64:
+        Wsrc = W64
+    else:
+        Wsrc = torch.empty((m, W64.shape[0]), dtype=dt, device=W64.device).t()
+        Wsrc.copy_(W64 / W64.abs().amax(dim=0))
+    W = torch.empty((m, W64.shape[0]), dtype=dt, device=W64.device).t()
+    bq = rhqr.FactorBuffers(sk, dt, m, want_q=True)
+    restore = lambda: W.copy_(Wsrc)
     t_q = _time(torch, lambda: rhqr.factor(sk, W, want_q=True, bufs=bq, panel=16), steps, 1, restore)
     t_n = _time(torch, lambda: rhqr.factor(sk, W, want_q=False, bufs=bq, panel=16), steps, 1, restore)
     n = W64.shape[0]
     ms = t_q - t_n
-    byts = 2 * 8 * (n - m) * m
+    es = torch.finfo(dt).bits // 8
+    byts = 2 * es * (n - m) * m
     flops = 2.0 * (n - m) * m * m
     del W, bq
     torch.cuda.empty_cache()
-    return {"workload": f"Q of a {n} x {m} float64 factorization", "ms": round(ms, 3),
-            "GBps": round(byts / (ms * 1e-3) / 1e9, 1), "TFLOPs": round(flops / (ms * 1e-3) / 1e12, 2),
-            "bound": "fp64 (AI = m/8 flop/B)", "frac_fp64_peak": round(flops / (ms * 1e-3) / 78.6e12, 4)}
+    out = {"workload": f"Q of a {n} x {m} {str(dt).split('.')[-1]} factorization",
+           "ms": round(ms, 3), "GBps": round(byts / (ms * 1e-3) / 1e9, 1),
+           "TFLOPs": round(flops / (ms * 1e-3) / 1e12, 2)}
+    if es == 8:
+        out["bound"] = "fp64 matrix cores (AI = m/8 flop/B)"
+        out["frac_fp64_peak"] = round(flops / (ms * 1e-3) / 78.6e12, 4)
+    else:
+        out["bound"] = "hbm (f32 MFMA, split coefficients)"
+        out["frac_hbm_peak"] = round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
 
 
 def run_c2(rhqr, torch, steps):
@@ -481,8 +495,11 @@ def main():
 
     extra = None
     if not args.no_extra:
-        extra = {"thin_q_f64": run_thin_q(rhqr, torch, sk, W64, m, max(2, args.steps // 2))}
-        print(f"# thin Q float64: {extra['thin_q_f64']['ms']:.2f} ms", file=sys.stderr, flush=True)
+        extra = {"thin_q_f64": run_thin_q(rhqr, torch, sk, W64, m, max(2, args.steps // 2)),
+                 "thin_q_f16": run_thin_q(rhqr, torch, sk, W64, m, max(2, args.steps // 2),
+                                          torch.float16)}
+        print(f"# thin Q float64: {extra['thin_q_f64']['ms']:.2f} ms, float16: "
+              f"{extra['thin_q_f16']['ms']:.2f} ms", file=sys.stderr, flush=True)
     batched = None
     if args.batch_count > 0:
         del W64

@@ -93,9 +93,12 @@ int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, doubl
                             void *mf, hipStream_t st);
 // scratch of the matrix-core panel update (split coefficients and scales)
 size_t panel_mfma_bytes(int32_t m);
+// thin Q = [I; 0] - U T U_1^t (Sec. 3.2); Mq: m x m float64 scratch, qmf:
+// thin_q_bytes(m) bytes of scratch (2-byte storage: split coefficients)
+size_t thin_q_bytes(int32_t m);
 int launch_thin_q(int dtype, int64_t n, int32_t m, const void *U, int64_t ldu, const double *S,
-                  int64_t lds, const double *T, int64_t ldt, double *Mq, void *Q, int64_t ldq,
-                  hipStream_t st);
+                  int64_t lds, const double *T, int64_t ldt, double *Mq, void *qmf, void *Q,
+                  int64_t ldq, hipStream_t st);
 int launch_fill(void *p, size_t bytes, hipStream_t st);
 // X M = B for `rows` rows (B, X n-row data in dtype, column-major; M upper
 // triangular m x m float64): blocked forward substitution (recRHQR, Alg. 6).

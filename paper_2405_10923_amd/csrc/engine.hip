@@ -147,6 +147,73 @@ __global__ void k_qhead(int32_t m, const double *S, int64_t lds, const double *M
   Q[k + (int64_t)cidx * ldq] = cvt_out<ST>(v);
 }
 
+// ------------------------------------------------------- thin Q, float64
+// Q_2 = -U_2 Mq (Mq = T U_1^t, m x m) on float64 matrix cores
+// (v_mfma_f64_16x16x4): a workgroup of 4 waves owns 64 rows x QF_NC columns
+// of Q_2, each wave 16 rows x QF_NC (QF_NC / 16 accumulator blocks).  The
+// 16 x QF_NC slices of Mq are staged in LDS and shared by the waves; every
+// lane loads one float64 of U_2 per 4-column step (16 consecutive rows of 4
+// columns per wave, 128-byte segments), the next slice's values in flight
+// during the products.  Operand layout (probed): A[i = lane % 16][k = lane / 16],
+// B[k = lane / 16][j = lane % 16], D[i = lane / 16 + 4 t][j = lane % 16].
+constexpr int QF_NC = 128, QF_KC = 16;
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_qtail64(const double *__restrict__ U, int64_t ldu,
+                                                 int64_t rows, int32_t m,
+                                                 const double *__restrict__ Mq,
+                                                 double *__restrict__ Q, int64_t ldq) {
+  __shared__ double Bs[QF_KC][QF_NC + 2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * 64 + w * 16;  // wave's first row (of U_2 / Q_2)
+  const int c0 = blockIdx.y * QF_NC;
+  const int i = lane & 15, kq = lane >> 4;
+  const int64_t row = r0 + i;
+  const bool rok = row < rows;
+  f64x4_t acc[QF_NC / 16];
+#pragma unroll
+  for (int b = 0; b < QF_NC / 16; ++b) acc[b] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+  double a[QF_KC / 4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < QF_KC / 4; ++s) {
+      const int k = k0 + 4 * s + kq;
+      a[s] = (rok && k < m) ? U[row + (int64_t)k * ldu] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < m; k0 += QF_KC) {
+    __syncthreads();  // the previous slice has been consumed
+    for (int e = threadIdx.x; e < QF_KC * QF_NC; e += 256) {
+      const int kk = e / QF_NC, c = e % QF_NC;
+      const int k = k0 + kk, col = c0 + c;
+      Bs[kk][c] = (k < m && col < m) ? Mq[k + (int64_t)col * m] : 0.0;
+    }
+    __syncthreads();
+    double cur[QF_KC / 4];
+#pragma unroll
+    for (int s = 0; s < QF_KC / 4; ++s) cur[s] = a[s];
+    if (k0 + QF_KC < m) fetch(k0 + QF_KC);
+#pragma unroll
+    for (int s = 0; s < QF_KC / 4; ++s) {
+#pragma unroll
+      for (int b = 0; b < QF_NC / 16; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[s], Bs[4 * s + kq][b * 16 + i], acc[b],
+                                                      0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < QF_NC / 16; ++b) {
+    const int col = c0 + b * 16 + i;
+    if (col >= m) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t r = r0 + kq + 4 * t;
+      if (r < rows) Q[r + (int64_t)col * ldq] = -acc[b][t];
+    }
+  }
+}
+
 // C[r0:r1, 0:N2] = alpha * A[r0:r1, 0:K] B  (B float64, K x N2).  64 x 64 tiles,
 // 16-deep K steps through LDS, 4 x 4 outputs per thread.
 template <typename ST>
@@ -644,6 +711,160 @@ __global__ void __launch_bounds__(PM_WAVES * 64) k_panel_mfma(
   }
 }
 
+// ------------------------------------------------ thin Q, 2-byte storage
+// Q_2 = -U_2 Mq on float32 MFMA with Mq split as in the panel update (per
+// column power-of-two scale, hi + lo parts in the storage type).  A wave owns
+// 64 rows x QH_NC columns of Q_2 (4 x QH_NC/16 accumulator blocks) and streams
+// all m columns of U_2 through its LDS slice, the next chunk in flight.
+constexpr int QH_NC = 64;
+
+// B operand order for a column tile of QH_NC: column group g (rows 4g..4g+3 of
+// Mq), tile column jt: B[((tile * Kg + g) * QH_NC + jt) * 4 + t], Kg = Kp / 4.
+template <typename ST>
+__global__ void __launch_bounds__(256) k_qconv(int32_t m, int32_t Kp,
+                                              const double *__restrict__ Mq,
+                                              unsigned short *__restrict__ Bh,
+                                              unsigned short *__restrict__ Bl,
+                                              float *__restrict__ scale) {
+  const int j = blockIdx.x;  // column of Mq
+  __shared__ float sc;
+  double mx = 0.0;
+  for (int k = threadIdx.x; k < m; k += blockDim.x) mx = fmax(mx, fabs(Mq[k + (int64_t)j * m]));
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  __shared__ double wm[4];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double a = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+    int e = 0;
+    if (a > 0.0) (void)frexp(a, &e);
+    sc = ldexpf(1.0f, e);
+    scale[j] = sc;
+  }
+  __syncthreads();
+  const int tile = j / QH_NC, jt = j % QH_NC, Kg = Kp / 4;
+  for (int k = threadIdx.x; k < Kp; k += blockDim.x) {
+    const double v = k < m ? Mq[k + (int64_t)j * m] / (double)sc : 0.0;
+    const unsigned short h = enc16<ST>((float)v);
+    const unsigned short lo = enc16<ST>((float)(v - (double)dec16<ST>(h)));
+    const int64_t o = ((((int64_t)tile * Kg + (k >> 2)) * QH_NC + jt) << 2) + (k & 3);
+    Bh[o] = h;
+    Bl[o] = lo;
+  }
+}
+
+template <typename ST, bool FULL>
+__device__ __forceinline__ void qtail16_wave(const ST *__restrict__ U, int64_t ldu, int64_t rows,
+                                             int32_t m, int32_t Kp, int tile,
+                                             const unsigned short *__restrict__ Bh,
+                                             const unsigned short *__restrict__ Bl,
+                                             unsigned short *sl, int64_t rb,
+                                             f32x4_t (&acc)[4][QH_NC / 16]) {
+  const int lane = threadIdx.x & 63;
+  const int lc = lane >> 3, lr = (lane & 7) * 8;
+  const int Kg = Kp / 4;
+  u32x4 buf[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = k0 + lc + 8 * r;
+      if constexpr (FULL) {
+        const int kc = k < m ? k : m - 1;  // clamped: finite values times zero coefficients
+        buf[r] = vraw_nt(U + (int64_t)kc * ldu + rb + lr);
+      } else {
+        const ST *src = U + (int64_t)k * ldu + rb + lr;
+        unsigned short e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          e[q] = (k < m && rb + lr + q < rows) ? __builtin_bit_cast(unsigned short, src[q]) : 0;
+        buf[r] = u32x4{(uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2] | ((uint32_t)e[3] << 16),
+                       (uint32_t)e[4] | ((uint32_t)e[5] << 16), (uint32_t)e[6] | ((uint32_t)e[7] << 16)};
+      }
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < m; k0 += PM_KC) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      *reinterpret_cast<u32x4 *>(sl + (lc + 8 * r) * PM_RS + lr) = buf[r];
+    uint2 bh[PM_KC / 16][QH_NC / 16], bl[PM_KC / 16][QH_NC / 16];
+#pragma unroll
+    for (int kk = 0; kk < PM_KC / 16; ++kk) {
+      const int g = (k0 >> 2) + kk * 4 + (lane >> 4);
+#pragma unroll
+      for (int nb = 0; nb < QH_NC / 16; ++nb) {
+        const int64_t o = ((((int64_t)tile * Kg + g) * QH_NC + nb * 16 + (lane & 15)) << 2);
+        bh[kk][nb] = *reinterpret_cast<const uint2 *>(Bh + o);
+        bl[kk][nb] = *reinterpret_cast<const uint2 *>(Bl + o);
+      }
+    }
+    if (FULL || k0 + PM_KC < m) fetch(k0 + PM_KC);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < PM_KC / 16; ++kk) {
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        unsigned short a[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          a[t] = sl[(kk * 16 + 4 * (lane >> 4) + t) * PM_RS + mb * 16 + (lane & 15)];
+#pragma unroll
+        for (int nb = 0; nb < QH_NC / 16; ++nb) {
+          acc[mb][nb] = mfma16<ST>(a, bh[kk][nb], acc[mb][nb]);
+          acc[mb][nb] = mfma16<ST>(a, bl[kk][nb], acc[mb][nb]);
+        }
+      }
+    }
+  }
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(PM_WAVES * 64) k_qtail16(const ST *__restrict__ U, int64_t ldu,
+                                                           int64_t rows, int32_t m, int32_t Kp,
+                                                           const unsigned short *__restrict__ Bh,
+                                                           const unsigned short *__restrict__ Bl,
+                                                           const float *__restrict__ scale,
+                                                           ST *__restrict__ Q, int64_t ldq,
+                                                           int aligned) {
+  __shared__ unsigned short lds[PM_WAVES][PM_KC * PM_RS];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t rb = ((int64_t)blockIdx.x * PM_WAVES + w) * PM_ROWS;
+  if (rb >= rows) return;
+  const int tile = blockIdx.y;
+  const bool full = aligned && rb + PM_ROWS <= rows;
+  f32x4_t acc[4][QH_NC / 16];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < QH_NC / 16; ++b) acc[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  if (full)
+    qtail16_wave<ST, true>(U, ldu, rows, m, Kp, tile, Bh, Bl, lds[w], rb, acc);
+  else
+    qtail16_wave<ST, false>(U, ldu, rows, m, Kp, tile, Bh, Bl, lds[w], rb, acc);
+#pragma unroll
+  for (int nb = 0; nb < QH_NC / 16; ++nb) {
+    const int col = tile * QH_NC + nb * 16 + (lane & 15);
+    if (col >= m) continue;
+    const float sj = -scale[col];
+    ST *qc = Q + (int64_t)col * ldq;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const int64_t r0 = rb + mb * 16 + 4 * (lane >> 4);
+      if (full) {
+        const uint32_t w0 = (uint32_t)enc16<ST>(sj * acc[mb][nb][0]) |
+                            ((uint32_t)enc16<ST>(sj * acc[mb][nb][1]) << 16);
+        const uint32_t w1 = (uint32_t)enc16<ST>(sj * acc[mb][nb][2]) |
+                            ((uint32_t)enc16<ST>(sj * acc[mb][nb][3]) << 16);
+        *reinterpret_cast<uint2 *>(qc + r0) = uint2{w0, w1};
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (r0 + t < rows) qc[r0 + t] = cvt_out<ST>((double)(sj * acc[mb][nb][t]));
+      }
+    }
+  }
+}
+
 inline int panel_width(int nb) { return nb <= 8 ? 8 : nb <= 16 ? 16 : 32; }
 
 template <typename ST, int NBC>
@@ -744,7 +965,8 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, double *C, 
 
 template <typename ST>
 int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S, int64_t lds,
-                 const double *T, int64_t ldt, double *Mq, ST *Q, int64_t ldq, hipStream_t st) {
+                 const double *T, int64_t ldt, double *Mq, void *qmf, ST *Q, int64_t ldq,
+                 hipStream_t st) {
   hipLaunchKernelGGL(k_tu1t, dim3((m + 255) / 256, m), dim3(256), 0, st, m, T, ldt, S, lds, Mq);
   RHQR_HIP(hipGetLastError());
   hipLaunchKernelGGL((k_qhead<ST>), dim3((m + 255) / 256, m), dim3(256), 0, st, m, S, lds, Mq, Q,
@@ -752,9 +974,32 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
   RHQR_HIP(hipGetLastError());
   const int64_t rows = n - m;
   if (rows > 0) {
-    dim3 grid((rows + 63) / 64, (m + 63) / 64);
-    hipLaunchKernelGGL((k_gemm_tall<ST>), grid, dim3(256), 0, st, U, ldu, (int64_t)m, n, m,
-                       (const double *)Mq, (int64_t)m, m, Q, ldq, -1.0);
+    if constexpr (std::is_same<ST, double>::value) {
+      dim3 grid((unsigned)((rows + 63) / 64), (m + QF_NC - 1) / QF_NC);
+      hipLaunchKernelGGL(k_qtail64, grid, dim3(256), 0, st, U + m, ldu, rows, m,
+                         (const double *)Mq, Q + m, ldq);
+    } else if constexpr (sizeof(ST) == 2) {
+      const int Kp = (m + PM_KC - 1) / PM_KC * PM_KC;
+      const int tiles = (m + QH_NC - 1) / QH_NC;
+      unsigned short *Bh = (unsigned short *)qmf;
+      unsigned short *Bl = Bh + (size_t)tiles * Kp * QH_NC;
+      float *sc = (float *)(Bl + (size_t)tiles * Kp * QH_NC);
+      hipLaunchKernelGGL((k_qconv<ST>), dim3(tiles * QH_NC), dim3(256), 0, st, m, Kp,
+                         (const double *)Mq, Bh, Bl, sc);
+      RHQR_HIP(hipGetLastError());
+      const int aligned = ((uintptr_t)(U + m) % 16 == 0) && ((uintptr_t)(Q + m) % 8 == 0) &&
+                          ((ldu * (int64_t)sizeof(ST)) % 16 == 0) &&
+                          ((ldq * (int64_t)sizeof(ST)) % 8 == 0);
+      const int64_t waves = (rows + PM_ROWS - 1) / PM_ROWS;
+      dim3 grid((unsigned)((waves + PM_WAVES - 1) / PM_WAVES), tiles);
+      hipLaunchKernelGGL((k_qtail16<ST>), grid, dim3(PM_WAVES * 64), 0, st, U + m, ldu, rows, m, Kp,
+                         (const unsigned short *)Bh, (const unsigned short *)Bl,
+                         (const float *)sc, Q + m, ldq, aligned);
+    } else {
+      dim3 grid((rows + 63) / 64, (m + 63) / 64);
+      hipLaunchKernelGGL((k_gemm_tall<ST>), grid, dim3(256), 0, st, U, ldu, (int64_t)m, n, m,
+                         (const double *)Mq, (int64_t)m, m, Q, ldq, -1.0);
+    }
     RHQR_HIP(hipGetLastError());
   }
   return RHQR_OK;
@@ -960,19 +1205,28 @@ int run_column_loop(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
   return RHQR_ERR_UNSUPPORTED;
 }
 
+size_t thin_q_bytes(int32_t m) {
+  const size_t Kp = (size_t)(m + PM_KC - 1) / PM_KC * PM_KC;
+  const size_t tiles = (size_t)(m + QH_NC - 1) / QH_NC;
+  return align_up(2 * tiles * Kp * QH_NC * sizeof(unsigned short) + tiles * QH_NC * sizeof(float));
+}
+
 int launch_thin_q(int dtype, int64_t n, int32_t m, const void *U, int64_t ldu, const double *S,
-                  int64_t lds, const double *T, int64_t ldt, double *Mq, void *Q, int64_t ldq,
-                  hipStream_t st) {
+                  int64_t lds, const double *T, int64_t ldt, double *Mq, void *qmf, void *Q,
+                  int64_t ldq, hipStream_t st) {
   switch (dtype) {
     case RHQR_F64:
-      return thin_q_typed<double>(n, m, (const double *)U, ldu, S, lds, T, ldt, Mq, (double *)Q, ldq, st);
+      return thin_q_typed<double>(n, m, (const double *)U, ldu, S, lds, T, ldt, Mq, qmf,
+                                  (double *)Q, ldq, st);
     case RHQR_F32:
-      return thin_q_typed<float>(n, m, (const float *)U, ldu, S, lds, T, ldt, Mq, (float *)Q, ldq, st);
+      return thin_q_typed<float>(n, m, (const float *)U, ldu, S, lds, T, ldt, Mq, qmf, (float *)Q,
+                                 ldq, st);
     case RHQR_F16:
-      return thin_q_typed<__half>(n, m, (const __half *)U, ldu, S, lds, T, ldt, Mq, (__half *)Q, ldq, st);
+      return thin_q_typed<__half>(n, m, (const __half *)U, ldu, S, lds, T, ldt, Mq, qmf,
+                                  (__half *)Q, ldq, st);
     case RHQR_BF16:
       return thin_q_typed<__hip_bfloat16>(n, m, (const __hip_bfloat16 *)U, ldu, S, lds, T, ldt, Mq,
-                                          (__hip_bfloat16 *)Q, ldq, st);
+                                          qmf, (__hip_bfloat16 *)Q, ldq, st);
   }
   return RHQR_ERR_UNSUPPORTED;
 }

@@ -67,6 +67,7 @@ struct RecWs {
   LoopWs loop;
   double *Z, *Zc, *G, *M, *Mq, *coef;
   float *stage;  // float32 copy of the solved columns (2-byte storage)
+  void *qmf;     // split coefficients of the matrix-core thin Q
   void *skws;
   size_t skws_bytes;
 };
@@ -79,6 +80,7 @@ size_t rec_ws_bytes(const rhqr_sketch_s *h, int dtype, int32_t m) {
   b += align_up(sketch_ws_bytes(h, m));
   b += trsm_coef_bytes(m);
   b += trsm_stage_bytes(dtype, h->n, m);
+  b += thin_q_bytes(m);
   return b;
 }
 
@@ -104,6 +106,7 @@ int rec_ws_carve(const rhqr_sketch_s *h, int dtype, int32_t m, void *ws, size_t 
   o->coef = (double *)take(trsm_coef_bytes(m));
   const size_t sb = trsm_stage_bytes(dtype, h->n, m);
   o->stage = sb ? (float *)take(sb) : nullptr;
+  o->qmf = take(thin_q_bytes(m));
   return RHQR_OK;
 }
 
@@ -199,7 +202,8 @@ extern "C" int recrhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, 
     if (rc) return rc;
     rc = launch_head_copy(dtype, d_U, ldu, m, d_S, lds, st);
     if (rc) return rc;
-    if (d_Q) rc = launch_thin_q(dtype, n, m, d_U, ldu, d_S, lds, d_T, ldt, w.Mq, d_Q, ldq, st);
+    if (d_Q)
+      rc = launch_thin_q(dtype, n, m, d_U, ldu, d_S, lds, d_T, ldt, w.Mq, w.qmf, d_Q, ldq, st);
     return rc;
   }
   // randomized Cholesky QR: Q = W R^-1
