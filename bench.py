@@ -8,9 +8,11 @@ float64 sketch-space step with one synchronisation per column), outputs U (in
 place of W), S, T, R.  The input is restored from a pristine copy between
 steps, outside the timed events.
 
-Schedules: "blocked" (panels of 16 columns: the earlier reflectors are applied
-to a whole panel by one tall product, the default) and "column" (every
-refresh reads all earlier reflectors, Alg. 4 as written).  Mixed precision
+Schedules: "blocked" (the earlier reflectors are applied to a whole panel of
+columns by one tall product, in two levels: inner panels updated from their
+outer panel's reflectors only; the default, widths per storage type in
+SCHEDULES) and "column" (every refresh reads all earlier reflectors, Alg. 4 as
+written).  Mixed precision
 (n-row data in float32 / float16 / bfloat16, float32 accumulation, unit-max
 column scaling before rounding) runs the same workload and is gated on
 ||W~ - QR||/||W~|| <= 1e-2 and ||(Psi Q)^t Psi Q - I||_2 <= 1e-2.
@@ -87,26 +89,57 @@ def _nparts(n, es):
     return (n + TILE * tpw - 1) // (TILE * tpw)
 
 
-def kernel_bytes(n, m, l, es, panel):
+# (panel, outer) of the blocked schedule per storage type, the fastest measured
+# on this workload: two levels, inner panels of 8 (float64, float32) or 16
+# (2-byte storage, panel update on matrix cores) in outer panels of 32
+# (float32: 16)
+SCHEDULES = {"float64": (8, 32), "float32": (8, 16), "float16": (16, 32), "bfloat16": (16, 32)}
+
+
+def sched_kw(dt):
+    panel, outer = SCHEDULES[str(dt).split(".")[-1]]
+    return {"panel": panel, "outer": outer}
+
+
+def schedule(m, panel, outer):
+    """The blocked schedule as rhqr_factor runs it: the panel updates
+    (K0, J, nb) -- W_{J:J+nb} -= U_{K0:J} C -- in launch order, and the first
+    column p0 of the inner panel of every column."""
+    if panel < 2:
+        return [], [0] * m
+    outer = max(outer, panel)
+    ups, p0 = [], [0] * m
+    for J0 in range(0, m, outer):
+        nbo = min(outer, m - J0)
+        if J0 > 0:
+            ups.append((0, J0, nbo))
+        for J in range(J0, J0 + nbo, panel):
+            nb = min(panel, J0 + nbo - J)
+            if J > J0:
+                ups.append((J0, J, nb))
+            for j in range(J, J + nb):
+                p0[j] = J
+    return ups, p0
+
+
+def kernel_bytes(n, m, l, es, panel, outer=0):
     """Algorithmic bytes of one factorization's launches of (a) the refresh +
     re-sketch kernel and (b) the panel-update kernel.  Launch j of (a) reads the
-    stored columns it applies (all earlier ones, or the panel's), the raw column
-    j-1 and w_j, writes u_{j-1} and the raw refreshed column, reads the sign
-    bits and writes one l-vector of partials per workgroup.  Launch J of (b)
-    reads the J earlier columns and the panel's nb columns and writes them."""
+    stored columns it applies (all earlier ones, or its inner panel's), the raw
+    column j-1 and w_j, writes u_{j-1} and the raw refreshed column, reads the
+    sign bits and writes one l-vector of partials per workgroup.  Launch
+    (K0, J, nb) of (b) reads the J - K0 columns it applies and the panel's nb
+    columns and writes them."""
     N = 1 << (n - 1).bit_length()
     tail = (n - m) * es
     side = _nparts(n, es) * l * 8 + N / 8
+    ups, p0 = schedule(m, panel, outer)
     tall = 0.0
     for j in range(1, m):
-        J = (j // panel) * panel if panel >= 2 else 0
+        J = p0[j]
         cols = (j - J + 3) if j > J else 2
         tall += cols * tail + side
-    pan = 0.0
-    if panel >= 2:
-        for J in range(panel, m, panel):
-            nb = min(panel, m - J)
-            pan += (J + 2 * nb) * tail
+    pan = sum((J - K0 + 2 * nb) * tail for K0, J, nb in ups)
     return tall, pan
 
 
@@ -132,7 +165,15 @@ def cpu_baseline(n, l, kappa, ncols, seed=0):
                       f"B_alg of that shape over {dt:.1f} s"}
 
 
-def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, steps, warmup, profile):
+def sched_name(panel, outer):
+    if panel < 2:
+        return "column by column"
+    if outer > panel:
+        return f"blocked, panels of {panel} in outer panels of {outer}"
+    return f"blocked, panels of {panel}"
+
+
+def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, outer, steps, warmup, profile):
     import numpy as np
     dev = W64.device
     es = torch.finfo(dt).bits // 8
@@ -146,7 +187,7 @@ def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, steps, warmup, profile):
     bufs = rhqr.FactorBuffers(sk, dt, m, want_q=False)
     for _ in range(warmup):
         Ww.copy_(Wsrc)
-        rhqr.factor(sk, Ww, bufs=bufs, panel=panel)
+        rhqr.factor(sk, Ww, bufs=bufs, panel=panel, outer=outer)
     torch.cuda.synchronize()
     evs = []
     for _ in range(steps):
@@ -154,7 +195,7 @@ def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, steps, warmup, profile):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        rhqr.factor(sk, Ww, bufs=bufs, panel=panel)
+        rhqr.factor(sk, Ww, bufs=bufs, panel=panel, outer=outer)
         e1.record()
         evs.append((e0, e1))
     torch.cuda.synchronize()
@@ -166,10 +207,10 @@ def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, steps, warmup, profile):
         rhqr.profile_begin()
         for _ in range(steps):
             Ww.copy_(Wsrc)
-            rhqr.factor(sk, Ww, bufs=bufs, panel=panel)
+            rhqr.factor(sk, Ww, bufs=bufs, panel=panel, outer=outer)
         torch.cuda.synchronize()
         (tall_ms, tall_n), (pan_ms, pan_n) = rhqr.profile_end()
-        tb, pb = kernel_bytes(n, m, l, es, panel)
+        tb, pb = kernel_bytes(n, m, l, es, panel, outer)
         kern = []
         if tall_n:
             ach = tb * steps / (tall_ms * 1e-3) / 1e9
@@ -197,7 +238,7 @@ def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, steps, warmup, profile):
     # accuracy of one more factorization with Q (untimed)
     Ww.copy_(Wsrc)
     bq = rhqr.FactorBuffers(sk, dt, m, want_q=True)
-    out = rhqr.factor(sk, Ww, want_q=True, bufs=bq, panel=panel)
+    out = rhqr.factor(sk, Ww, want_q=True, bufs=bq, panel=panel, outer=outer)
     Q, R = out["Q"], out["R"]
     Wt = Wsrc.to(torch.float64)
     ef = float(torch.linalg.norm(Wt - Q.to(torch.float64) @ R) / torch.linalg.norm(Wt))
@@ -334,8 +375,9 @@ def run_thin_q(rhqr, torch, sk, W64, m, steps, dt=None):
     W = torch.empty((m, W64.shape[0]), dtype=dt, device=W64.device).t()
     bq = rhqr.FactorBuffers(sk, dt, m, want_q=True)
     restore = lambda: W.copy_(Wsrc)
-    t_q = _time(torch, lambda: rhqr.factor(sk, W, want_q=True, bufs=bq, panel=16), steps, 1, restore)
-    t_n = _time(torch, lambda: rhqr.factor(sk, W, want_q=False, bufs=bq, panel=16), steps, 1, restore)
+    kw = sched_kw(dt)
+    t_q = _time(torch, lambda: rhqr.factor(sk, W, want_q=True, bufs=bq, **kw), steps, 1, restore)
+    t_n = _time(torch, lambda: rhqr.factor(sk, W, want_q=False, bufs=bq, **kw), steps, 1, restore)
     n = W64.shape[0]
     ms = t_q - t_n
     es = torch.finfo(dt).bits // 8
@@ -367,7 +409,8 @@ def run_c2(rhqr, torch, steps):
     for kind, name in ((rhqr.SRHT, "rhqr_srht"), (rhqr.GAUSS, "rhqr_gauss")):
         sk = rhqr.Sketch(kind, n, m, l, seed=0)
         bufs = rhqr.FactorBuffers(sk, torch.float64, m)
-        ms = _time(torch, lambda: rhqr.factor(sk, W, bufs=bufs, panel=16), steps, 1, restore)
+        ms = _time(torch, lambda: rhqr.factor(sk, W, bufs=bufs, **sched_kw(torch.float64)), steps,
+                   1, restore)
         ent = {"ms": round(ms, 3), "GBps_alg": round(b_alg(n, m, 8) / (ms * 1e-3) / 1e9, 1)}
         if kind == rhqr.GAUSS:
             # the Gaussian sketch re-reads Omega (l x (n-m) float64) in every column's pass
@@ -429,8 +472,11 @@ def main():
     ap.add_argument("--l", type=int, default=1024)
     ap.add_argument("--kappa", type=float, default=14.0)
     ap.add_argument("--dtypes", default="float64,float32,float16,bfloat16")
-    ap.add_argument("--panel", type=int, default=16,
-                    help="panel width of the blocked schedule (0: column by column)")
+    ap.add_argument("--panel", type=int, default=-1,
+                    help="panel width of the blocked schedule (0: column by column; "
+                         "default: per storage type, see SCHEDULES)")
+    ap.add_argument("--outer", type=int, default=-1,
+                    help="outer panel width (0: one level; default: per storage type)")
     ap.add_argument("--no-column", action="store_true",
                     help="skip the column-by-column float64 reference schedule")
     ap.add_argument("--no-cpu", action="store_true")
@@ -473,19 +519,27 @@ def main():
     W64 = synthetic_matrix_torch(n, m, kappa, seed=0, device="cuda")
     sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=0)
     res, roof = {}, None
+    scheds = {}
     for name in args.dtypes.split(","):
         dt = getattr(torch, name)
-        r, rf = run_case(rhqr, torch, sk, W64, n, m, l, dt, args.panel, args.steps, args.warmup,
+        panel, outer = SCHEDULES[name]
+        if args.panel >= 0:
+            panel, outer = args.panel, 0
+        if args.outer >= 0:
+            outer = args.outer
+        scheds[name] = (panel, outer)
+        r, rf = run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, outer, args.steps, args.warmup,
                          profile=(dt == torch.float64))
+        r["schedule"] = sched_name(panel, outer)
         res[name] = r
         if rf is not None:
             roof = rf
-        print(f"# {name} panel={args.panel}: {r['ms_per_step']:.2f} ms/step "
+        print(f"# {name} {r['schedule']}: {r['ms_per_step']:.2f} ms/step "
               f"{r['GBps_alg']:.0f} GB/s(alg)  e_fact {r['e_fact']:.2e} e_orth {r['e_orth']:.2e}",
               file=sys.stderr, flush=True)
     column = None
-    if not args.no_column and args.panel >= 2:
-        column, croof = run_case(rhqr, torch, sk, W64, n, m, l, torch.float64, 0,
+    if not args.no_column and scheds.get("float64", (0, 0))[0] >= 2:
+        column, croof = run_case(rhqr, torch, sk, W64, n, m, l, torch.float64, 0, 0,
                                  max(2, args.steps // 2), 1, profile=True)
         column["roofline"] = croof
         column["hbm_frac_alg"] = round(column["GBps_alg"] / HBM_PEAK_GBS, 4)
@@ -528,7 +582,7 @@ def main():
         v["meets_1e-2"] = bool(v["e_fact"] <= 1e-2 and v["e_orth"] <= 1e-2)
         mixed[k] = v
     head = f64 if f64 else next(iter(res.values()))
-    sched = f"blocked, panels of {args.panel}" if args.panel >= 2 else "column by column"
+    sched = head["schedule"]
     line = {
         "metric": METRIC,
         "value": head["GBps_alg"],

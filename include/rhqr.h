@@ -123,8 +123,13 @@ RHQR_API int rhqr_sketch(rhqr_sketch_t h, int dtype, int64_t n, int32_t k, const
  *           the earlier reflectors are applied to the whole panel at once by a
  *           tall matrix product with C = T^t S^t Psi W_panel (the block form of
  *           Alg. 5 / Prop. 3.2), the columns inside a panel are refreshed as in
- *           Alg. 4 with the panel's own reflectors).  Same factorization in
- *           exact arithmetic; the one synchronisation per column is kept.
+ *           Alg. 4 with the panel's own reflectors); bits 16-23 outer panel
+ *           width B (0: one level; otherwise b >= 2, b < B <= 32 and B a
+ *           multiple of b: the panels of b columns are grouped B at a time,
+ *           each outer panel is updated from all earlier reflectors and each
+ *           inner panel only from the reflectors of its outer panel).  Same
+ *           factorization in exact arithmetic; the one synchronisation per
+ *           column is kept.  Other bits must be 0.
  *   d_ws  : device workspace, >= rhqr_factor_workspace_size(h, dtype, m) bytes
  * One synchronisation per column: the refreshed column's sketch (Alg. 4).
  * Breakdown (rho_j = 0) gives an identity reflector (beta_j = 0, R_jj = 0) and

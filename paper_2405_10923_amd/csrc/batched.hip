@@ -124,7 +124,7 @@ __global__ void kb_ptri(const ColProblem *__restrict__ P, int32_t J, int per) {
   const int p = blockIdx.x / per, local = blockIdx.x % per;
   const ColProblem &Q = P[p];
   const int32_t nb = Q.m - J < BATCH_PB ? Q.m - J : BATCH_PB;
-  ptri_entry(J, nb, BATCH_PB, Q.T, Q.ldt, Q.G, Q.C, local * blockDim.x + threadIdx.x, blockIdx.y);
+  ptri_entry(0, J, nb, BATCH_PB, Q.T, Q.ldt, Q.G, Q.C, local * blockDim.x + threadIdx.x, blockIdx.y);
 }
 
 template <typename ST>
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(PANEL_TPB) kb_panel(const ColProblem *__restri
   const BlockMap b = map[blockIdx.x];
   const ColProblem &Q = P[b.p];
   const int32_t nb = Q.m - J < BATCH_PB ? Q.m - J : BATCH_PB;
-  panel_block<ST, BATCH_PB>((ST *)Q.W, Q.ldw, Q.n, Q.m, J, nb, Q.C, Q.aligned, b.local);
+  panel_block<ST, BATCH_PB>((ST *)Q.W, Q.ldw, Q.n, Q.m, 0, J, nb, Q.C, Q.aligned, b.local);
 }
 
 // last column stored as u = raw / alpha, head block of U written from S

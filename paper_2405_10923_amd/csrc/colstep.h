@@ -706,7 +706,9 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
 // which is exact because rows p < J of c_j = T^t S^t z_j only involve
 // T_{<J}; inside the panel each column is refreshed with the reflectors
 // J..j-1 only.  U_{:, <J} is then read once per panel instead of once per
-// column.
+// column.  The same holds one level down: inside an outer panel starting at
+// J0, an inner panel at J needs only the reflectors J0..J-1 (rows J0..J-1 of
+// its coefficients), the outer update having applied those below J0.
 
 // G = S_{:, <J}^t Z_{:, J:J+nb} (J x nb, ld J), one wave per entry
 __device__ __forceinline__ void pgram_block(int32_t L, int32_t J, int32_t nb,
@@ -725,23 +727,25 @@ __device__ __forceinline__ void pgram_block(int32_t L, int32_t J, int32_t nb,
   if (lane == 0) G[p + (int64_t)jj * J] = v;
 }
 
-// C = T_{<J}^t G: C_{p,jj} = sum_{q <= p} T_{q,p} G_{q,jj}, stored row-major (J x nb)
-// rows padded to pw >= nb entries (zeros beyond nb): the pw coefficients of
-// column p are contiguous and read unconditionally by the panel kernel
-__device__ __forceinline__ void ptri_entry(int32_t J, int32_t nb, int32_t pw,
+// C = T_{<J}^t G: C_{p,jj} = sum_{q <= p} T_{q,p} G_{q,jj} for rows J0 <= p < J,
+// stored row-major (row p at C + p * pw), rows padded to pw >= nb entries
+// (zeros beyond nb): the pw coefficients of column p are contiguous and read
+// unconditionally by the panel kernel
+__device__ __forceinline__ void ptri_entry(int32_t J0, int32_t J, int32_t nb, int32_t pw,
                                            const double *__restrict__ T, int64_t ldt,
                                            const double *__restrict__ G, double *__restrict__ C,
                                            int p, int jj) {
-  if (p >= J || jj >= pw) return;
+  if (p < J0 || p >= J || jj >= pw) return;
   double v = 0.0;
   if (jj < nb)
     for (int q = 0; q <= p; ++q) v += T[q + (int64_t)p * ldt] * G[q + (int64_t)jj * J];
   C[(int64_t)p * pw + jj] = v;
 }
 
-// W[m:n, J:J+nb] -= U[m:n, 0:J] C.  Each thread streams VEC consecutive rows
-// of U (one 16-byte load per column) against all NBC panel columns, whose
-// coefficients sit in LDS (broadcast reads); U is read exactly once.
+// W[m:n, J:J+nb] -= U[m:n, K0:J] C_{K0:J}.  Each thread streams VEC
+// consecutive rows of U (one 16-byte load per column) against all NBC panel
+// columns, whose coefficients are read with uniform (scalar) loads; U is read
+// exactly once.
 constexpr int PANEL_TPB = 256;
 constexpr int PANEL_KB = 8;  // columns of U whose loads are in flight together
 
@@ -779,8 +783,8 @@ __device__ __forceinline__ void panel_store(ST *p, const CT *x) {
 
 template <typename ST, int NBC>
 __device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
-                                            int32_t J, int32_t nb, const double *__restrict__ Ct,
-                                            int aligned, int bid) {
+                                            int32_t K0, int32_t J, int32_t nb,
+                                            const double *__restrict__ Ct, int aligned, int bid) {
   using CT = typename CompT<ST>::type;
   constexpr int VEC = sizeof(ST) == 8 ? 2 : 4;   // rows per thread
   const int64_t mb = m - (m % VEC);  // aligned start; head rows < m are not written
@@ -799,7 +803,7 @@ __device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int
   // addresses: scalar loads)
   auto coef = [&](int k, int c) -> CT { return (CT)Ct[(int64_t)k * NBC + c]; };
   if (fast) {
-    int k = 0;
+    int k = K0;
     for (; k + PANEL_KB <= J; k += PANEL_KB) {
       CT xs[PANEL_KB][VEC];
 #pragma unroll
@@ -831,7 +835,7 @@ __device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int
       }
     }
   } else {
-    for (int k = 0; k < J; ++k) {
+    for (int k = K0; k < J; ++k) {
       const ST *col = W + (int64_t)k * ldw + r0;
       CT x[VEC];
 #pragma unroll

@@ -87,10 +87,12 @@ int run_column_loop(const LoopArgs &a, const LoopWs &w, hipStream_t st);
 // (reduction, RHVector, T column; c_{j+1} when next != 0, from Z_{:, j+1}).
 int engine_tall(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st);
 int engine_step(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st);
-// blocked schedule: panels of `panel` (<= 32) columns; C and G are float64
-// scratch of m x 32 entries each, mf panel_mfma_bytes(m) bytes
-int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, double *C, double *G,
-                            void *mf, hipStream_t st);
+// blocked schedule: panels of `panel` (<= 32) columns, optionally grouped in
+// outer panels of `outer` (a multiple of panel, <= 32; outer <= panel: one
+// level); C and G are float64 scratch of m x 32 entries each, mf
+// panel_mfma_bytes(m) bytes
+int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, int outer, double *C,
+                            double *G, void *mf, hipStream_t st);
 // scratch of the matrix-core panel update (split coefficients and scales)
 size_t panel_mfma_bytes(int32_t m);
 // thin Q = [I; 0] - U T U_1^t (Sec. 3.2); Mq: m x m float64 scratch, qmf:

@@ -79,17 +79,17 @@ __global__ void __launch_bounds__(1024) k_pgram(int32_t L, int32_t J, int32_t nb
   pgram_block(L, J, nb, S, lds, Z, ldz, G, blockIdx.x);
 }
 
-// C = T_{<J}^t G, rows padded to pw entries
-__global__ void k_ptri(int32_t J, int32_t nb, int32_t pw, const double *__restrict__ T,
+// rows J0..J-1 of C = T_{<J}^t G, padded to pw entries
+__global__ void k_ptri(int32_t J0, int32_t J, int32_t nb, int32_t pw, const double *__restrict__ T,
                        int64_t ldt, const double *__restrict__ G, double *__restrict__ C) {
-  ptri_entry(J, nb, pw, T, ldt, G, C, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+  ptri_entry(J0, J, nb, pw, T, ldt, G, C, J0 + blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
 }
 
 template <typename ST, int NBC>
 __global__ void __launch_bounds__(PANEL_TPB) k_panel(ST *__restrict__ W, int64_t ldw, int64_t n,
-                                                     int32_t m, int32_t J, int32_t nb,
+                                                     int32_t m, int32_t K0, int32_t J, int32_t nb,
                                                      const double *__restrict__ Ct, int aligned) {
-  panel_block<ST, NBC>(W, ldw, n, m, J, nb, Ct, aligned, blockIdx.x);
+  panel_block<ST, NBC>(W, ldw, n, m, K0, J, nb, Ct, aligned, blockIdx.x);
 }
 
 // ------------------------------------------------------------ final stores
@@ -512,7 +512,7 @@ __global__ void __launch_bounds__(PANEL_TPB) k_trsm_blk(const ST *__restrict__ B
 }
 
 // ------------------------------------------- panel update on matrix cores
-// 2-byte storage, nb <= 16: W[m:n, J:J+nb] -= U[m:n, 0:J] C on float32 MFMA
+// 2-byte storage, nb <= 32: W[m:n, J:J+nb] -= U[m:n, K0:J] C on float32 MFMA
 // (v_mfma_f32_16x16x16 f16 / bf16).  C (float64) is scaled per column by a
 // power of two s_j (max |C_{:,j}| / s_j in (1/2, 1]) and split into two
 // storage-type parts, C / s = hi + lo, so the coefficients keep about 22
@@ -538,38 +538,43 @@ template <typename ST> __device__ __forceinline__ float dec16(unsigned short b) 
 }
 
 // Scales and split coefficients in the MFMA B-operand order: for column group
-// g (columns 4g..4g+3 of U, i.e. rows of C) and panel column j, the four
-// values sit at B[(g * 16 + j) * 4 + t].  Rows k >= J and columns j >= nb are
-// zero; Kp = J rounded up to PM_KC.  One workgroup of 16 waves.
-template <typename ST>
+// g (columns 4g..4g+3 of U, i.e. rows of C) and panel column j < NC, the four
+// values sit at B[(g * NC + j) * 4 + t].  Rows k >= J and columns j >= nb are
+// zero; Kp = J rounded up to PM_KC.  One workgroup of 16 waves, wave w
+// scaling columns w, w + 16, ...
+template <typename ST, int NC>
 __global__ void __launch_bounds__(1024) k_pconv(int32_t J, int32_t nb, int32_t pw, int32_t Kp,
                                                const double *__restrict__ Ct,
                                                unsigned short *__restrict__ Bh,
                                                unsigned short *__restrict__ Bl,
                                                float *__restrict__ scale) {
-  __shared__ float sc[16];
-  const int lane = threadIdx.x & 63, j = threadIdx.x >> 6;  // wave j: panel column j
-  double mx = 0.0;
-  if (j < nb)
-    for (int k = lane; k < J; k += 64) mx = fmax(mx, fabs(Ct[(int64_t)k * pw + j]));
-  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-  if (lane == 0) {
-    int e = 0;
-    if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [1/2, 1)
-    sc[j] = ldexpf(1.0f, e);
+  __shared__ float sc[NC];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int h = 0; h < NC / 16; ++h) {
+    const int j = w + 16 * h;
+    double mx = 0.0;
+    if (j < nb)
+      for (int k = lane; k < J; k += 64) mx = fmax(mx, fabs(Ct[(int64_t)k * pw + j]));
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) {
+      int e = 0;
+      if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [1/2, 1)
+      sc[j] = ldexpf(1.0f, e);
+    }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < Kp * 16; idx += blockDim.x) {
-    const int k = idx >> 4, jj = idx & 15;
+  for (int idx = threadIdx.x; idx < Kp * NC; idx += blockDim.x) {
+    const int k = idx / NC, jj = idx % NC;
     double v = 0.0;
     if (k < J && jj < nb) v = Ct[(int64_t)k * pw + jj] / (double)sc[jj];
     const unsigned short h = enc16<ST>((float)v);
     const unsigned short lo = enc16<ST>((float)(v - (double)dec16<ST>(h)));
-    const int o = (((k >> 2) * 16 + jj) << 2) + (k & 3);
+    const int o = (((k >> 2) * NC + jj) << 2) + (k & 3);
     Bh[o] = h;
     Bl[o] = lo;
   }
-  if (threadIdx.x < 16) scale[threadIdx.x] = sc[threadIdx.x];
+  if (threadIdx.x < NC) scale[threadIdx.x] = sc[threadIdx.x];
 }
 
 template <typename ST>
@@ -600,12 +605,12 @@ __device__ __forceinline__ f32x4_t mfma16(const unsigned short (&a)[4], const ui
 // column index of the loads is clamped to J - 1 (finite values, multiplied by
 // the zero padding of B), so the loads carry no condition.  !FULL (the last,
 // ragged wave): guarded element loads.
-template <typename ST, bool FULL>
+template <typename ST, bool FULL, int NC>
 __device__ __forceinline__ void panel_mfma_wave(ST *__restrict__ W, int64_t ldw, int64_t n,
                                                 int32_t J, const unsigned short *__restrict__ Bh,
                                                 const unsigned short *__restrict__ Bl,
                                                 unsigned short *sl, int64_t rb,
-                                                f32x4_t (&acc)[4]) {
+                                                f32x4_t (&acc)[4][NC / 16]) {
   const int lane = threadIdx.x & 63;
   // load lane: column lc (+ 8 r), rows rb + lr .. + 7
   const int lc = lane >> 3, lr = (lane & 7) * 8;
@@ -636,12 +641,16 @@ __device__ __forceinline__ void panel_mfma_wave(ST *__restrict__ W, int64_t ldw,
       *reinterpret_cast<u32x4 *>(sl + (lc + 8 * r) * PM_RS + lr) = buf[r];
     // this chunk's coefficients, loaded before the next chunk's columns so
     // that waiting for them does not wait for those (loads complete in order)
-    uint2 bh[PM_KC / 16], bl[PM_KC / 16];
+    uint2 bh[PM_KC / 16][NC / 16], bl[PM_KC / 16][NC / 16];
 #pragma unroll
     for (int kk = 0; kk < PM_KC / 16; ++kk) {
       const int g = (k0 >> 2) + kk * 4 + (lane >> 4);  // column group of this lane
-      bh[kk] = *reinterpret_cast<const uint2 *>(Bh + ((g * 16 + (lane & 15)) << 2));
-      bl[kk] = *reinterpret_cast<const uint2 *>(Bl + ((g * 16 + (lane & 15)) << 2));
+#pragma unroll
+      for (int h = 0; h < NC / 16; ++h) {
+        const int o = (g * NC + 16 * h + (lane & 15)) << 2;
+        bh[kk][h] = *reinterpret_cast<const uint2 *>(Bh + o);
+        bl[kk][h] = *reinterpret_cast<const uint2 *>(Bl + o);
+      }
     }
     // next chunk's columns, in flight during the products (FULL: always, with
     // clamped columns after the last chunk, so the loop has no branch and the
@@ -656,16 +665,21 @@ __device__ __forceinline__ void panel_mfma_wave(ST *__restrict__ W, int64_t ldw,
 #pragma unroll
         for (int t = 0; t < 4; ++t)
           a[t] = sl[(kk * 16 + 4 * (lane >> 4) + t) * PM_RS + mb * 16 + (lane & 15)];
-        acc[mb] = mfma16<ST>(a, bh[kk], acc[mb]);
-        acc[mb] = mfma16<ST>(a, bl[kk], acc[mb]);
+#pragma unroll
+        for (int h = 0; h < NC / 16; ++h) {
+          acc[mb][h] = mfma16<ST>(a, bh[kk][h], acc[mb][h]);
+          acc[mb][h] = mfma16<ST>(a, bl[kk][h], acc[mb][h]);
+        }
       }
     }
   }
 }
 
-template <typename ST>
+// W[m:n, J:J+nb] -= U[m:n, K0:J] C_{K0:J} (Bh, Bl and scale hold C_{K0:J}),
+// nb <= NC
+template <typename ST, int NC>
 __global__ void __launch_bounds__(PM_WAVES * 64) k_panel_mfma(
-    ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m, int32_t J, int32_t nb,
+    ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,
     const unsigned short *__restrict__ Bh, const unsigned short *__restrict__ Bl,
     const float *__restrict__ scale, int aligned) {
   __shared__ unsigned short lds[PM_WAVES][PM_KC * PM_RS];
@@ -674,38 +688,44 @@ __global__ void __launch_bounds__(PM_WAVES * 64) k_panel_mfma(
   const int64_t rb = mb0 + ((int64_t)blockIdx.x * PM_WAVES + w) * PM_ROWS;  // wave's first row
   if (rb >= n) return;  // whole wave beyond the last row (uniform)
   const bool full = aligned && rb + PM_ROWS <= n;
-  f32x4_t acc[4];
+  f32x4_t acc[4][NC / 16];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) acc[b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int h = 0; h < NC / 16; ++h) acc[b][h] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   if (full)
-    panel_mfma_wave<ST, true>(W, ldw, n, J, Bh, Bl, lds[w], rb, acc);
+    panel_mfma_wave<ST, true, NC>(W + (int64_t)K0 * ldw, ldw, n, J - K0, Bh, Bl, lds[w], rb, acc);
   else
-    panel_mfma_wave<ST, false>(W, ldw, n, J, Bh, Bl, lds[w], rb, acc);
-  // acc[mb][t] = (U C / s)[row rb + 16 mb + 4 (lane / 16) + t][panel column lane % 16]
-  const int j = lane & 15;
-  if (j >= nb) return;
-  const float sj = scale[j];
-  ST *col = W + (int64_t)(J + j) * ldw;
+    panel_mfma_wave<ST, false, NC>(W + (int64_t)K0 * ldw, ldw, n, J - K0, Bh, Bl, lds[w], rb, acc);
+  // acc[mb][h][t] = (U C / s)[row rb + 16 mb + 4 (lane / 16) + t][panel column 16 h + lane % 16]
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
-    const int64_t r0 = rb + mb * 16 + 4 * (lane >> 4);
-    if (full && r0 >= m) {
-      const uint2 old = *reinterpret_cast<const uint2 *>(col + r0);
-      const uint32_t wd[2] = {old.x, old.y};
-      uint32_t nw[2];
+  for (int h = 0; h < NC / 16; ++h) {
+    const int j = 16 * h + (lane & 15);
+    if (j < nb) {
+      const float sj = scale[j];
+      ST *col = W + (int64_t)(J + j) * ldw;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const float x0 = dec16<ST>((unsigned short)(wd[h] & 0xffff)) - sj * acc[mb][2 * h];
-        const float x1 = dec16<ST>((unsigned short)(wd[h] >> 16)) - sj * acc[mb][2 * h + 1];
-        nw[h] = (uint32_t)enc16<ST>(x0) | ((uint32_t)enc16<ST>(x1) << 16);
-      }
-      *reinterpret_cast<uint2 *>(col + r0) = uint2{nw[0], nw[1]};
-    } else {
+      for (int mb = 0; mb < 4; ++mb) {
+        const int64_t r0 = rb + mb * 16 + 4 * (lane >> 4);
+        if (full && r0 >= m) {
+          const uint2 old = *reinterpret_cast<const uint2 *>(col + r0);
+          const uint32_t wd[2] = {old.x, old.y};
+          uint32_t nw[2];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t r = r0 + t;
-        if (r >= m && r < n)
-          col[r] = cvt_out<ST>((double)(cvt_in<float>(col[r]) - sj * acc[mb][t]));
+          for (int q = 0; q < 2; ++q) {
+            const float x0 = dec16<ST>((unsigned short)(wd[q] & 0xffff)) - sj * acc[mb][h][2 * q];
+            const float x1 = dec16<ST>((unsigned short)(wd[q] >> 16)) - sj * acc[mb][h][2 * q + 1];
+            nw[q] = (uint32_t)enc16<ST>(x0) | ((uint32_t)enc16<ST>(x1) << 16);
+          }
+          *reinterpret_cast<uint2 *>(col + r0) = uint2{nw[0], nw[1]};
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int64_t r = r0 + t;
+            if (r >= m && r < n)
+              col[r] = cvt_out<ST>((double)(cvt_in<float>(col[r]) - sj * acc[mb][h][t]));
+          }
+        }
       }
     }
   }
@@ -868,96 +888,122 @@ __global__ void __launch_bounds__(PM_WAVES * 64) k_qtail16(const ST *__restrict_
 inline int panel_width(int nb) { return nb <= 8 ? 8 : nb <= 16 ? 16 : 32; }
 
 template <typename ST, int NBC>
-void launch_panel_w(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t J, int32_t nb,
+void launch_panel_w(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,
                     const double *C, int aligned, dim3 grid, hipStream_t st, hipEvent_t e0,
                     hipEvent_t e1) {
   if (e0)
     hipExtLaunchKernelGGL((k_panel<ST, NBC>), grid, dim3(PANEL_TPB), 0, st, e0, e1, 0, W, ldw, n, m,
-                          J, nb, C, aligned);
+                          K0, J, nb, C, aligned);
   else
-    hipLaunchKernelGGL((k_panel<ST, NBC>), grid, dim3(PANEL_TPB), 0, st, W, ldw, n, m, J, nb, C,
-                       aligned);
+    hipLaunchKernelGGL((k_panel<ST, NBC>), grid, dim3(PANEL_TPB), 0, st, W, ldw, n, m, K0, J, nb,
+                       C, aligned);
 }
 
 template <typename ST>
-void launch_panel(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t J, int32_t nb, const double *C,
-                  hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+void launch_panel(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,
+                  const double *C, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   constexpr int VEC = sizeof(ST) == 8 ? 2 : 4;
   const int aligned = ((uintptr_t)W % 16 == 0) && ((ldw * (int64_t)sizeof(ST)) % 16 == 0);
   const int64_t threads = (n - (m - m % VEC) + VEC - 1) / VEC;
   const dim3 grid((unsigned)((threads + PANEL_TPB - 1) / PANEL_TPB));
   if (nb <= 8)
-    launch_panel_w<ST, 8>(W, ldw, n, m, J, nb, C, aligned, grid, st, e0, e1);
+    launch_panel_w<ST, 8>(W, ldw, n, m, K0, J, nb, C, aligned, grid, st, e0, e1);
   else if (nb <= 16)
-    launch_panel_w<ST, 16>(W, ldw, n, m, J, nb, C, aligned, grid, st, e0, e1);
+    launch_panel_w<ST, 16>(W, ldw, n, m, K0, J, nb, C, aligned, grid, st, e0, e1);
   else
-    launch_panel_w<ST, 32>(W, ldw, n, m, J, nb, C, aligned, grid, st, e0, e1);
+    launch_panel_w<ST, 32>(W, ldw, n, m, K0, J, nb, C, aligned, grid, st, e0, e1);
 }
 
-// 2-byte storage with panels of at most 16 columns: the panel update runs on
-// matrix cores (k_panel_mfma); otherwise on the vector units (k_panel)
+// 2-byte storage: the panel update runs on matrix cores (k_panel_mfma);
+// otherwise on the vector units (k_panel)
 template <typename ST> constexpr bool panel_on_mfma() { return sizeof(ST) == 2; }
 
+template <typename ST, int NC>
+void launch_panel_mfma(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,
+                       int pw, const double *C, void *mf, hipStream_t st, hipEvent_t e0,
+                       hipEvent_t e1) {
+  const int K = J - K0;
+  const int Kp = (K + PM_KC - 1) / PM_KC * PM_KC;
+  unsigned short *Bh = (unsigned short *)mf;
+  unsigned short *Bl = Bh + (size_t)Kp * NC;
+  float *sc = (float *)(Bl + (size_t)Kp * NC);
+  hipLaunchKernelGGL((k_pconv<ST, NC>), dim3(1), dim3(1024), 0, st, K, nb, pw, Kp,
+                     C + (size_t)K0 * pw, Bh, Bl, sc);
+  const int64_t mb0 = m - (m % 8);
+  const int64_t waves = (n - mb0 + PM_ROWS - 1) / PM_ROWS;
+  const dim3 grid((unsigned)((waves + PM_WAVES - 1) / PM_WAVES));
+  const int aligned = ((uintptr_t)W % 16 == 0) && ((ldw * (int64_t)sizeof(ST)) % 16 == 0);
+  if (e0)
+    hipExtLaunchKernelGGL((k_panel_mfma<ST, NC>), grid, dim3(PM_WAVES * 64), 0, st, e0, e1, 0, W,
+                          ldw, n, m, K0, J, nb, (const unsigned short *)Bh,
+                          (const unsigned short *)Bl, (const float *)sc, aligned);
+  else
+    hipLaunchKernelGGL((k_panel_mfma<ST, NC>), grid, dim3(PM_WAVES * 64), 0, st, W, ldw, n, m, K0,
+                       J, nb, (const unsigned short *)Bh, (const unsigned short *)Bl,
+                       (const float *)sc, aligned);
+}
+
 template <typename ST>
-int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, double *C, double *G,
-                      void *mf, hipStream_t st) {
+int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, double *C,
+                      double *G, void *mf, hipStream_t st) {
   ST *W = (ST *)a.W;
   const int32_t m = a.m, L = a.l + a.m;
   const int64_t ntail = a.n - m;
-  for (int32_t J = 0; J < m; J += panel) {
-    const int32_t nb = m - J < panel ? m - J : panel;
-    if (J > 0) {
-      // store u_{J-1}, then apply the J earlier reflectors to the panel
-      if (ntail > 0) {
-        hipLaunchKernelGGL((k_scale_col<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W,
-                           a.ldw, a.n, m, J - 1, w.ia, w.wstage);
-        RHQR_HIP(hipGetLastError());
-      }
-      const int64_t ne = (int64_t)J * nb;
-      hipLaunchKernelGGL(k_pgram, dim3((ne + 15) / 16), dim3(1024), 0, st, L, J, nb, a.S, a.lds,
-                         a.Z, a.ldz, G);
+  // W_{:, J:J+nb} -= U_{:, K0:J} C_{K0:J}: finish u_{J-1}, form the
+  // coefficients in the sketch space, then one tall product
+  auto apply = [&](int32_t K0, int32_t J, int32_t nb) -> int {
+    if (ntail > 0) {
+      hipLaunchKernelGGL((k_scale_col<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W, a.ldw,
+                         a.n, m, J - 1, w.ia, w.wstage);
       RHQR_HIP(hipGetLastError());
-      const int pw = panel_width(nb);
-      hipLaunchKernelGGL(k_ptri, dim3((J + 255) / 256, pw), dim3(256), 0, st, J, nb, pw, a.T,
-                         a.ldt, G, C);
-      RHQR_HIP(hipGetLastError());
-      if (ntail > 0) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (g_prof.on && prof_pair(&e0, &e1, 1)) return RHQR_ERR_HIP;
-        bool on_mfma = false;
-        if constexpr (panel_on_mfma<ST>()) on_mfma = nb <= 16;
-        if constexpr (panel_on_mfma<ST>()) if (on_mfma) {
-          const int Kp = (J + PM_KC - 1) / PM_KC * PM_KC;
-          unsigned short *Bh = (unsigned short *)mf;
-          unsigned short *Bl = Bh + (size_t)Kp * 16;
-          float *sc = (float *)(Bl + (size_t)Kp * 16);
-          hipLaunchKernelGGL((k_pconv<ST>), dim3(1), dim3(1024), 0, st, J, nb, pw, Kp,
-                             (const double *)C, Bh, Bl, sc);
-          RHQR_HIP(hipGetLastError());
-          const int64_t mb0 = m - (m % 8);
-          const int64_t waves = (a.n - mb0 + PM_ROWS - 1) / PM_ROWS;
-          const dim3 grid((unsigned)((waves + PM_WAVES - 1) / PM_WAVES));
-          const int aligned = ((uintptr_t)W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
-          if (e0)
-            hipExtLaunchKernelGGL((k_panel_mfma<ST>), grid, dim3(PM_WAVES * 64), 0, st, e0, e1, 0,
-                                  W, a.ldw, a.n, m, J, nb, (const unsigned short *)Bh,
-                                  (const unsigned short *)Bl, (const float *)sc, aligned);
-          else
-            hipLaunchKernelGGL((k_panel_mfma<ST>), grid, dim3(PM_WAVES * 64), 0, st, W, a.ldw,
-                               a.n, m, J, nb, (const unsigned short *)Bh,
-                               (const unsigned short *)Bl, (const float *)sc, aligned);
-        }
-        if (!on_mfma) launch_panel<ST>(W, a.ldw, a.n, m, J, nb, (const double *)C, st, e0, e1);
-        RHQR_HIP(hipGetLastError());
-      }
     }
-    for (int32_t j = J; j < J + nb; ++j) {
-      if (j >= 1) {
-        const int rc = tall_typed<ST>(a, w, j, J, st);
+    const int64_t ne = (int64_t)J * nb;
+    hipLaunchKernelGGL(k_pgram, dim3((ne + 15) / 16), dim3(1024), 0, st, L, J, nb, a.S, a.lds, a.Z,
+                       a.ldz, G);
+    RHQR_HIP(hipGetLastError());
+    const int pw = panel_width(nb);
+    hipLaunchKernelGGL(k_ptri, dim3((J - K0 + 255) / 256, pw), dim3(256), 0, st, K0, J, nb, pw,
+                       a.T, a.ldt, G, C);
+    RHQR_HIP(hipGetLastError());
+    if (ntail == 0) return RHQR_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g_prof.on && prof_pair(&e0, &e1, 1)) return RHQR_ERR_HIP;
+    if constexpr (panel_on_mfma<ST>()) {
+      if (nb <= 16)
+        launch_panel_mfma<ST, 16>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, mf, st, e0,
+                                  e1);
+      else
+        launch_panel_mfma<ST, 32>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, mf, st, e0,
+                                  e1);
+    } else {
+      launch_panel<ST>(W, a.ldw, a.n, m, K0, J, nb, (const double *)C, st, e0, e1);
+    }
+    RHQR_HIP(hipGetLastError());
+    return RHQR_OK;
+  };
+  // two levels: outer panels of `outer` columns updated from U_{<J0}, inner
+  // panels of `panel` columns from the reflectors of their outer panel only
+  if (outer < panel) outer = panel;
+  for (int32_t J0 = 0; J0 < m; J0 += outer) {
+    const int32_t nbo = m - J0 < outer ? m - J0 : outer;
+    if (J0 > 0) {
+      const int rc = apply(0, J0, nbo);
+      if (rc) return rc;
+    }
+    for (int32_t J = J0; J < J0 + nbo; J += panel) {
+      const int32_t nb = J0 + nbo - J < panel ? J0 + nbo - J : panel;
+      if (J > J0) {
+        const int rc = apply(J0, J, nb);
         if (rc) return rc;
       }
-      const int rc = step_typed<ST>(a, w, j, j + 1 < m, st);
-      if (rc) return rc;
+      for (int32_t j = J; j < J + nb; ++j) {
+        if (j >= 1) {
+          const int rc = tall_typed<ST>(a, w, j, J, st);
+          if (rc) return rc;
+        }
+        const int rc = step_typed<ST>(a, w, j, j + 1 < m, st);
+        if (rc) return rc;
+      }
     }
   }
   return finish_typed<ST>(a, w, st);
@@ -1180,13 +1226,13 @@ int engine_tall(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st) {
 
 size_t panel_mfma_bytes(int32_t m) {
   const size_t Kp = (size_t)(m + PM_KC - 1) / PM_KC * PM_KC;
-  return align_up(2 * Kp * 16 * sizeof(unsigned short) + 16 * sizeof(float));
+  return align_up(2 * Kp * 32 * sizeof(unsigned short) + 32 * sizeof(float));
 }
 
-int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, double *C, double *G,
-                            void *mf, hipStream_t st) {
+int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, int outer, double *C,
+                            double *G, void *mf, hipStream_t st) {
   if (a.m > MAXM) return RHQR_ERR_UNSUPPORTED;
-  RHQR_DISPATCH(a.dtype, run_blocked_typed<ST>(a, w, panel, C, G, mf, st))
+  RHQR_DISPATCH(a.dtype, run_blocked_typed<ST>(a, w, panel, outer, C, G, mf, st))
 }
 
 int engine_step(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st) {

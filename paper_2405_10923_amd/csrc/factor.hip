@@ -70,6 +70,7 @@ extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, voi
                            void *d_ws, size_t ws_bytes, void *stream) {
   const int scaling = opts & 0xff;
   const int panel = (opts >> 8) & 0xff;
+  const int outer = (opts >> 16) & 0xff;
   if (!h) return -1;
   if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -2;
   if (n != h->n) return -3;
@@ -85,7 +86,8 @@ extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, voi
   if (ldr < m) return -12;
   if (d_Q && ldq < n) return -14;
   if ((scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) || panel > 32 ||
-      (opts >> 16) != 0)
+      (opts >> 24) != 0 || (outer != 0 && (panel < 2 || outer <= panel || outer > 32 ||
+                                            outer % panel != 0)))
     return -15;
   if (!d_ws) return -16;
   if (m > 1024) return RHQR_ERR_UNSUPPORTED;
@@ -124,7 +126,7 @@ extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, voi
   a.rows = h->d_rows;
   a.omega = h->d_omega;
   a.defer = 1;
-  rc = panel >= 2 ? run_column_loop_blocked(a, w.loop, panel, w.C, w.G, w.mf, st)
+  rc = panel >= 2 ? run_column_loop_blocked(a, w.loop, panel, outer, w.C, w.G, w.mf, st)
                   : run_column_loop(a, w.loop, st);
   if (rc) return rc;
   if (d_Q) rc = launch_thin_q(dtype, n, m, d_W, ldw, d_S, lds, d_T, ldt, w.Mq, w.qmf, d_Q, ldq, st);

@@ -15,7 +15,7 @@ from tests.gpu_util import cuda_or_skip, to_gpu, to_np, rel, log
 pytestmark = pytest.mark.gpu
 
 
-def _run(kind, n, m, l, kappa, seed=0, scaling=0, dtype="float64", want_q=True, panel=0):
+def _run(kind, n, m, l, kappa, seed=0, scaling=0, dtype="float64", want_q=True, panel=0, outer=0):
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
     W = synthetic_matrix(n, m, kappa, seed=seed)
@@ -26,19 +26,23 @@ def _run(kind, n, m, l, kappa, seed=0, scaling=0, dtype="float64", want_q=True, 
     # Gaussian: the oracle's Omega (its own Philox draw) is handed to the GPU
     om = to_gpu(osketch.omega) if kind == rhqr.GAUSS else None
     sk = rhqr.Sketch(kind, n, m, l, seed=seed + 1, omega=om)
-    out = rhqr.factor(sk, Wd, scaling=scaling, want_q=want_q, panel=panel)
+    out = rhqr.factor(sk, Wd, scaling=scaling, want_q=want_q, panel=panel, outer=outer)
     torch.cuda.synchronize()
     res = {k: to_np(v) for k, v in out.items() if k in ("U", "S", "T", "R") or (k == "Q" and v is not None)}
     res["info"] = rhqr.status(out["ws"])
     return W, Win, res, osketch
 
 
-@pytest.mark.parametrize("panel", [0, 16, 5])
+# (panel, outer): column schedule, one-level panels, two-level panels
+SCHED = [(0, 0), (16, 0), (5, 0), (8, 32), (5, 15)]
+
+
+@pytest.mark.parametrize("panel,outer", SCHED)
 @pytest.mark.parametrize("n,m,l", [(300, 7, 40), (4096, 32, 128), (3 * 4096 + 777, 24, 96),
                                    (2 * 4096 + 5, 70, 200)])
-def test_f64_srht_elementwise(n, m, l, panel):
-    log(f"rhqr f64 srht n={n} m={m} l={l} panel={panel}")
-    W, Win, g, sk = _run(0, n, m, l, 2, panel=panel)
+def test_f64_srht_elementwise(n, m, l, panel, outer):
+    log(f"rhqr f64 srht n={n} m={m} l={l} panel={panel} outer={outer}")
+    W, Win, g, sk = _run(0, n, m, l, 2, panel=panel, outer=outer)
     ref = orq.rhqr_left(W, sk)
     assert g["info"] == 0
     assert rel(g["R"], ref["R"]) < 1e-12
@@ -61,10 +65,10 @@ def test_f64_scaling_sqrt2():
     assert np.allclose(np.sum(g["S"] ** 2, axis=0), 2.0, rtol=1e-13)
 
 
-@pytest.mark.parametrize("panel", [0, 8])
-def test_f64_gauss_elementwise(panel):
+@pytest.mark.parametrize("panel,outer", [(0, 0), (8, 0), (4, 16)])
+def test_f64_gauss_elementwise(panel, outer):
     n, m, l = 2 * 4096 + 300, 20, 80
-    W, Win, g, sk = _run(1, n, m, l, 2, panel=panel)
+    W, Win, g, sk = _run(1, n, m, l, 2, panel=panel, outer=outer)
     ref = orq.rhqr_left(W, sk)
     assert rel(g["R"], ref["R"]) < 1e-12
     assert rel(g["S"], ref["S"]) < 1e-12
@@ -91,12 +95,12 @@ def test_c1_ill_conditioned(panel):
     assert np.linalg.norm(g["R"] - ref["R"]) <= 1e-12 * np.linalg.norm(ref["R"]) * 1e4
 
 
-@pytest.mark.parametrize("panel", [0, 8, 16])
+@pytest.mark.parametrize("panel,outer", [(0, 0), (8, 0), (16, 0), (4, 16), (8, 32)])
 @pytest.mark.parametrize("dt,tol", [("float32", 1e-5), ("float16", 1e-2), ("bfloat16", 1e-2)])
-def test_low_precision_bounds(dt, tol, panel):
-    n, m, l = 3 * 4096 + 77, 24, 96
+def test_low_precision_bounds(dt, tol, panel, outer):
+    n, m, l = 3 * 4096 + 77, 40, 160
     torch = cuda_or_skip()
-    W, Win, g, sk = _run(0, n, m, l, 6, dtype=dt, panel=panel)
+    W, Win, g, sk = _run(0, n, m, l, 6, dtype=dt, panel=panel, outer=outer)
     Q = g["Q"]
     ef = metrics.fact_error(Win, Q, g["R"])
     eo = metrics.orth_error(osk.rh_sketch(Q, sk))

@@ -16,8 +16,8 @@ products (no library kernel is involved in a check):
   columns, backward error within the tolerance.
 
 Workloads: W = G diag(s) V with singular values 1..1e-12 (2^20 x 128, SRHT and
-Gaussian l = 512) and 1..1e-14 (2^22 x 256, SRHT l = 1024, panels of 16: the
-configuration bench.py times).  float64 tolerance 1e-12."""
+Gaussian l = 512) and 1..1e-14 (2^22 x 256, SRHT l = 1024, two-level panels:
+the configuration bench.py times).  float64 tolerance 1e-12."""
 import numpy as np
 import pytest
 
@@ -141,22 +141,23 @@ def test_c2_f64_recrhqr_fullsize(mode):
             assert np.max(np.abs(res) / np.maximum(scale, 1e-300)) <= 64 * (j + 1) * 2.0 ** -53, j
 
 
-def test_c3_f64_blocked_fullsize():
-    """2^22 x 256, cond 1e14, SRHT l = 1024, panels of 16: the benchmark's
-    float64 configuration."""
+@pytest.mark.parametrize("panel,outer", [(8, 32), (16, 0)])
+def test_c3_f64_blocked_fullsize(panel, outer):
+    """2^22 x 256, cond 1e14, SRHT l = 1024; panels of 8 in outer panels of 32
+    (the benchmark's float64 configuration) and one level of 16."""
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
     n, m, l = 1 << 22, 256, 1024
-    log(f"c3 rhqr f64 blocked: W {n} x {m} cond 1e14, l={l}")
+    log(f"c3 rhqr f64 blocked {panel}/{outer}: W {n} x {m} cond 1e14, l={l}")
     W0 = _gen(torch, n, m, 14, seed=0)
     sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=0)
     osketch = osk.Sketch(osk.SRHT, n, m, l, seed=0)
     Wd = W0.clone()
-    out = rhqr.factor(sk, Wd, panel=16)
+    out = rhqr.factor(sk, Wd, panel=panel, outer=outer)
     torch.cuda.synchronize()
     assert rhqr.status(out["ws"]) == 0
     _checks(torch, W0, out["U"], out["S"], out["T"], out["R"], osketch, m, (0, 1, 128, 255),
-            "c3 f64 panel=16")
+            f"c3 f64 panel={panel} outer={outer}")
 
 
 @pytest.mark.parametrize("dt", ["float32", "float16"])
