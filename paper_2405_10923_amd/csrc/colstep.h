@@ -428,17 +428,24 @@ __device__ __forceinline__ void red_block(const ColProblem &P, int32_t j, int ne
     double v = 0.0;
     if (j >= 1) {
       if (head) {
+        // loads with clamped indices, issued together; terms with p >= pe
+        // are zeros, as before
         const int pe = valid ? min(j, k + 1) : 0;
-        for (int p0 = g; p0 < pe; p0 += 16 * RED_NP) {
+        const int kc = valid ? k : 0;
+        for (int p0 = g; p0 < j; p0 += 16 * RED_NP) {
+          double sv[RED_NP], cv[RED_NP];
+#pragma unroll
+          for (int b = 0; b < RED_NP; ++b) {
+            const int p = min(p0 + 16 * b, j - 1);
+            sv[b] = S[kc + (int64_t)p * lds];
+            cv[b] = c[p];
+          }
           double t[RED_NP];
 #pragma unroll
           for (int b = 0; b < RED_NP; ++b) {
             const int p = p0 + 16 * b;
-            t[b] = 0.0;
-            if (p < pe) {
-              const double cp = (defer && p == j - 1) ? clast : c[p];
-              t[b] = S[k + (int64_t)p * lds] * cp;
-            }
+            const double cp = (defer && p == j - 1) ? clast : cv[b];
+            t[b] = p < pe ? sv[b] * cp : 0.0;
           }
 #pragma unroll
           for (int b = 0; b < RED_NP; ++b) v += t[b];
@@ -553,6 +560,7 @@ __device__ __forceinline__ StepScalars step_scalars(const double *y, double ss, 
 // e_j to fs.  The partial sums, the rows of T and the pivot row of S are all
 // loaded before the first wait.
 constexpr int FIN_NQ = 4;  // T entries per lane loaded together
+constexpr int FIN_GB = 8;  // reduction groups' partial sums loaded together
 
 __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int next, int bid,
                                           int nblk) {
@@ -597,14 +605,27 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
     tr[i] = (pw && qr < j) ? Tt[qr + (int64_t)p * m] : 0.0;
     tc[i] = (pw && needc && qc <= p) ? T[qc + (int64_t)p * ldt] : 0.0;
   }
-  // thread q: the partial dot products d_q, e_q and the pivot-row entry S_{j,q}
+  // thread q: the partial dot products d_q, e_q and the pivot-row entry
+  // S_{j,q}; the partial sums are loaded FIN_GB groups at a time (clamped
+  // indices, issued together) and added in increasing g
   const int q = threadIdx.x;
   double dv = 0.0, ev = 0.0, sjq = 0.0;
   if (q < j) {
     sjq = S[j + (int64_t)q * lds];
-    for (int g = 0; g < gred; ++g) {
-      dv += dpart[(int64_t)g * m + q];
-      if (needc) ev += epart[(int64_t)g * m + q];
+    for (int g0 = 0; g0 < gred; g0 += FIN_GB) {
+      double dl[FIN_GB], el[FIN_GB];
+#pragma unroll
+      for (int b = 0; b < FIN_GB; ++b) {
+        const int g = min(g0 + b, gred - 1);
+        dl[b] = dpart[(int64_t)g * m + q];
+        el[b] = needc ? epart[(int64_t)g * m + q] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < FIN_GB; ++b)
+        if (g0 + b < gred) {
+          dv += dl[b];
+          if (needc) ev += el[b];
+        }
     }
   }
   if (w == 0) {
