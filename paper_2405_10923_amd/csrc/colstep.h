@@ -764,16 +764,29 @@ __device__ __forceinline__ void ptri_entry(int32_t J0, int32_t J, int32_t nb, in
 }
 
 // W[m:n, J:J+nb] -= U[m:n, K0:J] C_{K0:J}.  Each thread streams VEC
-// consecutive rows of U (one 16-byte load per column) against all NBC panel
-// columns, whose coefficients are read with uniform (scalar) loads; U is read
-// exactly once.
+// consecutive rows of U (one 16- or 8-byte load per column) against all NBC
+// panel columns, whose coefficients are read with uniform (scalar) loads; U
+// is read exactly once.
 constexpr int PANEL_TPB = 256;
 constexpr int PANEL_KB = 8;  // columns of U whose loads are in flight together
+
+// rows per thread: 16-byte loads, except 8-byte ones for 32-column panels of
+// 4- and 8-byte types (fewer accumulator registers, more waves per SIMD)
+template <typename ST, int NBC> constexpr int panel_vec() {
+  return sizeof(ST) == 2 ? 4 : (NBC >= 32 ? 8 / (int)sizeof(ST) : 16 / (int)sizeof(ST));
+}
 
 template <typename ST, typename CT, int VEC>
 __device__ __forceinline__ void panel_load(const ST *p, CT *x) {
   if constexpr (sizeof(ST) * VEC == 16) {
     vload<ST, CT, true>(p, x);
+  } else if constexpr (sizeof(ST) == 8) {  // one float64
+    x[0] = (CT)__builtin_nontemporal_load(p);
+  } else if constexpr (sizeof(ST) == 4) {  // two float32
+    typedef float f32x2v __attribute__((ext_vector_type(2)));
+    const f32x2v f = __builtin_nontemporal_load(reinterpret_cast<const f32x2v *>(p));
+    x[0] = (CT)f.x;
+    x[1] = (CT)f.y;
   } else {  // 8 bytes: four 2-byte values
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     const u32x2 u = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
@@ -793,6 +806,14 @@ template <typename ST, typename CT, int VEC>
 __device__ __forceinline__ void panel_store(ST *p, const CT *x) {
   if constexpr (sizeof(ST) * VEC == 16) {
     vstore<ST, CT>(p, x);
+  } else if constexpr (sizeof(ST) == 8) {
+    *p = (double)x[0];
+  } else if constexpr (sizeof(ST) == 4) {
+    typedef float f32x2v __attribute__((ext_vector_type(2)));
+    f32x2v f;
+    f.x = (float)x[0];
+    f.y = (float)x[1];
+    *reinterpret_cast<f32x2v *>(p) = f;
   } else {  // 8 bytes: four 2-byte values
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     u32x2 u;
@@ -807,7 +828,7 @@ __device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int
                                             int32_t K0, int32_t J, int32_t nb,
                                             const double *__restrict__ Ct, int aligned, int bid) {
   using CT = typename CompT<ST>::type;
-  constexpr int VEC = sizeof(ST) == 8 ? 2 : 4;   // rows per thread
+  constexpr int VEC = panel_vec<ST, NBC>();  // rows per thread
   const int64_t mb = m - (m % VEC);  // aligned start; head rows < m are not written
   const int64_t rb = mb + (int64_t)bid * PANEL_TPB * VEC;  // first row of the workgroup
   const int64_t r0 = rb + (int64_t)threadIdx.x * VEC;

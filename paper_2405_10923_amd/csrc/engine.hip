@@ -889,8 +889,10 @@ inline int panel_width(int nb) { return nb <= 8 ? 8 : nb <= 16 ? 16 : 32; }
 
 template <typename ST, int NBC>
 void launch_panel_w(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,
-                    const double *C, int aligned, dim3 grid, hipStream_t st, hipEvent_t e0,
-                    hipEvent_t e1) {
+                    const double *C, int aligned, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  constexpr int VEC = panel_vec<ST, NBC>();
+  const int64_t threads = (n - (m - m % VEC) + VEC - 1) / VEC;
+  const dim3 grid((unsigned)((threads + PANEL_TPB - 1) / PANEL_TPB));
   if (e0)
     hipExtLaunchKernelGGL((k_panel<ST, NBC>), grid, dim3(PANEL_TPB), 0, st, e0, e1, 0, W, ldw, n, m,
                           K0, J, nb, C, aligned);
@@ -902,16 +904,13 @@ void launch_panel_w(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_
 template <typename ST>
 void launch_panel(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,
                   const double *C, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  constexpr int VEC = sizeof(ST) == 8 ? 2 : 4;
   const int aligned = ((uintptr_t)W % 16 == 0) && ((ldw * (int64_t)sizeof(ST)) % 16 == 0);
-  const int64_t threads = (n - (m - m % VEC) + VEC - 1) / VEC;
-  const dim3 grid((unsigned)((threads + PANEL_TPB - 1) / PANEL_TPB));
   if (nb <= 8)
-    launch_panel_w<ST, 8>(W, ldw, n, m, K0, J, nb, C, aligned, grid, st, e0, e1);
+    launch_panel_w<ST, 8>(W, ldw, n, m, K0, J, nb, C, aligned, st, e0, e1);
   else if (nb <= 16)
-    launch_panel_w<ST, 16>(W, ldw, n, m, K0, J, nb, C, aligned, grid, st, e0, e1);
+    launch_panel_w<ST, 16>(W, ldw, n, m, K0, J, nb, C, aligned, st, e0, e1);
   else
-    launch_panel_w<ST, 32>(W, ldw, n, m, K0, J, nb, C, aligned, grid, st, e0, e1);
+    launch_panel_w<ST, 32>(W, ldw, n, m, K0, J, nb, C, aligned, st, e0, e1);
 }
 
 // 2-byte storage: the panel update runs on matrix cores (k_panel_mfma);
