@@ -14,8 +14,10 @@ namespace {
 // workgroups per compute unit overlap one's loads with the other's transform.
 constexpr int SK_TPB = 1024, SK_TPW = 2;
 
-template <typename A> __device__ void fwht_two_tiles(A *s) {
-#pragma unroll 1
+template <typename A> __device__ __forceinline__ void fwht_two_tiles(A *s) {
+  // fully unrolled: no inner loop, so the waits for loads in flight across
+  // the transform stay exact
+#pragma unroll
   for (int pass = 0; pass < 3; ++pass) {
     lds_barrier();
     const int sh = 4 * pass;
@@ -37,11 +39,19 @@ template <typename A> __device__ void fwht_two_tiles(A *s) {
   lds_barrier();
 }
 
-// Each workgroup walks the row groups g = blockIdx.x, blockIdx.x + gt, ... of
-// column blockIdx.y; the loads of group g + gt are issued before the transform
-// of group g (LDS-only barriers keep them in flight), so HBM reads overlap the
-// in-LDS butterflies.
-template <typename ST, typename AT, int QA>
+// Row groups whose loads are in flight ahead of the one being transformed:
+// about 128 bytes of the column per thread for every storage type.
+template <typename ST> constexpr int sk_prefetch() { return sizeof(ST) == 8 ? 2 : sizeof(ST) == 4 ? 4 : 8; }
+
+// Each workgroup walks the row groups g = gb, gb + gt, ... of column c (the
+// i-th of its groups is gb + i gt).  Groups that lie entirely inside the n
+// rows of a 16-byte aligned column are loaded PF at a time (past the last
+// full group the last one is read again and its extra transforms are not
+// accumulated, so every iteration issues the same loads); LDS-only barriers
+// keep the later groups' loads in flight across the butterflies of the
+// earlier ones.  The ragged last group (and every group of an unaligned
+// column) is loaded element by element.
+template <typename ST, typename AT, int QA, int PF = sk_prefetch<ST>()>
 __device__ __forceinline__ void srht_cols_block(const ST *__restrict__ X, int64_t ldx, int64_t n,
                                                 int32_t m, int32_t l, int64_t ngroups, int gt,
                                                 const uint64_t *__restrict__ signs,
@@ -52,63 +62,108 @@ __device__ __forceinline__ void srht_cols_block(const ST *__restrict__ X, int64_
   constexpr int ROWS = TILE * SK_TPW;
   constexpr int NV = ROWS / (SK_TPB * VEC);
   static_assert(NV >= 1, "tile too small for the vector width");
+  static_assert(VEC <= 32, "a thread's rows must share one 32-bit sign word");
   __shared__ AT s[SK_TPW * TILE_PAD];
   const ST *x = X + (int64_t)c * ldx;
+  // sign bit i is bit i % 32 of 32-bit word i / 32 (the 64-bit words, little-endian)
+  const uint32_t *__restrict__ sg32 = reinterpret_cast<const uint32_t *>(signs);
   double acc[QA];
+  int r2q[QA];
+  uint64_t r1q[QA];
 #pragma unroll
-  for (int a = 0; a < QA; ++a) acc[a] = 0.0;
-  AT xv[NV][VEC];
-  uint64_t wd[NV];
-  auto fetch = [&](int64_t g) {
-    const int64_t base = g * ROWS;
-    const bool fast = aligned && base + ROWS <= n;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int64_t i0 = base + VEC * (threadIdx.x + SK_TPB * v);
-      if (fast) {
-        vload<ST, AT, true>(x + i0, xv[v]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) xv[v][e] = (i0 + e < n) ? cvt_in<AT>(x[i0 + e]) : (AT)0;
-      }
-      wd[v] = i0 < n ? signs[i0 >> 6] : 0ull;
-    }
-  };
-  int64_t g = gb;
-  if (g < ngroups) fetch(g);
-  for (; g < ngroups; g += gt) {
+  for (int a = 0; a < QA; ++a) {
+    acc[a] = 0.0;
+    const int q = threadIdx.x + SK_TPB * a;
+    const int32_t r = q < l ? rows[q] : 0;
+    r2q[a] = tpad(r & (TILE - 1));
+    r1q[a] = (uint64_t)(r >> TILE_LOG);
+  }
+  const int64_t cnt = gb < ngroups ? (ngroups - 1 - gb) / gt + 1 : 0;
+  const int64_t nfullg = n / ROWS;  // groups entirely inside the n rows
+  const int64_t cntf = !aligned ? 0 : (gb < nfullg ? (nfullg - 1 - gb) / gt + 1 : 0);
+  // signed, transformed group g in LDS, then its samples into acc (if live)
+  // xs: the group's values, raw (RAW: 16-byte words as loaded, decoded here)
+  // or already in AT
+  auto transform = [&](int64_t g, const auto &xs, const uint32_t (&ws)[NV], bool live,
+                       auto &&between) {
     const int64_t base = g * ROWS;
     lds_barrier();  // the previous group's samples have been read
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int li0 = VEC * (threadIdx.x + SK_TPB * v);
       const int64_t i0 = base + li0;
+      AT xd[VEC];
+      if constexpr (std::is_same<std::decay_t<decltype(xs[0])>, u32x4>::value) {
+        vdecode<ST, AT>(xs[v], xd);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) xd[e] = xs[v][e];
+      }
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
-        const int64_t i = i0 + e;
-        AT val = (i >= m && i < n) ? xv[v][e] : (AT)0;
-        if ((wd[v] >> (i & 63)) & 1ull) val = -val;
+        const int64_t r = i0 + e;
+        AT val = (r >= m && r < n) ? xd[e] : (AT)0;
+        if ((ws[v] >> (r & 31)) & 1u) val = -val;
         const int li = li0 + e;
         s[(li >> TILE_LOG) * TILE_PAD + tpad(li & (TILE - 1))] = val;
       }
     }
-    if (g + gt < ngroups) fetch(g + gt);
+    between();
     fwht_two_tiles(s);
     const uint64_t t0 = (uint64_t)g * SK_TPW;
 #pragma unroll
     for (int a = 0; a < QA; ++a) {
       const int q = threadIdx.x + SK_TPB * a;
-      if (q < l) {
-        const int32_t r = rows[q];
-        const int r2 = tpad(r & (TILE - 1));
-        const uint64_t r1 = (uint64_t)(r >> TILE_LOG);
+      if (q < l && live) {
 #pragma unroll
         for (int tt = 0; tt < SK_TPW; ++tt) {
-          const double h = (double)s[tt * TILE_PAD + r2];
-          acc[a] += (__popcll(r1 & (t0 + tt)) & 1) ? -h : h;
+          const double hv = (double)s[tt * TILE_PAD + r2q[a]];
+          acc[a] += (__popcll(r1q[a] & (t0 + tt)) & 1) ? -hv : hv;
         }
       }
     }
+  };
+  if (cntf > 0) {
+    // PF groups per iteration, all their loads issued first (as raw 16-byte
+    // words), then transformed in order: each transform waits only for its
+    // own group while the later groups' loads are still in flight.  No load
+    // is carried across iterations (the compiler drains every outstanding
+    // load at a loop header that has loads in flight from the back edge).
+    for (int64_t i0 = 0; i0 < cntf; i0 += PF) {
+      u32x4 xv[PF][NV];
+      uint32_t wd[PF][NV];
+#pragma unroll
+      for (int sl = 0; sl < PF; ++sl) {
+        const int64_t i = i0 + sl;
+        const int64_t base = (gb + (i < cntf ? i : cntf - 1) * (int64_t)gt) * ROWS;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const int64_t r0 = base + VEC * (threadIdx.x + SK_TPB * v);
+          xv[sl][v] = vraw_nt(x + r0);
+          wd[sl][v] = sg32[r0 >> 5];
+        }
+      }
+#pragma unroll
+      for (int sl = 0; sl < PF; ++sl) {
+        const int64_t i = i0 + sl;
+        const bool live = i < cntf;  // uniform
+        transform(gb + (live ? i : cntf - 1) * (int64_t)gt, xv[sl], wd[sl], live, [] {});
+      }
+    }
+  }
+  for (int64_t i = cntf; i < cnt; ++i) {
+    const int64_t g = gb + i * (int64_t)gt;
+    const int64_t base = g * ROWS;
+    AT xs[NV][VEC];
+    uint32_t ws[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int64_t i0 = base + VEC * (threadIdx.x + SK_TPB * v);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) xs[v][e] = (i0 + e < n) ? cvt_in<AT>(x[i0 + e]) : (AT)0;
+      ws[v] = i0 < n ? sg32[i0 >> 5] : 0u;
+    }
+    transform(g, xs, ws, true, [] {});
   }
 #pragma unroll
   for (int a = 0; a < QA; ++a) {
