@@ -523,6 +523,7 @@ __global__ void __launch_bounds__(PANEL_TPB) k_trsm_blk(const ST *__restrict__ B
 // loads before the current chunk's products.
 constexpr int PM_ROWS = 64;                // rows per wave
 constexpr int PM_KC = 32;                  // columns of U per chunk
+constexpr int PM_KP = 2 * PM_KC;           // chunks go in pairs; coefficient rows padded to this
 constexpr int PM_RS = PM_ROWS + 8;         // LDS stride (elements) of one column slice
 constexpr int PM_WAVES = 4;
 
@@ -540,7 +541,7 @@ template <typename ST> __device__ __forceinline__ float dec16(unsigned short b) 
 // Scales and split coefficients in the MFMA B-operand order: for column group
 // g (columns 4g..4g+3 of U, i.e. rows of C) and panel column j < NC, the four
 // values sit at B[(g * NC + j) * 4 + t].  Rows k >= J and columns j >= nb are
-// zero; Kp = J rounded up to PM_KC.  One workgroup of 16 waves, wave w
+// zero; Kp = J rounded up to PM_KP.  One workgroup of 16 waves, wave w
 // scaling columns w, w + 16, ...
 template <typename ST, int NC>
 __global__ void __launch_bounds__(1024) k_pconv(int32_t J, int32_t nb, int32_t pw, int32_t Kp,
@@ -604,7 +605,64 @@ __device__ __forceinline__ f32x4_t mfma16(const unsigned short (&a)[4], const ui
 // One wave's 64 rows.  FULL: all rows in bounds and 16-byte aligned; the
 // column index of the loads is clamped to J - 1 (finite values, multiplied by
 // the zero padding of B), so the loads carry no condition.  !FULL (the last,
-// ragged wave): guarded element loads.
+// ragged wave): guarded element loads.  Chunks of PM_KC columns go in pairs:
+// both chunks' columns and coefficients are loaded first (the first chunk's
+// before the second's), so the second chunk's loads are in flight during the
+// first chunk's transpose and products, and no load is carried across loop
+// iterations.
+template <typename ST, bool FULL>
+__device__ __forceinline__ void mfma_fetch(const ST *__restrict__ U, int64_t ldu, int64_t n,
+                                           int32_t K, int64_t rb, int k0, u32x4 (&buf)[4]) {
+  const int lane = threadIdx.x & 63;
+  // load lane: column lc (+ 8 r), rows rb + lr .. + 7
+  const int lc = lane >> 3, lr = (lane & 7) * 8;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int k = k0 + lc + 8 * r;
+    if constexpr (FULL) {
+      const int kc = k < K ? k : K - 1;
+      buf[r] = vraw_nt(U + (int64_t)kc * ldu + rb + lr);
+    } else {
+      const ST *src = U + (int64_t)k * ldu + rb + lr;
+      unsigned short e[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        e[q] = (k < K && rb + lr + q < n) ? __builtin_bit_cast(unsigned short, src[q]) : 0;
+      buf[r] = u32x4{(uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2] | ((uint32_t)e[3] << 16),
+                     (uint32_t)e[4] | ((uint32_t)e[5] << 16), (uint32_t)e[6] | ((uint32_t)e[7] << 16)};
+    }
+  }
+}
+
+// the chunk's columns into this wave's LDS slice (column k at sl[k * PM_RS +
+// row]), then its products with NC coefficient columns (B-operand words of
+// 16 columns each, hi and lo parts)
+template <typename ST, int NC>
+__device__ __forceinline__ void mfma_chunk(const u32x4 (&buf)[4], const uint2 (&bh)[PM_KC / 16][NC / 16],
+                                           const uint2 (&bl)[PM_KC / 16][NC / 16],
+                                           unsigned short *sl, f32x4_t (&acc)[4][NC / 16]) {
+  const int lane = threadIdx.x & 63;
+  const int lc = lane >> 3, lr = (lane & 7) * 8;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    *reinterpret_cast<u32x4 *>(sl + (lc + 8 * r) * PM_RS + lr) = buf[r];
+#pragma unroll
+  for (int kk = 0; kk < PM_KC / 16; ++kk) {
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      unsigned short a[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        a[t] = sl[(kk * 16 + 4 * (lane >> 4) + t) * PM_RS + mb * 16 + (lane & 15)];
+#pragma unroll
+      for (int h = 0; h < NC / 16; ++h) {
+        acc[mb][h] = mfma16<ST>(a, bh[kk][h], acc[mb][h]);
+        acc[mb][h] = mfma16<ST>(a, bl[kk][h], acc[mb][h]);
+      }
+    }
+  }
+}
+
 template <typename ST, bool FULL, int NC>
 __device__ __forceinline__ void panel_mfma_wave(ST *__restrict__ W, int64_t ldw, int64_t n,
                                                 int32_t J, const unsigned short *__restrict__ Bh,
@@ -612,36 +670,7 @@ __device__ __forceinline__ void panel_mfma_wave(ST *__restrict__ W, int64_t ldw,
                                                 unsigned short *sl, int64_t rb,
                                                 f32x4_t (&acc)[4][NC / 16]) {
   const int lane = threadIdx.x & 63;
-  // load lane: column lc (+ 8 r), rows rb + lr .. + 7
-  const int lc = lane >> 3, lr = (lane & 7) * 8;
-  u32x4 buf[4];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k = k0 + lc + 8 * r;
-      if constexpr (FULL) {
-        const int kc = k < J ? k : J - 1;
-        buf[r] = vraw_nt(W + (int64_t)kc * ldw + rb + lr);
-      } else {
-        const ST *src = W + (int64_t)k * ldw + rb + lr;
-        unsigned short e[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          e[q] = (k < J && rb + lr + q < n) ? __builtin_bit_cast(unsigned short, src[q]) : 0;
-        buf[r] = u32x4{(uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2] | ((uint32_t)e[3] << 16),
-                       (uint32_t)e[4] | ((uint32_t)e[5] << 16), (uint32_t)e[6] | ((uint32_t)e[7] << 16)};
-      }
-    }
-  };
-  fetch(0);
-  for (int k0 = 0; k0 < J; k0 += PM_KC) {
-    // transpose the chunk into this wave's LDS slice: column k at sl[k * PM_RS + row]
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      *reinterpret_cast<u32x4 *>(sl + (lc + 8 * r) * PM_RS + lr) = buf[r];
-    // this chunk's coefficients, loaded before the next chunk's columns so
-    // that waiting for them does not wait for those (loads complete in order)
-    uint2 bh[PM_KC / 16][NC / 16], bl[PM_KC / 16][NC / 16];
+  auto coefs = [&](int k0, uint2 (&bh)[PM_KC / 16][NC / 16], uint2 (&bl)[PM_KC / 16][NC / 16]) {
 #pragma unroll
     for (int kk = 0; kk < PM_KC / 16; ++kk) {
       const int g = (k0 >> 2) + kk * 4 + (lane >> 4);  // column group of this lane
@@ -652,26 +681,18 @@ __device__ __forceinline__ void panel_mfma_wave(ST *__restrict__ W, int64_t ldw,
         bl[kk][h] = *reinterpret_cast<const uint2 *>(Bl + o);
       }
     }
-    // next chunk's columns, in flight during the products (FULL: always, with
-    // clamped columns after the last chunk, so the loop has no branch and the
-    // waits for the coefficients count the prefetch exactly)
-    if (FULL || k0 + PM_KC < J) fetch(k0 + PM_KC);
-    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
-#pragma unroll
-    for (int kk = 0; kk < PM_KC / 16; ++kk) {
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        unsigned short a[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          a[t] = sl[(kk * 16 + 4 * (lane >> 4) + t) * PM_RS + mb * 16 + (lane & 15)];
-#pragma unroll
-        for (int h = 0; h < NC / 16; ++h) {
-          acc[mb][h] = mfma16<ST>(a, bh[kk][h], acc[mb][h]);
-          acc[mb][h] = mfma16<ST>(a, bl[kk][h], acc[mb][h]);
-        }
-      }
-    }
+  };
+  for (int k0 = 0; k0 < J; k0 += PM_KP) {
+    u32x4 ba[4], bb[4];
+    uint2 ha[PM_KC / 16][NC / 16], la[PM_KC / 16][NC / 16];
+    uint2 hb[PM_KC / 16][NC / 16], lb[PM_KC / 16][NC / 16];
+    coefs(k0, ha, la);
+    mfma_fetch<ST, FULL>(W, ldw, n, J, rb, k0, ba);
+    coefs(k0 + PM_KC, hb, lb);
+    mfma_fetch<ST, FULL>(W, ldw, n, J, rb, k0 + PM_KC, bb);
+    __builtin_amdgcn_sched_barrier(0);  // all of the pair's loads issued first
+    mfma_chunk<ST, NC>(ba, ha, la, sl, acc);
+    mfma_chunk<ST, NC>(bb, hb, lb, sl, acc);
   }
 }
 
@@ -746,10 +767,12 @@ __global__ void __launch_bounds__(256) k_qconv(int32_t m, int32_t Kp,
                                               unsigned short *__restrict__ Bh,
                                               unsigned short *__restrict__ Bl,
                                               float *__restrict__ scale) {
-  const int j = blockIdx.x;  // column of Mq
+  const int j = blockIdx.x;  // column of Mq (columns j >= m of the last tile are zero)
+  const bool col = j < m;
   __shared__ float sc;
   double mx = 0.0;
-  for (int k = threadIdx.x; k < m; k += blockDim.x) mx = fmax(mx, fabs(Mq[k + (int64_t)j * m]));
+  if (col)
+    for (int k = threadIdx.x; k < m; k += blockDim.x) mx = fmax(mx, fabs(Mq[k + (int64_t)j * m]));
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
   __shared__ double wm[4];
   if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
@@ -764,7 +787,7 @@ __global__ void __launch_bounds__(256) k_qconv(int32_t m, int32_t Kp,
   __syncthreads();
   const int tile = j / QH_NC, jt = j % QH_NC, Kg = Kp / 4;
   for (int k = threadIdx.x; k < Kp; k += blockDim.x) {
-    const double v = k < m ? Mq[k + (int64_t)j * m] / (double)sc : 0.0;
+    const double v = (col && k < m) ? Mq[k + (int64_t)j * m] / (double)sc : 0.0;
     const unsigned short h = enc16<ST>((float)v);
     const unsigned short lo = enc16<ST>((float)(v - (double)dec16<ST>(h)));
     const int64_t o = ((((int64_t)tile * Kg + (k >> 2)) * QH_NC + jt) << 2) + (k & 3);
@@ -781,33 +804,9 @@ __device__ __forceinline__ void qtail16_wave(const ST *__restrict__ U, int64_t l
                                              unsigned short *sl, int64_t rb,
                                              f32x4_t (&acc)[4][QH_NC / 16]) {
   const int lane = threadIdx.x & 63;
-  const int lc = lane >> 3, lr = (lane & 7) * 8;
   const int Kg = Kp / 4;
-  u32x4 buf[4];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k = k0 + lc + 8 * r;
-      if constexpr (FULL) {
-        const int kc = k < m ? k : m - 1;  // clamped: finite values times zero coefficients
-        buf[r] = vraw_nt(U + (int64_t)kc * ldu + rb + lr);
-      } else {
-        const ST *src = U + (int64_t)k * ldu + rb + lr;
-        unsigned short e[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          e[q] = (k < m && rb + lr + q < rows) ? __builtin_bit_cast(unsigned short, src[q]) : 0;
-        buf[r] = u32x4{(uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2] | ((uint32_t)e[3] << 16),
-                       (uint32_t)e[4] | ((uint32_t)e[5] << 16), (uint32_t)e[6] | ((uint32_t)e[7] << 16)};
-      }
-    }
-  };
-  fetch(0);
-  for (int k0 = 0; k0 < m; k0 += PM_KC) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      *reinterpret_cast<u32x4 *>(sl + (lc + 8 * r) * PM_RS + lr) = buf[r];
-    uint2 bh[PM_KC / 16][QH_NC / 16], bl[PM_KC / 16][QH_NC / 16];
+  auto coefs = [&](int k0, uint2 (&bh)[PM_KC / 16][QH_NC / 16],
+                   uint2 (&bl)[PM_KC / 16][QH_NC / 16]) {
 #pragma unroll
     for (int kk = 0; kk < PM_KC / 16; ++kk) {
       const int g = (k0 >> 2) + kk * 4 + (lane >> 4);
@@ -818,23 +817,20 @@ __device__ __forceinline__ void qtail16_wave(const ST *__restrict__ U, int64_t l
         bl[kk][nb] = *reinterpret_cast<const uint2 *>(Bl + o);
       }
     }
-    if (FULL || k0 + PM_KC < m) fetch(k0 + PM_KC);
+  };
+  // chunk pairs as in the panel update (clamped columns times zero
+  // coefficients past m)
+  for (int k0 = 0; k0 < m; k0 += PM_KP) {
+    u32x4 ba[4], bb[4];
+    uint2 ha[PM_KC / 16][QH_NC / 16], la[PM_KC / 16][QH_NC / 16];
+    uint2 hb[PM_KC / 16][QH_NC / 16], lb[PM_KC / 16][QH_NC / 16];
+    coefs(k0, ha, la);
+    mfma_fetch<ST, FULL>(U, ldu, rows, m, rb, k0, ba);
+    coefs(k0 + PM_KC, hb, lb);
+    mfma_fetch<ST, FULL>(U, ldu, rows, m, rb, k0 + PM_KC, bb);
     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int kk = 0; kk < PM_KC / 16; ++kk) {
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        unsigned short a[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          a[t] = sl[(kk * 16 + 4 * (lane >> 4) + t) * PM_RS + mb * 16 + (lane & 15)];
-#pragma unroll
-        for (int nb = 0; nb < QH_NC / 16; ++nb) {
-          acc[mb][nb] = mfma16<ST>(a, bh[kk][nb], acc[mb][nb]);
-          acc[mb][nb] = mfma16<ST>(a, bl[kk][nb], acc[mb][nb]);
-        }
-      }
-    }
+    mfma_chunk<ST, QH_NC>(ba, ha, la, sl, acc);
+    mfma_chunk<ST, QH_NC>(bb, hb, lb, sl, acc);
   }
 }
 
@@ -922,7 +918,7 @@ void launch_panel_mfma(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int
                        int pw, const double *C, void *mf, hipStream_t st, hipEvent_t e0,
                        hipEvent_t e1) {
   const int K = J - K0;
-  const int Kp = (K + PM_KC - 1) / PM_KC * PM_KC;
+  const int Kp = (K + PM_KP - 1) / PM_KP * PM_KP;
   unsigned short *Bh = (unsigned short *)mf;
   unsigned short *Bl = Bh + (size_t)Kp * NC;
   float *sc = (float *)(Bl + (size_t)Kp * NC);
@@ -1024,7 +1020,7 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
       hipLaunchKernelGGL(k_qtail64, grid, dim3(256), 0, st, U + m, ldu, rows, m,
                          (const double *)Mq, Q + m, ldq);
     } else if constexpr (sizeof(ST) == 2) {
-      const int Kp = (m + PM_KC - 1) / PM_KC * PM_KC;
+      const int Kp = (m + PM_KP - 1) / PM_KP * PM_KP;
       const int tiles = (m + QH_NC - 1) / QH_NC;
       unsigned short *Bh = (unsigned short *)qmf;
       unsigned short *Bl = Bh + (size_t)tiles * Kp * QH_NC;
@@ -1224,7 +1220,7 @@ int engine_tall(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st) {
 }
 
 size_t panel_mfma_bytes(int32_t m) {
-  const size_t Kp = (size_t)(m + PM_KC - 1) / PM_KC * PM_KC;
+  const size_t Kp = (size_t)(m + PM_KP - 1) / PM_KP * PM_KP;
   return align_up(2 * Kp * 32 * sizeof(unsigned short) + 32 * sizeof(float));
 }
 
@@ -1251,7 +1247,7 @@ int run_column_loop(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
 }
 
 size_t thin_q_bytes(int32_t m) {
-  const size_t Kp = (size_t)(m + PM_KC - 1) / PM_KC * PM_KC;
+  const size_t Kp = (size_t)(m + PM_KP - 1) / PM_KP * PM_KP;
   const size_t tiles = (size_t)(m + QH_NC - 1) / QH_NC;
   return align_up(2 * tiles * Kp * QH_NC * sizeof(unsigned short) + tiles * QH_NC * sizeof(float));
 }

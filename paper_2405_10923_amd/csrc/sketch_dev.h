@@ -45,9 +45,7 @@ template <typename ST> constexpr int sk_prefetch() { return sizeof(ST) == 8 ? 2 
 
 // Each workgroup walks the row groups g = gb, gb + gt, ... of column c (the
 // i-th of its groups is gb + i gt).  Groups that lie entirely inside the n
-// rows of a 16-byte aligned column are loaded PF at a time (past the last
-// full group the last one is read again and its extra transforms are not
-// accumulated, so every iteration issues the same loads); LDS-only barriers
+// rows of a 16-byte aligned column are loaded PF at a time; LDS-only barriers
 // keep the later groups' loads in flight across the butterflies of the
 // earlier ones.  The ragged last group (and every group of an unaligned
 // column) is loaded element by element.
@@ -81,11 +79,10 @@ __device__ __forceinline__ void srht_cols_block(const ST *__restrict__ X, int64_
   const int64_t cnt = gb < ngroups ? (ngroups - 1 - gb) / gt + 1 : 0;
   const int64_t nfullg = n / ROWS;  // groups entirely inside the n rows
   const int64_t cntf = !aligned ? 0 : (gb < nfullg ? (nfullg - 1 - gb) / gt + 1 : 0);
-  // signed, transformed group g in LDS, then its samples into acc (if live)
-  // xs: the group's values, raw (RAW: 16-byte words as loaded, decoded here)
-  // or already in AT
-  auto transform = [&](int64_t g, const auto &xs, const uint32_t (&ws)[NV], bool live,
-                       auto &&between) {
+  // signed, transformed group g in LDS, then its samples into acc
+  // xs: the group's values, raw (16-byte words as loaded, decoded here) or
+  // already in AT
+  auto transform = [&](int64_t g, const auto &xs, const uint32_t (&ws)[NV]) {
     const int64_t base = g * ROWS;
     lds_barrier();  // the previous group's samples have been read
 #pragma unroll
@@ -108,13 +105,12 @@ __device__ __forceinline__ void srht_cols_block(const ST *__restrict__ X, int64_
         s[(li >> TILE_LOG) * TILE_PAD + tpad(li & (TILE - 1))] = val;
       }
     }
-    between();
     fwht_two_tiles(s);
     const uint64_t t0 = (uint64_t)g * SK_TPW;
 #pragma unroll
     for (int a = 0; a < QA; ++a) {
       const int q = threadIdx.x + SK_TPB * a;
-      if (q < l && live) {
+      if (q < l) {
 #pragma unroll
         for (int tt = 0; tt < SK_TPW; ++tt) {
           const double hv = (double)s[tt * TILE_PAD + r2q[a]];
@@ -123,47 +119,48 @@ __device__ __forceinline__ void srht_cols_block(const ST *__restrict__ X, int64_
       }
     }
   };
-  if (cntf > 0) {
-    // PF groups per iteration, all their loads issued first (as raw 16-byte
-    // words), then transformed in order: each transform waits only for its
-    // own group while the later groups' loads are still in flight.  No load
-    // is carried across iterations (the compiler drains every outstanding
-    // load at a loop header that has loads in flight from the back edge).
-    for (int64_t i0 = 0; i0 < cntf; i0 += PF) {
-      u32x4 xv[PF][NV];
-      uint32_t wd[PF][NV];
+  // PF groups per iteration, all their loads issued first (as raw 16-byte
+  // words), then transformed in order: each transform waits only for its own
+  // group while the later groups' loads are still in flight.  No load is
+  // carried across iterations (the compiler drains every outstanding load at
+  // a loop header that has loads in flight from the back edge).
+  const int64_t cntp = cntf / PF * PF;
+  for (int64_t i0 = 0; i0 < cntp; i0 += PF) {
+    u32x4 xv[PF][NV];
+    uint32_t wd[PF][NV];
 #pragma unroll
-      for (int sl = 0; sl < PF; ++sl) {
-        const int64_t i = i0 + sl;
-        const int64_t base = (gb + (i < cntf ? i : cntf - 1) * (int64_t)gt) * ROWS;
+    for (int sl = 0; sl < PF; ++sl) {
+      const int64_t base = (gb + (i0 + sl) * (int64_t)gt) * ROWS;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const int64_t r0 = base + VEC * (threadIdx.x + SK_TPB * v);
-          xv[sl][v] = vraw_nt(x + r0);
-          wd[sl][v] = sg32[r0 >> 5];
-        }
-      }
-#pragma unroll
-      for (int sl = 0; sl < PF; ++sl) {
-        const int64_t i = i0 + sl;
-        const bool live = i < cntf;  // uniform
-        transform(gb + (live ? i : cntf - 1) * (int64_t)gt, xv[sl], wd[sl], live, [] {});
+      for (int v = 0; v < NV; ++v) {
+        const int64_t r0 = base + VEC * (threadIdx.x + SK_TPB * v);
+        xv[sl][v] = vraw_nt(x + r0);
+        wd[sl][v] = sg32[r0 >> 5];
       }
     }
+#pragma unroll
+    for (int sl = 0; sl < PF; ++sl) transform(gb + (i0 + sl) * (int64_t)gt, xv[sl], wd[sl]);
   }
-  for (int64_t i = cntf; i < cnt; ++i) {
+  // the remaining groups one at a time: full ones with vector loads, the
+  // ragged last one (or any group of an unaligned column) element by element
+  for (int64_t i = cntp; i < cnt; ++i) {
     const int64_t g = gb + i * (int64_t)gt;
     const int64_t base = g * ROWS;
     AT xs[NV][VEC];
     uint32_t ws[NV];
+    const bool vec = i < cntf;  // uniform
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int64_t i0 = base + VEC * (threadIdx.x + SK_TPB * v);
+      if (vec) {
+        vload<ST, AT, true>(x + i0, xs[v]);
+      } else {
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) xs[v][e] = (i0 + e < n) ? cvt_in<AT>(x[i0 + e]) : (AT)0;
+        for (int e = 0; e < VEC; ++e) xs[v][e] = (i0 + e < n) ? cvt_in<AT>(x[i0 + e]) : (AT)0;
+      }
       ws[v] = i0 < n ? sg32[i0 >> 5] : 0u;
     }
-    transform(g, xs, ws, true, [] {});
+    transform(g, xs, ws);
   }
 #pragma unroll
   for (int a = 0; a < QA; ++a) {
