@@ -160,6 +160,49 @@ __global__ void k_sketch_finish(const ST *__restrict__ X, int64_t ldx, int32_t m
                         blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
 }
 
+// The same sum for few columns and many partial groups (gt > 64, e.g. the one
+// column of an Arnoldi step): workgroup (b, c) sums rows q in [64 b, 64 b + 64)
+// of column c, thread (qi, gs) the groups g = gs, gs + 16, ... (a 512-byte
+// row of part per g), then the 16 slices in order; the last workgroups of
+// each column copy the head rows.
+constexpr int FW_Q = 64, FW_G = 16;
+template <typename ST>
+__global__ void __launch_bounds__(FW_Q * FW_G) k_sketch_finish_wide(
+    const ST *__restrict__ X, int64_t ldx, int32_t m, int32_t l, int gt,
+    const double *__restrict__ part, double scale, double *__restrict__ Y, int64_t ldy) {
+  const int c = blockIdx.y;
+  const int qb = (l + FW_Q - 1) / FW_Q;
+  if ((int)blockIdx.x >= qb) {  // head rows
+    for (int k = ((int)blockIdx.x - qb) * blockDim.x + threadIdx.x; k < m;
+         k += (gridDim.x - qb) * blockDim.x)
+      Y[(int64_t)c * ldy + k] = cvt_in<double>(X[(int64_t)c * ldx + k]);
+    return;
+  }
+  __shared__ double red[FW_G][FW_Q];
+  const int qi = threadIdx.x % FW_Q, gs = threadIdx.x / FW_Q;
+  const int q = blockIdx.x * FW_Q + qi;
+  const int qc = q < l ? q : l - 1;
+  const double *p = part + (int64_t)c * gt * l + qc;
+  double v = 0.0;
+  int g = gs;
+  for (; g + FW_G * 7 < gt; g += FW_G * 8) {
+    double t[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) t[b] = p[(int64_t)(g + FW_G * b) * l];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) v += t[b];
+  }
+  for (; g < gt; g += FW_G) v += p[(int64_t)g * l];
+  red[gs][qi] = v;
+  __syncthreads();
+  if (gs == 0 && q < l) {
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < FW_G; ++i) sum += red[i][qi];
+    Y[(int64_t)c * ldy + m + q] = sum * scale;
+  }
+}
+
 // ------------------------------------------------------------ RHSketch, Gaussian
 // Split-K product  part[kc] = Omega[:, rows of chunk kc] X2[chunk, :]  with
 // 64 x 64 output tiles, 16-deep K steps staged in LDS, 4 x 4 per thread.
@@ -213,6 +256,21 @@ __global__ void __launch_bounds__(256) k_gauss_cols(const double *__restrict__ o
     }
 }
 
+// Y = [X head; scale * sum of the gt partial groups]: one thread per row,
+// or, for more than 64 groups, the group sum spread over 16 threads per row
+template <typename ST>
+void launch_finish(const ST *X, int64_t ldx, int32_t m, int32_t l, int32_t k, int gt,
+                   const double *part, double scale, double *Y, int64_t ldy, hipStream_t st) {
+  if (gt > 64) {
+    const int qb = (l + FW_Q - 1) / FW_Q, hb = (m + FW_Q * FW_G - 1) / (FW_Q * FW_G);
+    hipLaunchKernelGGL((k_sketch_finish_wide<ST>), dim3(qb + hb, k), dim3(FW_Q * FW_G), 0, st, X,
+                       ldx, m, l, gt, part, scale, Y, ldy);
+  } else {
+    hipLaunchKernelGGL((k_sketch_finish<ST>), dim3((m + l + 255) / 256, k), dim3(256), 0, st, X,
+                       ldx, m, l, gt, part, scale, Y, ldy);
+  }
+}
+
 template <typename ST>
 int launch_typed(const rhqr_sketch_s *h, int64_t n, int32_t k, const ST *X, int64_t ldx,
                  double *Y, int64_t ldy, double *part, hipStream_t st) {
@@ -237,8 +295,7 @@ int launch_typed(const rhqr_sketch_s *h, int64_t n, int32_t k, const ST *X, int6
     }
 #undef RHQR_SRHT_COLS
     RHQR_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_sketch_finish<ST>), dim3((m + l + 255) / 256, k), dim3(256), 0, st, X,
-                       ldx, m, l, gt, part, 1.0 / std::sqrt((double)l), Y, ldy);
+    launch_finish<ST>(X, ldx, m, l, k, gt, part, 1.0 / std::sqrt((double)l), Y, ldy, st);
   } else {
     const int64_t ntail = n - m;
     const int64_t kchunk = ((ntail + gt - 1) / gt + GK - 1) / GK * GK;
@@ -246,8 +303,7 @@ int launch_typed(const rhqr_sketch_s *h, int64_t n, int32_t k, const ST *X, int6
     hipLaunchKernelGGL((k_gauss_cols<ST, CT>), grid, dim3(256), 0, st, h->d_omega, (int64_t)l, X,
                        ldx, m, ntail, l, k, kchunk, part);
     RHQR_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_sketch_finish<ST>), dim3((m + l + 255) / 256, k), dim3(256), 0, st, X,
-                       ldx, m, l, gt, part, 1.0, Y, ldy);
+    launch_finish<ST>(X, ldx, m, l, k, gt, part, 1.0, Y, ldy, st);
   }
   RHQR_HIP(hipGetLastError());
   return RHQR_OK;
