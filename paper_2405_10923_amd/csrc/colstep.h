@@ -377,7 +377,7 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
 //   ypart   = sum y_k z_k                    (s_j^t z_{j+1} up to the pivot term)
 // Every load that does not depend on y (the S entries of the dot products, z,
 // the partials) is issued before the first wait.
-constexpr int RED_NP = 16;  // per-lane loads issued together
+constexpr int RED_NP = 8;  // per-lane loads issued together
 
 // RW waves per workgroup (16 with 1024 threads, 4 with 256).  The row sums
 // are formed in 16 fixed groups (element t of a row's sum belongs to group
