@@ -138,3 +138,89 @@ def test_repeatable_bitwise():
     b = rhqr.factor(sk, to_gpu(W))
     for k in ("U", "S", "T", "R"):
         assert torch.equal(a[k], b[k])
+
+
+# degenerate and extreme shapes: a single column, m = n - 1, every row of the
+# SRHT sampled (l = N), a one-row tail, and panels wider than m
+@pytest.mark.parametrize("n,m,l,panel,outer", [
+    (2, 1, 1, 0, 0), (17, 1, 4, 16, 0), (40, 39, 8, 8, 32), (4096, 16, 4096, 8, 16),
+    (4097, 12, 300, 0, 0), (1000, 5, 64, 16, 32)])
+def test_edge_shapes(n, m, l, panel, outer):
+    torch = cuda_or_skip()
+    log(f"edge n={n} m={m} l={l} panel={panel} outer={outer}")
+    W, Win, g, sk = _run(0, n, m, l, 1, seed=7, panel=panel, outer=outer)
+    ref = orq.rhqr_left(W, sk)
+    assert g["info"] == ref["info"] == 0
+    for k in ("R", "S", "T", "U"):
+        assert rel(g[k], ref[k]) < 1e-11, k
+    assert rel(g["Q"], orq.thin_q(ref["U"], ref["T"], m)) < 1e-11
+
+
+def _padded(torch, W, ld, dtype):
+    """W (n x m) in a column-major buffer with leading dimension ld > n."""
+    n, m = W.shape
+    buf = torch.zeros((m, ld), dtype=dtype, device="cuda")
+    buf[:, :n].copy_(torch.from_numpy(np.ascontiguousarray(W.T)).to(dtype))
+    return buf.t()[:n]
+
+
+@pytest.mark.parametrize("pad", [1, 3, 8])
+@pytest.mark.parametrize("panel,outer", [(0, 0), (8, 32)])
+def test_padded_leading_dimension_f64(pad, panel, outer):
+    """ld = n + pad: unaligned columns (pad 1, 3) take the element-wise paths,
+    pad 8 keeps 16-byte columns; the results equal the oracle's either way."""
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    n, m, l = 3 * 4096 + 100, 40, 160
+    W = synthetic_matrix(n, m, 3, seed=11)
+    Wd = _padded(torch, W, n + pad, torch.float64)
+    assert Wd.stride() == (1, n + pad)
+    sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=12)
+    out = rhqr.factor(sk, Wd, want_q=True, panel=panel, outer=outer)
+    torch.cuda.synchronize()
+    ref = orq.rhqr_left(W, osk.Sketch(osk.SRHT, n, m, l, seed=12))
+    for k in ("R", "S", "T"):
+        assert rel(to_np(out[k]), ref[k]) < 1e-12, k
+    assert rel(to_np(Wd), ref["U"]) < 1e-12
+    assert rel(to_np(out["Q"]), orq.thin_q(ref["U"], ref["T"], m)) < 1e-12
+
+
+@pytest.mark.parametrize("dt", ["float32", "float16", "bfloat16"])
+def test_padded_leading_dimension_low_precision(dt):
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    n, m, l = 2 * 4096 + 333, 24, 96
+    tdt = getattr(torch, dt)
+    W = synthetic_matrix(n, m, 3, seed=13)
+    tol = 1e-5 if dt == "float32" else 1e-2
+    for pad, (panel, outer) in ((1, (8, 16)), (3, (16, 0))):  # ld = n + 3: 16-byte columns
+        Wd = _padded(torch, W, n + pad, tdt)
+        Win = to_np(Wd)
+        sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=14)
+        out = rhqr.factor(sk, Wd, want_q=True, panel=panel, outer=outer)
+        torch.cuda.synchronize()
+        osketch = osk.Sketch(osk.SRHT, n, m, l, seed=14)
+        Q = to_np(out["Q"])
+        ef = metrics.fact_error(Win, Q, to_np(out["R"]))
+        eo = metrics.orth_error(osk.rh_sketch(Q, osketch))
+        log(f"{dt} pad={pad}: e_fact {ef:.2e} e_orth {eo:.2e}")
+        assert ef < tol and eo < tol
+
+
+def test_zero_matrix_all_identity_reflectors():
+    """W = 0: every rho_j is zero; the first is reported, R = 0, T = 0 and
+    every reflector is the identity (s_j = e_j)."""
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    n, m, l = 5000, 6, 32
+    W = np.zeros((n, m))
+    sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=1)
+    out = rhqr.factor(sk, to_gpu(W), want_q=True)
+    torch.cuda.synchronize()
+    assert rhqr.status(out["ws"]) == 1
+    ref = orq.rhqr_left(W, osk.Sketch(osk.SRHT, n, m, l, seed=1))
+    assert ref["info"] == 1
+    assert np.all(to_np(out["R"]) == 0.0) and np.all(to_np(out["T"]) == 0.0)
+    S = to_np(out["S"])
+    assert np.array_equal(S, np.eye(l + m, m))
+    assert rel(S, ref["S"]) == 0.0
