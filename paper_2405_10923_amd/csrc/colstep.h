@@ -605,6 +605,21 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
     tr[i] = (pw && qr < j) ? Tt[qr + (int64_t)p * m] : 0.0;
     tc[i] = (pw && needc && qc <= p) ? T[qc + (int64_t)p * ldt] : 0.0;
   }
+  // wave 0: the first 128 groups' partial sums of squares and of y^t z;
+  // every thread: the entry of y its first row of s_j needs
+  double sqv[2] = {0.0, 0.0}, ypv[2] = {0.0, 0.0};
+  if (w == 0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = lane + 64 * h;
+      if (g < gred) {
+        sqv[h] = sq[g];
+        if (needc) ypv[h] = ypart[g];
+      }
+    }
+  }
+  const int kfirst = bid * blockDim.x + threadIdx.x;
+  const double yfirst = kfirst > j && kfirst < l + m ? y[kfirst] : 0.0;
   // thread q: the partial dot products d_q, e_q and the pivot-row entry
   // S_{j,q}; the partial sums are loaded FIN_GB groups at a time (clamped
   // indices, issued together) and added in increasing g
@@ -630,7 +645,13 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
   }
   if (w == 0) {
     double ss = 0.0, yz = 0.0;
-    for (int g = lane; g < gred; g += 64) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (lane + 64 * h < gred) {
+        ss += sqv[h];
+        if (needc) yz += ypv[h];
+      }
+    for (int g = lane + 128; g < gred; g += 64) {  // sketches of more than 7168 rows
       ss += sq[g];
       if (needc) yz += ypart[g];
     }
@@ -654,12 +675,12 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
   }
   // s_j into S_{:, j} (grid-stride over the l+m rows)
   const int L = l + m;
-  for (int k = bid * blockDim.x + threadIdx.x; k < L; k += nblk * blockDim.x) {
+  for (int k = kfirst; k < L; k += nblk * blockDim.x) {
     double s = 0.0;
     if (k == j)
       s = sc.ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : sc.gamma / sc.alpha);
     else if (k > j)
-      s = sc.ident ? 0.0 : y[k] / sc.alpha;
+      s = sc.ident ? 0.0 : (k == kfirst ? yfirst : y[k]) / sc.alpha;
     S[k + (int64_t)j * lds] = s;
   }
   __syncthreads();
