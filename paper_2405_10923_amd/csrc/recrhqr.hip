@@ -116,6 +116,195 @@ __global__ void k_zero_mat(double *A, int64_t lda, int32_t rows, int32_t cols) {
   if (r < rows && c < cols) A[r + (int64_t)c * lda] = 0.0;
 }
 
+// ------------------------------------------- sketch-space Householder QR
+// Householder QR of the small L x m float64 sketch Z (overwritten) in one
+// workgroup, right-looking in panels of SQ_NB columns: the panel is factored
+// in LDS one column at a time (RHVector with Psi = I, Alg. 2: sigma, rho,
+// gamma, alpha, beta; identity reflector when rho = 0), its vectors go to S,
+// the T recursion of Prop. 3.2 (T_{:,j} = -beta_j T S^t s_j) extends T, and
+// the trailing columns are updated by the panel's block reflector,
+// Z <- (I - S_p T_p^t S_p^t) Z.  Every reduction runs in a fixed order.  The
+// same factorization as the column engine with Psi = I, in far fewer
+// launches (one).
+constexpr int SQ_NB = 8, SQ_TPB = 1024;
+constexpr int SQ_MAXL = 2048;  // panel of SQ_MAXL x SQ_NB float64 in LDS (128 KiB)
+constexpr int SQ_MAXM = 1024;  // largest m (recrhqr_factor rejects larger)
+
+// sum over the workgroup of one value per thread, fixed order; all threads
+// get the result
+__device__ __forceinline__ double sq_block_sum(double v, double *red16) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();  // red16 may still be read by the previous sum
+  if (lane == 0) red16[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < SQ_TPB / 64; ++i) s += red16[i];
+  return s;
+}
+
+__global__ void __launch_bounds__(SQ_TPB) k_hqr_small(int32_t L, int32_t m, double *Z, int64_t ldz,
+                                                      double *S, int64_t lds, double *T,
+                                                      int64_t ldt, double *R, int64_t ldr,
+                                                      int scaling, int32_t *status) {
+  extern __shared__ double Pn[];  // panel: column c at Pn + c * rows, rows J .. L-1
+  __shared__ double red16[SQ_TPB / 64];
+  __shared__ double redv[SQ_TPB / 64][SQ_NB];
+  __shared__ double gv[SQ_MAXM];
+  __shared__ double bet[SQ_NB];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int J = 0; J < m; J += SQ_NB) {
+    const int nb = m - J < SQ_NB ? m - J : SQ_NB;
+    const int rows = L - J;
+    // the panel's rows J.. into LDS; its rows < J are final entries of R
+    for (int e = tid; e < rows * nb; e += SQ_TPB) {
+      const int r = e % rows, c = e / rows;
+      Pn[c * rows + r] = Z[(J + r) + (int64_t)(J + c) * ldz];
+    }
+    for (int e = tid; e < J * nb; e += SQ_TPB) {
+      const int r = e % J, c = e / J;
+      R[r + (int64_t)(J + c) * ldr] = Z[r + (int64_t)(J + c) * ldz];
+    }
+    __syncthreads();
+    for (int c = 0; c < nb; ++c) {
+      const int j = J + c;
+      double *x = Pn + c * rows;  // local row r is row J + r; the pivot is local row c
+      double ss = 0.0;
+      for (int r = c + tid; r < rows; r += SQ_TPB) ss += x[r] * x[r];
+      ss = sq_block_sum(ss, red16);
+      // RHVector scalars (every thread computes the same values)
+      const double rho = sqrt(ss);
+      const double yj = x[c];
+      const double sigma = yj >= 0.0 ? 1.0 : -1.0;
+      const bool ident = !(rho > 0.0);
+      double gamma = 0.0, alpha = 1.0, beta = 0.0;
+      if (!ident) {
+        gamma = yj + sigma * rho;
+        if (scaling == RHQR_SCALE_UNIT_PIVOT) {
+          alpha = gamma;
+          beta = fabs(gamma) / rho;
+        } else {
+          alpha = sqrt(rho * fabs(gamma));
+          beta = 1.0;
+        }
+      }
+      const double sr = sigma * rho;
+      __syncthreads();  // every thread has read x[c]
+      // R column j: rows J..j-1 from the panel, -sigma rho on the diagonal, zeros below
+      for (int r = tid; r < m; r += SQ_TPB) {
+        if (r >= J && r < j) R[r + (int64_t)j * ldr] = x[r - J];
+        else if (r == j) R[r + (int64_t)j * ldr] = -sr;
+        else if (r > j) R[r + (int64_t)j * ldr] = 0.0;
+      }
+      __syncthreads();  // the R entries above the pivot have been read
+      // s_j in place of the column
+      for (int r = tid; r < rows; r += SQ_TPB) {
+        double sv = 0.0;
+        if (r == c)
+          sv = ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : gamma / alpha);
+        else if (r > c)
+          sv = ident ? 0.0 : x[r] / alpha;
+        x[r] = sv;
+      }
+      if (tid == 0) {
+        bet[c] = beta;
+        T[j + (int64_t)j * ldt] = beta;
+        if (ident) atomicCAS(status, 0, j + 1);
+      }
+      __syncthreads();
+      // H_j = I - beta s_j s_j^t on the panel's later columns (rows >= j)
+      const int nrem = nb - 1 - c;
+      if (nrem > 0 && !ident) {
+        double d[SQ_NB];
+#pragma unroll
+        for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
+        for (int r = c + tid; r < rows; r += SQ_TPB) {
+          const double sv = x[r];
+#pragma unroll
+          for (int q = 0; q < SQ_NB; ++q)
+            if (q < nrem) d[q] += sv * Pn[(c + 1 + q) * rows + r];
+        }
+#pragma unroll
+        for (int q = 0; q < SQ_NB; ++q) {
+          const double v = wave_sum(d[q]);
+          if (lane == 0 && q < nrem) redv[w][q] = v;
+        }
+        __syncthreads();
+        if (tid < nrem) {
+          double sum = 0.0;
+          for (int i = 0; i < SQ_TPB / 64; ++i) sum += redv[i][tid];
+          gv[tid] = beta * sum;
+        }
+        __syncthreads();
+        for (int e = tid; e < nrem * (rows - c); e += SQ_TPB) {
+          const int q = e / (rows - c), r = c + e % (rows - c);
+          Pn[(c + 1 + q) * rows + r] -= gv[q] * x[r];
+        }
+        __syncthreads();
+      }
+    }
+    // the panel's vectors into S (zeros above the panel rows)
+    for (int e = tid; e < L * nb; e += SQ_TPB) {
+      const int r = e % L, c = e / L;
+      S[r + (int64_t)(J + c) * lds] = r < J ? 0.0 : Pn[c * rows + (r - J)];
+    }
+    __syncthreads();
+    // T columns J..J+nb-1: g = S_{:,<j}^t s_j (nonzero rows >= j), then
+    // T_{p,j} = -beta_j sum_{q = p}^{j-1} T_{p,q} g_q
+    for (int c = 0; c < nb; ++c) {
+      const int j = J + c;
+      const double *sj = S + (int64_t)j * lds;
+      for (int p = w; p < j; p += SQ_TPB / 64) {
+        const double *sp = S + (int64_t)p * lds;
+        double v = 0.0;
+        for (int r = j + lane; r < L; r += 64) v += sp[r] * sj[r];
+        v = wave_sum(v);
+        if (lane == 0) gv[p] = v;
+      }
+      __syncthreads();
+      for (int p = tid; p < j; p += SQ_TPB) {
+        double t = 0.0;
+        for (int q = p; q < j; ++q) t += T[p + (int64_t)q * ldt] * gv[q];
+        T[p + (int64_t)j * ldt] = -bet[c] * t;
+      }
+      __syncthreads();
+    }
+    // trailing columns k >= J + nb: w = S_p^t Z_k, u = T_p^t w, Z_k -= S_p u
+    // (rows >= J; one wave per column)
+    for (int k = J + nb + w; k < m; k += SQ_TPB / 64) {
+      double *zk = Z + (int64_t)k * ldz;
+      double d[SQ_NB];
+#pragma unroll
+      for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
+      for (int r = lane; r < rows; r += 64) {
+        const double zv = zk[J + r];
+#pragma unroll
+        for (int q = 0; q < SQ_NB; ++q)
+          if (q < nb) d[q] += Pn[q * rows + r] * zv;
+      }
+      double u[SQ_NB];
+#pragma unroll
+      for (int q = 0; q < SQ_NB; ++q) d[q] = wave_sum(d[q]);
+#pragma unroll
+      for (int c = 0; c < SQ_NB; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < SQ_NB; ++q)
+          if (q <= c && c < nb) t += T[(J + q) + (int64_t)(J + c) * ldt] * d[q];
+        u[c] = t;
+      }
+      for (int r = lane; r < rows; r += 64) {
+        double zv = zk[J + r];
+#pragma unroll
+        for (int c = 0; c < SQ_NB; ++c)
+          if (c < nb) zv -= Pn[c * rows + r] * u[c];
+        zk[J + r] = zv;
+      }
+    }
+    __syncthreads();  // the next panel reads the updated columns
+  }
+}
+
 }  // namespace
 
 // Sketch-space Householder QR of Z (L x m float64, copied to Zc, which is
@@ -124,6 +313,20 @@ int sketch_space_hqr(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, d
                      int64_t ldt, double *R, int64_t ldr, const LoopWs &w, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_mat, dim3((m + 255) / 256, m), dim3(256), 0, st, T, ldt, m, m);
   RHQR_HIP(hipGetLastError());
+  if (L <= SQ_MAXL) {  // one workgroup, the panel in LDS
+    const size_t lds_bytes = sizeof(double) * (size_t)L * SQ_NB;
+    static bool attr_set = false;
+    if (!attr_set) {
+      RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_small,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(sizeof(double) * SQ_MAXL * SQ_NB)));
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(k_hqr_small, dim3(1), dim3(SQ_TPB), lds_bytes, st, L, m, Zc, (int64_t)L, S,
+                       lds, T, ldt, R, ldr, (int)RHQR_SCALE_UNIT_PIVOT, w.status);
+    RHQR_HIP(hipGetLastError());
+    return RHQR_OK;
+  }
   LoopArgs a;
   a.kind = RHQR_SKETCH_IDENT;
   a.dtype = RHQR_F64;
