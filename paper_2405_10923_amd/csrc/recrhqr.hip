@@ -121,13 +121,14 @@ __global__ void k_zero_mat(double *A, int64_t lda, int32_t rows, int32_t cols) {
 // workgroup, right-looking in panels of SQ_NB columns: the panel is factored
 // in LDS one column at a time (RHVector with Psi = I, Alg. 2: sigma, rho,
 // gamma, alpha, beta; identity reflector when rho = 0), its vectors go to S,
-// the T recursion of Prop. 3.2 (T_{:,j} = -beta_j T S^t s_j) extends T, and
-// the trailing columns are updated by the panel's block reflector,
+// the T recursion of Prop. 3.2 (T_{:,j} = -beta_j T S^t s_j, in block form
+// per panel) extends T, and the trailing columns are updated by the panel's
+// block reflector,
 // Z <- (I - S_p T_p^t S_p^t) Z.  Every reduction runs in a fixed order.  The
 // same factorization as the column engine with Psi = I, in far fewer
 // launches (one).
 constexpr int SQ_NB = 8, SQ_TPB = 1024;
-constexpr int SQ_MAXL = 2048;  // panel of SQ_MAXL x SQ_NB float64 in LDS (128 KiB)
+constexpr int SQ_MAXL = 2048;  // L + m at most: the panel (L x SQ_NB) and Y (m x SQ_NB) in LDS
 constexpr int SQ_MAXM = 1024;  // largest m (recrhqr_factor rejects larger)
 
 // sum over the workgroup of one value per thread, fixed order; all threads
@@ -147,7 +148,8 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_small(int32_t L, int32_t m, doub
                                                       double *S, int64_t lds, double *T,
                                                       int64_t ldt, double *R, int64_t ldr,
                                                       int scaling, int32_t *status) {
-  extern __shared__ double Pn[];  // panel: column c at Pn + c * rows, rows J .. L-1
+  // panel: column c at Pn + c * rows, rows J .. L-1; after it, Y (J x SQ_NB)
+  extern __shared__ double Pn[];
   __shared__ double red16[SQ_TPB / 64];
   __shared__ double redv[SQ_TPB / 64][SQ_NB];
   __shared__ double gv[SQ_MAXM];
@@ -249,23 +251,83 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_small(int32_t L, int32_t m, doub
       S[r + (int64_t)(J + c) * lds] = r < J ? 0.0 : Pn[c * rows + (r - J)];
     }
     __syncthreads();
-    // T columns J..J+nb-1: g = S_{:,<j}^t s_j (nonzero rows >= j), then
-    // T_{p,j} = -beta_j sum_{q = p}^{j-1} T_{p,q} g_q
+    // T columns J..J+nb-1, block form of the Prop. 3.2 recursion: the
+    // panel's own block T_pp (g = S_p^t s_j over the panel, from LDS), then
+    // T_{<J, p} = -T_{<J,<J} (S_{<J}^t S_p) T_pp.
     for (int c = 0; c < nb; ++c) {
-      const int j = J + c;
-      const double *sj = S + (int64_t)j * lds;
-      for (int p = w; p < j; p += SQ_TPB / 64) {
-        const double *sp = S + (int64_t)p * lds;
+      const double *xj = Pn + c * rows;
+      // g_q = s_q^t s_j for the panel's q < c (rows >= J + c), one wave per q
+      for (int q = w; q < c; q += SQ_TPB / 64) {
+        const double *xq = Pn + q * rows;
         double v = 0.0;
-        for (int r = j + lane; r < L; r += 64) v += sp[r] * sj[r];
+        for (int r = c + lane; r < rows; r += 64) v += xq[r] * xj[r];
         v = wave_sum(v);
-        if (lane == 0) gv[p] = v;
+        if (lane == 0) gv[q] = v;
       }
       __syncthreads();
-      for (int p = tid; p < j; p += SQ_TPB) {
+      if (tid < c) {
         double t = 0.0;
-        for (int q = p; q < j; ++q) t += T[p + (int64_t)q * ldt] * gv[q];
-        T[p + (int64_t)j * ldt] = -bet[c] * t;
+        for (int q = tid; q < c; ++q) t += T[(J + tid) + (int64_t)(J + q) * ldt] * gv[q];
+        T[(J + tid) + (int64_t)(J + c) * ldt] = -bet[c] * t;
+      }
+      __syncthreads();
+    }
+    if (J > 0) {
+      // X = S_{<J}^t S_p (rows >= J), one wave per earlier column p, into
+      // T[p, J + c] as scratch
+      for (int p = w; p < J; p += SQ_TPB / 64) {
+        const double *sp = S + (int64_t)p * lds + J;
+        double d[SQ_NB];
+#pragma unroll
+        for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
+#pragma unroll 4
+        for (int r = lane; r < rows; r += 64) {
+          const double sv = sp[r];
+#pragma unroll
+          for (int q = 0; q < SQ_NB; ++q)
+            if (q < nb) d[q] += sv * Pn[q * rows + r];
+        }
+#pragma unroll
+        for (int q = 0; q < SQ_NB; ++q) {
+          const double v = wave_sum(d[q]);
+          if (lane == 0 && q < nb) T[p + (int64_t)(J + q) * ldt] = v;
+        }
+      }
+      __syncthreads();
+      // Y = T_{<J,<J} X into LDS (after the panel), one wave per row p,
+      // lanes over q >= p
+      double *Yl = Pn + (size_t)SQ_NB * rows;
+      for (int p = w; p < J; p += SQ_TPB / 64) {
+        double t[SQ_NB];
+#pragma unroll
+        for (int c = 0; c < SQ_NB; ++c) t[c] = 0.0;
+        for (int q = p + lane; q < J; q += 64) {
+          const double tpq = T[p + (int64_t)q * ldt];
+#pragma unroll
+          for (int c = 0; c < SQ_NB; ++c)
+            if (c < nb) t[c] += tpq * T[q + (int64_t)(J + c) * ldt];
+        }
+#pragma unroll
+        for (int c = 0; c < SQ_NB; ++c) {
+          const double v = wave_sum(t[c]);
+          if (lane == 0) Yl[p * SQ_NB + c] = v;
+        }
+      }
+      __syncthreads();
+      // T_{<J, p} = -Y T_pp, row by row
+      for (int p = tid; p < J; p += SQ_TPB) {
+        double o[SQ_NB];
+#pragma unroll
+        for (int c = 0; c < SQ_NB; ++c) {
+          double t = 0.0;
+#pragma unroll
+          for (int q = 0; q < SQ_NB; ++q)
+            if (q <= c && c < nb) t += Yl[p * SQ_NB + q] * T[(J + q) + (int64_t)(J + c) * ldt];
+          o[c] = -t;
+        }
+#pragma unroll
+        for (int c = 0; c < SQ_NB; ++c)
+          if (c < nb) T[p + (int64_t)(J + c) * ldt] = o[c];
       }
       __syncthreads();
     }
@@ -276,6 +338,7 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_small(int32_t L, int32_t m, doub
       double d[SQ_NB];
 #pragma unroll
       for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
+#pragma unroll 4
       for (int r = lane; r < rows; r += 64) {
         const double zv = zk[J + r];
 #pragma unroll
@@ -293,6 +356,7 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_small(int32_t L, int32_t m, doub
           if (q <= c && c < nb) t += T[(J + q) + (int64_t)(J + c) * ldt] * d[q];
         u[c] = t;
       }
+#pragma unroll 4
       for (int r = lane; r < rows; r += 64) {
         double zv = zk[J + r];
 #pragma unroll
@@ -313,8 +377,8 @@ int sketch_space_hqr(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, d
                      int64_t ldt, double *R, int64_t ldr, const LoopWs &w, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_mat, dim3((m + 255) / 256, m), dim3(256), 0, st, T, ldt, m, m);
   RHQR_HIP(hipGetLastError());
-  if (L <= SQ_MAXL) {  // one workgroup, the panel in LDS
-    const size_t lds_bytes = sizeof(double) * (size_t)L * SQ_NB;
+  if (L + m <= SQ_MAXL) {  // one workgroup, the panel in LDS
+    const size_t lds_bytes = sizeof(double) * (size_t)(L + m) * SQ_NB;
     static bool attr_set = false;
     if (!attr_set) {
       RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_small,
