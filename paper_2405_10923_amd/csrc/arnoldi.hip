@@ -97,17 +97,15 @@ __global__ void k_head_comb(int32_t kh, int32_t ncol, const double *__restrict__
   out[r] = cvt_out<ST>(v);
 }
 
-// tail rows (i >= kh): out_i = a out_i - sum_{p < ncol} U_{i,p} gf_p; column
-// rawc holds raw refreshed values (float32 staging for 2/4-byte types when
-// rawc >= 1, the input column itself when rawc == 0).  Each thread owns VEC
-// consecutive rows (16-byte loads, eight columns' loads issued together) and
-// subtracts the columns in increasing p.
+// tail rows (i >= kh): out_i = a out_i - sum_{p < ncol} U_{i,p} gf_p (the last
+// column may hold the raw refreshed values, in place; gf folds in their
+// 1/alpha).  Each thread owns VEC consecutive rows (16-byte loads, eight
+// columns' loads issued together) and subtracts the columns in increasing p.
 constexpr int GV_TPB = 256, GV_KB = 8;
 template <typename ST>
 __global__ void __launch_bounds__(GV_TPB) k_tail_gemv(const ST *__restrict__ U, int64_t ldu,
                                                       int64_t n, int32_t kh, int32_t ncol,
-                                                      const double *__restrict__ gf, int32_t rawc,
-                                                      const float *__restrict__ wstage,
+                                                      const double *__restrict__ gf,
                                                       int accumulate, ST *__restrict__ out,
                                                       int aligned) {
   using CT = typename CompT<ST>::type;
@@ -116,8 +114,6 @@ __global__ void __launch_bounds__(GV_TPB) k_tail_gemv(const ST *__restrict__ U, 
   const int64_t r0 = mb + ((int64_t)blockIdx.x * GV_TPB + threadIdx.x) * VEC;
   if (r0 >= n) return;
   const bool fast = aligned && r0 + VEC <= n;
-  const bool staged = !std::is_same<ST, double>::value && rawc >= 1;
-  const int pend = staged ? rawc : ncol;  // columns read from U before the staged one
   CT v[VEC];
 #pragma unroll
   for (int e = 0; e < VEC; ++e) v[e] = (CT)0;
@@ -139,7 +135,7 @@ __global__ void __launch_bounds__(GV_TPB) k_tail_gemv(const ST *__restrict__ U, 
     }
   };
   int p = 0;
-  for (; p + GV_KB <= pend; p += GV_KB) {
+  for (; p + GV_KB <= ncol; p += GV_KB) {
     CT x[GV_KB][VEC];
 #pragma unroll
     for (int u = 0; u < GV_KB; ++u) column(p + u, x[u]);
@@ -152,12 +148,7 @@ __global__ void __launch_bounds__(GV_TPB) k_tail_gemv(const ST *__restrict__ U, 
   }
   for (; p < ncol; ++p) {
     CT x[VEC];
-    if (staged && p == rawc) {
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) x[e] = r0 + e < n ? (CT)wstage[r0 + e] : (CT)0;
-    } else {
-      column(p, x);
-    }
+    column(p, x);
     const CT g = (CT)gf[p];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) v[e] -= x[e] * g;
@@ -169,16 +160,14 @@ __global__ void __launch_bounds__(GV_TPB) k_tail_gemv(const ST *__restrict__ U, 
 
 template <typename ST>
 void launch_tail_gemv(const ST *U, int64_t ldu, int64_t n, int32_t kh, int32_t ncol,
-                      const double *gf, int32_t rawc, const float *wstage, int accumulate, ST *out,
-                      hipStream_t st) {
+                      const double *gf, int accumulate, ST *out, hipStream_t st) {
   constexpr int VEC = 16 / sizeof(ST);
   const int aligned = ((uintptr_t)U % 16 == 0) && ((uintptr_t)out % 16 == 0) &&
-                      ((ldu * (int64_t)sizeof(ST)) % 16 == 0) && ((uintptr_t)wstage % 16 == 0);
+                      ((ldu * (int64_t)sizeof(ST)) % 16 == 0);
   const int64_t mb = kh - kh % VEC;
   const int64_t threads = (n - mb + VEC - 1) / VEC;
   hipLaunchKernelGGL((k_tail_gemv<ST>), dim3((unsigned)((threads + GV_TPB - 1) / GV_TPB)),
-                     dim3(GV_TPB), 0, st, U, ldu, n, kh, ncol, gf, rawc, wstage, accumulate, out,
-                     aligned);
+                     dim3(GV_TPB), 0, st, U, ldu, n, kh, ncol, gf, accumulate, out, aligned);
 }
 
 // y = A x, A in CSR (float64 values), x and y in the basis type, float64 sums
@@ -205,8 +194,7 @@ int q_typed(rhqr_arnoldi_s *a, int32_t j, void *out, hipStream_t st) {
   RHQR_HIP(hipGetLastError());
   const int64_t nt = a->n - kh;
   if (nt > 0) {
-    launch_tail_gemv<ST>((const ST *)a->U, a->n, a->n, kh, j + 1, a->gf, j, a->lw.wstage, 0,
-                         (ST *)out, st);
+    launch_tail_gemv<ST>((const ST *)a->U, a->n, a->n, kh, j + 1, a->gf, 0, (ST *)out, st);
     RHQR_HIP(hipGetLastError());
   }
   return RHQR_OK;
@@ -424,8 +412,7 @@ int sol_typed(rhqr_arnoldi_s *a, int32_t j, const double *y, void *x, hipStream_
   RHQR_HIP(hipGetLastError());
   const int64_t nt = a->n - kh;
   if (nt > 0) {
-    launch_tail_gemv<ST>((const ST *)a->U, a->n, a->n, kh, j, a->g, -1, a->lw.wstage, 1, (ST *)x,
-                         st);
+    launch_tail_gemv<ST>((const ST *)a->U, a->n, a->n, kh, j, a->g, 1, (ST *)x, st);
     RHQR_HIP(hipGetLastError());
   }
   return RHQR_OK;

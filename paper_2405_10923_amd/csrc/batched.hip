@@ -103,12 +103,7 @@ __global__ void kb_scale_col(const ColProblem *__restrict__ P, int32_t cidx) {
   const double a = Q.ia[cidx];
   const int64_t stride = (int64_t)gridDim.y * blockDim.x;
   for (int64_t i = Q.m + (int64_t)blockIdx.y * blockDim.x + threadIdx.x; i < Q.n; i += stride) {
-    double raw;
-    if constexpr (std::is_same<ST, double>::value)
-      raw = col[i];
-    else
-      raw = cidx >= 1 ? (double)Q.wstage[i] : cvt_in<double>(col[i]);
-    col[i] = cvt_out<ST>(raw * a);
+    col[i] = cvt_out<ST>(cvt_in<double>(col[i]) * a);  // raw values in place
   }
 }
 
@@ -146,12 +141,7 @@ __global__ void kb_finish(const ColProblem *__restrict__ P) {
   ST *col = W + (int64_t)cidx * Q.ldw;
   const int64_t stride = (int64_t)gridDim.y * blockDim.x;
   for (int64_t i = m + (int64_t)blockIdx.y * blockDim.x + threadIdx.x; i < Q.n; i += stride) {
-    double raw;
-    if constexpr (std::is_same<ST, double>::value)
-      raw = col[i];
-    else
-      raw = cidx >= 1 ? (double)Q.wstage[i] : cvt_in<double>(col[i]);
-    col[i] = cvt_out<ST>(raw * a);
+    col[i] = cvt_out<ST>(cvt_in<double>(col[i]) * a);  // raw values in place
   }
   for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < (int64_t)m * m; e += stride) {
     const int k = (int)(e % m), c = (int)(e / m);

@@ -44,12 +44,10 @@ template <typename ST, bool FAST, int NV, int TPB>
 __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
                                           int32_t j, int32_t p0, bool prev,
                                           const double *__restrict__ cf, double cprev,
-                                          double iaprev, float *__restrict__ wstage,
-                                          int64_t base,
+                                          double iaprev, int64_t base,
                                           typename CompT<ST>::type (&acc)[NV][16 / sizeof(ST)]) {
   using CT = typename CompT<ST>::type;
   constexpr int VEC = 16 / sizeof(ST);
-  constexpr bool LOWP = !std::is_same<ST, double>::value;
   const int tid = threadIdx.x;
   auto row = [&](int v) { return base + (int64_t)VEC * (tid + TPB * v); };
   auto ok = [&](int64_t i) { return i >= m && i < n; };
@@ -150,25 +148,12 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
     const CT cp = (CT)cprev;
     const CT ia = (CT)iaprev;
     ST *col = W + (int64_t)(j - 1) * ldw;
-    const bool from_stage = LOWP && j >= 2;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int64_t i0 = row(v);
       CT x[VEC], o[VEC];
       if (FAST) {
-        if (from_stage) {
-          const float4 *ws4 = reinterpret_cast<const float4 *>(wstage + i0);
-#pragma unroll
-          for (int h = 0; h < VEC / 4; ++h) {
-            const float4 f = ws4[h];
-            x[4 * h] = f.x;
-            x[4 * h + 1] = f.y;
-            x[4 * h + 2] = f.z;
-            x[4 * h + 3] = f.w;
-          }
-        } else {
-          vload(col + i0, x);
-        }
+        vload(col + i0, x);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
           if (i0 + e >= m) acc[v][e] -= x[e] * cp;
@@ -179,7 +164,7 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
           if (ok(i0 + e)) {
-            x[e] = from_stage ? (CT)wstage[i0 + e] : cvt_in<CT>(col[i0 + e]);
+            x[e] = cvt_in<CT>(col[i0 + e]);
             acc[v][e] -= x[e] * cp;
             col[i0 + e] = cvt_out<ST>((double)(x[e] * ia));
           }
@@ -187,31 +172,17 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
       }
     }
   }
-  // store the raw refreshed column (float64: in place; otherwise: staging)
+  // store the raw refreshed column in place (in the storage type)
   ST *wjw = W + (int64_t)j * ldw;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int64_t i0 = row(v);
-    if (LOWP) {
-      if (FAST) {
-        float4 *ws4 = reinterpret_cast<float4 *>(wstage + i0);
-#pragma unroll
-        for (int h = 0; h < VEC / 4; ++h)
-          ws4[h] = make_float4((float)acc[v][4 * h], (float)acc[v][4 * h + 1],
-                               (float)acc[v][4 * h + 2], (float)acc[v][4 * h + 3]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          if (ok(i0 + e)) wstage[i0 + e] = (float)acc[v][e];
-      }
+    if (FAST) {
+      vstore(wjw + i0, acc[v]);  // head rows hold their unchanged input values
     } else {
-      if (FAST) {
-        vstore(wjw + i0, acc[v]);  // head rows hold their unchanged input values
-      } else {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          if (ok(i0 + e)) wjw[i0 + e] = cvt_out<ST>((double)acc[v][e]);
-      }
+      for (int e = 0; e < VEC; ++e)
+        if (ok(i0 + e)) wjw[i0 + e] = cvt_out<ST>((double)acc[v][e]);
     }
   }
 }
@@ -253,7 +224,6 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
   const int32_t m = P.m, l = P.l;
   const double *__restrict__ cf = P.cf;
   const double *__restrict__ ia = P.ia;
-  float *__restrict__ wstage = P.wstage;
   double *__restrict__ part = P.part;
   const uint64_t *__restrict__ signs = P.signs;
   const int32_t *__restrict__ rows = P.rows;
@@ -291,9 +261,9 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
   }
   CT acc[NV][VEC];
   if (fast)
-    tall_body<ST, true, NV, TPB>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, wstage, base, acc);
+    tall_body<ST, true, NV, TPB>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, base, acc);
   else
-    tall_body<ST, false, NV, TPB>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, wstage, base, acc);
+    tall_body<ST, false, NV, TPB>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, base, acc);
 
   if (KIND == RHQR_SKETCH_IDENT) return;
   const int tid = threadIdx.x;

@@ -19,7 +19,6 @@ struct LoopWs {
   double *ia;        // [m] 1/alpha_j applied when u_j is stored
   double *Tt;        // m x m transpose of T (ld m)
   double *part;      // [ntiles][l] per-tile sketch partials
-  float *wstage;     // n-vector staging of the raw refreshed column (low precision)
   void *skws;        // workspace of the multi-column pre-sketch
   size_t skws_bytes;
 };
@@ -70,7 +69,6 @@ struct ColProblem {
   int32_t gred;        // reduction workgroups
   int32_t scaling, defer, aligned;
   double *part, *y, *sq, *dpart, *epart, *ypart, *scal, *c, *cf, *ia, *Tt, *dcpart, *fs;
-  float *wstage;
   int32_t *status;
   double *C, *G;       // panel coefficients of the blocked schedule (batched path)
 };

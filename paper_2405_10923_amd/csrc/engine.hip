@@ -13,9 +13,9 @@
 //
 // Tall data is column-major in the storage type ST (double, float, half,
 // bfloat16); arithmetic on it runs in CT = double for double storage and float
-// otherwise.  The raw refreshed column is kept in float64 in place (ST=double)
-// or in a float32 staging vector (low precision) until alpha_j is known, and
-// the division by alpha_j is folded into the next pass's coefficient.
+// otherwise.  The raw refreshed column is kept in place, in the storage type,
+// until alpha_j is known, and the division by alpha_j is folded into the next
+// pass's coefficient.
 #include "colstep.h"
 
 #include <hip/hip_ext.h>
@@ -93,22 +93,15 @@ __global__ void __launch_bounds__(PANEL_TPB) k_panel(ST *__restrict__ W, int64_t
 }
 
 // ------------------------------------------------------------ final stores
-// Store column cidx (tail rows) as u = raw / alpha: raw values are in place
-// (float64), in the float32 staging vector (low precision, cidx >= 1), or the
-// input column itself (cidx == 0).
+// Store column cidx (tail rows) as u = raw / alpha; the raw refreshed values
+// (the input column itself for cidx == 0) are in place in the storage type.
 template <typename ST>
 __global__ void k_scale_col(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t cidx,
-                            const double *ia, const float *wstage) {
+                            const double *ia) {
   const int64_t i = m + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   ST *col = W + (int64_t)cidx * ldw;
-  const double a = ia[cidx];
-  double raw;
-  if constexpr (std::is_same<ST, double>::value)
-    raw = col[i];
-  else
-    raw = cidx >= 1 ? (double)wstage[i] : cvt_in<double>(col[i]);
-  col[i] = cvt_out<ST>(raw * a);
+  col[i] = cvt_out<ST>(cvt_in<double>(col[i]) * ia[cidx]);
 }
 
 template <typename ST>
@@ -335,7 +328,7 @@ int finish_typed(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
   const int64_t ntail = a.n - a.m;
   if (ntail > 0) {
     hipLaunchKernelGGL((k_scale_col<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W, a.ldw,
-                       a.n, a.m, a.m - 1, w.ia, w.wstage);
+                       a.n, a.m, a.m - 1, w.ia);
     RHQR_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL((k_head_store<ST>), dim3((a.m + 255) / 256, a.m), dim3(256), 0, st, W, a.ldw,
@@ -949,7 +942,7 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, 
   auto apply = [&](int32_t K0, int32_t J, int32_t nb) -> int {
     if (ntail > 0) {
       hipLaunchKernelGGL((k_scale_col<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W, a.ldw,
-                         a.n, m, J - 1, w.ia, w.wstage);
+                         a.n, m, J - 1, w.ia);
       RHQR_HIP(hipGetLastError());
     }
     const int64_t ne = (int64_t)J * nb;
@@ -1138,7 +1131,6 @@ ColProblem make_col_problem(const LoopArgs &a, const LoopWs &w, int tpw) {
   P.Tt = w.Tt;
   P.dcpart = w.dcpart;
   P.fs = w.fs;
-  P.wstage = w.wstage;
   P.status = w.status;
   P.C = P.G = nullptr;
   return P;
@@ -1169,7 +1161,6 @@ size_t loop_ws_bytes(int kind, int dtype, int64_t n, int32_t m, int32_t l) {
   b += 3 * align_up(sizeof(double) * m);
   b += align_up(sizeof(double) * (size_t)m * m);
   if (kind != RHQR_SKETCH_IDENT) b += align_up(sizeof(double) * (size_t)ntiles * l);
-  if (dtype != RHQR_F64) b += align_up(sizeof(float) * (size_t)n);
   return b;
 }
 
@@ -1200,7 +1191,6 @@ int loop_ws_carve(void *ws, size_t bytes, int kind, int dtype, int64_t n, int32_
   o->ia = (double *)take(sizeof(double) * m);
   o->Tt = (double *)take(sizeof(double) * (size_t)m * m);
   o->part = kind != RHQR_SKETCH_IDENT ? (double *)take(sizeof(double) * (size_t)ntiles * l) : nullptr;
-  o->wstage = dtype != RHQR_F64 ? (float *)take(sizeof(float) * (size_t)n) : nullptr;
   o->skws = nullptr;
   o->skws_bytes = 0;
   return RHQR_OK;
