@@ -333,6 +333,29 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
   }
 }
 
+// Sums eight values per lane over the 64 lanes at once: each exchange across
+// 32, 16 and 8 lanes keeps half of the values (own plus partner's), then the
+// last eight-lane groups are summed with row moves.  Lane L returns the total
+// of v[(L >> 3) & 7] (bit 5 of L selects the upper four values, bit 4 the
+// upper two of those, bit 3 the second).  Fixed order: deterministic.  All 64
+// lanes must be active.
+__device__ __forceinline__ double wave_sum8(const double (&v)[8]) {
+  const int lane = threadIdx.x & 63;
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+  double a[4], b[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    a[i] = (h5 ? v[i + 4] : v[i]) + __shfl_xor(h5 ? v[i] : v[i + 4], 32, 64);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    b[i] = (h4 ? a[i + 2] : a[i]) + __shfl_xor(h4 ? a[i] : a[i + 2], 16, 64);
+  double s = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8, 64);
+  s += dpp_mov<0xB1>(s);   // quad_perm [1,0,3,2]
+  s += dpp_mov<0x4E>(s);   // quad_perm [2,3,0,1]
+  s += dpp_mov<0x141>(s);  // row_half_mirror: the other quad of the eight lanes
+  return s;
+}
+
 // ------------------------------------------------------------------- k_red
 // One workgroup per RED_CHUNK rows of the (l+m) sketch space (head chunks
 // first).  Forms y = Psi w~_j on its rows: head rows y_k = w_{k,j} - sum_{p<j}
@@ -351,8 +374,9 @@ constexpr int RED_NP = 8;  // per-lane loads issued together
 
 // RW waves per workgroup (16 with 1024 threads, 4 with 256).  The row sums
 // are formed in 16 fixed groups (element t of a row's sum belongs to group
-// t mod 16, each group summed in increasing t, then the groups in order), so
-// the result does not depend on RW.
+// t mod 16, each group summed in increasing t, then the groups in order) and
+// every dot product by the same wave_sum8 tree (the same for any of its eight
+// slots), so the result does not depend on RW and equals red_split_block's.
 template <typename ST, int KIND, int RW = 16>
 __device__ __forceinline__ void red_block(const ColProblem &P, int32_t j, int next, int bid) {
   static_assert(16 % RW == 0, "RW must divide 16");
@@ -473,17 +497,155 @@ __device__ __forceinline__ void red_block(const ColProblem &P, int32_t j, int ne
       }
     }
 #pragma unroll
-    for (int b = 0; b < RED_NP; ++b) {
-      const int p = p0 + RW * b;
-      if (p < j) {  // uniform across the wave
-        const double dv = wave_sum(sp[b] * ym);
-        const double ev = next ? wave_sum(sp[b] * z) : 0.0;
-        if (lane == 0) {
-          dpart[(int64_t)bid * m + p] = dv;
-          if (next) epart[(int64_t)bid * m + p] = ev;
+    for (int b0 = 0; b0 < RED_NP; b0 += 4) {
+      if (p0 + RW * b0 < j) {  // uniform across the wave
+        double pr[8];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          pr[b] = sp[b0 + b] * ym;
+          pr[4 + b] = next ? sp[b0 + b] * z : 0.0;
+        }
+        const double tot = wave_sum8(pr);
+        const int idx = lane >> 3, p = p0 + RW * (b0 + (idx & 3));
+        if ((lane & 7) == 0 && p < j) {
+          if (idx < 4)
+            dpart[(int64_t)bid * m + p] = tot;
+          else if (next)
+            epart[(int64_t)bid * m + p] = tot;
         }
       }
     }
+  }
+}
+
+// k_red of one problem, with the dot products split over workgroups by p:
+// workgroup (r, chunk) forms y on the chunk's RED_CHUNK rows exactly as
+// red_block does (split 0 alone writes y, sq and ypart) and then only the
+// partial sums for p in [RSP r, RSP (r + 1)), four per wave, reduced by one
+// wave_sum8 per wave.  All loads that do not depend on y are issued in one
+// batch (RH_NP S entries per lane of the head rows, RT_NP partial sketches per
+// lane of the tail rows; more only beyond 16 RH_NP columns or 16 RT_NP tiles).
+// The row sums are formed in the same 16 fixed groups as red_block.
+constexpr int RSP = 64;     // values of p per workgroup (16 waves x 4)
+constexpr int RH_NP = 16;   // head: S entries per lane loaded together
+constexpr int RT_NP = 16;   // tail: partial sketches per lane loaded together
+__host__ __device__ inline int red_splits(int32_t j) { return j > RSP ? (j + RSP - 1) / RSP : 1; }
+
+template <typename ST, int KIND>
+__device__ __forceinline__ void red_split_block(const ColProblem &P, int32_t j, int next, int bid,
+                                                int split) {
+  const ST *__restrict__ W = (const ST *)P.W;
+  const int64_t ldw = P.ldw;
+  const int32_t m = P.m, l = P.l;
+  const double *__restrict__ Z = P.Z;
+  const int64_t ldz = P.ldz;
+  const double *__restrict__ S = P.S;
+  const int64_t lds = P.lds;
+  const double *__restrict__ c = P.c;
+  const int defer = P.defer && j >= 1;
+  const int gfin = fin_groups(j - 1);
+  const double *__restrict__ fs = P.fs;
+  const double *__restrict__ dcpart = P.dcpart;
+  const double *__restrict__ part = P.part;
+  const int64_t nparts = P.nparts;
+  const double scale = P.scale;
+  __shared__ double red[16][RED_CHUNK + 1];
+  __shared__ double yl[RED_CHUNK];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nhb = (m + RED_CHUNK - 1) / RED_CHUNK;
+  const bool head = bid < nhb;
+  const int k = head ? bid * RED_CHUNK + lane : m + (bid - nhb) * RED_CHUNK + lane;
+  const bool valid = head ? (k < m) : (k < m + l);
+  const int pb = split * RSP + w;  // this wave's values of p: pb + 16 b, b < 4
+  double sp[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int p = pb + 16 * b;
+    sp[b] = (valid && p < j) ? S[k + (int64_t)p * lds] : 0.0;
+  }
+  const double z = (next && valid) ? Z[k + (int64_t)(j + 1) * ldz] : 0.0;
+  const bool rawrow = w == 0 && valid && j >= 1 && (head || KIND == RHQR_SKETCH_IDENT);
+  const double wjk = rawrow ? cvt_in<double>(W[k + (int64_t)j * ldw]) : 0.0;
+  const double z0 = (w == 0 && valid && j == 0) ? Z[k] : 0.0;
+  const double clast = (j >= 1 && head && defer) ? deferred_c(fs, dcpart, gfin) : 0.0;
+  double v = 0.0;
+  if (j >= 1) {
+    if (head) {
+      const int pe = valid ? min(j, k + 1) : 0;
+      const int kc = valid ? k : 0;
+      for (int p0 = w; p0 < j; p0 += 16 * RH_NP) {
+        double sv[RH_NP], cv[RH_NP];
+#pragma unroll
+        for (int b = 0; b < RH_NP; ++b) {
+          const int p = min(p0 + 16 * b, j - 1);
+          sv[b] = S[kc + (int64_t)p * lds];
+          cv[b] = c[p];
+        }
+#pragma unroll
+        for (int b = 0; b < RH_NP; ++b) {
+          const int p = p0 + 16 * b;
+          const double cp = (defer && p == j - 1) ? clast : cv[b];
+          v += p < pe ? sv[b] * cp : 0.0;
+        }
+      }
+    } else if (KIND != RHQR_SKETCH_IDENT && valid) {
+      const double *pq = part + (k - m);
+      for (int64_t t0 = w; t0 < nparts; t0 += 16 * RT_NP) {
+        double t[RT_NP];
+#pragma unroll
+        for (int b = 0; b < RT_NP; ++b) {
+          const int64_t tt = t0 + 16 * b;
+          t[b] = tt < nparts ? pq[tt * l] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < RT_NP; ++b) v += t[b];
+      }
+    }
+  }
+  red[w][lane] = v;
+  __syncthreads();
+  if (w == 0) {
+    double s = 0.0;
+    for (int i = 0; i < 16; ++i) s += red[i][lane];
+    double out = 0.0;
+    if (valid) {
+      if (j == 0)
+        out = z0;  // column 0 of the pre-sketch
+      else if (head)
+        out = wjk - s;
+      else if (KIND == RHQR_SKETCH_IDENT)
+        out = wjk;
+      else
+        out = s * scale;
+      if (split == 0) P.y[k] = out;
+    }
+    const double ym = (valid && k >= j) ? out : 0.0;
+    yl[lane] = ym;
+    if (split == 0) {
+      const double tot = wave_sum(ym * ym);
+      const double yz = next ? wave_sum(ym * z) : 0.0;
+      if (lane == 0) {
+        P.sq[bid] = tot;
+        if (next) P.ypart[bid] = yz;
+      }
+    }
+  }
+  __syncthreads();
+  if (pb >= j) return;  // uniform across the wave; no barrier follows
+  const double ym = yl[lane];
+  double pr[8];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    pr[b] = sp[b] * ym;
+    pr[4 + b] = next ? sp[b] * z : 0.0;
+  }
+  const double tot = wave_sum8(pr);
+  const int idx = lane >> 3, b = idx & 3, p = pb + 16 * b;
+  if ((lane & 7) == 0 && p < j) {
+    if (idx < 4)
+      P.dpart[(int64_t)bid * m + p] = tot;
+    else if (next)
+      P.epart[(int64_t)bid * m + p] = tot;
   }
 }
 
@@ -493,12 +655,10 @@ struct StepScalars {
   int ident;
 };
 
-// ss: the sum of the partial sums of squares (rho^2)
-__device__ __forceinline__ StepScalars step_scalars(const double *y, double ss, int32_t j,
-                                                    int scaling) {
+// ss: the sum of the partial sums of squares (rho^2), yj = y_j
+__device__ __forceinline__ StepScalars step_scalars(double yj, double ss, int scaling) {
   StepScalars r;
   r.rho = sqrt(ss);
-  const double yj = y[j];
   r.sigma = yj >= 0.0 ? 1.0 : -1.0;
   r.ident = !(r.rho > 0.0);
   if (r.ident) {
@@ -558,6 +718,7 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
   double *__restrict__ dcpart = P.dcpart;
   double *__restrict__ fs = P.fs;
   __shared__ double d[MAXM], e[MAXM + 1];
+  __shared__ double pd[1024], pe[1024];  // per-sub partial dot products
   __shared__ double wdc[16];
   __shared__ StepScalars shs;
   __shared__ double yzs;
@@ -575,10 +736,11 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
     tr[i] = (pw && qr < j) ? Tt[qr + (int64_t)p * m] : 0.0;
     tc[i] = (pw && needc && qc <= p) ? T[qc + (int64_t)p * ldt] : 0.0;
   }
-  // wave 0: the first 128 groups' partial sums of squares and of y^t z;
-  // every thread: the entry of y its first row of s_j needs
-  double sqv[2] = {0.0, 0.0}, ypv[2] = {0.0, 0.0};
+  // wave 0: the first 128 groups' partial sums of squares and of y^t z, and
+  // y_j; every thread: the entry of y its first row of s_j needs
+  double sqv[2] = {0.0, 0.0}, ypv[2] = {0.0, 0.0}, yj = 0.0;
   if (w == 0) {
+    yj = y[j];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int g = lane + 64 * h;
@@ -590,28 +752,36 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
   }
   const int kfirst = bid * blockDim.x + threadIdx.x;
   const double yfirst = kfirst > j && kfirst < l + m ? y[kfirst] : 0.0;
-  // thread q: the partial dot products d_q, e_q and the pivot-row entry
-  // S_{j,q}; the partial sums are loaded FIN_GB groups at a time (clamped
-  // indices, issued together) and added in increasing g
+  // the partial dot products d_q, e_q: thread (sub, qq) with qq = t mod QW
+  // (QW the power of two >= j, at least 64) adds the groups g = sub + nsub i
+  // (nsub = 1024 / QW), loaded FIN_GB at a time (clamped indices, issued
+  // together) in increasing i; thread q adds the nsub sums in increasing sub
+  // after the barrier.  Thread q also loads the pivot-row entry S_{j,q}.
   const int q = threadIdx.x;
-  double dv = 0.0, ev = 0.0, sjq = 0.0;
-  if (q < j) {
-    sjq = S[j + (int64_t)q * lds];
-    for (int g0 = 0; g0 < gred; g0 += FIN_GB) {
-      double dl[FIN_GB], el[FIN_GB];
+  const int QW = j <= 64 ? 64 : j <= 128 ? 128 : j <= 256 ? 256 : j <= 512 ? 512 : 1024;
+  const int nsub = 1024 / QW, qq = q & (QW - 1), sub = q / QW;
+  const double sjq = q < j ? S[j + (int64_t)q * lds] : 0.0;
+  {
+    double dv = 0.0, ev = 0.0;
+    if (qq < j) {
+      for (int g0 = sub; g0 < gred; g0 += nsub * FIN_GB) {
+        double dl[FIN_GB], el[FIN_GB];
 #pragma unroll
-      for (int b = 0; b < FIN_GB; ++b) {
-        const int g = min(g0 + b, gred - 1);
-        dl[b] = dpart[(int64_t)g * m + q];
-        el[b] = needc ? epart[(int64_t)g * m + q] : 0.0;
-      }
-#pragma unroll
-      for (int b = 0; b < FIN_GB; ++b)
-        if (g0 + b < gred) {
-          dv += dl[b];
-          if (needc) ev += el[b];
+        for (int b = 0; b < FIN_GB; ++b) {
+          const int g = min(g0 + nsub * b, gred - 1);
+          dl[b] = dpart[(int64_t)g * m + qq];
+          el[b] = needc ? epart[(int64_t)g * m + qq] : 0.0;
         }
+#pragma unroll
+        for (int b = 0; b < FIN_GB; ++b)
+          if (g0 + nsub * b < gred) {
+            dv += dl[b];
+            if (needc) ev += el[b];
+          }
+      }
     }
+    pd[q] = dv;
+    pe[q] = ev;
   }
   if (w == 0) {
     double ss = 0.0, yz = 0.0;
@@ -628,7 +798,7 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
     ss = wave_sum(ss);
     yz = wave_sum(yz);
     if (lane == 0) {
-      shs = step_scalars(y, ss, j, scaling);
+      shs = step_scalars(yj, ss, scaling);
       yzs = yz;
     }
   }
@@ -636,6 +806,11 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
   const StepScalars sc = shs;
   const double sr = sc.sigma * sc.rho;
   if (q < j) {
+    double dv = 0.0, ev = 0.0;
+    for (int i = 0; i < nsub; ++i) {
+      dv += pd[q + QW * i];
+      ev += pe[q + QW * i];
+    }
     d[q] = sc.ident ? sjq : (dv + sr * sjq) / sc.alpha;
     e[q] = ev;
   }

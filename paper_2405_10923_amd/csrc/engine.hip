@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(TALL_TPB) k_tall(const ColProblem P, int32_t j
 
 template <typename ST, int KIND>
 __global__ void __launch_bounds__(1024) k_red(const ColProblem P, int32_t j, int next) {
-  red_block<ST, KIND>(P, j, next, blockIdx.x);
+  red_split_block<ST, KIND>(P, j, next, blockIdx.y, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(1024) k_fin(const ColProblem P, int32_t j, int next) {
@@ -313,9 +313,11 @@ template <typename ST>
 int step_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st) {
   const ColProblem P = make_col_problem(a, w, tall_tpw(a.n, sizeof(ST)));
   if (a.kind == RHQR_SKETCH_IDENT)
-    hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_IDENT>), dim3(P.gred), dim3(1024), 0, st, P, j, next);
+    hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_IDENT>), dim3(red_splits(j), P.gred), dim3(1024), 0,
+                       st, P, j, next);
   else
-    hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_SRHT>), dim3(P.gred), dim3(1024), 0, st, P, j, next);
+    hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_SRHT>), dim3(red_splits(j), P.gred), dim3(1024), 0,
+                       st, P, j, next);
   RHQR_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_fin, dim3(fin_groups(j)), dim3(1024), 0, st, P, j, next);
   RHQR_HIP(hipGetLastError());
