@@ -1085,4 +1085,170 @@ __device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int
 }
 
 
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// ------------------------- panel update on matrix cores, float64 / float32
+// W[m:n, J:J+nb] -= U[m:n, K0:J] C_{K0:J} (nb <= NC, C with row pitch pw,
+// zero beyond nb) on v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4, transposed so
+// that rows of W run along the 16 lanes of a product's j index:
+//   D^t (panel columns x rows) = W_panel^t + (-C)^t U^t.
+// Each lane loads 16 bytes (VEC = 2 float64 or 4 float32 consecutive rows) of
+// one column of U; element e of every lane forms one 16-row operand (rows
+// VEC j + e).  The accumulators start from the panel itself (same layout,
+// 16-byte loads) and are stored back as they are.  A wave owns PX_RG groups of
+// 16 VEC rows; PX_KS steps of 4 columns (U and -C) are loaded together ahead
+// of their products.  Waves that cross row m or n take guarded element
+// accesses; rows < m are never written.  Needs 16-byte aligned columns.
+constexpr int PX_RG = 2;     // row groups of 16 VEC rows per wave
+constexpr int PX_KS = 4;     // 4-column steps loaded together
+constexpr int PX_WAVES = 4;  // waves per workgroup
+constexpr int PX_MIN_NB = 8; // narrower panels stay on the vector units (k_panel)
+
+template <typename ST> struct PxOps;
+// di(q, t): the row i of D that accumulator element t of a lane in lane
+// group q = lane / 16 holds (probed: float64 i = q + 4 t, float32 i = 4 q + t)
+template <> struct PxOps<double> {
+  typedef f64x4_t acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static constexpr __device__ int di(int q, int t) { return q + 4 * t; }
+};
+template <> struct PxOps<float> {
+  typedef f32x4_t acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static constexpr __device__ int di(int q, int t) { return 4 * q + t; }
+};
+
+template <typename ST, int NC, bool FULL>
+__device__ __forceinline__ void panel_mx_wave(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
+                                              int32_t K0, int32_t J, int32_t nb, int pw,
+                                              const double *__restrict__ C, int64_t row0) {
+  using Ops = PxOps<ST>;
+  using acc_t = typename Ops::acc_t;
+  constexpr int VEC = 16 / sizeof(ST);
+  constexpr int GR = 16 * VEC;  // rows per group
+  constexpr int NCT = NC / 16;
+  const int lane = threadIdx.x & 63;
+  const int i16 = lane & 15, kq = lane >> 4;
+  // this lane's rows in group g: rv(g) + e, e < VEC
+  auto rv = [&](int g) { return row0 + (int64_t)g * GR + VEC * i16; };
+  auto ldv = [&](const ST *col, int64_t r, ST (&x)[VEC], bool headok) {
+    if constexpr (FULL) {
+      typedef ST vec_t __attribute__((ext_vector_type(VEC)));
+      const vec_t v = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(col + r));
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) x[e] = v[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+        x[e] = (r + e < n && (headok || r + e >= m)) ? col[r + e] : (ST)0;
+    }
+  };
+  acc_t acc[PX_RG][VEC][NCT];
+  // acc[g][e][ct][t] = panel column 16 ct + di(kq, t), row rv(g) + e
+#pragma unroll
+  for (int g = 0; g < PX_RG; ++g)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = 16 * ct + Ops::di(kq, t);
+        ST x[VEC];
+        if (c < nb) {
+          ldv(W + (int64_t)(J + c) * ldw, rv(g), x, false);
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) x[e] = (ST)0;
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[g][e][ct][t] = x[e];
+      }
+  for (int k0 = K0; k0 < J; k0 += 4 * PX_KS) {
+    ST ub[PX_KS][PX_RG][VEC];
+    ST cf[PX_KS][NCT];
+#pragma unroll
+    for (int s = 0; s < PX_KS; ++s) {
+      const int k = k0 + 4 * s + kq;
+      const bool kv = k < J;
+      const int kc = kv ? k : J - 1;  // clamped: every load is in bounds
+      const ST *col = W + (int64_t)kc * ldw;
+#pragma unroll
+      for (int g = 0; g < PX_RG; ++g) ldv(col, rv(g), ub[s][g], true);
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        const int c = 16 * ct + i16;  // < NC <= pw
+        const double cv = C[(int64_t)kc * pw + c];
+        cf[s][ct] = (kv && c < nb) ? (ST)(-cv) : (ST)0;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < PX_KS; ++s) {
+      // a column beyond J contributes zero coefficients; its (clamped) values
+      // are zeroed too, so no non-finite entry can enter the sum
+      const bool kv = k0 + 4 * s + kq < J;
+#pragma unroll
+      for (int g = 0; g < PX_RG; ++g)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const ST b = kv ? ub[s][g][e] : (ST)0;
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) acc[g][e][ct] = Ops::mma(cf[s][ct], b, acc[g][e][ct]);
+        }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < PX_RG; ++g)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = 16 * ct + Ops::di(kq, t);
+        if (c >= nb) continue;
+        ST *col = W + (int64_t)(J + c) * ldw;
+        const int64_t r = rv(g);
+        if constexpr (FULL) {
+          typedef ST vec_t __attribute__((ext_vector_type(VEC)));
+          vec_t v;
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) v[e] = acc[g][e][ct][t];
+          *reinterpret_cast<vec_t *>(col + r) = v;
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            if (r + e >= m && r + e < n) col[r + e] = acc[g][e][ct][t];
+        }
+      }
+}
+
+// one workgroup of PX_WAVES waves; wave w of workgroup bid owns the rows from
+// (m rounded down to VEC) + (PX_WAVES bid + w) PX_RG 16 VEC
+template <typename ST, int NC>
+__device__ __forceinline__ void panel_mx_block(ST *__restrict__ W, int64_t ldw, int64_t n,
+                                               int32_t m, int32_t K0, int32_t J, int32_t nb, int pw,
+                                               const double *__restrict__ C, int64_t bid) {
+  constexpr int VEC = 16 / sizeof(ST);
+  const int w = threadIdx.x >> 6;
+  const int64_t rb = m - (m % VEC);
+  const int64_t row0 = rb + (bid * PX_WAVES + w) * (PX_RG * 16 * VEC);
+  if (row0 >= n) return;  // whole wave beyond the last row (uniform)
+  if (row0 >= m && row0 + PX_RG * 16 * VEC <= n)
+    panel_mx_wave<ST, NC, true>(W, ldw, n, m, K0, J, nb, pw, C, row0);
+  else
+    panel_mx_wave<ST, NC, false>(W, ldw, n, m, K0, J, nb, pw, C, row0);
+}
+
+// workgroups of panel_mx_block over rows m..n
+__host__ __device__ inline int64_t panel_mx_groups(int64_t n, int32_t m, int es) {
+  const int vec = 16 / es;
+  const int64_t wr = PX_RG * 16 * vec;
+  const int64_t waves = (n - (m - m % vec) + wr - 1) / wr;
+  return (waves + PX_WAVES - 1) / PX_WAVES;
+}
+
+
 }  // namespace

@@ -150,7 +150,6 @@ __global__ void k_qhead(int32_t m, const double *S, int64_t lds, const double *M
 // during the products.  Operand layout (probed): A[i = lane % 16][k = lane / 16],
 // B[k = lane / 16][j = lane % 16], D[i = lane / 16 + 4 t][j = lane % 16].
 constexpr int QF_NC = 128, QF_KC = 16;
-typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_qtail64(const double *__restrict__ U, int64_t ldu,
                                                  int64_t rows, int32_t m,
@@ -524,7 +523,6 @@ constexpr int PM_WAVES = 4;
 
 typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
 typedef short s16x4_t __attribute__((ext_vector_type(4)));
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 template <typename ST> __device__ __forceinline__ float dec16(unsigned short b) {
   if constexpr (std::is_same<ST, __half>::value)
@@ -904,6 +902,31 @@ void launch_panel(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t 
     launch_panel_w<ST, 32>(W, ldw, n, m, K0, J, nb, C, aligned, st, e0, e1);
 }
 
+// W[m:n, J:J+nb] -= U[m:n, K0:J] C_{K0:J} on matrix cores (float64 / float32)
+template <typename ST, int NC>
+__global__ void __launch_bounds__(PX_WAVES * 64) k_panel_mx(ST *__restrict__ W, int64_t ldw,
+                                                            int64_t n, int32_t m, int32_t K0,
+                                                            int32_t J, int32_t nb, int pw,
+                                                            const double *__restrict__ C) {
+  panel_mx_block<ST, NC>(W, ldw, n, m, K0, J, nb, pw, C, blockIdx.x);
+}
+
+template <typename ST, int NC>
+void launch_panel_mx(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,
+                     int pw, const double *C, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  constexpr int VEC = 16 / sizeof(ST);
+  constexpr int WR = PX_RG * 16 * VEC;  // rows per wave
+  if (pw < NC || nb > NC) return;  // not reached: the caller picks NC = pw >= nb
+  const int64_t waves = (n - (m - m % VEC) + WR - 1) / WR;
+  const dim3 grid((unsigned)((waves + PX_WAVES - 1) / PX_WAVES));
+  if (e0)
+    hipExtLaunchKernelGGL((k_panel_mx<ST, NC>), grid, dim3(PX_WAVES * 64), 0, st, e0, e1, 0, W,
+                          ldw, n, m, K0, J, nb, pw, C);
+  else
+    hipLaunchKernelGGL((k_panel_mx<ST, NC>), grid, dim3(PX_WAVES * 64), 0, st, W, ldw, n, m, K0, J,
+                       nb, pw, C);
+}
+
 // 2-byte storage: the panel update runs on matrix cores (k_panel_mfma);
 // otherwise on the vector units (k_panel)
 template <typename ST> constexpr bool panel_on_mfma() { return sizeof(ST) == 2; }
@@ -966,7 +989,13 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, 
         launch_panel_mfma<ST, 32>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, mf, st, e0,
                                   e1);
     } else {
-      launch_panel<ST>(W, a.ldw, a.n, m, K0, J, nb, (const double *)C, st, e0, e1);
+      const int aligned = ((uintptr_t)W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
+      if (aligned && nb > PX_MIN_NB && nb <= 16)
+        launch_panel_mx<ST, 16>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
+      else if (aligned && nb > PX_MIN_NB)
+        launch_panel_mx<ST, 32>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
+      else
+        launch_panel<ST>(W, a.ldw, a.n, m, K0, J, nb, (const double *)C, st, e0, e1);
     }
     RHQR_HIP(hipGetLastError());
     return RHQR_OK;
