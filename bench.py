@@ -93,7 +93,7 @@ def _nparts(n, es):
 # on this workload: two levels, inner panels of 8 (float64, float32) or 16
 # (2-byte storage, panel update on matrix cores) in outer panels of 32
 # (float32: 16)
-SCHEDULES = {"float64": (8, 32), "float32": (8, 32), "float16": (16, 32), "bfloat16": (16, 32)}
+SCHEDULES = {"float64": (8, 32), "float32": (8, 32), "float16": (16, 0), "bfloat16": (16, 0)}
 
 
 def sched_kw(dt):

@@ -130,11 +130,9 @@ __global__ void __launch_bounds__(PANEL_TPB) kb_panel(const ColProblem *__restri
   const int32_t nb = Q.m - J < BATCH_PB ? Q.m - J : BATCH_PB;
   // the same choice of units and arithmetic as the single-problem update
   static_assert(PANEL_TPB == PX_WAVES * 64, "one panel workgroup layout for both units");
-  if constexpr (sizeof(ST) >= 4) {
-    if (Q.aligned && nb > PX_MIN_NB) {
-      panel_mx_block<ST, BATCH_PB>((ST *)Q.W, Q.ldw, Q.n, Q.m, 0, J, nb, BATCH_PB, Q.C, b.local);
-      return;
-    }
+  if (Q.aligned && nb > PX_MIN_NB) {
+    panel_mx_block<ST, BATCH_PB>((ST *)Q.W, Q.ldw, Q.n, Q.m, 0, J, nb, BATCH_PB, Q.C, b.local);
+    return;
   }
   panel_block<ST, BATCH_PB>((ST *)Q.W, Q.ldw, Q.n, Q.m, 0, J, nb, Q.C, Q.aligned, b.local);
 }
@@ -186,14 +184,14 @@ size_t problem_bytes(const rhqr_sketch_s *h, int dtype) {
 }
 
 // panel-update workgroups of one problem (rows from m rounded down to VEC):
-// enough for the vector-unit layout and, for 4- and 8-byte types, the
-// matrix-core one (each workgroup returns beyond its own last row)
+// enough for both the vector-unit and the matrix-core layout (each workgroup
+// returns beyond its own last row)
 int64_t panel_groups(int64_t n, int32_t m, int dtype) {
   const int es = (int)dtype_size(dtype);
   const int vec = es == 8 ? 2 : 4;
   const int64_t mb0 = m - (m % vec);
   const int64_t g = (n - mb0 + (int64_t)PANEL_TPB * vec - 1) / ((int64_t)PANEL_TPB * vec);
-  return es >= 4 ? std::max(g, panel_mx_groups(n, m, es)) : g;
+  return std::max(g, panel_mx_groups(n, m, es));
 }
 
 int plan(const rhqr_problem *probs, int32_t count, int dtype, Layout *o) {

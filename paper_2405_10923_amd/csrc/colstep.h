@@ -1088,24 +1088,28 @@ __device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// ------------------------- panel update on matrix cores, float64 / float32
+// ------------------------------------------ panel update on matrix cores
 // W[m:n, J:J+nb] -= U[m:n, K0:J] C_{K0:J} (nb <= NC, C with row pitch pw,
-// zero beyond nb) on v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4, transposed so
-// that rows of W run along the 16 lanes of a product's j index:
+// zero beyond nb) on v_mfma_f64_16x16x4 (float64 storage) or
+// v_mfma_f32_16x16x4 (float32 and 2-byte storage, float32 products and
+// accumulation as on the vector units), transposed so that rows of W run
+// along the 16 lanes of a product's j index:
 //   D^t (panel columns x rows) = W_panel^t + (-C)^t U^t.
-// Each lane loads 16 bytes (VEC = 2 float64 or 4 float32 consecutive rows) of
-// one column of U; element e of every lane forms one 16-row operand (rows
-// VEC j + e).  The accumulators start from the panel itself (same layout,
-// 16-byte loads) and are stored back as they are.  A wave owns PX_RG groups of
-// 16 VEC rows; PX_KS steps of 4 columns (U and -C) are loaded together ahead
-// of their products.  Waves that cross row m or n take guarded element
-// accesses; rows < m are never written.  Needs 16-byte aligned columns.
-constexpr int PX_RG = 2;     // row groups of 16 VEC rows per wave
+// Each lane loads 16 bytes (VEC = 2, 4 or 8 consecutive rows) of one column
+// of U; element e of every lane forms one 16-row operand (rows VEC j + e).
+// The accumulators start from the panel itself (same layout, 16-byte loads)
+// and are stored back as they are.  A wave owns px_rg groups of 16 VEC rows;
+// PX_KS steps of 4 columns (U as raw 16-byte words, and -C) are loaded
+// together ahead of their products.  Waves that cross row m or n take guarded
+// element accesses; rows < m are never written.  Needs 16-byte aligned
+// columns.
 constexpr int PX_KS = 4;     // 4-column steps loaded together
 constexpr int PX_WAVES = 4;  // waves per workgroup
 constexpr int PX_MIN_NB = 8; // narrower panels stay on the vector units (k_panel)
+// row groups of 16 VEC rows per wave: 64 rows (float64) or 128 rows
+__host__ __device__ constexpr int px_rg(int es) { return es == 2 ? 1 : 2; }
 
-template <typename ST> struct PxOps;
+template <typename CT> struct PxOps;
 // di(q, t): the row i of D that accumulator element t of a lane in lane
 // group q = lane / 16 holds (probed: float64 i = q + 4 t, float32 i = 4 q + t)
 template <> struct PxOps<double> {
@@ -1127,49 +1131,56 @@ template <typename ST, int NC, bool FULL>
 __device__ __forceinline__ void panel_mx_wave(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
                                               int32_t K0, int32_t J, int32_t nb, int pw,
                                               const double *__restrict__ C, int64_t row0) {
-  using Ops = PxOps<ST>;
+  using CT = typename CompT<ST>::type;
+  using Ops = PxOps<CT>;
   using acc_t = typename Ops::acc_t;
+  using UT = std::conditional_t<sizeof(ST) == 8, uint64_t,
+                                std::conditional_t<sizeof(ST) == 4, uint32_t, uint16_t>>;
   constexpr int VEC = 16 / sizeof(ST);
+  constexpr int RG = px_rg(sizeof(ST));
   constexpr int GR = 16 * VEC;  // rows per group
   constexpr int NCT = NC / 16;
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15, kq = lane >> 4;
   // this lane's rows in group g: rv(g) + e, e < VEC
   auto rv = [&](int g) { return row0 + (int64_t)g * GR + VEC * i16; };
-  auto ldv = [&](const ST *col, int64_t r, ST (&x)[VEC], bool headok) {
+  // 16 bytes of a column from row r as raw words; !FULL: element by element,
+  // rows >= n (and rows < m unless headok) read as zero
+  auto ldraw = [&](const ST *col, int64_t r, bool headok) -> u32x4 {
     if constexpr (FULL) {
-      typedef ST vec_t __attribute__((ext_vector_type(VEC)));
-      const vec_t v = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(col + r));
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) x[e] = v[e];
+      return vraw_nt(col + r);
     } else {
+      const UT *cu = reinterpret_cast<const UT *>(col);
+      UT e[VEC];
 #pragma unroll
-      for (int e = 0; e < VEC; ++e)
-        x[e] = (r + e < n && (headok || r + e >= m)) ? col[r + e] : (ST)0;
+      for (int q = 0; q < VEC; ++q) e[q] = (r + q < n && (headok || r + q >= m)) ? cu[r + q] : (UT)0;
+      u32x4 u;
+      __builtin_memcpy(&u, e, 16);
+      return u;
     }
   };
-  acc_t acc[PX_RG][VEC][NCT];
+  acc_t acc[RG][VEC][NCT];
   // acc[g][e][ct][t] = panel column 16 ct + di(kq, t), row rv(g) + e
 #pragma unroll
-  for (int g = 0; g < PX_RG; ++g)
+  for (int g = 0; g < RG; ++g)
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int c = 16 * ct + Ops::di(kq, t);
-        ST x[VEC];
+        CT x[VEC];
         if (c < nb) {
-          ldv(W + (int64_t)(J + c) * ldw, rv(g), x, false);
+          vdecode<ST, CT>(ldraw(W + (int64_t)(J + c) * ldw, rv(g), false), x);
         } else {
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) x[e] = (ST)0;
+          for (int e = 0; e < VEC; ++e) x[e] = (CT)0;
         }
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[g][e][ct][t] = x[e];
       }
   for (int k0 = K0; k0 < J; k0 += 4 * PX_KS) {
-    ST ub[PX_KS][PX_RG][VEC];
-    ST cf[PX_KS][NCT];
+    u32x4 ub[PX_KS][RG];
+    CT cf[PX_KS][NCT];
 #pragma unroll
     for (int s = 0; s < PX_KS; ++s) {
       const int k = k0 + 4 * s + kq;
@@ -1177,12 +1188,12 @@ __device__ __forceinline__ void panel_mx_wave(ST *__restrict__ W, int64_t ldw, i
       const int kc = kv ? k : J - 1;  // clamped: every load is in bounds
       const ST *col = W + (int64_t)kc * ldw;
 #pragma unroll
-      for (int g = 0; g < PX_RG; ++g) ldv(col, rv(g), ub[s][g], true);
+      for (int g = 0; g < RG; ++g) ub[s][g] = ldraw(col, rv(g), true);
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) {
         const int c = 16 * ct + i16;  // < NC <= pw
         const double cv = C[(int64_t)kc * pw + c];
-        cf[s][ct] = (kv && c < nb) ? (ST)(-cv) : (ST)0;
+        cf[s][ct] = (kv && c < nb) ? (CT)(-cv) : (CT)0;
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -1192,17 +1203,20 @@ __device__ __forceinline__ void panel_mx_wave(ST *__restrict__ W, int64_t ldw, i
       // are zeroed too, so no non-finite entry can enter the sum
       const bool kv = k0 + 4 * s + kq < J;
 #pragma unroll
-      for (int g = 0; g < PX_RG; ++g)
+      for (int g = 0; g < RG; ++g) {
+        CT x[VEC];
+        vdecode<ST, CT>(ub[s][g], x);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          const ST b = kv ? ub[s][g][e] : (ST)0;
+          const CT b = kv ? x[e] : (CT)0;
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) acc[g][e][ct] = Ops::mma(cf[s][ct], b, acc[g][e][ct]);
         }
+      }
     }
   }
 #pragma unroll
-  for (int g = 0; g < PX_RG; ++g)
+  for (int g = 0; g < RG; ++g)
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
@@ -1211,22 +1225,21 @@ __device__ __forceinline__ void panel_mx_wave(ST *__restrict__ W, int64_t ldw, i
         if (c >= nb) continue;
         ST *col = W + (int64_t)(J + c) * ldw;
         const int64_t r = rv(g);
-        if constexpr (FULL) {
-          typedef ST vec_t __attribute__((ext_vector_type(VEC)));
-          vec_t v;
+        CT v[VEC];
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) v[e] = acc[g][e][ct][t];
-          *reinterpret_cast<vec_t *>(col + r) = v;
+        for (int e = 0; e < VEC; ++e) v[e] = acc[g][e][ct][t];
+        if constexpr (FULL) {
+          vstore<ST, CT>(col + r, v);
         } else {
 #pragma unroll
           for (int e = 0; e < VEC; ++e)
-            if (r + e >= m && r + e < n) col[r + e] = acc[g][e][ct][t];
+            if (r + e >= m && r + e < n) col[r + e] = cvt_out<ST>((double)v[e]);
         }
       }
 }
 
 // one workgroup of PX_WAVES waves; wave w of workgroup bid owns the rows from
-// (m rounded down to VEC) + (PX_WAVES bid + w) PX_RG 16 VEC
+// (m rounded down to VEC) + (PX_WAVES bid + w) px_rg 16 VEC
 template <typename ST, int NC>
 __device__ __forceinline__ void panel_mx_block(ST *__restrict__ W, int64_t ldw, int64_t n,
                                                int32_t m, int32_t K0, int32_t J, int32_t nb, int pw,
@@ -1234,9 +1247,10 @@ __device__ __forceinline__ void panel_mx_block(ST *__restrict__ W, int64_t ldw, 
   constexpr int VEC = 16 / sizeof(ST);
   const int w = threadIdx.x >> 6;
   const int64_t rb = m - (m % VEC);
-  const int64_t row0 = rb + (bid * PX_WAVES + w) * (PX_RG * 16 * VEC);
+  constexpr int WR = px_rg(sizeof(ST)) * 16 * VEC;  // rows per wave
+  const int64_t row0 = rb + (bid * PX_WAVES + w) * WR;
   if (row0 >= n) return;  // whole wave beyond the last row (uniform)
-  if (row0 >= m && row0 + PX_RG * 16 * VEC <= n)
+  if (row0 >= m && row0 + WR <= n)
     panel_mx_wave<ST, NC, true>(W, ldw, n, m, K0, J, nb, pw, C, row0);
   else
     panel_mx_wave<ST, NC, false>(W, ldw, n, m, K0, J, nb, pw, C, row0);
@@ -1245,7 +1259,7 @@ __device__ __forceinline__ void panel_mx_block(ST *__restrict__ W, int64_t ldw, 
 // workgroups of panel_mx_block over rows m..n
 __host__ __device__ inline int64_t panel_mx_groups(int64_t n, int32_t m, int es) {
   const int vec = 16 / es;
-  const int64_t wr = PX_RG * 16 * vec;
+  const int64_t wr = px_rg(es) * 16 * vec;
   const int64_t waves = (n - (m - m % vec) + wr - 1) / wr;
   return (waves + PX_WAVES - 1) / PX_WAVES;
 }

@@ -915,7 +915,7 @@ template <typename ST, int NC>
 void launch_panel_mx(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,
                      int pw, const double *C, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   constexpr int VEC = 16 / sizeof(ST);
-  constexpr int WR = PX_RG * 16 * VEC;  // rows per wave
+  constexpr int WR = px_rg(sizeof(ST)) * 16 * VEC;  // rows per wave
   if (pw < NC || nb > NC) return;  // not reached: the caller picks NC = pw >= nb
   const int64_t waves = (n - (m - m % VEC) + WR - 1) / WR;
   const dim3 grid((unsigned)((waves + PX_WAVES - 1) / PX_WAVES));
@@ -927,8 +927,9 @@ void launch_panel_mx(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32
                        nb, pw, C);
 }
 
-// 2-byte storage: the panel update runs on matrix cores (k_panel_mfma);
-// otherwise on the vector units (k_panel)
+// Panels the matrix-core update k_panel_mx does not take (8 columns or fewer,
+// unaligned columns): for 2-byte storage the split-coefficient matrix-core
+// update (k_panel_mfma), otherwise the vector units (k_panel)
 template <typename ST> constexpr bool panel_on_mfma() { return sizeof(ST) == 2; }
 
 template <typename ST, int NC>
@@ -981,7 +982,12 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, 
     if (ntail == 0) return RHQR_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (g_prof.on && prof_pair(&e0, &e1, 1)) return RHQR_ERR_HIP;
-    if constexpr (panel_on_mfma<ST>()) {
+    const int aligned = ((uintptr_t)W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
+    if (aligned && nb > PX_MIN_NB && nb <= 16) {
+      launch_panel_mx<ST, 16>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
+    } else if (aligned && nb > PX_MIN_NB) {
+      launch_panel_mx<ST, 32>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
+    } else if constexpr (panel_on_mfma<ST>()) {
       if (nb <= 16)
         launch_panel_mfma<ST, 16>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, mf, st, e0,
                                   e1);
@@ -989,13 +995,7 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, 
         launch_panel_mfma<ST, 32>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, mf, st, e0,
                                   e1);
     } else {
-      const int aligned = ((uintptr_t)W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
-      if (aligned && nb > PX_MIN_NB && nb <= 16)
-        launch_panel_mx<ST, 16>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
-      else if (aligned && nb > PX_MIN_NB)
-        launch_panel_mx<ST, 32>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
-      else
-        launch_panel<ST>(W, a.ldw, a.n, m, K0, J, nb, (const double *)C, st, e0, e1);
+      launch_panel<ST>(W, a.ldw, a.n, m, K0, J, nb, (const double *)C, st, e0, e1);
     }
     RHQR_HIP(hipGetLastError());
     return RHQR_OK;
