@@ -87,12 +87,9 @@ int engine_tall(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st);
 int engine_step(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st);
 // blocked schedule: panels of `panel` (<= 32) columns, optionally grouped in
 // outer panels of `outer` (a multiple of panel, <= 32; outer <= panel: one
-// level); C and G are float64 scratch of m x 32 entries each, mf
-// panel_mfma_bytes(m) bytes
+// level); C and G are float64 scratch of m x 32 entries each
 int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, int outer, double *C,
-                            double *G, void *mf, hipStream_t st);
-// scratch of the matrix-core panel update (split coefficients and scales)
-size_t panel_mfma_bytes(int32_t m);
+                            double *G, hipStream_t st);
 // thin Q = [I; 0] - U T U_1^t (Sec. 3.2); Mq: m x m float64 scratch, qmf:
 // thin_q_bytes(m) bytes of scratch (2-byte storage: split coefficients)
 size_t thin_q_bytes(int32_t m);

@@ -505,16 +505,15 @@ __global__ void __launch_bounds__(PANEL_TPB) k_trsm_blk(const ST *__restrict__ B
   }
 }
 
-// ------------------------------------------- panel update on matrix cores
-// 2-byte storage, nb <= 32: W[m:n, J:J+nb] -= U[m:n, K0:J] C on float32 MFMA
-// (v_mfma_f32_16x16x16 f16 / bf16).  C (float64) is scaled per column by a
-// power of two s_j (max |C_{:,j}| / s_j in (1/2, 1]) and split into two
-// storage-type parts, C / s = hi + lo, so the coefficients keep about 22
-// (f16) or 16 (bf16) bits; the products accumulate in float32 as on the
-// vector path.  Each wave owns 64 rows: it loads 32 columns of U with 16-byte
-// row-contiguous loads, transposes them through its own LDS slice (the MFMA
-// operand needs 4 consecutive columns per lane) and issues the next chunk's
-// loads before the current chunk's products.
+// ------------------------------- 2-byte products on matrix cores (thin Q)
+// Float32-accumulating v_mfma_f32_16x16x16 f16 / bf16 products of n-row data
+// with a float64 matrix that is scaled per column by a power of two s_j
+// (max |B_{:,j}| / s_j in (1/2, 1]) and split into two storage-type parts,
+// B / s = hi + lo, so the coefficients keep about 22 (f16) or 16 (bf16) bits.
+// Each wave owns 64 rows: it loads 32 columns with 16-byte row-contiguous
+// loads, transposes them through its own LDS slice (the operand needs 4
+// consecutive columns per lane) and issues the next chunk's loads before the
+// current chunk's products.
 constexpr int PM_ROWS = 64;                // rows per wave
 constexpr int PM_KC = 32;                  // columns of U per chunk
 constexpr int PM_KP = 2 * PM_KC;           // chunks go in pairs; coefficient rows padded to this
@@ -529,46 +528,6 @@ template <typename ST> __device__ __forceinline__ float dec16(unsigned short b) 
     return __half2float(__ushort_as_half(b));
   else
     return __uint_as_float(((uint32_t)b) << 16);
-}
-
-// Scales and split coefficients in the MFMA B-operand order: for column group
-// g (columns 4g..4g+3 of U, i.e. rows of C) and panel column j < NC, the four
-// values sit at B[(g * NC + j) * 4 + t].  Rows k >= J and columns j >= nb are
-// zero; Kp = J rounded up to PM_KP.  One workgroup of 16 waves, wave w
-// scaling columns w, w + 16, ...
-template <typename ST, int NC>
-__global__ void __launch_bounds__(1024) k_pconv(int32_t J, int32_t nb, int32_t pw, int32_t Kp,
-                                               const double *__restrict__ Ct,
-                                               unsigned short *__restrict__ Bh,
-                                               unsigned short *__restrict__ Bl,
-                                               float *__restrict__ scale) {
-  __shared__ float sc[NC];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int h = 0; h < NC / 16; ++h) {
-    const int j = w + 16 * h;
-    double mx = 0.0;
-    if (j < nb)
-      for (int k = lane; k < J; k += 64) mx = fmax(mx, fabs(Ct[(int64_t)k * pw + j]));
-    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-    if (lane == 0) {
-      int e = 0;
-      if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [1/2, 1)
-      sc[j] = ldexpf(1.0f, e);
-    }
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < Kp * NC; idx += blockDim.x) {
-    const int k = idx / NC, jj = idx % NC;
-    double v = 0.0;
-    if (k < J && jj < nb) v = Ct[(int64_t)k * pw + jj] / (double)sc[jj];
-    const unsigned short h = enc16<ST>((float)v);
-    const unsigned short lo = enc16<ST>((float)(v - (double)dec16<ST>(h)));
-    const int o = (((k >> 2) * NC + jj) << 2) + (k & 3);
-    Bh[o] = h;
-    Bl[o] = lo;
-  }
-  if (threadIdx.x < NC) scale[threadIdx.x] = sc[threadIdx.x];
 }
 
 template <typename ST>
@@ -651,95 +610,6 @@ __device__ __forceinline__ void mfma_chunk(const u32x4 (&buf)[4], const uint2 (&
       for (int h = 0; h < NC / 16; ++h) {
         acc[mb][h] = mfma16<ST>(a, bh[kk][h], acc[mb][h]);
         acc[mb][h] = mfma16<ST>(a, bl[kk][h], acc[mb][h]);
-      }
-    }
-  }
-}
-
-template <typename ST, bool FULL, int NC>
-__device__ __forceinline__ void panel_mfma_wave(ST *__restrict__ W, int64_t ldw, int64_t n,
-                                                int32_t J, const unsigned short *__restrict__ Bh,
-                                                const unsigned short *__restrict__ Bl,
-                                                unsigned short *sl, int64_t rb,
-                                                f32x4_t (&acc)[4][NC / 16]) {
-  const int lane = threadIdx.x & 63;
-  auto coefs = [&](int k0, uint2 (&bh)[PM_KC / 16][NC / 16], uint2 (&bl)[PM_KC / 16][NC / 16]) {
-#pragma unroll
-    for (int kk = 0; kk < PM_KC / 16; ++kk) {
-      const int g = (k0 >> 2) + kk * 4 + (lane >> 4);  // column group of this lane
-#pragma unroll
-      for (int h = 0; h < NC / 16; ++h) {
-        const int o = (g * NC + 16 * h + (lane & 15)) << 2;
-        bh[kk][h] = *reinterpret_cast<const uint2 *>(Bh + o);
-        bl[kk][h] = *reinterpret_cast<const uint2 *>(Bl + o);
-      }
-    }
-  };
-  for (int k0 = 0; k0 < J; k0 += PM_KP) {
-    u32x4 ba[4], bb[4];
-    uint2 ha[PM_KC / 16][NC / 16], la[PM_KC / 16][NC / 16];
-    uint2 hb[PM_KC / 16][NC / 16], lb[PM_KC / 16][NC / 16];
-    coefs(k0, ha, la);
-    mfma_fetch<ST, FULL>(W, ldw, n, J, rb, k0, ba);
-    coefs(k0 + PM_KC, hb, lb);
-    mfma_fetch<ST, FULL>(W, ldw, n, J, rb, k0 + PM_KC, bb);
-    __builtin_amdgcn_sched_barrier(0);  // all of the pair's loads issued first
-    mfma_chunk<ST, NC>(ba, ha, la, sl, acc);
-    mfma_chunk<ST, NC>(bb, hb, lb, sl, acc);
-  }
-}
-
-// W[m:n, J:J+nb] -= U[m:n, K0:J] C_{K0:J} (Bh, Bl and scale hold C_{K0:J}),
-// nb <= NC
-template <typename ST, int NC>
-__global__ void __launch_bounds__(PM_WAVES * 64) k_panel_mfma(
-    ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,
-    const unsigned short *__restrict__ Bh, const unsigned short *__restrict__ Bl,
-    const float *__restrict__ scale, int aligned) {
-  __shared__ unsigned short lds[PM_WAVES][PM_KC * PM_RS];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t mb0 = m - (m % 8);
-  const int64_t rb = mb0 + ((int64_t)blockIdx.x * PM_WAVES + w) * PM_ROWS;  // wave's first row
-  if (rb >= n) return;  // whole wave beyond the last row (uniform)
-  const bool full = aligned && rb + PM_ROWS <= n;
-  f32x4_t acc[4][NC / 16];
-#pragma unroll
-  for (int b = 0; b < 4; ++b)
-#pragma unroll
-    for (int h = 0; h < NC / 16; ++h) acc[b][h] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  if (full)
-    panel_mfma_wave<ST, true, NC>(W + (int64_t)K0 * ldw, ldw, n, J - K0, Bh, Bl, lds[w], rb, acc);
-  else
-    panel_mfma_wave<ST, false, NC>(W + (int64_t)K0 * ldw, ldw, n, J - K0, Bh, Bl, lds[w], rb, acc);
-  // acc[mb][h][t] = (U C / s)[row rb + 16 mb + 4 (lane / 16) + t][panel column 16 h + lane % 16]
-#pragma unroll
-  for (int h = 0; h < NC / 16; ++h) {
-    const int j = 16 * h + (lane & 15);
-    if (j < nb) {
-      const float sj = scale[j];
-      ST *col = W + (int64_t)(J + j) * ldw;
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        const int64_t r0 = rb + mb * 16 + 4 * (lane >> 4);
-        if (full && r0 >= m) {
-          const uint2 old = *reinterpret_cast<const uint2 *>(col + r0);
-          const uint32_t wd[2] = {old.x, old.y};
-          uint32_t nw[2];
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const float x0 = dec16<ST>((unsigned short)(wd[q] & 0xffff)) - sj * acc[mb][h][2 * q];
-            const float x1 = dec16<ST>((unsigned short)(wd[q] >> 16)) - sj * acc[mb][h][2 * q + 1];
-            nw[q] = (uint32_t)enc16<ST>(x0) | ((uint32_t)enc16<ST>(x1) << 16);
-          }
-          *reinterpret_cast<uint2 *>(col + r0) = uint2{nw[0], nw[1]};
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int64_t r = r0 + t;
-            if (r >= m && r < n)
-              col[r] = cvt_out<ST>((double)(cvt_in<float>(col[r]) - sj * acc[mb][h][t]));
-          }
-        }
       }
     }
   }
@@ -927,39 +797,9 @@ void launch_panel_mx(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32
                        nb, pw, C);
 }
 
-// Panels the matrix-core update k_panel_mx does not take (8 columns or fewer,
-// unaligned columns): for 2-byte storage the split-coefficient matrix-core
-// update (k_panel_mfma), otherwise the vector units (k_panel)
-template <typename ST> constexpr bool panel_on_mfma() { return sizeof(ST) == 2; }
-
-template <typename ST, int NC>
-void launch_panel_mfma(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,
-                       int pw, const double *C, void *mf, hipStream_t st, hipEvent_t e0,
-                       hipEvent_t e1) {
-  const int K = J - K0;
-  const int Kp = (K + PM_KP - 1) / PM_KP * PM_KP;
-  unsigned short *Bh = (unsigned short *)mf;
-  unsigned short *Bl = Bh + (size_t)Kp * NC;
-  float *sc = (float *)(Bl + (size_t)Kp * NC);
-  hipLaunchKernelGGL((k_pconv<ST, NC>), dim3(1), dim3(1024), 0, st, K, nb, pw, Kp,
-                     C + (size_t)K0 * pw, Bh, Bl, sc);
-  const int64_t mb0 = m - (m % 8);
-  const int64_t waves = (n - mb0 + PM_ROWS - 1) / PM_ROWS;
-  const dim3 grid((unsigned)((waves + PM_WAVES - 1) / PM_WAVES));
-  const int aligned = ((uintptr_t)W % 16 == 0) && ((ldw * (int64_t)sizeof(ST)) % 16 == 0);
-  if (e0)
-    hipExtLaunchKernelGGL((k_panel_mfma<ST, NC>), grid, dim3(PM_WAVES * 64), 0, st, e0, e1, 0, W,
-                          ldw, n, m, K0, J, nb, (const unsigned short *)Bh,
-                          (const unsigned short *)Bl, (const float *)sc, aligned);
-  else
-    hipLaunchKernelGGL((k_panel_mfma<ST, NC>), grid, dim3(PM_WAVES * 64), 0, st, W, ldw, n, m, K0,
-                       J, nb, (const unsigned short *)Bh, (const unsigned short *)Bl,
-                       (const float *)sc, aligned);
-}
-
 template <typename ST>
 int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, double *C,
-                      double *G, void *mf, hipStream_t st) {
+                      double *G, hipStream_t st) {
   ST *W = (ST *)a.W;
   const int32_t m = a.m, L = a.l + a.m;
   const int64_t ntail = a.n - m;
@@ -987,14 +827,7 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, 
       launch_panel_mx<ST, 16>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
     } else if (aligned && nb > PX_MIN_NB) {
       launch_panel_mx<ST, 32>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
-    } else if constexpr (panel_on_mfma<ST>()) {
-      if (nb <= 16)
-        launch_panel_mfma<ST, 16>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, mf, st, e0,
-                                  e1);
-      else
-        launch_panel_mfma<ST, 32>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, mf, st, e0,
-                                  e1);
-    } else {
+    } else {  // 8 columns or fewer, or unaligned columns: vector units
       launch_panel<ST>(W, a.ldw, a.n, m, K0, J, nb, (const double *)C, st, e0, e1);
     }
     RHQR_HIP(hipGetLastError());
@@ -1240,15 +1073,11 @@ int engine_tall(const LoopArgs &a, const LoopWs &w, int32_t j, hipStream_t st) {
   RHQR_DISPATCH(a.dtype, tall_typed<ST>(a, w, j, 0, st))
 }
 
-size_t panel_mfma_bytes(int32_t m) {
-  const size_t Kp = (size_t)(m + PM_KP - 1) / PM_KP * PM_KP;
-  return align_up(2 * Kp * 32 * sizeof(unsigned short) + 32 * sizeof(float));
-}
 
 int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, int outer, double *C,
-                            double *G, void *mf, hipStream_t st) {
+                            double *G, hipStream_t st) {
   if (a.m > MAXM) return RHQR_ERR_UNSUPPORTED;
-  RHQR_DISPATCH(a.dtype, run_blocked_typed<ST>(a, w, panel, outer, C, G, mf, st))
+  RHQR_DISPATCH(a.dtype, run_blocked_typed<ST>(a, w, panel, outer, C, G, st))
 }
 
 int engine_step(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st) {

@@ -16,7 +16,6 @@ struct FactorWs {
   size_t skws_bytes;
   double *Mq;
   double *C, *G;  // panel coefficients (blocked schedule), m x 32 each
-  void *mf;       // split coefficients of the matrix-core panel update
   void *qmf;      // split coefficients of the matrix-core thin Q
 };
 
@@ -27,7 +26,6 @@ size_t factor_ws_bytes(const rhqr_sketch_s *h, int dtype, int32_t m) {
   b += align_up(sketch_ws_bytes(h, m));
   b += align_up(sizeof(double) * (size_t)m * m);
   b += 2 * align_up(sizeof(double) * (size_t)m * 32);
-  b += panel_mfma_bytes(m);
   b += thin_q_bytes(m);
   return b;
 }
@@ -51,8 +49,6 @@ int factor_ws_carve(const rhqr_sketch_s *h, int dtype, int32_t m, void *ws, size
   p += align_up(sizeof(double) * (size_t)m * 32);
   o->G = (double *)p;
   p += align_up(sizeof(double) * (size_t)m * 32);
-  o->mf = p;
-  p += panel_mfma_bytes(m);
   o->qmf = p;
   return RHQR_OK;
 }
@@ -126,7 +122,7 @@ extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, voi
   a.rows = h->d_rows;
   a.omega = h->d_omega;
   a.defer = 1;
-  rc = panel >= 2 ? run_column_loop_blocked(a, w.loop, panel, outer, w.C, w.G, w.mf, st)
+  rc = panel >= 2 ? run_column_loop_blocked(a, w.loop, panel, outer, w.C, w.G, st)
                   : run_column_loop(a, w.loop, st);
   if (rc) return rc;
   if (d_Q) rc = launch_thin_q(dtype, n, m, d_W, ldw, d_S, lds, d_T, ldt, w.Mq, w.qmf, d_Q, ldq, st);

@@ -34,11 +34,9 @@ def _inputs(torch, dt, kappa=3.0, shapes=SHAPES):
 @pytest.mark.parametrize("panel", [0, 16])
 @pytest.mark.parametrize("dt", ["float64", "float32", "float16", "bfloat16"])
 def test_batch_bitwise_equals_single(dt, panel):
-    """Same schedule, same device code: bitwise equal.  (2-byte storage with
-    panels: the single-problem path updates panels on matrix cores with split
-    coefficients, the batch on the vector units; elementwise agreement then
-    means nothing at the storage precision, so both are held to the
-    factorization bounds instead.)"""
+    """Same schedule, same device code, same choice of units for every panel
+    (matrix cores for panels wider than 8 with aligned columns, vector units
+    otherwise): bitwise equal in every storage type."""
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
     tdt = getattr(torch, dt)
@@ -49,24 +47,13 @@ def test_batch_bitwise_equals_single(dt, panel):
     outs = b.factor()
     torch.cuda.synchronize()
     assert b.status() == [0] * len(probs)
-    exact = not (panel and tdt in (torch.float16, torch.bfloat16))
     for (W, sk, shp), o in zip(probs, outs):
         log(f"  single {shp}")
         Wd = to_gpu(W, tdt)
         ref = rhqr.factor(sk, Wd, panel=panel)
         torch.cuda.synchronize()
-        if exact:
-            for k in ("U", "S", "T", "R"):
-                assert torch.equal(o[k], ref[k]), (shp, k)
-        else:
-            n, m, l, seed = shp
-            Win = to_np(to_gpu(W, tdt))  # the rounded input
-            osketch = osk.Sketch(osk.SRHT, n, m, l, seed=seed + 100)
-            for out in (o, ref):
-                Q = orq.thin_q(to_np(out["U"]), to_np(out["T"]), m)
-                ef = metrics.fact_error(Win, Q, to_np(out["R"]))
-                eo = metrics.orth_error(osk.rh_sketch(Q, osketch))
-                assert ef < 1e-2 and eo < 1e-2, (shp, ef, eo)
+        for k in ("U", "S", "T", "R"):
+            assert torch.equal(o[k], ref[k]), (shp, k)
     b.close()
 
 
