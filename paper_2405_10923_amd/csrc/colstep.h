@@ -23,14 +23,20 @@ __host__ __device__ inline int fin_groups(int32_t j) { return j > 0 ? (j + FIN_P
 // (d = S^t s_{j-1}, e = S^t z_j).  The step of column j-1 leaves beta and e_{j-1}
 // in fs[0..1] and per-workgroup partial sums of d_p c_p in dcpart[0..gfin); the
 // consumers (the next reduction and tall pass) finish it themselves, so the
-// step needs no cross-workgroup hand-off.  Called by whole waves; fixed order.
-__device__ __forceinline__ double deferred_c(const double *__restrict__ fs,
-                                             const double *__restrict__ dcpart, int gfin) {
+// step needs no cross-workgroup hand-off.  In two halves: the loads, issued
+// with a kernel's first loads, and the wave sum where the value is needed
+// (called by whole waves; fixed order).  gfin <= 64: one partial sum per lane.
+static_assert((MAXM + FIN_P - 1) / FIN_P <= 64, "one partial sum per lane");
+struct DeferredC {
+  double part, f0, f1;
+};
+__device__ __forceinline__ DeferredC deferred_c_load(const double *__restrict__ fs,
+                                                     const double *__restrict__ dcpart, int gfin) {
   const int lane = threadIdx.x & 63;
-  double v = 0.0;
-  for (int g = lane; g < gfin; g += 64) v += dcpart[g];
-  v = wave_sum(v);
-  return fs[0] * (fs[1] - v);
+  return DeferredC{lane < gfin ? dcpart[lane] : 0.0, fs[0], fs[1]};
+}
+__device__ __forceinline__ double deferred_c_finish(const DeferredC &d) {
+  return d.f0 * (d.f1 - wave_sum(d.part));
 }
 
 // ------------------------------------------------------------------ k_tall
@@ -40,10 +46,10 @@ __device__ __forceinline__ double deferred_c(const double *__restrict__ fs,
 // they keep their input values (head rows of W are refreshed in float64 from
 // U_1 = S_{1:m} by the reduction kernel).  !FAST: guarded element accesses
 // (ragged last tile or unaligned storage).
-template <typename ST, bool FAST, int NV, int TPB>
+template <typename ST, bool FAST, int NV, int TPB, typename CP>
 __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
                                           int32_t j, int32_t p0, bool prev,
-                                          const double *__restrict__ cf, double cprev,
+                                          const double *__restrict__ cf, const CP &cprev_of,
                                           double iaprev, int64_t base,
                                           typename CompT<ST>::type (&acc)[NV][16 / sizeof(ST)]) {
   using CT = typename CompT<ST>::type;
@@ -145,7 +151,7 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
   // (prev == false: column j-1 was already stored scaled and applied by the
   // panel update of the blocked schedule.)
   if (j >= 1 && prev) {
-    const CT cp = (CT)cprev;
+    const CT cp = (CT)cprev_of();  // formed only now: its loads were issued first
     const CT ia = (CT)iaprev;
     ST *col = W + (int64_t)(j - 1) * ldw;
 #pragma unroll
@@ -253,17 +259,23 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
     if (threadIdx.x < NSW && wi * 64 < n) sw = signs[wi];
     if ((int)threadIdx.x < l) rq = rows[threadIdx.x];
   }
-  // coefficient of the raw previous column: c_{j-1} / alpha_{j-1}
-  double iaprev = 0.0, cprev = 0.0;
+  // coefficient of the raw previous column: c_{j-1} / alpha_{j-1} (its loads
+  // issued here, its sum formed when the previous column is applied)
+  double iaprev = 0.0, cfprev = 0.0;
+  DeferredC dc{0.0, 0.0, 0.0};
   if (j >= 1 && prev) {
     iaprev = ia[j - 1];
-    cprev = defer ? deferred_c(fs, dcpart, gfin) * iaprev : cf[j - 1];
+    if (defer)
+      dc = deferred_c_load(fs, dcpart, gfin);
+    else
+      cfprev = cf[j - 1];
   }
+  auto cprev_of = [&]() { return defer ? deferred_c_finish(dc) * iaprev : cfprev; };
   CT acc[NV][VEC];
   if (fast)
-    tall_body<ST, true, NV, TPB>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, base, acc);
+    tall_body<ST, true, NV, TPB>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base, acc);
   else
-    tall_body<ST, false, NV, TPB>(W, ldw, n, m, j, p0, prev, cf, cprev, iaprev, base, acc);
+    tall_body<ST, false, NV, TPB>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base, acc);
 
   if (KIND == RHQR_SKETCH_IDENT) return;
   const int tid = threadIdx.x;
@@ -415,7 +427,8 @@ __device__ __forceinline__ void red_block(const ColProblem &P, int32_t j, int ne
     sp[b] = (valid && p < j) ? S[k + (int64_t)p * lds] : 0.0;
   }
   const double z = (next && valid) ? Z[k + (int64_t)(j + 1) * ldz] : 0.0;
-  const double clast = (j >= 1 && head && defer) ? deferred_c(fs, dcpart, gfin) : 0.0;
+  const DeferredC dc = (j >= 1 && head && defer) ? deferred_c_load(fs, dcpart, gfin)
+                                                 : DeferredC{0.0, 0.0, 0.0};
 #pragma unroll
   for (int gi = 0; gi < 16 / RW; ++gi) {
     const int g = w + RW * gi;  // this group's elements: g, g + 16, g + 32, ...
@@ -434,6 +447,8 @@ __device__ __forceinline__ void red_block(const ColProblem &P, int32_t j, int ne
             sv[b] = S[kc + (int64_t)p * lds];
             cv[b] = c[p];
           }
+          // the deferred c_{j-1}, formed after this batch's loads are issued
+          const double clast = defer ? deferred_c_finish(dc) : 0.0;
           double t[RED_NP];
 #pragma unroll
           for (int b = 0; b < RED_NP; ++b) {
@@ -567,7 +582,8 @@ __device__ __forceinline__ void red_split_block(const ColProblem &P, int32_t j, 
   const bool rawrow = w == 0 && valid && j >= 1 && (head || KIND == RHQR_SKETCH_IDENT);
   const double wjk = rawrow ? cvt_in<double>(W[k + (int64_t)j * ldw]) : 0.0;
   const double z0 = (w == 0 && valid && j == 0) ? Z[k] : 0.0;
-  const double clast = (j >= 1 && head && defer) ? deferred_c(fs, dcpart, gfin) : 0.0;
+  const DeferredC dc = (j >= 1 && head && defer) ? deferred_c_load(fs, dcpart, gfin)
+                                                 : DeferredC{0.0, 0.0, 0.0};
   double v = 0.0;
   if (j >= 1) {
     if (head) {
@@ -581,6 +597,8 @@ __device__ __forceinline__ void red_split_block(const ColProblem &P, int32_t j, 
           sv[b] = S[kc + (int64_t)p * lds];
           cv[b] = c[p];
         }
+        // the deferred c_{j-1}, formed after this batch's loads are issued
+        const double clast = defer ? deferred_c_finish(dc) : 0.0;
 #pragma unroll
         for (int b = 0; b < RH_NP; ++b) {
           const int p = p0 + 16 * b;
@@ -685,7 +703,7 @@ __device__ __forceinline__ StepScalars step_scalars(double yj, double ss, int sc
 //   d = S^t s_j,  e = S^t z_{j+1}  (from the k_red partials plus the pivot term);
 //   T_{p,j} = -beta (T_{j-1} d)_p,  c_{j+1,p} = (T_{j-1}^t e)_p  for p < j,
 // one wave per p, FIN_P values of p per workgroup; T_{j,j} = beta.  The last
-// coefficient c_{j+1,j} is left to its consumers (deferred_c): workgroup g
+// coefficient c_{j+1,j} is left to its consumers (DeferredC): workgroup g
 // writes sum_{p in g} d_p c_{j+1,p} to dcpart[g], workgroup 0 writes beta and
 // e_j to fs.  The partial sums, the rows of T and the pivot row of S are all
 // loaded before the first wait.
