@@ -115,11 +115,13 @@ __global__ void __launch_bounds__(1024) kb_pgram(const ColProblem *__restrict__ 
   pgram_block(Q.l + Q.m, J, nb, Q.S, Q.lds, Q.Z, Q.ldz, Q.G, local);
 }
 
-__global__ void kb_ptri(const ColProblem *__restrict__ P, int32_t J, int per) {
+__global__ void __launch_bounds__(PTRI_WAVES * 64) kb_ptri(const ColProblem *__restrict__ P,
+                                                          int32_t J, int per) {
   const int p = blockIdx.x / per, local = blockIdx.x % per;
   const ColProblem &Q = P[p];
   const int32_t nb = Q.m - J < BATCH_PB ? Q.m - J : BATCH_PB;
-  ptri_entry(0, J, nb, BATCH_PB, Q.T, Q.ldt, Q.G, Q.C, local * blockDim.x + threadIdx.x, blockIdx.y);
+  ptri_wave(0, J, nb, BATCH_PB, Q.T, Q.ldt, Q.G, Q.C, local * PTRI_WAVES + (threadIdx.x >> 6),
+            blockIdx.y);
 }
 
 template <typename ST>
@@ -322,8 +324,9 @@ int enqueue_typed(rhqr_batch_s *b, hipStream_t st) {
       const int pg = (J * BATCH_PB + 15) / 16;
       hipLaunchKernelGGL(kb_pgram, dim3(a * pg), dim3(1024), 0, st, b->d_probs, J, pg);
       RHQR_HIP(hipGetLastError());
-      const int pt = (J + 255) / 256;
-      hipLaunchKernelGGL(kb_ptri, dim3(a * pt, BATCH_PB), dim3(256), 0, st, b->d_probs, J, pt);
+      const int pt = (J + PTRI_WAVES - 1) / PTRI_WAVES;
+      hipLaunchKernelGGL(kb_ptri, dim3(a * pt, BATCH_PB), dim3(PTRI_WAVES * 64), 0, st, b->d_probs,
+                         J, pt);
       RHQR_HIP(hipGetLastError());
       hipLaunchKernelGGL((kb_panel<ST>), dim3(b->pan_start[a]), dim3(PANEL_TPB), 0, st, b->d_probs,
                          b->d_pan, J);

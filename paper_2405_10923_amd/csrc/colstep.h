@@ -916,6 +916,7 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
 // its coefficients), the outer update having applied those below J0.
 
 // G = S_{:, <J}^t Z_{:, J:J+nb} (J x nb, ld J), one wave per entry
+constexpr int PG_NP = 8;  // sketch rows per lane loaded together
 __device__ __forceinline__ void pgram_block(int32_t L, int32_t J, int32_t nb,
                                             const double *__restrict__ S, int64_t lds,
                                             const double *__restrict__ Z, int64_t ldz,
@@ -926,8 +927,21 @@ __device__ __forceinline__ void pgram_block(int32_t L, int32_t J, int32_t nb,
   const int p = (int)(e % J), jj = (int)(e / J);
   const double *sp = S + (int64_t)p * lds;
   const double *zp = Z + (int64_t)(J + jj) * ldz;
+  // k = lane, lane + 64, ... in increasing order, PG_NP of them loaded together
+  // (clamped indices; the extra terms are skipped)
   double v = 0.0;
-  for (int k = lane; k < L; k += 64) v += sp[k] * zp[k];
+  for (int k0 = lane; k0 < L; k0 += 64 * PG_NP) {
+    double sv[PG_NP], zv[PG_NP];
+#pragma unroll
+    for (int b = 0; b < PG_NP; ++b) {
+      const int k = min(k0 + 64 * b, L - 1);
+      sv[b] = sp[k];
+      zv[b] = zp[k];
+    }
+#pragma unroll
+    for (int b = 0; b < PG_NP; ++b)
+      if (k0 + 64 * b < L) v += sv[b] * zv[b];
+  }
   v = wave_sum(v);
   if (lane == 0) G[p + (int64_t)jj * J] = v;
 }
@@ -935,16 +949,20 @@ __device__ __forceinline__ void pgram_block(int32_t L, int32_t J, int32_t nb,
 // C = T_{<J}^t G: C_{p,jj} = sum_{q <= p} T_{q,p} G_{q,jj} for rows J0 <= p < J,
 // stored row-major (row p at C + p * pw), rows padded to pw >= nb entries
 // (zeros beyond nb): the pw coefficients of column p are contiguous and read
-// unconditionally by the panel kernel
-__device__ __forceinline__ void ptri_entry(int32_t J0, int32_t J, int32_t nb, int32_t pw,
-                                           const double *__restrict__ T, int64_t ldt,
-                                           const double *__restrict__ G, double *__restrict__ C,
-                                           int p, int jj) {
-  if (p < J0 || p >= J || jj >= pw) return;
+// unconditionally by the panel kernel.  One wave per entry (p, jj): lane i
+// adds q = i, i + 64, ..., then one wave sum.  Called by whole waves.
+constexpr int PTRI_WAVES = 4;  // waves (entries of one column jj) per workgroup
+__device__ __forceinline__ void ptri_wave(int32_t J0, int32_t J, int32_t nb, int32_t pw,
+                                          const double *__restrict__ T, int64_t ldt,
+                                          const double *__restrict__ G, double *__restrict__ C,
+                                          int p, int jj) {
+  if (p < J0 || p >= J || jj >= pw) return;  // uniform across the wave
+  const int lane = threadIdx.x & 63;
   double v = 0.0;
   if (jj < nb)
-    for (int q = 0; q <= p; ++q) v += T[q + (int64_t)p * ldt] * G[q + (int64_t)jj * J];
-  C[(int64_t)p * pw + jj] = v;
+    for (int q = lane; q <= p; q += 64) v += T[q + (int64_t)p * ldt] * G[q + (int64_t)jj * J];
+  v = wave_sum(v);
+  if (lane == 0) C[(int64_t)p * pw + jj] = v;
 }
 
 // W[m:n, J:J+nb] -= U[m:n, K0:J] C_{K0:J}.  Each thread streams VEC

@@ -79,10 +79,14 @@ __global__ void __launch_bounds__(1024) k_pgram(int32_t L, int32_t J, int32_t nb
   pgram_block(L, J, nb, S, lds, Z, ldz, G, blockIdx.x);
 }
 
-// rows J0..J-1 of C = T_{<J}^t G, padded to pw entries
-__global__ void k_ptri(int32_t J0, int32_t J, int32_t nb, int32_t pw, const double *__restrict__ T,
-                       int64_t ldt, const double *__restrict__ G, double *__restrict__ C) {
-  ptri_entry(J0, J, nb, pw, T, ldt, G, C, J0 + blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+// rows J0..J-1 of C = T_{<J}^t G, padded to pw entries; grid
+// (ceil((J - J0) / PTRI_WAVES), pw), PTRI_WAVES waves per workgroup
+__global__ void __launch_bounds__(PTRI_WAVES * 64) k_ptri(int32_t J0, int32_t J, int32_t nb,
+                                                         int32_t pw, const double *__restrict__ T,
+                                                         int64_t ldt, const double *__restrict__ G,
+                                                         double *__restrict__ C) {
+  ptri_wave(J0, J, nb, pw, T, ldt, G, C, J0 + blockIdx.x * PTRI_WAVES + (threadIdx.x >> 6),
+            blockIdx.y);
 }
 
 template <typename ST, int NBC>
@@ -816,8 +820,8 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, 
                        a.ldz, G);
     RHQR_HIP(hipGetLastError());
     const int pw = panel_width(nb);
-    hipLaunchKernelGGL(k_ptri, dim3((J - K0 + 255) / 256, pw), dim3(256), 0, st, K0, J, nb, pw,
-                       a.T, a.ldt, G, C);
+    hipLaunchKernelGGL(k_ptri, dim3((J - K0 + PTRI_WAVES - 1) / PTRI_WAVES, pw),
+                       dim3(PTRI_WAVES * 64), 0, st, K0, J, nb, pw, a.T, a.ldt, G, C);
     RHQR_HIP(hipGetLastError());
     if (ntail == 0) return RHQR_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
