@@ -46,7 +46,12 @@ __device__ __forceinline__ double deferred_c_finish(const DeferredC &d) {
 // they keep their input values (head rows of W are refreshed in float64 from
 // U_1 = S_{1:m} by the reduction kernel).  !FAST: guarded element accesses
 // (ragged last tile or unaligned storage).
-template <typename ST, bool FAST, int NV, int TPB, typename CP>
+// NTU: the stored columns are read with non-temporal loads (passes that apply
+// more than TALL_CACHED_COLS columns stream far more than the caches hold);
+// otherwise with ordinary loads (the blocked schedule's passes, whose few
+// columns were written moments before and are read again by the next pass).
+constexpr int TALL_CACHED_COLS = 32;
+template <typename ST, bool FAST, int NV, int TPB, bool NTU, typename CP>
 __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
                                           int32_t j, int32_t p0, bool prev,
                                           const double *__restrict__ cf, const CP &cprev_of,
@@ -89,7 +94,8 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
           for (int u = 0; u < UF; ++u) {
             const char *cb = (const char *)(W + (int64_t)(p + u) * ldw + base);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) raw[u][v] = vraw_nt(cb + off[v]);
+            for (int v = 0; v < NV; ++v)
+              raw[u][v] = NTU ? vraw_nt(cb + off[v]) : *reinterpret_cast<const u32x4 *>(cb + off[v]);
           }
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -112,7 +118,7 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           CT x[VEC];
-          vload<ST, CT, true>((const ST *)(cb + off[v]), x);
+          vload<ST, CT, NTU>((const ST *)(cb + off[v]), x);
 #pragma unroll
           for (int e = 0; e < VEC; ++e) acc[v][e] -= x[e] * cp;
         }
@@ -272,10 +278,13 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
   }
   auto cprev_of = [&]() { return defer ? deferred_c_finish(dc) * iaprev : cfprev; };
   CT acc[NV][VEC];
-  if (fast)
-    tall_body<ST, true, NV, TPB>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base, acc);
+  if (fast && j - 1 - p0 > TALL_CACHED_COLS)
+    tall_body<ST, true, NV, TPB, true>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base, acc);
+  else if (fast)
+    tall_body<ST, true, NV, TPB, false>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base, acc);
   else
-    tall_body<ST, false, NV, TPB>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base, acc);
+    tall_body<ST, false, NV, TPB, false>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base,
+                                         acc);
 
   if (KIND == RHQR_SKETCH_IDENT) return;
   const int tid = threadIdx.x;
