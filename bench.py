@@ -90,9 +90,8 @@ def _nparts(n, es):
 
 
 # (panel, outer) of the blocked schedule per storage type, the fastest measured
-# on this workload: two levels, inner panels of 8 (float64, float32) or 16
-# (2-byte storage, panel update on matrix cores) in outer panels of 32
-# (float32: 16)
+# on this workload: two levels, inner panels of 8 in outer panels of 32
+# (float64, float32); one level of 16 (2-byte storage)
 SCHEDULES = {"float64": (8, 32), "float32": (8, 32), "float16": (16, 0), "bfloat16": (16, 0)}
 
 
