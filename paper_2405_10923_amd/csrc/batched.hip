@@ -307,8 +307,11 @@ int enqueue_typed(rhqr_batch_s *b, hipStream_t st) {
     case 2:
       hipLaunchKernelGGL((kb_srht_cols<ST, AT, 2>), dim3(b->sk_blocks), dim3(SK_TPB), 0, st, b->d_jobs, b->d_sk);
       break;
-    default:
+    case 4:
       hipLaunchKernelGGL((kb_srht_cols<ST, AT, 4>), dim3(b->sk_blocks), dim3(SK_TPB), 0, st, b->d_jobs, b->d_sk);
+      break;
+    default:
+      hipLaunchKernelGGL((kb_srht_cols<ST, AT, 8>), dim3(b->sk_blocks), dim3(SK_TPB), 0, st, b->d_jobs, b->d_sk);
   }
   RHQR_HIP(hipGetLastError());
   hipLaunchKernelGGL((kb_sketch_finish<ST>), dim3(b->cols, (b->maxL + 255) / 256), dim3(256), 0, st,
@@ -415,7 +418,7 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
     b->ms.push_back(m);
     b->maxm = std::max(b->maxm, m);
     b->maxL = std::max(b->maxL, Lr);
-    b->qa = std::max(b->qa, h->l <= 1024 ? 1 : h->l <= 2048 ? 2 : 4);
+    b->qa = std::max(b->qa, h->l <= SK_TPB ? 1 : h->l <= 2 * SK_TPB ? 2 : h->l <= 4 * SK_TPB ? 4 : 8);
     char *region = ws + L.off[s];
     const size_t lb = loop_ws_bytes(h->kind, dtype, h->n, m, h->l);
     LoopWs lw;

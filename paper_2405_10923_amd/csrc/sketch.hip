@@ -283,15 +283,17 @@ int launch_typed(const rhqr_sketch_s *h, int64_t n, int32_t k, const ST *X, int6
     const int64_t ntiles = (n + TILE - 1) / TILE;
     const int aligned = ((uintptr_t)X % 16 == 0) && ((ldx * (int64_t)sizeof(ST)) % 16 == 0);
     const int64_t ngroups = (n + (int64_t)TILE * SK_TPW - 1) / ((int64_t)TILE * SK_TPW);
-    // samples per thread: ceil(l / 1024)
-    const int qa = l <= 1024 ? 1 : l <= 2048 ? 2 : 4;
+    // samples per thread: ceil(l / SK_TPB), rounded up to a power of two (l <= TILE)
+    static_assert(8 * SK_TPB >= TILE, "at most 8 samples per thread");
+    const int qa = l <= SK_TPB ? 1 : l <= 2 * SK_TPB ? 2 : l <= 4 * SK_TPB ? 4 : 8;
 #define RHQR_SRHT_COLS(Q)                                                                       \
   hipLaunchKernelGGL((k_srht_cols<ST, CT, Q>), dim3(gt, k), dim3(SK_TPB), 0, st, X, ldx, n, m, \
                      l, ngroups, gt, h->d_signs, h->d_rows, part, aligned)
     switch (qa) {
       case 1: RHQR_SRHT_COLS(1); break;
       case 2: RHQR_SRHT_COLS(2); break;
-      default: RHQR_SRHT_COLS(4); break;
+      case 4: RHQR_SRHT_COLS(4); break;
+      default: RHQR_SRHT_COLS(8); break;
     }
 #undef RHQR_SRHT_COLS
     RHQR_HIP(hipGetLastError());
@@ -315,8 +317,8 @@ int launch_typed(const rhqr_sketch_s *h, int64_t n, int32_t k, const ST *X, int6
 int sketch_tail_partials_size(const rhqr_sketch_s *h, int32_t k, int *gt_out, size_t *bytes_out) {
   int gt;
   if (h->kind == RHQR_SKETCH_SRHT) {
-    const int64_t ngroups = (h->n + (int64_t)TILE * 2 - 1) / ((int64_t)TILE * 2);
-    const int64_t target = std::max<int64_t>(1, 1024 / std::max<int32_t>(k, 1));
+    const int64_t ngroups = (h->n + (int64_t)TILE * SK_TPW - 1) / ((int64_t)TILE * SK_TPW);
+    const int64_t target = std::max<int64_t>(1, 2048 / std::max<int32_t>(k, 1));
     gt = (int)std::min<int64_t>(ngroups, target);
   } else {
     const int64_t ntail = h->n - h->m;

@@ -9,12 +9,13 @@ namespace {
 // ------------------------------------------------------------ RHSketch, SRHT
 // Grid (gt, k): workgroup (g, c) transforms tiles t = g, g+gt, ... of column c
 // and accumulates its contribution to each of the l samples; part[c][g][q].
-// The next tile's loads are issued before the current tile's transform.
-// 1024 threads transform two consecutive tiles (2 TILE rows) per step; two
-// workgroups per compute unit overlap one's loads with the other's transform.
-constexpr int SK_TPB = 1024, SK_TPW = 2;
+// Later tiles' loads are issued before the current tile's transform.  512
+// threads transform one tile (TILE rows) per step, so two workgroups fit on a
+// compute unit (about 110 registers per lane, 35 KB of LDS in float64) and
+// overlap one's loads with the other's transform.
+constexpr int SK_TPB = 512, SK_TPW = 1;
 
-template <typename A> __device__ __forceinline__ void fwht_two_tiles(A *s) {
+template <typename A> __device__ __forceinline__ void fwht_sk_group(A *s) {
   // fully unrolled: no inner loop, so the waits for loads in flight across
   // the transform stay exact
 #pragma unroll
@@ -105,7 +106,7 @@ __device__ __forceinline__ void srht_cols_block(const ST *__restrict__ X, int64_
         s[(li >> TILE_LOG) * TILE_PAD + tpad(li & (TILE - 1))] = val;
       }
     }
-    fwht_two_tiles(s);
+    fwht_sk_group(s);
     const uint64_t t0 = (uint64_t)g * SK_TPW;
 #pragma unroll
     for (int a = 0; a < QA; ++a) {

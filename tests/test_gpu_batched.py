@@ -57,6 +57,26 @@ def test_batch_bitwise_equals_single(dt, panel):
     b.close()
 
 
+def test_batch_large_sketches_bitwise():
+    """Problems whose sketches take 2 and 8 samples per thread in the
+    pre-sketch (l = 600 and 3000): the batch equals the single-problem
+    factorization bitwise."""
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    probs = _inputs(torch, torch.float64, shapes=[(5000, 20, 600, 21), (8192 + 3, 12, 3000, 22)])
+    b = rhqr.Batch([(sk, to_gpu(W)) for W, sk, _ in probs], panel=16)
+    outs = b.factor()
+    torch.cuda.synchronize()
+    assert b.status() == [0] * len(probs)
+    for (W, sk, shp), o in zip(probs, outs):
+        log(f"  single {shp}")
+        ref = rhqr.factor(sk, to_gpu(W), panel=16)
+        torch.cuda.synchronize()
+        for k in ("U", "S", "T", "R"):
+            assert torch.equal(o[k], ref[k]), (shp, k)
+    b.close()
+
+
 @pytest.mark.parametrize("panel", [0, 16])
 def test_batch_f64_matches_oracle(panel):
     torch = cuda_or_skip()

@@ -37,7 +37,10 @@ def test_gaussian_draw_matches_oracle():
 
 
 @pytest.mark.parametrize("n,m,l,k", [(300, 7, 40, 3), (3 * 4096 + 777, 24, 96, 5),
-                                     (5 * 4096, 4, 64, 2)])
+                                     (5 * 4096, 4, 64, 2),
+                                     # 2, 4 and 8 samples per thread, l = TILE
+                                     (5000, 6, 600, 2), (3 * 4096 + 5, 10, 1500, 2),
+                                     (8192 + 3, 5, 3000, 2), (2 * 4096, 4, 4096, 1)])
 def test_srht_sketch_f64(n, m, l, k):
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
