@@ -786,11 +786,12 @@ __global__ void __launch_bounds__(PX_WAVES * 64) k_panel_mx(ST *__restrict__ W, 
 }
 
 template <typename ST, int NC>
-void launch_panel_mx(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,
-                     int pw, const double *C, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+int launch_panel_mx(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,
+                    int pw, const double *C, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   constexpr int VEC = 16 / sizeof(ST);
   constexpr int WR = px_rg(sizeof(ST)) * 16 * VEC;  // rows per wave
-  if (pw < NC || nb > NC) return;  // not reached: the caller picks NC = pw >= nb
+  // the kernel reads NC coefficients per row of C: the caller picks NC = pw >= nb
+  if (pw < NC || nb > NC) return RHQR_ERR_UNSUPPORTED;
   const int64_t waves = (n - (m - m % VEC) + WR - 1) / WR;
   const dim3 grid((unsigned)((waves + PX_WAVES - 1) / PX_WAVES));
   if (e0)
@@ -799,6 +800,7 @@ void launch_panel_mx(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32
   else
     hipLaunchKernelGGL((k_panel_mx<ST, NC>), grid, dim3(PX_WAVES * 64), 0, st, W, ldw, n, m, K0, J,
                        nb, pw, C);
+  return RHQR_OK;
 }
 
 template <typename ST>
@@ -827,13 +829,15 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (g_prof.on && prof_pair(&e0, &e1, 1)) return RHQR_ERR_HIP;
     const int aligned = ((uintptr_t)W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
+    int rc = RHQR_OK;
     if (aligned && nb > PX_MIN_NB && nb <= 16) {
-      launch_panel_mx<ST, 16>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
+      rc = launch_panel_mx<ST, 16>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
     } else if (aligned && nb > PX_MIN_NB) {
-      launch_panel_mx<ST, 32>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
+      rc = launch_panel_mx<ST, 32>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
     } else {  // 8 columns or fewer, or unaligned columns: vector units
       launch_panel<ST>(W, a.ldw, a.n, m, K0, J, nb, (const double *)C, st, e0, e1);
     }
+    if (rc) return rc;
     RHQR_HIP(hipGetLastError());
     return RHQR_OK;
   };
