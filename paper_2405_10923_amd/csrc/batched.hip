@@ -133,7 +133,9 @@ __global__ void __launch_bounds__(PANEL_TPB) kb_panel(const ColProblem *__restri
   // the same choice of units and arithmetic as the single-problem update
   static_assert(PANEL_TPB == PX_WAVES * 64, "one panel workgroup layout for both units");
   if (Q.aligned && nb > PX_MIN_NB) {
-    panel_mx_block<ST, BATCH_PB>((ST *)Q.W, Q.ldw, Q.n, Q.m, 0, J, nb, BATCH_PB, Q.C, b.local);
+    ST *W = (ST *)Q.W;
+    panel_mx_block<ST, BATCH_PB>(W, Q.ldw, W + (int64_t)J * Q.ldw, Q.ldw, false, Q.n, Q.m, 0, J, nb,
+                                 BATCH_PB, Q.C, b.local);
     return;
   }
   panel_block<ST, BATCH_PB>((ST *)Q.W, Q.ldw, Q.n, Q.m, 0, J, nb, Q.C, Q.aligned, b.local);

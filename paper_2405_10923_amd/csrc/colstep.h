@@ -1172,10 +1172,14 @@ template <> struct PxOps<float> {
   static constexpr __device__ int di(int q, int t) { return 4 * q + t; }
 };
 
+// General form: P[m:n, 0:nb] = (zero ? 0 : P[m:n, 0:nb]) - U[m:n, K0:K1] C_{K0:K1}
+// (U and P may be columns of one array that do not overlap).
 template <typename ST, int NC, bool FULL>
-__device__ __forceinline__ void panel_mx_wave(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
-                                              int32_t K0, int32_t J, int32_t nb, int pw,
-                                              const double *__restrict__ C, int64_t row0) {
+__device__ __forceinline__ void panel_mx_wave(const ST *__restrict__ U, int64_t ldu,
+                                              ST *__restrict__ P, int64_t ldp, bool zero,
+                                              int64_t n, int32_t m, int32_t K0, int32_t K1,
+                                              int32_t nb, int pw, const double *__restrict__ C,
+                                              int64_t row0) {
   using CT = typename CompT<ST>::type;
   using Ops = PxOps<CT>;
   using acc_t = typename Ops::acc_t;
@@ -1214,8 +1218,8 @@ __device__ __forceinline__ void panel_mx_wave(ST *__restrict__ W, int64_t ldw, i
       for (int t = 0; t < 4; ++t) {
         const int c = 16 * ct + Ops::di(kq, t);
         CT x[VEC];
-        if (c < nb) {
-          vdecode<ST, CT>(ldraw(W + (int64_t)(J + c) * ldw, rv(g), false), x);
+        if (c < nb && !zero) {
+          vdecode<ST, CT>(ldraw(P + (int64_t)c * ldp, rv(g), false), x);
         } else {
 #pragma unroll
           for (int e = 0; e < VEC; ++e) x[e] = (CT)0;
@@ -1223,15 +1227,15 @@ __device__ __forceinline__ void panel_mx_wave(ST *__restrict__ W, int64_t ldw, i
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[g][e][ct][t] = x[e];
       }
-  for (int k0 = K0; k0 < J; k0 += 4 * PX_KS) {
+  for (int k0 = K0; k0 < K1; k0 += 4 * PX_KS) {
     u32x4 ub[PX_KS][RG];
     CT cf[PX_KS][NCT];
 #pragma unroll
     for (int s = 0; s < PX_KS; ++s) {
       const int k = k0 + 4 * s + kq;
-      const bool kv = k < J;
-      const int kc = kv ? k : J - 1;  // clamped: every load is in bounds
-      const ST *col = W + (int64_t)kc * ldw;
+      const bool kv = k < K1;
+      const int kc = kv ? k : K1 - 1;  // clamped: every load is in bounds
+      const ST *col = U + (int64_t)kc * ldu;
 #pragma unroll
       for (int g = 0; g < RG; ++g) ub[s][g] = ldraw(col, rv(g), true);
 #pragma unroll
@@ -1246,7 +1250,7 @@ __device__ __forceinline__ void panel_mx_wave(ST *__restrict__ W, int64_t ldw, i
     for (int s = 0; s < PX_KS; ++s) {
       // a column beyond J contributes zero coefficients; its (clamped) values
       // are zeroed too, so no non-finite entry can enter the sum
-      const bool kv = k0 + 4 * s + kq < J;
+      const bool kv = k0 + 4 * s + kq < K1;
 #pragma unroll
       for (int g = 0; g < RG; ++g) {
         CT x[VEC];
@@ -1268,7 +1272,7 @@ __device__ __forceinline__ void panel_mx_wave(ST *__restrict__ W, int64_t ldw, i
       for (int t = 0; t < 4; ++t) {
         const int c = 16 * ct + Ops::di(kq, t);
         if (c >= nb) continue;
-        ST *col = W + (int64_t)(J + c) * ldw;
+        ST *col = P + (int64_t)c * ldp;
         const int64_t r = rv(g);
         CT v[VEC];
 #pragma unroll
@@ -1284,11 +1288,14 @@ __device__ __forceinline__ void panel_mx_wave(ST *__restrict__ W, int64_t ldw, i
 }
 
 // one workgroup of PX_WAVES waves; wave w of workgroup bid owns the rows from
-// (m rounded down to VEC) + (PX_WAVES bid + w) px_rg 16 VEC
+// (m rounded down to VEC) + (PX_WAVES bid + w) px_rg 16 VEC.  FULL waves need
+// 16-byte aligned columns of U and P.
 template <typename ST, int NC>
-__device__ __forceinline__ void panel_mx_block(ST *__restrict__ W, int64_t ldw, int64_t n,
-                                               int32_t m, int32_t K0, int32_t J, int32_t nb, int pw,
-                                               const double *__restrict__ C, int64_t bid) {
+__device__ __forceinline__ void panel_mx_block(const ST *__restrict__ U, int64_t ldu,
+                                               ST *__restrict__ P, int64_t ldp, bool zero,
+                                               int64_t n, int32_t m, int32_t K0, int32_t K1,
+                                               int32_t nb, int pw, const double *__restrict__ C,
+                                               int64_t bid) {
   constexpr int VEC = 16 / sizeof(ST);
   const int w = threadIdx.x >> 6;
   const int64_t rb = m - (m % VEC);
@@ -1296,9 +1303,9 @@ __device__ __forceinline__ void panel_mx_block(ST *__restrict__ W, int64_t ldw, 
   const int64_t row0 = rb + (bid * PX_WAVES + w) * WR;
   if (row0 >= n) return;  // whole wave beyond the last row (uniform)
   if (row0 >= m && row0 + WR <= n)
-    panel_mx_wave<ST, NC, true>(W, ldw, n, m, K0, J, nb, pw, C, row0);
+    panel_mx_wave<ST, NC, true>(U, ldu, P, ldp, zero, n, m, K0, K1, nb, pw, C, row0);
   else
-    panel_mx_wave<ST, NC, false>(W, ldw, n, m, K0, J, nb, pw, C, row0);
+    panel_mx_wave<ST, NC, false>(U, ldu, P, ldp, zero, n, m, K0, K1, nb, pw, C, row0);
 }
 
 // workgroups of panel_mx_block over rows m..n

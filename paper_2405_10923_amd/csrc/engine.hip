@@ -782,7 +782,8 @@ __global__ void __launch_bounds__(PX_WAVES * 64) k_panel_mx(ST *__restrict__ W, 
                                                             int64_t n, int32_t m, int32_t K0,
                                                             int32_t J, int32_t nb, int pw,
                                                             const double *__restrict__ C) {
-  panel_mx_block<ST, NC>(W, ldw, n, m, K0, J, nb, pw, C, blockIdx.x);
+  panel_mx_block<ST, NC>(W, ldw, W + (int64_t)J * ldw, ldw, false, n, m, K0, J, nb, pw, C,
+                         blockIdx.x);
 }
 
 template <typename ST, int NC>
@@ -869,6 +870,33 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, 
   return finish_typed<ST>(a, w, st);
 }
 
+// ------------------------------------------- thin Q tail on matrix cores
+// Q_2 = -U_2 Mq as the panel product with a zero start (panel_mx_block),
+// one grid row per QX_NC columns of Q.  k_mqt lays Mq out for it: tile t
+// holds Mq[k][t QX_NC + c] at Ct[(t m + k) QX_NC + c], zero beyond column m.
+constexpr int QX_NC = 32;
+
+__global__ void k_mqt(int32_t m, const double *__restrict__ Mq, double *__restrict__ Ct) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tile = blockIdx.y;
+  if (e >= m * QX_NC) return;
+  const int k = e / QX_NC, c = e % QX_NC;
+  const int col = tile * QX_NC + c;
+  Ct[((int64_t)tile * m + k) * QX_NC + c] = col < m ? Mq[k + (int64_t)col * m] : 0.0;
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(PX_WAVES * 64) k_qtail_mx(int64_t n, int32_t m,
+                                                            const ST *__restrict__ U, int64_t ldu,
+                                                            const double *__restrict__ Ct,
+                                                            ST *__restrict__ Q, int64_t ldq) {
+  const int tile = blockIdx.y;
+  const int c0 = tile * QX_NC;
+  const int nb = m - c0 < QX_NC ? m - c0 : QX_NC;
+  panel_mx_block<ST, QX_NC>(U, ldu, Q + (int64_t)c0 * ldq, ldq, true, n, m, 0, m, nb, QX_NC,
+                            Ct + (int64_t)tile * m * QX_NC, blockIdx.x);
+}
+
 template <typename ST>
 int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S, int64_t lds,
                  const double *T, int64_t ldt, double *Mq, void *qmf, ST *Q, int64_t ldq,
@@ -879,7 +907,24 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
                      ldq);
   RHQR_HIP(hipGetLastError());
   const int64_t rows = n - m;
-  if (rows > 0) {
+  // float64 and float32 with 16-byte aligned columns: the matrix-core panel
+  // product (for 2-byte storage, re-reading U once per 32 columns of Q costs
+  // more than the split-coefficient product below saves)
+  constexpr bool mx_type = sizeof(ST) >= 4;
+  const bool mx_ok = mx_type && ((uintptr_t)U % 16 == 0) && ((uintptr_t)Q % 16 == 0) &&
+                     ((ldu * (int64_t)sizeof(ST)) % 16 == 0) &&
+                     ((ldq * (int64_t)sizeof(ST)) % 16 == 0);
+  if (rows > 0 && mx_ok) {
+    const int tiles = (m + QX_NC - 1) / QX_NC;
+    double *Ct = (double *)qmf;
+    hipLaunchKernelGGL(k_mqt, dim3((m * QX_NC + 255) / 256, tiles), dim3(256), 0, st, m,
+                       (const double *)Mq, Ct);
+    RHQR_HIP(hipGetLastError());
+    const dim3 grid((unsigned)panel_mx_groups(n, m, (int)sizeof(ST)), tiles);
+    hipLaunchKernelGGL((k_qtail_mx<ST>), grid, dim3(PX_WAVES * 64), 0, st, n, m, U, ldu,
+                       (const double *)Ct, Q, ldq);
+    RHQR_HIP(hipGetLastError());
+  } else if (rows > 0) {
     if constexpr (std::is_same<ST, double>::value) {
       dim3 grid((unsigned)((rows + 63) / 64), (m + QF_NC - 1) / QF_NC);
       hipLaunchKernelGGL(k_qtail64, grid, dim3(256), 0, st, U + m, ldu, rows, m,
@@ -1105,9 +1150,13 @@ int run_column_loop(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
 }
 
 size_t thin_q_bytes(int32_t m) {
+  // the larger of: split coefficients (2-byte storage, unaligned columns) and
+  // Mq in the tile layout of the matrix-core product
   const size_t Kp = (size_t)(m + PM_KP - 1) / PM_KP * PM_KP;
   const size_t tiles = (size_t)(m + QH_NC - 1) / QH_NC;
-  return align_up(2 * tiles * Kp * QH_NC * sizeof(unsigned short) + tiles * QH_NC * sizeof(float));
+  const size_t split = 2 * tiles * Kp * QH_NC * sizeof(unsigned short) + tiles * QH_NC * sizeof(float);
+  const size_t xt = (size_t)(m + QX_NC - 1) / QX_NC * QX_NC * (size_t)m * sizeof(double);
+  return align_up(split > xt ? split : xt);
 }
 
 int launch_thin_q(int dtype, int64_t n, int32_t m, const void *U, int64_t ldu, const double *S,
