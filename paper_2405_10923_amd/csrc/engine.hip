@@ -874,7 +874,7 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, 
 // Q_2 = -U_2 Mq as the panel product with a zero start (panel_mx_block),
 // one grid row per QX_NC columns of Q.  k_mqt lays Mq out for it: tile t
 // holds Mq[k][t QX_NC + c] at Ct[(t m + k) QX_NC + c], zero beyond column m.
-constexpr int QX_NC = 32;
+constexpr int QX_NC = 64;
 
 __global__ void k_mqt(int32_t m, const double *__restrict__ Mq, double *__restrict__ Ct) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -908,23 +908,26 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
   RHQR_HIP(hipGetLastError());
   const int64_t rows = n - m;
   // float64 and float32 with 16-byte aligned columns: the matrix-core panel
-  // product (for 2-byte storage, re-reading U once per 32 columns of Q costs
+  // product (for 2-byte storage, re-reading U once per 64 columns of Q costs
   // more than the split-coefficient product below saves)
-  constexpr bool mx_type = sizeof(ST) >= 4;
-  const bool mx_ok = mx_type && ((uintptr_t)U % 16 == 0) && ((uintptr_t)Q % 16 == 0) &&
-                     ((ldu * (int64_t)sizeof(ST)) % 16 == 0) &&
-                     ((ldq * (int64_t)sizeof(ST)) % 16 == 0);
-  if (rows > 0 && mx_ok) {
-    const int tiles = (m + QX_NC - 1) / QX_NC;
-    double *Ct = (double *)qmf;
-    hipLaunchKernelGGL(k_mqt, dim3((m * QX_NC + 255) / 256, tiles), dim3(256), 0, st, m,
-                       (const double *)Mq, Ct);
-    RHQR_HIP(hipGetLastError());
-    const dim3 grid((unsigned)panel_mx_groups(n, m, (int)sizeof(ST)), tiles);
-    hipLaunchKernelGGL((k_qtail_mx<ST>), grid, dim3(PX_WAVES * 64), 0, st, n, m, U, ldu,
-                       (const double *)Ct, Q, ldq);
-    RHQR_HIP(hipGetLastError());
-  } else if (rows > 0) {
+  if constexpr (sizeof(ST) >= 4) {
+    const bool aligned = ((uintptr_t)U % 16 == 0) && ((uintptr_t)Q % 16 == 0) &&
+                         ((ldu * (int64_t)sizeof(ST)) % 16 == 0) &&
+                         ((ldq * (int64_t)sizeof(ST)) % 16 == 0);
+    if (rows > 0 && aligned) {
+      const int tiles = (m + QX_NC - 1) / QX_NC;
+      double *Ct = (double *)qmf;
+      hipLaunchKernelGGL(k_mqt, dim3((m * QX_NC + 255) / 256, tiles), dim3(256), 0, st, m,
+                         (const double *)Mq, Ct);
+      RHQR_HIP(hipGetLastError());
+      const dim3 grid((unsigned)panel_mx_groups(n, m, (int)sizeof(ST)), tiles);
+      hipLaunchKernelGGL((k_qtail_mx<ST>), grid, dim3(PX_WAVES * 64), 0, st, n, m, U, ldu,
+                         (const double *)Ct, Q, ldq);
+      RHQR_HIP(hipGetLastError());
+      return RHQR_OK;
+    }
+  }
+  if (rows > 0) {
     if constexpr (std::is_same<ST, double>::value) {
       dim3 grid((unsigned)((rows + 63) / 64), (m + QF_NC - 1) / QF_NC);
       hipLaunchKernelGGL(k_qtail64, grid, dim3(256), 0, st, U + m, ldu, rows, m,
