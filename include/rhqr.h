@@ -210,8 +210,8 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
  *     caller's workspace d_ws (kept by the batch until rhqr_batch_destroy: the
  *     caller must keep it alive), uploads them on `stream` and synchronises.
  *     opts: bits 0-7 rhqr_scaling; bits 8-15 panel width: 0 (column
- *     schedule) or 16 (blocked schedule as in rhqr_factor, the panel update
- *     on the vector units); other bits 0.
+ *     schedule) or 16 (blocked schedule as in rhqr_factor with one level of
+ *     panels of 16); other bits 0.
  *     Returns -1 for an invalid problem array, -3 bad dtype, -4 bad opts,
  *     -5 null workspace, RHQR_ERR_WORKSPACE if ws_bytes is too small.
  *   rhqr_batch_factor: factors every problem of the batch.  The work is a
@@ -221,9 +221,8 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
  *     m_p > j.  use_graph != 0: the sequence is captured once into a hipGraph
  *     (on the batch's own stream) and the graph is launched on `stream`; later
  *     calls replay it.  Each problem's U, S, T, R equal those of rhqr_factor
- *     with the same schedule (same device code, same reduction orders;
- *     except 2-byte storage with panels, whose single-problem panel update
- *     runs on matrix cores).
+ *     with the same schedule bitwise (same device code, same choice of
+ *     matrix cores or vector units per panel, same reduction orders).
  *   rhqr_batch_status: h_info[i] (host, count entries, caller order) = the
  *     first column of problem i with rho_j = 0 (1-based), or 0.  Synchronous.
  * Not in the paper as such: the paper factors one matrix at a time; the batch
