@@ -1130,9 +1130,6 @@ __device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int
 }
 
 
-typedef double f64x4_t __attribute__((ext_vector_type(4)));
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
-
 // ------------------------------------------ panel update on matrix cores
 // W[m:n, J:J+nb] -= U[m:n, K0:J] C_{K0:J} (nb <= NC, C with row pitch pw,
 // zero beyond nb) on v_mfma_f64_16x16x4 (float64 storage) or
@@ -1154,26 +1151,6 @@ constexpr int PX_MIN_NB = 8; // narrower panels stay on the vector units (k_pane
 // row groups of 16 VEC rows per wave: 64 rows (float64) or 128 rows
 __host__ __device__ constexpr int px_rg(int es) { return es == 2 ? 1 : 2; }
 
-template <typename CT> struct PxOps;
-// di(q, t): the row i of D that accumulator element t of a lane in lane
-// group q = lane / 16 holds (probed: float64 i = q + 4 t, float32 i = 4 q + t)
-template <> struct PxOps<double> {
-  typedef f64x4_t acc_t;
-  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static constexpr __device__ int di(int q, int t) { return q + 4 * t; }
-};
-template <> struct PxOps<float> {
-  typedef f32x4_t acc_t;
-  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static constexpr __device__ int di(int q, int t) { return 4 * q + t; }
-};
-
-// General form: P[m:n, 0:nb] = (zero ? 0 : P[m:n, 0:nb]) - U[m:n, K0:K1] C_{K0:K1}
-// (U and P may be columns of one array that do not overlap).
 template <typename ST, int NC, bool FULL>
 __device__ __forceinline__ void panel_mx_wave(const ST *__restrict__ U, int64_t ldu,
                                               ST *__restrict__ P, int64_t ldp, bool zero,

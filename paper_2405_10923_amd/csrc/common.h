@@ -240,6 +240,33 @@ template <typename T> __device__ T block_sum(T v, T *red) {
   return s;
 }
 
+// ------------------------------------------------------- matrix-core tiles
+// 16 x 16 x 4 products on matrix cores in the computation type CT
+// (v_mfma_f64_16x16x4 or v_mfma_f32_16x16x4).  Operands: lane l holds
+// A[i = l % 16][k = l / 16] and B[k = l / 16][j = l % 16]; the accumulator's
+// element t of lane l holds D[di(l / 16, t)][l % 16] (probed: float64
+// i = q + 4 t, float32 i = 4 q + t).
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+template <typename CT> struct PxOps;
+template <> struct PxOps<double> {
+  typedef f64x4_t acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static constexpr __device__ int di(int q, int t) { return q + 4 * t; }
+};
+template <> struct PxOps<float> {
+  typedef f32x4_t acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static constexpr __device__ int di(int q, int t) { return 4 * q + t; }
+};
+
+// General form: P[m:n, 0:nb] = (zero ? 0 : P[m:n, 0:nb]) - U[m:n, K0:K1] C_{K0:K1}
+// (U and P may be columns of one array that do not overlap).
+
 // ---------------------------------------------------------------- FWHT
 // In-place unnormalised Walsh-Hadamard transform (natural order) of TILE
 // values held in LDS at padded positions tpad(i).  Three radix-16 passes over

@@ -204,56 +204,94 @@ __global__ void __launch_bounds__(FW_Q * FW_G) k_sketch_finish_wide(
 }
 
 // ------------------------------------------------------------ RHSketch, Gaussian
-// Split-K product  part[kc] = Omega[:, rows of chunk kc] X2[chunk, :]  with
-// 64 x 64 output tiles, 16-deep K steps staged in LDS, 4 x 4 per thread.
-constexpr int GB = 64, GK = 16;
+// Split-K product  part[kc] = Omega[:, rows of chunk kc] X2[chunk, :]  on
+// matrix cores (v_mfma_f64_16x16x4; float32 for low-precision storage, as the
+// vector path computed in): 128 x 128 output tiles, so each chunk of Omega is
+// read once per 128 columns of X2 and each chunk of X2 once per 128 rows of
+// Omega; GMK-deep K steps staged in LDS, the next step's loads issued before
+// this step's products.  Wave w owns tile rows 32 w .. 32 w + 31 (2 row
+// blocks) and all 8 column blocks.
+constexpr int GM = 128, GN = 128, GMK = 16;
+template <typename CT> constexpr int gpad() {
+  // row pitch of the LDS tiles: the 4 rows a product step reads (one per lane
+  // group) fall on different halves of the banks
+  return sizeof(CT) == 8 ? 16 : 32;
+}
 template <typename ST, typename CT>
-__global__ void __launch_bounds__(256) k_gauss_cols(const double *__restrict__ om, int64_t ldo,
-                                                    const ST *__restrict__ X, int64_t ldx,
-                                                    int32_t m, int64_t ntail, int32_t l, int32_t k,
-                                                    int64_t kchunk, double *__restrict__ part) {
-  __shared__ CT As[GK][GB + 1];
-  __shared__ CT Bs[GK][GB + 1];
+__global__ void __launch_bounds__(256) k_gauss_mx(const double *__restrict__ om, int64_t ldo,
+                                                  const ST *__restrict__ X, int64_t ldx, int32_t m,
+                                                  int64_t ntail, int32_t l, int32_t k,
+                                                  int64_t kchunk, double *__restrict__ part) {
+  using Ops = PxOps<CT>;
+  using acc_t = typename Ops::acc_t;
+  constexpr int P = gpad<CT>();
+  constexpr int NL = GMK * GM / 256;  // elements per thread and tile
+  static_assert(GM == GN, "one staging pattern for both tiles");
+  __shared__ CT As[GMK][GM + P];  // As[kk][q]   = Omega[q][chunk row kk]
+  __shared__ CT Bs[GMK][GN + P];  // Bs[kk][col] = X2[chunk row kk][col]
   const int qt = blockIdx.x, ct = blockIdx.y, kc = blockIdx.z;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
   const int64_t k0 = (int64_t)kc * kchunk;
   const int64_t k1 = min(ntail, k0 + kchunk);
-  CT acc[4][4] = {};
-  for (int64_t kk = k0; kk < k1; kk += GK) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < GK * GB; e += 256) {
-      const int r = e & (GB - 1), kq = e / GB;
-      const int64_t ki = kk + kq;
-      const int q = qt * GB + r;
-      As[kq][r] = (ki < k1 && q < l) ? (CT)om[ki * ldo + q] : (CT)0;
-      const int kr = e & (GK - 1), cc = e / GK;
-      const int64_t ki2 = kk + kr;
-      const int col = ct * GB + cc;
-      Bs[kr][cc] = (ki2 < k1 && col < k) ? cvt_in<CT>(X[(int64_t)col * ldx + m + ki2]) : (CT)0;
+  acc_t acc[2][8];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 8; ++cb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[rb][cb][t] = (CT)0;
+  // element e of a step: Omega row e % GM of chunk row e / GM (rows of Omega
+  // contiguous), X2 chunk row e % GMK of column e / GMK (rows of X2 contiguous)
+  CT ra[NL], rb_[NL];
+  auto gload = [&](int64_t kk) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int e = tid + 256 * i;
+      const int64_t ki = kk + e / GM;
+      const int q = qt * GM + e % GM;
+      ra[i] = (ki < k1 && q < l) ? (CT)om[ki * ldo + q] : (CT)0;
+      const int64_t ki2 = kk + e % GMK;
+      const int col = ct * GN + e / GMK;
+      rb_[i] = (ki2 < k1 && col < k) ? cvt_in<CT>(X[(int64_t)col * ldx + m + ki2]) : (CT)0;
+    }
+  };
+  if (k0 < k1) gload(k0);
+  for (int64_t kk = k0; kk < k1; kk += GMK) {
+    __syncthreads();  // the previous step's tiles have been read
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int e = tid + 256 * i;
+      As[e / GM][e % GM] = ra[i];
+      Bs[e % GMK][e / GMK] = rb_[i];
     }
     __syncthreads();
+    if (kk + GMK < k1) gload(kk + GMK);
 #pragma unroll
-    for (int kq = 0; kq < GK; ++kq) {
-      CT a[4], b[4];
+    for (int s4 = 0; s4 < GMK / 4; ++s4) {
+      CT a[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kq][ty + 16 * i];
+      for (int rb = 0; rb < 2; ++rb) a[rb] = As[4 * s4 + kq][32 * w + 16 * rb + i16];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kq][tx + 16 * j];
+      for (int cb = 0; cb < 8; ++cb) {
+        const CT bv = Bs[4 * s4 + kq][16 * cb + i16];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        for (int rb = 0; rb < 2; ++rb) acc[rb][cb] = Ops::mma(a[rb], bv, acc[rb][cb]);
+      }
     }
   }
   // part layout: [col][kc][q]
   const int nkc = gridDim.z;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = qt * GB + ty + 16 * i, col = ct * GB + tx + 16 * j;
-      if (q < l && col < k) part[((int64_t)col * nkc + kc) * l + q] = (double)acc[i][j];
-    }
+    for (int cb = 0; cb < 8; ++cb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int q = qt * GM + 32 * w + 16 * rb + Ops::di(kq, t);
+        const int col = ct * GN + 16 * cb + i16;
+        if (q < l && col < k) part[((int64_t)col * nkc + kc) * l + q] = (double)acc[rb][cb][t];
+      }
 }
 
 // Y = [X head; scale * sum of the gt partial groups]: one thread per row,
@@ -300,9 +338,9 @@ int launch_typed(const rhqr_sketch_s *h, int64_t n, int32_t k, const ST *X, int6
     launch_finish<ST>(X, ldx, m, l, k, gt, part, 1.0 / std::sqrt((double)l), Y, ldy, st);
   } else {
     const int64_t ntail = n - m;
-    const int64_t kchunk = ((ntail + gt - 1) / gt + GK - 1) / GK * GK;
-    dim3 grid((l + GB - 1) / GB, (k + GB - 1) / GB, gt);
-    hipLaunchKernelGGL((k_gauss_cols<ST, CT>), grid, dim3(256), 0, st, h->d_omega, (int64_t)l, X,
+    const int64_t kchunk = ((ntail + gt - 1) / gt + GMK - 1) / GMK * GMK;
+    dim3 grid((l + GM - 1) / GM, (k + GN - 1) / GN, gt);
+    hipLaunchKernelGGL((k_gauss_mx<ST, CT>), grid, dim3(256), 0, st, h->d_omega, (int64_t)l, X,
                        ldx, m, ntail, l, k, kchunk, part);
     RHQR_HIP(hipGetLastError());
     launch_finish<ST>(X, ldx, m, l, k, gt, part, 1.0, Y, ldy, st);
@@ -322,8 +360,8 @@ int sketch_tail_partials_size(const rhqr_sketch_s *h, int32_t k, int *gt_out, si
     gt = (int)std::min<int64_t>(ngroups, target);
   } else {
     const int64_t ntail = h->n - h->m;
-    const int64_t tiles = (int64_t)((h->l + GB - 1) / GB) * ((k + GB - 1) / GB);
-    const int64_t target = std::max<int64_t>(1, 2048 / tiles);
+    const int64_t tiles = (int64_t)((h->l + GM - 1) / GM) * ((k + GN - 1) / GN);
+    const int64_t target = std::max<int64_t>(1, 512 / tiles);  // about 2 workgroups per unit
     gt = (int)std::max<int64_t>(1, std::min<int64_t>(target, (ntail + 4095) / 4096));
   }
   *gt_out = gt;
