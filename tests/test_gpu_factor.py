@@ -112,6 +112,24 @@ def test_low_precision_bounds(dt, tol, panel, outer):
     assert abs(ef - ef_o) < tol
 
 
+# the matrix-core panel update at awkward shapes: m not a multiple of the
+# 4- or 8-row vectors (the first wave straddles the head rows), a ragged last
+# wave, and last panels narrower than the 16- or 32-column tiles
+@pytest.mark.parametrize("n,m,l,panel,outer", [
+    (3 * 4096 + 5, 37, 150, 16, 0), (2 * 4096 + 3, 45, 180, 8, 32), (1500, 21, 96, 12, 24)])
+@pytest.mark.parametrize("dt,tol", [("float32", 1e-5), ("float16", 1e-2), ("bfloat16", 1e-2)])
+def test_low_precision_edge_shapes(dt, tol, n, m, l, panel, outer):
+    torch = cuda_or_skip()
+    W, Win, g, sk = _run(0, n, m, l, 6, dtype=dt, panel=panel, outer=outer)
+    ef = metrics.fact_error(Win, g["Q"], g["R"])
+    eo = metrics.orth_error(osk.rh_sketch(g["Q"], sk))
+    ref = orq.rhqr_left(Win, sk)
+    ef_o = metrics.fact_error(Win, orq.thin_q(ref["U"], ref["T"], m), ref["R"])
+    log(f"{dt} n={n} m={m} panel={panel}/{outer}: e_fact {ef:.2e} e_orth {eo:.2e} (oracle {ef_o:.2e})")
+    assert ef < tol and eo < tol
+    assert abs(ef - ef_o) < tol
+
+
 def test_rank_deficient_zero_column():
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
