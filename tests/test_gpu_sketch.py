@@ -80,10 +80,13 @@ def test_srht_sketch_low_precision(dt):
         assert rel(Y[:, c], ref[:, c]) < 2e-6      # float32 accumulation
 
 
-def test_gauss_sketch_f64():
+@pytest.mark.parametrize("n,m,l,k", [(9000, 12, 80, 70),
+                                     # several 128 x 128 tiles in both directions, ragged
+                                     (20000 + 7, 30, 300, 150)])
+def test_gauss_sketch_f64(n, m, l, k):
     cuda_or_skip()
     from paper_2405_10923_amd import rhqr
-    n, m, l, k = 9000, 12, 80, 70
+    log(f"gauss sketch f64 n={n} m={m} l={l} k={k}")
     X = np.random.default_rng(3).standard_normal((n, k))
     om = osk.gaussian_omega(6, l, n - m)  # the oracle's draw, handed to the GPU
     sk = rhqr.Sketch(rhqr.GAUSS, n, m, l, seed=6, omega=to_gpu(om))
@@ -91,6 +94,23 @@ def test_gauss_sketch_f64():
     ref = np.concatenate([X[:m], om @ X[m:]])
     for c in range(k):
         assert rel(Y[:, c], ref[:, c]) < 1e-13
+
+
+@pytest.mark.parametrize("dt", ["float32", "float16"])
+def test_gauss_sketch_low_precision(dt):
+    """Low-precision storage: the product runs in float32 on matrix cores."""
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    n, m, l, k = 12000 + 3, 20, 200, 140
+    X = np.random.default_rng(5).standard_normal((n, k))
+    Xd = to_gpu(X, getattr(torch, dt))
+    Xr = to_np(Xd)  # the rounded input
+    om = osk.gaussian_omega(7, l, n - m)
+    sk = rhqr.Sketch(rhqr.GAUSS, n, m, l, seed=7, omega=to_gpu(om))
+    Y = to_np(rhqr.sketch(sk, Xd))
+    ref = np.concatenate([Xr[:m], om @ Xr[m:]])
+    # float32 products of n - m terms: well inside the storage type's tolerance
+    assert rel(Y, ref) < (1e-5 if dt == "float32" else 1e-4)
 
 
 def test_sketch_large_column_sampled():
