@@ -510,22 +510,23 @@ __global__ void __launch_bounds__(PANEL_TPB) k_trsm_blk(const ST *__restrict__ B
 }
 
 // ------------------------------- 2-byte products on matrix cores (thin Q)
-// Float32-accumulating v_mfma_f32_16x16x16 f16 / bf16 products of n-row data
+// Float32-accumulating v_mfma_f32_16x16x32 f16 / bf16 products of n-row data
 // with a float64 matrix that is scaled per column by a power of two s_j
 // (max |B_{:,j}| / s_j in (1/2, 1]) and split into two storage-type parts,
 // B / s = hi + lo, so the coefficients keep about 22 (f16) or 16 (bf16) bits.
 // Each wave owns 64 rows: it loads 32 columns with 16-byte row-contiguous
-// loads, transposes them through its own LDS slice (the operand needs 4
+// loads, transposes them through its own LDS slice (the operand needs 8
 // consecutive columns per lane) and issues the next chunk's loads before the
-// current chunk's products.
+// current chunk's products.  Lane L of an operand holds contraction indices
+// 8 (L >> 4) .. + 7; the A and B operands use the same assignment, so the
+// products do not depend on how the instruction orders them.
 constexpr int PM_ROWS = 64;                // rows per wave
 constexpr int PM_KC = 32;                  // columns of U per chunk
 constexpr int PM_KP = 2 * PM_KC;           // chunks go in pairs; coefficient rows padded to this
 constexpr int PM_RS = PM_ROWS + 8;         // LDS stride (elements) of one column slice
-constexpr int PM_WAVES = 4;
 
-typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
-typedef short s16x4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 template <typename ST> __device__ __forceinline__ float dec16(unsigned short b) {
   if constexpr (std::is_same<ST, __half>::value)
@@ -535,27 +536,13 @@ template <typename ST> __device__ __forceinline__ float dec16(unsigned short b) 
 }
 
 template <typename ST>
-__device__ __forceinline__ f32x4_t mfma16(const unsigned short (&a)[4], const uint2 b,
-                                         f32x4_t acc) {
-  if constexpr (std::is_same<ST, __half>::value) {
-    f16x4_t av, bv;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) av[t] = __builtin_bit_cast(_Float16, a[t]);
-    bv[0] = __builtin_bit_cast(_Float16, (unsigned short)(b.x & 0xffff));
-    bv[1] = __builtin_bit_cast(_Float16, (unsigned short)(b.x >> 16));
-    bv[2] = __builtin_bit_cast(_Float16, (unsigned short)(b.y & 0xffff));
-    bv[3] = __builtin_bit_cast(_Float16, (unsigned short)(b.y >> 16));
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(av, bv, acc, 0, 0, 0);
-  } else {
-    s16x4_t av, bv;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) av[t] = (short)a[t];
-    bv[0] = (short)(b.x & 0xffff);
-    bv[1] = (short)(b.x >> 16);
-    bv[2] = (short)(b.y & 0xffff);
-    bv[3] = (short)(b.y >> 16);
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-  }
+__device__ __forceinline__ f32x4_t mfma32(const u32x4 a, const u32x4 b, f32x4_t acc) {
+  if constexpr (std::is_same<ST, __half>::value)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8_t, a),
+                                                  __builtin_bit_cast(f16x8_t, b), acc, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                   __builtin_bit_cast(bf16x8_t, b), acc, 0, 0, 0);
 }
 
 // One wave's 64 rows.  FULL: all rows in bounds and 16-byte aligned; the
@@ -591,30 +578,37 @@ __device__ __forceinline__ void mfma_fetch(const ST *__restrict__ U, int64_t ldu
 }
 
 // the chunk's columns into this wave's LDS slice (column k at sl[k * PM_RS +
-// row]), then its products with NC coefficient columns (B-operand words of
-// 16 columns each, hi and lo parts)
+// row]), then its products with NC coefficient columns.  The B-operand words
+// (8 contraction indices each, hi and lo parts) are in LDS, staged by the
+// workgroup: cbh[g * NC + column] for the chunk's 8-row group g.
 template <typename ST, int NC>
-__device__ __forceinline__ void mfma_chunk(const u32x4 (&buf)[4], const uint2 (&bh)[PM_KC / 16][NC / 16],
-                                           const uint2 (&bl)[PM_KC / 16][NC / 16],
-                                           unsigned short *sl, f32x4_t (&acc)[4][NC / 16]) {
+__device__ __forceinline__ void mfma_chunk(const u32x4 (&buf)[4], const u32x4 *cbh,
+                                           const u32x4 *cbl, unsigned short *sl,
+                                           f32x4_t (&acc)[4][NC / 16]) {
+  static_assert(PM_KC == 32, "one contraction step of 32 columns per chunk");
   const int lane = threadIdx.x & 63;
   const int lc = lane >> 3, lr = (lane & 7) * 8;
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     *reinterpret_cast<u32x4 *>(sl + (lc + 8 * r) * PM_RS + lr) = buf[r];
+  u32x4 bh[NC / 16], bl[NC / 16];
 #pragma unroll
-  for (int kk = 0; kk < PM_KC / 16; ++kk) {
+  for (int h = 0; h < NC / 16; ++h) {
+    const int o = (lane >> 4) * NC + h * 16 + (lane & 15);
+    bh[h] = cbh[o];
+    bl[h] = cbl[o];
+  }
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-      unsigned short a[4];
+  for (int mb = 0; mb < 4; ++mb) {
+    uint32_t a[8];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        a[t] = sl[(kk * 16 + 4 * (lane >> 4) + t) * PM_RS + mb * 16 + (lane & 15)];
+    for (int t = 0; t < 8; ++t) a[t] = sl[(8 * (lane >> 4) + t) * PM_RS + mb * 16 + (lane & 15)];
+    const u32x4 av{a[0] | (a[1] << 16), a[2] | (a[3] << 16), a[4] | (a[5] << 16),
+                   a[6] | (a[7] << 16)};
 #pragma unroll
-      for (int h = 0; h < NC / 16; ++h) {
-        acc[mb][h] = mfma16<ST>(a, bh[kk][h], acc[mb][h]);
-        acc[mb][h] = mfma16<ST>(a, bl[kk][h], acc[mb][h]);
-      }
+    for (int h = 0; h < NC / 16; ++h) {
+      acc[mb][h] = mfma32<ST>(av, bh[h], acc[mb][h]);
+      acc[mb][h] = mfma32<ST>(av, bl[h], acc[mb][h]);
     }
   }
 }
@@ -626,8 +620,8 @@ __device__ __forceinline__ void mfma_chunk(const u32x4 (&buf)[4], const uint2 (&
 // all m columns of U_2 through its LDS slice, the next chunk in flight.
 constexpr int QH_NC = 64;
 
-// B operand order for a column tile of QH_NC: column group g (rows 4g..4g+3 of
-// Mq), tile column jt: B[((tile * Kg + g) * QH_NC + jt) * 4 + t], Kg = Kp / 4.
+// B operand order for a column tile of QH_NC: row group g (rows 8g..8g+7 of
+// Mq), tile column jt: B[((tile * Kg + g) * QH_NC + jt) * 8 + t], Kg = Kp / 8.
 template <typename ST>
 __global__ void __launch_bounds__(256) k_qconv(int32_t m, int32_t Kp,
                                               const double *__restrict__ Mq,
@@ -652,68 +646,126 @@ __global__ void __launch_bounds__(256) k_qconv(int32_t m, int32_t Kp,
     scale[j] = sc;
   }
   __syncthreads();
-  const int tile = j / QH_NC, jt = j % QH_NC, Kg = Kp / 4;
+  const int tile = j / QH_NC, jt = j % QH_NC, Kg = Kp / 8;
   for (int k = threadIdx.x; k < Kp; k += blockDim.x) {
     const double v = (col && k < m) ? Mq[k + (int64_t)j * m] / (double)sc : 0.0;
     const unsigned short h = enc16<ST>((float)v);
     const unsigned short lo = enc16<ST>((float)(v - (double)dec16<ST>(h)));
-    const int64_t o = ((((int64_t)tile * Kg + (k >> 2)) * QH_NC + jt) << 2) + (k & 3);
+    const int64_t o = ((((int64_t)tile * Kg + (k >> 3)) * QH_NC + jt) << 3) + (k & 7);
     Bh[o] = h;
     Bl[o] = lo;
   }
 }
 
+constexpr int QS_WAVES = 8;  // waves per workgroup of the 2-byte thin Q (64 rows each)
+
+// One wave's 64 rows x one column tile, all m columns of U_2 in chunk pairs.
+// The workgroup stages each pair's coefficient words in LDS (double-buffered:
+// the next pair's words are loaded during this pair's products and stored
+// after them, one barrier per pair), so the 8 waves share one fetch of them.
+// Every wave of the workgroup runs the loop (the barriers), `active` ones
+// also load and multiply.
 template <typename ST, bool FULL>
-__device__ __forceinline__ void qtail16_wave(const ST *__restrict__ U, int64_t ldu, int64_t rows,
+__device__ __forceinline__ void qtail16_loop(const ST *__restrict__ U, int64_t ldu, int64_t rows,
                                              int32_t m, int32_t Kp, int tile,
                                              const unsigned short *__restrict__ Bh,
-                                             const unsigned short *__restrict__ Bl,
-                                             unsigned short *sl, int64_t rb,
+                                             const unsigned short *__restrict__ Bl, u32x4 *cb,
+                                             unsigned short *sl, int64_t rb, bool active,
                                              f32x4_t (&acc)[4][QH_NC / 16]) {
-  const int lane = threadIdx.x & 63;
-  const int Kg = Kp / 4;
-  auto coefs = [&](int k0, uint2 (&bh)[PM_KC / 16][QH_NC / 16],
-                   uint2 (&bl)[PM_KC / 16][QH_NC / 16]) {
+  constexpr int PART = (PM_KP / 8) * QH_NC;        // words of one part of a pair
+  constexpr int CE = 2 * PART / (QS_WAVES * 64);   // words staged per thread and pair
+  static_assert(CE * QS_WAVES * 64 == 2 * PART, "staging covers the pair exactly");
+  const int Kg = Kp / 8;
+  u32x4 cr[CE];
+  auto cload = [&](int k0) {
 #pragma unroll
-    for (int kk = 0; kk < PM_KC / 16; ++kk) {
-      const int g = (k0 >> 2) + kk * 4 + (lane >> 4);
-#pragma unroll
-      for (int nb = 0; nb < QH_NC / 16; ++nb) {
-        const int64_t o = ((((int64_t)tile * Kg + g) * QH_NC + nb * 16 + (lane & 15)) << 2);
-        bh[kk][nb] = *reinterpret_cast<const uint2 *>(Bh + o);
-        bl[kk][nb] = *reinterpret_cast<const uint2 *>(Bl + o);
-      }
+    for (int q = 0; q < CE; ++q) {
+      const int e = threadIdx.x + q * QS_WAVES * 64;
+      const int r = e % PART, g = r / QH_NC, jt = r % QH_NC;
+      const unsigned short *B = e < PART ? Bh : Bl;
+      cr[q] = *reinterpret_cast<const u32x4 *>(
+          B + ((((int64_t)tile * Kg + (k0 >> 3) + g) * QH_NC + jt) << 3));
     }
   };
+  auto cstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < CE; ++q) cb[buf * 2 * PART + threadIdx.x + q * QS_WAVES * 64] = cr[q];
+  };
+  // a barrier over LDS only: the LDS stores are complete (lgkmcnt(0)) when
+  // the wave arrives, the next pair's loads of U stay in flight across it
+  auto lds_barrier = [] {
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_s_barrier();
+  };
+  // two register sets for the columns of U, used in turn: the set of the
+  // next pair is loaded while this pair's products run, with no copies
+  // between them (a copy would wait for the loads)
+  u32x4 xa[4], xb[4], ya[4], yb[4];
+  auto fetch = [&](int k0, u32x4 (&fa)[4], u32x4 (&fb)[4]) {
+    mfma_fetch<ST, FULL>(U, ldu, rows, m, rb, k0, fa);
+    mfma_fetch<ST, FULL>(U, ldu, rows, m, rb, k0 + PM_KC, fb);
+  };
+  int buf = 0;
+  // one chunk pair; PRE: also load the next pair (coefficient words first,
+  // so the wait for them before cstore leaves the column loads in flight).
+  // The last pair is peeled off so no branch separates a prefetch from its
+  // use (a wait count after a branch assumes the path without the loads).
+  const bool act = FULL || active;
+  auto step = [&](auto pre, int k0, const u32x4 (&ca)[4], const u32x4 (&cb2)[4],
+                  u32x4 (&na)[4], u32x4 (&nb)[4]) {
+    constexpr bool PRE = decltype(pre)::value;
+    if constexpr (PRE) {
+      cload(k0 + PM_KP);
+      if (act) fetch(k0 + PM_KP, na, nb);
+    }
+    if (act) {
+      const u32x4 *c0 = cb + buf * 2 * PART;
+      mfma_chunk<ST, QH_NC>(ca, c0, c0 + PART, sl, acc);
+      mfma_chunk<ST, QH_NC>(cb2, c0 + 4 * QH_NC, c0 + PART + 4 * QH_NC, sl, acc);
+    }
+    if constexpr (PRE) cstore(buf ^ 1);
+    lds_barrier();
+    buf ^= 1;
+  };
+  if (act) fetch(0, xa, xb);
+  cload(0);
+  cstore(0);
+  lds_barrier();
   // chunk pairs as in the panel update (clamped columns times zero
   // coefficients past m)
-  for (int k0 = 0; k0 < m; k0 += PM_KP) {
-    u32x4 ba[4], bb[4];
-    uint2 ha[PM_KC / 16][QH_NC / 16], la[PM_KC / 16][QH_NC / 16];
-    uint2 hb[PM_KC / 16][QH_NC / 16], lb[PM_KC / 16][QH_NC / 16];
-    coefs(k0, ha, la);
-    mfma_fetch<ST, FULL>(U, ldu, rows, m, rb, k0, ba);
-    coefs(k0 + PM_KC, hb, lb);
-    mfma_fetch<ST, FULL>(U, ldu, rows, m, rb, k0 + PM_KC, bb);
-    __builtin_amdgcn_sched_barrier(0);
-    mfma_chunk<ST, QH_NC>(ba, ha, la, sl, acc);
-    mfma_chunk<ST, QH_NC>(bb, hb, lb, sl, acc);
+  const int np = (m + PM_KP - 1) / PM_KP;
+  int p = 0;
+  for (; p + 2 < np; p += 2) {
+    step(std::true_type{}, p * PM_KP, xa, xb, ya, yb);
+    step(std::true_type{}, (p + 1) * PM_KP, ya, yb, xa, xb);
+  }
+  if (p + 1 < np) {
+    step(std::true_type{}, p * PM_KP, xa, xb, ya, yb);
+    step(std::false_type{}, (p + 1) * PM_KP, ya, yb, xa, xb);
+  } else {
+    step(std::false_type{}, p * PM_KP, xa, xb, ya, yb);
   }
 }
 
 template <typename ST>
-__global__ void __launch_bounds__(PM_WAVES * 64) k_qtail16(const ST *__restrict__ U, int64_t ldu,
+__global__ void __launch_bounds__(QS_WAVES * 64) k_qtail16(const ST *__restrict__ U, int64_t ldu,
                                                            int64_t rows, int32_t m, int32_t Kp,
                                                            const unsigned short *__restrict__ Bh,
                                                            const unsigned short *__restrict__ Bl,
                                                            const float *__restrict__ scale,
                                                            ST *__restrict__ Q, int64_t ldq,
-                                                           int aligned) {
-  __shared__ unsigned short lds[PM_WAVES][PM_KC * PM_RS];
+                                                           int aligned, int tiles) {
+  __shared__ unsigned short lds[QS_WAVES][PM_KC * PM_RS];
+  __shared__ u32x4 cb[2 * 2 * (PM_KP / 8) * QH_NC];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t rb = ((int64_t)blockIdx.x * PM_WAVES + w) * PM_ROWS;
-  if (rb >= rows) return;
-  const int tile = blockIdx.y;
+  // workgroup b runs on XCD b % 8: the tiles of one row block go to the same
+  // XCD one after another, so U is read from HBM about once
+  const int64_t slot = blockIdx.x >> 3;
+  const int tile = (int)(slot % tiles);
+  const int64_t blk = (slot / tiles) * 8 + (blockIdx.x & 7);
+  if (blk * QS_WAVES * PM_ROWS >= rows) return;  // the whole workgroup (uniform)
+  const int64_t rb = (blk * QS_WAVES + w) * PM_ROWS;
+  const bool active = rb < rows;
   const bool full = aligned && rb + PM_ROWS <= rows;
   f32x4_t acc[4][QH_NC / 16];
 #pragma unroll
@@ -721,9 +773,10 @@ __global__ void __launch_bounds__(PM_WAVES * 64) k_qtail16(const ST *__restrict_
 #pragma unroll
     for (int b = 0; b < QH_NC / 16; ++b) acc[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   if (full)
-    qtail16_wave<ST, true>(U, ldu, rows, m, Kp, tile, Bh, Bl, lds[w], rb, acc);
+    qtail16_loop<ST, true>(U, ldu, rows, m, Kp, tile, Bh, Bl, cb, lds[w], rb, true, acc);
   else
-    qtail16_wave<ST, false>(U, ldu, rows, m, Kp, tile, Bh, Bl, lds[w], rb, acc);
+    qtail16_loop<ST, false>(U, ldu, rows, m, Kp, tile, Bh, Bl, cb, lds[w], rb, active, acc);
+  if (!active) return;
 #pragma unroll
   for (int nb = 0; nb < QH_NC / 16; ++nb) {
     const int col = tile * QH_NC + nb * 16 + (lane & 15);
@@ -889,12 +942,18 @@ template <typename ST>
 __global__ void __launch_bounds__(PX_WAVES * 64) k_qtail_mx(int64_t n, int32_t m,
                                                             const ST *__restrict__ U, int64_t ldu,
                                                             const double *__restrict__ Ct,
-                                                            ST *__restrict__ Q, int64_t ldq) {
-  const int tile = blockIdx.y;
+                                                            ST *__restrict__ Q, int64_t ldq,
+                                                            int64_t groups, int tiles) {
+  // workgroup b runs on XCD b % 8: the tiles of one row group go to the same
+  // XCD one after another, so U is read from HBM about once
+  const int64_t slot = blockIdx.x >> 3;
+  const int tile = (int)(slot % tiles);
+  const int64_t g = (slot / tiles) * 8 + (blockIdx.x & 7);
+  if (g >= groups) return;
   const int c0 = tile * QX_NC;
   const int nb = m - c0 < QX_NC ? m - c0 : QX_NC;
   panel_mx_block<ST, QX_NC>(U, ldu, Q + (int64_t)c0 * ldq, ldq, true, n, m, 0, m, nb, QX_NC,
-                            Ct + (int64_t)tile * m * QX_NC, blockIdx.x);
+                            Ct + (int64_t)tile * m * QX_NC, g);
 }
 
 template <typename ST>
@@ -920,9 +979,10 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
       hipLaunchKernelGGL(k_mqt, dim3((m * QX_NC + 255) / 256, tiles), dim3(256), 0, st, m,
                          (const double *)Mq, Ct);
       RHQR_HIP(hipGetLastError());
-      const dim3 grid((unsigned)panel_mx_groups(n, m, (int)sizeof(ST)), tiles);
+      const int64_t groups = panel_mx_groups(n, m, (int)sizeof(ST));
+      const dim3 grid((unsigned)((groups + 7) / 8 * 8 * tiles));
       hipLaunchKernelGGL((k_qtail_mx<ST>), grid, dim3(PX_WAVES * 64), 0, st, n, m, U, ldu,
-                         (const double *)Ct, Q, ldq);
+                         (const double *)Ct, Q, ldq, groups, tiles);
       RHQR_HIP(hipGetLastError());
       return RHQR_OK;
     }
@@ -945,10 +1005,11 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
                           ((ldu * (int64_t)sizeof(ST)) % 16 == 0) &&
                           ((ldq * (int64_t)sizeof(ST)) % 8 == 0);
       const int64_t waves = (rows + PM_ROWS - 1) / PM_ROWS;
-      dim3 grid((unsigned)((waves + PM_WAVES - 1) / PM_WAVES), tiles);
-      hipLaunchKernelGGL((k_qtail16<ST>), grid, dim3(PM_WAVES * 64), 0, st, U + m, ldu, rows, m, Kp,
+      const int64_t blks = (waves + QS_WAVES - 1) / QS_WAVES;
+      const dim3 grid((unsigned)((blks + 7) / 8 * 8 * tiles));
+      hipLaunchKernelGGL((k_qtail16<ST>), grid, dim3(QS_WAVES * 64), 0, st, U + m, ldu, rows, m, Kp,
                          (const unsigned short *)Bh, (const unsigned short *)Bl,
-                         (const float *)sc, Q + m, ldq, aligned);
+                         (const float *)sc, Q + m, ldq, aligned, tiles);
     } else {
       dim3 grid((rows + 63) / 64, (m + 63) / 64);
       hipLaunchKernelGGL((k_gemm_tall<ST>), grid, dim3(256), 0, st, U, ldu, (int64_t)m, n, m,

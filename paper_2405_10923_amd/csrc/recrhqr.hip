@@ -130,6 +130,7 @@ __global__ void k_zero_mat(double *A, int64_t lda, int32_t rows, int32_t cols) {
 constexpr int SQ_NB = 8, SQ_TPB = 1024;
 constexpr int SQ_MAXL = 2048;  // L + m at most: the panel (L x SQ_NB) and Y (m x SQ_NB) in LDS
 constexpr int SQ_MAXM = 1024;  // largest m (recrhqr_factor rejects larger)
+constexpr int SQ_RC = 8;       // rows per lane held in registers by a column pass (512 rows)
 
 // sum over the workgroup of one value per thread, fixed order; all threads
 // get the result
@@ -280,8 +281,25 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_small(int32_t L, int32_t m, doub
         double d[SQ_NB];
 #pragma unroll
         for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
+        // the column's first SQ_RC * 64 rows are loaded at once, the rest
+        // streamed; the sums run over rows in increasing order either way
+        double sr[SQ_RC];
+#pragma unroll
+        for (int i = 0; i < SQ_RC; ++i) {
+          const int r = lane + 64 * i;
+          sr[i] = r < rows ? sp[r] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < SQ_RC; ++i) {
+          const int r = lane + 64 * i;
+          if (r < rows) {
+#pragma unroll
+            for (int q = 0; q < SQ_NB; ++q)
+              if (q < nb) d[q] += sr[i] * Pn[q * rows + r];
+          }
+        }
 #pragma unroll 4
-        for (int r = lane; r < rows; r += 64) {
+        for (int r = lane + 64 * SQ_RC; r < rows; r += 64) {
           const double sv = sp[r];
 #pragma unroll
           for (int q = 0; q < SQ_NB; ++q)
@@ -338,8 +356,25 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_small(int32_t L, int32_t m, doub
       double d[SQ_NB];
 #pragma unroll
       for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
+      // the column's first SQ_RC * 64 rows stay in registers from the dot
+      // products to the update; same order of operations as the streamed rest
+      double zr[SQ_RC];
+#pragma unroll
+      for (int i = 0; i < SQ_RC; ++i) {
+        const int r = lane + 64 * i;
+        zr[i] = r < rows ? zk[J + r] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < SQ_RC; ++i) {
+        const int r = lane + 64 * i;
+        if (r < rows) {
+#pragma unroll
+          for (int q = 0; q < SQ_NB; ++q)
+            if (q < nb) d[q] += Pn[q * rows + r] * zr[i];
+        }
+      }
 #pragma unroll 4
-      for (int r = lane; r < rows; r += 64) {
+      for (int r = lane + 64 * SQ_RC; r < rows; r += 64) {
         const double zv = zk[J + r];
 #pragma unroll
         for (int q = 0; q < SQ_NB; ++q)
@@ -356,8 +391,19 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_small(int32_t L, int32_t m, doub
           if (q <= c && c < nb) t += T[(J + q) + (int64_t)(J + c) * ldt] * d[q];
         u[c] = t;
       }
+#pragma unroll
+      for (int i = 0; i < SQ_RC; ++i) {
+        const int r = lane + 64 * i;
+        if (r < rows) {
+          double zv = zr[i];
+#pragma unroll
+          for (int c = 0; c < SQ_NB; ++c)
+            if (c < nb) zv -= Pn[c * rows + r] * u[c];
+          zk[J + r] = zv;
+        }
+      }
 #pragma unroll 4
-      for (int r = lane; r < rows; r += 64) {
+      for (int r = lane + 64 * SQ_RC; r < rows; r += 64) {
         double zv = zk[J + r];
 #pragma unroll
         for (int c = 0; c < SQ_NB; ++c)

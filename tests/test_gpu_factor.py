@@ -130,6 +130,22 @@ def test_low_precision_edge_shapes(dt, tol, n, m, l, panel, outer):
     assert abs(ef - ef_o) < tol
 
 
+# the thin Q product over several 64-column tiles of Q with a partial last
+# tile, and a last workgroup of waves whose rows end inside it
+@pytest.mark.parametrize("n,m,l", [(2 * 4096 + 300, 100, 400), (5000 + 13, 130, 520)])
+@pytest.mark.parametrize("dt,tol", [("float32", 1e-5), ("float16", 1e-2), ("bfloat16", 1e-2)])
+def test_low_precision_thin_q_tiles(dt, tol, n, m, l):
+    torch = cuda_or_skip()
+    W, Win, g, sk = _run(0, n, m, l, 1, dtype=dt, panel=16)
+    ref = orq.rhqr_left(Win, sk)
+    Qr = orq.thin_q(ref["U"], ref["T"], m)
+    ef = metrics.fact_error(Win, g["Q"], g["R"])
+    eo = metrics.orth_error(osk.rh_sketch(g["Q"], sk))
+    eq = np.linalg.norm(g["Q"].astype(np.float64) - Qr) / np.linalg.norm(Qr)
+    log(f"{dt} n={n} m={m}: e_fact {ef:.2e} e_orth {eo:.2e} ||Q - Q_oracle||/||Q_oracle|| {eq:.2e}")
+    assert ef < tol and eo < tol and eq < tol
+
+
 def test_rank_deficient_zero_column():
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
