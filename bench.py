@@ -391,7 +391,7 @@ def run_thin_q(rhqr, torch, sk, W64, m, steps, dt=None):
         out["bound"] = "fp64 matrix cores (AI = m/8 flop/B)"
         out["frac_fp64_peak"] = round(flops / (ms * 1e-3) / 78.6e12, 4)
     else:
-        out["bound"] = "hbm (f32 MFMA, split coefficients of Mq)"
+        out["bound"] = "hbm (16x16x32 f16/bf16 MFMA on split coefficients of Mq, float32 accumulation)"
         out["frac_hbm_peak"] = round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     return out
 

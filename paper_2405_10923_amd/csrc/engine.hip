@@ -523,7 +523,7 @@ __global__ void __launch_bounds__(PANEL_TPB) k_trsm_blk(const ST *__restrict__ B
 constexpr int PM_ROWS = 64;                // rows per wave
 constexpr int PM_KC = 32;                  // columns of U per chunk
 constexpr int PM_KP = 2 * PM_KC;           // chunks go in pairs; coefficient rows padded to this
-constexpr int PM_RS = PM_ROWS + 8;         // LDS stride (elements) of one column slice
+constexpr int PM_RS = PM_ROWS + 12;        // LDS stride (elements) of one column slice
 
 typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -588,9 +588,14 @@ __device__ __forceinline__ void mfma_chunk(const u32x4 (&buf)[4], const u32x4 *c
   static_assert(PM_KC == 32, "one contraction step of 32 columns per chunk");
   const int lane = threadIdx.x & 63;
   const int lc = lane >> 3, lr = (lane & 7) * 8;
+  // column starts 8-byte aligned (stride 152 bytes): the four 16-lane groups
+  // of an operand read fall in different banks
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-    *reinterpret_cast<u32x4 *>(sl + (lc + 8 * r) * PM_RS + lr) = buf[r];
+  for (int r = 0; r < 4; ++r) {
+    uint2 *d = reinterpret_cast<uint2 *>(sl + (lc + 8 * r) * PM_RS + lr);
+    d[0] = uint2{buf[r][0], buf[r][1]};
+    d[1] = uint2{buf[r][2], buf[r][3]};
+  }
   u32x4 bh[NC / 16], bl[NC / 16];
 #pragma unroll
   for (int h = 0; h < NC / 16; ++h) {
@@ -614,11 +619,15 @@ __device__ __forceinline__ void mfma_chunk(const u32x4 (&buf)[4], const u32x4 *c
 }
 
 // ------------------------------------------------ thin Q, 2-byte storage
-// Q_2 = -U_2 Mq on float32 MFMA with Mq split as in the panel update (per
-// column power-of-two scale, hi + lo parts in the storage type).  A wave owns
-// 64 rows x QH_NC columns of Q_2 (4 x QH_NC/16 accumulator blocks) and streams
-// all m columns of U_2 through its LDS slice, the next chunk in flight.
-constexpr int QH_NC = 64;
+// Q_2 = -U_2 Mq on the 16x16x32 f16/bf16 instruction with float32
+// accumulation, Mq split per column into a power-of-two scale and hi + lo
+// parts in the storage type.  A wave owns 64 rows x QH_NC columns of Q_2
+// (4 x QH_NC/16 accumulator blocks) and streams all m columns of U_2 through
+// its LDS slice, the second chunk of a pair in flight during the first
+// chunk's products.  Tiles of 128 columns: U is read twice at m = 256, and
+// each element loaded feeds 256 products (64-column tiles measured 25 %
+// slower, and a next-pair prefetch does not fit in registers at this width).
+constexpr int QH_NC = 128;
 
 // B operand order for a column tile of QH_NC: row group g (rows 8g..8g+7 of
 // Mq), tile column jt: B[((tile * Kg + g) * QH_NC + jt) * 8 + t], Kg = Kp / 8.
@@ -691,59 +700,28 @@ __device__ __forceinline__ void qtail16_loop(const ST *__restrict__ U, int64_t l
 #pragma unroll
     for (int q = 0; q < CE; ++q) cb[buf * 2 * PART + threadIdx.x + q * QS_WAVES * 64] = cr[q];
   };
-  // a barrier over LDS only: the LDS stores are complete (lgkmcnt(0)) when
-  // the wave arrives, the next pair's loads of U stay in flight across it
-  auto lds_barrier = [] {
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    __builtin_amdgcn_s_barrier();
-  };
-  // two register sets for the columns of U, used in turn: the set of the
-  // next pair is loaded while this pair's products run, with no copies
-  // between them (a copy would wait for the loads)
-  u32x4 xa[4], xb[4], ya[4], yb[4];
-  auto fetch = [&](int k0, u32x4 (&fa)[4], u32x4 (&fb)[4]) {
-    mfma_fetch<ST, FULL>(U, ldu, rows, m, rb, k0, fa);
-    mfma_fetch<ST, FULL>(U, ldu, rows, m, rb, k0 + PM_KC, fb);
-  };
-  int buf = 0;
-  // one chunk pair; PRE: also load the next pair (coefficient words first,
-  // so the wait for them before cstore leaves the column loads in flight).
-  // The last pair is peeled off so no branch separates a prefetch from its
-  // use (a wait count after a branch assumes the path without the loads).
-  const bool act = FULL || active;
-  auto step = [&](auto pre, int k0, const u32x4 (&ca)[4], const u32x4 (&cb2)[4],
-                  u32x4 (&na)[4], u32x4 (&nb)[4]) {
-    constexpr bool PRE = decltype(pre)::value;
-    if constexpr (PRE) {
-      cload(k0 + PM_KP);
-      if (act) fetch(k0 + PM_KP, na, nb);
-    }
-    if (act) {
-      const u32x4 *c0 = cb + buf * 2 * PART;
-      mfma_chunk<ST, QH_NC>(ca, c0, c0 + PART, sl, acc);
-      mfma_chunk<ST, QH_NC>(cb2, c0 + 4 * QH_NC, c0 + PART + 4 * QH_NC, sl, acc);
-    }
-    if constexpr (PRE) cstore(buf ^ 1);
-    lds_barrier();
-    buf ^= 1;
-  };
-  if (act) fetch(0, xa, xb);
   cload(0);
   cstore(0);
-  lds_barrier();
+  __syncthreads();
+  int buf = 0;
   // chunk pairs as in the panel update (clamped columns times zero
   // coefficients past m)
-  const int np = (m + PM_KP - 1) / PM_KP;
-  int p = 0;
-  for (; p + 2 < np; p += 2) {
-    step(std::true_type{}, p * PM_KP, xa, xb, ya, yb);
-    step(std::true_type{}, (p + 1) * PM_KP, ya, yb, xa, xb);
-  }
-  if (p + 1 < np) {
-    step(std::true_type{}, p * PM_KP, xa, xb, ya, yb);
-    step(std::false_type{}, (p + 1) * PM_KP, ya, yb, xa, xb);
-  } else {
-    step(std::false_type{}, p * PM_KP, xa, xb, ya, yb);
+  for (int k0 = 0; k0 < m; k0 += PM_KP) {
+    const bool more = k0 + PM_KP < m;
+    if (active) {
+      u32x4 ba[4], bb[4];
+      mfma_fetch<ST, FULL>(U, ldu, rows, m, rb, k0, ba);
+      mfma_fetch<ST, FULL>(U, ldu, rows, m, rb, k0 + PM_KC, bb);
+      if (more) cload(k0 + PM_KP);
+      const u32x4 *c0 = cb + buf * 2 * PART;
+      mfma_chunk<ST, QH_NC>(ba, c0, c0 + PART, sl, acc);
+      mfma_chunk<ST, QH_NC>(bb, c0 + 4 * QH_NC, c0 + PART + 4 * QH_NC, sl, acc);
+    } else if (more) {
+      cload(k0 + PM_KP);
+    }
+    if (more) cstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
 }
 
