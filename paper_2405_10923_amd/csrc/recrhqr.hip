@@ -117,16 +117,16 @@ __global__ void k_zero_mat(double *A, int64_t lda, int32_t rows, int32_t cols) {
 }
 
 // ------------------------------------------- sketch-space Householder QR
-// Householder QR of the small L x m float64 sketch Z (overwritten) in one
-// workgroup, right-looking in panels of SQ_NB columns: the panel is factored
-// in LDS one column at a time (RHVector with Psi = I, Alg. 2: sigma, rho,
-// gamma, alpha, beta; identity reflector when rho = 0), its vectors go to S,
-// the T recursion of Prop. 3.2 (T_{:,j} = -beta_j T S^t s_j, in block form
-// per panel) extends T, and the trailing columns are updated by the panel's
-// block reflector,
-// Z <- (I - S_p T_p^t S_p^t) Z.  Every reduction runs in a fixed order.  The
-// same factorization as the column engine with Psi = I, in far fewer
-// launches (one).
+// Householder QR of the small L x m float64 sketch Z (overwritten),
+// right-looking in panels of SQ_NB columns, two launches per panel.
+// k_hqr_panel (one workgroup) factors the panel in LDS one column at a time
+// (RHVector with Psi = I, Alg. 2: sigma, rho, gamma, alpha, beta; identity
+// reflector when rho = 0), writes its vectors to S and extends T by the
+// recursion of Prop. 3.2 (T_{:,j} = -beta_j T S^t s_j, in block form per
+// panel).  k_hqr_trail (one wave per trailing column) applies the panel's
+// block reflector, Z <- (I - S_p T_p^t S_p^t) Z.  Every reduction runs in a
+// fixed order.  The same factorization as the column engine with Psi = I,
+// in far fewer launches.
 constexpr int SQ_NB = 8, SQ_TPB = 1024;
 constexpr int SQ_MAXL = 2048;  // L + m at most: the panel (L x SQ_NB) and Y (m x SQ_NB) in LDS
 constexpr int SQ_MAXM = 1024;  // largest m (recrhqr_factor rejects larger)
@@ -145,10 +145,10 @@ __device__ __forceinline__ double sq_block_sum(double v, double *red16) {
   return s;
 }
 
-__global__ void __launch_bounds__(SQ_TPB) k_hqr_small(int32_t L, int32_t m, double *Z, int64_t ldz,
-                                                      double *S, int64_t lds, double *T,
-                                                      int64_t ldt, double *R, int64_t ldr,
-                                                      int scaling, int32_t *status) {
+__global__ void __launch_bounds__(SQ_TPB) k_hqr_panel(int32_t L, int32_t m, int32_t J, double *Z,
+                                                      int64_t ldz, double *S, int64_t lds,
+                                                      double *T, int64_t ldt, double *R,
+                                                      int64_t ldr, int scaling, int32_t *status) {
   // panel: column c at Pn + c * rows, rows J .. L-1; after it, Y (J x SQ_NB)
   extern __shared__ double Pn[];
   __shared__ double red16[SQ_TPB / 64];
@@ -156,213 +156,137 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_small(int32_t L, int32_t m, doub
   __shared__ double gv[SQ_MAXM];
   __shared__ double bet[SQ_NB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int J = 0; J < m; J += SQ_NB) {
-    const int nb = m - J < SQ_NB ? m - J : SQ_NB;
-    const int rows = L - J;
-    // the panel's rows J.. into LDS; its rows < J are final entries of R
-    for (int e = tid; e < rows * nb; e += SQ_TPB) {
-      const int r = e % rows, c = e / rows;
-      Pn[c * rows + r] = Z[(J + r) + (int64_t)(J + c) * ldz];
-    }
-    for (int e = tid; e < J * nb; e += SQ_TPB) {
-      const int r = e % J, c = e / J;
-      R[r + (int64_t)(J + c) * ldr] = Z[r + (int64_t)(J + c) * ldz];
-    }
-    __syncthreads();
-    for (int c = 0; c < nb; ++c) {
-      const int j = J + c;
-      double *x = Pn + c * rows;  // local row r is row J + r; the pivot is local row c
-      double ss = 0.0;
-      for (int r = c + tid; r < rows; r += SQ_TPB) ss += x[r] * x[r];
-      ss = sq_block_sum(ss, red16);
-      // RHVector scalars (every thread computes the same values)
-      const double rho = sqrt(ss);
-      const double yj = x[c];
-      const double sigma = yj >= 0.0 ? 1.0 : -1.0;
-      const bool ident = !(rho > 0.0);
-      double gamma = 0.0, alpha = 1.0, beta = 0.0;
-      if (!ident) {
-        gamma = yj + sigma * rho;
-        if (scaling == RHQR_SCALE_UNIT_PIVOT) {
-          alpha = gamma;
-          beta = fabs(gamma) / rho;
-        } else {
-          alpha = sqrt(rho * fabs(gamma));
-          beta = 1.0;
-        }
-      }
-      const double sr = sigma * rho;
-      __syncthreads();  // every thread has read x[c]
-      // R column j: rows J..j-1 from the panel, -sigma rho on the diagonal, zeros below
-      for (int r = tid; r < m; r += SQ_TPB) {
-        if (r >= J && r < j) R[r + (int64_t)j * ldr] = x[r - J];
-        else if (r == j) R[r + (int64_t)j * ldr] = -sr;
-        else if (r > j) R[r + (int64_t)j * ldr] = 0.0;
-      }
-      __syncthreads();  // the R entries above the pivot have been read
-      // s_j in place of the column
-      for (int r = tid; r < rows; r += SQ_TPB) {
-        double sv = 0.0;
-        if (r == c)
-          sv = ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : gamma / alpha);
-        else if (r > c)
-          sv = ident ? 0.0 : x[r] / alpha;
-        x[r] = sv;
-      }
-      if (tid == 0) {
-        bet[c] = beta;
-        T[j + (int64_t)j * ldt] = beta;
-        if (ident) atomicCAS(status, 0, j + 1);
-      }
-      __syncthreads();
-      // H_j = I - beta s_j s_j^t on the panel's later columns (rows >= j)
-      const int nrem = nb - 1 - c;
-      if (nrem > 0 && !ident) {
-        double d[SQ_NB];
-#pragma unroll
-        for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
-        for (int r = c + tid; r < rows; r += SQ_TPB) {
-          const double sv = x[r];
-#pragma unroll
-          for (int q = 0; q < SQ_NB; ++q)
-            if (q < nrem) d[q] += sv * Pn[(c + 1 + q) * rows + r];
-        }
-#pragma unroll
-        for (int q = 0; q < SQ_NB; ++q) {
-          const double v = wave_sum(d[q]);
-          if (lane == 0 && q < nrem) redv[w][q] = v;
-        }
-        __syncthreads();
-        if (tid < nrem) {
-          double sum = 0.0;
-          for (int i = 0; i < SQ_TPB / 64; ++i) sum += redv[i][tid];
-          gv[tid] = beta * sum;
-        }
-        __syncthreads();
-        for (int e = tid; e < nrem * (rows - c); e += SQ_TPB) {
-          const int q = e / (rows - c), r = c + e % (rows - c);
-          Pn[(c + 1 + q) * rows + r] -= gv[q] * x[r];
-        }
-        __syncthreads();
+  const int nb = m - J < SQ_NB ? m - J : SQ_NB;
+  const int rows = L - J;
+  // the panel's rows J.. into LDS; its rows < J are final entries of R
+  for (int e = tid; e < rows * nb; e += SQ_TPB) {
+    const int r = e % rows, c = e / rows;
+    Pn[c * rows + r] = Z[(J + r) + (int64_t)(J + c) * ldz];
+  }
+  for (int e = tid; e < J * nb; e += SQ_TPB) {
+    const int r = e % J, c = e / J;
+    R[r + (int64_t)(J + c) * ldr] = Z[r + (int64_t)(J + c) * ldz];
+  }
+  __syncthreads();
+  for (int c = 0; c < nb; ++c) {
+    const int j = J + c;
+    double *x = Pn + c * rows;  // local row r is row J + r; the pivot is local row c
+    double ss = 0.0;
+    for (int r = c + tid; r < rows; r += SQ_TPB) ss += x[r] * x[r];
+    ss = sq_block_sum(ss, red16);
+    // RHVector scalars (every thread computes the same values)
+    const double rho = sqrt(ss);
+    const double yj = x[c];
+    const double sigma = yj >= 0.0 ? 1.0 : -1.0;
+    const bool ident = !(rho > 0.0);
+    double gamma = 0.0, alpha = 1.0, beta = 0.0;
+    if (!ident) {
+      gamma = yj + sigma * rho;
+      if (scaling == RHQR_SCALE_UNIT_PIVOT) {
+        alpha = gamma;
+        beta = fabs(gamma) / rho;
+      } else {
+        alpha = sqrt(rho * fabs(gamma));
+        beta = 1.0;
       }
     }
-    // the panel's vectors into S (zeros above the panel rows)
-    for (int e = tid; e < L * nb; e += SQ_TPB) {
-      const int r = e % L, c = e / L;
-      S[r + (int64_t)(J + c) * lds] = r < J ? 0.0 : Pn[c * rows + (r - J)];
+    const double sr = sigma * rho;
+    __syncthreads();  // every thread has read x[c]
+    // R column j: rows J..j-1 from the panel, -sigma rho on the diagonal, zeros below
+    for (int r = tid; r < m; r += SQ_TPB) {
+      if (r >= J && r < j) R[r + (int64_t)j * ldr] = x[r - J];
+      else if (r == j) R[r + (int64_t)j * ldr] = -sr;
+      else if (r > j) R[r + (int64_t)j * ldr] = 0.0;
+    }
+    __syncthreads();  // the R entries above the pivot have been read
+    // s_j in place of the column
+    for (int r = tid; r < rows; r += SQ_TPB) {
+      double sv = 0.0;
+      if (r == c)
+        sv = ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : gamma / alpha);
+      else if (r > c)
+        sv = ident ? 0.0 : x[r] / alpha;
+      x[r] = sv;
+    }
+    if (tid == 0) {
+      bet[c] = beta;
+      T[j + (int64_t)j * ldt] = beta;
+      if (ident) atomicCAS(status, 0, j + 1);
     }
     __syncthreads();
-    // T columns J..J+nb-1, block form of the Prop. 3.2 recursion: the
-    // panel's own block T_pp (g = S_p^t s_j over the panel, from LDS), then
-    // T_{<J, p} = -T_{<J,<J} (S_{<J}^t S_p) T_pp.
-    for (int c = 0; c < nb; ++c) {
-      const double *xj = Pn + c * rows;
-      // g_q = s_q^t s_j for the panel's q < c (rows >= J + c), one wave per q
-      for (int q = w; q < c; q += SQ_TPB / 64) {
-        const double *xq = Pn + q * rows;
-        double v = 0.0;
-        for (int r = c + lane; r < rows; r += 64) v += xq[r] * xj[r];
-        v = wave_sum(v);
-        if (lane == 0) gv[q] = v;
-      }
-      __syncthreads();
-      if (tid < c) {
-        double t = 0.0;
-        for (int q = tid; q < c; ++q) t += T[(J + tid) + (int64_t)(J + q) * ldt] * gv[q];
-        T[(J + tid) + (int64_t)(J + c) * ldt] = -bet[c] * t;
-      }
-      __syncthreads();
-    }
-    if (J > 0) {
-      // X = S_{<J}^t S_p (rows >= J), one wave per earlier column p, into
-      // T[p, J + c] as scratch
-      for (int p = w; p < J; p += SQ_TPB / 64) {
-        const double *sp = S + (int64_t)p * lds + J;
-        double d[SQ_NB];
-#pragma unroll
-        for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
-        // the column's first SQ_RC * 64 rows are loaded at once, the rest
-        // streamed; the sums run over rows in increasing order either way
-        double sr[SQ_RC];
-#pragma unroll
-        for (int i = 0; i < SQ_RC; ++i) {
-          const int r = lane + 64 * i;
-          sr[i] = r < rows ? sp[r] : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < SQ_RC; ++i) {
-          const int r = lane + 64 * i;
-          if (r < rows) {
-#pragma unroll
-            for (int q = 0; q < SQ_NB; ++q)
-              if (q < nb) d[q] += sr[i] * Pn[q * rows + r];
-          }
-        }
-#pragma unroll 4
-        for (int r = lane + 64 * SQ_RC; r < rows; r += 64) {
-          const double sv = sp[r];
-#pragma unroll
-          for (int q = 0; q < SQ_NB; ++q)
-            if (q < nb) d[q] += sv * Pn[q * rows + r];
-        }
-#pragma unroll
-        for (int q = 0; q < SQ_NB; ++q) {
-          const double v = wave_sum(d[q]);
-          if (lane == 0 && q < nb) T[p + (int64_t)(J + q) * ldt] = v;
-        }
-      }
-      __syncthreads();
-      // Y = T_{<J,<J} X into LDS (after the panel), one wave per row p,
-      // lanes over q >= p
-      double *Yl = Pn + (size_t)SQ_NB * rows;
-      for (int p = w; p < J; p += SQ_TPB / 64) {
-        double t[SQ_NB];
-#pragma unroll
-        for (int c = 0; c < SQ_NB; ++c) t[c] = 0.0;
-        for (int q = p + lane; q < J; q += 64) {
-          const double tpq = T[p + (int64_t)q * ldt];
-#pragma unroll
-          for (int c = 0; c < SQ_NB; ++c)
-            if (c < nb) t[c] += tpq * T[q + (int64_t)(J + c) * ldt];
-        }
-#pragma unroll
-        for (int c = 0; c < SQ_NB; ++c) {
-          const double v = wave_sum(t[c]);
-          if (lane == 0) Yl[p * SQ_NB + c] = v;
-        }
-      }
-      __syncthreads();
-      // T_{<J, p} = -Y T_pp, row by row
-      for (int p = tid; p < J; p += SQ_TPB) {
-        double o[SQ_NB];
-#pragma unroll
-        for (int c = 0; c < SQ_NB; ++c) {
-          double t = 0.0;
-#pragma unroll
-          for (int q = 0; q < SQ_NB; ++q)
-            if (q <= c && c < nb) t += Yl[p * SQ_NB + q] * T[(J + q) + (int64_t)(J + c) * ldt];
-          o[c] = -t;
-        }
-#pragma unroll
-        for (int c = 0; c < SQ_NB; ++c)
-          if (c < nb) T[p + (int64_t)(J + c) * ldt] = o[c];
-      }
-      __syncthreads();
-    }
-    // trailing columns k >= J + nb: w = S_p^t Z_k, u = T_p^t w, Z_k -= S_p u
-    // (rows >= J; one wave per column)
-    for (int k = J + nb + w; k < m; k += SQ_TPB / 64) {
-      double *zk = Z + (int64_t)k * ldz;
+    // H_j = I - beta s_j s_j^t on the panel's later columns (rows >= j)
+    const int nrem = nb - 1 - c;
+    if (nrem > 0 && !ident) {
       double d[SQ_NB];
 #pragma unroll
       for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
-      // the column's first SQ_RC * 64 rows stay in registers from the dot
-      // products to the update; same order of operations as the streamed rest
-      double zr[SQ_RC];
+      for (int r = c + tid; r < rows; r += SQ_TPB) {
+        const double sv = x[r];
+#pragma unroll
+        for (int q = 0; q < SQ_NB; ++q)
+          if (q < nrem) d[q] += sv * Pn[(c + 1 + q) * rows + r];
+      }
+#pragma unroll
+      for (int q = 0; q < SQ_NB; ++q) {
+        const double v = wave_sum(d[q]);
+        if (lane == 0 && q < nrem) redv[w][q] = v;
+      }
+      __syncthreads();
+      if (tid < nrem) {
+        double sum = 0.0;
+        for (int i = 0; i < SQ_TPB / 64; ++i) sum += redv[i][tid];
+        gv[tid] = beta * sum;
+      }
+      __syncthreads();
+      for (int e = tid; e < nrem * (rows - c); e += SQ_TPB) {
+        const int q = e / (rows - c), r = c + e % (rows - c);
+        Pn[(c + 1 + q) * rows + r] -= gv[q] * x[r];
+      }
+      __syncthreads();
+    }
+  }
+  // the panel's vectors into S (zeros above the panel rows)
+  for (int e = tid; e < L * nb; e += SQ_TPB) {
+    const int r = e % L, c = e / L;
+    S[r + (int64_t)(J + c) * lds] = r < J ? 0.0 : Pn[c * rows + (r - J)];
+  }
+  __syncthreads();
+  // T columns J..J+nb-1, block form of the Prop. 3.2 recursion: the
+  // panel's own block T_pp (g = S_p^t s_j over the panel, from LDS), then
+  // T_{<J, p} = -T_{<J,<J} (S_{<J}^t S_p) T_pp.
+  for (int c = 0; c < nb; ++c) {
+    const double *xj = Pn + c * rows;
+    // g_q = s_q^t s_j for the panel's q < c (rows >= J + c), one wave per q
+    for (int q = w; q < c; q += SQ_TPB / 64) {
+      const double *xq = Pn + q * rows;
+      double v = 0.0;
+      for (int r = c + lane; r < rows; r += 64) v += xq[r] * xj[r];
+      v = wave_sum(v);
+      if (lane == 0) gv[q] = v;
+    }
+    __syncthreads();
+    if (tid < c) {
+      double t = 0.0;
+      for (int q = tid; q < c; ++q) t += T[(J + tid) + (int64_t)(J + q) * ldt] * gv[q];
+      T[(J + tid) + (int64_t)(J + c) * ldt] = -bet[c] * t;
+    }
+    __syncthreads();
+  }
+  if (J > 0) {
+    // X = S_{<J}^t S_p (rows >= J), one wave per earlier column p, into
+    // T[p, J + c] as scratch
+    for (int p = w; p < J; p += SQ_TPB / 64) {
+      const double *sp = S + (int64_t)p * lds + J;
+      double d[SQ_NB];
+#pragma unroll
+      for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
+      // the column's first SQ_RC * 64 rows are loaded at once, the rest
+      // streamed; the sums run over rows in increasing order either way
+      double sr[SQ_RC];
 #pragma unroll
       for (int i = 0; i < SQ_RC; ++i) {
         const int r = lane + 64 * i;
-        zr[i] = r < rows ? zk[J + r] : 0.0;
+        sr[i] = r < rows ? sp[r] : 0.0;
       }
 #pragma unroll
       for (int i = 0; i < SQ_RC; ++i) {
@@ -370,48 +294,129 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_small(int32_t L, int32_t m, doub
         if (r < rows) {
 #pragma unroll
           for (int q = 0; q < SQ_NB; ++q)
-            if (q < nb) d[q] += Pn[q * rows + r] * zr[i];
+            if (q < nb) d[q] += sr[i] * Pn[q * rows + r];
         }
       }
 #pragma unroll 4
       for (int r = lane + 64 * SQ_RC; r < rows; r += 64) {
-        const double zv = zk[J + r];
+        const double sv = sp[r];
 #pragma unroll
         for (int q = 0; q < SQ_NB; ++q)
-          if (q < nb) d[q] += Pn[q * rows + r] * zv;
+          if (q < nb) d[q] += sv * Pn[q * rows + r];
       }
-      double u[SQ_NB];
 #pragma unroll
-      for (int q = 0; q < SQ_NB; ++q) d[q] = wave_sum(d[q]);
+      for (int q = 0; q < SQ_NB; ++q) {
+        const double v = wave_sum(d[q]);
+        if (lane == 0 && q < nb) T[p + (int64_t)(J + q) * ldt] = v;
+      }
+    }
+    __syncthreads();
+    // Y = T_{<J,<J} X into LDS (after the panel), one wave per row p,
+    // lanes over q >= p
+    double *Yl = Pn + (size_t)SQ_NB * rows;
+    for (int p = w; p < J; p += SQ_TPB / 64) {
+      double t[SQ_NB];
+#pragma unroll
+      for (int c = 0; c < SQ_NB; ++c) t[c] = 0.0;
+      for (int q = p + lane; q < J; q += 64) {
+        const double tpq = T[p + (int64_t)q * ldt];
+#pragma unroll
+        for (int c = 0; c < SQ_NB; ++c)
+          if (c < nb) t[c] += tpq * T[q + (int64_t)(J + c) * ldt];
+      }
+#pragma unroll
+      for (int c = 0; c < SQ_NB; ++c) {
+        const double v = wave_sum(t[c]);
+        if (lane == 0) Yl[p * SQ_NB + c] = v;
+      }
+    }
+    __syncthreads();
+    // T_{<J, p} = -Y T_pp, row by row
+    for (int p = tid; p < J; p += SQ_TPB) {
+      double o[SQ_NB];
 #pragma unroll
       for (int c = 0; c < SQ_NB; ++c) {
         double t = 0.0;
 #pragma unroll
         for (int q = 0; q < SQ_NB; ++q)
-          if (q <= c && c < nb) t += T[(J + q) + (int64_t)(J + c) * ldt] * d[q];
-        u[c] = t;
+          if (q <= c && c < nb) t += Yl[p * SQ_NB + q] * T[(J + q) + (int64_t)(J + c) * ldt];
+        o[c] = -t;
       }
 #pragma unroll
-      for (int i = 0; i < SQ_RC; ++i) {
-        const int r = lane + 64 * i;
-        if (r < rows) {
-          double zv = zr[i];
-#pragma unroll
-          for (int c = 0; c < SQ_NB; ++c)
-            if (c < nb) zv -= Pn[c * rows + r] * u[c];
-          zk[J + r] = zv;
-        }
-      }
-#pragma unroll 4
-      for (int r = lane + 64 * SQ_RC; r < rows; r += 64) {
-        double zv = zk[J + r];
-#pragma unroll
-        for (int c = 0; c < SQ_NB; ++c)
-          if (c < nb) zv -= Pn[c * rows + r] * u[c];
-        zk[J + r] = zv;
-      }
+      for (int c = 0; c < SQ_NB; ++c)
+        if (c < nb) T[p + (int64_t)(J + c) * ldt] = o[c];
     }
-    __syncthreads();  // the next panel reads the updated columns
+    __syncthreads();
+  }
+}
+
+// trailing column k = J + nb + blockIdx.x of panel J: w = S_p^t Z_k,
+// u = T_p^t w, Z_k -= S_p u (rows >= J), with the panel's vectors read from S
+__global__ void __launch_bounds__(64) k_hqr_trail(int32_t L, int32_t m, int32_t J, double *Z,
+                                                  int64_t ldz, const double *S, int64_t lds,
+                                                  const double *T, int64_t ldt) {
+  const int nb = m - J < SQ_NB ? m - J : SQ_NB;
+  const int rows = L - J, lane = threadIdx.x;
+  const int k = J + nb + (int)blockIdx.x;
+  if (k >= m) return;
+  const double *Sp = S + J + (int64_t)J * lds;  // Sp[r + q * lds]: panel vector q, row J + r
+  double *zk = Z + (int64_t)k * ldz;
+  double d[SQ_NB];
+#pragma unroll
+  for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
+  // the column's first SQ_RC * 64 rows stay in registers from the dot
+  // products to the update; same order of operations as the streamed rest
+  double zr[SQ_RC];
+#pragma unroll
+  for (int i = 0; i < SQ_RC; ++i) {
+    const int r = lane + 64 * i;
+    zr[i] = r < rows ? zk[J + r] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < SQ_RC; ++i) {
+    const int r = lane + 64 * i;
+    if (r < rows) {
+#pragma unroll
+      for (int q = 0; q < SQ_NB; ++q)
+        if (q < nb) d[q] += Sp[r + (int64_t)q * lds] * zr[i];
+    }
+  }
+#pragma unroll 4
+  for (int r = lane + 64 * SQ_RC; r < rows; r += 64) {
+    const double zv = zk[J + r];
+#pragma unroll
+    for (int q = 0; q < SQ_NB; ++q)
+      if (q < nb) d[q] += Sp[r + (int64_t)q * lds] * zv;
+  }
+  double u[SQ_NB];
+#pragma unroll
+  for (int q = 0; q < SQ_NB; ++q) d[q] = wave_sum(d[q]);
+#pragma unroll
+  for (int c = 0; c < SQ_NB; ++c) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < SQ_NB; ++q)
+      if (q <= c && c < nb) t += T[(J + q) + (int64_t)(J + c) * ldt] * d[q];
+    u[c] = t;
+  }
+#pragma unroll
+  for (int i = 0; i < SQ_RC; ++i) {
+    const int r = lane + 64 * i;
+    if (r < rows) {
+      double zv = zr[i];
+#pragma unroll
+      for (int c = 0; c < SQ_NB; ++c)
+        if (c < nb) zv -= Sp[r + (int64_t)c * lds] * u[c];
+      zk[J + r] = zv;
+    }
+  }
+#pragma unroll 4
+  for (int r = lane + 64 * SQ_RC; r < rows; r += 64) {
+    double zv = zk[J + r];
+#pragma unroll
+    for (int c = 0; c < SQ_NB; ++c)
+      if (c < nb) zv -= Sp[r + (int64_t)c * lds] * u[c];
+    zk[J + r] = zv;
   }
 }
 
@@ -423,18 +428,27 @@ int sketch_space_hqr(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, d
                      int64_t ldt, double *R, int64_t ldr, const LoopWs &w, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_mat, dim3((m + 255) / 256, m), dim3(256), 0, st, T, ldt, m, m);
   RHQR_HIP(hipGetLastError());
-  if (L + m <= SQ_MAXL) {  // one workgroup, the panel in LDS
+  if (L + m <= SQ_MAXL) {  // the panel in LDS; two launches per panel
     const size_t lds_bytes = sizeof(double) * (size_t)(L + m) * SQ_NB;
     static bool attr_set = false;
     if (!attr_set) {
-      RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_small,
+      RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_panel,
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)(sizeof(double) * SQ_MAXL * SQ_NB)));
       attr_set = true;
     }
-    hipLaunchKernelGGL(k_hqr_small, dim3(1), dim3(SQ_TPB), lds_bytes, st, L, m, Zc, (int64_t)L, S,
-                       lds, T, ldt, R, ldr, (int)RHQR_SCALE_UNIT_PIVOT, w.status);
-    RHQR_HIP(hipGetLastError());
+    for (int32_t J = 0; J < m; J += SQ_NB) {
+      const int32_t nb = m - J < SQ_NB ? m - J : SQ_NB;
+      hipLaunchKernelGGL(k_hqr_panel, dim3(1), dim3(SQ_TPB), lds_bytes, st, L, m, J, Zc,
+                         (int64_t)L, S, lds, T, ldt, R, ldr, (int)RHQR_SCALE_UNIT_PIVOT,
+                         w.status);
+      RHQR_HIP(hipGetLastError());
+      if (J + nb < m) {
+        hipLaunchKernelGGL(k_hqr_trail, dim3((unsigned)(m - J - nb)), dim3(64), 0, st, L, m, J,
+                           Zc, (int64_t)L, (const double *)S, lds, (const double *)T, ldt);
+        RHQR_HIP(hipGetLastError());
+      }
+    }
     return RHQR_OK;
   }
   LoopArgs a;
