@@ -320,7 +320,11 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
       part[(int64_t)bid * l + q] = h;
     }
   } else {  // Gaussian: partial Omega[:, rows] w~_rows, four row groups per sample
-    __shared__ double red[KIND == RHQR_SKETCH_GAUSS ? 1024 : 1];
+    // Each thread takes two adjacent samples (one 16-byte load of Omega per
+    // row when l is even) and four accumulators over rows 16 apart, so that
+    // four loads per thread are in flight; odd l (or an Omega not 16-byte
+    // aligned) takes the samples one by one.
+    __shared__ double red[KIND == RHQR_SKETCH_GAUSS ? 2048 : 1];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int li0 = VEC * (tid + TPB * v);
@@ -332,24 +336,44 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
     }
     const int64_t lo = base > m ? base : (int64_t)m;
     const int64_t hi = base + ROWS < n ? base + ROWS : n;
-    const int g = tid >> 8;
-    for (int q0 = 0; q0 < l; q0 += 256) {
+    const int g = tid >> 8, t = tid & 255;
+    const bool pairs = (l & 1) == 0 && ((uintptr_t)om & 15) == 0;
+    for (int q0 = 0; q0 < l; q0 += 512) {
       __syncthreads();
-      const int q = q0 + (tid & 255);
-      double a0 = 0, a1 = 0;
-      if (q < l) {
+      const int q = q0 + 2 * t;
+      double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
+      if (pairs && q < l) {  // q + 1 < l as well (l even, q even)
         int64_t i = lo + g;
-        for (; i + 4 < hi; i += 8) {
-          a0 += om[(i - m) * l + q] * (double)s[i - base];
-          a1 += om[(i + 4 - m) * l + q] * (double)s[i + 4 - base];
+#pragma unroll 2
+        for (; i + 12 < hi; i += 16) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double2 o = *reinterpret_cast<const double2 *>(om + (i + 4 * u - m) * l + q);
+            const double x = (double)s[i + 4 * u - base];
+            a[u] += o.x * x;
+            b[u] += o.y * x;
+          }
         }
-        for (; i < hi; i += 4) a0 += om[(i - m) * l + q] * (double)s[i - base];
+        for (; i < hi; i += 4) {
+          const double2 o = *reinterpret_cast<const double2 *>(om + (i - m) * l + q);
+          const double x = (double)s[i - base];
+          a[0] += o.x * x;
+          b[0] += o.y * x;
+        }
+      } else if (!pairs) {
+        for (int e = 0; e < 2; ++e) {
+          if (q + e >= l) break;
+          double c = 0.0;
+          for (int64_t i = lo + g; i < hi; i += 4) c += om[(i - m) * l + q + e] * (double)s[i - base];
+          (e ? b : a)[0] = c;
+        }
       }
-      red[g * 256 + (tid & 255)] = a0 + a1;
+      red[2 * (g * 256 + t)] = (a[0] + a[1]) + (a[2] + a[3]);
+      red[2 * (g * 256 + t) + 1] = (b[0] + b[1]) + (b[2] + b[3]);
       __syncthreads();
-      if (g == 0 && q < l)
-        part[(int64_t)bid * l + q] =
-            (red[tid] + red[256 + tid]) + (red[512 + tid] + red[768 + tid]);
+      if (tid < 512 && q0 + tid < l)  // sample q0 + tid of row group g is red[512 g + tid]
+        part[(int64_t)bid * l + q0 + tid] =
+            (red[tid] + red[512 + tid]) + (red[1024 + tid] + red[1536 + tid]);
     }
   }
 }

@@ -65,9 +65,12 @@ def test_f64_scaling_sqrt2():
     assert np.allclose(np.sum(g["S"] ** 2, axis=0), 2.0, rtol=1e-13)
 
 
+# Gaussian re-sketch: even l (two samples per thread), odd l (one by one)
+# and l above 512 (two sample blocks)
+@pytest.mark.parametrize("n,m,l", [(2 * 4096 + 300, 20, 80), (4096 + 77, 12, 61),
+                                   (3 * 4096 + 5, 16, 600)])
 @pytest.mark.parametrize("panel,outer", [(0, 0), (8, 0), (4, 16)])
-def test_f64_gauss_elementwise(panel, outer):
-    n, m, l = 2 * 4096 + 300, 20, 80
+def test_f64_gauss_elementwise(panel, outer, n, m, l):
     W, Win, g, sk = _run(1, n, m, l, 2, panel=panel, outer=outer)
     ref = orq.rhqr_left(W, sk)
     assert rel(g["R"], ref["R"]) < 1e-12
