@@ -123,7 +123,7 @@ __global__ void k_zero_mat(double *A, int64_t lda, int32_t rows, int32_t cols) {
 // (RHVector with Psi = I, Alg. 2: sigma, rho, gamma, alpha, beta; identity
 // reflector when rho = 0), writes its vectors to S and extends T by the
 // recursion of Prop. 3.2 (T_{:,j} = -beta_j T S^t s_j, in block form per
-// panel).  k_hqr_trail (one wave per trailing column) applies the panel's
+// panel).  k_hqr_trail (one workgroup per trailing column) applies the panel's
 // block reflector, Z <- (I - S_p T_p^t S_p^t) Z.  Every reduction runs in a
 // fixed order.  The same factorization as the column engine with Psi = I,
 // in far fewer launches.
@@ -351,46 +351,51 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
 }
 
 // trailing column k = J + nb + blockIdx.x of panel J: w = S_p^t Z_k,
-// u = T_p^t w, Z_k -= S_p u (rows >= J), with the panel's vectors read from S
-__global__ void __launch_bounds__(64) k_hqr_trail(int32_t L, int32_t m, int32_t J, double *Z,
-                                                  int64_t ldz, const double *S, int64_t lds,
-                                                  const double *T, int64_t ldt) {
+// u = T_p^t w, Z_k -= S_p u (rows >= J), with the panel's vectors read from
+// S.  One workgroup per column: every thread loads its rows (at most
+// SQ_MAXL / TR_TPB) at once, the dot products are summed per wave and then
+// over the waves in a fixed order.
+constexpr int TR_TPB = 256;
+constexpr int TR_RC = SQ_MAXL / TR_TPB;  // rows per thread
+__global__ void __launch_bounds__(TR_TPB) k_hqr_trail(int32_t L, int32_t m, int32_t J, double *Z,
+                                                      int64_t ldz, const double *S, int64_t lds,
+                                                      const double *T, int64_t ldt) {
+  __shared__ double red[TR_TPB / 64][SQ_NB];
   const int nb = m - J < SQ_NB ? m - J : SQ_NB;
-  const int rows = L - J, lane = threadIdx.x;
+  const int rows = L - J, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int k = J + nb + (int)blockIdx.x;
-  if (k >= m) return;
+  if (k >= m) return;  // the whole workgroup
   const double *Sp = S + J + (int64_t)J * lds;  // Sp[r + q * lds]: panel vector q, row J + r
-  double *zk = Z + (int64_t)k * ldz;
-  double d[SQ_NB];
+  double *zk = Z + (int64_t)k * ldz + J;
+  double zr[TR_RC], d[SQ_NB];
 #pragma unroll
   for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
-  // the column's first SQ_RC * 64 rows stay in registers from the dot
-  // products to the update; same order of operations as the streamed rest
-  double zr[SQ_RC];
 #pragma unroll
-  for (int i = 0; i < SQ_RC; ++i) {
-    const int r = lane + 64 * i;
-    zr[i] = r < rows ? zk[J + r] : 0.0;
+  for (int i = 0; i < TR_RC; ++i) {
+    const int r = tid + TR_TPB * i;
+    zr[i] = r < rows ? zk[r] : 0.0;
   }
 #pragma unroll
-  for (int i = 0; i < SQ_RC; ++i) {
-    const int r = lane + 64 * i;
+  for (int i = 0; i < TR_RC; ++i) {
+    const int r = tid + TR_TPB * i;
     if (r < rows) {
 #pragma unroll
       for (int q = 0; q < SQ_NB; ++q)
         if (q < nb) d[q] += Sp[r + (int64_t)q * lds] * zr[i];
     }
   }
-#pragma unroll 4
-  for (int r = lane + 64 * SQ_RC; r < rows; r += 64) {
-    const double zv = zk[J + r];
 #pragma unroll
-    for (int q = 0; q < SQ_NB; ++q)
-      if (q < nb) d[q] += Sp[r + (int64_t)q * lds] * zv;
+  for (int q = 0; q < SQ_NB; ++q) {
+    const double v = wave_sum(d[q]);
+    if (lane == 0) red[w][q] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < SQ_NB; ++q) {
+    static_assert(TR_TPB / 64 == 4, "four partial sums per value");
+    d[q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
   }
   double u[SQ_NB];
-#pragma unroll
-  for (int q = 0; q < SQ_NB; ++q) d[q] = wave_sum(d[q]);
 #pragma unroll
   for (int c = 0; c < SQ_NB; ++c) {
     double t = 0.0;
@@ -400,23 +405,15 @@ __global__ void __launch_bounds__(64) k_hqr_trail(int32_t L, int32_t m, int32_t 
     u[c] = t;
   }
 #pragma unroll
-  for (int i = 0; i < SQ_RC; ++i) {
-    const int r = lane + 64 * i;
+  for (int i = 0; i < TR_RC; ++i) {
+    const int r = tid + TR_TPB * i;
     if (r < rows) {
       double zv = zr[i];
 #pragma unroll
       for (int c = 0; c < SQ_NB; ++c)
         if (c < nb) zv -= Sp[r + (int64_t)c * lds] * u[c];
-      zk[J + r] = zv;
+      zk[r] = zv;
     }
-  }
-#pragma unroll 4
-  for (int r = lane + 64 * SQ_RC; r < rows; r += 64) {
-    double zv = zk[J + r];
-#pragma unroll
-    for (int c = 0; c < SQ_NB; ++c)
-      if (c < nb) zv -= Sp[r + (int64_t)c * lds] * u[c];
-    zk[J + r] = zv;
   }
 }
 
@@ -444,7 +441,7 @@ int sketch_space_hqr(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, d
                          w.status);
       RHQR_HIP(hipGetLastError());
       if (J + nb < m) {
-        hipLaunchKernelGGL(k_hqr_trail, dim3((unsigned)(m - J - nb)), dim3(64), 0, st, L, m, J,
+        hipLaunchKernelGGL(k_hqr_trail, dim3((unsigned)(m - J - nb)), dim3(TR_TPB), 0, st, L, m, J,
                            Zc, (int64_t)L, (const double *)S, lds, (const double *)T, ldt);
         RHQR_HIP(hipGetLastError());
       }
