@@ -495,7 +495,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}): the row-sharded "
-              "multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
+              "multi-GPU path is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
