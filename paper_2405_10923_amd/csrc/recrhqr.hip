@@ -155,6 +155,7 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
   __shared__ double redv[SQ_TPB / 64][SQ_NB];
   __shared__ double gv[SQ_MAXM];
   __shared__ double bet[SQ_NB];
+  __shared__ double Tp[SQ_NB][SQ_NB];  // T_pp (upper triangle), also written to T
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nb = m - J < SQ_NB ? m - J : SQ_NB;
   const int rows = L - J;
@@ -210,6 +211,7 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
     }
     if (tid == 0) {
       bet[c] = beta;
+      Tp[c][c] = beta;
       T[j + (int64_t)j * ldt] = beta;
       if (ident) atomicCAS(status, 0, j + 1);
     }
@@ -267,8 +269,10 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
     __syncthreads();
     if (tid < c) {
       double t = 0.0;
-      for (int q = tid; q < c; ++q) t += T[(J + tid) + (int64_t)(J + q) * ldt] * gv[q];
-      T[(J + tid) + (int64_t)(J + c) * ldt] = -bet[c] * t;
+      for (int q = tid; q < c; ++q) t += Tp[tid][q] * gv[q];
+      const double v = -bet[c] * t;
+      Tp[tid][c] = v;
+      T[(J + tid) + (int64_t)(J + c) * ldt] = v;
     }
     __syncthreads();
   }
@@ -339,7 +343,7 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
         double t = 0.0;
 #pragma unroll
         for (int q = 0; q < SQ_NB; ++q)
-          if (q <= c && c < nb) t += Yl[p * SQ_NB + q] * T[(J + q) + (int64_t)(J + c) * ldt];
+          if (q <= c && c < nb) t += Yl[p * SQ_NB + q] * Tp[q][c];
         o[c] = -t;
       }
 #pragma unroll
