@@ -141,10 +141,34 @@ RHQR_API int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void 
                 int64_t ldr, void *d_Q, int64_t ldq, int opts, void *d_ws,
                 size_t ws_bytes, void *stream);
 
-/* Status of the last rhqr_factor / recrhqr_factor / Arnoldi call that used
- * this workspace: 0, or j (1-based) of the first column with rho_j = 0.
- * Synchronises `stream`. */
+/* Status of the last rhqr_factor / recrhqr_factor call that used this
+ * workspace, in *h_info (host):
+ *    0  every reflector was formed;
+ *    j  (> 0) column j (1-based) was the first with rho_j = 0 (breakdown: the
+ *       column is already eliminated, the reflector is the identity);
+ *   -j  column j was the first whose rho_j or pivot entry y_j is NaN or
+ *       infinite (a non-finite input, or overflow); this takes precedence over
+ *       a breakdown, and every output from column j on is meaningless.
+ * Returns -1 for d_ws NULL, -3 for h_info NULL.  Synchronises `stream`. */
 RHQR_API int rhqr_status(const void *d_ws, void *stream, int32_t *h_info);
+
+/* ------------------------------------------------------------------------
+ * Column scaling for low-precision storage (the mixed-precision experiment of
+ * Sec. 8, where W is held in half precision): before W is rounded to a
+ * narrow type its columns are scaled to unit max-norm, and R is scaled back
+ * afterwards, so that W = Q (R D) for the unscaled W.
+ *   rhqr_colscale: d_scale[j] = max_i |W_ij| (1 for a zero column), computed
+ *     in float64; d_Wout = W D^-1 rounded to dtype (to float32 first, then to
+ *     the 2-byte type, both round-to-nearest-even).  d_W64: n x m float64
+ *     (ldw >= n), read only; d_Wout: n x m in dtype (ldo >= n), may not
+ *     overlap d_W64; d_scale: m float64.  Device pointers; asynchronous.
+ *   rhqr_scale_r: R <- R D, column j of the m x m upper-triangular R (ldr >=
+ *     m) multiplied by d_scale[j].  Device pointers; asynchronous.
+ * ---------------------------------------------------------------------- */
+RHQR_API int rhqr_colscale(int dtype, int64_t n, int32_t m, const double *d_W64, int64_t ldw,
+                           void *d_Wout, int64_t ldo, double *d_scale, void *stream);
+RHQR_API int rhqr_scale_r(int32_t m, double *d_R, int64_t ldr, const double *d_scale,
+                          void *stream);
 
 /* ------------------------------------------------------------------------
  * recrhqr_factor: recRHQR (Alg. 6), one synchronisation.
@@ -224,7 +248,9 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
  *     with the same schedule bitwise (same device code, same choice of
  *     matrix cores or vector units per panel, same reduction orders).
  *   rhqr_batch_status: h_info[i] (host, count entries, caller order) = the
- *     first column of problem i with rho_j = 0 (1-based), or 0.  Synchronous.
+ *     status of problem i as rhqr_status reports it (0; j > 0 for the first
+ *     column with rho_j = 0; -j for the first non-finite column).
+ *     Synchronous.
  * Not in the paper as such: the paper factors one matrix at a time; the batch
  * applies Alg. 4 to each problem independently.
  * ---------------------------------------------------------------------- */
@@ -249,18 +275,43 @@ RHQR_API int rhqr_batch_status(rhqr_batch_t b, void *stream, int32_t *h_info);
 RHQR_API int rhqr_batch_destroy(rhqr_batch_t b);
 
 /* ------------------------------------------------------------------------
- * Measurement aid.  Between rhqr_profile_begin() and rhqr_profile_end(), every
- * launch of the tall kernels of rhqr_factor / recrhqr_factor / the Arnoldi
- * step records a start and an end HIP event from its own dispatch: the
- * per-column refresh + re-sketch pass, and the panel update of the blocked
- * schedule.  rhqr_profile_end synchronises those events and returns, for each
- * of the two kernels, the summed kernel time (ms) and the number of launches
- * (NULL pointers are skipped).  Host-side state, not thread-safe; intended for
- * benchmarks.
+ * Measurement aid (not part of the method).  Between rhqr_profile_begin() and
+ * rhqr_profile_end(), every launch of the kernels listed below records a start
+ * and an end HIP event from its own dispatch, so each duration is that
+ * kernel's own (launch gaps excluded).  Classes:
+ *   RHQR_PROF_TALL        per-column refresh + re-sketch pass (Alg. 4)
+ *   RHQR_PROF_PANEL_MX    panel update of the blocked schedule, matrix cores
+ *   RHQR_PROF_PANEL_VALU  panel update of the blocked schedule, vector units
+ *   RHQR_PROF_PRESKETCH   multi-column sketch Psi X (Alg. 1): the SRHT tile
+ *                         pass or the Gaussian product, without its finish
+ *   RHQR_PROF_RED         per-column reduction of the sketch partials
+ *   RHQR_PROF_FIN         per-column float64 step (RHVector, T, c)
+ *   RHQR_PROF_QTAIL       tail product of the thin Q (Sec. 3.2)
+ *   RHQR_PROF_TRSM        blocked substitution of recRHQR (Alg. 6)
+ *   RHQR_PROF_HQR         sketch-space Householder QR of recRHQR (Alg. 6)
+ * rhqr_profile_end(nclass, h_ms, h_launches) synchronises the recorded events
+ * and writes, for classes 0 .. nclass-1, the summed kernel time in ms
+ * (h_ms[c]) and the number of launches (h_launches[c]); host arrays of nclass
+ * entries, nclass <= RHQR_PROF_NCLASS (0: only close the window).  Returns -1
+ * for a bad nclass, -2 / -3 for a NULL array, RHQR_ERR_HIP if an event
+ * failed.  The window is process-wide and mutex-guarded: launches from every
+ * host thread are collected.  Profiling adds two events per launch; time
+ * work outside the window.
  * ---------------------------------------------------------------------- */
+enum {
+  RHQR_PROF_TALL = 0,
+  RHQR_PROF_PANEL_MX = 1,
+  RHQR_PROF_PANEL_VALU = 2,
+  RHQR_PROF_PRESKETCH = 3,
+  RHQR_PROF_RED = 4,
+  RHQR_PROF_FIN = 5,
+  RHQR_PROF_QTAIL = 6,
+  RHQR_PROF_TRSM = 7,
+  RHQR_PROF_HQR = 8,
+  RHQR_PROF_NCLASS = 9
+};
 RHQR_API int rhqr_profile_begin(void);
-RHQR_API int rhqr_profile_end(double *tall_ms, int64_t *tall_launches, double *panel_ms,
-                              int64_t *panel_launches);
+RHQR_API int rhqr_profile_end(int32_t nclass, double *h_ms, int64_t *h_launches);
 
 #ifdef __cplusplus
 }

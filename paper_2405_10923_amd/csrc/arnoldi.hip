@@ -447,7 +447,9 @@ extern "C" int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const i
                              const double *d_val, const void *d_x, void *d_y, void *stream) {
   if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -1;
   if (n < 1) return -2;
-  if (!d_ptr || !d_idx || !d_val) return -3;
+  if (!d_ptr) return -3;
+  if (!d_idx) return -4;
+  if (!d_val) return -5;
   if (!d_x) return -6;
   if (!d_y) return -7;
   hipStream_t st = (hipStream_t)stream;

@@ -255,7 +255,8 @@ int plan(const rhqr_problem *probs, int32_t count, int dtype, Layout *o) {
 }
 
 int check_problems(const rhqr_problem *probs, int32_t count, int dtype) {
-  if (!probs || count < 1) return -1;
+  if (!probs) return -1;
+  if (count < 1) return -2;
   if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -3;
   for (int32_t i = 0; i < count; ++i) {
     const rhqr_problem &q = probs[i];
@@ -536,10 +537,13 @@ extern "C" int rhqr_batch_status(rhqr_batch_t b, void *stream, int32_t *h_info) 
   if (!b) return -1;
   if (!h_info) return -3;
   hipStream_t st = (hipStream_t)stream;
+  std::vector<int32_t> w(2 * (size_t)b->count, 0);  // per problem: breakdown, non-finite
   for (int s = 0; s < b->count; ++s)
-    RHQR_HIP(hipMemcpyAsync(h_info + b->order[s], b->hp[s].status, sizeof(int32_t),
+    RHQR_HIP(hipMemcpyAsync(&w[2 * (size_t)s], b->hp[s].status, 2 * sizeof(int32_t),
                             hipMemcpyDeviceToHost, st));
   RHQR_HIP(hipStreamSynchronize(st));
+  for (int s = 0; s < b->count; ++s)
+    h_info[b->order[s]] = w[2 * s + 1] ? -w[2 * s + 1] : w[2 * s];
   return RHQR_OK;
 }
 

@@ -704,6 +704,7 @@ __device__ __forceinline__ void red_split_block(const ColProblem &P, int32_t j, 
 struct StepScalars {
   double sigma, rho, alpha, beta, gamma;
   int ident;
+  int nonfinite;  // rho or the pivot entry is NaN or infinite
 };
 
 // ss: the sum of the partial sums of squares (rho^2), yj = y_j
@@ -711,6 +712,7 @@ __device__ __forceinline__ StepScalars step_scalars(double yj, double ss, int sc
   StepScalars r;
   r.rho = sqrt(ss);
   r.sigma = yj >= 0.0 ? 1.0 : -1.0;
+  r.nonfinite = !(isfinite(ss) && isfinite(yj));
   r.ident = !(r.rho > 0.0);
   if (r.ident) {
     r.gamma = 0.0;
@@ -928,6 +930,7 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
       scal[4 * j + 2] = sc.alpha;
       scal[4 * j + 3] = sc.beta;
       if (sc.ident) atomicCAS(status, 0, j + 1);
+      if (sc.nonfinite) atomicCAS(status + 1, 0, j + 1);
     }
   }
   if (bid == 0)

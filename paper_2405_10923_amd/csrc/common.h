@@ -1,6 +1,7 @@
 // Shared definitions of the gfx950 RHQR library (device helpers, handle layout).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_bf16.h>
 #include <stdint.h>
@@ -14,6 +15,26 @@
   do {                                                \
     hipError_t e_ = (x);                              \
     if (e_ != hipSuccess) return RHQR_ERR_HIP;        \
+  } while (0)
+
+// Per-kernel timing (rhqr_profile_begin / rhqr_profile_end).  While profiling
+// is on, prof_events hands out a start and a stop event for one launch of
+// kernel class `cls` (RHQR_PROF_*), which the dispatch itself records
+// (hipExtLaunchKernel), so the time measured is the kernel's own; otherwise it
+// returns null events and the launch is an ordinary one.
+int prof_events(int cls, hipEvent_t *e0, hipEvent_t *e1);
+
+// launch K, timed as class `cls` when profiling is on; returns RHQR_ERR_HIP
+// from the enclosing function if the launch fails
+#define RHQR_LAUNCH(cls, K, grid, block, shm, st, ...)                         \
+  do {                                                                        \
+    hipEvent_t e0_ = nullptr, e1_ = nullptr;                                  \
+    if (prof_events((cls), &e0_, &e1_)) return RHQR_ERR_HIP;                  \
+    if (e0_)                                                                  \
+      hipExtLaunchKernelGGL(K, grid, block, shm, st, e0_, e1_, 0, __VA_ARGS__); \
+    else                                                                      \
+      hipLaunchKernelGGL(K, grid, block, shm, st, __VA_ARGS__);                \
+    RHQR_HIP(hipGetLastError());                                              \
   } while (0)
 
 // Internal sketch kind: Psi = I (used for the sketch-space Householder QR of

@@ -28,34 +28,6 @@
 namespace {
 
 
-// Optional timing of the tall kernels (rhqr_profile_begin / rhqr_profile_end):
-// the dispatch itself records a start and an end event (hipExtLaunchKernel),
-// so the measured time is the kernel's own.  Class 0 = the refresh +
-// re-sketch pass, class 1 = the panel update of the blocked schedule.
-struct TallProfile {
-  bool on = false;
-  std::vector<hipEvent_t> ev;   // pairs (start, stop)
-  std::vector<int> cls;         // class of each pair
-  size_t used = 0;
-};
-TallProfile g_prof;
-
-int prof_pair(hipEvent_t *a, hipEvent_t *b, int cls) {
-  if (g_prof.used + 2 > g_prof.ev.size()) {
-    for (int k = 0; k < 2; ++k) {
-      hipEvent_t e;
-      RHQR_HIP(hipEventCreate(&e));
-      g_prof.ev.push_back(e);
-    }
-  }
-  if (g_prof.cls.size() < g_prof.ev.size() / 2) g_prof.cls.resize(g_prof.ev.size() / 2);
-  *a = g_prof.ev[g_prof.used];
-  *b = g_prof.ev[g_prof.used + 1];
-  g_prof.cls[g_prof.used / 2] = cls;
-  g_prof.used += 2;
-  return RHQR_OK;
-}
-
 // ----------------------------------------------------- single-problem kernels
 template <typename ST, int KIND, int TPW>
 __global__ void __launch_bounds__(TALL_TPB) k_tall(const ColProblem P, int32_t j, int32_t p0) {
@@ -302,7 +274,7 @@ int tall_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int32_t p0, hipStr
   const int tpw = tall_tpw(a.n, sizeof(ST));
   const ColProblem P = make_col_problem(a, w, tpw);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (g_prof.on && prof_pair(&e0, &e1, 0)) return RHQR_ERR_HIP;
+  if (prof_events(RHQR_PROF_TALL, &e0, &e1)) return RHQR_ERR_HIP;
   switch (a.kind) {
     case RHQR_SKETCH_SRHT: launch_tall_k<ST, RHQR_SKETCH_SRHT>(P, j, p0, tpw, st, e0, e1); break;
     case RHQR_SKETCH_GAUSS: launch_tall_k<ST, RHQR_SKETCH_GAUSS>(P, j, p0, tpw, st, e0, e1); break;
@@ -316,14 +288,12 @@ template <typename ST>
 int step_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st) {
   const ColProblem P = make_col_problem(a, w, tall_tpw(a.n, sizeof(ST)));
   if (a.kind == RHQR_SKETCH_IDENT)
-    hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_IDENT>), dim3(red_splits(j), P.gred), dim3(1024), 0,
-                       st, P, j, next);
+    RHQR_LAUNCH(RHQR_PROF_RED, (k_red<ST, RHQR_SKETCH_IDENT>), dim3(red_splits(j), P.gred),
+                dim3(1024), 0, st, P, j, next);
   else
-    hipLaunchKernelGGL((k_red<ST, RHQR_SKETCH_SRHT>), dim3(red_splits(j), P.gred), dim3(1024), 0,
-                       st, P, j, next);
-  RHQR_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_fin, dim3(fin_groups(j)), dim3(1024), 0, st, P, j, next);
-  RHQR_HIP(hipGetLastError());
+    RHQR_LAUNCH(RHQR_PROF_RED, (k_red<ST, RHQR_SKETCH_SRHT>), dim3(red_splits(j), P.gred),
+                dim3(1024), 0, st, P, j, next);
+  RHQR_LAUNCH(RHQR_PROF_FIN, k_fin, dim3(fin_groups(j)), dim3(1024), 0, st, P, j, next);
   return RHQR_OK;
 }
 
@@ -859,8 +829,9 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, 
     RHQR_HIP(hipGetLastError());
     if (ntail == 0) return RHQR_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (g_prof.on && prof_pair(&e0, &e1, 1)) return RHQR_ERR_HIP;
     const int aligned = ((uintptr_t)W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
+    const bool mx = aligned && nb > PX_MIN_NB;
+    if (prof_events(mx ? RHQR_PROF_PANEL_MX : RHQR_PROF_PANEL_VALU, &e0, &e1)) return RHQR_ERR_HIP;
     int rc = RHQR_OK;
     if (aligned && nb > PX_MIN_NB && nb <= 16) {
       rc = launch_panel_mx<ST, 16>(W, a.ldw, a.n, m, K0, J, nb, pw, (const double *)C, st, e0, e1);
@@ -959,17 +930,16 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
       RHQR_HIP(hipGetLastError());
       const int64_t groups = panel_mx_groups(n, m, (int)sizeof(ST));
       const dim3 grid((unsigned)((groups + 7) / 8 * 8 * tiles));
-      hipLaunchKernelGGL((k_qtail_mx<ST>), grid, dim3(PX_WAVES * 64), 0, st, n, m, U, ldu,
-                         (const double *)Ct, Q, ldq, groups, tiles);
-      RHQR_HIP(hipGetLastError());
+      RHQR_LAUNCH(RHQR_PROF_QTAIL, (k_qtail_mx<ST>), grid, dim3(PX_WAVES * 64), 0, st, n, m, U,
+                  ldu, (const double *)Ct, Q, ldq, groups, tiles);
       return RHQR_OK;
     }
   }
   if (rows > 0) {
     if constexpr (std::is_same<ST, double>::value) {
       dim3 grid((unsigned)((rows + 63) / 64), (m + QF_NC - 1) / QF_NC);
-      hipLaunchKernelGGL(k_qtail64, grid, dim3(256), 0, st, U + m, ldu, rows, m,
-                         (const double *)Mq, Q + m, ldq);
+      RHQR_LAUNCH(RHQR_PROF_QTAIL, k_qtail64, grid, dim3(256), 0, st, U + m, ldu, rows, m,
+                  (const double *)Mq, Q + m, ldq);
     } else if constexpr (sizeof(ST) == 2) {
       const int Kp = (m + PM_KP - 1) / PM_KP * PM_KP;
       const int tiles = (m + QH_NC - 1) / QH_NC;
@@ -985,13 +955,13 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
       const int64_t waves = (rows + PM_ROWS - 1) / PM_ROWS;
       const int64_t blks = (waves + QS_WAVES - 1) / QS_WAVES;
       const dim3 grid((unsigned)((blks + 7) / 8 * 8 * tiles));
-      hipLaunchKernelGGL((k_qtail16<ST>), grid, dim3(QS_WAVES * 64), 0, st, U + m, ldu, rows, m, Kp,
-                         (const unsigned short *)Bh, (const unsigned short *)Bl,
-                         (const float *)sc, Q + m, ldq, aligned, tiles);
+      RHQR_LAUNCH(RHQR_PROF_QTAIL, (k_qtail16<ST>), grid, dim3(QS_WAVES * 64), 0, st, U + m, ldu,
+                  rows, m, Kp, (const unsigned short *)Bh, (const unsigned short *)Bl,
+                  (const float *)sc, Q + m, ldq, aligned, tiles);
     } else {
       dim3 grid((rows + 63) / 64, (m + 63) / 64);
-      hipLaunchKernelGGL((k_gemm_tall<ST>), grid, dim3(256), 0, st, U, ldu, (int64_t)m, n, m,
-                         (const double *)Mq, (int64_t)m, m, Q, ldq, -1.0);
+      RHQR_LAUNCH(RHQR_PROF_QTAIL, (k_gemm_tall<ST>), grid, dim3(256), 0, st, U, ldu, (int64_t)m,
+                  n, m, (const double *)Mq, (int64_t)m, m, Q, ldq, -1.0);
     }
     RHQR_HIP(hipGetLastError());
   }
@@ -1017,9 +987,8 @@ int trsm_blocked_typed(const ST *B, int64_t ldb, int64_t rows, int32_t m, const 
     hipLaunchKernelGGL(k_trsm_coef, dim3((kmax + 255) / 256, TRSM_NB), dim3(256), 0, st, J, nb, M,
                        ldm, Ct, Md);
     RHQR_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_trsm_blk<ST>), grid, dim3(PANEL_TPB), 0, st, B, ldb, X, ldx, stage, rows,
-                       J, nb, (const double *)Ct, (const double *)Md, aligned);
-    RHQR_HIP(hipGetLastError());
+    RHQR_LAUNCH(RHQR_PROF_TRSM, (k_trsm_blk<ST>), grid, dim3(PANEL_TPB), 0, st, B, ldb, X, ldx,
+                stage, rows, J, nb, (const double *)Ct, (const double *)Md, aligned);
   }
   return RHQR_OK;
 }
@@ -1219,31 +1188,4 @@ int launch_thin_q(int dtype, int64_t n, int32_t m, const void *U, int64_t ldu, c
                                           qmf, (__hip_bfloat16 *)Q, ldq, st);
   }
   return RHQR_ERR_UNSUPPORTED;
-}
-
-extern "C" int rhqr_profile_begin(void) {
-  g_prof.on = true;
-  g_prof.used = 0;
-  return RHQR_OK;
-}
-
-extern "C" int rhqr_profile_end(double *tall_ms, int64_t *tall_launches, double *panel_ms,
-                                int64_t *panel_launches) {
-  g_prof.on = false;
-  double tot[2] = {0.0, 0.0};
-  int64_t cnt[2] = {0, 0};
-  for (size_t k = 0; k + 1 < g_prof.used; k += 2) {
-    RHQR_HIP(hipEventSynchronize(g_prof.ev[k + 1]));
-    float ms = 0.f;
-    RHQR_HIP(hipEventElapsedTime(&ms, g_prof.ev[k], g_prof.ev[k + 1]));
-    const int c = g_prof.cls[k / 2] ? 1 : 0;
-    tot[c] += ms;
-    cnt[c] += 1;
-  }
-  if (tall_ms) *tall_ms = tot[0];
-  if (tall_launches) *tall_launches = cnt[0];
-  if (panel_ms) *panel_ms = tot[1];
-  if (panel_launches) *panel_launches = cnt[1];
-  g_prof.used = 0;
-  return RHQR_OK;
 }

@@ -133,7 +133,9 @@ extern "C" int rhqr_status(const void *d_ws, void *stream, int32_t *h_info) {
   if (!d_ws) return -1;
   if (!h_info) return -3;
   hipStream_t st = (hipStream_t)stream;
-  RHQR_HIP(hipMemcpyAsync(h_info, d_ws, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  int32_t w[2] = {0, 0};  // first breakdown, first non-finite column (1-based)
+  RHQR_HIP(hipMemcpyAsync(w, d_ws, sizeof(w), hipMemcpyDeviceToHost, st));
   RHQR_HIP(hipStreamSynchronize(st));
+  *h_info = w[1] ? -w[1] : w[0];
   return RHQR_OK;
 }

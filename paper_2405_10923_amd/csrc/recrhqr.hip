@@ -214,6 +214,7 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
       Tp[c][c] = beta;
       T[j + (int64_t)j * ldt] = beta;
       if (ident) atomicCAS(status, 0, j + 1);
+      if (!(isfinite(ss) && isfinite(yj))) atomicCAS(status + 1, 0, j + 1);
     }
     __syncthreads();
     // H_j = I - beta s_j s_j^t on the panel's later columns (rows >= j)
@@ -440,14 +441,11 @@ int sketch_space_hqr(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, d
     }
     for (int32_t J = 0; J < m; J += SQ_NB) {
       const int32_t nb = m - J < SQ_NB ? m - J : SQ_NB;
-      hipLaunchKernelGGL(k_hqr_panel, dim3(1), dim3(SQ_TPB), lds_bytes, st, L, m, J, Zc,
-                         (int64_t)L, S, lds, T, ldt, R, ldr, (int)RHQR_SCALE_UNIT_PIVOT,
-                         w.status);
-      RHQR_HIP(hipGetLastError());
+      RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_panel, dim3(1), dim3(SQ_TPB), lds_bytes, st, L, m, J, Zc,
+                  (int64_t)L, S, lds, T, ldt, R, ldr, (int)RHQR_SCALE_UNIT_PIVOT, w.status);
       if (J + nb < m) {
-        hipLaunchKernelGGL(k_hqr_trail, dim3((unsigned)(m - J - nb)), dim3(TR_TPB), 0, st, L, m, J,
-                           Zc, (int64_t)L, (const double *)S, lds, (const double *)T, ldt);
-        RHQR_HIP(hipGetLastError());
+        RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_trail, dim3((unsigned)(m - J - nb)), dim3(TR_TPB), 0, st,
+                    L, m, J, Zc, (int64_t)L, (const double *)S, lds, (const double *)T, ldt);
       }
     }
     return RHQR_OK;

@@ -324,9 +324,9 @@ int launch_typed(const rhqr_sketch_s *h, int64_t n, int32_t k, const ST *X, int6
     // samples per thread: ceil(l / SK_TPB), rounded up to a power of two (l <= TILE)
     static_assert(8 * SK_TPB >= TILE, "at most 8 samples per thread");
     const int qa = l <= SK_TPB ? 1 : l <= 2 * SK_TPB ? 2 : l <= 4 * SK_TPB ? 4 : 8;
-#define RHQR_SRHT_COLS(Q)                                                                       \
-  hipLaunchKernelGGL((k_srht_cols<ST, CT, Q>), dim3(gt, k), dim3(SK_TPB), 0, st, X, ldx, n, m, \
-                     l, ngroups, gt, h->d_signs, h->d_rows, part, aligned)
+#define RHQR_SRHT_COLS(Q)                                                                    \
+  RHQR_LAUNCH(RHQR_PROF_PRESKETCH, (k_srht_cols<ST, CT, Q>), dim3(gt, k), dim3(SK_TPB), 0, st, X, \
+              ldx, n, m, l, ngroups, gt, h->d_signs, h->d_rows, part, aligned)
     switch (qa) {
       case 1: RHQR_SRHT_COLS(1); break;
       case 2: RHQR_SRHT_COLS(2); break;
@@ -340,9 +340,8 @@ int launch_typed(const rhqr_sketch_s *h, int64_t n, int32_t k, const ST *X, int6
     const int64_t ntail = n - m;
     const int64_t kchunk = ((ntail + gt - 1) / gt + GMK - 1) / GMK * GMK;
     dim3 grid((l + GM - 1) / GM, (k + GN - 1) / GN, gt);
-    hipLaunchKernelGGL((k_gauss_mx<ST, CT>), grid, dim3(256), 0, st, h->d_omega, (int64_t)l, X,
-                       ldx, m, ntail, l, k, kchunk, part);
-    RHQR_HIP(hipGetLastError());
+    RHQR_LAUNCH(RHQR_PROF_PRESKETCH, (k_gauss_mx<ST, CT>), grid, dim3(256), 0, st, h->d_omega,
+                (int64_t)l, X, ldx, m, ntail, l, k, kchunk, part);
     launch_finish<ST>(X, ldx, m, l, k, gt, part, 1.0, Y, ldy, st);
   }
   RHQR_HIP(hipGetLastError());

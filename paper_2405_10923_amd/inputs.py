@@ -10,8 +10,6 @@ factorization's arithmetic.
 * ``cm_matrix``: the parametric-function matrix C_m of Sec. 8,
   C_{i,j} = f((i-1)/(n-1), (j-1)/(m-1)), f(x, mu) = sin(10(mu+x)) /
   (cos(100(mu-x)) + 1.1).
-* ``unit_max_scale``: the column scaling that maps each column to max-abs 1
-  before the matrix is rounded to a low-precision type.
 * ``convdiff_csr``: a 5-point upwind convection-diffusion operator in CSR
   form (the sparse operator of the GMRES workload).
 """
@@ -64,14 +62,6 @@ def cm_matrix(n, m):
     mu = np.arange(m) / (m - 1)
     X, MU = np.meshgrid(x, mu, indexing="ij")
     return np.asfortranarray(np.sin(10 * (MU + X)) / (np.cos(100 * (MU - X)) + 1.1))
-
-
-def unit_max_scale(W):
-    """Column scales d_j = max_i |W_ij| (1 for a zero column)."""
-    W = np.asarray(W)
-    d = np.max(np.abs(W), axis=0)
-    d[d == 0] = 1.0
-    return d
 
 
 def convdiff_csr(nx, peclet=10.0):

@@ -17,6 +17,7 @@ F64, F32, F16, BF16 = 0, 1, 2, 3
 SRHT, GAUSS = 0, 1
 SCALE_UNIT_PIVOT, SCALE_SQRT2 = 0, 1
 REC_M, REC_RCHOL = 0, 1
+RHQR_OK, RHQR_ERR_HIP, RHQR_ERR_WORKSPACE, RHQR_ERR_UNSUPPORTED = 0, -1000, -1001, -1002
 
 _lib = None
 
@@ -49,9 +50,10 @@ _SIGS = {
     "rhqr_batch_factor": (C.c_int, [_vp, C.c_int, _vp]),
     "rhqr_batch_status": (C.c_int, [_vp, _vp, _vp]),
     "rhqr_batch_destroy": (C.c_int, [_vp]),
+    "rhqr_colscale": (C.c_int, [C.c_int, _i64, _i32, _vp, _i64, _vp, _i64, _vp, _vp]),
+    "rhqr_scale_r": (C.c_int, [_i32, _vp, _i64, _vp, _vp]),
     "rhqr_profile_begin": (C.c_int, []),
-    "rhqr_profile_end": (C.c_int, [C.POINTER(C.c_double), C.POINTER(_i64),
-                                   C.POINTER(C.c_double), C.POINTER(_i64)]),
+    "rhqr_profile_end": (C.c_int, [_i32, _vp, _vp]),
 }
 
 
@@ -223,6 +225,28 @@ def factor(sk, W, scaling=SCALE_UNIT_PIVOT, want_q=False, bufs=None, panel=0, ou
     return dict(U=W, S=bufs.S, T=bufs.T, R=bufs.R, Q=Q, ws=bufs.ws)
 
 
+def colscale(W64, dtype, out=None, scale=None):
+    """Unit max-norm column scaling of a float64 W (n x m, column-major, GPU)
+    rounded to ``dtype`` (rhqr_colscale).  Returns (W D^-1 in dtype, d)."""
+    torch = _torch()
+    n, m = W64.shape
+    if out is None:
+        out = colmajor_empty(n, m, dtype, W64.device)
+    if scale is None:
+        scale = torch.empty(m, dtype=torch.float64, device=W64.device)
+    rc = lib().rhqr_colscale(dtype_code(dtype), n, m, _ptr(W64), _ld(W64), _ptr(out), _ld(out),
+                             _ptr(scale), _stream())
+    _check(rc, "rhqr_colscale")
+    return out, scale
+
+
+def scale_r(R, scale):
+    """R <- R D in place (rhqr_scale_r)."""
+    m = R.shape[0]
+    _check(lib().rhqr_scale_r(m, _ptr(R), _ld(R), _ptr(scale), _stream()), "rhqr_scale_r")
+    return R
+
+
 def status(ws):
     info = C.c_int32()
     _check(lib().rhqr_status(_ptr(ws), _stream(), C.byref(info)), "rhqr_status")
@@ -320,15 +344,20 @@ def profile_begin():
     _check(lib().rhqr_profile_begin(), "rhqr_profile_begin")
 
 
+# kernel classes of rhqr_profile_end, in the order of RHQR_PROF_*
+PROF_CLASSES = ("tall", "panel_mx", "panel_valu", "presketch", "red", "fin", "qtail", "trsm",
+                "hqr")
+
+
 def profile_end():
-    """Summed duration (ms) and launch count of the refresh + re-sketch kernel
-    and of the panel-update kernel since profile_begin(), measured with HIP
-    events on the launching stream: ((tall_ms, tall_n), (panel_ms, panel_n))."""
-    ms0, ms1 = C.c_double(), C.c_double()
-    n0, n1 = C.c_int64(), C.c_int64()
-    _check(lib().rhqr_profile_end(C.byref(ms0), C.byref(n0), C.byref(ms1), C.byref(n1)),
-           "rhqr_profile_end")
-    return (ms0.value, n0.value), (ms1.value, n1.value)
+    """Summed kernel time (ms) and launch count per kernel class since
+    profile_begin(), from HIP events recorded by each dispatch:
+    {class name: (ms, launches)}."""
+    k = len(PROF_CLASSES)
+    ms = (C.c_double * k)()
+    cnt = (C.c_int64 * k)()
+    _check(lib().rhqr_profile_end(k, ms, cnt), "rhqr_profile_end")
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(PROF_CLASSES)}
 
 
 class CSR:

@@ -186,3 +186,39 @@ def test_c5_gmres_fullsize(dt):
         f"cycle residuals {[f'{v:.1e}' for v in h[::10]]}")
     assert res <= 1e-6
     assert len(h) <= (len(h64) + 10 if dt == "float32" else 2 * len(h64))
+
+
+def test_c2_recrhqr_against_oracle_metrics():
+    """recRHQR at 2^20 x 128, cond 1e12, SRHT l = 512: the oracle's own
+    recRHQR runs on the host and both factorizations are measured the same
+    way (e_fact in float64, e_orth of Psi Q from the returned Q with the
+    oracle's Psi, cond(Q)).  At cond 1e12 the two Q differ element-wise by
+    about cond(W) u, so the comparison is of the metrics: e_fact within the
+    float64 tolerance on both sides; the sketch orthogonality, which recRHQR
+    loses in proportion to cond(W) u (Sec. 8, Fig. reconstruct32), of the
+    same order on both sides; cond(Q) equal to a few digits."""
+    torch = cuda_or_skip()
+    from oracle import rhqr as orq
+    from paper_2405_10923_amd import rhqr
+    from paper_2405_10923_amd.inputs import synthetic_matrix
+    from tests.gpu_util import psi_apply_torch, cond_gram, orth_err
+    n, m, l = 1 << 20, 128, 512
+    Wn = synthetic_matrix(n, m, 12, seed=0)
+    W = torch.from_numpy(Wn).cuda()
+    osketch = osk.Sketch(osk.SRHT, n, m, l, seed=0)
+    sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=0)
+    out = rhqr.recrhqr(sk, W, mode=rhqr.REC_M, want_q=True)
+    torch.cuda.synchronize()
+    ref = orq.rec_rhqr(Wn, osketch, "M")
+    Qo = torch.from_numpy(ref["Q"]).cuda()
+    Ro = torch.from_numpy(ref["R"]).cuda()
+    res = {}
+    for name, Q, R in (("gpu", out["Q"], out["R"]), ("oracle", Qo, Ro)):
+        ef = float(torch.linalg.norm(W - Q @ R) / torch.linalg.norm(W))
+        eo = orth_err(psi_apply_torch(osketch, Q))
+        res[name] = (ef, eo, cond_gram(Q))
+    log(f"c2 recRHQR gpu (e_fact, e_orth, cond Q) = {res['gpu']}, oracle = {res['oracle']}")
+    (ef, eo, cq), (ef_o, eo_o, cq_o) = res["gpu"], res["oracle"]
+    assert ef <= TOL and ef_o <= TOL
+    assert eo <= 1e12 * m * 2.0 ** -53 and 0.1 < eo / eo_o < 10.0
+    assert abs(cq - cq_o) <= 1e-3 * cq_o

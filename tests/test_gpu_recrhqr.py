@@ -78,3 +78,16 @@ def test_rec_low_precision(dt, tol):
     eo = metrics.orth_error(osk.rh_sketch(g["Q"], sk))
     log(f"rec {dt}: e_fact {ef:.2e} e_orth {eo:.2e}")
     assert ef < tol and eo < tol
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_rec_psi_identity_fallback_elementwise(mode):
+    """l + 2m > 2048: the sketch-space QR runs the column engine with Psi = I
+    instead of the panel kernels (the path C_m with m = 600 takes)."""
+    n, m, l = 8192, 64, 2000
+    log(f"recrhqr fallback mode={mode} n={n} m={m} l={l} (l + 2m = {l + 2 * m})")
+    W, Win, g, sk = _rec(n, m, l, 3, mode)
+    ref = orq.rec_rhqr(W, sk, "M" if mode == 0 else "R")
+    keys = ("S", "T", "R", "U", "Q") if mode == 0 else ("S", "T", "R", "Q")
+    for k in keys:
+        assert rel(g[k], ref[k]) < 1e-12, k

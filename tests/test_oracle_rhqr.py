@@ -198,3 +198,28 @@ def test_column_scale_equivariance():
     b = rhqr.rhqr_left(W * d, sk)
     assert np.array_equal(a["U"], b["U"]) and np.array_equal(a["T"], b["T"])
     assert np.array_equal(a["R"] * d, b["R"])
+
+
+def test_cm_stress_input_claims():
+    """The paper's stress input C_600 (Sec. 8; numerically singular from about
+    its 500th column), SRHT l = 4096: RHQR keeps Psi Q numerically orthogonal
+    and the factorization accurate (Figs. perf64), cond(Q) small; recRHQR's
+    basis has cond(Q) < 5 and is better conditioned than randomized Cholesky
+    QR's on the same sketch (Fig. reconstruct32)."""
+    from oracle import metrics
+    from paper_2405_10923_amd.inputs import cm_matrix
+    n, m, l = 50000, 600, 4096
+    W = cm_matrix(n, m)
+    assert metrics.cond(W) > 1e15                        # numerically singular
+    sk = sketch.Sketch(sketch.SRHT, n, m, l, seed=0)
+    r = rhqr.rhqr_left(W, sk)
+    Q = rhqr.thin_q(r["U"], r["T"], m)
+    assert r["info"] == 0
+    assert metrics.fact_error(W, Q, r["R"]) < 1e-14
+    assert metrics.orth_error(sketch.rh_sketch(Q, sk)) < 1e-13
+    assert metrics.cond(Q) < 2.5
+    rec = rhqr.rec_rhqr(W, sk, "M")
+    rch = rhqr.rec_rhqr(W, sk, "R")
+    c_rec, c_rch = metrics.cond(rec["Q"]), metrics.cond(rch["Q"])
+    assert metrics.fact_error(W, rec["Q"], rec["R"]) < 1e-14
+    assert c_rec < 5.0 and c_rec < c_rch

@@ -103,3 +103,19 @@ def test_psi_is_an_epsilon_embedding_of_a_range(kind):
     sk = sketch.Sketch(kind, n, m, l, seed=1)
     eps = metrics.embedding_distortion(lambda X: sketch.rh_sketch(X, sk), W)
     assert eps < 0.6
+
+
+def test_embedding_distortion_pins():
+    """epsilon of the embedding definition (Sec. 2.3) on range(W): 0 for the
+    identity whatever basis spans the range (so a missing orthonormalisation
+    of W fails), |c - 1| for x -> c x, and max(a - 1, 1 - b) for a diagonal map
+    with gains a >= b on the coordinate axes spanning the range."""
+    rng = np.random.default_rng(0)
+    W = np.zeros((50, 2))
+    W[0, 0], W[1, 1] = 1.0, 3.0                      # not orthonormal
+    assert metrics.embedding_distortion(lambda X: X, W) == pytest.approx(0.0, abs=1e-15)
+    G = rng.standard_normal((40, 5))
+    assert metrics.embedding_distortion(lambda X: 1.25 * X, G) == pytest.approx(0.25, abs=1e-14)
+    D = np.ones(50)
+    D[0], D[1] = 1.5, 0.6
+    assert metrics.embedding_distortion(lambda X: D[:, None] * X, W) == pytest.approx(0.5, abs=1e-14)
