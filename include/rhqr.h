@@ -153,6 +153,30 @@ RHQR_API int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void 
 RHQR_API int rhqr_status(const void *d_ws, void *stream, int32_t *h_info);
 
 /* ------------------------------------------------------------------------
+ * rhqr_rgs_factor: BLAS2-RGS (Alg. 9, Sec. 6), randomized Gram-Schmidt
+ * obtained as left-looking RHQR of [0_{m x m}; W] with Psi = [I_m 0; 0 Omega]
+ * and Omega applied to the n rows of W.  The head of every refreshed column
+ * below its pivot is exactly zero, so the pivot sign is never flipped and
+ * the Householder vectors are [e_j; q_j].
+ *   h     : sketch handle with n + m rows and head m (its Omega acts on W)
+ *   d_W   : n x m in dtype (ldw >= n), read only
+ *   d_Q   : (n+m) x m in dtype (ldq >= n + m): rows m .. n+m-1 receive Q
+ *           (Omega Q orthonormal, W = Q R), rows 0 .. m-1 receive I_m
+ *   d_S   : (l+m) x m float64: [I_m; Omega Q]
+ *   d_T   : m x m float64, unit upper triangular (I_m in exact arithmetic)
+ *   d_R   : m x m float64, upper triangular with diagonal rho_j > 0
+ *   opts  : the schedule bits of rhqr_factor (scaling must be UNIT_PIVOT)
+ *   d_ws  : rhqr_rgs_workspace_size(h, dtype, m) bytes
+ * Alg. 9's optional last line (Q <- Q T) is not applied.  Breakdown and
+ * non-finite columns are reported by rhqr_status as for rhqr_factor.
+ * ---------------------------------------------------------------------- */
+RHQR_API size_t rhqr_rgs_workspace_size(rhqr_sketch_t h, int dtype, int32_t m);
+RHQR_API int rhqr_rgs_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, const void *d_W,
+                             int64_t ldw, void *d_Q, int64_t ldq, double *d_S, int64_t lds,
+                             double *d_T, int64_t ldt, double *d_R, int64_t ldr, int opts,
+                             void *d_ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Column scaling for low-precision storage (the mixed-precision experiment of
  * Sec. 8, where W is held in half precision): before W is rounded to a
  * narrow type its columns are scaled to unit max-norm, and R is scaled back
@@ -188,7 +212,8 @@ RHQR_API int recrhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, co
  * RHQR-Arnoldi (Alg. 7, Sec. 5).  The operator stays with the caller.
  *   rhqr_arnoldi_create: state for up to mmax Arnoldi steps; the sketch handle
  *     must have head m = mmax + 1 (the loop forms mmax + 1 reflectors).  The
- *     state owns its device memory (basis U, n x (mmax+1) in dtype, S, T, H).
+ *     state owns its device memory (basis U, n x (mmax+1) in dtype, S, T, H,
+ *     and the n-vectors of the GMRES driver below).
  *   rhqr_arnoldi_start(r0): r0 = b - A x0 (n, dtype, device).  Forms u_1 from
  *     r0 and its sketch, writes q_1 (n, dtype, device) and, on the host,
  *     beta = (h_0)_1 = -sigma_1 rho_1 so that r0 = beta q_1.  Synchronous.
@@ -203,6 +228,29 @@ RHQR_API int recrhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, co
  *     Householder vectors are the head rows of S), S ((l+mmax+1) x (mmax+1),
  *     ld l+mmax+1) and T ((mmax+1) x (mmax+1), ld mmax+1).  The most recent
  *     column of U is stored before its division by alpha.
+ *   rhqr_arnoldi_solve_ls(j, y, res): the small least-squares problem of
+ *     Alg. 8 and of the proposition after it, min_y ||beta e_1 - H y||_2 with
+ *     H the (j+1) x j upper Hessenberg matrix [h_1 .. h_j] of the steps taken
+ *     and beta = (h_0)_1 = -sigma_1 rho_1 from rhqr_arnoldi_start, solved on
+ *     the device in float64 by Givens rotations and back substitution.
+ *     d_y: j float64 (device) receives y; d_res: optional (NULL to skip) one
+ *     float64 (device) receiving the minimal residual |(Q^t beta e_1)_{j+1}|,
+ *     which equals ||Psi (r_0 - A Q_j y)|| (the sketched GMRES residual).
+ *     1 <= j <= number of steps taken (-2 otherwise).  Asynchronous.
+ *   rhqr_gmres_csr: restarted RHQR-GMRES(mmax) (Alg. 8) on a CSR operator,
+ *     run entirely by the library on the handle's basis and vectors: per
+ *     cycle r = b - A x in float64 (rounded to dtype for the basis), the
+ *     Arnoldi process of mmax steps (Alg. 7), rhqr_arnoldi_solve_ls, and
+ *     x += Q y accumulated in float64; the true relative residual
+ *     ||b - A x|| / ||b|| is recomputed in float64 after every cycle and the
+ *     iteration stops once it is <= tol or after max_cycles cycles.
+ *     d_ptr, d_idx, d_val: the CSR operator as for rhqr_spmv_csr (n = the
+ *     handle's n); d_b: n float64; d_x: n float64, x_0 on entry, the solution
+ *     on return.  h_hist: optional host array of max_cycles doubles receiving
+ *     the relative residual after each cycle; h_cycles, h_steps: optional
+ *     host outputs (cycles run, Arnoldi steps taken).  Synchronises `stream`
+ *     once per cycle (the convergence test).  Returns -7 for tol < 0 or NaN,
+ *     -8 for max_cycles < 1.
  * rhqr_spmv_csr: y = A x for A in CSR (row pointers int64, column indices
  *   int32, values float64; n rows), x and y in dtype, float64 accumulation.
  *   Device pointers; asynchronous.
@@ -217,6 +265,12 @@ RHQR_API int rhqr_arnoldi_step(rhqr_arnoldi_t a, const void *d_w, void *d_qnext,
 RHQR_API int rhqr_arnoldi_solution(rhqr_arnoldi_t a, int32_t j, const double *d_y, void *d_x,
                           void *stream);
 RHQR_API int rhqr_arnoldi_basis(rhqr_arnoldi_t a, void **d_U, double **d_S, double **d_T);
+RHQR_API int rhqr_arnoldi_solve_ls(rhqr_arnoldi_t a, int32_t j, double *d_y, double *d_res,
+                                   void *stream);
+RHQR_API int rhqr_gmres_csr(rhqr_arnoldi_t a, const int64_t *d_ptr, const int32_t *d_idx,
+                            const double *d_val, const double *d_b, double *d_x, double tol,
+                            int32_t max_cycles, double *h_hist, int32_t *h_cycles,
+                            int64_t *h_steps, void *stream);
 RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int32_t *d_idx,
                   const double *d_val, const void *d_x, void *d_y, void *stream);
 

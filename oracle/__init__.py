@@ -17,5 +17,6 @@ algorithms in float64, written for checking by eye against the paper:
   RHQR (Alg. 4), deterministic Householder QR (Sec. 2.2), the thin Q factor
   (Sec. 3.2), recRHQR (Alg. 6) and its Randomized-Cholesky-QR variant.
 * ``arnoldi`` -- RHQR-Arnoldi (Alg. 7) and RHQR-GMRES (Alg. 8).
+* ``rgs``     -- BLAS2-RGS (Alg. 9) and plain randomized Gram-Schmidt.
 * ``metrics`` -- factorization error, sketch orthogonality, condition numbers.
 """

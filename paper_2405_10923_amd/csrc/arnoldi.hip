@@ -13,6 +13,8 @@
 
 #include <cmath>
 
+constexpr int NORM_BLOCKS = 1024;  // workgroups of the residual-norm reduction
+
 struct rhqr_arnoldi_s {
   rhqr_sketch_s *h;
   int dtype;
@@ -21,7 +23,13 @@ struct rhqr_arnoldi_s {
   int32_t nc;  // reflectors formed
   void *U;     // n x k, dtype (tail rows of the Householder vectors)
   double *S, *T, *R, *Z, *g, *gf;
+  double *Hs;       // k x k: rotated copy of H for the least-squares solve
+  double *lsres;    // least-squares residual of the last solve
+  double *r64;      // n: float64 residual b - A x (GMRES driver)
+  double *npart;    // norm partial sums (GMRES driver)
+  void *vr, *vq0, *vq1, *vw;  // n each, basis type: residual, q_j, q_{j+1}, A q_j
   void *ws;
+  void *vec;
   LoopWs lw;
   void *skws;
   size_t skws_bytes;
@@ -260,11 +268,25 @@ extern "C" int rhqr_arnoldi_create(rhqr_sketch_t h, int dtype, int64_t n, int32_
   bytes += align_up(sizeof(double) * (size_t)L * kh);
   const size_t offg = bytes;
   bytes += 2 * align_up(sizeof(double) * (size_t)kh);
+  const size_t offH = bytes;
+  bytes += align_up(sizeof(double) * (size_t)kh * kh);
+  const size_t offres = bytes;
+  bytes += align_up(sizeof(double) * 4);
+  const size_t offnp = bytes;
+  bytes += align_up(sizeof(double) * NORM_BLOCKS);
   if (hipMalloc(&a->ws, bytes) != hipSuccess) {
     delete a;
     return RHQR_ERR_HIP;
   }
+  // vectors of the GMRES driver: r (float64) and four basis-type vectors
+  const size_t vb = align_up((size_t)n * es);
+  if (hipMalloc(&a->vec, align_up(sizeof(double) * (size_t)n) + 4 * vb) != hipSuccess) {
+    (void)hipFree(a->ws);
+    delete a;
+    return RHQR_ERR_HIP;
+  }
   if (hipMalloc(&a->U, (size_t)n * kh * es) != hipSuccess) {
+    (void)hipFree(a->vec);
     (void)hipFree(a->ws);
     delete a;
     return RHQR_ERR_HIP;
@@ -278,6 +300,16 @@ extern "C" int rhqr_arnoldi_create(rhqr_sketch_t h, int dtype, int64_t n, int32_
   a->Z = (double *)(base + offZ);
   a->g = (double *)(base + offg);
   a->gf = (double *)(base + offg + align_up(sizeof(double) * (size_t)kh));
+  a->Hs = (double *)(base + offH);
+  a->lsres = (double *)(base + offres);
+  a->npart = (double *)(base + offnp);
+  char *vbase = (char *)a->vec;
+  a->r64 = (double *)vbase;
+  vbase += align_up(sizeof(double) * (size_t)n);
+  a->vr = vbase;
+  a->vq0 = vbase + vb;
+  a->vq1 = vbase + 2 * vb;
+  a->vw = vbase + 3 * vb;
   LoopArgs &la = a->la;
   la.kind = h->kind;
   la.dtype = dtype;
@@ -317,6 +349,7 @@ extern "C" int rhqr_arnoldi_destroy(rhqr_arnoldi_t a) {
   if (!a) return -1;
   if (a->U) (void)hipFree(a->U);
   if (a->ws) (void)hipFree(a->ws);
+  if (a->vec) (void)hipFree(a->vec);
   delete a;
   return RHQR_OK;
 }
@@ -464,4 +497,240 @@ extern "C" int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const i
   }
   RHQR_HIP(hipGetLastError());
   return RHQR_OK;
+}
+
+// ------------------------------------------------ Hessenberg least squares
+// min_y || beta e_1 - H y ||_2 for the (j+1) x j upper Hessenberg H whose
+// column c is h_{c+1} (the Arnoldi relation A Q_j = Q_{j+1} H) and beta =
+// (h_0)_1 = -sigma_1 rho_1: the small least-squares problem of Alg. 8, by
+// Givens rotations in float64.  One workgroup: at step i the rotation that
+// zeroes H_{i+1,i} is formed, then applied to rows i, i+1 of every later
+// column in parallel (columns k > i have had rotations 0..i-1 applied by
+// then); back substitution on the rotated triangle, one row per step.
+namespace {
+
+constexpr int LS_TPB = 1024;
+
+__global__ void __launch_bounds__(LS_TPB) k_hess_ls(int32_t j, int32_t kh,
+                                                    const double *__restrict__ Hcols,
+                                                    double *__restrict__ Hs,
+                                                    double *__restrict__ y,
+                                                    double *__restrict__ res) {
+  __shared__ double g[1025];
+  __shared__ double rot[2];
+  const int t = threadIdx.x;
+  // Hs(:, c) = h_{c+1}, rows 0..c+1 (the rest of the column is zero)
+  for (int c = t; c < j; c += LS_TPB)
+    for (int r = 0; r <= c + 1 && r < kh; ++r)
+      Hs[r + (int64_t)c * kh] = Hcols[r + (int64_t)(c + 1) * kh];
+  for (int r = t; r <= j; r += LS_TPB) g[r] = r == 0 ? Hcols[0] : 0.0;
+  __syncthreads();
+  for (int i = 0; i < j; ++i) {
+    if (t == 0) {
+      const double a = Hs[i + (int64_t)i * kh], b = Hs[i + 1 + (int64_t)i * kh];
+      const double r = hypot(a, b);
+      const double c = r > 0.0 ? a / r : 1.0, s = r > 0.0 ? b / r : 0.0;
+      Hs[i + (int64_t)i * kh] = r;
+      Hs[i + 1 + (int64_t)i * kh] = 0.0;
+      const double gi = g[i];
+      g[i] = c * gi;
+      g[i + 1] = -s * gi;
+      rot[0] = c;
+      rot[1] = s;
+    }
+    __syncthreads();
+    const double c = rot[0], s = rot[1];
+    for (int k = i + 1 + t; k < j; k += LS_TPB) {
+      double *col = Hs + (int64_t)k * kh;
+      const double a = col[i], b = col[i + 1];
+      col[i] = c * a + s * b;
+      col[i + 1] = -s * a + c * b;
+    }
+    __syncthreads();
+  }
+  // R y = g_{0:j}, R = the rotated upper triangle
+  for (int i = j - 1; i >= 0; --i) {
+    if (t == 0) g[i] = g[i] / Hs[i + (int64_t)i * kh];
+    __syncthreads();
+    const double yi = g[i];
+    for (int k = t; k < i; k += LS_TPB) g[k] -= Hs[k + (int64_t)i * kh] * yi;
+    __syncthreads();
+  }
+  for (int i = t; i < j; i += LS_TPB) y[i] = g[i];
+  if (t == 0 && res) *res = fabs(g[j]);
+}
+
+// r = b - A x (float64, A in CSR), the residual also rounded to the basis
+// type; per-workgroup partial sums of r^2 and of b^2 (grid of NORM_BLOCKS)
+template <typename ST>
+__global__ void __launch_bounds__(256) k_resid(int64_t n, const int64_t *__restrict__ ptr,
+                                               const int32_t *__restrict__ idx,
+                                               const double *__restrict__ val,
+                                               const double *__restrict__ x,
+                                               const double *__restrict__ b,
+                                               double *__restrict__ r, ST *__restrict__ rdt,
+                                               double *__restrict__ part) {
+  double rr = 0.0, bb = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) s += val[e] * x[idx[e]];
+    const double ri = b[i] - s;
+    r[i] = ri;
+    rdt[i] = cvt_out<ST>(ri);
+    rr += ri * ri;
+    bb += b[i] * b[i];
+  }
+  __shared__ double sr[4], sb[4];
+  rr = wave_sum(rr);
+  bb = wave_sum(bb);
+  if ((threadIdx.x & 63) == 0) {
+    sr[threadIdx.x >> 6] = rr;
+    sb[threadIdx.x >> 6] = bb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sr[0] + sr[1] + sr[2] + sr[3];
+    part[2 * blockIdx.x + 1] = sb[0] + sb[1] + sb[2] + sb[3];
+  }
+}
+
+// out[0] = sqrt(sum r^2), out[1] = sqrt(sum b^2) over the partials, fixed order
+__global__ void __launch_bounds__(256) k_norms(int nb, const double *__restrict__ part,
+                                               double *__restrict__ out) {
+  double rr = 0.0, bb = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    rr += part[2 * i];
+    bb += part[2 * i + 1];
+  }
+  __shared__ double sr[4], sb[4];
+  rr = wave_sum(rr);
+  bb = wave_sum(bb);
+  if ((threadIdx.x & 63) == 0) {
+    sr[threadIdx.x >> 6] = rr;
+    sb[threadIdx.x >> 6] = bb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = sqrt(sr[0] + sr[1] + sr[2] + sr[3]);
+    out[1] = sqrt(sb[0] + sb[1] + sb[2] + sb[3]);
+  }
+}
+
+template <typename ST>
+__global__ void k_zero_vec(int64_t n, ST *__restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) v[i] = cvt_out<ST>(0.0);
+}
+
+// x += dx (dx in the basis type, x float64)
+template <typename ST>
+__global__ void k_add64(int64_t n, const ST *__restrict__ dx, double *__restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] += cvt_in<double>(dx[i]);
+}
+
+template <typename ST>
+int gmres_typed(rhqr_arnoldi_s *a, const int64_t *ptr, const int32_t *idx, const double *val,
+                const double *b, double *x, double tol, int32_t max_cycles, double *h_hist,
+                int32_t *h_cycles, int64_t *h_steps, hipStream_t st) {
+  const int64_t n = a->n;
+  const int32_t m = a->k - 1;
+  const dim3 vgrid((unsigned)((n + 255) / 256));
+  double nrm[2] = {0.0, 0.0};
+  auto residual = [&]() -> int {
+    hipLaunchKernelGGL((k_resid<ST>), dim3(NORM_BLOCKS), dim3(256), 0, st, n, ptr, idx, val,
+                       (const double *)x, b, a->r64, (ST *)a->vr, a->npart);
+    RHQR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_norms, dim3(1), dim3(256), 0, st, NORM_BLOCKS,
+                       (const double *)a->npart, a->lsres + 2);
+    RHQR_HIP(hipGetLastError());
+    RHQR_HIP(hipMemcpyAsync(nrm, a->lsres + 2, sizeof(nrm), hipMemcpyDeviceToHost, st));
+    RHQR_HIP(hipStreamSynchronize(st));
+    return RHQR_OK;
+  };
+  int rc = residual();
+  if (rc) return rc;
+  const double nb = nrm[1] > 0.0 ? nrm[1] : 1.0;
+  int32_t cycles = 0;
+  int64_t steps = 0;
+  while (cycles < max_cycles) {
+    // one cycle of Alg. 8 from r = b - A x, in the basis type
+    rc = rhqr_arnoldi_start(a, a->vr, a->vq0, nullptr, st);
+    if (rc) return rc;
+    void *q = a->vq0, *qn = a->vq1;
+    for (int32_t j = 0; j < m; ++j) {
+      rc = rhqr_spmv_csr(a->dtype, n, ptr, idx, val, q, a->vw, st);
+      if (rc) return rc;
+      rc = rhqr_arnoldi_step(a, a->vw, j + 1 < m ? qn : nullptr, nullptr, st);
+      if (rc) return rc;
+      void *tq = q;
+      q = qn;
+      qn = tq;
+    }
+    steps += m;
+    hipLaunchKernelGGL(k_hess_ls, dim3(1), dim3(LS_TPB), 0, st, m, a->k, (const double *)a->R,
+                       a->Hs, a->g, a->lsres);
+    RHQR_HIP(hipGetLastError());
+    // dx = Q_m y in the basis type (a->vw is free now), x += dx in float64
+    hipLaunchKernelGGL((k_zero_vec<ST>), vgrid, dim3(256), 0, st, n, (ST *)a->vw);
+    RHQR_HIP(hipGetLastError());
+    rc = rhqr_arnoldi_solution(a, m, a->g, a->vw, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_add64<ST>), vgrid, dim3(256), 0, st, n, (const ST *)a->vw, x);
+    RHQR_HIP(hipGetLastError());
+    rc = residual();
+    if (rc) return rc;
+    const double rel = nrm[0] / nb;
+    if (h_hist) h_hist[cycles] = rel;
+    ++cycles;
+    if (rel <= tol) break;
+  }
+  if (h_cycles) *h_cycles = cycles;
+  if (h_steps) *h_steps = steps;
+  return RHQR_OK;
+}
+
+}  // namespace
+
+extern "C" int rhqr_arnoldi_solve_ls(rhqr_arnoldi_t a, int32_t j, double *d_y, double *d_res,
+                                     void *stream) {
+  if (!a) return -1;
+  if (j < 1 || j >= a->nc) return -2;
+  if (!d_y) return -3;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_hess_ls, dim3(1), dim3(LS_TPB), 0, st, j, a->k, (const double *)a->R,
+                     a->Hs, d_y, d_res);
+  RHQR_HIP(hipGetLastError());
+  return RHQR_OK;
+}
+
+extern "C" int rhqr_gmres_csr(rhqr_arnoldi_t a, const int64_t *d_ptr, const int32_t *d_idx,
+                              const double *d_val, const double *d_b, double *d_x, double tol,
+                              int32_t max_cycles, double *h_hist, int32_t *h_cycles,
+                              int64_t *h_steps, void *stream) {
+  if (!a) return -1;
+  if (!d_ptr) return -2;
+  if (!d_idx) return -3;
+  if (!d_val) return -4;
+  if (!d_b) return -5;
+  if (!d_x) return -6;
+  if (!(tol >= 0.0)) return -7;
+  if (max_cycles < 1) return -8;
+  if (a->k < 2) return -1;
+  hipStream_t st = (hipStream_t)stream;
+  switch (a->dtype) {
+    case RHQR_F64:
+      return gmres_typed<double>(a, d_ptr, d_idx, d_val, d_b, d_x, tol, max_cycles, h_hist,
+                                 h_cycles, h_steps, st);
+    case RHQR_F32:
+      return gmres_typed<float>(a, d_ptr, d_idx, d_val, d_b, d_x, tol, max_cycles, h_hist,
+                                h_cycles, h_steps, st);
+    case RHQR_F16:
+      return gmres_typed<__half>(a, d_ptr, d_idx, d_val, d_b, d_x, tol, max_cycles, h_hist,
+                                 h_cycles, h_steps, st);
+    case RHQR_BF16:
+      return gmres_typed<__hip_bfloat16>(a, d_ptr, d_idx, d_val, d_b, d_x, tol, max_cycles, h_hist,
+                                         h_cycles, h_steps, st);
+  }
+  return RHQR_ERR_UNSUPPORTED;
 }

@@ -60,37 +60,26 @@ extern "C" size_t rhqr_factor_workspace_size(rhqr_sketch_t h, int dtype, int32_t
   return factor_ws_bytes(h, dtype, m);
 }
 
-extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W,
-                           int64_t ldw, double *d_S, int64_t lds, double *d_T, int64_t ldt,
-                           double *d_R, int64_t ldr, void *d_Q, int64_t ldq, int opts,
-                           void *d_ws, size_t ws_bytes, void *stream) {
+namespace {
+
+bool opts_ok(int opts) {
   const int scaling = opts & 0xff;
   const int panel = (opts >> 8) & 0xff;
   const int outer = (opts >> 16) & 0xff;
-  if (!h) return -1;
-  if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -2;
-  if (n != h->n) return -3;
-  if (m != h->m) return -4;
-  if (!d_W) return -5;
-  if (ldw < n) return -6;
+  return !((scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) || panel > 32 ||
+           (opts >> 24) != 0 ||
+           (outer != 0 && (panel < 2 || outer <= panel || outer > 32 || outer % panel != 0)));
+}
+
+// the factorization itself, arguments validated and the workspace carved
+int factor_core(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W, int64_t ldw,
+                double *d_S, int64_t lds, double *d_T, int64_t ldt, double *d_R, int64_t ldr,
+                void *d_Q, int64_t ldq, int opts, const FactorWs &w, hipStream_t st) {
+  const int scaling = opts & 0xff;
+  const int panel = (opts >> 8) & 0xff;
+  const int outer = (opts >> 16) & 0xff;
   const int32_t L = h->l + m;
-  if (!d_S) return -7;
-  if (lds < L) return -8;
-  if (!d_T) return -9;
-  if (ldt < m) return -10;
-  if (!d_R) return -11;
-  if (ldr < m) return -12;
-  if (d_Q && ldq < n) return -14;
-  if ((scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) || panel > 32 ||
-      (opts >> 24) != 0 || (outer != 0 && (panel < 2 || outer <= panel || outer > 32 ||
-                                            outer % panel != 0)))
-    return -15;
-  if (!d_ws) return -16;
-  if (m > 1024) return RHQR_ERR_UNSUPPORTED;
-  hipStream_t st = (hipStream_t)stream;
-  FactorWs w;
-  int rc = factor_ws_carve(h, dtype, m, d_ws, ws_bytes, &w);
-  if (rc) return rc;
+  int rc;
 
   rc = launch_fill(w.loop.status, 16, st);
   if (rc) return rc;
@@ -127,6 +116,110 @@ extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, voi
   if (rc) return rc;
   if (d_Q) rc = launch_thin_q(dtype, n, m, d_W, ldw, d_S, lds, d_T, ldt, w.Mq, w.qmf, d_Q, ldq, st);
   return rc;
+}
+
+__global__ void k_neg_sq(double *A, int64_t lda, int32_t m) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r < m) A[r + (int64_t)c * lda] = -A[r + (int64_t)c * lda];
+}
+
+template <typename ST>
+__global__ void k_zero_head(ST *A, int64_t lda, int32_t m) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r < m) A[r + (int64_t)c * lda] = cvt_out<ST>(0.0);
+}
+
+// rows m .. m+n-1 of Qw <- W (n x m), rows 0 .. m-1 <- 0, in the storage type
+template <typename ST>
+int stage_zero_topped(const void *W, int64_t ldw, int64_t n, int32_t m, void *Qw, int64_t ldq,
+                      hipStream_t st) {
+  const size_t es = sizeof(ST);
+  RHQR_HIP(hipMemcpy2DAsync((char *)Qw + (size_t)m * es, (size_t)ldq * es, W, (size_t)ldw * es,
+                            (size_t)n * es, (size_t)m, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL((k_zero_head<ST>), dim3((m + 255) / 256, m), dim3(256), 0, st, (ST *)Qw,
+                     ldq, m);
+  RHQR_HIP(hipGetLastError());
+  return RHQR_OK;
+}
+
+}  // namespace
+
+extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W,
+                           int64_t ldw, double *d_S, int64_t lds, double *d_T, int64_t ldt,
+                           double *d_R, int64_t ldr, void *d_Q, int64_t ldq, int opts,
+                           void *d_ws, size_t ws_bytes, void *stream) {
+  if (!h) return -1;
+  if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -2;
+  if (n != h->n) return -3;
+  if (m != h->m) return -4;
+  if (!d_W) return -5;
+  if (ldw < n) return -6;
+  const int32_t L = h->l + m;
+  if (!d_S) return -7;
+  if (lds < L) return -8;
+  if (!d_T) return -9;
+  if (ldt < m) return -10;
+  if (!d_R) return -11;
+  if (ldr < m) return -12;
+  if (d_Q && ldq < n) return -14;
+  if (!opts_ok(opts)) return -15;
+  if (!d_ws) return -16;
+  if (m > 1024) return RHQR_ERR_UNSUPPORTED;
+  FactorWs w;
+  const int rc = factor_ws_carve(h, dtype, m, d_ws, ws_bytes, &w);
+  if (rc) return rc;
+  return factor_core(h, dtype, n, m, d_W, ldw, d_S, lds, d_T, ldt, d_R, ldr, d_Q, ldq, opts, w,
+                     (hipStream_t)stream);
+}
+
+extern "C" size_t rhqr_rgs_workspace_size(rhqr_sketch_t h, int dtype, int32_t m) {
+  return rhqr_factor_workspace_size(h, dtype, m);
+}
+
+extern "C" int rhqr_rgs_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, const void *d_W,
+                               int64_t ldw, void *d_Q, int64_t ldq, double *d_S, int64_t lds,
+                               double *d_T, int64_t ldt, double *d_R, int64_t ldr, int opts,
+                               void *d_ws, size_t ws_bytes, void *stream) {
+  if (!h) return -1;
+  if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -2;
+  if (n < 1 || n + m != h->n) return -3;
+  if (m != h->m) return -4;
+  if (!d_W) return -5;
+  if (ldw < n) return -6;
+  if (!d_Q) return -7;
+  if (ldq < n + m) return -8;
+  const int32_t L = h->l + m;
+  if (!d_S) return -9;
+  if (lds < L) return -10;
+  if (!d_T) return -11;
+  if (ldt < m) return -12;
+  if (!d_R) return -13;
+  if (ldr < m) return -14;
+  if (!opts_ok(opts) || (opts & 0xff) != RHQR_SCALE_UNIT_PIVOT) return -15;
+  if (!d_ws) return -16;
+  if (m > 1024) return RHQR_ERR_UNSUPPORTED;
+  FactorWs w;
+  int rc = factor_ws_carve(h, dtype, m, d_ws, ws_bytes, &w);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  switch (dtype) {
+    case RHQR_F64: rc = stage_zero_topped<double>(d_W, ldw, n, m, d_Q, ldq, st); break;
+    case RHQR_F32: rc = stage_zero_topped<float>(d_W, ldw, n, m, d_Q, ldq, st); break;
+    case RHQR_F16: rc = stage_zero_topped<__half>(d_W, ldw, n, m, d_Q, ldq, st); break;
+    default: rc = stage_zero_topped<__hip_bfloat16>(d_W, ldw, n, m, d_Q, ldq, st);
+  }
+  if (rc) return rc;
+  // left-looking RHQR of [0; W]: the head of every refreshed column below its
+  // pivot is exactly zero, so sigma = +1, alpha = rho and beta = 1 throughout
+  rc = factor_core(h, dtype, n + m, m, d_Q, ldq, d_S, lds, d_T, ldt, d_R, ldr, nullptr, 0, opts,
+                   w, st);
+  if (rc) return rc;
+  // U = [I; Q] with R_RHQR = -R: Alg. 9's R has the positive diagonal rho_j
+  hipLaunchKernelGGL(k_neg_sq, dim3((m + 255) / 256, m), dim3(256), 0, st, d_R, ldr, m);
+  RHQR_HIP(hipGetLastError());
+  return RHQR_OK;
 }
 
 extern "C" int rhqr_status(const void *d_ws, void *stream, int32_t *h_info) {

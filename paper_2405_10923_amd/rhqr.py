@@ -35,6 +35,9 @@ _SIGS = {
     "rhqr_factor": (C.c_int, [_vp, C.c_int, _i64, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
                               _i64, _vp, _i64, C.c_int, _vp, _sz, _vp]),
     "rhqr_status": (C.c_int, [_vp, _vp, C.POINTER(_i32)]),
+    "rhqr_rgs_workspace_size": (_sz, [_vp, C.c_int, _i32]),
+    "rhqr_rgs_factor": (C.c_int, [_vp, C.c_int, _i64, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
+                                  _i64, _vp, _i64, C.c_int, _vp, _sz, _vp]),
     "recrhqr_workspace_size": (_sz, [_vp, C.c_int, _i32]),
     "recrhqr_factor": (C.c_int, [_vp, C.c_int, _i64, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
                                  _i64, _vp, _i64, _vp, _i64, C.c_int, _vp, _sz, _vp]),
@@ -44,6 +47,9 @@ _SIGS = {
     "rhqr_arnoldi_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "rhqr_arnoldi_solution": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "rhqr_arnoldi_basis": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp)]),
+    "rhqr_arnoldi_solve_ls": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "rhqr_gmres_csr": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, C.c_double, _i32, _vp,
+                                 C.POINTER(_i32), C.POINTER(_i64), _vp]),
     "rhqr_spmv_csr": (C.c_int, [C.c_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rhqr_batch_workspace_size": (_sz, [_vp, _i32, C.c_int]),
     "rhqr_batch_create": (C.c_int, [_vp, _i32, C.c_int, C.c_int, _vp, _sz, _vp, C.POINTER(_vp)]),
@@ -223,6 +229,26 @@ def factor(sk, W, scaling=SCALE_UNIT_PIVOT, want_q=False, bufs=None, panel=0, ou
                            bufs.ws.numel(), _stream())
     _check(rc, "rhqr_factor")
     return dict(U=W, S=bufs.S, T=bufs.T, R=bufs.R, Q=Q, ws=bufs.ws)
+
+
+def rgs(sk, W, panel=0, outer=0):
+    """BLAS2-RGS (Alg. 9) by rhqr_rgs_factor.  ``sk`` has n + m rows and head
+    m; W (n x m, column-major, GPU) is read only.  Returns dict(Q (n x m view
+    of the (n+m)-row output), S, T, R, ws)."""
+    torch = _torch()
+    n, m = W.shape
+    dev = W.device
+    Qb = colmajor_empty(n + m, m, W.dtype, dev)
+    S = colmajor_empty(sk.rows_out, m, torch.float64, dev)
+    T = colmajor_empty(m, m, torch.float64, dev)
+    R = colmajor_empty(m, m, torch.float64, dev)
+    ws = workspace(lib().rhqr_rgs_workspace_size(sk.h, dtype_code(W.dtype), m), dev)
+    rc = lib().rhqr_rgs_factor(sk.h, dtype_code(W.dtype), n, m, _ptr(W), _ld(W), _ptr(Qb), _ld(Qb),
+                               _ptr(S), _ld(S), _ptr(T), _ld(T), _ptr(R), _ld(R),
+                               (int(panel) << 8) | (int(outer) << 16), _ptr(ws), ws.numel(),
+                               _stream())
+    _check(rc, "rhqr_rgs_factor")
+    return dict(Q=Qb[m:], Qfull=Qb, S=S, T=T, R=R, ws=ws)
 
 
 def colscale(W64, dtype, out=None, scale=None):
@@ -417,46 +443,26 @@ class Arnoldi:
         _check(lib().rhqr_arnoldi_solution(self.h, int(j), _ptr(y), _ptr(x), _stream()),
                "rhqr_arnoldi_solution")
 
+    def solve_ls(self, j, y, res=None):
+        """y (j float64, GPU) <- argmin ||beta e_1 - H_{j+1,j} y|| (rhqr_arnoldi_solve_ls)."""
+        _check(lib().rhqr_arnoldi_solve_ls(self.h, int(j), _ptr(y), _ptr(res), _stream()),
+               "rhqr_arnoldi_solve_ls")
 
-def gmres(A, b, sk, m, dtype, tol=1e-6, max_cycles=1000, x0=None, callback=None):
-    """Restarted RHQR-GMRES(m) (Alg. 8): Krylov basis in ``dtype`` on the GPU,
-    Hessenberg least squares in float64 on the host, true residual recomputed
-    in float64 at every restart.  Returns (x float64, list of relative
-    residuals, total Arnoldi steps)."""
+
+def gmres(A, b, sk, m, dtype, tol=1e-6, max_cycles=1000, x0=None):
+    """Restarted RHQR-GMRES(m) (Alg. 8) by rhqr_gmres_csr: Krylov basis in
+    ``dtype``, Hessenberg least squares and solution update in float64, true
+    residual recomputed in float64 after every cycle, all in the library.
+    ``A`` is a CSR, ``b`` a float64 GPU vector.  Returns (x float64, list of
+    relative residuals after each cycle, total Arnoldi steps)."""
     torch = _torch()
-    dev = b.device
-    n = A.n
-    x = torch.zeros(n, dtype=torch.float64, device=dev) if x0 is None else x0.clone()
-    nb = float(torch.linalg.norm(b))
+    x = torch.zeros(A.n, dtype=torch.float64, device=b.device) if x0 is None else x0.clone()
     arn = Arnoldi(sk, dtype, m)
-    Hcols = torch.zeros((m, m + 1), dtype=torch.float64, device=dev)
-    qa = torch.empty(n, dtype=dtype, device=dev)
-    qb = torch.empty(n, dtype=dtype, device=dev)
-    w = torch.empty(n, dtype=dtype, device=dev)
-    hist, steps = [], 0
-    for _ in range(max_cycles):
-        r = b - A.matvec(x)
-        rel = float(torch.linalg.norm(r)) / nb
-        if hist and rel <= tol:
-            break
-        beta = arn.start(r.to(dtype), qa)
-        for j in range(m):
-            A.matvec(qa, w)
-            arn.step(w, qb, Hcols[j])
-            qa, qb = qb, qa
-        steps += m
-        H = Hcols.t().cpu().numpy()          # (m+1) x m
-        rhs = np.zeros(m + 1)
-        rhs[0] = beta
-        y = np.linalg.lstsq(H, rhs, rcond=None)[0]
-        dx = torch.zeros(n, dtype=dtype, device=dev)
-        arn.solution(m, torch.from_numpy(y).to(dev), dx)
-        x += dx.to(torch.float64)
-        rel = float(torch.linalg.norm(b - A.matvec(x))) / nb
-        hist.append(rel)
-        if callback:
-            callback(len(hist), rel)
-        if rel <= tol:
-            break
+    hist = np.zeros(max_cycles, dtype=np.float64)
+    cyc, steps = C.c_int32(), C.c_int64()
+    rc = lib().rhqr_gmres_csr(arn.h, _ptr(A.ptr), _ptr(A.idx), _ptr(A.val), _ptr(b), _ptr(x),
+                              float(tol), int(max_cycles), hist.ctypes.data_as(C.c_void_p),
+                              C.byref(cyc), C.byref(steps), _stream())
     arn.close()
-    return x, hist, steps
+    _check(rc, "rhqr_gmres_csr")
+    return x, [float(v) for v in hist[:cyc.value]], steps.value

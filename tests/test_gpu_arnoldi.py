@@ -75,3 +75,41 @@ def test_gmres_low_precision_basis_converges(dt):
     x, hist, steps = rhqr.gmres(A, b, sk, 24, getattr(torch, dt), tol=1e-6, max_cycles=200)
     log(f"gmres {dt}: cycles {len(hist)} final {hist[-1]:.2e}")
     assert hist[-1] <= 1e-6
+
+
+def test_solve_ls_matches_lstsq():
+    """The library's Givens solve of min ||beta e_1 - H y|| (Alg. 8) against
+    LAPACK's least squares on the same H (the GPU's own Hessenberg columns) and
+    against the oracle's H; the returned residual is the minimum itself."""
+    nx, m, l = 40, 20, 80
+    torch, rhqr, A, Acpu, n, sk, osketch = _setup(nx, m, l)
+    r0 = np.random.default_rng(0).standard_normal(n)
+    ref = oarn.rhqr_arnoldi(Acpu, r0, osketch, m)
+    arn = rhqr.Arnoldi(sk, torch.float64, m)
+    q = torch.empty(n, dtype=torch.float64, device="cuda")
+    qn, w = torch.empty_like(q), torch.empty_like(q)
+    H = torch.zeros((m, m + 1), dtype=torch.float64, device="cuda")
+    beta = arn.start(torch.from_numpy(r0).cuda(), q)
+    for j in range(m):
+        A.matvec(q, w)
+        arn.step(w, qn, H[j])
+        q, qn = qn, q
+    Hg = to_np(H).T
+    y = torch.empty(m, dtype=torch.float64, device="cuda")
+    res = torch.empty(1, dtype=torch.float64, device="cuda")
+    for j in (1, 2, 7, m):
+        arn.solve_ls(j, y, res)
+        torch.cuda.synchronize()
+        rhs = np.zeros(j + 1)
+        rhs[0] = beta
+        yl = np.linalg.lstsq(Hg[:j + 1, :j], rhs, rcond=None)[0]
+        yo = np.linalg.lstsq(ref["H"][:j + 1, :j], rhs, rcond=None)[0]
+        yg = to_np(y).ravel()[:j]
+        assert rel(yg, yl) < 1e-11, j
+        assert rel(yg, yo) < 1e-10, j
+        rmin = np.linalg.norm(rhs - Hg[:j + 1, :j] @ yl)
+        assert abs(float(res.item()) - rmin) <= 1e-11 * abs(beta), j
+    with pytest.raises(rhqr.RHQRError):
+        arn.solve_ls(m + 1, y)
+    with pytest.raises(rhqr.RHQRError):
+        arn.solve_ls(0, y)

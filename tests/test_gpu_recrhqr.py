@@ -86,7 +86,7 @@ def test_rec_psi_identity_fallback_elementwise(mode):
     instead of the panel kernels (the path C_m with m = 600 takes)."""
     n, m, l = 8192, 64, 2000
     log(f"recrhqr fallback mode={mode} n={n} m={m} l={l} (l + 2m = {l + 2 * m})")
-    W, Win, g, sk = _rec(n, m, l, 3, mode)
+    W, Win, g, sk = _rec(n, m, l, 2, mode)
     ref = orq.rec_rhqr(W, sk, "M" if mode == 0 else "R")
     keys = ("S", "T", "R", "U", "Q") if mode == 0 else ("S", "T", "R", "Q")
     for k in keys:
