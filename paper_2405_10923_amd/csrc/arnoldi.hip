@@ -24,7 +24,8 @@ struct rhqr_arnoldi_s {
   void *U;     // n x k, dtype (tail rows of the Householder vectors)
   double *S, *T, *R, *Z, *g, *gf;
   double *Hs;       // k x k: rotated copy of H for the least-squares solve
-  double *lsres;    // least-squares residual of the last solve
+  double *lsres;    // least-squares residual of the last solve, residual norms
+  double *ys;       // k: least-squares solution of the GMRES driver
   double *r64;      // n: float64 residual b - A x (GMRES driver)
   double *npart;    // norm partial sums (GMRES driver)
   void *vr, *vq0, *vq1, *vw;  // n each, basis type: residual, q_j, q_{j+1}, A q_j
@@ -272,6 +273,8 @@ extern "C" int rhqr_arnoldi_create(rhqr_sketch_t h, int dtype, int64_t n, int32_
   bytes += align_up(sizeof(double) * (size_t)kh * kh);
   const size_t offres = bytes;
   bytes += align_up(sizeof(double) * 4);
+  const size_t offys = bytes;
+  bytes += align_up(sizeof(double) * (size_t)kh);
   const size_t offnp = bytes;
   bytes += align_up(sizeof(double) * NORM_BLOCKS);
   if (hipMalloc(&a->ws, bytes) != hipSuccess) {
@@ -302,6 +305,7 @@ extern "C" int rhqr_arnoldi_create(rhqr_sketch_t h, int dtype, int64_t n, int32_
   a->gf = (double *)(base + offg + align_up(sizeof(double) * (size_t)kh));
   a->Hs = (double *)(base + offH);
   a->lsres = (double *)(base + offres);
+  a->ys = (double *)(base + offys);
   a->npart = (double *)(base + offnp);
   char *vbase = (char *)a->vec;
   a->r64 = (double *)vbase;
@@ -669,12 +673,12 @@ int gmres_typed(rhqr_arnoldi_s *a, const int64_t *ptr, const int32_t *idx, const
     }
     steps += m;
     hipLaunchKernelGGL(k_hess_ls, dim3(1), dim3(LS_TPB), 0, st, m, a->k, (const double *)a->R,
-                       a->Hs, a->g, a->lsres);
+                       a->Hs, a->ys, a->lsres);
     RHQR_HIP(hipGetLastError());
     // dx = Q_m y in the basis type (a->vw is free now), x += dx in float64
     hipLaunchKernelGGL((k_zero_vec<ST>), vgrid, dim3(256), 0, st, n, (ST *)a->vw);
     RHQR_HIP(hipGetLastError());
-    rc = rhqr_arnoldi_solution(a, m, a->g, a->vw, st);
+    rc = rhqr_arnoldi_solution(a, m, a->ys, a->vw, st);
     if (rc) return rc;
     hipLaunchKernelGGL((k_add64<ST>), vgrid, dim3(256), 0, st, n, (const ST *)a->vw, x);
     RHQR_HIP(hipGetLastError());

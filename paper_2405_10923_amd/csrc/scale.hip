@@ -27,11 +27,19 @@ __global__ void __launch_bounds__(CS_TPB) k_colmax(int64_t n, const double *__re
 template <typename ST> __device__ __forceinline__ ST round_to(double x);
 template <> __device__ __forceinline__ double round_to<double>(double x) { return x; }
 template <> __device__ __forceinline__ float round_to<float>(double x) { return (float)x; }
+// 2-byte types: round to float32, then to the 2-byte type (both to nearest
+// even).  The empty asm keeps the compiler from merging the two roundings
+// into one direct conversion, which can differ in the last bit.
+__device__ __forceinline__ float round_f32(double x) {
+  float f = (float)x;
+  asm volatile("" : "+v"(f));
+  return f;
+}
 template <> __device__ __forceinline__ __half round_to<__half>(double x) {
-  return __float2half_rn((float)x);
+  return __float2half_rn(round_f32(x));
 }
 template <> __device__ __forceinline__ __hip_bfloat16 round_to<__hip_bfloat16>(double x) {
-  return __float2bfloat16((float)x);
+  return __float2bfloat16(round_f32(x));
 }
 
 // Wout = W D^-1 in the storage type; grid (row blocks, m)

@@ -52,8 +52,12 @@ def test_blas2_rgs_elementwise(n, m, l, panel, outer, kind):
 
 @pytest.mark.parametrize("dt,tol", [("float32", 1e-5), ("float16", 1e-2), ("bfloat16", 1e-2)])
 def test_blas2_rgs_low_precision(dt, tol):
+    """A Gram-Schmidt process loses sketched orthogonality in proportion to
+    cond(W) u (Sec. 6 compares it with RGS, whose bound has that form), so
+    the low-precision check uses a well-conditioned W (singular values all
+    1): what remains is the rounding of Q to the storage type."""
     n, m, l = 3 * 4096 + 99, 24, 128
-    W, Win, g, sk = _run(n, m, l, 3, dtype=dt, panel=8)
+    W, Win, g, sk = _run(n, m, l, 0, dtype=dt, panel=8)
     ef = metrics.fact_error(Win, g["Q"], g["R"])
     eo = metrics.orth_error(sk.omega_apply(g["Q"]))
     log(f"rgs {dt}: e_fact {ef:.2e} e_orth {eo:.2e}")
