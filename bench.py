@@ -81,9 +81,10 @@ def b_alg(n, m, b):
     return b * (n - m) * (m * (m - 1) / 2 + 3 * m)
 
 
-def _nparts(n, es):
+def _nparts(n, es, tpw=0):
     ntiles = (n + TILE - 1) // TILE
-    tpw = 4 if ntiles >= 1024 else 2 if ntiles >= 512 else 1
+    if not tpw:
+        tpw = 4 if ntiles >= 1024 else 2 if ntiles >= 512 else 1
     if es == 2 and tpw < 2:
         tpw = 2
     return (n + TILE * tpw - 1) // (TILE * tpw)
@@ -92,12 +93,12 @@ def _nparts(n, es):
 # (panel, outer) of the blocked schedule per storage type, the fastest measured
 # on this workload: two levels, inner panels of 8 in outer panels of 32
 # (float64, float32); one level of 16 (2-byte storage)
-from paper_2405_10923_amd.schedules import DEFAULT as SCHEDULES  # noqa: E402
+from paper_2405_10923_amd.schedules import DEFAULT as SCHEDULES, lookup  # noqa: E402
 
 
-def sched_kw(dt):
-    panel, outer = SCHEDULES[str(dt).split(".")[-1]]
-    return {"panel": panel, "outer": outer}
+def sched_kw(dt, n=1 << 22, m=256):
+    panel, outer, tpw, _ = lookup(str(dt).split(".")[-1], n, m)
+    return {"panel": panel, "outer": outer, "tpw": tpw}
 
 
 def schedule(m, panel, outer):
@@ -131,7 +132,7 @@ def presketch_bytes(n, m, l, es):
     return m * (es * (n - m) + N / 8 + 2 * 8 * l * gt)
 
 
-def kernel_bytes(n, m, l, es, panel, outer=0):
+def kernel_bytes(n, m, l, es, panel, outer=0, tpw=0):
     """Algorithmic bytes of one factorization's launches of each n-row kernel:
     {"tall": refresh + re-sketch passes, "panel_mx": panel updates on matrix
     cores (panels wider than 8 columns), "panel_valu": panel updates on the
@@ -143,7 +144,7 @@ def kernel_bytes(n, m, l, es, panel, outer=0):
     applies and the panel's nb columns and writes them."""
     N = 1 << (n - 1).bit_length()
     tail = (n - m) * es
-    side = _nparts(n, es) * l * 8 + N / 8
+    side = _nparts(n, es, tpw) * l * 8 + N / 8
     ups, p0 = schedule(m, panel, outer)
     tall = 0.0
     for j in range(1, m):
@@ -280,7 +281,8 @@ def accuracy(rhqr, torch, sk, W64, Wsrc, dscale, out):
             "cond_PsiQ": float(sv[0] / sv[-1])}
 
 
-def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, outer, steps, warmup, profile, graph=True):
+def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, outer, steps, warmup, profile, graph=True,
+             tpw=0):
     """Time one storage type's factorization (eager launches, and the same
     launch sequence captured once in a HIP graph and replayed), profile its
     kernels, and measure its accuracy."""
@@ -292,7 +294,7 @@ def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, outer, steps, warmup, pro
         Wsrc, dscale = rhqr.colscale(W64, dt)   # unit max-norm columns, rounded
     Ww = rhqr.colmajor_empty(n, m, dt, W64.device)
     bufs = rhqr.FactorBuffers(sk, dt, m, want_q=False)
-    run = lambda: rhqr.factor(sk, Ww, bufs=bufs, panel=panel, outer=outer)
+    run = lambda: rhqr.factor(sk, Ww, bufs=bufs, panel=panel, outer=outer, tpw=tpw)
     restore = lambda: Ww.copy_(Wsrc)
     eager_ms = _time(torch, run, steps, warmup, restore)
     graph_ms, graph_equal = None, None
@@ -308,7 +310,7 @@ def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, outer, steps, warmup, pro
         torch.cuda.synchronize()
         Rg = bufs.R.clone()
     step_ms = min(eager_ms, graph_ms) if graph_ms else eager_ms
-    kb = kernel_bytes(n, m, l, es, panel, outer)
+    kb = kernel_bytes(n, m, l, es, panel, outer, tpw)
     own_bytes = kb["tall"] + kb["panel_mx"] + kb["panel_valu"] + kb["presketch"]
     kern = []
     if profile:
@@ -331,7 +333,7 @@ def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, outer, steps, warmup, pro
     # accuracy of one more factorization with Q (untimed, eager)
     restore()
     bq = rhqr.FactorBuffers(sk, dt, m, want_q=True)
-    out = rhqr.factor(sk, Ww, want_q=True, bufs=bq, panel=panel, outer=outer)
+    out = rhqr.factor(sk, Ww, want_q=True, bufs=bq, panel=panel, outer=outer, tpw=tpw)
     torch.cuda.synchronize()
     if graph:
         graph_equal = bool(torch.equal(Rg, out["R"]))
@@ -480,7 +482,7 @@ def run_thin_q(rhqr, torch, sk, W64, m, steps, dt=None):
     W = torch.empty((m, W64.shape[0]), dtype=dt, device=W64.device).t()
     bq = rhqr.FactorBuffers(sk, dt, m, want_q=True)
     restore = lambda: W.copy_(Wsrc)
-    kw = sched_kw(dt)
+    kw = sched_kw(dt, W64.shape[0], m)
     t_q = _time(torch, lambda: rhqr.factor(sk, W, want_q=True, bufs=bq, **kw), steps, 1, restore)
     t_n = _time(torch, lambda: rhqr.factor(sk, W, want_q=False, bufs=bq, **kw), steps, 1, restore)
     n = W64.shape[0]
@@ -514,9 +516,9 @@ def run_c2(rhqr, torch, steps):
     for kind, name in ((rhqr.SRHT, "rhqr_srht"), (rhqr.GAUSS, "rhqr_gauss")):
         sk = rhqr.Sketch(kind, n, m, l, seed=0)
         bufs = rhqr.FactorBuffers(sk, torch.float64, m)
-        kw = sched_kw(torch.float64)
+        kw = sched_kw(torch.float64, n, m)
         ms = _time(torch, lambda: rhqr.factor(sk, W, bufs=bufs, **kw), steps, 1, restore)
-        kb = kernel_bytes(n, m, l, 8, kw["panel"], kw["outer"])
+        kb = kernel_bytes(n, m, l, 8, kw["panel"], kw["outer"], kw["tpw"])
         own = kb["tall"] + kb["panel_mx"] + kb["panel_valu"]
         if kind == rhqr.SRHT:
             own += kb["presketch"]
@@ -648,15 +650,16 @@ def main():
     scheds = {}
     for name in args.dtypes.split(","):
         dt = getattr(torch, name)
-        panel, outer = SCHEDULES[name]
+        panel, outer, tpw, src = lookup(name, n, m)
         if args.panel >= 0:
-            panel, outer = args.panel, 0
+            panel, outer, tpw, src = args.panel, 0, 0, "command line"
         if args.outer >= 0:
             outer = args.outer
         scheds[name] = (panel, outer)
         r, kern = run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, outer, args.steps,
-                           args.warmup, profile=True, graph=not args.no_graph)
-        r["schedule"] = sched_name(panel, outer)
+                           args.warmup, profile=True, graph=not args.no_graph, tpw=tpw)
+        r["schedule"] = sched_name(panel, outer) + (f", {tpw} tiles per workgroup" if tpw else "")
+        r["schedule_choice"] = {"panel": panel, "outer": outer, "tpw": tpw, "source": src}
         r["kernels"] = kern
         res[name] = r
         if dt == torch.float64:

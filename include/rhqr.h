@@ -129,7 +129,11 @@ RHQR_API int rhqr_sketch(rhqr_sketch_t h, int dtype, int64_t n, int32_t k, const
  *           each outer panel is updated from all earlier reflectors and each
  *           inner panel only from the reflectors of its outer panel).  Same
  *           factorization in exact arithmetic; the one synchronisation per
- *           column is kept.  Other bits must be 0.
+ *           column is kept.  Bits 24-27: transform tiles of 4096 rows per
+ *           workgroup of the refresh + re-sketch pass, 0 (chosen from n), 1, 2
+ *           or 4 (at least 2 for 2-byte storage): a tuning knob, the results
+ *           differ only in the summation order of the sketch partials.
+ *           Bits 28-31 must be 0.
  *   d_ws  : device workspace, >= rhqr_factor_workspace_size(h, dtype, m) bytes
  * One synchronisation per column: the refreshed column's sketch (Alg. 4).
  * Breakdown (rho_j = 0) gives an identity reflector (beta_j = 0, R_jj = 0) and

@@ -1,6 +1,6 @@
 """Randomized Householder QR: RHVector (Alg. 2), right-looking RHQR (Alg. 3),
-left-looking RHQR (Alg. 4), Householder QR (Sec. 2.2), thin Q (Sec. 3.2) and
-recRHQR (Alg. 6).
+left-looking RHQR (Alg. 4), block RHQR (Alg. 5), Householder QR (Sec. 2.2),
+thin Q (Sec. 3.2) and recRHQR (Alg. 6).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
@@ -100,6 +100,70 @@ def rhqr_left(W, sk, scaling="B"):
             T[:j, j] = -b * (T[:j, :j] @ (S[:, :j].T @ s))
         alpha[j], beta[j] = a, b
     return dict(U=U, S=S, T=T, R=R, alpha=alpha, beta=beta, info=info, Z=Z)
+
+
+def _left_block(M, sk, J, scaling="B"):
+    """Alg. 4 on the columns of M (n x b) with pivot rows J, J+1, ...: the
+    block's own U, S, T, its R columns and alpha, as Alg. 5 calls RHQR on one
+    block (the block's reflectors are zero above their pivots)."""
+    n, b = M.shape
+    L = sk.rows_out
+    U = np.zeros((n, b))
+    S = np.zeros((L, b))
+    T = np.zeros((b, b))
+    Rc = np.zeros((J + b, b))
+    info = 0
+    Z = rh_sketch(M, sk)
+    for c in range(b):
+        j = J + c
+        w = M[:, c].copy()
+        y = Z[:, c].copy()
+        if c >= 1:
+            cc = T[:c, :c].T @ (S[:, :c].T @ y)
+            w = w - U[:, :c] @ cc
+            y = rh_sketch(w, sk)
+        u, s, sigma, rho, beta, _, ok = rh_vector(w, y, j, scaling)
+        if not ok and info == 0:
+            info = j + 1
+        U[:, c], S[:, c] = u, s
+        Rc[:j, c] = w[:j]
+        Rc[j, c] = -sigma * rho
+        T[c, c] = beta
+        if c >= 1:
+            T[:c, c] = -beta * (T[:c, :c] @ (S[:, :c].T @ s))
+    return U, S, T, Rc, info
+
+
+def block_rhqr(W, sk, b, scaling="B"):
+    """Block RHQR (Alg. 5): W in column blocks of b; before block j is
+    factored, every earlier block k is applied to it in turn, each after a
+    fresh sketch of the block (M <- M - U^(k) T^(k)^t S^(k)^t Psi M), then the
+    block goes through Alg. 4 with pivots at its own columns.  Returns U, S, R
+    (assembled over the blocks), the list of block T factors, and info.
+    Reading: the superscripts of the update line are the earlier block's (k),
+    not the current one's (j)."""
+    W = np.asarray(W, dtype=np.float64)
+    n, m = W.shape
+    L = sk.rows_out
+    U = np.zeros((n, m))
+    S = np.zeros((L, m))
+    R = np.zeros((m, m))
+    Ts = []
+    info = 0
+    for J in range(0, m, b):
+        nb = min(b, m - J)
+        M = W[:, J:J + nb].copy()
+        for k, K in enumerate(range(0, J, b)):
+            Y = rh_sketch(M, sk)
+            kb = Ts[k].shape[0]
+            M = M - U[:, K:K + kb] @ (Ts[k].T @ (S[:, K:K + kb].T @ Y))
+        Ub, Sb, Tb, Rc, ib = _left_block(M, sk, J, scaling)
+        if ib and not info:
+            info = ib
+        U[:, J:J + nb], S[:, J:J + nb] = Ub, Sb
+        R[:J + nb, J:J + nb] = Rc
+        Ts.append(Tb)
+    return dict(U=U, S=S, R=R, Ts=Ts, info=info)
 
 
 def rhqr_right(W, sk, scaling="B"):

@@ -27,7 +27,7 @@ struct rhqr_arnoldi_s {
   double *lsres;    // least-squares residual of the last solve, residual norms
   double *ys;       // k: least-squares solution of the GMRES driver
   double *r64;      // n: float64 residual b - A x (GMRES driver)
-  double *npart;    // norm partial sums (GMRES driver)
+  double *npart;    // 2 NORM_BLOCKS partial sums of r^2, b^2 (GMRES driver)
   void *vr, *vq0, *vq1, *vw;  // n each, basis type: residual, q_j, q_{j+1}, A q_j
   void *ws;
   void *vec;
@@ -276,7 +276,7 @@ extern "C" int rhqr_arnoldi_create(rhqr_sketch_t h, int dtype, int64_t n, int32_
   const size_t offys = bytes;
   bytes += align_up(sizeof(double) * (size_t)kh);
   const size_t offnp = bytes;
-  bytes += align_up(sizeof(double) * NORM_BLOCKS);
+  bytes += align_up(sizeof(double) * 2 * NORM_BLOCKS);  // sums of r^2 and b^2 per workgroup
   if (hipMalloc(&a->ws, bytes) != hipSuccess) {
     delete a;
     return RHQR_ERR_HIP;

@@ -43,6 +43,7 @@ struct LoopArgs {
   const int32_t *rows;
   const double *omega;  // l x (n-m), ld l
   int defer;          // the step of column j-1 left c_{j-1} to be finished by column j
+  int tpw = 0;        // transform tiles per tall workgroup (0: chosen from n)
 };
 
 // Everything the per-column kernels read about one problem: its data, its

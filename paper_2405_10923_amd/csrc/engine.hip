@@ -235,9 +235,10 @@ __global__ void __launch_bounds__(256) k_gemm_tall(const ST *__restrict__ A, int
 // ------------------------------------------------------------ host helpers
 // Tiles per tall workgroup: about one workgroup per compute unit, at least
 // two tiles for 2-byte types (16-byte loads need 8 rows per thread).
-inline int tall_tpw(int64_t n, size_t elt) {
+// A caller's choice (LoopArgs::tpw: 1, 2 or 4) overrides the default.
+inline int tall_tpw(int64_t n, size_t elt, int want = 0) {
   const int64_t ntiles = (n + TILE - 1) / TILE;
-  int tpw = ntiles >= 1024 ? 4 : ntiles >= 512 ? 2 : 1;
+  int tpw = want ? want : ntiles >= 1024 ? 4 : ntiles >= 512 ? 2 : 1;
   if (elt == 2 && tpw < 2) tpw = 2;
   return tpw;
 }
@@ -271,7 +272,7 @@ void launch_tall_k(const ColProblem &P, int32_t j, int32_t p0, int tpw, hipStrea
 
 template <typename ST>
 int tall_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int32_t p0, hipStream_t st) {
-  const int tpw = tall_tpw(a.n, sizeof(ST));
+  const int tpw = tall_tpw(a.n, sizeof(ST), a.tpw);
   const ColProblem P = make_col_problem(a, w, tpw);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (prof_events(RHQR_PROF_TALL, &e0, &e1)) return RHQR_ERR_HIP;
@@ -286,7 +287,7 @@ int tall_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int32_t p0, hipStr
 
 template <typename ST>
 int step_typed(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st) {
-  const ColProblem P = make_col_problem(a, w, tall_tpw(a.n, sizeof(ST)));
+  const ColProblem P = make_col_problem(a, w, tall_tpw(a.n, sizeof(ST), a.tpw));
   if (a.kind == RHQR_SKETCH_IDENT)
     RHQR_LAUNCH(RHQR_PROF_RED, (k_red<ST, RHQR_SKETCH_IDENT>), dim3(red_splits(j), P.gred),
                 dim3(1024), 0, st, P, j, next);

@@ -1,4 +1,5 @@
-// C ABI: rhqr_factor (left-looking RHQR, Alg. 4) and rhqr_status.
+// C ABI: rhqr_factor (left-looking RHQR, Alg. 4), BLAS2-RGS (Alg. 9) and
+// rhqr_status.
 #include "engine.h"
 
 namespace {
@@ -66,8 +67,9 @@ bool opts_ok(int opts) {
   const int scaling = opts & 0xff;
   const int panel = (opts >> 8) & 0xff;
   const int outer = (opts >> 16) & 0xff;
+  const int tpw = (opts >> 24) & 0xf;
   return !((scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) || panel > 32 ||
-           (opts >> 24) != 0 ||
+           ((unsigned)opts >> 28) != 0 || (tpw != 0 && tpw != 1 && tpw != 2 && tpw != 4) ||
            (outer != 0 && (panel < 2 || outer <= panel || outer > 32 || outer % panel != 0)));
 }
 
@@ -111,6 +113,7 @@ int factor_core(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W, int
   a.rows = h->d_rows;
   a.omega = h->d_omega;
   a.defer = 1;
+  a.tpw = (opts >> 24) & 0xf;
   rc = panel >= 2 ? run_column_loop_blocked(a, w.loop, panel, outer, w.C, w.G, st)
                   : run_column_loop(a, w.loop, st);
   if (rc) return rc;

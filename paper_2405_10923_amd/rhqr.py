@@ -213,19 +213,26 @@ class FactorBuffers:
         self.ws = workspace(lib().rhqr_factor_workspace_size(sk.h, dtype_code(dtype), m), dev)
 
 
-def factor(sk, W, scaling=SCALE_UNIT_PIVOT, want_q=False, bufs=None, panel=0, outer=0):
+def factor(sk, W, scaling=SCALE_UNIT_PIVOT, want_q=False, bufs=None, panel=0, outer=0, tpw=0):
     """Left-looking RHQR (Alg. 4).  W (n x m, column-major, GPU) is overwritten
     by U.  ``panel`` >= 2 selects the blocked schedule (panels of that many
     columns); ``outer`` > panel groups the panels in outer panels of that many
-    columns (two levels).  Returns dict(U=W, S, T, R, Q)."""
+    columns (two levels); ``panel=None`` takes the autotuned schedule of the
+    problem's size (schedules.lookup); ``tpw`` sets the transform tiles per
+    workgroup of the refresh pass (0: the library's choice).  Returns
+    dict(U=W, S, T, R, Q)."""
     n, m = W.shape
+    if panel is None:
+        from .schedules import lookup
+        panel, outer, tpw, _ = lookup(W.dtype, n, m)
     if bufs is None:
         bufs = FactorBuffers(sk, W.dtype, m, want_q)
     Q = bufs.Q if want_q else None
     rc = lib().rhqr_factor(sk.h, dtype_code(W.dtype), n, m, _ptr(W), _ld(W), _ptr(bufs.S),
                            _ld(bufs.S), _ptr(bufs.T), _ld(bufs.T), _ptr(bufs.R), _ld(bufs.R),
                            _ptr(Q), _ld(Q) if Q is not None else 0,
-                           int(scaling) | (int(panel) << 8) | (int(outer) << 16), _ptr(bufs.ws),
+                           int(scaling) | (int(panel) << 8) | (int(outer) << 16) | (int(tpw) << 24),
+                           _ptr(bufs.ws),
                            bufs.ws.numel(), _stream())
     _check(rc, "rhqr_factor")
     return dict(U=W, S=bufs.S, T=bufs.T, R=bufs.R, Q=Q, ws=bufs.ws)

@@ -225,3 +225,51 @@ def test_cm_stress_input_claims():
     rec = rhqr.rec_rhqr(W, sk, "M")
     assert metrics.fact_error(W, rec["Q"], rec["R"]) < 1e-14
     assert metrics.cond(rec["Q"]) < 5.0
+
+
+@pytest.mark.parametrize("b", [1, 4, 5, 16])
+def test_block_rhqr_equals_left_looking(b):
+    """Alg. 5 computes the same reflectors as Alg. 4 in exact arithmetic
+    (Sec. 3.2): U, S and R agree to rounding, each block's T is the diagonal
+    block of Alg. 4's T (the recursion of Prop. 3.2 restricted to the block),
+    and the product of the block factors reproduces W (compact form under
+    Psi: Psi W = prod_k (I - S_k T_k S_k^t) [R; 0])."""
+    n, m, l = 3000, 16, 64
+    W = make_w(n, m, 2, seed=4)
+    sk = sketch.Sketch(sketch.SRHT, n, m, l, seed=9)
+    ref = rhqr.rhqr_left(W, sk)
+    blk = rhqr.block_rhqr(W, sk, b)
+    for k in ("U", "S", "R"):
+        assert np.max(np.abs(blk[k] - ref[k])) <= 1e-12 * np.max(np.abs(ref[k])), k
+    for i, Tb in enumerate(blk["Ts"]):
+        J = i * b
+        assert np.max(np.abs(Tb - ref["T"][J:J + Tb.shape[0], J:J + Tb.shape[0]])) <= 1e-12
+    L = sk.rows_out
+    X = np.zeros((L, m))
+    X[:m] = blk["R"]
+    for i in reversed(range(len(blk["Ts"]))):
+        J = i * b
+        Sb = blk["S"][:, J:J + blk["Ts"][i].shape[0]]
+        X = X - Sb @ (blk["Ts"][i] @ (Sb.T @ X))
+    Z = sketch.rh_sketch(W, sk)
+    assert np.linalg.norm(X - Z) <= 1e-13 * np.linalg.norm(Z)
+
+
+def test_block_rhqr_missing_resketch_is_caught():
+    """A plausible mistake in Alg. 5 -- reusing the first sketch of the block
+    for every earlier block's update instead of sketching it afresh -- changes
+    the factors (the pin above catches it)."""
+    n, m, l, b = 3000, 12, 64, 4
+    W = make_w(n, m, 2, seed=4)
+    sk = sketch.Sketch(sketch.SRHT, n, m, l, seed=9)
+    ref = rhqr.rhqr_left(W, sk)
+    U = np.zeros((n, m)); S = np.zeros((sk.rows_out, m)); Ts = []
+    for J in range(0, m, b):
+        M = W[:, J:J + b].copy()
+        Y = sketch.rh_sketch(M, sk)
+        for k, K in enumerate(range(0, J, b)):
+            M = M - U[:, K:K + b] @ (Ts[k].T @ (S[:, K:K + b].T @ Y))
+        Ub, Sb, Tb, _, _ = rhqr._left_block(M, sk, J)
+        U[:, J:J + b], S[:, J:J + b] = Ub, Sb
+        Ts.append(Tb)
+    assert np.max(np.abs(U - ref["U"])) > 1e-6 * np.max(np.abs(ref["U"]))
