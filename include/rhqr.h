@@ -145,6 +145,29 @@ RHQR_API int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void 
                 int64_t ldr, void *d_Q, int64_t ldq, int opts, void *d_ws,
                 size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * rhqr_factor_noalloc: rhqr_factor without a workspace argument, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * and errors as rhqr_factor (bitwise the same outputs), minus d_ws/ws_bytes.
+ * The workspace is a device array inside the library of
+ * RHQR_NOALLOC_SCRATCH_BYTES (64 MiB) that every GPU the library runs on
+ * holds until the process ends; the call allocates nothing.  Returns
+ * RHQR_ERR_WORKSPACE when rhqr_factor_workspace_size(h, dtype, m) exceeds
+ * that size (nothing is launched).  Every call on one GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (several streams or host
+ * threads) race and must be serialised by the caller.
+ *   d_info: optional (NULL to skip) device array of 2 int32 receiving, at the
+ *           end of the call on `stream`, the first column (1-based) with
+ *           rho_j = 0 and the first non-finite column, 0 if none (what
+ *           rhqr_status reports for rhqr_factor).
+ * ---------------------------------------------------------------------- */
+#define RHQR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+RHQR_API int rhqr_factor_noalloc(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W,
+                                 int64_t ldw, double *d_S, int64_t lds, double *d_T, int64_t ldt,
+                                 double *d_R, int64_t ldr, void *d_Q, int64_t ldq, int opts,
+                                 int32_t *d_info, void *stream);
+
 /* Status of the last rhqr_factor / recrhqr_factor call that used this
  * workspace, in *h_info (host):
  *    0  every reflector was formed;

@@ -1,6 +1,9 @@
-// C ABI: rhqr_factor (left-looking RHQR, Alg. 4), BLAS2-RGS (Alg. 9) and
-// rhqr_status.
+// C ABI: rhqr_factor (left-looking RHQR, Alg. 4), its allocation-free variant
+// rhqr_factor_noalloc, BLAS2-RGS (Alg. 9) and rhqr_status.
 #include "engine.h"
+
+#include <mutex>
+#include <vector>
 
 namespace {
 
@@ -233,5 +236,86 @@ extern "C" int rhqr_status(const void *d_ws, void *stream, int32_t *h_info) {
   RHQR_HIP(hipMemcpyAsync(w, d_ws, sizeof(w), hipMemcpyDeviceToHost, st));
   RHQR_HIP(hipStreamSynchronize(st));
   *h_info = w[1] ? -w[1] : w[0];
+  return RHQR_OK;
+}
+
+// ------------------------------------------------- allocation-free variant
+// The workspace of rhqr_factor_noalloc lives in a file-scope device array:
+// every GPU the library runs on holds its own copy for the life of the
+// process.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address is looked up once per device with
+// hipGetSymbolAddress and only that address is ever passed to kernels.
+static __device__ __align__(256) unsigned char scratch[RHQR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// d_info[0] = first breakdown column, d_info[1] = first non-finite column
+__global__ void k_copy_status(const int32_t *status, int32_t *info) {
+  if (threadIdx.x < 2) info[threadIdx.x] = status[threadIdx.x];
+}
+
+struct ScratchTable {
+  std::mutex mu;
+  std::vector<void *> ptr;  // device address of `scratch`, per device ordinal
+};
+
+ScratchTable &scratch_table() {
+  static ScratchTable t;
+  return t;
+}
+
+// device address of this device's copy of `scratch` (the current device)
+int scratch_address(void **out) {
+  int dev = 0;
+  RHQR_HIP(hipGetDevice(&dev));
+  ScratchTable &t = scratch_table();
+  std::lock_guard<std::mutex> lk(t.mu);
+  if ((int)t.ptr.size() <= dev) t.ptr.resize(dev + 1, nullptr);
+  if (!t.ptr[dev]) {
+    void *p = nullptr;
+    RHQR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return RHQR_ERR_HIP;
+    t.ptr[dev] = p;
+  }
+  *out = t.ptr[dev];
+  return RHQR_OK;
+}
+
+}  // namespace
+
+extern "C" int rhqr_factor_noalloc(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W,
+                                   int64_t ldw, double *d_S, int64_t lds, double *d_T,
+                                   int64_t ldt, double *d_R, int64_t ldr, void *d_Q, int64_t ldq,
+                                   int opts, int32_t *d_info, void *stream) {
+  if (!h) return -1;
+  if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -2;
+  if (n != h->n) return -3;
+  if (m != h->m) return -4;
+  if (!d_W) return -5;
+  if (ldw < n) return -6;
+  const int32_t L = h->l + m;
+  if (!d_S) return -7;
+  if (lds < L) return -8;
+  if (!d_T) return -9;
+  if (ldt < m) return -10;
+  if (!d_R) return -11;
+  if (ldr < m) return -12;
+  if (d_Q && ldq < n) return -14;
+  if (!opts_ok(opts)) return -15;
+  if (m > 1024) return RHQR_ERR_UNSUPPORTED;
+  const size_t need = factor_ws_bytes(h, dtype, m);
+  if (need > RHQR_NOALLOC_SCRATCH_BYTES) return RHQR_ERR_WORKSPACE;
+  void *ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc) return rc;
+  FactorWs w;
+  rc = factor_ws_carve(h, dtype, m, ws, need, &w);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  rc = factor_core(h, dtype, n, m, d_W, ldw, d_S, lds, d_T, ldt, d_R, ldr, d_Q, ldq, opts, w, st);
+  if (rc || !d_info) return rc;
+  hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, st, (const int32_t *)w.loop.status,
+                     d_info);
+  RHQR_HIP(hipGetLastError());
   return RHQR_OK;
 }

@@ -34,6 +34,8 @@ _SIGS = {
     "rhqr_factor_workspace_size": (_sz, [_vp, C.c_int, _i32]),
     "rhqr_factor": (C.c_int, [_vp, C.c_int, _i64, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
                               _i64, _vp, _i64, C.c_int, _vp, _sz, _vp]),
+    "rhqr_factor_noalloc": (C.c_int, [_vp, C.c_int, _i64, _i32, _vp, _i64, _vp, _i64, _vp, _i64,
+                                      _vp, _i64, _vp, _i64, C.c_int, _vp, _vp]),
     "rhqr_status": (C.c_int, [_vp, _vp, C.POINTER(_i32)]),
     "rhqr_rgs_workspace_size": (_sz, [_vp, C.c_int, _i32]),
     "rhqr_rgs_factor": (C.c_int, [_vp, C.c_int, _i64, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
