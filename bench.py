@@ -504,6 +504,39 @@ def run_thin_q(rhqr, torch, sk, W64, m, steps, dt=None):
     return out
 
 
+def run_alg5(rhqr, torch, sk, W64, m, steps, blocks=(32, 8)):
+    """Block RHQR exactly as Alg. 5 writes it (every earlier block applied to
+    the current block after a fresh sketch of it; opts bit 28) beside the
+    panel-product schedule, float64, same workload."""
+    n = W64.shape[0]
+    W = rhqr.colmajor_empty(n, m, torch.float64, W64.device)
+    bufs = rhqr.FactorBuffers(sk, torch.float64, m, want_q=True)
+    out = {"workload": f"float64 {n} x {m}, SRHT l = {sk.l}"}
+    for b in blocks:
+        def run():
+            P = rhqr._ptr
+            rc = rhqr.lib().rhqr_factor(sk.h, 0, n, m, P(W), rhqr._ld(W), P(bufs.S), rhqr._ld(bufs.S),
+                                        P(bufs.T), rhqr._ld(bufs.T), P(bufs.R), rhqr._ld(bufs.R),
+                                        None, 0, (1 << 28) | (b << 8), P(bufs.ws),
+                                        bufs.ws.numel(), rhqr._stream())
+            assert rc == 0
+        ms = _time(torch, run, steps, 1, lambda: W.copy_(W64))
+        W.copy_(W64)
+        run()
+        U, T, R = W.clone(), bufs.T, bufs.R
+        Q = -U @ (T @ U[:m].t())
+        Q[:m] += torch.eye(m, dtype=torch.float64, device=W.device)
+        ef = float(torch.linalg.norm(W64 - Q @ R) / torch.linalg.norm(W64))
+        Y = rhqr.sketch(sk, Q)
+        import numpy as np
+        eo = float(np.linalg.norm((Y.t() @ Y).cpu().numpy() - np.eye(m), 2))
+        out[f"blocks_of_{b}"] = {"ms": round(ms, 3), "e_fact": ef, "e_orth": eo}
+        del U, Q, Y
+    del W, bufs
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_c2(rhqr, torch, steps):
     """2^20 x 128, cond 1e12, float64: RHQR with the SRHT and the Gaussian
     sketch (l = 512, blocked schedule) and recRHQR (SRHT)."""
@@ -686,6 +719,9 @@ def main():
                                           torch.float16)}
         print(f"# thin Q float64: {extra['thin_q_f64']['ms']:.2f} ms, float16: "
               f"{extra['thin_q_f16']['ms']:.2f} ms", file=sys.stderr, flush=True)
+        extra["block_rhqr_alg5_f64"] = run_alg5(rhqr, torch, sk, W64, m, max(2, args.steps // 2))
+        print(f"# Alg. 5 block RHQR float64: {json.dumps(extra['block_rhqr_alg5_f64'])}",
+              file=sys.stderr, flush=True)
     batched = None
     if args.batch_count > 0:
         del W64

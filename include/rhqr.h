@@ -133,7 +133,15 @@ RHQR_API int rhqr_sketch(rhqr_sketch_t h, int dtype, int64_t n, int32_t k, const
  *           workgroup of the refresh + re-sketch pass, 0 (chosen from n), 1, 2
  *           or 4 (at least 2 for 2-byte storage): a tuning knob, the results
  *           differ only in the summation order of the sketch partials.
- *           Bits 28-31 must be 0.
+ *           Bit 28: block RHQR exactly as Alg. 5 writes it, with blocks of b
+ *           = bits 8-15 columns (1 <= b <= 32, outer width 0): before each
+ *           block is factored (Alg. 4 over its columns, refresh coefficients
+ *           from its own reflectors), every earlier block is applied to it in
+ *           turn, each after a fresh sketch of the block.  Same factorization
+ *           in exact arithmetic (U, S, T, R as without the bit).  For storage
+ *           types narrower than float64 the block's head rows pass through
+ *           the storage type between the earlier blocks' updates.
+ *           Bits 29-31 must be 0.
  *   d_ws  : device workspace, >= rhqr_factor_workspace_size(h, dtype, m) bytes
  * One synchronisation per column: the refreshed column's sketch (Alg. 4).
  * Breakdown (rho_j = 0) gives an identity reflector (beta_j = 0, R_jj = 0) and

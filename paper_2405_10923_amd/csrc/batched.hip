@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(PANEL_TPB) kb_panel(const ColProblem *__restri
                                  BATCH_PB, Q.C, b.local);
     return;
   }
-  panel_block<ST, BATCH_PB>((ST *)Q.W, Q.ldw, Q.n, Q.m, 0, J, nb, Q.C, Q.aligned, b.local);
+  panel_block<ST, BATCH_PB>((ST *)Q.W, Q.ldw, Q.n, Q.m, 0, J, nb, Q.C, Q.aligned, b.local, J);
 }
 
 // last column stored as u = raw / alpha, head block of U written from S

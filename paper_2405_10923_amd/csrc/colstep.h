@@ -487,7 +487,7 @@ __device__ __forceinline__ void red_block(const ColProblem &P, int32_t j, int ne
           for (int b = 0; b < RED_NP; ++b) {
             const int p = p0 + 16 * b;
             const double cp = (defer && p == j - 1) ? clast : cv[b];
-            t[b] = p < pe ? sv[b] * cp : 0.0;
+            t[b] = (p < pe && p >= P.c0) ? sv[b] * cp : 0.0;
           }
 #pragma unroll
           for (int b = 0; b < RED_NP; ++b) v += t[b];
@@ -636,7 +636,7 @@ __device__ __forceinline__ void red_split_block(const ColProblem &P, int32_t j, 
         for (int b = 0; b < RH_NP; ++b) {
           const int p = p0 + 16 * b;
           const double cp = (defer && p == j - 1) ? clast : cv[b];
-          v += p < pe ? sv[b] * cp : 0.0;
+          v += (p < pe && p >= P.c0) ? sv[b] * cp : 0.0;
         }
       }
     } else if (KIND != RHQR_SKETCH_IDENT && valid) {
@@ -783,11 +783,12 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
   // column of T (T_{q,p}, q <= p)
   double tr[FIN_NQ], tc[FIN_NQ];
   const bool pw = w < FIN_P && p < j;
+  const int c0 = P.c0;
 #pragma unroll
   for (int i = 0; i < FIN_NQ; ++i) {
     const int qr = p + lane + 64 * i, qc = lane + 64 * i;
     tr[i] = (pw && qr < j) ? Tt[qr + (int64_t)p * m] : 0.0;
-    tc[i] = (pw && needc && qc <= p) ? T[qc + (int64_t)p * ldt] : 0.0;
+    tc[i] = (pw && needc && qc <= p && qc >= c0) ? T[qc + (int64_t)p * ldt] : 0.0;
   }
   // wave 0: the first 128 groups' partial sums of squares and of y^t z, and
   // y_j; every thread: the entry of y its first row of s_j needs
@@ -890,12 +891,13 @@ __device__ __forceinline__ void fin_block(const ColProblem &P, int32_t j, int ne
     for (int i = 0; i < FIN_NQ; ++i) {
       const int qr = p + lane + 64 * i, qc = lane + 64 * i;
       if (qr < j) td += tr[i] * d[qr];
-      if (needc && qc <= p) te += tc[i] * e[qc];
+      if (needc && qc <= p && qc >= c0) te += tc[i] * e[qc];
     }
     // rows beyond the prefetched ones (j > 64 FIN_NQ)
     for (int qr = p + lane + 64 * FIN_NQ; qr < j; qr += 64) td += Tt[qr + (int64_t)p * m] * d[qr];
     if (needc)
-      for (int qc = lane + 64 * FIN_NQ; qc <= p; qc += 64) te += T[qc + (int64_t)p * ldt] * e[qc];
+      for (int qc = lane + 64 * FIN_NQ; qc <= p; qc += 64)
+        if (qc >= c0) te += T[qc + (int64_t)p * ldt] * e[qc];
     td = wave_sum(td);
     te = wave_sum(te);
     dcw = d[p] * te;
@@ -1061,10 +1063,13 @@ __device__ __forceinline__ void panel_store(ST *p, const CT *x) {
   }
 }
 
+// Output columns JO .. JO+nb-1 (JO = J for the blocked schedule, where the
+// panel follows the reflectors it is updated with).
 template <typename ST, int NBC>
 __device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
                                             int32_t K0, int32_t J, int32_t nb,
-                                            const double *__restrict__ Ct, int aligned, int bid) {
+                                            const double *__restrict__ Ct, int aligned, int bid,
+                                            int32_t JO) {
   using CT = typename CompT<ST>::type;
   constexpr int VEC = panel_vec<ST, NBC>();  // rows per thread
   const int64_t mb = m - (m % VEC);  // aligned start; head rows < m are not written
@@ -1134,7 +1139,7 @@ __device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int
 #pragma unroll
     for (int c = 0; c < NBC; ++c) {
       if (c < nb) {  // uniform; a break here would stop the unrolling
-        ST *wc = W + (int64_t)(J + c) * ldw + r0;
+        ST *wc = W + (int64_t)(JO + c) * ldw + r0;
         CT x[VEC];
         panel_load<ST, CT, VEC>(wc, x);
 #pragma unroll
@@ -1147,7 +1152,7 @@ __device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int
 #pragma unroll
   for (int c = 0; c < NBC; ++c) {
     if (c < nb) {
-      ST *wc = W + (int64_t)(J + c) * ldw + r0;
+      ST *wc = W + (int64_t)(JO + c) * ldw + r0;
 #pragma unroll
       for (int e = 0; e < VEC; ++e)
         if (r0 + e < n && r0 + e >= m)

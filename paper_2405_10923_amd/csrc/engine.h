@@ -44,6 +44,7 @@ struct LoopArgs {
   const double *omega;  // l x (n-m), ld l
   int defer;          // the step of column j-1 left c_{j-1} to be finished by column j
   int tpw = 0;        // transform tiles per tall workgroup (0: chosen from n)
+  int32_t c0 = 0;     // first reflector of the refresh coefficients (block RHQR, Alg. 5)
 };
 
 // Everything the per-column kernels read about one problem: its data, its
@@ -69,6 +70,8 @@ struct ColProblem {
   int64_t nparts;      // tall workgroups (= partial sketches per column)
   int32_t gred;        // reduction workgroups
   int32_t scaling, defer, aligned;
+  int32_t c0 = 0;      // c_p = sum_{c0 <= q <= p} T_{q,p} (S^t z)_q: only the reflectors
+                       // from c0 on (block RHQR, Alg. 5, refreshes inside one block)
   double *part, *y, *sq, *dpart, *epart, *ypart, *scal, *c, *cf, *ia, *Tt, *dcpart, *fs;
   int32_t *status;
   double *C, *G;       // panel coefficients of the blocked schedule (batched path)
@@ -91,6 +94,13 @@ int engine_step(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStre
 // level); C and G are float64 scratch of m x 32 entries each
 int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, int outer, double *C,
                             double *G, hipStream_t st);
+// block RHQR as Alg. 5 writes it: blocks of b (<= 32) columns, each earlier
+// block applied after a fresh sketch of the current block; C: m x 32 and G:
+// 32 x 32 float64 scratch, Z: (l+m) x m float64 (the fresh sketches), skws:
+// the multi-column sketch workspace for b columns
+int run_column_loop_alg5(const rhqr_sketch_s *h, const LoopArgs &a, const LoopWs &w, int b,
+                         double *C, double *G, double *Z, void *skws, size_t skws_bytes,
+                         hipStream_t st);
 // thin Q = [I; 0] - U T U_1^t (Sec. 3.2); Mq: m x m float64 scratch, qmf:
 // thin_q_bytes(m) bytes of scratch (2-byte storage: split coefficients)
 size_t thin_q_bytes(int32_t m);

@@ -65,7 +65,7 @@ template <typename ST, int NBC>
 __global__ void __launch_bounds__(PANEL_TPB) k_panel(ST *__restrict__ W, int64_t ldw, int64_t n,
                                                      int32_t m, int32_t K0, int32_t J, int32_t nb,
                                                      const double *__restrict__ Ct, int aligned) {
-  panel_block<ST, NBC>(W, ldw, n, m, K0, J, nb, Ct, aligned, blockIdx.x);
+  panel_block<ST, NBC>(W, ldw, n, m, K0, J, nb, Ct, aligned, blockIdx.x, J);
 }
 
 // ------------------------------------------------------------ final stores
@@ -873,6 +873,184 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, 
   return finish_typed<ST>(a, w, st);
 }
 
+// ------------------------------------------------- block RHQR (Alg. 5)
+// Before block J (columns J .. J+nb-1) is factored, every earlier block K
+// (columns K .. K+kb-1) is applied to it in turn after a fresh sketch of the
+// block:  Y = Psi M,  C = T_KK^t S_K^t Y,  M -= U_K C,  with T_KK the
+// diagonal block of T (the block's own T factor).  Then the block goes
+// through Alg. 4 with refresh coefficients over its own reflectors only
+// (LoopArgs::c0 = J) and its own fresh sketch as the pre-sketch.  The head
+// rows of M are updated in float64 from the head rows of U (= those of S) and
+// kept in place in W (rounded to the storage type), so the sketches and the
+// column loop see the current block.
+
+// G = S_{:, K:K+kb}^t Z_{:, J:J+nb} (kb x nb, ld kb), one wave per entry
+__global__ void __launch_bounds__(256) k_a5_gram(int32_t L, int32_t K, int32_t kb, int32_t J,
+                                                 int32_t nb, const double *__restrict__ S,
+                                                 int64_t lds, const double *__restrict__ Z,
+                                                 int64_t ldz, double *__restrict__ G) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = blockIdx.x * 4 + w;
+  if (e >= kb * nb) return;  // uniform across the wave
+  const int q = e % kb, c = e / kb;
+  const double *sp = S + (int64_t)(K + q) * lds;
+  const double *zp = Z + (int64_t)(J + c) * ldz;
+  double v = 0.0;
+  for (int r = lane; r < L; r += 64) v += sp[r] * zp[r];
+  v = wave_sum(v);
+  if (lane == 0) G[q + (int64_t)c * kb] = v;
+}
+
+// C_{K+p, c} = sum_{q <= p} T_{K+q, K+p} G_{q, c} (row K+p at C + (K+p) pw,
+// zero for c >= nb), one thread per entry
+__global__ void k_a5_coef(int32_t K, int32_t kb, int32_t nb, int32_t pw,
+                          const double *__restrict__ T, int64_t ldt, const double *__restrict__ G,
+                          double *__restrict__ C) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kb * pw) return;
+  const int p = e / pw, c = e % pw;
+  double v = 0.0;
+  if (c < nb)
+    for (int q = 0; q <= p; ++q) v += T[(K + q) + (int64_t)(K + p) * ldt] * G[q + (int64_t)c * kb];
+  C[(int64_t)(K + p) * pw + c] = v;
+}
+
+// head rows of the block: W_{k, J+c} -= sum_p S_{k, K+p} C_{K+p, c}, k < m
+template <typename ST>
+__global__ void k_a5_head(int32_t m, int32_t K, int32_t kb, int32_t J, int32_t nb, int32_t pw,
+                          const double *__restrict__ S, int64_t lds, const double *__restrict__ C,
+                          ST *__restrict__ W, int64_t ldw) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (k >= m || c >= nb) return;
+  ST *wp = W + k + (int64_t)(J + c) * ldw;
+  double v = cvt_in<double>(*wp);
+  for (int p = 0; p < kb; ++p) v -= S[k + (int64_t)(K + p) * lds] * C[(int64_t)(K + p) * pw + c];
+  *wp = cvt_out<ST>(v);
+}
+
+// W[m:n, J:J+nb] -= U[m:n, K:K+kb] C_{K:K+kb}: matrix cores, or vector units
+template <typename ST, int NC>
+__global__ void __launch_bounds__(PX_WAVES * 64) k_a5_panel_mx(ST *__restrict__ W, int64_t ldw,
+                                                               int64_t n, int32_t m, int32_t K,
+                                                               int32_t kb, int32_t J, int32_t nb,
+                                                               int pw,
+                                                               const double *__restrict__ C) {
+  panel_mx_block<ST, NC>(W, ldw, W + (int64_t)J * ldw, ldw, false, n, m, K, K + kb, nb, pw, C,
+                         blockIdx.x);
+}
+
+template <typename ST, int NBC>
+__global__ void __launch_bounds__(PANEL_TPB) k_a5_panel(ST *__restrict__ W, int64_t ldw, int64_t n,
+                                                        int32_t m, int32_t K, int32_t kb,
+                                                        int32_t J, int32_t nb,
+                                                        const double *__restrict__ C,
+                                                        int aligned) {
+  panel_block<ST, NBC>(W, ldw, n, m, K, K + kb, nb, C, aligned, blockIdx.x, J);
+}
+
+template <typename ST>
+int a5_update(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K, int32_t kb, int32_t J,
+              int32_t nb, int pw, const double *C, hipStream_t st) {
+  const int aligned = ((uintptr_t)W % 16 == 0) && ((ldw * (int64_t)sizeof(ST)) % 16 == 0);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool mx = aligned && nb > PX_MIN_NB;
+  if (prof_events(mx ? RHQR_PROF_PANEL_MX : RHQR_PROF_PANEL_VALU, &e0, &e1)) return RHQR_ERR_HIP;
+  if (mx) {
+    constexpr int VEC = 16 / sizeof(ST);
+    constexpr int WR = px_rg(sizeof(ST)) * 16 * VEC;
+    const int64_t waves = (n - (m - m % VEC) + WR - 1) / WR;
+    const dim3 grid((unsigned)((waves + PX_WAVES - 1) / PX_WAVES));
+#define RHQR_A5_MX(NC)                                                                      \
+  if (e0)                                                                                   \
+    hipExtLaunchKernelGGL((k_a5_panel_mx<ST, NC>), grid, dim3(PX_WAVES * 64), 0, st, e0, e1, \
+                          0, W, ldw, n, m, K, kb, J, nb, pw, C);                            \
+  else                                                                                      \
+    hipLaunchKernelGGL((k_a5_panel_mx<ST, NC>), grid, dim3(PX_WAVES * 64), 0, st, W, ldw, n, \
+                       m, K, kb, J, nb, pw, C)
+    if (pw <= 16) {
+      RHQR_A5_MX(16);
+    } else {
+      RHQR_A5_MX(32);
+    }
+#undef RHQR_A5_MX
+  } else {
+#define RHQR_A5_VALU(NBC)                                                                     \
+  do {                                                                                        \
+    constexpr int VEC = panel_vec<ST, NBC>();                                                 \
+    const int64_t threads = (n - (m - m % VEC) + VEC - 1) / VEC;                              \
+    const dim3 grid((unsigned)((threads + PANEL_TPB - 1) / PANEL_TPB));                       \
+    if (e0)                                                                                   \
+      hipExtLaunchKernelGGL((k_a5_panel<ST, NBC>), grid, dim3(PANEL_TPB), 0, st, e0, e1, 0, W, \
+                            ldw, n, m, K, kb, J, nb, C, aligned);                             \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_a5_panel<ST, NBC>), grid, dim3(PANEL_TPB), 0, st, W, ldw, n, m, K, \
+                         kb, J, nb, C, aligned);                                              \
+  } while (0)
+    if (pw <= 8)
+      RHQR_A5_VALU(8);
+    else if (pw <= 16)
+      RHQR_A5_VALU(16);
+    else
+      RHQR_A5_VALU(32);
+#undef RHQR_A5_VALU
+  }
+  RHQR_HIP(hipGetLastError());
+  return RHQR_OK;
+}
+
+template <typename ST>
+int run_alg5_typed(const rhqr_sketch_s *h, LoopArgs a, const LoopWs &w, int b, double *C,
+                   double *G, double *Z, void *skws, size_t skws_bytes, hipStream_t st) {
+  ST *W = (ST *)a.W;
+  const int32_t m = a.m, L = a.l + a.m;
+  const int64_t n = a.n, ntail = n - m;
+  a.Z = Z;
+  a.ldz = L;
+  for (int32_t J = 0; J < m; J += b) {
+    const int32_t nb = m - J < b ? m - J : b;
+    const int pw = panel_width(nb);
+    if (J > 0 && ntail > 0) {  // u_{J-1} is still raw: store it scaled before it is applied
+      hipLaunchKernelGGL((k_scale_col<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W, a.ldw,
+                         n, m, J - 1, w.ia);
+      RHQR_HIP(hipGetLastError());
+    }
+    for (int32_t K = 0; K < J; K += b) {
+      const int32_t kb = J - K < b ? J - K : b;
+      int rc = launch_sketch(h, a.dtype, n, nb, W + (int64_t)J * a.ldw, a.ldw,
+                             Z + (int64_t)J * L, L, skws, skws_bytes, st);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_a5_gram, dim3((kb * nb + 3) / 4), dim3(256), 0, st, L, K, kb, J, nb,
+                         (const double *)a.S, a.lds, (const double *)Z, (int64_t)L, G);
+      RHQR_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_a5_coef, dim3((kb * pw + 255) / 256), dim3(256), 0, st, K, kb, nb, pw,
+                         (const double *)a.T, a.ldt, (const double *)G, C);
+      RHQR_HIP(hipGetLastError());
+      hipLaunchKernelGGL((k_a5_head<ST>), dim3((m + 255) / 256, nb), dim3(256), 0, st, m, K, kb,
+                         J, nb, pw, (const double *)a.S, a.lds, (const double *)C, W, a.ldw);
+      RHQR_HIP(hipGetLastError());
+      if (ntail > 0) {
+        rc = a5_update<ST>(W, a.ldw, n, m, K, kb, J, nb, pw, C, st);
+        if (rc) return rc;
+      }
+    }
+    // the block's own pre-sketch, then Alg. 4 over its columns
+    int rc = launch_sketch(h, a.dtype, n, nb, W + (int64_t)J * a.ldw, a.ldw, Z + (int64_t)J * L,
+                           L, skws, skws_bytes, st);
+    if (rc) return rc;
+    a.c0 = J;
+    for (int32_t j = J; j < J + nb; ++j) {
+      if (j >= 1) {
+        rc = tall_typed<ST>(a, w, j, J, st);
+        if (rc) return rc;
+      }
+      rc = step_typed<ST>(a, w, j, j + 1 < J + nb, st);
+      if (rc) return rc;
+    }
+  }
+  return finish_typed<ST>(a, w, st);
+}
+
 // ------------------------------------------- thin Q tail on matrix cores
 // Q_2 = -U_2 Mq as the panel product with a zero start (panel_mx_block),
 // one grid row per QX_NC columns of Q.  k_mqt lays Mq out for it: tile t
@@ -1046,6 +1224,7 @@ ColProblem make_col_problem(const LoopArgs &a, const LoopWs &w, int tpw) {
   P.gred = (a.m + RED_CHUNK - 1) / RED_CHUNK + (a.l + RED_CHUNK - 1) / RED_CHUNK;
   P.scaling = a.scaling;
   P.defer = a.defer;
+  P.c0 = a.c0;
   P.aligned = ((uintptr_t)a.W % 16 == 0) && ((a.ldw * (int64_t)es) % 16 == 0);
   P.part = w.part;
   P.y = w.y;
@@ -1143,6 +1322,13 @@ int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, int o
                             double *G, hipStream_t st) {
   if (a.m > MAXM) return RHQR_ERR_UNSUPPORTED;
   RHQR_DISPATCH(a.dtype, run_blocked_typed<ST>(a, w, panel, outer, C, G, st))
+}
+
+int run_column_loop_alg5(const rhqr_sketch_s *h, const LoopArgs &a, const LoopWs &w, int b,
+                         double *C, double *G, double *Z, void *skws, size_t skws_bytes,
+                         hipStream_t st) {
+  if (a.m > MAXM) return RHQR_ERR_UNSUPPORTED;
+  RHQR_DISPATCH(a.dtype, run_alg5_typed<ST>(h, a, w, b, C, G, Z, skws, skws_bytes, st))
 }
 
 int engine_step(const LoopArgs &a, const LoopWs &w, int32_t j, int next, hipStream_t st) {

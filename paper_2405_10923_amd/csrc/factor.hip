@@ -23,11 +23,23 @@ struct FactorWs {
   void *qmf;      // split coefficients of the matrix-core thin Q
 };
 
+// the multi-column sketch workspace for m columns, or for any block of at most
+// 32 columns (block RHQR sketches one block at a time; fewer columns can take
+// more partial groups each)
+size_t factor_sketch_ws(const rhqr_sketch_s *h, int32_t m) {
+  size_t b = sketch_ws_bytes(h, m);
+  for (int32_t k = 1; k <= 32 && k <= m; ++k) {
+    const size_t bk = sketch_ws_bytes(h, k);
+    if (bk > b) b = bk;
+  }
+  return b;
+}
+
 size_t factor_ws_bytes(const rhqr_sketch_s *h, int dtype, int32_t m) {
   const int32_t L = h->l + m;
   size_t b = loop_ws_bytes(h->kind, dtype, h->n, m, h->l);
   b += align_up(sizeof(double) * (size_t)L * m);
-  b += align_up(sketch_ws_bytes(h, m));
+  b += align_up(factor_sketch_ws(h, m));
   b += align_up(sizeof(double) * (size_t)m * m);
   b += 2 * align_up(sizeof(double) * (size_t)m * 32);
   b += thin_q_bytes(m);
@@ -45,7 +57,7 @@ int factor_ws_carve(const rhqr_sketch_s *h, int dtype, int32_t m, void *ws, size
   o->Z = (double *)p;
   p += align_up(sizeof(double) * (size_t)L * m);
   o->skws = p;
-  o->skws_bytes = align_up(sketch_ws_bytes(h, m));
+  o->skws_bytes = align_up(factor_sketch_ws(h, m));
   p += o->skws_bytes;
   o->Mq = (double *)p;
   p += align_up(sizeof(double) * (size_t)m * m);
@@ -71,8 +83,10 @@ bool opts_ok(int opts) {
   const int panel = (opts >> 8) & 0xff;
   const int outer = (opts >> 16) & 0xff;
   const int tpw = (opts >> 24) & 0xf;
+  const bool alg5 = (opts >> 28) & 1;
   return !((scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) || panel > 32 ||
-           ((unsigned)opts >> 28) != 0 || (tpw != 0 && tpw != 1 && tpw != 2 && tpw != 4) ||
+           ((unsigned)opts >> 29) != 0 || (tpw != 0 && tpw != 1 && tpw != 2 && tpw != 4) ||
+           (alg5 && (panel < 1 || outer != 0)) ||
            (outer != 0 && (panel < 2 || outer <= panel || outer > 32 || outer % panel != 0)));
 }
 
@@ -90,10 +104,14 @@ int factor_core(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W, int
   if (rc) return rc;
   hipLaunchKernelGGL(k_zero_sq, dim3((m + 255) / 256, m), dim3(256), 0, st, d_T, ldt, m, m);
   RHQR_HIP(hipGetLastError());
+  const bool alg5 = (opts >> 28) & 1;
 
   // pre-sketch of every column: "if next vector available, sketch it now"
-  rc = launch_sketch(h, dtype, n, m, d_W, ldw, w.Z, L, w.skws, w.skws_bytes, st);
-  if (rc) return rc;
+  // (block RHQR sketches each block afresh instead)
+  if (!alg5) {
+    rc = launch_sketch(h, dtype, n, m, d_W, ldw, w.Z, L, w.skws, w.skws_bytes, st);
+    if (rc) return rc;
+  }
 
   LoopArgs a;
   a.kind = h->kind;
@@ -117,8 +135,11 @@ int factor_core(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W, int
   a.omega = h->d_omega;
   a.defer = 1;
   a.tpw = (opts >> 24) & 0xf;
-  rc = panel >= 2 ? run_column_loop_blocked(a, w.loop, panel, outer, w.C, w.G, st)
-                  : run_column_loop(a, w.loop, st);
+  if (alg5)
+    rc = run_column_loop_alg5(h, a, w.loop, panel, w.C, w.G, w.Z, w.skws, w.skws_bytes, st);
+  else
+    rc = panel >= 2 ? run_column_loop_blocked(a, w.loop, panel, outer, w.C, w.G, st)
+                    : run_column_loop(a, w.loop, st);
   if (rc) return rc;
   if (d_Q) rc = launch_thin_q(dtype, n, m, d_W, ldw, d_S, lds, d_T, ldt, w.Mq, w.qmf, d_Q, ldq, st);
   return rc;
