@@ -537,6 +537,42 @@ def run_alg5(rhqr, torch, sk, W64, m, steps, blocks=(32, 8)):
     return out
 
 
+def run_trim(rhqr, torch, steps, n=1 << 20, m=128, l=64):
+    """Left-looking trimRHQR (Alg. 12) of a 2^20 x 128 float64 matrix (cond
+    1e12) with an SRHT of l = 64 < m rows on every row: time per
+    factorization, the refresh kernel against its algorithmic bytes (launch j
+    reads the j stored columns and column j and writes column j), e_fact."""
+    from paper_2405_10923_amd.inputs import synthetic_matrix_torch
+    W0 = synthetic_matrix_torch(n, m, 12, seed=0, device="cuda")
+    W = rhqr.colmajor_empty(n, m, torch.float64, W0.device)
+    sk = rhqr.Sketch(rhqr.SRHT, n, 0, l, seed=0)
+    W.copy_(W0)
+    rhqr.trim(sk, W, want_q=False)
+    ms = _time(torch, lambda: rhqr.trim(sk, W, want_q=False), steps, 1, lambda: W.copy_(W0))
+    rhqr.profile_begin()
+    for _ in range(steps):
+        W.copy_(W0)
+        rhqr.trim(sk, W, want_q=False)
+    torch.cuda.synchronize()
+    prof = rhqr.profile_end()
+    W.copy_(W0)
+    out = rhqr.trim(sk, W, want_q=True)
+    ef = float(torch.linalg.norm(W0 - out["Q"] @ out["R"]) / torch.linalg.norm(W0))
+    info = rhqr.status(out["ws"])
+    ms_ref, cnt = prof["tall"]
+    byts = 8.0 * n * sum(j + 2 for j in range(1, m)) * steps
+    ach = byts / (ms_ref * 1e-3) / 1e9 if cnt else None
+    del W, W0, out
+    torch.cuda.empty_cache()
+    return {"workload": f"trimRHQR float64 {n} x {m} cond 1e12, SRHT l = {l} (< m) on every row",
+            "ms": round(ms, 3), "e_fact": ef, "info": info,
+            "refresh_kernel": {"launches_per_step": cnt // steps if cnt else 0,
+                               "avg_launch_ms": round(ms_ref / cnt, 4) if cnt else None,
+                               "achieved_GBps": round(ach, 1) if ach else None,
+                               "frac_hbm": round(ach / HBM_PEAK_GBS, 4) if ach else None},
+            "kernels_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items() if v[1]}}
+
+
 def run_c2(rhqr, torch, steps):
     """2^20 x 128, cond 1e12, float64: RHQR with the SRHT and the Gaussian
     sketch (l = 512, blocked schedule) and recRHQR (SRHT)."""
@@ -737,6 +773,8 @@ def main():
         torch.cuda.empty_cache()
         extra["c2_f64"] = run_c2(rhqr, torch, max(2, args.steps // 2))
         print(f"# 2^20 x 128: {json.dumps(extra['c2_f64'])}", file=sys.stderr, flush=True)
+        extra["trim_rhqr"] = run_trim(rhqr, torch, max(2, args.steps // 2))
+        print(f"# trimRHQR: {json.dumps(extra['trim_rhqr'])}", file=sys.stderr, flush=True)
         extra["gmres_c5"] = run_gmres_c5(rhqr, torch)
         print(f"# GMRES c5: {json.dumps(extra['gmres_c5'])}", file=sys.stderr, flush=True)
 

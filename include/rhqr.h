@@ -74,7 +74,9 @@ typedef struct rhqr_arnoldi_s *rhqr_arnoldi_t;
 /* ------------------------------------------------------------------------
  * Sketch handle.  Draws Psi for problems with n rows and an m-row head.
  *   kind   : RHQR_SKETCH_SRHT or RHQR_SKETCH_GAUSS
- *   n, m, l: 0 < m < n, 0 < l <= N (SRHT; l <= 4096) or l >= 1 (GAUSS)
+ *   n, m, l: 0 <= m < n, 0 < l <= N (SRHT; l <= 4096) or l >= 1 (GAUSS);
+ *            m = 0 gives Psi = Omega on every row (for rhqr_trim_factor; the
+ *            entry points built on Psi = [I_m 0; 0 Omega] need m >= 1)
  *   seed   : Philox4x64-10 key word 0 (key word 1 selects the stream)
  *   d_omega: GAUSS only, optional caller-supplied l x (n-m) float64 Omega
  *            (ld_omega >= l); it is copied.  NULL: Omega is drawn on the
@@ -210,6 +212,33 @@ RHQR_API int rhqr_rgs_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, c
                              int64_t ldw, void *d_Q, int64_t ldq, double *d_S, int64_t lds,
                              double *d_T, int64_t ldt, double *d_R, int64_t ldr, int opts,
                              void *d_ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * rhqr_trim_factor: left-looking trimRHQR (Alg. 12, Sec. 7) with
+ * trimRHVector (Alg. 10): reflectors H_j = I - beta u (Omega u)^t
+ * [0 Omega_{j:n}] that sketch only the rows from their pivot on, with an
+ * Omega (l x n) over every row, so l may be smaller than m.
+ *   h     : SRHT sketch handle with head 0 (rhqr_sketch_create(..., n, 0, l,
+ *           ...)): its Omega acts on all n rows; its columns have unit norm,
+ *           which the elimination needs (the Gaussian sketch's do not)
+ *   dtype : RHQR_F64 or RHQR_F32 (n-row arithmetic in that type)
+ *   d_W   : n x m, overwritten by U (u_j zero above row j; unit pivot in the
+ *           UNIT_PIVOT scaling), 1 <= m <= min(n, 1024)
+ *   d_S   : l x m float64 (lds = l), S = Omega U
+ *   d_T   : m x m float64: H_1 ... H_m = I - U T ut((Omega U)^t Omega)
+ *   d_Tt  : m x m float64 (T~): H_m ... H_1 = I - U T~^t ut((Omega U)^t Omega)
+ *   d_R   : m x m float64 upper triangular: W = H_1 ... H_m [R; 0]
+ *   d_Q   : optional n x m thin factor Q = H_1 ... H_m [I_m; 0] in dtype
+ *   opts  : bits 0-7 rhqr_scaling (alpha = 1/v_j, or sqrt 2 / ||Omega v||)
+ *   d_ws  : rhqr_trim_workspace_size(h, dtype, m) bytes
+ * One synchronisation per column (the sketch of the refreshed column).
+ * Breakdown and non-finite columns are reported by rhqr_status(d_ws).
+ * ---------------------------------------------------------------------- */
+RHQR_API size_t rhqr_trim_workspace_size(rhqr_sketch_t h, int dtype, int32_t m);
+RHQR_API int rhqr_trim_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W,
+                              int64_t ldw, double *d_S, int64_t lds, double *d_T, int64_t ldt,
+                              double *d_Tt, int64_t ldtt, double *d_R, int64_t ldr, void *d_Q,
+                              int64_t ldq, int opts, void *d_ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * Column scaling for low-precision storage (the mixed-precision experiment of

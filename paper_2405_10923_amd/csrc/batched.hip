@@ -262,7 +262,7 @@ int check_problems(const rhqr_problem *probs, int32_t count, int dtype) {
     const rhqr_problem &q = probs[i];
     const rhqr_sketch_s *h = q.sketch;
     if (!h || h->kind != RHQR_SKETCH_SRHT) return -1;
-    if (h->m > MAXM || h->l > 4096) return -1;
+    if (h->m < 1 || h->m > MAXM || h->l > 4096) return -1;
     if (!q.d_W || q.ldw < h->n) return -1;
     if (!q.d_S || q.lds < h->l + h->m) return -1;
     if (!q.d_T || q.ldt < h->m) return -1;

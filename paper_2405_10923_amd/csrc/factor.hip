@@ -72,7 +72,7 @@ int factor_ws_carve(const rhqr_sketch_s *h, int dtype, int32_t m, void *ws, size
 }  // namespace
 
 extern "C" size_t rhqr_factor_workspace_size(rhqr_sketch_t h, int dtype, int32_t m) {
-  if (!h || m != h->m || dtype < RHQR_F64 || dtype > RHQR_BF16) return 0;
+  if (!h || m < 1 || m != h->m || dtype < RHQR_F64 || dtype > RHQR_BF16) return 0;
   return factor_ws_bytes(h, dtype, m);
 }
 
@@ -180,7 +180,7 @@ extern "C" int rhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, voi
   if (!h) return -1;
   if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -2;
   if (n != h->n) return -3;
-  if (m != h->m) return -4;
+  if (m < 1 || m != h->m) return -4;
   if (!d_W) return -5;
   if (ldw < n) return -6;
   const int32_t L = h->l + m;
@@ -212,7 +212,7 @@ extern "C" int rhqr_rgs_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m,
   if (!h) return -1;
   if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -2;
   if (n < 1 || n + m != h->n) return -3;
-  if (m != h->m) return -4;
+  if (m < 1 || m != h->m) return -4;
   if (!d_W) return -5;
   if (ldw < n) return -6;
   if (!d_Q) return -7;
@@ -311,7 +311,7 @@ extern "C" int rhqr_factor_noalloc(rhqr_sketch_t h, int dtype, int64_t n, int32_
   if (!h) return -1;
   if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -2;
   if (n != h->n) return -3;
-  if (m != h->m) return -4;
+  if (m < 1 || m != h->m) return -4;
   if (!d_W) return -5;
   if (ldw < n) return -6;
   const int32_t L = h->l + m;

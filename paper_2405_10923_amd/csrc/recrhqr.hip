@@ -475,7 +475,7 @@ int sketch_space_hqr(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, d
 }
 
 extern "C" size_t recrhqr_workspace_size(rhqr_sketch_t h, int dtype, int32_t m) {
-  if (!h || m != h->m || dtype < RHQR_F64 || dtype > RHQR_BF16) return 0;
+  if (!h || m < 1 || m != h->m || dtype < RHQR_F64 || dtype > RHQR_BF16) return 0;
   return rec_ws_bytes(h, dtype, m);
 }
 
@@ -486,7 +486,7 @@ extern "C" int recrhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, 
   if (!h) return -1;
   if (dtype < RHQR_F64 || dtype > RHQR_BF16) return -2;
   if (n != h->n) return -3;
-  if (m != h->m) return -4;
+  if (m < 1 || m != h->m) return -4;
   if (!d_W) return -5;
   if (ldw < n) return -6;
   if (mode == RHQR_REC_M && !d_U) return -7;

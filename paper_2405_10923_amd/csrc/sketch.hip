@@ -395,7 +395,7 @@ extern "C" int rhqr_sketch_create(int kind, int64_t n, int32_t m, int32_t l, uin
                                   rhqr_sketch_t *out) {
   if (kind != RHQR_SKETCH_SRHT && kind != RHQR_SKETCH_GAUSS) return -1;
   if (n < 2) return -2;
-  if (m < 1 || m >= n) return -3;
+  if (m < 0 || m >= n) return -3;  // m = 0: Omega on every row (trimRHQR)
   int64_t N = 1;
   while (N < n) N <<= 1;
   if (l < 1 || (kind == RHQR_SKETCH_SRHT && (l > N || l > TILE))) return -4;

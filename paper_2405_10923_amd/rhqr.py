@@ -58,6 +58,9 @@ _SIGS = {
     "rhqr_batch_factor": (C.c_int, [_vp, C.c_int, _vp]),
     "rhqr_batch_status": (C.c_int, [_vp, _vp, _vp]),
     "rhqr_batch_destroy": (C.c_int, [_vp]),
+    "rhqr_trim_workspace_size": (_sz, [_vp, C.c_int, _i32]),
+    "rhqr_trim_factor": (C.c_int, [_vp, C.c_int, _i64, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
+                                   _i64, _vp, _i64, _vp, _i64, C.c_int, _vp, _sz, _vp]),
     "rhqr_colscale": (C.c_int, [C.c_int, _i64, _i32, _vp, _i64, _vp, _i64, _vp, _vp]),
     "rhqr_scale_r": (C.c_int, [_i32, _vp, _i64, _vp, _vp]),
     "rhqr_profile_begin": (C.c_int, []),
@@ -258,6 +261,28 @@ def rgs(sk, W, panel=0, outer=0):
                                _stream())
     _check(rc, "rhqr_rgs_factor")
     return dict(Q=Qb[m:], Qfull=Qb, S=S, T=T, R=R, ws=ws)
+
+
+def trim(sk, W, scaling=SCALE_UNIT_PIVOT, want_q=True):
+    """Left-looking trimRHQR (Alg. 12) by rhqr_trim_factor.  ``sk`` is an SRHT
+    sketch with head 0 (Omega on every row: Sketch(SRHT, n, 0, l)); W (n x m,
+    column-major, GPU, float64 or float32) is overwritten by U.  Returns
+    dict(U, S = Omega U, T, Tt, R, Q, ws)."""
+    torch = _torch()
+    n, m = W.shape
+    dev = W.device
+    S = colmajor_empty(sk.l, m, torch.float64, dev)
+    T = colmajor_empty(m, m, torch.float64, dev)
+    Tt = colmajor_empty(m, m, torch.float64, dev)
+    R = colmajor_empty(m, m, torch.float64, dev)
+    Q = colmajor_empty(n, m, W.dtype, dev) if want_q else None
+    ws = workspace(lib().rhqr_trim_workspace_size(sk.h, dtype_code(W.dtype), m), dev)
+    rc = lib().rhqr_trim_factor(sk.h, dtype_code(W.dtype), n, m, _ptr(W), _ld(W), _ptr(S), sk.l,
+                                _ptr(T), _ld(T), _ptr(Tt), _ld(Tt), _ptr(R), _ld(R), _ptr(Q),
+                                _ld(Q) if Q is not None else 0, int(scaling), _ptr(ws), ws.numel(),
+                                _stream())
+    _check(rc, "rhqr_trim_factor")
+    return dict(U=W, S=S, T=T, Tt=Tt, R=R, Q=Q, ws=ws)
 
 
 def colscale(W64, dtype, out=None, scale=None):

@@ -66,7 +66,7 @@ def test_sketch_create_argument_errors():
     bh = ctypes.byref(h)
     assert L.rhqr_sketch_create(7, 100, 4, 8, 0, None, 0, None, bh) == -1
     assert L.rhqr_sketch_create(0, 1, 4, 8, 0, None, 0, None, bh) == -2
-    assert L.rhqr_sketch_create(0, 100, 0, 8, 0, None, 0, None, bh) == -3
+    assert L.rhqr_sketch_create(0, 100, -1, 8, 0, None, 0, None, bh) == -3
     assert L.rhqr_sketch_create(0, 100, 100, 8, 0, None, 0, None, bh) == -3
     assert L.rhqr_sketch_create(0, 100, 4, 0, 0, None, 0, None, bh) == -4
     assert L.rhqr_sketch_create(0, 100, 4, 129, 0, None, 0, None, bh) == -4      # l > N = 128
@@ -82,6 +82,9 @@ def test_null_handle_errors():
     assert L.rhqr_sketch_workspace_size(None, 4) == 0
     assert L.rhqr_factor_workspace_size(None, 0, 4) == 0
     assert L.recrhqr_workspace_size(None, 0, 4) == 0
+    assert L.rhqr_trim_workspace_size(None, 0, 4) == 0
+    assert L.rhqr_trim_factor(None, 0, 100, 4, FAKE, 100, FAKE, 8, FAKE, 4, FAKE, 4, FAKE, 4,
+                              None, 0, 0, FAKE, 1 << 20, None) == -1
     assert L.rhqr_sketch(None, 0, 100, 4, FAKE, 100, FAKE, 12, FAKE, 1 << 20, None) == -1
     assert L.rhqr_factor(None, 0, 100, 4, FAKE, 100, FAKE, 12, FAKE, 4, FAKE, 4, None, 0, 0,
                          FAKE, 1 << 20, None) == -1
