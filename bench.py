@@ -326,7 +326,8 @@ def run_case(rhqr, torch, sk, W64, n, m, l, dt, panel, outer, steps, warmup, pro
             ms, cnt = prof.get(key, (0.0, 0))
             if cnt:
                 tkey = {"tall": "k_tall_column" if panel < 2 else "k_tall_blocked",
-                        "panel_mx": "k_panel_mx", "panel_valu": "k_panel_valu"}.get(key)
+                        "panel_mx": "k_panel_mx", "panel_valu": "k_panel_valu",
+                        "presketch": "k_srht_cols"}.get(key)
                 traffic = measured_traffic(tkey) if (es == 8 and tkey) else None
                 kern.append(kernel_entry(key, ms, cnt, steps, kb.get(key), traffic))
         kern.sort(key=lambda k: -k["ms_per_step"])
@@ -685,6 +686,10 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="first copy a GIB-sized buffer three times (a plain copy kernel of "
                          "known traffic, to scale hardware byte counters)")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="run only the matrix-core kernels once each (a float64 and a float16 "
+                         "factorization with thin Q at the workload's size, the Gaussian "
+                         "pre-sketch of a 2^20 x 128 matrix with l = 512), for counter runs")
     ap.add_argument("--print-digest", action="store_true",
                     help="print the digest of the kernel sources and exit")
     args = ap.parse_args()
@@ -715,6 +720,20 @@ def main():
     print(f"# workload n={n} m={m} l={l} cond=1e{kappa:g}", file=sys.stderr, flush=True)
     W64 = synthetic_matrix_torch(n, m, kappa, seed=0, device="cuda")
     sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=0)
+    if args.mfma_probe:
+        for name in ("float64", "float16"):
+            dt = getattr(torch, name)
+            Wst = W64 if dt == torch.float64 else rhqr.colscale(W64, dt)[0]
+            p_, o_, t_, _ = lookup(name, n, m)
+            rhqr.factor(sk, Wst.clone(), want_q=True, panel=p_, outer=o_, tpw=t_)
+        del W64
+        n2, m2, l2 = 1 << 20, 128, 512
+        W2 = synthetic_matrix_torch(n2, m2, 12, seed=0, device="cuda")
+        skg = rhqr.Sketch(rhqr.GAUSS, n2, m2, l2, seed=0)
+        rhqr.sketch(skg, W2)
+        torch.cuda.synchronize()
+        print(json.dumps({"mfma_probe": "done"}), flush=True)
+        return
     res, kern64 = {}, []
     scheds = {}
     for name in args.dtypes.split(","):

@@ -1147,6 +1147,56 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
   return RHQR_OK;
 }
 
+// ------------------------------------------------ row-resident substitution
+// X M = B with every row of X solved by its own thread: x_c = (b_c - sum_{k<c}
+// x_k M_kc) / M_cc, the x_k kept in registers (the column loop is unrolled
+// over MC >= m), so W_2 is read once and U_2 written once (the blocked kernel
+// above re-reads the solved columns once per block).  The coefficients are a
+// padded MC x MC copy of M (identity beyond m; uniform scalar loads).  The
+// sum over k is formed in four interleaved partial sums (k mod 4), added in a
+// fixed order.  Arithmetic in float64 for float64 storage, float32 otherwise,
+// with a single rounding to the storage type per element.
+template <int MC>
+__global__ void k_trsm_pad(int32_t m, const double *__restrict__ M, int64_t ldm,
+                           double *__restrict__ Mp) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (k >= MC) return;
+  double v = 0.0;
+  if (k < m && c < m) v = k <= c ? M[k + (int64_t)c * ldm] : 0.0;
+  else if (k == c) v = 1.0;
+  Mp[k + (int64_t)c * MC] = v;
+}
+
+constexpr int TR_RB = 64;  // rows (threads) per workgroup
+template <typename ST, int MC>
+__global__ void __launch_bounds__(TR_RB) k_trsm_rows(const ST *__restrict__ B, int64_t ldb,
+                                                     ST *__restrict__ X, int64_t ldx, int64_t rows,
+                                                     int32_t m, const double *__restrict__ Mp) {
+  using CT = typename CompT<ST>::type;
+  const int64_t i = (int64_t)blockIdx.x * TR_RB + threadIdx.x;
+  if (i >= rows) return;
+  const ST *b = B + i;
+  ST *x_out = X + i;
+  constexpr int PF = 8;  // columns of B loaded ahead
+  CT x[MC];
+  CT bq[PF];
+#pragma unroll
+  for (int c = 0; c < PF; ++c) bq[c] = c < m ? cvt_in<CT>(b[(int64_t)c * ldb]) : (CT)0;
+#pragma unroll
+  for (int c = 0; c < MC; ++c) {
+    const CT bc = bq[c % PF];
+    if (c + PF < MC) bq[c % PF] = c + PF < m ? cvt_in<CT>(b[(int64_t)(c + PF) * ldb]) : (CT)0;
+    const double *mc = Mp + (int64_t)c * MC;
+    CT s[4] = {(CT)0, (CT)0, (CT)0, (CT)0};
+#pragma unroll
+    for (int k = 0; k < c; ++k) s[k & 3] += x[k] * (CT)mc[k];
+    const CT v = (bc - ((s[0] + s[1]) + (s[2] + s[3]))) / (CT)mc[c];
+    x[c] = v;
+    if (c < m) x_out[(int64_t)c * ldx] = cvt_out<ST>((double)v);
+  }
+}
+
 template <typename ST>
 int trsm_blocked_typed(const ST *B, int64_t ldb, int64_t rows, int32_t m, const double *M,
                        int64_t ldm, ST *X, int64_t ldx, double *coef, float *stage,
@@ -1158,6 +1208,26 @@ int trsm_blocked_typed(const ST *B, int64_t ldb, int64_t rows, int32_t m, const 
                       ((ldb * (int64_t)sizeof(ST)) % 16 == 0) &&
                       ((ldx * (int64_t)sizeof(ST)) % 16 == 0) &&
                       (sizeof(ST) != 2 || (uintptr_t)stage % 16 == 0);
+  // m within the register-resident kernel's reach: one pass, every row its own
+  // substitution (64 columns for 2-byte storage keep the float32 unknowns in
+  // 64 registers; 128 for float32 / float64)
+  {
+    const dim3 rg((unsigned)((rows + TR_RB - 1) / TR_RB));
+#define RHQR_TRSM_ROWS(MCV)                                                                     \
+  do {                                                                                          \
+    hipLaunchKernelGGL(k_trsm_pad<MCV>, dim3((MCV + 255) / 256, MCV), dim3(256), 0, st, m, M,   \
+                       ldm, coef);                                                              \
+    RHQR_HIP(hipGetLastError());                                                                \
+    RHQR_LAUNCH(RHQR_PROF_TRSM, (k_trsm_rows<ST, MCV>), rg, dim3(TR_RB), 0, st, B, ldb, X, ldx, \
+                rows, m, (const double *)coef);                                                 \
+    return RHQR_OK;                                                                             \
+  } while (0)
+    if (m <= 16) RHQR_TRSM_ROWS(16);
+    if (m <= 32) RHQR_TRSM_ROWS(32);
+    if (m <= 64) RHQR_TRSM_ROWS(64);
+    if (m <= 128) RHQR_TRSM_ROWS(128);
+#undef RHQR_TRSM_ROWS
+  }
   double *Ct = coef, *Md = coef + (size_t)m * TRSM_NB;
   const dim3 grid((unsigned)((rows + (int64_t)PANEL_TPB * VEC - 1) / ((int64_t)PANEL_TPB * VEC)));
   for (int32_t J = 0; J < m; J += TRSM_NB) {
@@ -1174,7 +1244,13 @@ int trsm_blocked_typed(const ST *B, int64_t ldb, int64_t rows, int32_t m, const 
 
 }  // namespace
 
-size_t trsm_coef_bytes(int32_t m) { return align_up(sizeof(double) * ((size_t)m * TRSM_NB + 256)); }
+size_t trsm_coef_bytes(int32_t m) {
+  // the blocked kernel's tables, or the padded copy of M of the row kernel
+  const size_t blk = (size_t)m * TRSM_NB + 256;
+  const size_t mc = m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 128;
+  const size_t pad = m <= 128 ? mc * mc : 0;
+  return align_up(sizeof(double) * (blk > pad ? blk : pad));
+}
 
 size_t trsm_stage_bytes(int dtype, int64_t rows, int32_t m) {
   return dtype_size(dtype) == 2 ? align_up(sizeof(float) * (size_t)((rows + 3) & ~(int64_t)3) * m) : 0;
