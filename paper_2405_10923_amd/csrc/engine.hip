@@ -21,6 +21,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <type_traits>
 #include <vector>
@@ -1147,53 +1148,175 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
   return RHQR_OK;
 }
 
-// ------------------------------------------------ row-resident substitution
-// X M = B with every row of X solved by its own thread: x_c = (b_c - sum_{k<c}
-// x_k M_kc) / M_cc, the x_k kept in registers (the column loop is unrolled
-// over MC >= m), so W_2 is read once and U_2 written once (the blocked kernel
-// above re-reads the solved columns once per block).  The coefficients are a
-// padded MC x MC copy of M (identity beyond m; uniform scalar loads).  The
-// sum over k is formed in four interleaved partial sums (k mod 4), added in a
-// fixed order.  Arithmetic in float64 for float64 storage, float32 otherwise,
-// with a single rounding to the storage type per element.
-template <int MC>
-__global__ void k_trsm_pad(int32_t m, const double *__restrict__ M, int64_t ldm,
-                           double *__restrict__ Mp) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
-  if (k >= MC) return;
-  double v = 0.0;
-  if (k < m && c < m) v = k <= c ? M[k + (int64_t)c * ldm] : 0.0;
-  else if (k == c) v = 1.0;
-  Mp[k + (int64_t)c * MC] = v;
+// compute units of the current device (cached per device; 256 if unknown)
+inline int device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int c = cache[dev].load(std::memory_order_relaxed);
+  if (c > 0) return c;
+  if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
+    c = 256;
+  cache[dev].store(c, std::memory_order_relaxed);
+  return c;
 }
 
-constexpr int TR_RB = 64;  // rows (threads) per workgroup
-template <typename ST, int MC>
-__global__ void __launch_bounds__(TR_RB) k_trsm_rows(const ST *__restrict__ B, int64_t ldb,
-                                                     ST *__restrict__ X, int64_t ldx, int64_t rows,
-                                                     int32_t m, const double *__restrict__ Mp) {
+// ------------------------------------------- substitution on matrix cores
+// X M = B (m <= 128) with one wave per 16 rows and every unknown of those rows
+// kept in registers, so B is read once and X written once.  The columns are
+// taken in blocks of 16:
+//   X_b = (B_b - sum_{b' < b} X_{b'} M_{b', b}) M_{b, b}^{-1}.
+// The products run on v_mfma_f64_16x16x4 (float32 unknowns for float32 and
+// 2-byte storage: v_mfma_f32_16x16x4), transposed as in the panel update, so a
+// block of unknowns sits in the accumulator layout: lane (g = lane / 16,
+// r = lane % 16) holds row r, columns 16 b + di(g, t), t < 4.  That is also
+// the layout of a product's right operand once the four columns a step
+// consumes are chosen as 16 b' + di(g, t) (one step per earlier block and t):
+// the solved blocks enter the products straight from their registers.  The
+// 16 x 16 triangle of a block is then solved by forward substitution, every
+// lane group redundantly over its row's 16 columns (gathered across the four
+// groups), keeping its own four: column c is scaled by 1 / M_cc and removed
+// from the later columns at once, so the later columns' sums still add the
+// terms k = 0, 1, ... in order.  The coefficients (a padded copy of M, row
+// pitch MC + 16 so that the four lane groups' rows fall on different LDS
+// banks, identity beyond m, then the reciprocals of the diagonal) are staged
+// in LDS once per workgroup; the waves loop over the 16-row strips.
+__host__ __device__ inline int trsm_ldp(int mc) { return mc + 16; }
+__global__ void k_trsm_pad(int32_t m, int32_t mc, const double *__restrict__ M, int64_t ldm,
+                           double *__restrict__ Mp) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  const int ldp = trsm_ldp(mc);
+  if (c >= ldp) return;
+  double v = 0.0;
+  if (c < mc) {
+    if (k < m && c < m) v = k <= c ? M[k + (int64_t)c * ldm] : 0.0;
+    else if (k == c) v = 1.0;
+  }
+  Mp[(int64_t)k * ldp + c] = v;
+  if (k == 0 && c < mc) Mp[(int64_t)mc * ldp + c] = c < m ? 1.0 / M[c + (int64_t)c * ldm] : 1.0;
+}
+
+constexpr int TM_WAVES = 16;  // waves per workgroup
+template <typename ST, int NB>
+__global__ void __launch_bounds__(TM_WAVES * 64) k_trsm_mx(const ST *__restrict__ B, int64_t ldb,
+                                                           ST *__restrict__ X, int64_t ldx,
+                                                           int64_t rows, int32_t m,
+                                                           const double *__restrict__ Mp) {
   using CT = typename CompT<ST>::type;
-  const int64_t i = (int64_t)blockIdx.x * TR_RB + threadIdx.x;
-  if (i >= rows) return;
-  const ST *b = B + i;
-  ST *x_out = X + i;
-  constexpr int PF = 8;  // columns of B loaded ahead
-  CT x[MC];
-  CT bq[PF];
+  using Ops = PxOps<CT>;
+  using acc_t = typename Ops::acc_t;
+  constexpr int MC = 16 * NB, LDP = MC + 16;
+  constexpr int NCOEF = MC * LDP + MC;
+  static_assert(NCOEF % 2 == 0, "16-byte staging");
+  extern __shared__ double Ml[];
+  for (int i = threadIdx.x; i < NCOEF / 2; i += TM_WAVES * 64)
+    reinterpret_cast<double2 *>(Ml)[i] = reinterpret_cast<const double2 *>(Mp)[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int64_t nstrips = (rows + 15) / 16;
+  for (int64_t sidx = (int64_t)blockIdx.x * TM_WAVES + w; sidx < nstrips;
+       sidx += (int64_t)gridDim.x * TM_WAVES) {
+    const int64_t row = sidx * 16 + r;
+    const bool rv = row < rows;
+    // the coefficients are the same for every strip and block: an opaque
+    // offset keeps their loads next to their use (hoisted, they would take
+    // every register)
+    int zoff = 0;
+    acc_t x[NB];
+    // every right-hand side of the strip, loaded at once (clamped indices,
+    // so the loads issue together without branches; out-of-range entries
+    // are replaced by zeros)
+    // column 16 b + di(g, t) = 16 b + di(0, t) + di(g, 0): one per-lane base
+    // and uniform offsets (only the last block can reach beyond m)
+    const ST *bg = B + (rv ? row : rows - 1) + (int64_t)Ops::di(g, 0) * ldb;
 #pragma unroll
-  for (int c = 0; c < PF; ++c) bq[c] = c < m ? cvt_in<CT>(b[(int64_t)c * ldb]) : (CT)0;
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-  for (int c = 0; c < MC; ++c) {
-    const CT bc = bq[c % PF];
-    if (c + PF < MC) bq[c % PF] = c + PF < m ? cvt_in<CT>(b[(int64_t)(c + PF) * ldb]) : (CT)0;
-    const double *mc = Mp + (int64_t)c * MC;
-    CT s[4] = {(CT)0, (CT)0, (CT)0, (CT)0};
+      for (int t = 0; t < 4; ++t) {
+        if (b + 1 < NB) {
+          x[b][t] = cvt_in<CT>(bg[(int64_t)(16 * b + Ops::di(0, t)) * ldb]);
+        } else {
+          const int col = 16 * b + Ops::di(g, t);
+          x[b][t] = cvt_in<CT>(B[(rv ? row : rows - 1) + (int64_t)(col < m ? col : m - 1) * ldb]);
+        }
+      }
 #pragma unroll
-    for (int k = 0; k < c; ++k) s[k & 3] += x[k] * (CT)mc[k];
-    const CT v = (bc - ((s[0] + s[1]) + (s[2] + s[3]))) / (CT)mc[c];
-    x[c] = v;
-    if (c < m) x_out[(int64_t)c * ldx] = cvt_out<ST>((double)v);
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int col = 16 * b + Ops::di(g, t);
+        if (!(rv && col < m)) x[b][t] = (CT)0;
+      }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      // this block's coefficient loads stay after the previous block's stores
+      asm volatile("" : "+v"(zoff));
+      const double *Mq = Ml + zoff;
+      // x_b -= X_{b'} M_{b', b}: left operand -M[16 b' + di(g, t)][16 b + r];
+      // the next earlier block's operands load while this one's products run
+      CT a[4], an[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[t] = (CT)(-Mq[Ops::di(g, t) * LDP + 16 * b + r]);
+#pragma unroll
+      for (int b2 = 0; b2 < b; ++b2) {
+        if (b2 + 1 < b) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            an[t] = (CT)(-Mq[(16 * (b2 + 1) + Ops::di(g, t)) * LDP + 16 * b + r]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x[b] = Ops::mma(a[t], x[b2][t], x[b]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = an[t];
+      }
+      // forward substitution over the diagonal block: column c (held by lane
+      // group gc, register tc) is scaled by 1 / M_cc, broadcast to the row's
+      // other lane groups and removed from their later columns
+      const double *md = Mq + 16 * b * LDP + 16 * b;
+      const double *iv = Mq + MC * LDP + 16 * b;
+      CT cf[4], cn[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) cf[t] = (CT)md[Ops::di(g, t)];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        int gc = 0, tc = 0;
+#pragma unroll
+        for (int g2 = 0; g2 < 4; ++g2)
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (Ops::di(g2, t) == c) {
+              gc = g2;
+              tc = t;
+            }
+        if (c + 1 < 16) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) cn[t] = (CT)md[(c + 1) * LDP + Ops::di(g, t)];
+        }
+        const CT icv = (CT)iv[c];
+        __builtin_amdgcn_sched_barrier(0);
+        const CT xc = __shfl(x[b][tc] * icv, 16 * gc + r, 64);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int col = Ops::di(g, t);
+          const CT upd = x[b][t] - xc * cf[t];
+          x[b][t] = col == c ? xc : (col > c ? upd : x[b][t]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) cf[t] = cn[t];
+      }
+      ST *xg = X + row + (int64_t)Ops::di(g, 0) * ldx;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int col = 16 * b + Ops::di(g, t);
+        if (rv && col < m)
+          xg[(int64_t)(16 * b + Ops::di(0, t)) * ldx] = cvt_out<ST>((double)x[b][t]);
+      }
+    }
   }
 }
 
@@ -1208,25 +1331,39 @@ int trsm_blocked_typed(const ST *B, int64_t ldb, int64_t rows, int32_t m, const 
                       ((ldb * (int64_t)sizeof(ST)) % 16 == 0) &&
                       ((ldx * (int64_t)sizeof(ST)) % 16 == 0) &&
                       (sizeof(ST) != 2 || (uintptr_t)stage % 16 == 0);
-  // m within the register-resident kernel's reach: one pass, every row its own
-  // substitution (64 columns for 2-byte storage keep the float32 unknowns in
-  // 64 registers; 128 for float32 / float64)
-  {
-    const dim3 rg((unsigned)((rows + TR_RB - 1) / TR_RB));
-#define RHQR_TRSM_ROWS(MCV)                                                                     \
-  do {                                                                                          \
-    hipLaunchKernelGGL(k_trsm_pad<MCV>, dim3((MCV + 255) / 256, MCV), dim3(256), 0, st, m, M,   \
-                       ldm, coef);                                                              \
-    RHQR_HIP(hipGetLastError());                                                                \
-    RHQR_LAUNCH(RHQR_PROF_TRSM, (k_trsm_rows<ST, MCV>), rg, dim3(TR_RB), 0, st, B, ldb, X, ldx, \
-                rows, m, (const double *)coef);                                                 \
-    return RHQR_OK;                                                                             \
-  } while (0)
-    if (m <= 16) RHQR_TRSM_ROWS(16);
-    if (m <= 32) RHQR_TRSM_ROWS(32);
-    if (m <= 64) RHQR_TRSM_ROWS(64);
-    if (m <= 128) RHQR_TRSM_ROWS(128);
-#undef RHQR_TRSM_ROWS
+  // m <= 128: one pass on matrix cores, every unknown in registers
+  if (m <= 128) {
+    const int nb16 = (m + 15) / 16, mc = 16 * nb16, ldp = trsm_ldp(mc);
+    hipLaunchKernelGGL(k_trsm_pad, dim3((ldp + 255) / 256, mc), dim3(256), 0, st, m, mc, M, ldm,
+                       coef);
+    RHQR_HIP(hipGetLastError());
+    const size_t shm = sizeof(double) * ((size_t)mc * ldp + mc);
+    const int64_t strips = (rows + 15) / 16;
+    const int64_t wgs = (strips + TM_WAVES - 1) / TM_WAVES;
+    // persistent workgroups: as many as the LDS of a compute unit holds (at most two)
+    const int64_t per_cu = shm * 2 + 2048 <= 160 * 1024 ? 2 : 1;
+    const int64_t cap = per_cu * device_cus();
+    const dim3 rg((unsigned)(wgs < cap ? wgs : cap));
+#define RHQR_TRSM_MX(NBV)                                                                    \
+  case NBV:                                                                                  \
+    RHQR_HIP(hipFuncSetAttribute((const void *)k_trsm_mx<ST, NBV>,                           \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));     \
+    RHQR_LAUNCH(RHQR_PROF_TRSM, (k_trsm_mx<ST, NBV>), rg, dim3(TM_WAVES * 64), shm, st, B, ldb, \
+                X, ldx, rows, m, (const double *)coef);                                      \
+    break
+    switch (nb16) {
+      RHQR_TRSM_MX(1);
+      RHQR_TRSM_MX(2);
+      RHQR_TRSM_MX(3);
+      RHQR_TRSM_MX(4);
+      RHQR_TRSM_MX(5);
+      RHQR_TRSM_MX(6);
+      RHQR_TRSM_MX(7);
+      RHQR_TRSM_MX(8);
+    }
+#undef RHQR_TRSM_MX
+    RHQR_HIP(hipGetLastError());
+    return RHQR_OK;
   }
   double *Ct = coef, *Md = coef + (size_t)m * TRSM_NB;
   const dim3 grid((unsigned)((rows + (int64_t)PANEL_TPB * VEC - 1) / ((int64_t)PANEL_TPB * VEC)));
@@ -1245,10 +1382,10 @@ int trsm_blocked_typed(const ST *B, int64_t ldb, int64_t rows, int32_t m, const 
 }  // namespace
 
 size_t trsm_coef_bytes(int32_t m) {
-  // the blocked kernel's tables, or the padded copy of M of the row kernel
+  // the blocked kernel's tables, or the padded copy of M of the matrix-core kernel
   const size_t blk = (size_t)m * TRSM_NB + 256;
-  const size_t mc = m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 128;
-  const size_t pad = m <= 128 ? mc * mc : 0;
+  const size_t mc = 16 * (size_t)((m + 15) / 16);
+  const size_t pad = m <= 128 ? mc * (size_t)trsm_ldp((int)mc) + mc : 0;
   return align_up(sizeof(double) * (blk > pad ? blk : pad));
 }
 

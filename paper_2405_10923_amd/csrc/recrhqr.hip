@@ -4,7 +4,7 @@
 //   S, T, R = HouseholderQR(Z)                 (float64, on the device: the
 //                                               column engine run with Psi = I)
 //   M = ut(T^t S^t Z)   (= -T U_1^t R, Sec. 3.3)
-//   U_2 M = W_2         (blocked forward substitution, launch_trsm_blocked)
+//   U_2 M = W_2         (forward substitution, launch_trsm_blocked)
 //   U = [S_{1:m}; U_2],  Q = [I; 0] - U T U_1^t (optional)
 // Mode RCHOL: Q = W R^-1 with the same substitution kernel.
 #include "engine.h"
@@ -118,63 +118,64 @@ __global__ void k_zero_mat(double *A, int64_t lda, int32_t rows, int32_t cols) {
 
 // ------------------------------------------- sketch-space Householder QR
 // Householder QR of the small L x m float64 sketch Z (overwritten),
-// right-looking in panels of SQ_NB columns, two launches per panel.
+// right-looking in panels of NB columns (16, or 8 for tall sketches).
 // k_hqr_panel (one workgroup) factors the panel in LDS one column at a time
 // (RHVector with Psi = I, Alg. 2: sigma, rho, gamma, alpha, beta; identity
-// reflector when rho = 0), writes its vectors to S and extends T by the
-// recursion of Prop. 3.2 (T_{:,j} = -beta_j T S^t s_j, in block form per
-// panel).  k_hqr_trail (one workgroup per trailing column) applies the panel's
-// block reflector, Z <- (I - S_p T_p^t S_p^t) Z.  Every reduction runs in a
-// fixed order.  The same factorization as the column engine with Psi = I,
-// in far fewer launches.
-constexpr int SQ_NB = 8, SQ_TPB = 1024;
-constexpr int SQ_MAXL = 2048;  // L + m at most: the panel (L x SQ_NB) and Y (m x SQ_NB) in LDS
+// reflector when rho = 0), writes its vectors to S and the panel's diagonal
+// block of T (Prop. 3.2 recursion within the panel).  Thread t owns the panel
+// rows r = t mod HQ_TPB for every column, so a column costs two workgroup
+// reductions (its norm, then its products with the later panel columns) and
+// no other synchronisation.  k_hqr_trail (one workgroup per trailing column)
+// applies the panel's block reflector, Z <- (I - S_p T_pp^t S_p^t) Z.  After
+// the last panel the off-diagonal blocks of T follow from the Gram matrix
+// G = S^t S: T_{<J, p} = -T_{<J,<J} G_{<J, p} T_pp (Prop. 3.2 in block form),
+// one launch per panel.  Every reduction runs in a fixed order.  The same
+// factorization as the column engine with Psi = I, in far fewer launches.
+constexpr int HQ_TPB = 256;
+constexpr int HQ_W = HQ_TPB / 64;
+constexpr int SQ_MAXL = 2048;  // L + m at most on this path (else the column engine)
 constexpr int SQ_MAXM = 1024;  // largest m (recrhqr_factor rejects larger)
-constexpr int SQ_RC = 8;       // rows per lane held in registers by a column pass (512 rows)
+constexpr size_t HQ_LDS_MAX = 150 * 1024;  // dynamic LDS budget of the panel kernel
 
-// sum over the workgroup of one value per thread, fixed order; all threads
-// get the result
-__device__ __forceinline__ double sq_block_sum(double v, double *red16) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  v = wave_sum(v);
-  __syncthreads();  // red16 may still be read by the previous sum
-  if (lane == 0) red16[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < SQ_TPB / 64; ++i) s += red16[i];
-  return s;
+// panel width for an L-row sketch: 16 when the panel fits the LDS budget
+inline int hqr_nb(int32_t L, int32_t m) {
+  return (size_t)L * 16 * sizeof(double) <= HQ_LDS_MAX && m <= 512 ? 16 : 8;
 }
 
-__global__ void __launch_bounds__(SQ_TPB) k_hqr_panel(int32_t L, int32_t m, int32_t J, double *Z,
+template <int NB>
+__global__ void __launch_bounds__(HQ_TPB) k_hqr_panel(int32_t L, int32_t m, int32_t J, double *Z,
                                                       int64_t ldz, double *S, int64_t lds,
                                                       double *T, int64_t ldt, double *R,
                                                       int64_t ldr, int scaling, int32_t *status) {
-  // panel: column c at Pn + c * rows, rows J .. L-1; after it, Y (J x SQ_NB)
+  // panel: column c at Pn + c * rows, local row r is row J + r
   extern __shared__ double Pn[];
-  __shared__ double red16[SQ_TPB / 64];
-  __shared__ double redv[SQ_TPB / 64][SQ_NB];
-  __shared__ double gv[SQ_MAXM];
-  __shared__ double bet[SQ_NB];
-  __shared__ double Tp[SQ_NB][SQ_NB];  // T_pp (upper triangle), also written to T
+  __shared__ double nrm[2][HQ_W];
+  __shared__ double red[2][HQ_W][NB];
+  __shared__ double gp[NB][NB];  // s_q^t s_c over the panel (q < c)
+  __shared__ double bet[NB], spv[NB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int nb = m - J < SQ_NB ? m - J : SQ_NB;
+  const int nb = m - J < NB ? m - J : NB;
   const int rows = L - J;
-  // the panel's rows J.. into LDS; its rows < J are final entries of R
-  for (int e = tid; e < rows * nb; e += SQ_TPB) {
+  for (int e = tid; e < rows * nb; e += HQ_TPB) {
     const int r = e % rows, c = e / rows;
     Pn[c * rows + r] = Z[(J + r) + (int64_t)(J + c) * ldz];
   }
-  for (int e = tid; e < J * nb; e += SQ_TPB) {
+  for (int e = tid; e < J * nb; e += HQ_TPB) {
     const int r = e % J, c = e / J;
     R[r + (int64_t)(J + c) * ldr] = Z[r + (int64_t)(J + c) * ldz];
   }
   __syncthreads();
   for (int c = 0; c < nb; ++c) {
-    const int j = J + c;
-    double *x = Pn + c * rows;  // local row r is row J + r; the pivot is local row c
+    const int j = J + c, b = c & 1;
+    double *x = Pn + c * rows;  // the pivot is local row c
     double ss = 0.0;
-    for (int r = c + tid; r < rows; r += SQ_TPB) ss += x[r] * x[r];
-    ss = sq_block_sum(ss, red16);
+    for (int r = tid; r < rows; r += HQ_TPB) ss += r >= c ? x[r] * x[r] : 0.0;
+    ss = wave_sum(ss);
+    if (lane == 0) nrm[b][w] = ss;
+    __syncthreads();  // the norm partials; the pivot (updated by its owner) is final
+    ss = 0.0;
+#pragma unroll
+    for (int i = 0; i < HQ_W; ++i) ss += nrm[b][i];
     // RHVector scalars (every thread computes the same values)
     const double rho = sqrt(ss);
     const double yj = x[c];
@@ -192,189 +193,125 @@ __global__ void __launch_bounds__(SQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
       }
     }
     const double sr = sigma * rho;
-    __syncthreads();  // every thread has read x[c]
-    // R column j: rows J..j-1 from the panel, -sigma rho on the diagonal, zeros below
-    for (int r = tid; r < m; r += SQ_TPB) {
-      if (r >= J && r < j) R[r + (int64_t)j * ldr] = x[r - J];
-      else if (r == j) R[r + (int64_t)j * ldr] = -sr;
-      else if (r > j) R[r + (int64_t)j * ldr] = 0.0;
-    }
-    __syncthreads();  // the R entries above the pivot have been read
-    // s_j in place of the column
-    for (int r = tid; r < rows; r += SQ_TPB) {
-      double sv = 0.0;
-      if (r == c)
-        sv = ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : gamma / alpha);
-      else if (r > c)
-        sv = ident ? 0.0 : x[r] / alpha;
-      x[r] = sv;
-    }
+    // R column j (rows J..m-1): the final entries above the pivot, -sigma rho
+    // on the diagonal, zeros below; local row r is owned by thread r mod HQ_TPB
+    for (int r = tid; r < m - J; r += HQ_TPB)
+      R[(J + r) + (int64_t)j * ldr] = r < c ? x[r] : (r == c ? -sr : 0.0);
+    // s_j in place of the column (own rows > c); the pivot entry is written
+    // after the column loop, since every thread reads the pivot above
+    const double spiv = ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : gamma / alpha);
+    for (int r = tid; r < rows; r += HQ_TPB)
+      if (r > c) x[r] = ident ? 0.0 : x[r] / alpha;
     if (tid == 0) {
+      spv[c] = spiv;
       bet[c] = beta;
-      Tp[c][c] = beta;
-      T[j + (int64_t)j * ldt] = beta;
       if (ident) atomicCAS(status, 0, j + 1);
       if (!(isfinite(ss) && isfinite(yj))) atomicCAS(status + 1, 0, j + 1);
     }
-    __syncthreads();
-    // H_j = I - beta s_j s_j^t on the panel's later columns (rows >= j)
+    // H_j = I - beta s_j s_j^t on the panel's later columns (own rows >= c)
     const int nrem = nb - 1 - c;
-    if (nrem > 0 && !ident) {
-      double d[SQ_NB];
+    if (nrem > 0) {  // uniform
+      double d[NB];
 #pragma unroll
-      for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
-      for (int r = c + tid; r < rows; r += SQ_TPB) {
-        const double sv = x[r];
+      for (int q = 0; q < NB; ++q) d[q] = 0.0;
+      for (int r = tid; r < rows; r += HQ_TPB) {
+        if (r < c) continue;
+        const double sv = r == c ? spiv : x[r];
 #pragma unroll
-        for (int q = 0; q < SQ_NB; ++q)
+        for (int q = 0; q < NB - 1; ++q)
           if (q < nrem) d[q] += sv * Pn[(c + 1 + q) * rows + r];
       }
 #pragma unroll
-      for (int q = 0; q < SQ_NB; ++q) {
-        const double v = wave_sum(d[q]);
-        if (lane == 0 && q < nrem) redv[w][q] = v;
-      }
-      __syncthreads();
-      if (tid < nrem) {
-        double sum = 0.0;
-        for (int i = 0; i < SQ_TPB / 64; ++i) sum += redv[i][tid];
-        gv[tid] = beta * sum;
-      }
-      __syncthreads();
-      for (int e = tid; e < nrem * (rows - c); e += SQ_TPB) {
-        const int q = e / (rows - c), r = c + e % (rows - c);
-        Pn[(c + 1 + q) * rows + r] -= gv[q] * x[r];
-      }
-      __syncthreads();
-    }
-  }
-  // the panel's vectors into S (zeros above the panel rows)
-  for (int e = tid; e < L * nb; e += SQ_TPB) {
-    const int r = e % L, c = e / L;
-    S[r + (int64_t)(J + c) * lds] = r < J ? 0.0 : Pn[c * rows + (r - J)];
-  }
-  __syncthreads();
-  // T columns J..J+nb-1, block form of the Prop. 3.2 recursion: the
-  // panel's own block T_pp (g = S_p^t s_j over the panel, from LDS), then
-  // T_{<J, p} = -T_{<J,<J} (S_{<J}^t S_p) T_pp.
-  for (int c = 0; c < nb; ++c) {
-    const double *xj = Pn + c * rows;
-    // g_q = s_q^t s_j for the panel's q < c (rows >= J + c), one wave per q
-    for (int q = w; q < c; q += SQ_TPB / 64) {
-      const double *xq = Pn + q * rows;
-      double v = 0.0;
-      for (int r = c + lane; r < rows; r += 64) v += xq[r] * xj[r];
-      v = wave_sum(v);
-      if (lane == 0) gv[q] = v;
-    }
-    __syncthreads();
-    if (tid < c) {
-      double t = 0.0;
-      for (int q = tid; q < c; ++q) t += Tp[tid][q] * gv[q];
-      const double v = -bet[c] * t;
-      Tp[tid][c] = v;
-      T[(J + tid) + (int64_t)(J + c) * ldt] = v;
-    }
-    __syncthreads();
-  }
-  if (J > 0) {
-    // X = S_{<J}^t S_p (rows >= J), one wave per earlier column p, into
-    // T[p, J + c] as scratch
-    for (int p = w; p < J; p += SQ_TPB / 64) {
-      const double *sp = S + (int64_t)p * lds + J;
-      double d[SQ_NB];
-#pragma unroll
-      for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
-      // the column's first SQ_RC * 64 rows are loaded at once, the rest
-      // streamed; the sums run over rows in increasing order either way
-      double sr[SQ_RC];
-#pragma unroll
-      for (int i = 0; i < SQ_RC; ++i) {
-        const int r = lane + 64 * i;
-        sr[i] = r < rows ? sp[r] : 0.0;
-      }
-#pragma unroll
-      for (int i = 0; i < SQ_RC; ++i) {
-        const int r = lane + 64 * i;
-        if (r < rows) {
-#pragma unroll
-          for (int q = 0; q < SQ_NB; ++q)
-            if (q < nb) d[q] += sr[i] * Pn[q * rows + r];
+      for (int q = 0; q < NB - 1; ++q) {
+        if (q < nrem) {
+          const double v = wave_sum(d[q]);
+          if (lane == 0) red[b][w][q] = v;
         }
       }
-#pragma unroll 4
-      for (int r = lane + 64 * SQ_RC; r < rows; r += 64) {
-        const double sv = sp[r];
+      __syncthreads();  // the product partials
+      double gq[NB];
 #pragma unroll
-        for (int q = 0; q < SQ_NB; ++q)
-          if (q < nb) d[q] += sv * Pn[q * rows + r];
+      for (int q = 0; q < NB - 1; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < HQ_W; ++i) s += q < nrem ? red[b][i][q] : 0.0;
+        gq[q] = beta * s;
       }
+      for (int r = tid; r < rows; r += HQ_TPB) {
+        if (r < c) continue;
+        const double sv = r == c ? spiv : x[r];
 #pragma unroll
-      for (int q = 0; q < SQ_NB; ++q) {
-        const double v = wave_sum(d[q]);
-        if (lane == 0 && q < nb) T[p + (int64_t)(J + q) * ldt] = v;
-      }
-    }
-    __syncthreads();
-    // Y = T_{<J,<J} X into LDS (after the panel), one wave per row p,
-    // lanes over q >= p
-    double *Yl = Pn + (size_t)SQ_NB * rows;
-    for (int p = w; p < J; p += SQ_TPB / 64) {
-      double t[SQ_NB];
-#pragma unroll
-      for (int c = 0; c < SQ_NB; ++c) t[c] = 0.0;
-      for (int q = p + lane; q < J; q += 64) {
-        const double tpq = T[p + (int64_t)q * ldt];
-#pragma unroll
-        for (int c = 0; c < SQ_NB; ++c)
-          if (c < nb) t[c] += tpq * T[q + (int64_t)(J + c) * ldt];
-      }
-#pragma unroll
-      for (int c = 0; c < SQ_NB; ++c) {
-        const double v = wave_sum(t[c]);
-        if (lane == 0) Yl[p * SQ_NB + c] = v;
+        for (int q = 0; q < NB - 1; ++q)
+          if (q < nrem) Pn[(c + 1 + q) * rows + r] -= gq[q] * sv;
       }
     }
-    __syncthreads();
-    // T_{<J, p} = -Y T_pp, row by row
-    for (int p = tid; p < J; p += SQ_TPB) {
-      double o[SQ_NB];
+  }
+  __syncthreads();
+  if (tid < nb) Pn[tid * rows + tid] = spv[tid];
+  __syncthreads();
+  // the panel's vectors into S (zeros above each pivot: the panel column
+  // still holds its R entries there)
+  for (int e = tid; e < L * nb; e += HQ_TPB) {
+    const int r = e % L, c = e / L;
+    S[r + (int64_t)(J + c) * lds] = r < J + c ? 0.0 : Pn[c * rows + (r - J)];
+  }
+  // T_pp: g_{q,c} = s_q^t s_c over rows >= c (s_c is zero above its pivot),
+  // one wave per pair
+  for (int pr = w; pr < nb * nb; pr += HQ_W) {
+    const int q = pr % nb, c = pr / nb;
+    if (q >= c) continue;  // uniform across the wave
+    const double *xq = Pn + q * rows, *xc = Pn + c * rows;
+    double v = 0.0;
+    for (int r = c + lane; r < rows; r += 64) v += xq[r] * xc[r];
+    v = wave_sum(v);
+    if (lane == 0) gp[q][c] = v;
+  }
+  __syncthreads();
+  // row q of T_pp on lane q: T_qq = beta_q, T_qc = -beta_c sum_{q <= k < c} T_qk g_kc
+  if (w == 0 && lane < nb) {
+    const int q = lane;
+    double tq[NB];
 #pragma unroll
-      for (int c = 0; c < SQ_NB; ++c) {
-        double t = 0.0;
+    for (int c = 0; c < NB; ++c) {
+      double v = 0.0;
+      if (c < nb) {
+        if (c == q) {
+          v = bet[c];
+        } else if (c > q) {
+          double t = 0.0;
 #pragma unroll
-        for (int q = 0; q < SQ_NB; ++q)
-          if (q <= c && c < nb) t += Yl[p * SQ_NB + q] * Tp[q][c];
-        o[c] = -t;
+          for (int k = 0; k < NB; ++k)
+            if (k < c && k >= q) t += tq[k] * gp[k][c];
+          v = -bet[c] * t;
+        }
+        if (c >= q) T[(J + q) + (int64_t)(J + c) * ldt] = v;
       }
-#pragma unroll
-      for (int c = 0; c < SQ_NB; ++c)
-        if (c < nb) T[p + (int64_t)(J + c) * ldt] = o[c];
+      tq[c] = v;
     }
-    __syncthreads();
   }
 }
 
 // trailing column k = J + nb + blockIdx.x of panel J: w = S_p^t Z_k,
-// u = T_p^t w, Z_k -= S_p u (rows >= J), with the panel's vectors read from
+// u = T_pp^t w, Z_k -= S_p u (rows >= J), with the panel's vectors read from
 // S.  One workgroup per column: every thread loads its rows (at most
 // SQ_MAXL / TR_TPB) at once, the dot products are summed per wave and then
 // over the waves in a fixed order.
 constexpr int TR_TPB = 256;
 constexpr int TR_RC = SQ_MAXL / TR_TPB;  // rows per thread
+template <int NB>
 __global__ void __launch_bounds__(TR_TPB) k_hqr_trail(int32_t L, int32_t m, int32_t J, double *Z,
                                                       int64_t ldz, const double *S, int64_t lds,
                                                       const double *T, int64_t ldt) {
-  __shared__ double red[TR_TPB / 64][SQ_NB];
-  const int nb = m - J < SQ_NB ? m - J : SQ_NB;
+  __shared__ double red[TR_TPB / 64][NB];
+  const int nb = m - J < NB ? m - J : NB;
   const int rows = L - J, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int k = J + nb + (int)blockIdx.x;
   if (k >= m) return;  // the whole workgroup
   const double *Sp = S + J + (int64_t)J * lds;  // Sp[r + q * lds]: panel vector q, row J + r
   double *zk = Z + (int64_t)k * ldz + J;
-  double zr[TR_RC], d[SQ_NB];
+  double zr[TR_RC], d[NB];
 #pragma unroll
-  for (int q = 0; q < SQ_NB; ++q) d[q] = 0.0;
+  for (int q = 0; q < NB; ++q) d[q] = 0.0;
 #pragma unroll
   for (int i = 0; i < TR_RC; ++i) {
     const int r = tid + TR_TPB * i;
@@ -385,27 +322,27 @@ __global__ void __launch_bounds__(TR_TPB) k_hqr_trail(int32_t L, int32_t m, int3
     const int r = tid + TR_TPB * i;
     if (r < rows) {
 #pragma unroll
-      for (int q = 0; q < SQ_NB; ++q)
+      for (int q = 0; q < NB; ++q)
         if (q < nb) d[q] += Sp[r + (int64_t)q * lds] * zr[i];
     }
   }
 #pragma unroll
-  for (int q = 0; q < SQ_NB; ++q) {
+  for (int q = 0; q < NB; ++q) {
     const double v = wave_sum(d[q]);
     if (lane == 0) red[w][q] = v;
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < SQ_NB; ++q) {
+  for (int q = 0; q < NB; ++q) {
     static_assert(TR_TPB / 64 == 4, "four partial sums per value");
     d[q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
   }
-  double u[SQ_NB];
+  double u[NB];
 #pragma unroll
-  for (int c = 0; c < SQ_NB; ++c) {
+  for (int c = 0; c < NB; ++c) {
     double t = 0.0;
 #pragma unroll
-    for (int q = 0; q < SQ_NB; ++q)
+    for (int q = 0; q < NB; ++q)
       if (q <= c && c < nb) t += T[(J + q) + (int64_t)(J + c) * ldt] * d[q];
     u[c] = t;
   }
@@ -415,37 +352,100 @@ __global__ void __launch_bounds__(TR_TPB) k_hqr_trail(int32_t L, int32_t m, int3
     if (r < rows) {
       double zv = zr[i];
 #pragma unroll
-      for (int c = 0; c < SQ_NB; ++c)
+      for (int c = 0; c < NB; ++c)
         if (c < nb) zv -= Sp[r + (int64_t)c * lds] * u[c];
       zk[r] = zv;
     }
   }
 }
 
+// T_{<J, p} = -(T_{<J,<J} G_{<J, p}) T_pp for the panel p = J..J+nb-1, with
+// G = S^t S (ld m).  One workgroup: Y = T_{<J,<J} G_{<J,p} into LDS (one
+// thread per entry, sum over q in increasing order), then the product with
+// the panel's diagonal block.  T_{<J,<J} comes from the earlier launches.
+constexpr int TF_TPB = 1024;
+template <int NB>
+__global__ void __launch_bounds__(TF_TPB) k_hqr_tfill(int32_t m, int32_t J,
+                                                      const double *__restrict__ G,
+                                                      double *__restrict__ T, int64_t ldt) {
+  extern __shared__ double Y[];  // J x nb, ld J
+  const int nb = m - J < NB ? m - J : NB;
+  for (int e = threadIdx.x; e < J * nb; e += TF_TPB) {
+    const int p = e % J, c = e / J;
+    const double *g = G + (int64_t)(J + c) * m;
+    double y = 0.0;
+    for (int q = p; q < J; ++q) y += T[p + (int64_t)q * ldt] * g[q];
+    Y[p + c * J] = y;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < J * nb; e += TF_TPB) {
+    const int p = e % J, c = e / J;
+    double t = 0.0;
+    for (int q = 0; q <= c; ++q) t += Y[p + q * J] * T[(J + q) + (int64_t)(J + c) * ldt];
+    T[p + (int64_t)(J + c) * ldt] = -t;
+  }
+}
+
 }  // namespace
 
 // Sketch-space Householder QR of Z (L x m float64, copied to Zc, which is
-// overwritten): S (Householder vectors, unit pivot), T, R.
+// overwritten): S (Householder vectors, unit pivot), T, R.  G: m x m float64
+// scratch (S^t S).
 int sketch_space_hqr(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, double *T,
-                     int64_t ldt, double *R, int64_t ldr, const LoopWs &w, hipStream_t st) {
+                     int64_t ldt, double *R, int64_t ldr, double *G, const LoopWs &w,
+                     hipStream_t st) {
   hipLaunchKernelGGL(k_zero_mat, dim3((m + 255) / 256, m), dim3(256), 0, st, T, ldt, m, m);
   RHQR_HIP(hipGetLastError());
   if (L + m <= SQ_MAXL) {  // the panel in LDS; two launches per panel
-    const size_t lds_bytes = sizeof(double) * (size_t)(L + m) * SQ_NB;
+    const int NBv = hqr_nb(L, m);
     static bool attr_set = false;
     if (!attr_set) {
-      RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_panel,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)(sizeof(double) * SQ_MAXL * SQ_NB)));
+      RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_panel<16>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)HQ_LDS_MAX));
+      RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_panel<8>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)HQ_LDS_MAX));
+      RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_tfill<16>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)HQ_LDS_MAX));
+      RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_tfill<8>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)HQ_LDS_MAX));
       attr_set = true;
     }
-    for (int32_t J = 0; J < m; J += SQ_NB) {
-      const int32_t nb = m - J < SQ_NB ? m - J : SQ_NB;
-      RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_panel, dim3(1), dim3(SQ_TPB), lds_bytes, st, L, m, J, Zc,
-                  (int64_t)L, S, lds, T, ldt, R, ldr, (int)RHQR_SCALE_UNIT_PIVOT, w.status);
+    const size_t lds_bytes = sizeof(double) * (size_t)L * NBv;
+    for (int32_t J = 0; J < m; J += NBv) {
+      const int32_t nb = m - J < NBv ? m - J : NBv;
+      if (NBv == 16)
+        RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_panel<16>, dim3(1), dim3(HQ_TPB), lds_bytes, st, L, m, J,
+                    Zc, (int64_t)L, S, lds, T, ldt, R, ldr, (int)RHQR_SCALE_UNIT_PIVOT, w.status);
+      else
+        RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_panel<8>, dim3(1), dim3(HQ_TPB), lds_bytes, st, L, m, J,
+                    Zc, (int64_t)L, S, lds, T, ldt, R, ldr, (int)RHQR_SCALE_UNIT_PIVOT, w.status);
+      RHQR_HIP(hipGetLastError());
       if (J + nb < m) {
-        RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_trail, dim3((unsigned)(m - J - nb)), dim3(TR_TPB), 0, st,
-                    L, m, J, Zc, (int64_t)L, (const double *)S, lds, (const double *)T, ldt);
+        const dim3 g((unsigned)(m - J - nb));
+        if (NBv == 16)
+          RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_trail<16>, g, dim3(TR_TPB), 0, st, L, m, J, Zc,
+                      (int64_t)L, (const double *)S, lds, (const double *)T, ldt);
+        else
+          RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_trail<8>, g, dim3(TR_TPB), 0, st, L, m, J, Zc,
+                      (int64_t)L, (const double *)S, lds, (const double *)T, ldt);
+        RHQR_HIP(hipGetLastError());
+      }
+    }
+    if (m > NBv) {
+      const int64_t nent = (int64_t)m * m;
+      RHQR_LAUNCH(RHQR_PROF_HQR, k_gram, dim3((nent + 15) / 16), dim3(1024), 0, st, m, L,
+                  (const double *)S, lds, (const double *)S, lds, G);
+      RHQR_HIP(hipGetLastError());
+      for (int32_t J = NBv; J < m; J += NBv) {
+        const int32_t nb = m - J < NBv ? m - J : NBv;
+        const size_t yb = sizeof(double) * (size_t)J * nb;
+        if (NBv == 16)
+          RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_tfill<16>, dim3(1), dim3(TF_TPB), yb, st, m, J,
+                      (const double *)G, T, ldt);
+        else
+          RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_tfill<8>, dim3(1), dim3(TF_TPB), yb, st, m, J,
+                      (const double *)G, T, ldt);
+        RHQR_HIP(hipGetLastError());
       }
     }
     return RHQR_OK;
@@ -513,7 +513,7 @@ extern "C" int recrhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, 
   rc = launch_sketch(h, dtype, n, m, d_W, ldw, w.Z, L, w.skws, w.skws_bytes, st);
   if (rc) return rc;
   RHQR_HIP(hipMemcpyAsync(w.Zc, w.Z, sizeof(double) * (size_t)L * m, hipMemcpyDeviceToDevice, st));
-  rc = sketch_space_hqr(L, m, w.Zc, d_S, lds, d_T, ldt, d_R, ldr, w.loop, st);
+  rc = sketch_space_hqr(L, m, w.Zc, d_S, lds, d_T, ldt, d_R, ldr, w.G, w.loop, st);
   if (rc) return rc;
   if (mode == RHQR_REC_M) {
     const int64_t nent = (int64_t)m * m;

@@ -27,7 +27,10 @@ def _rec(n, m, l, kappa, mode, dtype="float64", seed=0, kind=0):
     return W, to_np(Wd), g, osketch
 
 
-@pytest.mark.parametrize("n,m,l", [(300, 7, 40), (3 * 4096 + 777, 24, 96), (2 * 4096 + 5, 70, 200)])
+# m = 128 fills the matrix-core substitution's eight column blocks; m = 136
+# takes the blocked substitution (m > 128)
+@pytest.mark.parametrize("n,m,l", [(300, 7, 40), (3 * 4096 + 777, 24, 96), (2 * 4096 + 5, 70, 200),
+                                   (2 * 4096 + 9, 128, 300), (4096 + 21, 136, 300)])
 def test_rec_m_elementwise(n, m, l):
     log(f"recrhqr M n={n} m={m} l={l}")
     W, Win, g, sk = _rec(n, m, l, 2, 0)
