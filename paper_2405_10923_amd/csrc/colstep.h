@@ -51,7 +51,7 @@ __device__ __forceinline__ double deferred_c_finish(const DeferredC &d) {
 // otherwise with ordinary loads (the blocked schedule's passes, whose few
 // columns were written moments before and are read again by the next pass).
 constexpr int TALL_CACHED_COLS = 32;
-template <typename ST, bool FAST, int NV, int TPB, bool NTU, typename CP>
+template <typename ST, bool FAST, int NV, int TPB, bool NTU, bool PRE = false, typename CP>
 __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64_t n, int32_t m,
                                           int32_t j, int32_t p0, bool prev,
                                           const double *__restrict__ cf, const CP &cprev_of,
@@ -68,16 +68,18 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
 #pragma unroll
   for (int v = 0; v < NV; ++v) off[v] = (uint32_t)((row(v) - base) * (int64_t)sizeof(ST));
 
-  // acc <- w_j
+  // acc <- w_j (PRE: already loaded by the caller)
   const ST *wj = W + (int64_t)j * ldw;
+  if constexpr (!PRE) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const int64_t i0 = row(v);
-    if (FAST) {
-      vload(wj + i0, acc[v]);
-    } else {
+    for (int v = 0; v < NV; ++v) {
+      const int64_t i0 = row(v);
+      if (FAST) {
+        vload(wj + i0, acc[v]);
+      } else {
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) acc[v][e] = ok(i0 + e) ? cvt_in<CT>(wj[i0 + e]) : (CT)0;
+        for (int e = 0; e < VEC; ++e) acc[v][e] = ok(i0 + e) ? cvt_in<CT>(wj[i0 + e]) : (CT)0;
+      }
     }
   }
   // acc -= U_{:, <j-1} c  (stored columns, already scaled)
@@ -224,6 +226,30 @@ template <typename A, int TPW> __device__ void fwht_tiles_lds(A *s) {
   __syncthreads();
 }
 
+// The same transform on NT tiles from s with LDS-only barriers, so global
+// loads issued before it stay in flight.
+template <typename A, int NT> __device__ void fwht_tiles_lds_part(A *s) {
+#pragma unroll 1
+  for (int pass = 0; pass < 3; ++pass) {
+    lds_barrier();
+    const int sh = 4 * pass;
+    for (int gg = threadIdx.x; gg < (TILE / 16) * NT; gg += blockDim.x) {
+      A *st = s + (gg >> 8) * TILE_PAD;
+      const int g = gg & 255;
+      const int lo = g & ((1 << sh) - 1);
+      const int hi = g >> sh;
+      const int base = lo + (hi << (sh + 4));
+      A v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = st[tpad(base + (k << sh))];
+      fwht16(v);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) st[tpad(base + (k << sh))] = v[k];
+    }
+  }
+  lds_barrier();
+}
+
 // TPB threads per workgroup: 1024 (one workgroup per compute unit on large
 // problems) or 256 (several workgroups per compute unit, for the many small
 // problems of a batch).  The result does not depend on TPB: every row is
@@ -277,35 +303,133 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
       cfprev = cf[j - 1];
   }
   auto cprev_of = [&]() { return defer ? deferred_c_finish(dc) * iaprev : cfprev; };
-  CT acc[NV][VEC];
-  if (fast && j - 1 - p0 > TALL_CACHED_COLS)
-    tall_body<ST, true, NV, TPB, true>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base, acc);
-  else if (fast)
-    tall_body<ST, true, NV, TPB, false>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base, acc);
-  else
-    tall_body<ST, false, NV, TPB, false>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base,
-                                         acc);
-
-  if (KIND == RHQR_SKETCH_IDENT) return;
   const int tid = threadIdx.x;
-  if (KIND == RHQR_SKETCH_SRHT) {
-    if (tid < NSW) sgn[tid] = sw;
-    lds_barrier();
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int li0 = VEC * (tid + TPB * v);
+  // signed values of rows li0 + e (li0 = VEC (tid + TPB v) + off) into their tiles
+  auto to_lds = [&](const CT(*a)[VEC], int nv, int off) {
+    for (int v = 0; v < nv; ++v) {
+      const int li0 = VEC * (tid + TPB * v) + off;
       const int64_t i0 = base + li0;
       const uint64_t word = sgn[li0 >> 6];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         const int64_t i = i0 + e;
-        CT x = (i >= m && i < n) ? acc[v][e] : (CT)0;
+        CT x = (i >= m && i < n) ? a[v][e] : (CT)0;
         if ((word >> (i & 63)) & 1ull) x = -x;
         const int li = li0 + e;
         s[(li >> TILE_LOG) * TILE_PAD + tpad(li & (TILE - 1))] = x;
       }
     }
-    fwht_tiles_lds<CT, TPW>(s);
+  };
+  // SRHT, full workgroups of several tiles: two halves, the first half's
+  // tiles transformed while the second half's loads of w_j are in flight
+  // (the same arithmetic per row and per tile as the one-pass order)
+  constexpr bool PIPE = KIND == RHQR_SKETCH_SRHT && TPW >= 2 && NV % 2 == 0 && TPB == 1024;
+  bool piped = false;
+  if constexpr (PIPE) {
+    if (fast) {
+      piped = true;
+      constexpr int NVH = NV / 2, ROWSH = ROWS / 2, TPH = TPW / 2;
+      const bool ntu = j - 1 - p0 > TALL_CACHED_COLS;
+      CT a0[NVH][VEC], a1[NVH][VEC];
+      if (ntu)
+        tall_body<ST, true, NVH, TPB, true>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base, a0);
+      else
+        tall_body<ST, true, NVH, TPB, false>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base,
+                                             a0);
+      if (tid < NSW) sgn[tid] = sw;
+      lds_barrier();
+      to_lds(a0, NVH, 0);
+      const ST *wj = W + (int64_t)j * ldw + base + ROWSH;
+#pragma unroll
+      for (int v = 0; v < NVH; ++v) vload(wj + VEC * (tid + TPB * v), a1[v]);
+      fwht_tiles_lds_part<CT, TPH>(s);
+      if (ntu)
+        tall_body<ST, true, NVH, TPB, true, true>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev,
+                                                  base + ROWSH, a1);
+      else
+        tall_body<ST, true, NVH, TPB, false, true>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev,
+                                                   base + ROWSH, a1);
+      to_lds(a1, NVH, ROWSH);
+      fwht_tiles_lds_part<CT, TPH>(s + TPH * TILE_PAD);
+    }
+  }
+  if (!piped) {
+    CT acc[NV][VEC];
+    if (fast && j - 1 - p0 > TALL_CACHED_COLS)
+      tall_body<ST, true, NV, TPB, true>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base,
+                                         acc);
+    else if (fast)
+      tall_body<ST, true, NV, TPB, false>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base,
+                                          acc);
+    else
+      tall_body<ST, false, NV, TPB, false>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base,
+                                           acc);
+    if (KIND == RHQR_SKETCH_IDENT) return;
+    if (KIND == RHQR_SKETCH_SRHT) {
+      if (tid < NSW) sgn[tid] = sw;
+      lds_barrier();
+      to_lds(acc, NV, 0);
+      fwht_tiles_lds<CT, TPW>(s);
+    } else {
+      // Gaussian: partial Omega[:, rows] w~_rows, four row groups per sample
+        // Each thread takes two adjacent samples (one 16-byte load of Omega per
+        // row when l is even) and four accumulators over rows 16 apart, so that
+        // four loads per thread are in flight; odd l (or an Omega not 16-byte
+        // aligned) takes the samples one by one.
+        __shared__ double red[KIND == RHQR_SKETCH_GAUSS ? 2048 : 1];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const int li0 = VEC * (tid + TPB * v);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) {
+            const int64_t i = base + li0 + e;
+            s[li0 + e] = (i >= m && i < n) ? acc[v][e] : (CT)0;
+          }
+        }
+        const int64_t lo = base > m ? base : (int64_t)m;
+        const int64_t hi = base + ROWS < n ? base + ROWS : n;
+        const int g = tid >> 8, t = tid & 255;
+        const bool pairs = (l & 1) == 0 && ((uintptr_t)om & 15) == 0;
+        for (int q0 = 0; q0 < l; q0 += 512) {
+          __syncthreads();
+          const int q = q0 + 2 * t;
+          double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
+          if (pairs && q < l) {  // q + 1 < l as well (l even, q even)
+            int64_t i = lo + g;
+#pragma unroll 2
+            for (; i + 12 < hi; i += 16) {
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const double2 o = *reinterpret_cast<const double2 *>(om + (i + 4 * u - m) * l + q);
+                const double x = (double)s[i + 4 * u - base];
+                a[u] += o.x * x;
+                b[u] += o.y * x;
+              }
+            }
+            for (; i < hi; i += 4) {
+              const double2 o = *reinterpret_cast<const double2 *>(om + (i - m) * l + q);
+              const double x = (double)s[i - base];
+              a[0] += o.x * x;
+              b[0] += o.y * x;
+            }
+          } else if (!pairs) {
+            for (int e = 0; e < 2; ++e) {
+              if (q + e >= l) break;
+              double c = 0.0;
+              for (int64_t i = lo + g; i < hi; i += 4) c += om[(i - m) * l + q + e] * (double)s[i - base];
+              (e ? b : a)[0] = c;
+            }
+          }
+          red[2 * (g * 256 + t)] = (a[0] + a[1]) + (a[2] + a[3]);
+          red[2 * (g * 256 + t) + 1] = (b[0] + b[1]) + (b[2] + b[3]);
+          __syncthreads();
+          if (tid < 512 && q0 + tid < l)  // sample q0 + tid of row group g is red[512 g + tid]
+            part[(int64_t)bid * l + q0 + tid] =
+                (red[tid] + red[512 + tid]) + (red[1024 + tid] + red[1536 + tid]);
+        }
+    }
+  }
+  if (KIND == RHQR_SKETCH_SRHT) {
     const uint64_t t0 = (uint64_t)bid * TPW;
     for (int q = tid; q < l; q += TPB) {
       const int32_t r = q == tid ? rq : rows[q];
@@ -319,87 +443,9 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
       }
       part[(int64_t)bid * l + q] = h;
     }
-  } else {  // Gaussian: partial Omega[:, rows] w~_rows, four row groups per sample
-    // Each thread takes two adjacent samples (one 16-byte load of Omega per
-    // row when l is even) and four accumulators over rows 16 apart, so that
-    // four loads per thread are in flight; odd l (or an Omega not 16-byte
-    // aligned) takes the samples one by one.
-    __shared__ double red[KIND == RHQR_SKETCH_GAUSS ? 2048 : 1];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int li0 = VEC * (tid + TPB * v);
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const int64_t i = base + li0 + e;
-        s[li0 + e] = (i >= m && i < n) ? acc[v][e] : (CT)0;
-      }
-    }
-    const int64_t lo = base > m ? base : (int64_t)m;
-    const int64_t hi = base + ROWS < n ? base + ROWS : n;
-    const int g = tid >> 8, t = tid & 255;
-    const bool pairs = (l & 1) == 0 && ((uintptr_t)om & 15) == 0;
-    for (int q0 = 0; q0 < l; q0 += 512) {
-      __syncthreads();
-      const int q = q0 + 2 * t;
-      double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
-      if (pairs && q < l) {  // q + 1 < l as well (l even, q even)
-        int64_t i = lo + g;
-#pragma unroll 2
-        for (; i + 12 < hi; i += 16) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const double2 o = *reinterpret_cast<const double2 *>(om + (i + 4 * u - m) * l + q);
-            const double x = (double)s[i + 4 * u - base];
-            a[u] += o.x * x;
-            b[u] += o.y * x;
-          }
-        }
-        for (; i < hi; i += 4) {
-          const double2 o = *reinterpret_cast<const double2 *>(om + (i - m) * l + q);
-          const double x = (double)s[i - base];
-          a[0] += o.x * x;
-          b[0] += o.y * x;
-        }
-      } else if (!pairs) {
-        for (int e = 0; e < 2; ++e) {
-          if (q + e >= l) break;
-          double c = 0.0;
-          for (int64_t i = lo + g; i < hi; i += 4) c += om[(i - m) * l + q + e] * (double)s[i - base];
-          (e ? b : a)[0] = c;
-        }
-      }
-      red[2 * (g * 256 + t)] = (a[0] + a[1]) + (a[2] + a[3]);
-      red[2 * (g * 256 + t) + 1] = (b[0] + b[1]) + (b[2] + b[3]);
-      __syncthreads();
-      if (tid < 512 && q0 + tid < l)  // sample q0 + tid of row group g is red[512 g + tid]
-        part[(int64_t)bid * l + q0 + tid] =
-            (red[tid] + red[512 + tid]) + (red[1024 + tid] + red[1536 + tid]);
-    }
   }
 }
 
-// Sums eight values per lane over the 64 lanes at once: each exchange across
-// 32, 16 and 8 lanes keeps half of the values (own plus partner's), then the
-// last eight-lane groups are summed with row moves.  Lane L returns the total
-// of v[(L >> 3) & 7] (bit 5 of L selects the upper four values, bit 4 the
-// upper two of those, bit 3 the second).  Fixed order: deterministic.  All 64
-// lanes must be active.
-__device__ __forceinline__ double wave_sum8(const double (&v)[8]) {
-  const int lane = threadIdx.x & 63;
-  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
-  double a[4], b[2];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    a[i] = (h5 ? v[i + 4] : v[i]) + __shfl_xor(h5 ? v[i] : v[i + 4], 32, 64);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-    b[i] = (h4 ? a[i + 2] : a[i]) + __shfl_xor(h4 ? a[i] : a[i + 2], 16, 64);
-  double s = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8, 64);
-  s += dpp_mov<0xB1>(s);   // quad_perm [1,0,3,2]
-  s += dpp_mov<0x4E>(s);   // quad_perm [2,3,0,1]
-  s += dpp_mov<0x141>(s);  // row_half_mirror: the other quad of the eight lanes
-  return s;
-}
 
 // ------------------------------------------------------------------- k_red
 // One workgroup per RED_CHUNK rows of the (l+m) sketch space (head chunks

@@ -248,6 +248,29 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
   return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
+// Sums eight values per lane over the 64 lanes at once: each exchange across
+// 32, 16 and 8 lanes keeps half of the values (own plus partner's), then the
+// last eight-lane groups are summed with row moves.  Lane L returns the total
+// of v[(L >> 3) & 7] (bit 5 of L selects the upper four values, bit 4 the
+// upper two of those, bit 3 the second).  Fixed order: deterministic.  All 64
+// lanes must be active.
+__device__ __forceinline__ double wave_sum8(const double (&v)[8]) {
+  const int lane = threadIdx.x & 63;
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+  double a[4], b[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    a[i] = (h5 ? v[i + 4] : v[i]) + __shfl_xor(h5 ? v[i] : v[i + 4], 32, 64);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    b[i] = (h4 ? a[i + 2] : a[i]) + __shfl_xor(h4 ? a[i] : a[i + 2], 16, 64);
+  double s = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8, 64);
+  s += dpp_mov<0xB1>(s);   // quad_perm [1,0,3,2]
+  s += dpp_mov<0x4E>(s);   // quad_perm [2,3,0,1]
+  s += dpp_mov<0x141>(s);  // row_half_mirror: the other quad of the eight lanes
+  return s;
+}
+
 // Sum over a workgroup; `red` is LDS scratch of >= blockDim.x/64 entries.
 // Every thread returns the total.  Fixed order: deterministic.
 template <typename T> __device__ T block_sum(T v, T *red) {
