@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace {
 
@@ -118,153 +119,229 @@ __global__ void k_zero_mat(double *A, int64_t lda, int32_t rows, int32_t cols) {
 
 // ------------------------------------------- sketch-space Householder QR
 // Householder QR of the small L x m float64 sketch Z (overwritten),
-// right-looking in panels of NB columns (16, or 8 for tall sketches).
-// k_hqr_panel (one workgroup) factors the panel in LDS one column at a time
-// (RHVector with Psi = I, Alg. 2: sigma, rho, gamma, alpha, beta; identity
-// reflector when rho = 0), writes its vectors to S and the panel's diagonal
-// block of T (Prop. 3.2 recursion within the panel).  Thread t owns the panel
-// rows r = t mod HQ_TPB for every column, so a column costs two workgroup
-// reductions (its norm, then its products with the later panel columns) and
-// no other synchronisation.  k_hqr_trail (one workgroup per trailing column)
-// applies the panel's block reflector, Z <- (I - S_p T_pp^t S_p^t) Z.  After
-// the last panel the off-diagonal blocks of T follow from the Gram matrix
-// G = S^t S: T_{<J, p} = -T_{<J,<J} G_{<J, p} T_pp (Prop. 3.2 in block form),
-// one launch per panel.  Every reduction runs in a fixed order.  The same
+// right-looking in panels of NB columns (16, or 8 for sketches of more than
+// 1024 rows), two launches per panel.
+// k_hqr_panel (one workgroup of HQ_TPB threads) factors the panel one column
+// at a time (RHVector with Psi = I, Alg. 2: sigma, rho, gamma, alpha, beta;
+// identity reflector when rho = 0) with the panel in registers: thread t holds
+// rows t + HQ_TPB i of every panel column, so a column costs two workgroup
+// reductions (its norm; its products with the later panel columns, summed
+// eight at a time per wave) and nothing else.  Then it writes the panel's
+// vectors to S, its columns of R and the diagonal block T_pp (Prop. 3.2
+// recursion within the panel).
+// k_hqr_trail runs three kinds of workgroups: one per trailing column, which
+// applies the panel's block reflector, Z <- (I - S_p T_pp^t S_p^t) Z; one per
+// four earlier columns q, the products X_p = S_{<J}^t S_p (one wave per q);
+// and one per sixteen rows of the previous panel's off-diagonal block of T,
+// T_{<J', p'} = -(T_{<J',<J'} X_p') T_p'p' (Prop. 3.2 in block form), which is
+// needed only at the end.  Every reduction runs in a fixed order.  The same
 // factorization as the column engine with Psi = I, in far fewer launches.
 constexpr int HQ_TPB = 256;
 constexpr int HQ_W = HQ_TPB / 64;
 constexpr int SQ_MAXL = 2048;  // L + m at most on this path (else the column engine)
 constexpr int SQ_MAXM = 1024;  // largest m (recrhqr_factor rejects larger)
-constexpr size_t HQ_LDS_MAX = 150 * 1024;  // dynamic LDS budget of the panel kernel
 
-// panel width for an L-row sketch: 16 when the panel fits the LDS budget
-inline int hqr_nb(int32_t L, int32_t m) {
-  return (size_t)L * 16 * sizeof(double) <= HQ_LDS_MAX && m <= 512 ? 16 : 8;
+// panel width for an L-row sketch: 16 while the panel fits 4 rows per thread
+inline int hqr_nb(int32_t L) { return L <= 4 * HQ_TPB ? 16 : 8; }
+
+// f(integral_constant<int, I>) for I = B .. E-1, in order
+template <int B, int E, typename F> __device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
 }
 
-template <int NB>
+template <int NB, int RPT>
 __global__ void __launch_bounds__(HQ_TPB) k_hqr_panel(int32_t L, int32_t m, int32_t J, double *Z,
                                                       int64_t ldz, double *S, int64_t lds,
                                                       double *T, int64_t ldt, double *R,
                                                       int64_t ldr, int scaling, int32_t *status) {
-  // panel: column c at Pn + c * rows, local row r is row J + r
-  extern __shared__ double Pn[];
-  __shared__ double nrm[2][HQ_W];
+  __shared__ double nrm[2][HQ_W], pv[2];
   __shared__ double red[2][HQ_W][NB];
   __shared__ double gp[NB][NB];  // s_q^t s_c over the panel (q < c)
-  __shared__ double bet[NB], spv[NB];
+  __shared__ double bet[NB], dg[NB];
+  __shared__ int flags[NB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nb = m - J < NB ? m - J : NB;
   const int rows = L - J;
-  for (int e = tid; e < rows * nb; e += HQ_TPB) {
-    const int r = e % rows, c = e / rows;
-    Pn[c * rows + r] = Z[(J + r) + (int64_t)(J + c) * ldz];
-  }
-  for (int e = tid; e < J * nb; e += HQ_TPB) {
-    const int r = e % J, c = e / J;
-    R[r + (int64_t)(J + c) * ldr] = Z[r + (int64_t)(J + c) * ldz];
-  }
-  __syncthreads();
-  for (int c = 0; c < nb; ++c) {
-    const int j = J + c, b = c & 1;
-    double *x = Pn + c * rows;  // the pivot is local row c
-    double ss = 0.0;
-    for (int r = tid; r < rows; r += HQ_TPB) ss += r >= c ? x[r] * x[r] : 0.0;
-    ss = wave_sum(ss);
-    if (lane == 0) nrm[b][w] = ss;
-    __syncthreads();  // the norm partials; the pivot (updated by its owner) is final
-    ss = 0.0;
+  // own rows r_i = tid + HQ_TPB i of every column, loaded together (clamped
+  // indices; rows beyond the sketch and columns beyond nb hold zeros)
+  double P[RPT][NB];
 #pragma unroll
-    for (int i = 0; i < HQ_W; ++i) ss += nrm[b][i];
-    // RHVector scalars (every thread computes the same values)
-    const double rho = sqrt(ss);
-    const double yj = x[c];
-    const double sigma = yj >= 0.0 ? 1.0 : -1.0;
-    const bool ident = !(rho > 0.0);
-    double gamma = 0.0, alpha = 1.0, beta = 0.0;
-    if (!ident) {
-      gamma = yj + sigma * rho;
-      if (scaling == RHQR_SCALE_UNIT_PIVOT) {
-        alpha = gamma;
-        beta = fabs(gamma) / rho;
-      } else {
-        alpha = sqrt(rho * fabs(gamma));
-        beta = 1.0;
-      }
+  for (int c = 0; c < NB; ++c) {
+    const double *zc = Z + (int64_t)(J + (c < nb ? c : nb - 1)) * ldz + J;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = tid + HQ_TPB * i;
+      const double v = zc[r < rows ? r : rows - 1];
+      P[i][c] = (r < rows && c < nb) ? v : 0.0;
     }
-    const double sr = sigma * rho;
-    // R column j (rows J..m-1): the final entries above the pivot, -sigma rho
-    // on the diagonal, zeros below; local row r is owned by thread r mod HQ_TPB
-    for (int r = tid; r < m - J; r += HQ_TPB)
-      R[(J + r) + (int64_t)j * ldr] = r < c ? x[r] : (r == c ? -sr : 0.0);
-    // s_j in place of the column (own rows > c); the pivot entry is written
-    // after the column loop, since every thread reads the pivot above
-    const double spiv = ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : gamma / alpha);
-    for (int r = tid; r < rows; r += HQ_TPB)
-      if (r > c) x[r] = ident ? 0.0 : x[r] / alpha;
-    if (tid == 0) {
-      spv[c] = spiv;
-      bet[c] = beta;
-      if (ident) atomicCAS(status, 0, j + 1);
-      if (!(isfinite(ss) && isfinite(yj))) atomicCAS(status + 1, 0, j + 1);
-    }
-    // H_j = I - beta s_j s_j^t on the panel's later columns (own rows >= c)
-    const int nrem = nb - 1 - c;
-    if (nrem > 0) {  // uniform
-      double d[NB];
+  }
+  // the final entries of R above the panel
+  for (int r = tid; r < J; r += HQ_TPB) {
+    double v[NB];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) d[q] = 0.0;
-      for (int r = tid; r < rows; r += HQ_TPB) {
-        if (r < c) continue;
-        const double sv = r == c ? spiv : x[r];
+    for (int c = 0; c < NB; ++c) v[c] = Z[r + (int64_t)(J + (c < nb ? c : nb - 1)) * ldz];
 #pragma unroll
-        for (int q = 0; q < NB - 1; ++q)
-          if (q < nrem) d[q] += sv * Pn[(c + 1 + q) * rows + r];
+    for (int c = 0; c < NB; ++c)
+      if (c < nb) R[r + (int64_t)(J + c) * ldr] = v[c];
+  }
+  // one column step per compile-time c (the panel stays in registers)
+  static_for<0, NB>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    if (c < nb) {  // uniform
+      const int b = c & 1;
+      // the norm of rows >= c; the pivot (row c, thread c) to LDS
+      double ss = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = tid + HQ_TPB * i;
+        if (r >= c && r < rows) ss += P[i][c] * P[i][c];
       }
+      ss = wave_sum(ss);
+      if (lane == 0) nrm[b][w] = ss;
+      if (tid == c) pv[b] = P[0][c];
+      __syncthreads();
+      ss = 0.0;
 #pragma unroll
-      for (int q = 0; q < NB - 1; ++q) {
-        if (q < nrem) {
-          const double v = wave_sum(d[q]);
-          if (lane == 0) red[b][w][q] = v;
+      for (int k = 0; k < HQ_W; ++k) ss += nrm[b][k];
+      // RHVector scalars (every thread computes the same values)
+      const double rho = sqrt(ss);
+      const double yj = pv[b];
+      const double sigma = yj >= 0.0 ? 1.0 : -1.0;
+      const bool ident = !(rho > 0.0);
+      double gamma = 0.0, alpha = 1.0, beta = 0.0;
+      if (!ident) {
+        gamma = yj + sigma * rho;
+        if (scaling == RHQR_SCALE_UNIT_PIVOT) {
+          alpha = gamma;
+          beta = fabs(gamma) / rho;
+        } else {
+          alpha = sqrt(rho * fabs(gamma));
+          beta = 1.0;
         }
       }
-      __syncthreads();  // the product partials
-      double gq[NB];
+      // s_j in place of rows >= c (the rows above keep their R entries)
+      const double spiv = ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : gamma / alpha);
 #pragma unroll
-      for (int q = 0; q < NB - 1; ++q) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < HQ_W; ++i) s += q < nrem ? red[b][i][q] : 0.0;
-        gq[q] = beta * s;
+      for (int i = 0; i < RPT; ++i) {
+        const int r = tid + HQ_TPB * i;
+        if (r == c) P[i][c] = spiv;
+        else if (r > c && r < rows) P[i][c] = ident ? 0.0 : P[i][c] / alpha;
       }
-      for (int r = tid; r < rows; r += HQ_TPB) {
-        if (r < c) continue;
-        const double sv = r == c ? spiv : x[r];
+      if (tid == 0) {
+        bet[c] = beta;
+        dg[c] = -sigma * rho;
+        flags[c] = (ident ? 1 : 0) | (!(isfinite(ss) && isfinite(yj)) ? 2 : 0);
+      }
+      // H_j = I - beta s_j s_j^t on the panel's later columns (rows >= c)
+      if (c + 1 < nb) {  // uniform
+        double d[NB];
 #pragma unroll
-        for (int q = 0; q < NB - 1; ++q)
-          if (q < nrem) Pn[(c + 1 + q) * rows + r] -= gq[q] * sv;
+        for (int q = 0; q < NB; ++q) d[q] = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const int r = tid + HQ_TPB * i;
+          if (r >= c && r < rows) {
+#pragma unroll
+            for (int q = c + 1; q < NB; ++q) d[q] += P[i][c] * P[i][q];
+          }
+        }
+        // wave sums eight columns at a time: lane L holds the sum of column
+        // 8 h + (L >> 3) of group h
+#pragma unroll
+        for (int h = 0; h < NB / 8; ++h) {
+          if (8 * h + 7 <= c) continue;  // no later column in this group (uniform)
+          double v8[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v8[k] = d[8 * h + k];
+          const double tot = wave_sum8(v8);
+          if ((lane & 7) == 0) red[b][w][8 * h + (lane >> 3)] = tot;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = c + 1; q < NB; ++q) {
+          double sq = 0.0;
+#pragma unroll
+          for (int k = 0; k < HQ_W; ++k) sq += red[b][k][q];
+          const double g = beta * sq;
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) {
+            const int r = tid + HQ_TPB * i;
+            if (r >= c && r < rows) P[i][q] -= g * P[i][c];
+          }
+        }
       }
     }
+  });
+  // R columns J..J+nb-1, rows J..m-1 (the entries above each pivot, -sigma
+  // rho on the diagonal, zeros below) and S (the vectors: zeros above each
+  // pivot and above the panel), straight from the registers
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = tid + HQ_TPB * i;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c >= nb) continue;
+      if (r < m - J) R[(J + r) + (int64_t)(J + c) * ldr] = r < c ? P[i][c] : (r == c ? dg[c] : 0.0);
+      if (r < rows) S[(J + r) + (int64_t)(J + c) * lds] = r < c ? 0.0 : P[i][c];
+    }
+  }
+  for (int r = tid; r < J; r += HQ_TPB) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c < nb) S[r + (int64_t)(J + c) * lds] = 0.0;
+  }
+  if (tid == 0) {  // in column order: the first breakdown is the one kept
+    for (int c = 0; c < nb; ++c) {
+      if (flags[c] & 1) atomicCAS(status, 0, J + c + 1);
+      if (flags[c] & 2) atomicCAS(status + 1, 0, J + c + 1);
+    }
+  }
+  // T_pp: g_{q,c} = s_q^t s_c over rows >= c (s_c is zero above its pivot)
+  // for the NP = NB (NB - 1) / 2 pairs q < c, from the registers: per-thread
+  // partial sums, eight pairs per wave butterfly, then the waves in order
+  constexpr int NP = NB * (NB - 1) / 2;
+  constexpr int NP8 = (NP + 7) / 8;
+  double pp[NP8 * 8];
+#pragma unroll
+  for (int k = 0; k < NP8 * 8; ++k) pp[k] = 0.0;
+  {
+    int k = 0;
+#pragma unroll
+    for (int c = 1; c < NB; ++c)
+#pragma unroll
+      for (int q = 0; q < c; ++q, ++k) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const int r = tid + HQ_TPB * i;
+          if (r >= c && r < rows) pp[k] += P[i][q] * P[i][c];
+        }
+      }
+  }
+  __shared__ double gred[HQ_W][NP8 * 8];
+#pragma unroll
+  for (int h = 0; h < NP8; ++h) {
+    double v8[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v8[k] = pp[8 * h + k];
+    const double tot = wave_sum8(v8);
+    if ((lane & 7) == 0) gred[w][8 * h + (lane >> 3)] = tot;
   }
   __syncthreads();
-  if (tid < nb) Pn[tid * rows + tid] = spv[tid];
-  __syncthreads();
-  // the panel's vectors into S (zeros above each pivot: the panel column
-  // still holds its R entries there)
-  for (int e = tid; e < L * nb; e += HQ_TPB) {
-    const int r = e % L, c = e / L;
-    S[r + (int64_t)(J + c) * lds] = r < J + c ? 0.0 : Pn[c * rows + (r - J)];
-  }
-  // T_pp: g_{q,c} = s_q^t s_c over rows >= c (s_c is zero above its pivot),
-  // one wave per pair
-  for (int pr = w; pr < nb * nb; pr += HQ_W) {
-    const int q = pr % nb, c = pr / nb;
-    if (q >= c) continue;  // uniform across the wave
-    const double *xq = Pn + q * rows, *xc = Pn + c * rows;
+  if (tid < NP) {
+    int k = 0, qq = 0, cc = 1;
+    for (int c = 1; c < NB; ++c)
+      for (int q = 0; q < c; ++q, ++k)
+        if (k == tid) {
+          qq = q;
+          cc = c;
+        }
     double v = 0.0;
-    for (int r = c + lane; r < rows; r += 64) v += xq[r] * xc[r];
-    v = wave_sum(v);
-    if (lane == 0) gp[q][c] = v;
+#pragma unroll
+    for (int k2 = 0; k2 < HQ_W; ++k2) v += gred[k2][tid];
+    gp[qq][cc] = v;
   }
   __syncthreads();
   // row q of T_pp on lane q: T_qq = beta_q, T_qc = -beta_c sum_{q <= k < c} T_qk g_kc
@@ -291,40 +368,127 @@ __global__ void __launch_bounds__(HQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
   }
 }
 
-// trailing column k = J + nb + blockIdx.x of panel J: w = S_p^t Z_k,
-// u = T_pp^t w, Z_k -= S_p u (rows >= J), with the panel's vectors read from
-// S.  One workgroup per column: every thread loads its rows (at most
-// SQ_MAXL / TR_TPB) at once, the dot products are summed per wave and then
-// over the waves in a fixed order.
+// The trail launch of panel J (columns J..J+nb-1), workgroups in three
+// ranges:
+//  [0, ntrail): trailing column k = J + nb + b: w = S_p^t Z_k, u = T_pp^t w,
+//    Z_k -= S_p u (rows >= J), with the panel's vectors read from S.  Every
+//    thread loads its rows (at most SQ_MAXL / TR_TPB) at once, the dot
+//    products are summed per wave and then over the waves in a fixed order.
+//  [ntrail, ntrail + nx): X_p = S_{<J}^t S_p (J x nb, ld m) into Xc, one wave
+//    per earlier column q (rows >= J; the panel's vectors are zero above J).
+//  the rest: rows p0 .. p0 + TF_ROWS - 1 of the off-diagonal block of T of
+//    panel Jt (columns Jt..Jt+nbt-1): T_{<Jt, p} = -(T_{<Jt,<Jt} X) T_pp with
+//    X = Xt from that panel's trail launch, one thread per (row, column) of
+//    Y = T_{<Jt,<Jt} X.
 constexpr int TR_TPB = 256;
 constexpr int TR_RC = SQ_MAXL / TR_TPB;  // rows per thread
+constexpr int TF_ROWS = 16;              // rows of T per workgroup
 template <int NB>
 __global__ void __launch_bounds__(TR_TPB) k_hqr_trail(int32_t L, int32_t m, int32_t J, double *Z,
                                                       int64_t ldz, const double *S, int64_t lds,
-                                                      const double *T, int64_t ldt) {
+                                                      double *T, int64_t ldt, int ntrail, int nx,
+                                                      double *__restrict__ Xc, int32_t Jt,
+                                                      const double *__restrict__ Xt) {
   __shared__ double red[TR_TPB / 64][NB];
+  __shared__ double tpp[NB][NB];
+  __shared__ double yv[TF_ROWS][NB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int bid = (int)blockIdx.x;
+  if (bid >= ntrail + nx) {
+    // ---- off-diagonal block of T of panel Jt: rows p0 .. p0 + TF_ROWS - 1 (< Jt)
+    const int nbt = m - Jt < NB ? m - Jt : NB;
+    const int p0 = (bid - ntrail - nx) * TF_ROWS;
+    if (tid < NB * NB) {
+      const int q = tid % NB, c = tid / NB;
+      tpp[q][c] = (q < nbt && c < nbt && q <= c) ? T[(Jt + q) + (int64_t)(Jt + c) * ldt] : 0.0;
+    }
+    static_assert(TF_ROWS * NB <= TR_TPB, "one thread per entry");
+    const int pr = tid % TF_ROWS, c = tid / TF_ROWS;  // c < NB for tid < TF_ROWS NB
+    const int p = p0 + pr;
+    double y = 0.0;
+    if (p < Jt && c < nbt) {
+      const double *xc = Xt + (int64_t)c * m;
+      int q = p;
+      for (; q + 8 <= Jt; q += 8) {  // eight terms' loads together, added in order
+        double tv[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          tv[u] = T[p + (int64_t)(q + u) * ldt];
+          xv[u] = xc[q + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y += tv[u] * xv[u];
+      }
+      for (; q < Jt; ++q) y += T[p + (int64_t)q * ldt] * xc[q];
+    }
+    if (c < NB) yv[pr][c] = y;
+    __syncthreads();
+    if (p < Jt && c < nbt) {
+      double t = 0.0;
+      for (int q = 0; q <= c; ++q) t += yv[pr][q] * tpp[q][c];
+      T[p + (int64_t)(Jt + c) * ldt] = -t;
+    }
+    return;
+  }
   const int nb = m - J < NB ? m - J : NB;
-  const int rows = L - J, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int k = J + nb + (int)blockIdx.x;
-  if (k >= m) return;  // the whole workgroup
+  const int rows = L - J;
   const double *Sp = S + J + (int64_t)J * lds;  // Sp[r + q * lds]: panel vector q, row J + r
+  if (bid >= ntrail) {
+    // ---- X = S_{<J}^t S_p: wave w of workgroup bid - ntrail takes column q
+    const int q = (bid - ntrail) * (TR_TPB / 64) + w;
+    if (q >= J) return;  // the whole wave (no barrier follows)
+    const double *sq = S + (int64_t)q * lds + J;
+    double d[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) d[c] = 0.0;
+    for (int r0 = 0; r0 < rows; r0 += 64 * 4) {
+      double sv[4], pv[4][NB];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = r0 + lane + 64 * i, rc = r < rows ? r : rows - 1;
+        sv[i] = r < rows ? sq[rc] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) pv[i][c] = Sp[rc + (int64_t)(c < nb ? c : nb - 1) * lds];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) d[c] += sv[i] * pv[i][c];
+    }
+#pragma unroll
+    for (int h = 0; h < NB / 8; ++h) {
+      double v8[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v8[k] = d[8 * h + k];
+      const double tot = wave_sum8(v8);
+      const int c = 8 * h + (lane >> 3);
+      if ((lane & 7) == 0 && c < nb) Xc[q + (int64_t)c * m] = tot;
+    }
+    return;
+  }
+  // ---- trailing column
+  const int k = J + nb + bid;
   double *zk = Z + (int64_t)k * ldz + J;
+  if (tid < NB * NB) {
+    const int q = tid % NB, c = tid / NB;
+    tpp[q][c] = (q < nb && c < nb && q <= c) ? T[(J + q) + (int64_t)(J + c) * ldt] : 0.0;
+  }
   double zr[TR_RC], d[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) d[q] = 0.0;
+  // clamped row and column indices (every load in bounds, no branches, so
+  // the loads issue together); rows beyond the sketch carry z = 0 and
+  // columns beyond nb are not used
 #pragma unroll
   for (int i = 0; i < TR_RC; ++i) {
     const int r = tid + TR_TPB * i;
-    zr[i] = r < rows ? zk[r] : 0.0;
+    zr[i] = r < rows ? zk[r < rows ? r : rows - 1] : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < TR_RC; ++i) {
-    const int r = tid + TR_TPB * i;
-    if (r < rows) {
+    const int r = tid + TR_TPB * i, rc = r < rows ? r : rows - 1;
 #pragma unroll
-      for (int q = 0; q < NB; ++q)
-        if (q < nb) d[q] += Sp[r + (int64_t)q * lds] * zr[i];
-    }
+    for (int q = 0; q < NB; ++q) d[q] += Sp[rc + (int64_t)(q < nb ? q : nb - 1) * lds] * zr[i];
   }
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
@@ -343,112 +507,93 @@ __global__ void __launch_bounds__(TR_TPB) k_hqr_trail(int32_t L, int32_t m, int3
     double t = 0.0;
 #pragma unroll
     for (int q = 0; q < NB; ++q)
-      if (q <= c && c < nb) t += T[(J + q) + (int64_t)(J + c) * ldt] * d[q];
-    u[c] = t;
+      if (q <= c) t += tpp[q][c] * d[q];
+    u[c] = c < nb ? t : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < TR_RC; ++i) {
-    const int r = tid + TR_TPB * i;
-    if (r < rows) {
-      double zv = zr[i];
+    const int r = tid + TR_TPB * i, rc = r < rows ? r : rows - 1;
+    double zv = zr[i];
 #pragma unroll
-      for (int c = 0; c < NB; ++c)
-        if (c < nb) zv -= Sp[r + (int64_t)c * lds] * u[c];
-      zk[r] = zv;
-    }
+    for (int c = 0; c < NB; ++c)
+      if (c < nb) zv -= Sp[rc + (int64_t)c * lds] * u[c];
+    if (r < rows) zk[r] = zv;
   }
 }
 
-// T_{<J, p} = -(T_{<J,<J} G_{<J, p}) T_pp for the panel p = J..J+nb-1, with
-// G = S^t S (ld m).  One workgroup: Y = T_{<J,<J} G_{<J,p} into LDS (one
-// thread per entry, sum over q in increasing order), then the product with
-// the panel's diagonal block.  T_{<J,<J} comes from the earlier launches.
-constexpr int TF_TPB = 1024;
 template <int NB>
-__global__ void __launch_bounds__(TF_TPB) k_hqr_tfill(int32_t m, int32_t J,
-                                                      const double *__restrict__ G,
-                                                      double *__restrict__ T, int64_t ldt) {
-  extern __shared__ double Y[];  // J x nb, ld J
-  const int nb = m - J < NB ? m - J : NB;
-  for (int e = threadIdx.x; e < J * nb; e += TF_TPB) {
-    const int p = e % J, c = e / J;
-    const double *g = G + (int64_t)(J + c) * m;
-    double y = 0.0;
-    for (int q = p; q < J; ++q) y += T[p + (int64_t)q * ldt] * g[q];
-    Y[p + c * J] = y;
+int hqr_panel_launch(int rpt, int32_t L, int32_t m, int32_t J, double *Zc, double *S, int64_t lds,
+                     double *T, int64_t ldt, double *R, int64_t ldr, int32_t *status,
+                     hipStream_t st) {
+#define RHQR_HQR_PANEL(RPTV)                                                                    \
+  case RPTV:                                                                                    \
+    RHQR_LAUNCH(RHQR_PROF_HQR, (k_hqr_panel<NB, RPTV>), dim3(1), dim3(HQ_TPB), 0, st, L, m, J,   \
+                Zc, (int64_t)L, S, lds, T, ldt, R, ldr, (int)RHQR_SCALE_UNIT_PIVOT, status);   \
+    return RHQR_OK
+  switch (rpt) {
+    RHQR_HQR_PANEL(1);
+    RHQR_HQR_PANEL(2);
+    RHQR_HQR_PANEL(3);
+    RHQR_HQR_PANEL(4);
+    RHQR_HQR_PANEL(5);
+    RHQR_HQR_PANEL(6);
+    RHQR_HQR_PANEL(7);
+    RHQR_HQR_PANEL(8);
+    default:
+      return RHQR_ERR_UNSUPPORTED;
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < J * nb; e += TF_TPB) {
-    const int p = e % J, c = e / J;
-    double t = 0.0;
-    for (int q = 0; q <= c; ++q) t += Y[p + q * J] * T[(J + q) + (int64_t)(J + c) * ldt];
-    T[p + (int64_t)(J + c) * ldt] = -t;
+#undef RHQR_HQR_PANEL
+}
+
+template <int NB>
+int hqr_run(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, double *T, int64_t ldt,
+            double *R, int64_t ldr, double *X0, double *X1, int32_t *status, hipStream_t st) {
+  double *Xb[2] = {X0, X1};
+  int32_t Jprev = -1;  // the panel whose block of T is still to be formed
+  for (int32_t J = 0; J < m; J += NB) {
+    const int32_t nb = m - J < NB ? m - J : NB;
+    const int rpt = (L - J + HQ_TPB - 1) / HQ_TPB;
+    if (NB == 16 && rpt > 4) return RHQR_ERR_UNSUPPORTED;
+    int rc = hqr_panel_launch<NB>(rpt, L, m, J, Zc, S, lds, T, ldt, R, ldr, status, st);
+    if (rc) return rc;
+    const int ntrail = m - J - nb;
+    const int nx = (J + TR_TPB / 64 - 1) / (TR_TPB / 64);
+    const int ntf = Jprev > 0 ? (Jprev + TF_ROWS - 1) / TF_ROWS : 0;
+    const int grid = ntrail + nx + ntf;
+    if (grid > 0) {
+      double *Xc = Xb[(J / NB) & 1];
+      const double *Xt = Jprev >= 0 ? Xb[(Jprev / NB) & 1] : X0;
+      RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_trail<NB>, dim3((unsigned)grid), dim3(TR_TPB), 0, st, L, m,
+                  J, Zc, (int64_t)L, (const double *)S, lds, T, ldt, ntrail, nx, Xc,
+                  Jprev > 0 ? Jprev : 0, Xt);
+    }
+    Jprev = J;
   }
+  // the last panel's block of T
+  if (Jprev > 0) {
+    const int ntf = (Jprev + TF_ROWS - 1) / TF_ROWS;
+    RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_trail<NB>, dim3((unsigned)ntf), dim3(TR_TPB), 0, st, L, m,
+                Jprev, Zc, (int64_t)L, (const double *)S, lds, T, ldt, 0, 0, Xb[(Jprev / NB) & 1],
+                Jprev, (const double *)Xb[(Jprev / NB) & 1]);
+  }
+  return RHQR_OK;
 }
 
 }  // namespace
 
 // Sketch-space Householder QR of Z (L x m float64, copied to Zc, which is
-// overwritten): S (Householder vectors, unit pivot), T, R.  G: m x m float64
-// scratch (S^t S).
+// overwritten): S (Householder vectors, unit pivot), T, R.  X0, X1: two
+// m x m float64 scratch buffers (the products S_{<J}^t S_p of consecutive
+// panels).
 int sketch_space_hqr(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, double *T,
-                     int64_t ldt, double *R, int64_t ldr, double *G, const LoopWs &w,
-                     hipStream_t st) {
+                     int64_t ldt, double *R, int64_t ldr, double *X0, double *X1,
+                     const LoopWs &w, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_mat, dim3((m + 255) / 256, m), dim3(256), 0, st, T, ldt, m, m);
   RHQR_HIP(hipGetLastError());
-  if (L + m <= SQ_MAXL) {  // the panel in LDS; two launches per panel
-    const int NBv = hqr_nb(L, m);
-    static bool attr_set = false;
-    if (!attr_set) {
-      RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_panel<16>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)HQ_LDS_MAX));
-      RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_panel<8>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)HQ_LDS_MAX));
-      RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_tfill<16>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)HQ_LDS_MAX));
-      RHQR_HIP(hipFuncSetAttribute((const void *)k_hqr_tfill<8>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)HQ_LDS_MAX));
-      attr_set = true;
-    }
-    const size_t lds_bytes = sizeof(double) * (size_t)L * NBv;
-    for (int32_t J = 0; J < m; J += NBv) {
-      const int32_t nb = m - J < NBv ? m - J : NBv;
-      if (NBv == 16)
-        RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_panel<16>, dim3(1), dim3(HQ_TPB), lds_bytes, st, L, m, J,
-                    Zc, (int64_t)L, S, lds, T, ldt, R, ldr, (int)RHQR_SCALE_UNIT_PIVOT, w.status);
-      else
-        RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_panel<8>, dim3(1), dim3(HQ_TPB), lds_bytes, st, L, m, J,
-                    Zc, (int64_t)L, S, lds, T, ldt, R, ldr, (int)RHQR_SCALE_UNIT_PIVOT, w.status);
-      RHQR_HIP(hipGetLastError());
-      if (J + nb < m) {
-        const dim3 g((unsigned)(m - J - nb));
-        if (NBv == 16)
-          RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_trail<16>, g, dim3(TR_TPB), 0, st, L, m, J, Zc,
-                      (int64_t)L, (const double *)S, lds, (const double *)T, ldt);
-        else
-          RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_trail<8>, g, dim3(TR_TPB), 0, st, L, m, J, Zc,
-                      (int64_t)L, (const double *)S, lds, (const double *)T, ldt);
-        RHQR_HIP(hipGetLastError());
-      }
-    }
-    if (m > NBv) {
-      const int64_t nent = (int64_t)m * m;
-      RHQR_LAUNCH(RHQR_PROF_HQR, k_gram, dim3((nent + 15) / 16), dim3(1024), 0, st, m, L,
-                  (const double *)S, lds, (const double *)S, lds, G);
-      RHQR_HIP(hipGetLastError());
-      for (int32_t J = NBv; J < m; J += NBv) {
-        const int32_t nb = m - J < NBv ? m - J : NBv;
-        const size_t yb = sizeof(double) * (size_t)J * nb;
-        if (NBv == 16)
-          RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_tfill<16>, dim3(1), dim3(TF_TPB), yb, st, m, J,
-                      (const double *)G, T, ldt);
-        else
-          RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_tfill<8>, dim3(1), dim3(TF_TPB), yb, st, m, J,
-                      (const double *)G, T, ldt);
-        RHQR_HIP(hipGetLastError());
-      }
-    }
-    return RHQR_OK;
+  if (L + m <= SQ_MAXL) {  // the panel in registers; two launches per panel
+    if (hqr_nb(L) == 16)
+      return hqr_run<16>(L, m, Zc, S, lds, T, ldt, R, ldr, X0, X1, w.status, st);
+    return hqr_run<8>(L, m, Zc, S, lds, T, ldt, R, ldr, X0, X1, w.status, st);
   }
   LoopArgs a;
   a.kind = RHQR_SKETCH_IDENT;
@@ -513,7 +658,7 @@ extern "C" int recrhqr_factor(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, 
   rc = launch_sketch(h, dtype, n, m, d_W, ldw, w.Z, L, w.skws, w.skws_bytes, st);
   if (rc) return rc;
   RHQR_HIP(hipMemcpyAsync(w.Zc, w.Z, sizeof(double) * (size_t)L * m, hipMemcpyDeviceToDevice, st));
-  rc = sketch_space_hqr(L, m, w.Zc, d_S, lds, d_T, ldt, d_R, ldr, w.G, w.loop, st);
+  rc = sketch_space_hqr(L, m, w.Zc, d_S, lds, d_T, ldt, d_R, ldr, w.G, w.M, w.loop, st);
   if (rc) return rc;
   if (mode == RHQR_REC_M) {
     const int64_t nent = (int64_t)m * m;
