@@ -365,6 +365,16 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
  *     calls replay it.  Each problem's U, S, T, R equal those of rhqr_factor
  *     with the same schedule bitwise (same device code, same choice of
  *     matrix cores or vector units per panel, same reduction orders).
+ *   rhqr_batch_thin_q: after rhqr_batch_factor (on the same stream), the
+ *     thin Q of every problem i with d_Q[i] != NULL: Q_i = [I_m; 0] -
+ *     U_i T_i U_{i,1}^t (Sec. 3.2), n_i x m_i in the batch dtype, column-major
+ *     with leading dimension ldq[i] >= n_i.  d_Q and ldq are host arrays of
+ *     `count` entries in caller order (device pointers in d_Q, owned by the
+ *     caller).  The same kernels as rhqr_factor's thin Q, so each Q_i equals
+ *     the one rhqr_factor forms for that problem bitwise.  Launches per
+ *     problem on `stream` (not part of the factorization graph).  Returns -1
+ *     for a null batch, -2 for a null d_Q, -3 for a null ldq or ldq[i] < n_i
+ *     (before any launch).
  *   rhqr_batch_status: h_info[i] (host, count entries, caller order) = the
  *     status of problem i as rhqr_status reports it (0; j > 0 for the first
  *     column with rho_j = 0; -j for the first non-finite column).
@@ -389,6 +399,8 @@ RHQR_API size_t rhqr_batch_workspace_size(const rhqr_problem *probs, int32_t cou
 RHQR_API int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int dtype, int opts,
                                void *d_ws, size_t ws_bytes, void *stream, rhqr_batch_t *out);
 RHQR_API int rhqr_batch_factor(rhqr_batch_t b, int use_graph, void *stream);
+RHQR_API int rhqr_batch_thin_q(rhqr_batch_t b, void *const *d_Q, const int64_t *ldq,
+                               void *stream);
 RHQR_API int rhqr_batch_status(rhqr_batch_t b, void *stream, int32_t *h_info);
 RHQR_API int rhqr_batch_destroy(rhqr_batch_t b);
 

@@ -184,7 +184,8 @@ size_t problem_bytes(const rhqr_sketch_s *h, int dtype) {
   sketch_tail_partials_size(h, m, &gt, &skb);
   return align_up(loop_ws_bytes(h->kind, dtype, h->n, m, h->l)) +
          align_up(sizeof(double) * (size_t)L * m) + align_up(skb) +
-         2 * align_up(sizeof(double) * (size_t)m * BATCH_PB);
+         2 * align_up(sizeof(double) * (size_t)m * BATCH_PB) +
+         align_up(sizeof(double) * (size_t)m * m) + thin_q_bytes(m);  // thin Q: Mq, split coefficients
 }
 
 // panel-update workgroups of one problem (rows from m rounded down to VEC):
@@ -281,6 +282,8 @@ struct rhqr_batch_s {
   std::vector<int64_t> tall_start, red_start, pan_start;
   int64_t sk_blocks = 0, cols = 0;
   std::vector<ColProblem> hp;     // host copy of the descriptors (sorted)
+  std::vector<double *> mq;       // per problem (sorted): thin-Q scratch (m x m float64)
+  std::vector<void *> qmf;        //   and the split coefficients of the 2-byte thin Q
   ColProblem *d_probs = nullptr;
   SketchJob *d_jobs = nullptr;
   BlockMap *d_tall = nullptr, *d_red = nullptr, *d_sk = nullptr, *d_col = nullptr,
@@ -437,6 +440,9 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
     sketch_tail_partials_size(h, m, &gt0, &skb0);
     double *Cc = (double *)((char *)skpart + align_up(skb0));
     double *Gc = (double *)((char *)Cc + align_up(sizeof(double) * (size_t)m * BATCH_PB));
+    double *Mq = (double *)((char *)Gc + align_up(sizeof(double) * (size_t)m * BATCH_PB));
+    b->mq.push_back(Mq);
+    b->qmf.push_back((char *)Mq + align_up(sizeof(double) * (size_t)m * m));
     LoopArgs a;
     a.kind = h->kind;
     a.dtype = dtype;
@@ -530,6 +536,27 @@ extern "C" int rhqr_batch_factor(rhqr_batch_t b, int use_graph, void *stream) {
     RHQR_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   }
   RHQR_HIP(hipGraphLaunch(b->exec, st));
+  return RHQR_OK;
+}
+
+extern "C" int rhqr_batch_thin_q(rhqr_batch_t b, void *const *d_Q, const int64_t *ldq,
+                                 void *stream) {
+  if (!b) return -1;
+  if (!d_Q) return -2;
+  if (!ldq) return -3;
+  for (int s = 0; s < b->count; ++s) {
+    const int i = b->order[s];
+    if (d_Q[i] && ldq[i] < b->hp[s].n) return -3;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  for (int s = 0; s < b->count; ++s) {
+    const int i = b->order[s];
+    if (!d_Q[i]) continue;
+    const ColProblem &P = b->hp[s];
+    const int rc = launch_thin_q(b->dtype, P.n, P.m, P.W, P.ldw, P.S, P.lds, P.T, P.ldt, b->mq[s],
+                                 b->qmf[s], d_Q[i], ldq[i], st);
+    if (rc) return rc;
+  }
   return RHQR_OK;
 }
 

@@ -320,22 +320,24 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
       }
     }
   };
-  // SRHT, full workgroups of several tiles: two halves, the first half's
-  // tiles transformed while the second half's loads of w_j are in flight
-  // (the same arithmetic per row and per tile as the one-pass order)
-  constexpr bool PIPE = KIND == RHQR_SKETCH_SRHT && TPW >= 2 && NV % 2 == 0 && TPB == 1024;
+  // SRHT, float64, full workgroups of several tiles: two halves, the first
+  // half's tiles transformed while the second half's loads of w_j are in
+  // flight (the same arithmetic per row and per tile as the one-pass order;
+  // narrower types, with one or two vectors per thread and half, measured
+  // slower this way)
+  constexpr bool PIPE =
+      KIND == RHQR_SKETCH_SRHT && TPW >= 2 && NV % 2 == 0 && TPB == 1024 && sizeof(ST) == 8;
   bool piped = false;
   if constexpr (PIPE) {
-    if (fast) {
+    // only the short passes (at most TALL_CACHED_COLS stored columns, the
+    // blocked schedule's): a long pass gains nothing from hiding one transform
+    // and streams better in one piece
+    if (fast && j - 1 - p0 <= TALL_CACHED_COLS) {
       piped = true;
       constexpr int NVH = NV / 2, ROWSH = ROWS / 2, TPH = TPW / 2;
-      const bool ntu = j - 1 - p0 > TALL_CACHED_COLS;
       CT a0[NVH][VEC], a1[NVH][VEC];
-      if (ntu)
-        tall_body<ST, true, NVH, TPB, true>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base, a0);
-      else
-        tall_body<ST, true, NVH, TPB, false>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base,
-                                             a0);
+      tall_body<ST, true, NVH, TPB, false>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev, base,
+                                           a0);
       if (tid < NSW) sgn[tid] = sw;
       lds_barrier();
       to_lds(a0, NVH, 0);
@@ -343,12 +345,8 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
 #pragma unroll
       for (int v = 0; v < NVH; ++v) vload(wj + VEC * (tid + TPB * v), a1[v]);
       fwht_tiles_lds_part<CT, TPH>(s);
-      if (ntu)
-        tall_body<ST, true, NVH, TPB, true, true>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev,
-                                                  base + ROWSH, a1);
-      else
-        tall_body<ST, true, NVH, TPB, false, true>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev,
-                                                   base + ROWSH, a1);
+      tall_body<ST, true, NVH, TPB, false, true>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev,
+                                                 base + ROWSH, a1);
       to_lds(a1, NVH, ROWSH);
       fwht_tiles_lds_part<CT, TPH>(s + TPH * TILE_PAD);
     }

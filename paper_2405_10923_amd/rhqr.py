@@ -56,6 +56,7 @@ _SIGS = {
     "rhqr_batch_workspace_size": (_sz, [_vp, _i32, C.c_int]),
     "rhqr_batch_create": (C.c_int, [_vp, _i32, C.c_int, C.c_int, _vp, _sz, _vp, C.POINTER(_vp)]),
     "rhqr_batch_factor": (C.c_int, [_vp, C.c_int, _vp]),
+    "rhqr_batch_thin_q": (C.c_int, [_vp, _vp, _vp, _vp]),
     "rhqr_batch_status": (C.c_int, [_vp, _vp, _vp]),
     "rhqr_batch_destroy": (C.c_int, [_vp]),
     "rhqr_trim_workspace_size": (_sz, [_vp, C.c_int, _i32]),
@@ -344,7 +345,8 @@ class Batch:
     overwritten by U.  Allocates S, T, R per problem and the batch workspace;
     ``panel`` 16 selects the blocked schedule (0: column by column);
     ``factor(graph)`` runs the whole batch (as a replayed hipGraph when
-    ``graph`` is true).  ``outputs[i]`` = dict(U, S, T, R) in caller order."""
+    ``graph`` is true), ``thin_q()`` forms every problem's thin Q afterwards.
+    ``outputs[i]`` = dict(U, S, T, R[, Q]) in caller order."""
 
     def __init__(self, problems, scaling=SCALE_UNIT_PIVOT, panel=0):
         torch = _torch()
@@ -382,6 +384,21 @@ class Batch:
         _check(self._lib.rhqr_batch_factor(self.h, 1 if graph else 0, _stream()),
                "rhqr_batch_factor")
         return self.outputs
+
+    def thin_q(self, Qs=None):
+        """Thin Q of every problem (rhqr_batch_thin_q) after factor(): into
+        ``Qs[i]`` (n x m, column-major, the batch dtype; allocated when None);
+        returns the list in caller order."""
+        if Qs is None:
+            Qs = [colmajor_empty(W.shape[0], W.shape[1], self.dtype, W.device)
+                  for _, W in self.problems]
+        k = len(self.problems)
+        ptrs = (C.c_void_p * k)(*[Q.data_ptr() for Q in Qs])
+        lds = (C.c_int64 * k)(*[_ld(Q) for Q in Qs])
+        _check(self._lib.rhqr_batch_thin_q(self.h, ptrs, lds, _stream()), "rhqr_batch_thin_q")
+        for out, Q in zip(self.outputs, Qs):
+            out["Q"] = Q
+        return Qs
 
     def status(self):
         info = (C.c_int32 * len(self.problems))()

@@ -148,4 +148,5 @@ def test_batch_argument_errors():
     assert L.rhqr_batch_create(arr, 1, 0, 0, FAKE, 1 << 20, None, ctypes.byref(b)) == -1  # null sketch
     assert L.rhqr_batch_factor(None, 0, None) == -1
     assert L.rhqr_batch_status(None, None, None) == -1
+    assert L.rhqr_batch_thin_q(None, None, None, None) == -1
     assert L.rhqr_batch_destroy(None) == -1

@@ -164,3 +164,44 @@ def test_batch_c4_shapes_fp32_bounds():
         log(f"  n={n} m={m} cond=1e{kap:.1f}: e_fact {ef:.2e} e_orth {eo:.2e}")
         assert ef <= 1e-5 and eo <= 1e-5
     b.close()
+
+
+@pytest.mark.parametrize("panel", [0, 16])
+@pytest.mark.parametrize("dt", ["float64", "float32", "float16"])
+def test_batch_thin_q_bitwise_equals_single(dt, panel):
+    """rhqr_batch_thin_q after the batch: every problem's thin Q (Sec. 3.2)
+    equals the one rhqr_factor forms with want_q, bitwise (same kernels on the
+    same U, S, T); one problem is skipped (NULL Q) and must stay untouched."""
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    from paper_2405_10923_amd.rhqr import colmajor_empty
+    tdt = getattr(torch, dt)
+    probs = _inputs(torch, tdt)
+    log(f"batch thin Q {dt} panel={panel}: {len(probs)} problems")
+    b = rhqr.Batch([(sk, to_gpu(W, tdt)) for W, sk, _ in probs], panel=panel)
+    b.factor()
+    Qs = [colmajor_empty(W.shape[0], W.shape[1], tdt, "cuda") for W, _, _ in probs]
+    for Q in Qs:
+        Q.fill_(7.0)
+    skip = 3
+    import ctypes as C
+    k = len(Qs)
+    ptrs = (C.c_void_p * k)(*[None if i == skip else Q.data_ptr() for i, Q in enumerate(Qs)])
+    lds = (C.c_int64 * k)(*[Q.stride(1) for Q in Qs])
+    assert rhqr.lib().rhqr_batch_thin_q(b.h, ptrs, lds, rhqr._stream()) == 0
+    torch.cuda.synchronize()
+    assert b.status() == [0] * k
+    for i, ((W, sk, shp), Q) in enumerate(zip(probs, Qs)):
+        if i == skip:
+            assert bool((Q == 7.0).all()), shp
+            continue
+        ref = rhqr.factor(sk, to_gpu(W, tdt), panel=panel, want_q=True)
+        torch.cuda.synchronize()
+        assert torch.equal(Q, ref["Q"]), shp
+    # the Python wrapper on its own buffers
+    Qw = b.thin_q()
+    torch.cuda.synchronize()
+    for i, Q in enumerate(Qw):
+        if i != skip:
+            assert torch.equal(Q, Qs[i])
+    b.close()
