@@ -52,6 +52,41 @@ __global__ void __launch_bounds__(1024) k_pgram(int32_t L, int32_t J, int32_t nb
   pgram_block(L, J, nb, S, lds, Z, ldz, G, blockIdx.x);
 }
 
+// The same launch with the store of u_{J-1} beside it (the two are
+// independent; the panel update after them reads both): workgroups below npg
+// form G, the others scale rows of column cidx by 1/alpha, 16 bytes per
+// thread (aligned columns; the last rows one by one), as k_scale_col does.
+template <typename ST>
+__global__ void __launch_bounds__(1024) k_pgram_scale(int32_t L, int32_t J, int32_t nb,
+                                                      const double *__restrict__ S, int64_t lds,
+                                                      const double *__restrict__ Z, int64_t ldz,
+                                                      double *__restrict__ G, int npg,
+                                                      ST *__restrict__ W, int64_t ldw, int64_t n,
+                                                      int32_t m, int32_t cidx,
+                                                      const double *__restrict__ ia) {
+  if ((int)blockIdx.x < npg) {
+    pgram_block(L, J, nb, S, lds, Z, ldz, G, blockIdx.x);
+    return;
+  }
+  constexpr int VEC = 16 / sizeof(ST);
+  ST *col = W + (int64_t)cidx * ldw;
+  const double s = ia[cidx];
+  const int64_t r0 = m - (m % VEC);  // 16-byte aligned start at or below m
+  const int64_t i0 = r0 + ((int64_t)(blockIdx.x - npg) * 1024 + threadIdx.x) * VEC;
+  if (i0 >= n) return;
+  if (i0 + VEC <= n) {
+    ST v[VEC];
+    *reinterpret_cast<u32x4 *>(v) = *reinterpret_cast<const u32x4 *>(col + i0);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+      if (i0 + e >= m) v[e] = cvt_out<ST>(cvt_in<double>(v[e]) * s);
+    *reinterpret_cast<u32x4 *>(col + i0) = *reinterpret_cast<const u32x4 *>(v);
+  } else {
+    for (int64_t i = i0; i < n; ++i)
+      if (i >= m) col[i] = cvt_out<ST>(cvt_in<double>(col[i]) * s);
+  }
+}
+
 // rows J0..J-1 of C = T_{<J}^t G, padded to pw entries; grid
 // (ceil((J - J0) / PTRI_WAVES), pw), PTRI_WAVES waves per workgroup
 __global__ void __launch_bounds__(PTRI_WAVES * 64) k_ptri(int32_t J0, int32_t J, int32_t nb,
@@ -815,16 +850,27 @@ int run_blocked_typed(const LoopArgs &a, const LoopWs &w, int panel, int outer, 
   const int64_t ntail = a.n - m;
   // W_{:, J:J+nb} -= U_{:, K0:J} C_{K0:J}: finish u_{J-1}, form the
   // coefficients in the sketch space, then one tall product
+  const bool colaligned = ((uintptr_t)W % 16 == 0) && ((a.ldw * (int64_t)sizeof(ST)) % 16 == 0);
   auto apply = [&](int32_t K0, int32_t J, int32_t nb) -> int {
-    if (ntail > 0) {
-      hipLaunchKernelGGL((k_scale_col<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W, a.ldw,
-                         a.n, m, J - 1, w.ia);
+    const int64_t ne = (int64_t)J * nb;
+    const int npg = (int)((ne + 15) / 16);
+    if (ntail > 0 && colaligned) {  // u_{J-1} stored in the coefficient launch
+      constexpr int VEC = 16 / sizeof(ST);
+      const int64_t r0 = m - (m % VEC);
+      const int64_t nsc = (a.n - r0 + 1024LL * VEC - 1) / (1024LL * VEC);
+      hipLaunchKernelGGL((k_pgram_scale<ST>), dim3((unsigned)(npg + nsc)), dim3(1024), 0, st, L, J,
+                         nb, a.S, a.lds, a.Z, a.ldz, G, npg, W, a.ldw, a.n, m, J - 1, w.ia);
+      RHQR_HIP(hipGetLastError());
+    } else {
+      if (ntail > 0) {
+        hipLaunchKernelGGL((k_scale_col<ST>), dim3((ntail + 255) / 256), dim3(256), 0, st, W,
+                           a.ldw, a.n, m, J - 1, w.ia);
+        RHQR_HIP(hipGetLastError());
+      }
+      hipLaunchKernelGGL(k_pgram, dim3(npg), dim3(1024), 0, st, L, J, nb, a.S, a.lds, a.Z, a.ldz,
+                         G);
       RHQR_HIP(hipGetLastError());
     }
-    const int64_t ne = (int64_t)J * nb;
-    hipLaunchKernelGGL(k_pgram, dim3((ne + 15) / 16), dim3(1024), 0, st, L, J, nb, a.S, a.lds, a.Z,
-                       a.ldz, G);
-    RHQR_HIP(hipGetLastError());
     const int pw = panel_width(nb);
     hipLaunchKernelGGL(k_ptri, dim3((J - K0 + PTRI_WAVES - 1) / PTRI_WAVES, pw),
                        dim3(PTRI_WAVES * 64), 0, st, K0, J, nb, pw, a.T, a.ldt, G, C);
