@@ -545,6 +545,47 @@ def run_alg5(rhqr, torch, sk, W64, m, steps, blocks=(32, 8)):
     return out
 
 
+def run_right(rhqr, torch, sk, W64, m, steps):
+    """Right-looking RHQR (Alg. 3; opts bit 29: at step j the m - j trailing
+    columns sketched afresh, the reflector applied to every trailing column),
+    float64, same workload as the headline: time per factorization, the row
+    pass against its algorithmic bytes (step j reads and writes columns j ..
+    m-1: n m (m + 1) elements over the factorization), e_fact, e_orth."""
+    n = W64.shape[0]
+    W = rhqr.colmajor_empty(n, m, torch.float64, W64.device)
+    bufs = rhqr.FactorBuffers(sk, torch.float64, m)
+    restore = lambda: W.copy_(W64)
+    run = lambda: rhqr.factor(sk, W, bufs=bufs, right=True)
+    ms = _time(torch, run, steps, 1, restore)
+    rhqr.profile_begin()
+    for _ in range(steps):
+        restore()
+        run()
+    torch.cuda.synchronize()
+    prof = rhqr.profile_end()
+    U, T, R = W, bufs.T, bufs.R
+    Q = -U @ (T @ U[:m].t())
+    Q[:m] += torch.eye(m, dtype=torch.float64, device=W.device)
+    ef = float(torch.linalg.norm(W64 - Q @ R) / torch.linalg.norm(W64))
+    Y = rhqr.sketch(sk, Q)
+    import numpy as np
+    eo = float(np.linalg.norm((Y.t() @ Y).cpu().numpy() - np.eye(m), 2))
+    info = rhqr.status(bufs.ws)
+    del Q, Y
+    ms_ap, cnt = prof["right_apply"]
+    byts = 8.0 * n * m * (m + 1) * steps
+    ach = byts / (ms_ap * 1e-3) / 1e9 if cnt else None
+    del W, bufs
+    torch.cuda.empty_cache()
+    return {"workload": f"float64 {n} x {m}, SRHT l = {sk.l}", "ms": round(ms, 3),
+            "e_fact": ef, "e_orth": eo, "info": info,
+            "row_pass": {"launches_per_step": cnt // steps if cnt else 0,
+                         "ms_per_step": round(ms_ap / steps, 3) if cnt else None,
+                         "achieved_GBps": round(ach, 1) if ach else None,
+                         "frac_hbm": round(ach / HBM_PEAK_GBS, 4) if ach else None},
+            "kernels_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items() if v[1]}}
+
+
 def run_trim(rhqr, torch, steps, n=1 << 20, m=128, l=64):
     """Left-looking trimRHQR (Alg. 12) of a 2^20 x 128 float64 matrix (cond
     1e12) with an SRHT of l = 64 < m rows on every row: time per
@@ -780,6 +821,9 @@ def main():
         extra["block_rhqr_alg5_f64"] = run_alg5(rhqr, torch, sk, W64, m, max(2, args.steps // 2))
         print(f"# Alg. 5 block RHQR float64: {json.dumps(extra['block_rhqr_alg5_f64'])}",
               file=sys.stderr, flush=True)
+        extra["right_looking_alg3_f64"] = run_right(rhqr, torch, sk, W64, m, 2)
+        print(f"# Alg. 3 right-looking RHQR float64: "
+              f"{json.dumps(extra['right_looking_alg3_f64'])}", file=sys.stderr, flush=True)
     batched = None
     if args.batch_count > 0:
         del W64

@@ -143,7 +143,16 @@ RHQR_API int rhqr_sketch(rhqr_sketch_t h, int dtype, int64_t n, int32_t k, const
  *           in exact arithmetic (U, S, T, R as without the bit).  For storage
  *           types narrower than float64 the block's head rows pass through
  *           the storage type between the earlier blocks' updates.
- *           Bits 29-31 must be 0.
+ *           Bit 29: right-looking RHQR as Alg. 3 writes it (bits 8-28 must
+ *           then be 0): at step j the m - j trailing columns are sketched
+ *           afresh, RHVector of column j is formed from the first of those
+ *           sketches and the reflector is applied to every trailing column
+ *           (W_{:,k} -= beta_j u_j s_j^t Psi w_k).  Same U, S, T, R as Alg. 4
+ *           in exact arithmetic (T by Alg. 4's recursion); about three times
+ *           the HBM traffic of the left-looking form.  For storage types
+ *           narrower than float64 the trailing columns (head rows included)
+ *           pass through the storage type after every step.
+ *           Bits 30-31 must be 0.
  *   d_ws  : device workspace, >= rhqr_factor_workspace_size(h, dtype, m) bytes
  * One synchronisation per column: the refreshed column's sketch (Alg. 4).
  * Breakdown (rho_j = 0) gives an identity reflector (beta_j = 0, R_jj = 0) and
@@ -419,6 +428,10 @@ RHQR_API int rhqr_batch_destroy(rhqr_batch_t b);
  *   RHQR_PROF_QTAIL       tail product of the thin Q (Sec. 3.2)
  *   RHQR_PROF_TRSM        blocked substitution of recRHQR (Alg. 6)
  *   RHQR_PROF_HQR         sketch-space Householder QR of recRHQR (Alg. 6)
+ *   RHQR_PROF_RIGHT_VEC   per-column RHVector step of right-looking RHQR
+ *                         (Alg. 3): s_j, R, T and the trailing coefficients
+ *   RHQR_PROF_RIGHT_APPLY per-column row pass of right-looking RHQR (Alg. 3):
+ *                         u_j stored, the trailing columns updated
  * rhqr_profile_end(nclass, h_ms, h_launches) synchronises the recorded events
  * and writes, for classes 0 .. nclass-1, the summed kernel time in ms
  * (h_ms[c]) and the number of launches (h_launches[c]); host arrays of nclass
@@ -438,7 +451,9 @@ enum {
   RHQR_PROF_QTAIL = 6,
   RHQR_PROF_TRSM = 7,
   RHQR_PROF_HQR = 8,
-  RHQR_PROF_NCLASS = 9
+  RHQR_PROF_RIGHT_VEC = 9,
+  RHQR_PROF_RIGHT_APPLY = 10,
+  RHQR_PROF_NCLASS = 11
 };
 RHQR_API int rhqr_profile_begin(void);
 RHQR_API int rhqr_profile_end(int32_t nclass, double *h_ms, int64_t *h_launches);

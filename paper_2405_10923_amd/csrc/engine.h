@@ -101,6 +101,11 @@ int run_column_loop_blocked(const LoopArgs &a, const LoopWs &w, int panel, int o
 int run_column_loop_alg5(const rhqr_sketch_s *h, const LoopArgs &a, const LoopWs &w, int b,
                          double *C, double *G, double *Z, void *skws, size_t skws_bytes,
                          hipStream_t st);
+// right-looking RHQR as Alg. 3 writes it: at step j the m - j trailing
+// columns are sketched into Z ((l+m) x m float64) with the multi-column sketch
+// workspace skws, then RHVector and the trailing update (right.hip)
+int run_column_loop_right(const rhqr_sketch_s *h, const LoopArgs &a, const LoopWs &w, double *Z,
+                          void *skws, size_t skws_bytes, hipStream_t st);
 // thin Q = [I; 0] - U T U_1^t (Sec. 3.2); Mq: m x m float64 scratch, qmf:
 // thin_q_bytes(m) bytes of scratch (2-byte storage: split coefficients)
 size_t thin_q_bytes(int32_t m);

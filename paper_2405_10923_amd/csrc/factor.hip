@@ -23,12 +23,12 @@ struct FactorWs {
   void *qmf;      // split coefficients of the matrix-core thin Q
 };
 
-// the multi-column sketch workspace for m columns, or for any block of at most
-// 32 columns (block RHQR sketches one block at a time; fewer columns can take
-// more partial groups each)
+// the multi-column sketch workspace for any number of columns up to m (the
+// pre-sketch takes m, block RHQR one block of at most 32, right-looking RHQR
+// the m - j trailing columns; fewer columns can take more partial groups each)
 size_t factor_sketch_ws(const rhqr_sketch_s *h, int32_t m) {
-  size_t b = sketch_ws_bytes(h, m);
-  for (int32_t k = 1; k <= 32 && k <= m; ++k) {
+  size_t b = 0;
+  for (int32_t k = 1; k <= m; ++k) {
     const size_t bk = sketch_ws_bytes(h, k);
     if (bk > b) b = bk;
   }
@@ -84,8 +84,10 @@ bool opts_ok(int opts) {
   const int outer = (opts >> 16) & 0xff;
   const int tpw = (opts >> 24) & 0xf;
   const bool alg5 = (opts >> 28) & 1;
+  const bool alg3 = (opts >> 29) & 1;
   return !((scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) || panel > 32 ||
-           ((unsigned)opts >> 29) != 0 || (tpw != 0 && tpw != 1 && tpw != 2 && tpw != 4) ||
+           ((unsigned)opts >> 30) != 0 ||
+           (alg3 && (opts & 0x1fffff00) != 0) || (tpw != 0 && tpw != 1 && tpw != 2 && tpw != 4) ||
            (alg5 && (panel < 1 || outer != 0)) ||
            (outer != 0 && (panel < 2 || outer <= panel || outer > 32 || outer % panel != 0)));
 }
@@ -105,10 +107,12 @@ int factor_core(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W, int
   hipLaunchKernelGGL(k_zero_sq, dim3((m + 255) / 256, m), dim3(256), 0, st, d_T, ldt, m, m);
   RHQR_HIP(hipGetLastError());
   const bool alg5 = (opts >> 28) & 1;
+  const bool alg3 = (opts >> 29) & 1;
 
   // pre-sketch of every column: "if next vector available, sketch it now"
-  // (block RHQR sketches each block afresh instead)
-  if (!alg5) {
+  // (block RHQR sketches each block afresh instead, right-looking RHQR the
+  // trailing columns at every step)
+  if (!alg5 && !alg3) {
     rc = launch_sketch(h, dtype, n, m, d_W, ldw, w.Z, L, w.skws, w.skws_bytes, st);
     if (rc) return rc;
   }
@@ -135,7 +139,9 @@ int factor_core(rhqr_sketch_t h, int dtype, int64_t n, int32_t m, void *d_W, int
   a.omega = h->d_omega;
   a.defer = 1;
   a.tpw = (opts >> 24) & 0xf;
-  if (alg5)
+  if (alg3)
+    rc = run_column_loop_right(h, a, w.loop, w.Z, w.skws, w.skws_bytes, st);
+  else if (alg5)
     rc = run_column_loop_alg5(h, a, w.loop, panel, w.C, w.G, w.Z, w.skws, w.skws_bytes, st);
   else
     rc = panel >= 2 ? run_column_loop_blocked(a, w.loop, panel, outer, w.C, w.G, st)

@@ -219,16 +219,21 @@ class FactorBuffers:
         self.ws = workspace(lib().rhqr_factor_workspace_size(sk.h, dtype_code(dtype), m), dev)
 
 
-def factor(sk, W, scaling=SCALE_UNIT_PIVOT, want_q=False, bufs=None, panel=0, outer=0, tpw=0):
+def factor(sk, W, scaling=SCALE_UNIT_PIVOT, want_q=False, bufs=None, panel=0, outer=0, tpw=0,
+           right=False):
     """Left-looking RHQR (Alg. 4).  W (n x m, column-major, GPU) is overwritten
     by U.  ``panel`` >= 2 selects the blocked schedule (panels of that many
     columns); ``outer`` > panel groups the panels in outer panels of that many
     columns (two levels); ``panel=None`` takes the autotuned schedule of the
     problem's size (schedules.lookup); ``tpw`` sets the transform tiles per
-    workgroup of the refresh pass (0: the library's choice).  Returns
-    dict(U=W, S, T, R, Q)."""
+    workgroup of the refresh pass (0: the library's choice).  ``right=True``
+    runs right-looking RHQR (Alg. 3) instead (the schedule arguments must then
+    be 0).  Returns dict(U=W, S, T, R, Q)."""
     n, m = W.shape
-    if panel is None:
+    if right:
+        if panel or outer or tpw:
+            raise ValueError("right-looking RHQR takes no schedule options")
+    elif panel is None:
         from .schedules import lookup
         panel, outer, tpw, _ = lookup(W.dtype, n, m)
     if bufs is None:
@@ -237,7 +242,8 @@ def factor(sk, W, scaling=SCALE_UNIT_PIVOT, want_q=False, bufs=None, panel=0, ou
     rc = lib().rhqr_factor(sk.h, dtype_code(W.dtype), n, m, _ptr(W), _ld(W), _ptr(bufs.S),
                            _ld(bufs.S), _ptr(bufs.T), _ld(bufs.T), _ptr(bufs.R), _ld(bufs.R),
                            _ptr(Q), _ld(Q) if Q is not None else 0,
-                           int(scaling) | (int(panel) << 8) | (int(outer) << 16) | (int(tpw) << 24),
+                           int(scaling) | (int(panel) << 8) | (int(outer) << 16) | (int(tpw) << 24)
+                           | ((1 << 29) if right else 0),
                            _ptr(bufs.ws),
                            bufs.ws.numel(), _stream())
     _check(rc, "rhqr_factor")
@@ -423,7 +429,7 @@ def profile_begin():
 
 # kernel classes of rhqr_profile_end, in the order of RHQR_PROF_*
 PROF_CLASSES = ("tall", "panel_mx", "panel_valu", "presketch", "red", "fin", "qtail", "trsm",
-                "hqr")
+                "hqr", "right_vec", "right_apply")
 
 
 def profile_end():

@@ -125,15 +125,16 @@ def test_spmv_colscale_profile_argument_errors():
     assert L.rhqr_scale_r(4, None, 4, FAKE, None) == -2
     assert L.rhqr_scale_r(4, FAKE, 3, FAKE, None) == -3
     assert L.rhqr_scale_r(4, FAKE, 4, None, None) == -4
-    ms = (ctypes.c_double * 9)()
-    cnt = (ctypes.c_int64 * 9)()
+    ncls = 11  # RHQR_PROF_NCLASS
+    ms = (ctypes.c_double * (ncls + 1))()
+    cnt = (ctypes.c_int64 * (ncls + 1))()
     assert L.rhqr_profile_end(-1, ms, cnt) == -1
-    assert L.rhqr_profile_end(10, ms, cnt) == -1
+    assert L.rhqr_profile_end(ncls + 1, ms, cnt) == -1
     assert L.rhqr_profile_end(2, None, cnt) == -2
     assert L.rhqr_profile_end(2, ms, None) == -3
     assert L.rhqr_profile_begin() == 0
-    assert L.rhqr_profile_end(9, ms, cnt) == 0      # an empty window
-    assert list(cnt) == [0] * 9
+    assert L.rhqr_profile_end(ncls, ms, cnt) == 0   # an empty window
+    assert list(cnt) == [0] * (ncls + 1)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

@@ -56,7 +56,10 @@ def test_factor_argument_errors_before_launch():
     assert call(a15=(33 << 8)) == -15               # panel wider than 32
     assert call(a15=(8 << 8) | (12 << 16)) == -15   # outer not a multiple of the panel
     assert call(a15=(3 << 24)) == -15               # tiles per workgroup not 0, 1, 2 or 4
-    assert call(a15=(1 << 28)) == -15               # reserved bits
+    assert call(a15=(1 << 28)) == -15               # Alg. 5 needs a block width
+    assert call(a15=(1 << 29) | (8 << 8)) == -15    # Alg. 3 takes no schedule bits
+    assert call(a15=(1 << 29) | (1 << 28)) == -15
+    assert call(a15=(1 << 30)) == -15               # reserved bits
     assert call(a16=None) == -16
     need = L.rhqr_factor_workspace_size(sk.h, 0, m)
     assert call(a17=need - 1) == rhqr.RHQR_ERR_WORKSPACE

@@ -16,7 +16,8 @@ products (no library kernel is involved in a check):
   columns, backward error within the tolerance.
 
 Workloads: W = G diag(s) V with singular values 1..1e-12 (2^20 x 128, SRHT and
-Gaussian l = 512) and 1..1e-14 (2^22 x 256, SRHT l = 1024, two-level panels:
+Gaussian l = 512; left-looking column by column, in panels, and right-looking
+as Alg. 3 writes it) and 1..1e-14 (2^22 x 256, SRHT l = 1024, two-level panels:
 the configuration bench.py times).  float64 tolerance 1e-12."""
 import numpy as np
 import pytest
@@ -73,7 +74,7 @@ def _checks(torch, W, U, S, T, R, osketch, m, cols, what):
 
 
 @pytest.mark.parametrize("kind", ["srht", "gauss"])
-@pytest.mark.parametrize("panel", [16, 0])
+@pytest.mark.parametrize("panel", [16, 0, "alg3"])
 def test_c2_f64_rhqr_fullsize(kind, panel):
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
@@ -90,7 +91,10 @@ def test_c2_f64_rhqr_fullsize(kind, panel):
         sk = rhqr.Sketch(rhqr.GAUSS, n, m, l, seed=0, omega=omd)
         del omd
     Wd = W0.clone()
-    out = rhqr.factor(sk, Wd, panel=panel)
+    if panel == "alg3":  # right-looking RHQR (Alg. 3)
+        out = rhqr.factor(sk, Wd, right=True)
+    else:
+        out = rhqr.factor(sk, Wd, panel=panel)
     torch.cuda.synchronize()
     assert rhqr.status(out["ws"]) == 0
     _checks(torch, W0, out["U"], out["S"], out["T"], out["R"], osketch, m, (0, 1, 63, 127),

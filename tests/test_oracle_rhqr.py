@@ -87,6 +87,35 @@ def test_rhqr_left_equals_lapack_qr_of_sketch(kind):
     assert np.allclose(out["T"], _woodbury_T(out["S"]), rtol=0, atol=1e-11)
 
 
+@pytest.mark.parametrize("kind,scaling", [(sketch.SRHT, "B"), (sketch.GAUSS, "B"),
+                                          (sketch.SRHT, "A")])
+def test_rhqr_right_equals_lapack_qr_of_sketch(kind, scaling):
+    """Alg. 3 pinned on its own (not through Alg. 4): Thm. 3.1 makes its R and
+    its sketched reflectors those of Householder QR of Psi W; its U satisfies
+    S = Psi U column by column; scaling "A" gives the same reflector
+    directions with ||s_j||^2 = 2."""
+    n, m, l = 520, 11, 44
+    W = make_w(n, m, 3, seed=14)
+    sk = sketch.Sketch(kind, n, m, l, seed=9)
+    out = rhqr.rhqr_right(W, sk, scaling)
+    Z = sketch.rh_sketch(W, sk)
+    (qr, tau), _ = scipy.linalg.qr(Z, mode="raw")
+    V = np.tril(qr[:, :m], -1)
+    V[np.arange(m), np.arange(m)] = 1.0
+    Rl = np.triu(qr[:m, :m])
+    assert np.allclose(out["R"], Rl, rtol=0, atol=1e-13 * np.max(np.abs(Rl)))
+    S = out["S"]
+    if scaling == "B":
+        assert np.allclose(S, V, rtol=0, atol=1e-12)
+        assert np.allclose(out["beta"], tau, rtol=1e-12, atol=0)
+    else:
+        assert np.allclose(S / S[np.arange(m), np.arange(m)], V, rtol=0, atol=1e-12)
+        assert np.allclose(np.sum(S * S, axis=0), 2.0, rtol=1e-13)
+        assert np.all(out["beta"] == 1.0)
+    assert np.allclose(sketch.rh_sketch(out["U"], sk), S, rtol=0, atol=1e-13)
+    assert np.all(np.triu(out["U"][:m], 1) == 0)
+
+
 def test_rhqr_left_compact_form_and_sketch_orthogonality():
     n, m, l = 700, 10, 40
     W = make_w(n, m, 6, seed=5)
