@@ -732,6 +732,9 @@ def main():
                          "factorization with thin Q at the workload's size, the Gaussian "
                          "pre-sketch and the recRHQR of a 2^20 x 128 matrix with l = 512), for "
                          "counter runs")
+    ap.add_argument("--alg3-probe", action="store_true",
+                    help="only time right-looking RHQR (Alg. 3) on the workload (for a kernel "
+                         "trace) and exit")
     ap.add_argument("--print-digest", action="store_true",
                     help="print the digest of the kernel sources and exit")
     args = ap.parse_args()
@@ -762,6 +765,10 @@ def main():
     print(f"# workload n={n} m={m} l={l} cond=1e{kappa:g}", file=sys.stderr, flush=True)
     W64 = synthetic_matrix_torch(n, m, kappa, seed=0, device="cuda")
     sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=0)
+    if args.alg3_probe:
+        out = run_right(rhqr, torch, sk, W64, m, 2)
+        print(json.dumps({"alg3_probe": out}), flush=True)
+        return
     if args.mfma_probe:
         for name in ("float64", "float16"):
             dt = getattr(torch, name)

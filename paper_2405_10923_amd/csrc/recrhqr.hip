@@ -222,13 +222,15 @@ __global__ void __launch_bounds__(HQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
           beta = 1.0;
         }
       }
-      // s_j in place of rows >= c (the rows above keep their R entries)
-      const double spiv = ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : gamma / alpha);
+      // s_j in place of rows >= c (the rows above keep their R entries),
+      // scaled by one reciprocal of alpha
+      const double ia = 1.0 / alpha;
+      const double spiv = ident ? 1.0 : (scaling == RHQR_SCALE_UNIT_PIVOT ? 1.0 : gamma * ia);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const int r = tid + HQ_TPB * i;
         if (r == c) P[i][c] = spiv;
-        else if (r > c && r < rows) P[i][c] = ident ? 0.0 : P[i][c] / alpha;
+        else if (r > c && r < rows) P[i][c] = ident ? 0.0 : P[i][c] * ia;
       }
       if (tid == 0) {
         bet[c] = beta;
@@ -260,12 +262,14 @@ __global__ void __launch_bounds__(HQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
           if ((lane & 7) == 0) red[b][w][8 * h + (lane >> 3)] = tot;
         }
         __syncthreads();
+        // lane q (mod NB) sums column q over the waves in order; every thread
+        // then reads the sums from those lanes
+        double sq = 0.0;
+#pragma unroll
+        for (int k = 0; k < HQ_W; ++k) sq += red[b][k][lane & (NB - 1)];
 #pragma unroll
         for (int q = c + 1; q < NB; ++q) {
-          double sq = 0.0;
-#pragma unroll
-          for (int k = 0; k < HQ_W; ++k) sq += red[b][k][q];
-          const double g = beta * sq;
+          const double g = beta * lane_read(sq, q);
 #pragma unroll
           for (int i = 0; i < RPT; ++i) {
             const int r = tid + HQ_TPB * i;
@@ -300,44 +304,41 @@ __global__ void __launch_bounds__(HQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
     }
   }
   // T_pp: g_{q,c} = s_q^t s_c over rows >= c (s_c is zero above its pivot)
-  // for the NP = NB (NB - 1) / 2 pairs q < c, from the registers: per-thread
-  // partial sums, eight pairs per wave butterfly, then the waves in order
+  // for the NP = NB (NB - 1) / 2 pairs q < c (pair k = c (c - 1) / 2 + q),
+  // from the registers: per-thread partial sums, eight pairs per wave
+  // butterfly, then the waves in order
   constexpr int NP = NB * (NB - 1) / 2;
   constexpr int NP8 = (NP + 7) / 8;
-  double pp[NP8 * 8];
-#pragma unroll
-  for (int k = 0; k < NP8 * 8; ++k) pp[k] = 0.0;
-  {
-    int k = 0;
-#pragma unroll
-    for (int c = 1; c < NB; ++c)
-#pragma unroll
-      for (int q = 0; q < c; ++q, ++k) {
+  __shared__ double gred[HQ_W][NP8 * 8];
+  static_for<0, NP8>([&](auto hh) {
+    constexpr int h = decltype(hh)::value;
+    double v8[8];
+    static_for<0, 8>([&](auto kk) {
+      constexpr int k = 8 * h + decltype(kk)::value;
+      constexpr int c = [] {
+        int cc = 1, first = 0;
+        while (first + cc <= k) first += cc++;
+        return cc;
+      }();
+      constexpr int q = k - c * (c - 1) / 2;
+      double acc = 0.0;
+      if constexpr (k < NP) {
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
           const int r = tid + HQ_TPB * i;
-          if (r >= c && r < rows) pp[k] += P[i][q] * P[i][c];
+          if (r >= c && r < rows) acc += P[i][q] * P[i][c];
         }
       }
-  }
-  __shared__ double gred[HQ_W][NP8 * 8];
-#pragma unroll
-  for (int h = 0; h < NP8; ++h) {
-    double v8[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v8[k] = pp[8 * h + k];
+      v8[decltype(kk)::value] = acc;
+    });
     const double tot = wave_sum8(v8);
     if ((lane & 7) == 0) gred[w][8 * h + (lane >> 3)] = tot;
-  }
+  });
   __syncthreads();
   if (tid < NP) {
-    int k = 0, qq = 0, cc = 1;
-    for (int c = 1; c < NB; ++c)
-      for (int q = 0; q < c; ++q, ++k)
-        if (k == tid) {
-          qq = q;
-          cc = c;
-        }
+    int cc = 1;
+    while (cc * (cc + 1) / 2 <= tid) ++cc;  // pair tid = cc (cc - 1) / 2 + qq
+    const int qq = tid - cc * (cc - 1) / 2;
     double v = 0.0;
 #pragma unroll
     for (int k2 = 0; k2 < HQ_W; ++k2) v += gred[k2][tid];
