@@ -349,15 +349,16 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
 
 /* ------------------------------------------------------------------------
  * Batched left-looking RHQR: `count` independent factorizations (Alg. 4 with
- * RHVector, Alg. 2), each with its own n, m, l (taken from its SRHT sketch
- * handle), W, S, T and R as in rhqr_factor, all in one element type.
- *   rhqr_problem: sketch (SRHT handle with the problem's n, head m and l),
+ * RHVector, Alg. 2), each with its own n, m, l (taken from its sketch
+ * handle), W, S, T and R as in rhqr_factor, all in one element type and one
+ * sketch kind (every handle SRHT, or every handle Gaussian).
+ *   rhqr_problem: sketch (handle with the problem's n, head m and l),
  *     d_W (n x m in dtype, ld >= n; overwritten by U), d_S ((l+m) x m float64),
  *     d_T, d_R (m x m float64).  Device pointers, owned by the caller.
  *   rhqr_batch_workspace_size: device workspace bytes for the batch (0 if a
  *     problem is invalid).
  *   rhqr_batch_create: validates the problems (m <= 1024, l <= 4096, leading
- *     dimensions), lays the descriptors and per-problem scratch out in the
+ *     dimensions, one sketch kind), lays the descriptors and per-problem scratch out in the
  *     caller's workspace d_ws (kept by the batch until rhqr_batch_destroy: the
  *     caller must keep it alive), uploads them on `stream` and synchronises.
  *     opts: bits 0-7 rhqr_scaling; bits 8-15 panel width: 0 (column
@@ -367,9 +368,10 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
  *     -5 null workspace, RHQR_ERR_WORKSPACE if ws_bytes is too small.
  *   rhqr_batch_factor: factors every problem of the batch.  The work is a
  *     fixed sequence of kernel launches (no allocation, no host
- *     synchronisation, no memset): per column index j one refresh + re-sketch
- *     launch, one reduction and one float64 step over the problems with
- *     m_p > j.  use_graph != 0: the sequence is captured once into a hipGraph
+ *     synchronisation, no memset): the pre-sketch (one launch over every
+ *     problem for SRHT batches; per problem, as rhqr_sketch, for Gaussian
+ *     ones), then per column index j one refresh + re-sketch launch, one
+ *     reduction and one float64 step over the problems with m_p > j.  use_graph != 0: the sequence is captured once into a hipGraph
  *     (on the batch's own stream) and the graph is launched on `stream`; later
  *     calls replay it.  Each problem's U, S, T, R equal those of rhqr_factor
  *     with the same schedule bitwise (same device code, same choice of

@@ -1,5 +1,6 @@
 // Batched left-looking RHQR (Alg. 4 with RHVector, Alg. 2): many independent
-// problems, each with its own W (n_p x m_p), SRHT sketch and outputs, factored
+// problems, each with its own W (n_p x m_p), sketch (SRHT or Gaussian, one
+// kind per batch) and outputs, factored
 // by one fixed sequence of launches that allocates nothing, synchronises with
 // nothing on the host and can be captured once in a hipGraph and replayed.
 //
@@ -74,6 +75,16 @@ __global__ void __launch_bounds__(BATCH_TPB) kb_tall(const ColProblem *__restric
                                                      int32_t p0) {
   const BlockMap b = map[blockIdx.x];
   tall_block<ST, RHQR_SKETCH_SRHT, TPW, BATCH_TPB>(P[b.p], j, p0, b.local);
+}
+
+// Gaussian sketches: the tall workgroups of the single-problem path (1024
+// threads; the Gaussian partial products assume them)
+template <typename ST, int TPW>
+__global__ void __launch_bounds__(1024) kb_tall_gauss(const ColProblem *__restrict__ P,
+                                                      const BlockMap *__restrict__ map, int32_t j,
+                                                      int32_t p0) {
+  const BlockMap b = map[blockIdx.x];
+  tall_block<ST, RHQR_SKETCH_GAUSS, TPW, 1024>(P[b.p], j, p0, b.local);
 }
 
 template <typename ST>
@@ -227,7 +238,9 @@ int plan(const rhqr_problem *probs, int32_t count, int dtype, Layout *o) {
     o->ngroups[s] = (h->n + (int64_t)TILE * SK_TPW - 1) / ((int64_t)TILE * SK_TPW);
     o->tall_start[s + 1] = o->tall_start[s] + o->nparts[s];
     o->red_start[s + 1] = o->red_start[s] + o->gred[s];
-    o->sk_start[s + 1] = o->sk_start[s] + (int64_t)h->m * gt;
+    // the SRHT pre-sketch runs as blocks of one launch; a Gaussian batch
+    // pre-sketches problem by problem (the split-K product of rhqr_sketch)
+    o->sk_start[s + 1] = o->sk_start[s] + (h->kind == RHQR_SKETCH_SRHT ? (int64_t)h->m * gt : 0);
     o->col_start[s + 1] = o->col_start[s] + h->m;
     o->npanel[s] = panel_groups(h->n, h->m, dtype);
     o->pan_start[s + 1] = o->pan_start[s] + o->npanel[s];
@@ -262,7 +275,8 @@ int check_problems(const rhqr_problem *probs, int32_t count, int dtype) {
   for (int32_t i = 0; i < count; ++i) {
     const rhqr_problem &q = probs[i];
     const rhqr_sketch_s *h = q.sketch;
-    if (!h || h->kind != RHQR_SKETCH_SRHT) return -1;
+    if (!h || (h->kind != RHQR_SKETCH_SRHT && h->kind != RHQR_SKETCH_GAUSS)) return -1;
+    if (h->kind != probs[0].sketch->kind) return -1;  // one sketch kind per batch
     if (h->m < 1 || h->m > MAXM || h->l > 4096) return -1;
     if (!q.d_W || q.ldw < h->n) return -1;
     if (!q.d_S || q.lds < h->l + h->m) return -1;
@@ -276,6 +290,10 @@ int check_problems(const rhqr_problem *probs, int32_t count, int dtype) {
 
 struct rhqr_batch_s {
   int dtype = 0, count = 0, maxm = 0, tpw = 1, qa = 1, maxL = 0;
+  int kind = RHQR_SKETCH_SRHT;     // every problem's sketch kind
+  std::vector<const rhqr_sketch_s *> hs;  // per problem (sorted): its sketch handle,
+  std::vector<double *> skpart, zs;       //   pre-sketch partials and Z (Gaussian batches)
+  std::vector<size_t> skbytes;
   int panel = 0;                  // 0: column schedule, BATCH_PB: blocked
   std::vector<int32_t> order;     // sorted position -> caller index
   std::vector<int32_t> ms;        // m of each sorted problem (decreasing)
@@ -306,6 +324,17 @@ int enqueue_typed(rhqr_batch_s *b, hipStream_t st) {
   using AT = typename CompT<ST>::type;
   hipLaunchKernelGGL(kb_init, dim3(b->count), dim3(256), 0, st, b->d_probs);
   RHQR_HIP(hipGetLastError());
+  const bool gauss = b->kind == RHQR_SKETCH_GAUSS;
+  if (gauss) {
+    // Z = Psi W per problem: the single-problem pre-sketch (split-K product
+    // on matrix cores and its finish), so Z equals rhqr_factor's bitwise
+    for (int s = 0; s < b->count; ++s) {
+      const ColProblem &P = b->hp[s];
+      const int rc = launch_sketch(b->hs[s], b->dtype, P.n, P.m, P.W, P.ldw, b->zs[s],
+                                   P.ldz, b->skpart[s], b->skbytes[s], st);
+      if (rc) return rc;
+    }
+  } else {
   switch (b->qa) {
     case 1:
       hipLaunchKernelGGL((kb_srht_cols<ST, AT, 1>), dim3(b->sk_blocks), dim3(SK_TPB), 0, st, b->d_jobs, b->d_sk);
@@ -323,6 +352,7 @@ int enqueue_typed(rhqr_batch_s *b, hipStream_t st) {
   hipLaunchKernelGGL((kb_sketch_finish<ST>), dim3(b->cols, (b->maxL + 255) / 256), dim3(256), 0, st,
                      b->d_jobs, b->d_col);
   RHQR_HIP(hipGetLastError());
+  }
   const int pb = b->panel >= 2 ? b->panel : b->maxm;  // column schedule: one panel
   for (int32_t J = 0; J < b->maxm; J += pb) {
     if (J > 0) {
@@ -346,8 +376,12 @@ int enqueue_typed(rhqr_batch_s *b, hipStream_t st) {
       const int a = active(b, j);
       if (j >= 1) {
         constexpr int TPW = sizeof(ST) == 2 ? 2 : 1;  // = batch_tpw(dtype)
-        hipLaunchKernelGGL((kb_tall<ST, TPW>), dim3(b->tall_start[a]), dim3(BATCH_TPB), 0, st,
-                           b->d_probs, b->d_tall, j, J);
+        if (gauss)
+          hipLaunchKernelGGL((kb_tall_gauss<ST, TPW>), dim3(b->tall_start[a]), dim3(1024), 0, st,
+                             b->d_probs, b->d_tall, j, J);
+        else
+          hipLaunchKernelGGL((kb_tall<ST, TPW>), dim3(b->tall_start[a]), dim3(BATCH_TPB), 0, st,
+                             b->d_probs, b->d_tall, j, J);
         RHQR_HIP(hipGetLastError());
       }
       hipLaunchKernelGGL((kb_red<ST>), dim3(b->red_start[a]), dim3(256), 0, st, b->d_probs,
@@ -404,6 +438,7 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
 
   rhqr_batch_s *b = new rhqr_batch_s();
   b->dtype = dtype;
+  b->kind = probs[0].sketch->kind;
   b->count = count;
   b->tpw = tpw;
   b->panel = panel;
@@ -442,6 +477,10 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
     double *Gc = (double *)((char *)Cc + align_up(sizeof(double) * (size_t)m * BATCH_PB));
     double *Mq = (double *)((char *)Gc + align_up(sizeof(double) * (size_t)m * BATCH_PB));
     b->mq.push_back(Mq);
+    b->hs.push_back(h);
+    b->skpart.push_back(skpart);
+    b->skbytes.push_back(skb0);
+    b->zs.push_back(Z);
     b->qmf.push_back((char *)Mq + align_up(sizeof(double) * (size_t)m * m));
     LoopArgs a;
     a.kind = h->kind;
@@ -462,7 +501,7 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
     a.scaling = scaling;
     a.signs = h->d_signs;
     a.rows = h->d_rows;
-    a.omega = nullptr;
+    a.omega = h->d_omega;  // null for the SRHT
     a.defer = 1;
     b->hp[s] = make_col_problem(a, lw, tpw);
     b->hp[s].C = Cc;
@@ -484,7 +523,8 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
     jb.scale = 1.0 / std::sqrt((double)h->l);
     for (int64_t k = 0; k < L.nparts[s]; ++k) tall_map[L.tall_start[s] + k] = {s, (int32_t)k};
     for (int64_t k = 0; k < L.gred[s]; ++k) red_map[L.red_start[s] + k] = {s, (int32_t)k};
-    for (int64_t k = 0; k < (int64_t)m * L.gt[s]; ++k) sk_map[L.sk_start[s] + k] = {s, (int32_t)k};
+    if (h->kind == RHQR_SKETCH_SRHT)  // the blocks of the one-launch SRHT pre-sketch
+      for (int64_t k = 0; k < (int64_t)m * L.gt[s]; ++k) sk_map[L.sk_start[s] + k] = {s, (int32_t)k};
     for (int32_t k = 0; k < m; ++k) col_map[L.col_start[s] + k] = {s, k};
     for (int64_t k = 0; k < L.npanel[s]; ++k) pan_map[L.pan_start[s] + k] = {s, (int32_t)k};
   }

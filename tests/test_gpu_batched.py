@@ -205,3 +205,78 @@ def test_batch_thin_q_bitwise_equals_single(dt, panel):
         if i != skip:
             assert torch.equal(Q, Qs[i])
     b.close()
+
+
+# Gaussian batches: Omega drawn by the test (the oracle's draw) and handed to
+# both sides; one sketch kind per batch
+GSHAPES = [(5000, 12, 48, 1), (3 * 4096 + 777, 24, 96, 3), (300, 7, 40, 4), (2 * 4096 + 5, 40, 130, 7)]
+
+
+def _gauss_inputs(shapes=GSHAPES, kappa=3.0):
+    from paper_2405_10923_amd import rhqr
+    probs = []
+    for n, m, l, seed in shapes:
+        W = synthetic_matrix(n, m, kappa, seed=seed)
+        osketch = osk.Sketch(osk.GAUSS, n, m, l, seed=seed + 200)
+        sk = rhqr.Sketch(rhqr.GAUSS, n, m, l, seed=seed + 200, omega=to_gpu(osketch.omega))
+        probs.append((W, sk, osketch, (n, m, l, seed)))
+    return probs
+
+
+@pytest.mark.parametrize("panel", [0, 16])
+@pytest.mark.parametrize("dt", ["float64", "float32", "bfloat16"])
+def test_batch_gauss_bitwise_equals_single(dt, panel):
+    """A batch of Gaussian-sketch problems: per problem the single-problem
+    pre-sketch and tall workgroups, so every factor equals rhqr_factor's
+    bitwise; the hipGraph form replays to the same bits."""
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    tdt = getattr(torch, dt)
+    probs = _gauss_inputs()
+    log(f"gaussian batch {dt} panel={panel}: {len(probs)} problems")
+    b = rhqr.Batch([(sk, to_gpu(W, tdt)) for W, sk, _, _ in probs], panel=panel)
+    outs = b.factor()
+    torch.cuda.synchronize()
+    assert b.status() == [0] * len(probs)
+    eager = [{k: o[k].clone() for k in ("U", "S", "T", "R")} for o in outs]
+    for (W, sk, _, shp), o in zip(probs, outs):
+        log(f"  single {shp}")
+        ref = rhqr.factor(sk, to_gpu(W, tdt), panel=panel)
+        torch.cuda.synchronize()
+        for k in ("U", "S", "T", "R"):
+            assert torch.equal(o[k], ref[k]), (shp, k)
+    if dt == "float64":
+        for rep in range(2):
+            for (W, _, _, _), o in zip(probs, outs):
+                o["U"].copy_(to_gpu(W, tdt))
+            b.factor(graph=True)
+            torch.cuda.synchronize()
+            for e, o in zip(eager, outs):
+                for k in e:
+                    assert torch.equal(o[k], e[k]), (rep, k)
+    b.close()
+
+
+def test_batch_gauss_f64_matches_oracle():
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    probs = _gauss_inputs(kappa=2.0)
+    b = rhqr.Batch([(sk, to_gpu(W)) for W, sk, _, _ in probs], panel=16)
+    outs = b.factor()
+    torch.cuda.synchronize()
+    for (W, _, osketch, (n, m, l, _)), o in zip(probs, outs):
+        log(f"  oracle gaussian {n} {m} {l}")
+        ref = orq.rhqr_left(W, osketch)
+        for k in ("U", "S", "T", "R"):
+            assert rel(to_np(o[k]), ref[k]) < 1e-12, (n, m, l, k)
+    b.close()
+
+
+def test_batch_rejects_mixed_sketch_kinds():
+    torch = cuda_or_skip()
+    from paper_2405_10923_amd import rhqr
+    (W0, sk0, _, _), = _gauss_inputs(shapes=[(5000, 12, 48, 1)])
+    sk1 = rhqr.Sketch(rhqr.SRHT, 4096, 8, 32, seed=3)
+    W1 = synthetic_matrix(4096, 8, 2.0, seed=3)
+    with pytest.raises(rhqr.RHQRError):
+        rhqr.Batch([(sk0, to_gpu(W0)), (sk1, to_gpu(W1))])
