@@ -412,12 +412,15 @@ def run_batched(rhqr, torch, count, steps, warmup, dtype_name="float32", panel=1
     torch.cuda.synchronize()
     ms = float(np.mean([a.elapsed_time(c) for a, c in evs]))
     info = b.status()
-    # the batch's thin Q (rhqr_batch_thin_q, every problem), timed after the
-    # factorization of the last step
+    # the batch's thin Q (rhqr_batch_thin_q, every problem) after the
+    # factorization of the last step: outputs allocated and one call made
+    # first, then one call timed
+    Qall = [rhqr.colmajor_empty(W.shape[0], W.shape[1], W.dtype, W.device) for _, W in b.problems]
+    b.thin_q(Qall)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    Qall = b.thin_q()
+    b.thin_q(Qall)
     e1.record()
     torch.cuda.synchronize()
     ms_q = e0.elapsed_time(e1)

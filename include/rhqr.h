@@ -381,11 +381,15 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
  *     U_i T_i U_{i,1}^t (Sec. 3.2), n_i x m_i in the batch dtype, column-major
  *     with leading dimension ldq[i] >= n_i.  d_Q and ldq are host arrays of
  *     `count` entries in caller order (device pointers in d_Q, owned by the
- *     caller).  The same kernels as rhqr_factor's thin Q, so each Q_i equals
- *     the one rhqr_factor forms for that problem bitwise.  Launches per
- *     problem on `stream` (not part of the factorization graph).  Returns -1
- *     for a null batch, -2 for a null d_Q, -3 for a null ldq or ldq[i] < n_i
- *     (before any launch).
+ *     caller).  The same device code per entry and per workgroup as
+ *     rhqr_factor's thin Q, so each Q_i equals the one rhqr_factor forms for
+ *     that problem bitwise.  One launch per stage over all problems (a job
+ *     table of the Q pointers is uploaded on `stream` from pinned memory the
+ *     batch owns); problem by problem instead when a float64/float32 problem's
+ *     U or Q columns are not 16-byte aligned.  Not part of the factorization
+ *     graph.  Calls on one batch must be ordered (one stream): they share the
+ *     batch's scratch.  Returns -1 for a null batch, -2 for a null d_Q, -3
+ *     for a null ldq or ldq[i] < n_i (before any launch).
  *   rhqr_batch_status: h_info[i] (host, count entries, caller order) = the
  *     status of problem i as rhqr_status reports it (0; j > 0 for the first
  *     column with rho_j = 0; -j for the first non-finite column).

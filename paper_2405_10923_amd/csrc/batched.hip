@@ -179,13 +179,16 @@ inline int batch_tpw(int dtype) { return dtype_size(dtype) == 2 ? 2 : 1; }
 struct Layout {
   // sorted order and per-problem geometry
   std::vector<int32_t> order;
-  std::vector<int64_t> nparts, gred, gt, ngroups, npanel;
+  std::vector<int64_t> nparts, gred, gt, ngroups, npanel, qblocks, qgroups;
+  std::vector<int32_t> qtiles, qkp;
+  int64_t qblocks_total = 0;
+  int32_t qtiles_max = 0;
   // prefix sums over the sorted problems
   std::vector<int64_t> tall_start, red_start, sk_start, col_start, pan_start;
   size_t head_bytes = 0, total = 0;
   std::vector<size_t> off;  // per sorted problem: start of its region
   size_t off_probs = 0, off_jobs = 0, off_tall = 0, off_red = 0, off_sk = 0, off_col = 0,
-         off_pan = 0;
+         off_pan = 0, off_qjobs = 0, off_qmap = 0;
 };
 
 size_t problem_bytes(const rhqr_sketch_s *h, int dtype) {
@@ -222,6 +225,10 @@ int plan(const rhqr_problem *probs, int32_t count, int dtype, Layout *o) {
   o->gt.resize(count);
   o->ngroups.resize(count);
   o->npanel.resize(count);
+  o->qblocks.resize(count);
+  o->qgroups.resize(count);
+  o->qtiles.resize(count);
+  o->qkp.resize(count);
   o->pan_start.assign(count + 1, 0);
   o->tall_start.assign(count + 1, 0);
   o->red_start.assign(count + 1, 0);
@@ -243,10 +250,13 @@ int plan(const rhqr_problem *probs, int32_t count, int dtype, Layout *o) {
     o->sk_start[s + 1] = o->sk_start[s] + (h->kind == RHQR_SKETCH_SRHT ? (int64_t)h->m * gt : 0);
     o->col_start[s + 1] = o->col_start[s] + h->m;
     o->npanel[s] = panel_groups(h->n, h->m, dtype);
+    o->qblocks[s] = thin_q_tail_blocks(dtype, h->n, h->m, &o->qtiles[s], &o->qgroups[s], &o->qkp[s]);
+    o->qblocks_total += o->qblocks[s];
+    o->qtiles_max = std::max(o->qtiles_max, o->qtiles[s]);
     o->pan_start[s + 1] = o->pan_start[s] + o->npanel[s];
   }
   if (o->tall_start[count] > INT32_MAX || o->sk_start[count] > INT32_MAX ||
-      o->pan_start[count] > INT32_MAX)
+      o->pan_start[count] > INT32_MAX || o->qblocks_total > INT32_MAX)
     return RHQR_ERR_UNSUPPORTED;
   size_t b = 0;
   auto take = [&](size_t bytes) {
@@ -261,6 +271,8 @@ int plan(const rhqr_problem *probs, int32_t count, int dtype, Layout *o) {
   o->off_sk = take(sizeof(BlockMap) * o->sk_start[count]);
   o->off_col = take(sizeof(BlockMap) * o->col_start[count]);
   o->off_pan = take(sizeof(BlockMap) * o->pan_start[count]);
+  o->off_qjobs = take(sizeof(ThinQJob) * count);
+  o->off_qmap = take(sizeof(ThinQBlock) * o->qblocks_total);
   o->head_bytes = b;
   o->off.resize(count);
   for (int s = 0; s < count; ++s) o->off[s] = take(problem_bytes(probs[o->order[s]].sketch, dtype));
@@ -302,6 +314,15 @@ struct rhqr_batch_s {
   std::vector<ColProblem> hp;     // host copy of the descriptors (sorted)
   std::vector<double *> mq;       // per problem (sorted): thin-Q scratch (m x m float64)
   std::vector<void *> qmf;        //   and the split coefficients of the 2-byte thin Q
+  // batched thin Q: the per-problem jobs without their Q (filled per call in
+  // a pinned staging table, uploaded to d_qjobs), the tail-workgroup map
+  std::vector<ThinQJob> qjob;
+  ThinQJob *h_qjobs = nullptr, *d_qjobs = nullptr;
+  ThinQBlock *d_qmap = nullptr;
+  int64_t qblocks = 0;
+  int32_t qtiles_max = 0;
+  hipEvent_t qev = nullptr;  // the last upload of the staging table
+  bool qev_pending = false;
   ColProblem *d_probs = nullptr;
   SketchJob *d_jobs = nullptr;
   BlockMap *d_tall = nullptr, *d_red = nullptr, *d_sk = nullptr, *d_col = nullptr,
@@ -451,6 +472,11 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
   std::vector<SketchJob> jobs(count);
   std::vector<BlockMap> tall_map(L.tall_start[count]), red_map(L.red_start[count]),
       sk_map(L.sk_start[count]), col_map(L.col_start[count]), pan_map(L.pan_start[count]);
+  std::vector<ThinQBlock> qmap((size_t)L.qblocks_total);
+  b->qjob.resize(count);
+  b->qblocks = L.qblocks_total;
+  b->qtiles_max = L.qtiles_max;
+  int64_t qpos = 0;
   b->hp.resize(count);
   for (int s = 0; s < count; ++s) {
     const rhqr_problem &q = probs[L.order[s]];
@@ -527,6 +553,22 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
       for (int64_t k = 0; k < (int64_t)m * L.gt[s]; ++k) sk_map[L.sk_start[s] + k] = {s, (int32_t)k};
     for (int32_t k = 0; k < m; ++k) col_map[L.col_start[s] + k] = {s, k};
     for (int64_t k = 0; k < L.npanel[s]; ++k) pan_map[L.pan_start[s] + k] = {s, (int32_t)k};
+    ThinQJob &qj = b->qjob[s];
+    qj = ThinQJob{};
+    qj.n = h->n;
+    qj.ldu = q.ldw;
+    qj.lds = q.lds;
+    qj.ldt = q.ldt;
+    qj.groups = L.qgroups[s];
+    qj.m = m;
+    qj.tiles = L.qtiles[s];
+    qj.Kp = L.qkp[s];
+    qj.U = q.d_W;
+    qj.S = q.d_S;
+    qj.T = q.d_T;
+    qj.Mq = Mq;
+    qj.qmf = b->qmf.back();
+    for (int64_t k = 0; k < L.qblocks[s]; ++k) qmap[qpos++] = {s, (int32_t)k};
   }
   b->d_probs = (ColProblem *)(ws + L.off_probs);
   b->d_jobs = (SketchJob *)(ws + L.off_jobs);
@@ -535,6 +577,8 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
   b->d_sk = (BlockMap *)(ws + L.off_sk);
   b->d_col = (BlockMap *)(ws + L.off_col);
   b->d_pan = (BlockMap *)(ws + L.off_pan);
+  b->d_qjobs = (ThinQJob *)(ws + L.off_qjobs);
+  b->d_qmap = (ThinQBlock *)(ws + L.off_qmap);
   auto up = [&](void *dst, const void *src, size_t bytes) -> int {
     if (bytes == 0) return RHQR_OK;
     RHQR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
@@ -547,9 +591,17 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
   if (!rc) rc = up(b->d_sk, sk_map.data(), sizeof(BlockMap) * sk_map.size());
   if (!rc) rc = up(b->d_col, col_map.data(), sizeof(BlockMap) * col_map.size());
   if (!rc) rc = up(b->d_pan, pan_map.data(), sizeof(BlockMap) * pan_map.size());
+  if (!rc) rc = up(b->d_qmap, qmap.data(), sizeof(ThinQBlock) * qmap.size());
   if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = RHQR_ERR_HIP;
   if (!rc && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) rc = RHQR_ERR_HIP;
+  if (!rc && hipHostMalloc((void **)&b->h_qjobs, sizeof(ThinQJob) * count, hipHostMallocDefault) !=
+                 hipSuccess)
+    rc = RHQR_ERR_HIP;
+  if (!rc && hipEventCreateWithFlags(&b->qev, hipEventDisableTiming) != hipSuccess)
+    rc = RHQR_ERR_HIP;
   if (rc) {
+    if (b->qev) (void)hipEventDestroy(b->qev);
+    if (b->h_qjobs) (void)hipHostFree(b->h_qjobs);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
     return rc;
@@ -589,6 +641,42 @@ extern "C" int rhqr_batch_thin_q(rhqr_batch_t b, void *const *d_Q, const int64_t
     if (d_Q[i] && ldq[i] < b->hp[s].n) return -3;
   }
   hipStream_t st = (hipStream_t)stream;
+  // one launch per stage over every problem, unless a float64/float32
+  // problem has columns that are not 16-byte aligned (then problem by problem)
+  const size_t es = dtype_size(b->dtype);
+  bool batched = true;
+  for (int s = 0; s < b->count && es >= 4; ++s) {
+    const int i = b->order[s];
+    const ThinQJob &t = b->qjob[s];
+    if (d_Q[i] && !((uintptr_t)t.U % 16 == 0 && (uintptr_t)d_Q[i] % 16 == 0 &&
+                    (t.ldu * (int64_t)es) % 16 == 0 && (ldq[i] * (int64_t)es) % 16 == 0))
+      batched = false;
+  }
+  if (batched) {
+    if (b->qev_pending) RHQR_HIP(hipEventSynchronize(b->qev));  // the staging table is free
+    for (int s = 0; s < b->count; ++s) {
+      const int i = b->order[s];
+      ThinQJob t = b->qjob[s];
+      if (d_Q[i]) {
+        t.Q = d_Q[i];
+        t.ldq = ldq[i];
+        const char *u1 = (const char *)t.U + (size_t)t.m * es;
+        const char *q1 = (const char *)d_Q[i] + (size_t)t.m * es;
+        t.aligned = ((uintptr_t)u1 % 16 == 0) && ((uintptr_t)q1 % 8 == 0) &&
+                    ((t.ldu * (int64_t)es) % 16 == 0) && ((ldq[i] * (int64_t)es) % 8 == 0);
+      } else {
+        t.m = 0;  // skipped
+        t.tiles = 0;
+      }
+      b->h_qjobs[s] = t;
+    }
+    RHQR_HIP(hipMemcpyAsync(b->d_qjobs, b->h_qjobs, sizeof(ThinQJob) * b->count,
+                            hipMemcpyHostToDevice, st));
+    RHQR_HIP(hipEventRecord(b->qev, st));
+    b->qev_pending = true;
+    return launch_thin_q_batched(b->dtype, b->count, b->maxm, b->qtiles_max, b->d_qjobs, b->d_qmap,
+                                 b->qblocks, st);
+  }
   for (int s = 0; s < b->count; ++s) {
     const int i = b->order[s];
     if (!d_Q[i]) continue;
@@ -619,6 +707,8 @@ extern "C" int rhqr_batch_destroy(rhqr_batch_t b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->qev) (void)hipEventDestroy(b->qev);
+  if (b->h_qjobs) (void)hipHostFree(b->h_qjobs);
   delete b;
   return RHQR_OK;
 }

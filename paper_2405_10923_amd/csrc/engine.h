@@ -112,6 +112,30 @@ size_t thin_q_bytes(int32_t m);
 int launch_thin_q(int dtype, int64_t n, int32_t m, const void *U, int64_t ldu, const double *S,
                   int64_t lds, const double *T, int64_t ldt, double *Mq, void *qmf, void *Q,
                   int64_t ldq, hipStream_t st);
+// The thin Q of many problems, one launch per stage over all of them (the
+// same per-entry and per-workgroup code as launch_thin_q, so each Q is the
+// single-problem one bitwise).  A job with m = 0 and tiles = 0 is skipped.
+// float64/float32 need every job's U and Q 16-byte aligned (the matrix-core
+// tail product); 2-byte storage takes any alignment.  Mq: m x m float64
+// scratch, qmf: thin_q_bytes(m) bytes of scratch, per job.
+struct ThinQJob {
+  int64_t n, ldu, lds, ldt, ldq, groups;
+  int32_t m, tiles, Kp, aligned;
+  const void *U;
+  const double *S, *T;
+  double *Mq;
+  void *qmf, *Q;
+};
+struct ThinQBlock {
+  int32_t p, local;  // job, workgroup of its tail product
+};
+// workgroups of one problem's tail product and its geometry (tiles of Q's
+// columns, row groups, padded coefficient rows)
+int64_t thin_q_tail_blocks(int dtype, int64_t n, int32_t m, int32_t *tiles, int64_t *groups,
+                           int32_t *Kp);
+int launch_thin_q_batched(int dtype, int32_t count, int32_t maxm, int32_t maxtiles,
+                          const ThinQJob *d_jobs, const ThinQBlock *d_map, int64_t nblocks,
+                          hipStream_t st);
 int launch_fill(void *p, size_t bytes, hipStream_t st);
 // X M = B for `rows` rows (B, X n-row data in dtype, column-major; M upper
 // triangular m x m float64): blocked forward substitution (recRHQR, Alg. 6).

@@ -130,26 +130,34 @@ __global__ void k_fill(uint32_t *p, size_t nwords) {
 
 // ----------------------------------------------------------------- thin Q
 // Mq = T U_1^t (m x m):  Mq_{p,c} = sum_{q=p..c} T_{p,q} U1_{c,q}
-__global__ void k_tu1t(int32_t m, const double *T, int64_t ldt, const double *S, int64_t lds,
-                       double *Mq) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int cidx = blockIdx.y;
-  if (p >= m) return;
+__device__ __forceinline__ void tu1t_entry(int32_t m, const double *T, int64_t ldt, const double *S,
+                                           int64_t lds, double *Mq, int p, int cidx) {
   double v = 0.0;
   for (int q = p; q <= cidx; ++q) v += T[p + (int64_t)q * ldt] * S[cidx + (int64_t)q * lds];
   Mq[p + (int64_t)cidx * m] = v;
 }
 
+__global__ void k_tu1t(int32_t m, const double *T, int64_t ldt, const double *S, int64_t lds,
+                       double *Mq) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < m) tu1t_entry(m, T, ldt, S, lds, Mq, p, blockIdx.y);
+}
+
 // Q head: I - U_1 Mq (float64 U_1 from S)
+template <typename ST>
+__device__ __forceinline__ void qhead_entry(int32_t m, const double *S, int64_t lds,
+                                            const double *Mq, ST *Q, int64_t ldq, int k,
+                                            int cidx) {
+  double v = (k == cidx) ? 1.0 : 0.0;
+  for (int p = 0; p <= k; ++p) v -= S[k + (int64_t)p * lds] * Mq[p + (int64_t)cidx * m];
+  Q[k + (int64_t)cidx * ldq] = cvt_out<ST>(v);
+}
+
 template <typename ST>
 __global__ void k_qhead(int32_t m, const double *S, int64_t lds, const double *Mq, ST *Q,
                         int64_t ldq) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int cidx = blockIdx.y;
-  if (k >= m) return;
-  double v = (k == cidx) ? 1.0 : 0.0;
-  for (int p = 0; p <= k; ++p) v -= S[k + (int64_t)p * lds] * Mq[p + (int64_t)cidx * m];
-  Q[k + (int64_t)cidx * ldq] = cvt_out<ST>(v);
+  if (k < m) qhead_entry<ST>(m, S, lds, Mq, Q, ldq, k, blockIdx.y);
 }
 
 // ------------------------------------------------------- thin Q, float64
@@ -638,13 +646,12 @@ constexpr int QH_NC = 128;
 
 // B operand order for a column tile of QH_NC: row group g (rows 8g..8g+7 of
 // Mq), tile column jt: B[((tile * Kg + g) * QH_NC + jt) * 8 + t], Kg = Kp / 8.
+// column j of Mq (columns j >= m of the last tile are zero); 256 threads
 template <typename ST>
-__global__ void __launch_bounds__(256) k_qconv(int32_t m, int32_t Kp,
-                                              const double *__restrict__ Mq,
-                                              unsigned short *__restrict__ Bh,
-                                              unsigned short *__restrict__ Bl,
-                                              float *__restrict__ scale) {
-  const int j = blockIdx.x;  // column of Mq (columns j >= m of the last tile are zero)
+__device__ __forceinline__ void qconv_col(int32_t m, int32_t Kp, const double *__restrict__ Mq,
+                                          unsigned short *__restrict__ Bh,
+                                          unsigned short *__restrict__ Bl,
+                                          float *__restrict__ scale, int j) {
   const bool col = j < m;
   __shared__ float sc;
   double mx = 0.0;
@@ -671,6 +678,15 @@ __global__ void __launch_bounds__(256) k_qconv(int32_t m, int32_t Kp,
     Bh[o] = h;
     Bl[o] = lo;
   }
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(256) k_qconv(int32_t m, int32_t Kp,
+                                              const double *__restrict__ Mq,
+                                              unsigned short *__restrict__ Bh,
+                                              unsigned short *__restrict__ Bl,
+                                              float *__restrict__ scale) {
+  qconv_col<ST>(m, Kp, Mq, Bh, Bl, scale, blockIdx.x);
 }
 
 constexpr int QS_WAVES = 8;  // waves per workgroup of the 2-byte thin Q (64 rows each)
@@ -732,22 +748,22 @@ __device__ __forceinline__ void qtail16_loop(const ST *__restrict__ U, int64_t l
   }
 }
 
+// workgroup `wg` of the 2-byte tail product (one launch: wg = blockIdx.x)
 template <typename ST>
-__global__ void __launch_bounds__(QS_WAVES * 64) k_qtail16(const ST *__restrict__ U, int64_t ldu,
-                                                           int64_t rows, int32_t m, int32_t Kp,
-                                                           const unsigned short *__restrict__ Bh,
-                                                           const unsigned short *__restrict__ Bl,
-                                                           const float *__restrict__ scale,
-                                                           ST *__restrict__ Q, int64_t ldq,
-                                                           int aligned, int tiles) {
+__device__ __forceinline__ void qtail16_wg(const ST *__restrict__ U, int64_t ldu, int64_t rows,
+                                           int32_t m, int32_t Kp,
+                                           const unsigned short *__restrict__ Bh,
+                                           const unsigned short *__restrict__ Bl,
+                                           const float *__restrict__ scale, ST *__restrict__ Q,
+                                           int64_t ldq, int aligned, int tiles, int64_t wg) {
   __shared__ unsigned short lds[QS_WAVES][PM_KC * PM_RS];
   __shared__ u32x4 cb[2 * 2 * (PM_KP / 8) * QH_NC];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   // workgroup b runs on XCD b % 8: the tiles of one row block go to the same
   // XCD one after another, so U is read from HBM about once
-  const int64_t slot = blockIdx.x >> 3;
+  const int64_t slot = wg >> 3;
   const int tile = (int)(slot % tiles);
-  const int64_t blk = (slot / tiles) * 8 + (blockIdx.x & 7);
+  const int64_t blk = (slot / tiles) * 8 + (wg & 7);
   if (blk * QS_WAVES * PM_ROWS >= rows) return;  // the whole workgroup (uniform)
   const int64_t rb = (blk * QS_WAVES + w) * PM_ROWS;
   const bool active = rb < rows;
@@ -784,6 +800,17 @@ __global__ void __launch_bounds__(QS_WAVES * 64) k_qtail16(const ST *__restrict_
       }
     }
   }
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(QS_WAVES * 64) k_qtail16(const ST *__restrict__ U, int64_t ldu,
+                                                           int64_t rows, int32_t m, int32_t Kp,
+                                                           const unsigned short *__restrict__ Bh,
+                                                           const unsigned short *__restrict__ Bl,
+                                                           const float *__restrict__ scale,
+                                                           ST *__restrict__ Q, int64_t ldq,
+                                                           int aligned, int tiles) {
+  qtail16_wg<ST>(U, ldu, rows, m, Kp, Bh, Bl, scale, Q, ldq, aligned, tiles, blockIdx.x);
 }
 
 inline int panel_width(int nb) { return nb <= 8 ? 8 : nb <= 16 ? 16 : 32; }
@@ -1104,13 +1131,34 @@ int run_alg5_typed(const rhqr_sketch_s *h, LoopArgs a, const LoopWs &w, int b, d
 // holds Mq[k][t QX_NC + c] at Ct[(t m + k) QX_NC + c], zero beyond column m.
 constexpr int QX_NC = 64;
 
-__global__ void k_mqt(int32_t m, const double *__restrict__ Mq, double *__restrict__ Ct) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int tile = blockIdx.y;
-  if (e >= m * QX_NC) return;
+__device__ __forceinline__ void mqt_entry(int32_t m, const double *__restrict__ Mq,
+                                          double *__restrict__ Ct, int e, int tile) {
   const int k = e / QX_NC, c = e % QX_NC;
   const int col = tile * QX_NC + c;
   Ct[((int64_t)tile * m + k) * QX_NC + c] = col < m ? Mq[k + (int64_t)col * m] : 0.0;
+}
+
+__global__ void k_mqt(int32_t m, const double *__restrict__ Mq, double *__restrict__ Ct) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m * QX_NC) mqt_entry(m, Mq, Ct, e, blockIdx.y);
+}
+
+// workgroup `wg` of the tail product (one launch: wg = blockIdx.x)
+template <typename ST>
+__device__ __forceinline__ void qtail_mx_wg(int64_t n, int32_t m, const ST *__restrict__ U,
+                                            int64_t ldu, const double *__restrict__ Ct,
+                                            ST *__restrict__ Q, int64_t ldq, int64_t groups,
+                                            int tiles, int64_t wg) {
+  // workgroup b runs on XCD b % 8: the tiles of one row group go to the same
+  // XCD one after another, so U is read from HBM about once
+  const int64_t slot = wg >> 3;
+  const int tile = (int)(slot % tiles);
+  const int64_t g = (slot / tiles) * 8 + (wg & 7);
+  if (g >= groups) return;
+  const int c0 = tile * QX_NC;
+  const int nb = m - c0 < QX_NC ? m - c0 : QX_NC;
+  panel_mx_block<ST, QX_NC>(U, ldu, Q + (int64_t)c0 * ldq, ldq, true, n, m, 0, m, nb, QX_NC,
+                            Ct + (int64_t)tile * m * QX_NC, g);
 }
 
 template <typename ST>
@@ -1119,16 +1167,7 @@ __global__ void __launch_bounds__(PX_WAVES * 64) k_qtail_mx(int64_t n, int32_t m
                                                             const double *__restrict__ Ct,
                                                             ST *__restrict__ Q, int64_t ldq,
                                                             int64_t groups, int tiles) {
-  // workgroup b runs on XCD b % 8: the tiles of one row group go to the same
-  // XCD one after another, so U is read from HBM about once
-  const int64_t slot = blockIdx.x >> 3;
-  const int tile = (int)(slot % tiles);
-  const int64_t g = (slot / tiles) * 8 + (blockIdx.x & 7);
-  if (g >= groups) return;
-  const int c0 = tile * QX_NC;
-  const int nb = m - c0 < QX_NC ? m - c0 : QX_NC;
-  panel_mx_block<ST, QX_NC>(U, ldu, Q + (int64_t)c0 * ldq, ldq, true, n, m, 0, m, nb, QX_NC,
-                            Ct + (int64_t)tile * m * QX_NC, g);
+  qtail_mx_wg<ST>(n, m, U, ldu, Ct, Q, ldq, groups, tiles, blockIdx.x);
 }
 
 template <typename ST>
@@ -1190,6 +1229,100 @@ int thin_q_typed(int64_t n, int32_t m, const ST *U, int64_t ldu, const double *S
                   n, m, (const double *)Mq, (int64_t)m, m, Q, ldq, -1.0);
     }
     RHQR_HIP(hipGetLastError());
+  }
+  return RHQR_OK;
+}
+
+// ------------------------------------------------- thin Q over a batch
+// The thin-Q stages of many problems, one launch per stage: the same device
+// code per entry and per tail workgroup as thin_q_typed (so every Q equals
+// the single-problem one bitwise), each workgroup reading its problem from a
+// job table (a skipped problem has m = 0 and tiles = 0).
+__global__ void __launch_bounds__(256) kq_tu1t(const ThinQJob *__restrict__ J) {
+  const ThinQJob &q = J[blockIdx.x];
+  const int cidx = blockIdx.y;
+  if (cidx >= q.m) return;
+  for (int p = threadIdx.x; p < q.m; p += blockDim.x)
+    tu1t_entry(q.m, q.T, q.ldt, q.S, q.lds, q.Mq, p, cidx);
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(256) kq_qhead(const ThinQJob *__restrict__ J) {
+  const ThinQJob &q = J[blockIdx.x];
+  const int cidx = blockIdx.y;
+  if (cidx >= q.m) return;
+  for (int k = threadIdx.x; k < q.m; k += blockDim.x)
+    qhead_entry<ST>(q.m, q.S, q.lds, q.Mq, (ST *)q.Q, q.ldq, k, cidx);
+}
+
+__global__ void __launch_bounds__(256) kq_mqt(const ThinQJob *__restrict__ J) {
+  const ThinQJob &q = J[blockIdx.x];
+  const int tile = blockIdx.y;
+  if (tile >= q.tiles) return;
+  for (int e = blockIdx.z * blockDim.x + threadIdx.x; e < q.m * QX_NC; e += gridDim.z * blockDim.x)
+    mqt_entry(q.m, q.Mq, (double *)q.qmf, e, tile);
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(PX_WAVES * 64) kq_qtail_mx(const ThinQJob *__restrict__ J,
+                                                             const ThinQBlock *__restrict__ map) {
+  const ThinQBlock b = map[blockIdx.x];
+  const ThinQJob &q = J[b.p];
+  if (q.m == 0) return;
+  qtail_mx_wg<ST>(q.n, q.m, (const ST *)q.U, q.ldu, (const double *)q.qmf, (ST *)q.Q, q.ldq,
+                  q.groups, q.tiles, b.local);
+}
+
+// split coefficients of a problem's qmf scratch, as thin_q_typed lays them out
+struct SplitCoef {
+  unsigned short *Bh, *Bl;
+  float *sc;
+};
+__device__ __forceinline__ SplitCoef split_coef(const ThinQJob &q) {
+  unsigned short *Bh = (unsigned short *)q.qmf;
+  unsigned short *Bl = Bh + (size_t)q.tiles * q.Kp * QH_NC;
+  return SplitCoef{Bh, Bl, (float *)(Bl + (size_t)q.tiles * q.Kp * QH_NC)};
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(256) kq_qconv(const ThinQJob *__restrict__ J) {
+  const ThinQJob &q = J[blockIdx.x];
+  const int j = blockIdx.y;
+  if (q.m == 0 || j >= q.tiles * QH_NC) return;  // the whole workgroup
+  const SplitCoef c = split_coef(q);
+  qconv_col<ST>(q.m, q.Kp, q.Mq, c.Bh, c.Bl, c.sc, j);
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(QS_WAVES * 64) kq_qtail16(const ThinQJob *__restrict__ J,
+                                                            const ThinQBlock *__restrict__ map) {
+  const ThinQBlock b = map[blockIdx.x];
+  const ThinQJob &q = J[b.p];
+  if (q.m == 0) return;  // the whole workgroup
+  const SplitCoef c = split_coef(q);
+  qtail16_wg<ST>((const ST *)q.U + q.m, q.ldu, q.n - q.m, q.m, q.Kp, c.Bh, c.Bl, c.sc,
+                 (ST *)q.Q + q.m, q.ldq, q.aligned, q.tiles, b.local);
+}
+
+template <typename ST>
+int thin_q_batched_typed(int32_t count, int32_t maxm, int32_t maxtiles, const ThinQJob *d_jobs,
+                         const ThinQBlock *d_map, int64_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(kq_tu1t, dim3(count, maxm), dim3(256), 0, st, d_jobs);
+  RHQR_HIP(hipGetLastError());
+  hipLaunchKernelGGL((kq_qhead<ST>), dim3(count, maxm), dim3(256), 0, st, d_jobs);
+  RHQR_HIP(hipGetLastError());
+  if (nblocks == 0) return RHQR_OK;
+  if constexpr (sizeof(ST) >= 4) {
+    const unsigned zb = (unsigned)((maxm * QX_NC + 255) / 256);
+    hipLaunchKernelGGL(kq_mqt, dim3(count, maxtiles, zb), dim3(256), 0, st, d_jobs);
+    RHQR_HIP(hipGetLastError());
+    RHQR_LAUNCH(RHQR_PROF_QTAIL, (kq_qtail_mx<ST>), dim3((unsigned)nblocks), dim3(PX_WAVES * 64), 0,
+                st, d_jobs, d_map);
+  } else {
+    hipLaunchKernelGGL((kq_qconv<ST>), dim3(count, maxtiles * QH_NC), dim3(256), 0, st, d_jobs);
+    RHQR_HIP(hipGetLastError());
+    RHQR_LAUNCH(RHQR_PROF_QTAIL, (kq_qtail16<ST>), dim3((unsigned)nblocks), dim3(QS_WAVES * 64), 0,
+                st, d_jobs, d_map);
   }
   return RHQR_OK;
 }
@@ -1602,6 +1735,41 @@ int run_column_loop(const LoopArgs &a, const LoopWs &w, hipStream_t st) {
     case RHQR_F32: return run_typed<float>(a, w, st);
     case RHQR_F16: return run_typed<__half>(a, w, st);
     case RHQR_BF16: return run_typed<__hip_bfloat16>(a, w, st);
+  }
+  return RHQR_ERR_UNSUPPORTED;
+}
+
+int64_t thin_q_tail_blocks(int dtype, int64_t n, int32_t m, int32_t *tiles, int64_t *groups,
+                           int32_t *Kp) {
+  const int es = (int)dtype_size(dtype);
+  const int64_t rows = n - m;
+  *Kp = (m + PM_KP - 1) / PM_KP * PM_KP;
+  if (es >= 4) {
+    *tiles = (m + QX_NC - 1) / QX_NC;
+    *groups = panel_mx_groups(n, m, es);
+  } else {
+    *tiles = (m + QH_NC - 1) / QH_NC;
+    const int64_t waves = (rows + PM_ROWS - 1) / PM_ROWS;
+    *groups = (waves + QS_WAVES - 1) / QS_WAVES;
+  }
+  if (rows <= 0) return 0;
+  return (*groups + 7) / 8 * 8 * *tiles;
+}
+
+int launch_thin_q_batched(int dtype, int32_t count, int32_t maxm, int32_t maxtiles,
+                          const ThinQJob *d_jobs, const ThinQBlock *d_map, int64_t nblocks,
+                          hipStream_t st) {
+  if (count < 1 || maxm < 1) return RHQR_OK;
+  switch (dtype) {
+    case RHQR_F64:
+      return thin_q_batched_typed<double>(count, maxm, maxtiles, d_jobs, d_map, nblocks, st);
+    case RHQR_F32:
+      return thin_q_batched_typed<float>(count, maxm, maxtiles, d_jobs, d_map, nblocks, st);
+    case RHQR_F16:
+      return thin_q_batched_typed<__half>(count, maxm, maxtiles, d_jobs, d_map, nblocks, st);
+    case RHQR_BF16:
+      return thin_q_batched_typed<__hip_bfloat16>(count, maxm, maxtiles, d_jobs, d_map, nblocks,
+                                                  st);
   }
   return RHQR_ERR_UNSUPPORTED;
 }
