@@ -145,10 +145,11 @@ def test_c2_f64_recrhqr_fullsize(mode):
             assert np.max(np.abs(res) / np.maximum(scale, 1e-300)) <= 64 * (j + 1) * 2.0 ** -53, j
 
 
-@pytest.mark.parametrize("panel,outer", [(8, 32), (16, 0)])
+@pytest.mark.parametrize("panel,outer", [(8, 32), (16, 0), ("alg3", 0)])
 def test_c3_f64_blocked_fullsize(panel, outer):
     """2^22 x 256, cond 1e14, SRHT l = 1024; panels of 8 in outer panels of 32
-    (the benchmark's float64 configuration) and one level of 16."""
+    (the benchmark's float64 configuration), one level of 16, and
+    right-looking RHQR (Alg. 3) as the benchmark times it beside them."""
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
     n, m, l = 1 << 22, 256, 1024
@@ -157,7 +158,10 @@ def test_c3_f64_blocked_fullsize(panel, outer):
     sk = rhqr.Sketch(rhqr.SRHT, n, m, l, seed=0)
     osketch = osk.Sketch(osk.SRHT, n, m, l, seed=0)
     Wd = W0.clone()
-    out = rhqr.factor(sk, Wd, panel=panel, outer=outer)
+    if panel == "alg3":
+        out = rhqr.factor(sk, Wd, right=True)
+    else:
+        out = rhqr.factor(sk, Wd, panel=panel, outer=outer)
     torch.cuda.synchronize()
     assert rhqr.status(out["ws"]) == 0
     _checks(torch, W0, out["U"], out["S"], out["T"], out["R"], osketch, m, (0, 1, 128, 255),
