@@ -46,7 +46,7 @@ TILE = 4096
 # WRITE_SIZE runs, scaled by a plain copy of known size), committed as text;
 # used only while the kernel sources still hash to the recorded digest.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3.md")
-KERNEL_SOURCES = ["common.h", "engine.h", "colstep.h", "engine.hip"]
+KERNEL_SOURCES = ["common.h", "engine.h", "colstep.h", "engine.hip", "sketch_dev.h", "sketch.hip"]
 
 
 def source_digest():
