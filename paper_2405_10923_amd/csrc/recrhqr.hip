@@ -379,12 +379,13 @@ __global__ void __launch_bounds__(HQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
 //    per earlier column q (rows >= J; the panel's vectors are zero above J).
 //  the rest: rows p0 .. p0 + TF_ROWS - 1 of the off-diagonal block of T of
 //    panel Jt (columns Jt..Jt+nbt-1): T_{<Jt, p} = -(T_{<Jt,<Jt} X) T_pp with
-//    X = Xt from that panel's trail launch, one thread per (row, column) of
-//    Y = T_{<Jt,<Jt} X.
+//    X = Xt from that panel's trail launch; each row of Y = T_{<Jt,<Jt} X by
+//    one wave (lanes over the inner index, eight columns per butterfly).
+// RC: rows of the trailing columns per thread (the launch's L - J rows).
 constexpr int TR_TPB = 256;
-constexpr int TR_RC = SQ_MAXL / TR_TPB;  // rows per thread
-constexpr int TF_ROWS = 16;              // rows of T per workgroup
-template <int NB>
+constexpr int TR_MAXRC = SQ_MAXL / TR_TPB;  // rows per thread at most
+constexpr int TF_ROWS = 16;                 // rows of T per workgroup
+template <int NB, int RC>
 __global__ void __launch_bounds__(TR_TPB) k_hqr_trail(int32_t L, int32_t m, int32_t J, double *Z,
                                                       int64_t ldz, const double *S, int64_t lds,
                                                       double *T, int64_t ldt, int ntrail, int nx,
@@ -403,27 +404,31 @@ __global__ void __launch_bounds__(TR_TPB) k_hqr_trail(int32_t L, int32_t m, int3
       const int q = tid % NB, c = tid / NB;
       tpp[q][c] = (q < nbt && c < nbt && q <= c) ? T[(Jt + q) + (int64_t)(Jt + c) * ldt] : 0.0;
     }
-    static_assert(TF_ROWS * NB <= TR_TPB, "one thread per entry");
+    static_assert(TF_ROWS * NB <= TR_TPB, "one thread per entry of the block");
+    static_assert(NB % 8 == 0, "eight columns per butterfly");
+    for (int pr = w; pr < TF_ROWS; pr += TR_TPB / 64) {
+      const int p = p0 + pr;
+      double yc[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) yc[c] = 0.0;
+      for (int q = p + lane; q < Jt; q += 64) {  // p >= Jt: no term (uniform per wave)
+        const double t = T[p + (int64_t)q * ldt];
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (c < nbt) yc[c] += t * Xt[q + (int64_t)c * m];
+      }
+#pragma unroll
+      for (int h = 0; h < NB / 8; ++h) {
+        double v8[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v8[k] = yc[8 * h + k];
+        const double tot = wave_sum8(v8);
+        if ((lane & 7) == 0) yv[pr][8 * h + (lane >> 3)] = tot;
+      }
+    }
+    __syncthreads();
     const int pr = tid % TF_ROWS, c = tid / TF_ROWS;  // c < NB for tid < TF_ROWS NB
     const int p = p0 + pr;
-    double y = 0.0;
-    if (p < Jt && c < nbt) {
-      const double *xc = Xt + (int64_t)c * m;
-      int q = p;
-      for (; q + 8 <= Jt; q += 8) {  // eight terms' loads together, added in order
-        double tv[8], xv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          tv[u] = T[p + (int64_t)(q + u) * ldt];
-          xv[u] = xc[q + u];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) y += tv[u] * xv[u];
-      }
-      for (; q < Jt; ++q) y += T[p + (int64_t)q * ldt] * xc[q];
-    }
-    if (c < NB) yv[pr][c] = y;
-    __syncthreads();
     if (p < Jt && c < nbt) {
       double t = 0.0;
       for (int q = 0; q <= c; ++q) t += yv[pr][q] * tpp[q][c];
@@ -474,19 +479,19 @@ __global__ void __launch_bounds__(TR_TPB) k_hqr_trail(int32_t L, int32_t m, int3
     const int q = tid % NB, c = tid / NB;
     tpp[q][c] = (q < nb && c < nb && q <= c) ? T[(J + q) + (int64_t)(J + c) * ldt] : 0.0;
   }
-  double zr[TR_RC], d[NB];
+  double zr[RC], d[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) d[q] = 0.0;
   // clamped row and column indices (every load in bounds, no branches, so
   // the loads issue together); rows beyond the sketch carry z = 0 and
   // columns beyond nb are not used
 #pragma unroll
-  for (int i = 0; i < TR_RC; ++i) {
+  for (int i = 0; i < RC; ++i) {
     const int r = tid + TR_TPB * i;
     zr[i] = r < rows ? zk[r < rows ? r : rows - 1] : 0.0;
   }
 #pragma unroll
-  for (int i = 0; i < TR_RC; ++i) {
+  for (int i = 0; i < RC; ++i) {
     const int r = tid + TR_TPB * i, rc = r < rows ? r : rows - 1;
 #pragma unroll
     for (int q = 0; q < NB; ++q) d[q] += Sp[rc + (int64_t)(q < nb ? q : nb - 1) * lds] * zr[i];
@@ -512,7 +517,7 @@ __global__ void __launch_bounds__(TR_TPB) k_hqr_trail(int32_t L, int32_t m, int3
     u[c] = c < nb ? t : 0.0;
   }
 #pragma unroll
-  for (int i = 0; i < TR_RC; ++i) {
+  for (int i = 0; i < RC; ++i) {
     const int r = tid + TR_TPB * i, rc = r < rows ? r : rows - 1;
     double zv = zr[i];
 #pragma unroll
@@ -546,6 +551,32 @@ int hqr_panel_launch(int rpt, int32_t L, int32_t m, int32_t J, double *Zc, doubl
 #undef RHQR_HQR_PANEL
 }
 
+// the trail launch with rc rows per thread of the trailing columns (1 .. 8)
+template <int NB>
+int hqr_trail_launch(int rc, int grid, int32_t L, int32_t m, int32_t J, double *Zc,
+                     const double *S, int64_t lds, double *T, int64_t ldt, int ntrail, int nx,
+                     double *Xc, int32_t Jt, const double *Xt, hipStream_t st) {
+#define RHQR_HQR_TRAIL(RCV)                                                                     \
+  case RCV:                                                                                     \
+    RHQR_LAUNCH(RHQR_PROF_HQR, (k_hqr_trail<NB, RCV>), dim3((unsigned)grid), dim3(TR_TPB), 0, st, \
+                L, m, J, Zc, (int64_t)L, S, lds, T, ldt, ntrail, nx, Xc, Jt, Xt);               \
+    return RHQR_OK
+  static_assert(TR_MAXRC == 8, "one case per row count");
+  switch (rc) {
+    RHQR_HQR_TRAIL(1);
+    RHQR_HQR_TRAIL(2);
+    RHQR_HQR_TRAIL(3);
+    RHQR_HQR_TRAIL(4);
+    RHQR_HQR_TRAIL(5);
+    RHQR_HQR_TRAIL(6);
+    RHQR_HQR_TRAIL(7);
+    RHQR_HQR_TRAIL(8);
+    default:
+      return RHQR_ERR_UNSUPPORTED;
+  }
+#undef RHQR_HQR_TRAIL
+}
+
 template <int NB>
 int hqr_run(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, double *T, int64_t ldt,
             double *R, int64_t ldr, double *X0, double *X1, int32_t *status, hipStream_t st) {
@@ -564,18 +595,19 @@ int hqr_run(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, double *T,
     if (grid > 0) {
       double *Xc = Xb[(J / NB) & 1];
       const double *Xt = Jprev >= 0 ? Xb[(Jprev / NB) & 1] : X0;
-      RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_trail<NB>, dim3((unsigned)grid), dim3(TR_TPB), 0, st, L, m,
-                  J, Zc, (int64_t)L, (const double *)S, lds, T, ldt, ntrail, nx, Xc,
-                  Jprev > 0 ? Jprev : 0, Xt);
+      rc = hqr_trail_launch<NB>((L - J + TR_TPB - 1) / TR_TPB, grid, L, m, J, Zc, S, lds, T, ldt,
+                                ntrail, nx, Xc, Jprev > 0 ? Jprev : 0, Xt, st);
+      if (rc) return rc;
     }
     Jprev = J;
   }
   // the last panel's block of T
   if (Jprev > 0) {
     const int ntf = (Jprev + TF_ROWS - 1) / TF_ROWS;
-    RHQR_LAUNCH(RHQR_PROF_HQR, k_hqr_trail<NB>, dim3((unsigned)ntf), dim3(TR_TPB), 0, st, L, m,
-                Jprev, Zc, (int64_t)L, (const double *)S, lds, T, ldt, 0, 0, Xb[(Jprev / NB) & 1],
-                Jprev, (const double *)Xb[(Jprev / NB) & 1]);
+    const int rc = hqr_trail_launch<NB>(1, ntf, L, m, Jprev, Zc, S, lds, T, ldt, 0, 0,
+                                        Xb[(Jprev / NB) & 1], Jprev,
+                                        (const double *)Xb[(Jprev / NB) & 1], st);
+    if (rc) return rc;
   }
   return RHQR_OK;
 }
