@@ -371,7 +371,7 @@ def batched_workload(count, seed=0):
     return out
 
 
-def run_batched(rhqr, torch, count, steps, warmup, dtype_name="float32", panel=16):
+def run_batched(rhqr, torch, count, steps, warmup, dtype_name="float32", panel=16, outer=0):
     """Factor the whole batch per step (one hipGraph launch); value = sum of the
     problems' B_alg over the step time."""
     import numpy as np
@@ -389,7 +389,7 @@ def run_batched(rhqr, torch, count, steps, warmup, dtype_name="float32", panel=1
         src.append(Ws)
         work.append(Ws.clone())
         sks.append(rhqr.Sketch(rhqr.SRHT, n, m, l, seed=sd))
-    b = rhqr.Batch(list(zip(sks, work)), panel=panel)
+    b = rhqr.Batch(list(zip(sks, work)), panel=panel, outer=outer)
     bytes_alg = sum(b_alg(n, m, es) for n, m, _, _, _ in shapes)
 
     def restore():
@@ -440,7 +440,7 @@ def run_batched(rhqr, torch, count, steps, warmup, dtype_name="float32", panel=1
     gbs = bytes_alg / (ms * 1e-3) / 1e9
     own = 0.0
     for n_, m_, l_, _, _ in shapes:
-        kb = kernel_bytes(n_, m_, l_, es, panel, 0)
+        kb = kernel_bytes(n_, m_, l_, es, panel, outer)
         own += kb["tall"] + kb["panel_mx"] + kb["panel_valu"] + kb["presketch"]
     gown = own / (ms * 1e-3) / 1e9
     return {"problems": count, "dtype": dtype_name, "ms_per_batch": round(ms, 3),
@@ -449,7 +449,7 @@ def run_batched(rhqr, torch, count, steps, warmup, dtype_name="float32", panel=1
             "hbm_frac_own": round(gown / HBM_PEAK_GBS, 4),
             "GBps_alg_effective": round(gbs, 1),
             "bytes_alg": bytes_alg, "launch": "one hipGraph replay per batch",
-            "schedule": f"blocked, panels of {panel}" if panel else "column by column",
+            "schedule": sched_name(panel, outer),
             "value_is": "sum of the problems' own kernel bytes (refresh + re-sketch passes, "
                         "panel updates, pre-sketch) / time",
             "breakdowns": int(sum(1 for v in info if v)),

@@ -361,9 +361,10 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
  *     dimensions, one sketch kind), lays the descriptors and per-problem scratch out in the
  *     caller's workspace d_ws (kept by the batch until rhqr_batch_destroy: the
  *     caller must keep it alive), uploads them on `stream` and synchronises.
- *     opts: bits 0-7 rhqr_scaling; bits 8-15 panel width: 0 (column
- *     schedule) or 16 (blocked schedule as in rhqr_factor with one level of
- *     panels of 16); other bits 0.
+ *     opts: bits 0-7 rhqr_scaling; bits 8-15 panel width b and bits 16-23
+ *     outer panel width B with rhqr_factor's meaning and rules (b = 0: column
+ *     schedule; 2 <= b <= 32: blocked, one level when B = 0, else outer
+ *     panels of B, a multiple of b, b < B <= 32); other bits 0.
  *     Returns -1 for an invalid problem array, -3 bad dtype, -4 bad opts,
  *     -5 null workspace, RHQR_ERR_WORKSPACE if ws_bytes is too small.
  *   rhqr_batch_factor: factors every problem of the batch.  The work is a

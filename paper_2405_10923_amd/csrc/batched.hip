@@ -101,10 +101,14 @@ __global__ void __launch_bounds__(1024) kb_fin(const ColProblem *__restrict__ P,
   fin_block(Q, j, j + 1 < Q.m, local, fg);
 }
 
-// ---- blocked schedule (panels of BATCH_PB columns), per problem as in the
-// single-problem path: store u_{J-1}, G = S_{<J}^t Z_panel, C = T^t G, then
-// W_panel -= U_{<J} C.
-constexpr int BATCH_PB = 16;
+// ---- blocked schedule, per problem as in the single-problem path
+// (run_blocked_typed): panels of `panel` columns, optionally grouped in outer
+// panels of `outer`; before a panel at J, with the reflectors K0..J-1: store
+// u_{J-1}, G = S_{<J}^t Z_panel, C = rows K0..J-1 of T^t G, then
+// W_panel -= U_{K0:J} C.  A problem's panel has nb = min(width, m - J)
+// columns; C has row pitch panel_width(nb) (8, 16 or 32), as in the single
+// path, and is m x 32 per problem.
+constexpr int BATCH_MAXPB = 32;
 constexpr int SCALE_CH = 64;  // workgroups per problem in kb_scale_col
 
 template <typename ST>
@@ -119,37 +123,48 @@ __global__ void kb_scale_col(const ColProblem *__restrict__ P, int32_t cidx) {
 }
 
 __global__ void __launch_bounds__(1024) kb_pgram(const ColProblem *__restrict__ P, int32_t J,
-                                                 int per) {
+                                                 int32_t width, int per) {
   const int p = blockIdx.x / per, local = blockIdx.x % per;
   const ColProblem &Q = P[p];
-  const int32_t nb = Q.m - J < BATCH_PB ? Q.m - J : BATCH_PB;
+  const int32_t nb = Q.m - J < width ? Q.m - J : width;
   pgram_block(Q.l + Q.m, J, nb, Q.S, Q.lds, Q.Z, Q.ldz, Q.G, local);
 }
 
 __global__ void __launch_bounds__(PTRI_WAVES * 64) kb_ptri(const ColProblem *__restrict__ P,
-                                                          int32_t J, int per) {
+                                                          int32_t K0, int32_t J, int32_t width,
+                                                          int per) {
   const int p = blockIdx.x / per, local = blockIdx.x % per;
   const ColProblem &Q = P[p];
-  const int32_t nb = Q.m - J < BATCH_PB ? Q.m - J : BATCH_PB;
-  ptri_wave(0, J, nb, BATCH_PB, Q.T, Q.ldt, Q.G, Q.C, local * PTRI_WAVES + (threadIdx.x >> 6),
-            blockIdx.y);
+  const int32_t nb = Q.m - J < width ? Q.m - J : width;
+  ptri_wave(K0, J, nb, panel_width(nb), Q.T, Q.ldt, Q.G, Q.C,
+            local * PTRI_WAVES + (threadIdx.x >> 6), blockIdx.y);
 }
 
 template <typename ST>
 __global__ void __launch_bounds__(PANEL_TPB) kb_panel(const ColProblem *__restrict__ P,
-                                                      const BlockMap *__restrict__ map, int32_t J) {
+                                                      const BlockMap *__restrict__ map, int32_t K0,
+                                                      int32_t J, int32_t width) {
   const BlockMap b = map[blockIdx.x];
   const ColProblem &Q = P[b.p];
-  const int32_t nb = Q.m - J < BATCH_PB ? Q.m - J : BATCH_PB;
+  const int32_t nb = Q.m - J < width ? Q.m - J : width;
+  if (nb <= 0) return;  // the problem ended before this panel (whole workgroup)
   // the same choice of units and arithmetic as the single-problem update
   static_assert(PANEL_TPB == PX_WAVES * 64, "one panel workgroup layout for both units");
-  if (Q.aligned && nb > PX_MIN_NB) {
-    ST *W = (ST *)Q.W;
-    panel_mx_block<ST, BATCH_PB>(W, Q.ldw, W + (int64_t)J * Q.ldw, Q.ldw, false, Q.n, Q.m, 0, J, nb,
-                                 BATCH_PB, Q.C, b.local);
-    return;
+  ST *W = (ST *)Q.W;
+  const int pw = panel_width(nb);
+  if (Q.aligned && nb > PX_MIN_NB && nb <= 16) {
+    panel_mx_block<ST, 16>(W, Q.ldw, W + (int64_t)J * Q.ldw, Q.ldw, false, Q.n, Q.m, K0, J, nb, pw,
+                           Q.C, b.local);
+  } else if (Q.aligned && nb > PX_MIN_NB) {
+    panel_mx_block<ST, 32>(W, Q.ldw, W + (int64_t)J * Q.ldw, Q.ldw, false, Q.n, Q.m, K0, J, nb, pw,
+                           Q.C, b.local);
+  } else if (pw == 8) {
+    panel_block<ST, 8>(W, Q.ldw, Q.n, Q.m, K0, J, nb, Q.C, Q.aligned, b.local, J);
+  } else if (pw == 16) {
+    panel_block<ST, 16>(W, Q.ldw, Q.n, Q.m, K0, J, nb, Q.C, Q.aligned, b.local, J);
+  } else {
+    panel_block<ST, 32>(W, Q.ldw, Q.n, Q.m, K0, J, nb, Q.C, Q.aligned, b.local, J);
   }
-  panel_block<ST, BATCH_PB>((ST *)Q.W, Q.ldw, Q.n, Q.m, 0, J, nb, Q.C, Q.aligned, b.local, J);
 }
 
 // last column stored as u = raw / alpha, head block of U written from S
@@ -198,19 +213,32 @@ size_t problem_bytes(const rhqr_sketch_s *h, int dtype) {
   sketch_tail_partials_size(h, m, &gt, &skb);
   return align_up(loop_ws_bytes(h->kind, dtype, h->n, m, h->l)) +
          align_up(sizeof(double) * (size_t)L * m) + align_up(skb) +
-         2 * align_up(sizeof(double) * (size_t)m * BATCH_PB) +
+         2 * align_up(sizeof(double) * (size_t)m * BATCH_MAXPB) +
          align_up(sizeof(double) * (size_t)m * m) + thin_q_bytes(m);  // thin Q: Mq, split coefficients
 }
 
-// panel-update workgroups of one problem (rows from m rounded down to VEC):
-// enough for both the vector-unit and the matrix-core layout (each workgroup
-// returns beyond its own last row)
+// panel-update workgroups of one problem (rows from m rounded down to the
+// vector width): enough for every layout kb_panel may take (matrix cores,
+// vector units with 8-, 16- or 32-column panels; each workgroup returns
+// beyond its own last row)
+template <typename ST> int64_t panel_groups_typed(int64_t n, int32_t m) {
+  auto g = [&](int vec) {
+    const int64_t mb0 = m - (m % vec);
+    return (n - mb0 + (int64_t)PANEL_TPB * vec - 1) / ((int64_t)PANEL_TPB * vec);
+  };
+  int64_t r = panel_mx_groups(n, m, (int)sizeof(ST));
+  r = std::max(r, g(panel_vec<ST, 8>()));
+  r = std::max(r, g(panel_vec<ST, 16>()));
+  return std::max(r, g(panel_vec<ST, 32>()));
+}
+
 int64_t panel_groups(int64_t n, int32_t m, int dtype) {
-  const int es = (int)dtype_size(dtype);
-  const int vec = es == 8 ? 2 : 4;
-  const int64_t mb0 = m - (m % vec);
-  const int64_t g = (n - mb0 + (int64_t)PANEL_TPB * vec - 1) / ((int64_t)PANEL_TPB * vec);
-  return std::max(g, panel_mx_groups(n, m, es));
+  switch (dtype) {
+    case RHQR_F64: return panel_groups_typed<double>(n, m);
+    case RHQR_F32: return panel_groups_typed<float>(n, m);
+    case RHQR_F16: return panel_groups_typed<__half>(n, m);
+    default: return panel_groups_typed<__hip_bfloat16>(n, m);
+  }
 }
 
 int plan(const rhqr_problem *probs, int32_t count, int dtype, Layout *o) {
@@ -306,7 +334,8 @@ struct rhqr_batch_s {
   std::vector<const rhqr_sketch_s *> hs;  // per problem (sorted): its sketch handle,
   std::vector<double *> skpart, zs;       //   pre-sketch partials and Z (Gaussian batches)
   std::vector<size_t> skbytes;
-  int panel = 0;                  // 0: column schedule, BATCH_PB: blocked
+  int panel = 0;                  // 0: column schedule; 2 .. 32: blocked
+  int outer = 0;                  // 0: one level; else outer panels (a multiple of panel)
   std::vector<int32_t> order;     // sorted position -> caller index
   std::vector<int32_t> ms;        // m of each sorted problem (decreasing)
   std::vector<int64_t> tall_start, red_start, pan_start;
@@ -374,43 +403,56 @@ int enqueue_typed(rhqr_batch_s *b, hipStream_t st) {
                      b->d_jobs, b->d_col);
   RHQR_HIP(hipGetLastError());
   }
-  const int pb = b->panel >= 2 ? b->panel : b->maxm;  // column schedule: one panel
-  for (int32_t J = 0; J < b->maxm; J += pb) {
-    if (J > 0) {
-      // store u_{J-1}, then apply the J earlier reflectors to every active panel
-      const int a = active(b, J);
-      hipLaunchKernelGGL((kb_scale_col<ST>), dim3(a, SCALE_CH), dim3(256), 0, st, b->d_probs, J - 1);
-      RHQR_HIP(hipGetLastError());
-      const int pg = (J * BATCH_PB + 15) / 16;
-      hipLaunchKernelGGL(kb_pgram, dim3(a * pg), dim3(1024), 0, st, b->d_probs, J, pg);
-      RHQR_HIP(hipGetLastError());
-      const int pt = (J + PTRI_WAVES - 1) / PTRI_WAVES;
-      hipLaunchKernelGGL(kb_ptri, dim3(a * pt, BATCH_PB), dim3(PTRI_WAVES * 64), 0, st, b->d_probs,
-                         J, pt);
-      RHQR_HIP(hipGetLastError());
-      hipLaunchKernelGGL((kb_panel<ST>), dim3(b->pan_start[a]), dim3(PANEL_TPB), 0, st, b->d_probs,
-                         b->d_pan, J);
-      RHQR_HIP(hipGetLastError());
+  // W_{:, J:J+width} -= U_{:, K0:J} C for every problem still active at J
+  auto apply = [&](int32_t K0, int32_t J, int32_t width) -> int {
+    const int a = active(b, J);
+    hipLaunchKernelGGL((kb_scale_col<ST>), dim3(a, SCALE_CH), dim3(256), 0, st, b->d_probs, J - 1);
+    RHQR_HIP(hipGetLastError());
+    const int pg = (J * width + 15) / 16;
+    hipLaunchKernelGGL(kb_pgram, dim3(a * pg), dim3(1024), 0, st, b->d_probs, J, width, pg);
+    RHQR_HIP(hipGetLastError());
+    const int pt = (J + PTRI_WAVES - 1) / PTRI_WAVES;
+    hipLaunchKernelGGL(kb_ptri, dim3(a * pt, panel_width(width)), dim3(PTRI_WAVES * 64), 0, st,
+                       b->d_probs, K0, J, width, pt);
+    RHQR_HIP(hipGetLastError());
+    hipLaunchKernelGGL((kb_panel<ST>), dim3(b->pan_start[a]), dim3(PANEL_TPB), 0, st, b->d_probs,
+                       b->d_pan, K0, J, width);
+    RHQR_HIP(hipGetLastError());
+    return RHQR_OK;
+  };
+  // the loop of run_blocked_typed over the largest m (column schedule: one panel)
+  const int pb = b->panel >= 2 ? b->panel : b->maxm;
+  const int ob = b->outer > pb ? b->outer : pb;
+  for (int32_t J0 = 0; J0 < b->maxm; J0 += ob) {
+    if (J0 > 0) {
+      const int rc = apply(0, J0, ob);
+      if (rc) return rc;
     }
-    const int32_t jend = J + pb < b->maxm ? J + pb : b->maxm;
-    for (int32_t j = J; j < jend; ++j) {
-      const int a = active(b, j);
-      if (j >= 1) {
-        constexpr int TPW = sizeof(ST) == 2 ? 2 : 1;  // = batch_tpw(dtype)
-        if (gauss)
-          hipLaunchKernelGGL((kb_tall_gauss<ST, TPW>), dim3(b->tall_start[a]), dim3(1024), 0, st,
-                             b->d_probs, b->d_tall, j, J);
-        else
-          hipLaunchKernelGGL((kb_tall<ST, TPW>), dim3(b->tall_start[a]), dim3(BATCH_TPB), 0, st,
-                             b->d_probs, b->d_tall, j, J);
+    for (int32_t J = J0; J < J0 + ob && J < b->maxm; J += pb) {
+      if (J > J0) {
+        const int rc = apply(J0, J, pb);
+        if (rc) return rc;
+      }
+      const int32_t jend = std::min(std::min(J + pb, J0 + ob), b->maxm);
+      for (int32_t j = J; j < jend; ++j) {
+        const int a = active(b, j);
+        if (j >= 1) {
+          constexpr int TPW = sizeof(ST) == 2 ? 2 : 1;  // = batch_tpw(dtype)
+          if (gauss)
+            hipLaunchKernelGGL((kb_tall_gauss<ST, TPW>), dim3(b->tall_start[a]), dim3(1024), 0, st,
+                               b->d_probs, b->d_tall, j, J);
+          else
+            hipLaunchKernelGGL((kb_tall<ST, TPW>), dim3(b->tall_start[a]), dim3(BATCH_TPB), 0, st,
+                               b->d_probs, b->d_tall, j, J);
+          RHQR_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL((kb_red<ST>), dim3(b->red_start[a]), dim3(256), 0, st, b->d_probs,
+                           b->d_red, j);
+        RHQR_HIP(hipGetLastError());
+        const int fg = fin_groups(j);
+        hipLaunchKernelGGL(kb_fin, dim3(a * fg), dim3(1024), 0, st, b->d_probs, j, fg);
         RHQR_HIP(hipGetLastError());
       }
-      hipLaunchKernelGGL((kb_red<ST>), dim3(b->red_start[a]), dim3(256), 0, st, b->d_probs,
-                         b->d_red, j);
-      RHQR_HIP(hipGetLastError());
-      const int fg = fin_groups(j);
-      hipLaunchKernelGGL(kb_fin, dim3(a * fg), dim3(1024), 0, st, b->d_probs, j, fg);
-      RHQR_HIP(hipGetLastError());
     }
   }
   hipLaunchKernelGGL((kb_finish<ST>), dim3(b->count, FINISH_CH), dim3(256), 0, st, b->d_probs);
@@ -443,8 +485,10 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
   if (rc) return rc;
   const int scaling = opts & 0xff;
   const int panel = (opts >> 8) & 0xff;
-  if ((scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) ||
-      (panel != 0 && panel != BATCH_PB) || (opts >> 16) != 0)
+  const int outer = (opts >> 16) & 0xff;
+  if ((scaling != RHQR_SCALE_UNIT_PIVOT && scaling != RHQR_SCALE_SQRT2) || panel == 1 ||
+      panel > BATCH_MAXPB || ((unsigned)opts >> 24) != 0 ||
+      (outer != 0 && (panel < 2 || outer <= panel || outer > BATCH_MAXPB || outer % panel != 0)))
     return -4;
   if (!d_ws) return -5;
   if (!out) return -8;
@@ -463,6 +507,7 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
   b->count = count;
   b->tpw = tpw;
   b->panel = panel;
+  b->outer = outer;
   b->pan_start = L.pan_start;
   b->order = L.order;
   b->tall_start = L.tall_start;
@@ -500,8 +545,8 @@ extern "C" int rhqr_batch_create(const rhqr_problem *probs, int32_t count, int d
     size_t skb0;
     sketch_tail_partials_size(h, m, &gt0, &skb0);
     double *Cc = (double *)((char *)skpart + align_up(skb0));
-    double *Gc = (double *)((char *)Cc + align_up(sizeof(double) * (size_t)m * BATCH_PB));
-    double *Mq = (double *)((char *)Gc + align_up(sizeof(double) * (size_t)m * BATCH_PB));
+    double *Gc = (double *)((char *)Cc + align_up(sizeof(double) * (size_t)m * BATCH_MAXPB));
+    double *Mq = (double *)((char *)Gc + align_up(sizeof(double) * (size_t)m * BATCH_MAXPB));
     b->mq.push_back(Mq);
     b->hs.push_back(h);
     b->skpart.push_back(skpart);

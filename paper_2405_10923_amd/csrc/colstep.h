@@ -1052,6 +1052,8 @@ __device__ __forceinline__ void ptri_wave(int32_t J0, int32_t J, int32_t nb, int
 // panel columns, whose coefficients are read with uniform (scalar) loads; U
 // is read exactly once.
 constexpr int PANEL_TPB = 256;
+// row pitch of a panel's coefficients (and the vector-unit kernel's width)
+__host__ __device__ inline int panel_width(int nb) { return nb <= 8 ? 8 : nb <= 16 ? 16 : 32; }
 constexpr int PANEL_KB = 8;  // columns of U whose loads are in flight together
 
 // rows per thread: 16-byte loads, except 8-byte ones for 32-column panels of

@@ -813,7 +813,6 @@ __global__ void __launch_bounds__(QS_WAVES * 64) k_qtail16(const ST *__restrict_
   qtail16_wg<ST>(U, ldu, rows, m, Kp, Bh, Bl, scale, Q, ldq, aligned, tiles, blockIdx.x);
 }
 
-inline int panel_width(int nb) { return nb <= 8 ? 8 : nb <= 16 ? 16 : 32; }
 
 template <typename ST, int NBC>
 void launch_panel_w(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t J, int32_t nb,

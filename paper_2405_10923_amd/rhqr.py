@@ -349,12 +349,13 @@ class Batch:
     """Batched left-looking RHQR (rhqr_batch_*): ``problems`` is a list of
     (Sketch, W) pairs, W (n x m, column-major, GPU, one dtype for the batch)
     overwritten by U.  Allocates S, T, R per problem and the batch workspace;
-    ``panel`` 16 selects the blocked schedule (0: column by column);
+    ``panel`` >= 2 selects the blocked schedule (0: column by column) and
+    ``outer`` > panel groups its panels in outer panels (as in ``factor``);
     ``factor(graph)`` runs the whole batch (as a replayed hipGraph when
     ``graph`` is true), ``thin_q()`` forms every problem's thin Q afterwards.
     ``outputs[i]`` = dict(U, S, T, R[, Q]) in caller order."""
 
-    def __init__(self, problems, scaling=SCALE_UNIT_PIVOT, panel=0):
+    def __init__(self, problems, scaling=SCALE_UNIT_PIVOT, panel=0, outer=0):
         torch = _torch()
         self._lib = lib()
         self.problems = list(problems)
@@ -380,7 +381,8 @@ class Batch:
             raise RHQRError("rhqr_batch_workspace_size rejected the problems")
         self.ws = workspace(nb, self.problems[0][1].device)
         h = C.c_void_p()
-        _check(self._lib.rhqr_batch_create(arr, len(arr), code, int(scaling) | (int(panel) << 8),
+        _check(self._lib.rhqr_batch_create(arr, len(arr), code,
+                                           int(scaling) | (int(panel) << 8) | (int(outer) << 16),
                                            _ptr(self.ws),
                                            self.ws.numel(), _stream(), C.byref(h)),
                "rhqr_batch_create")

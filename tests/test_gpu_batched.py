@@ -22,6 +22,11 @@ SHAPES = [(5000, 12, 48, 1), (4096, 32, 128, 2), (3 * 4096 + 777, 24, 96, 3), (3
           (2 * 8192 + 1, 40, 160, 5), (16384, 16, 64, 6), (2 * 4096 + 5, 70, 200, 7)]
 
 
+def _sched(panel):
+    """(panel, outer) of a schedule parameter: a panel width or a pair."""
+    return panel if isinstance(panel, tuple) else (panel, 0)
+
+
 def _inputs(torch, dt, kappa=3.0, shapes=SHAPES):
     from paper_2405_10923_amd import rhqr
     probs = []
@@ -31,7 +36,7 @@ def _inputs(torch, dt, kappa=3.0, shapes=SHAPES):
     return probs
 
 
-@pytest.mark.parametrize("panel", [0, 16])
+@pytest.mark.parametrize("panel", [0, 16, (8, 32), (5, 15)])
 @pytest.mark.parametrize("dt", ["float64", "float32", "float16", "bfloat16"])
 def test_batch_bitwise_equals_single(dt, panel):
     """Same schedule, same device code, same choice of units for every panel
@@ -43,14 +48,15 @@ def test_batch_bitwise_equals_single(dt, panel):
     probs = _inputs(torch, tdt)
     log(f"batch {dt} panel={panel}: {len(probs)} problems")
     batch_in = [(sk, to_gpu(W, tdt)) for W, sk, _ in probs]
-    b = rhqr.Batch(batch_in, panel=panel)
+    pn, outer = _sched(panel)
+    b = rhqr.Batch(batch_in, panel=pn, outer=outer)
     outs = b.factor()
     torch.cuda.synchronize()
     assert b.status() == [0] * len(probs)
     for (W, sk, shp), o in zip(probs, outs):
         log(f"  single {shp}")
         Wd = to_gpu(W, tdt)
-        ref = rhqr.factor(sk, Wd, panel=panel)
+        ref = rhqr.factor(sk, Wd, panel=pn, outer=outer)
         torch.cuda.synchronize()
         for k in ("U", "S", "T", "R"):
             assert torch.equal(o[k], ref[k]), (shp, k)
@@ -77,12 +83,13 @@ def test_batch_large_sketches_bitwise():
     b.close()
 
 
-@pytest.mark.parametrize("panel", [0, 16])
+@pytest.mark.parametrize("panel", [0, 16, (8, 32)])
 def test_batch_f64_matches_oracle(panel):
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
     probs = _inputs(torch, torch.float64, kappa=2.0)
-    b = rhqr.Batch([(sk, to_gpu(W)) for W, sk, _ in probs], panel=panel)
+    pn, outer = _sched(panel)
+    b = rhqr.Batch([(sk, to_gpu(W)) for W, sk, _ in probs], panel=pn, outer=outer)
     outs = b.factor()
     torch.cuda.synchronize()
     for (W, sk, (n, m, l, seed)), o in zip(probs, outs):
@@ -93,14 +100,15 @@ def test_batch_f64_matches_oracle(panel):
     b.close()
 
 
-@pytest.mark.parametrize("panel", [0, 16])
+@pytest.mark.parametrize("panel", [0, 16, (8, 32)])
 def test_batch_graph_replays_match_eager(panel):
     torch = cuda_or_skip()
     from paper_2405_10923_amd import rhqr
     probs = _inputs(torch, torch.float32)
     src = [to_gpu(W, torch.float32) for W, _, _ in probs]
     work = [s.clone() for s in src]
-    b = rhqr.Batch([(sk, w) for (_, sk, _), w in zip(probs, work)], panel=panel)
+    pn, outer = _sched(panel)
+    b = rhqr.Batch([(sk, w) for (_, sk, _), w in zip(probs, work)], panel=pn, outer=outer)
     eager = [{k: v.clone() for k, v in o.items()} for o in b.factor(graph=False)]
     torch.cuda.synchronize()
     for rep in range(3):
@@ -223,7 +231,7 @@ def _gauss_inputs(shapes=GSHAPES, kappa=3.0):
     return probs
 
 
-@pytest.mark.parametrize("panel", [0, 16])
+@pytest.mark.parametrize("panel", [0, 16, (8, 32)])
 @pytest.mark.parametrize("dt", ["float64", "float32", "bfloat16"])
 def test_batch_gauss_bitwise_equals_single(dt, panel):
     """A batch of Gaussian-sketch problems: per problem the single-problem
@@ -234,14 +242,15 @@ def test_batch_gauss_bitwise_equals_single(dt, panel):
     tdt = getattr(torch, dt)
     probs = _gauss_inputs()
     log(f"gaussian batch {dt} panel={panel}: {len(probs)} problems")
-    b = rhqr.Batch([(sk, to_gpu(W, tdt)) for W, sk, _, _ in probs], panel=panel)
+    pn, outer = _sched(panel)
+    b = rhqr.Batch([(sk, to_gpu(W, tdt)) for W, sk, _, _ in probs], panel=pn, outer=outer)
     outs = b.factor()
     torch.cuda.synchronize()
     assert b.status() == [0] * len(probs)
     eager = [{k: o[k].clone() for k in ("U", "S", "T", "R")} for o in outs]
     for (W, sk, _, shp), o in zip(probs, outs):
         log(f"  single {shp}")
-        ref = rhqr.factor(sk, to_gpu(W, tdt), panel=panel)
+        ref = rhqr.factor(sk, to_gpu(W, tdt), panel=pn, outer=outer)
         torch.cuda.synchronize()
         for k in ("U", "S", "T", "R"):
             assert torch.equal(o[k], ref[k]), (shp, k)
