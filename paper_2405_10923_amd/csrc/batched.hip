@@ -66,11 +66,13 @@ __global__ void kb_sketch_finish(const SketchJob *__restrict__ J, const BlockMap
 }
 
 // 256-thread tall workgroups: several per compute unit, so one workgroup's
-// transform overlaps the others' streaming (the problems are small)
+// transform overlaps the others' streaming (the problems are small); at least
+// three per compute unit (the 2-byte types' 16 values per thread sit at the
+// register budget of three)
 constexpr int BATCH_TPB = 256;
 
 template <typename ST, int TPW>
-__global__ void __launch_bounds__(BATCH_TPB) kb_tall(const ColProblem *__restrict__ P,
+__global__ void __launch_bounds__(BATCH_TPB, 3) kb_tall(const ColProblem *__restrict__ P,
                                                      const BlockMap *__restrict__ map, int32_t j,
                                                      int32_t p0) {
   const BlockMap b = map[blockIdx.x];

@@ -203,51 +203,70 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
 
 // A tall workgroup covers TPW consecutive transform tiles (TPW * TILE rows),
 // so the per-column partials shrink by TPW.
+//
+// The transform's order of butterflies depends only on the storage type and
+// TPW, never on TPB, so that every launch scheme gives bitwise the same
+// partials.  It is defined for the 1024-thread layout, li = VEC (t + 1024 v)
+// + e (t < 1024): the low VL bits (the elements of a 16-byte vector) and the
+// bits from VL + 10 up (a thread's vectors) are a thread's own, the 10 bits
+// between are the thread index.  Own values are transformed in registers:
+// within-tile bits and tile-index bits alike (the butterflies over the
+// tile-index bits form the +/- combination of the workgroup's tiles that every
+// sample takes, H_{n/TILE} restricted to them).  Two radix-16 LDS passes cover
+// the thread-index bits [VL, VL + 8); the two thread-index bits above those are
+// left to the sample reads: within-tile ones (the fold bits) as +/- sums of
+// entries, tile-index ones as +/- sums of tiles.  Butterflies over distinct
+// bits commute, so this is Alg. 1's transform up to rounding, with fewer LDS
+// passes than three radix-16 passes per tile and one entry per sample instead
+// of TPW where the tile bits are own.  With fewer threads (TPB = 256 or 512)
+// a thread holds the values of 1024 / TPB threads of that layout and leaves
+// the bits between them to the LDS passes and the sample reads as well.
+// HALVES: the two halves of the rows are transformed apart (their top bit is
+// then read at sample time too).
+template <int VEC, int TPW, bool HALVES> struct TallBits {
+  static constexpr int VL = VEC == 2 ? 1 : VEC == 4 ? 2 : 3;
+  static constexpr int TOP = VL + 10;  // lowest own bit above the vector
+  static constexpr int FLO = VL + 8;   // fold bits [FLO, FHI)
+  static constexpr int FHI = TOP < TILE_LOG ? TOP : TILE_LOG;
+  static constexpr int NF = FHI - FLO;
+  static constexpr int FMASK = ((1 << FHI) - 1) & ~((1 << FLO) - 1);
+  // tile-index bits held by the thread index, by the halves, in registers
+  static constexpr int MTID = TOP > TILE_LOG ? ((1 << (TOP - TILE_LOG)) - 1) & (TPW - 1) : 0;
+  static constexpr int MRAW = MTID | (HALVES ? (TPW >> 1) : 0);
+  static constexpr int MREG = (TPW - 1) & ~MRAW;
+  static constexpr int NRAW = (MRAW & 1) + ((MRAW >> 1) & 1);
+  static_assert(VEC == 2 || VEC == 4 || VEC == 8, "16-byte vectors of 8, 4 or 2 byte values");
+  static_assert(TPW <= 4, "at most two tile-index bits");
+};
 
-template <typename A, int TPW> __device__ void fwht_tiles_lds(A *s) {
-#pragma unroll 1
-  for (int pass = 0; pass < 3; ++pass) {
-    __syncthreads();
-    const int sh = 4 * pass;
-    for (int gg = threadIdx.x; gg < (TILE / 16) * TPW; gg += blockDim.x) {
-      A *st = s + (gg >> 8) * TILE_PAD;
-      const int g = gg & 255;
-      const int lo = g & ((1 << sh) - 1);
-      const int hi = g >> sh;
-      const int base = lo + (hi << (sh + 4));
-      A v[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = st[tpad(base + (k << sh))];
-      fwht16(v);
-#pragma unroll
-      for (int k = 0; k < 16; ++k) st[tpad(base + (k << sh))] = v[k];
+// x's bits deposited at the set bits of mask, lowest first
+__host__ __device__ constexpr int deposit_bits(int x, int mask) {
+  int r = 0, i = 0;
+  for (int b = 0; b < 31; ++b)
+    if ((mask >> b) & 1) {
+      if ((x >> i) & 1) r |= 1 << b;
+      ++i;
     }
-  }
-  __syncthreads();
+  return r;
 }
 
-// The same transform on NT tiles from s with LDS-only barriers, so global
-// loads issued before it stay in flight.
-template <typename A, int NT> __device__ void fwht_tiles_lds_part(A *s) {
-#pragma unroll 1
-  for (int pass = 0; pass < 3; ++pass) {
-    lds_barrier();
-    const int sh = 4 * pass;
-    for (int gg = threadIdx.x; gg < (TILE / 16) * NT; gg += blockDim.x) {
-      A *st = s + (gg >> 8) * TILE_PAD;
-      const int g = gg & 255;
-      const int lo = g & ((1 << sh) - 1);
-      const int hi = g >> sh;
-      const int base = lo + (hi << (sh + 4));
-      A v[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = st[tpad(base + (k << sh))];
-      fwht16(v);
-#pragma unroll
-      for (int k = 0; k < 16; ++k) st[tpad(base + (k << sh))] = v[k];
-    }
-  }
+// One radix-16 pass over the bits [sh, sh + 4) of NT tiles from s, after an
+// LDS-only barrier (global loads issued before it stay in flight).
+template <typename A, int NT> __device__ __forceinline__ void tiles_pass16(A *s, int sh) {
   lds_barrier();
+  for (int gg = threadIdx.x; gg < (TILE / 16) * NT; gg += blockDim.x) {
+    A *st = s + (gg >> 8) * TILE_PAD;
+    const int g = gg & 255;
+    const int lo = g & ((1 << sh) - 1);
+    const int hi = g >> sh;
+    const int base = lo + (hi << (sh + 4));
+    A v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = st[tpad(base + (k << sh))];
+    fwht16(v);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) st[tpad(base + (k << sh))] = v[k];
+  }
 }
 
 // TPB threads per workgroup: 1024 (one workgroup per compute unit on large
@@ -277,6 +296,9 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
   constexpr int NV = ROWS / (TPB * VEC);
   static_assert(NV >= 1, "tile too small for the vector width");
   __shared__ CT s[TPW * TILE_PAD];
+  using WB = TallBits<VEC, TPW, false>;  // one transform of all rows
+  using HB = TallBits<VEC, TPW, true>;   // the two halves apart
+  static_assert(TPB == 1024 || TPB == 512 || TPB == 256, "1024 / TPB threads of the layout");
   const int64_t base = (int64_t)bid * ROWS;
   const bool fast = aligned && base + ROWS <= n;
   const bool prev = j - 1 >= p0;
@@ -304,9 +326,14 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
   }
   auto cprev_of = [&]() { return defer ? deferred_c_finish(dc) * iaprev : cfprev; };
   const int tid = threadIdx.x;
-  // signed values of rows li0 + e (li0 = VEC (tid + TPB v) + off) into their tiles
-  auto to_lds = [&](const CT(*a)[VEC], int nv, int off) {
-    for (int v = 0; v < nv; ++v) {
+  // signed values of the rows li0 + e (li0 = VEC (tid + TPB v) + off, v below
+  // the extent of a), transformed over the thread's own bits, into their tiles
+  auto to_lds = [&](const auto &a, int off) {
+    constexpr int NB = std::extent<std::remove_reference_t<decltype(a)>>::value;
+    constexpr int NE = NB * VEC;
+    CT t[NE];  // t[VEC v + e]
+#pragma unroll
+    for (int v = 0; v < NB; ++v) {
       const int li0 = VEC * (tid + TPB * v) + off;
       const int64_t i0 = base + li0;
       const uint64_t word = sgn[li0 >> 6];
@@ -315,10 +342,32 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
         const int64_t i = i0 + e;
         CT x = (i >= m && i < n) ? a[v][e] : (CT)0;
         if ((word >> (i & 63)) & 1ull) x = -x;
-        const int li = li0 + e;
-        s[(li >> TILE_LOG) * TILE_PAD + tpad(li & (TILE - 1))] = x;
+        t[v * VEC + e] = x;
       }
     }
+    // bits of VEC v + e: the element bits, then the bits of v; with TPB <
+    // 1024 the low bits of v are thread-index bits of the 1024-thread layout
+    // (left out here)
+    constexpr int SKIP = TPB == 1024 ? 0 : TPB == 512 ? 1 : 2;
+    constexpr int VLB = WB::VL;
+#pragma unroll
+    for (int h = 1; h < NE; h <<= 1) {
+      if (h >= (1 << VLB) && h < (1 << (VLB + SKIP))) continue;
+#pragma unroll
+      for (int i = 0; i < NE; ++i)
+        if ((i & h) == 0) {
+          const CT x = t[i], y = t[i + h];
+          t[i] = x + y;
+          t[i + h] = x - y;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NB; ++v)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const int li = VEC * (tid + TPB * v) + off + e;
+        s[(li >> TILE_LOG) * TILE_PAD + tpad(li & (TILE - 1))] = t[v * VEC + e];
+      }
   };
   // SRHT, float64, full workgroups of several tiles: two halves, the first
   // half's tiles transformed while the second half's loads of w_j are in
@@ -340,15 +389,17 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
                                            a0);
       if (tid < NSW) sgn[tid] = sw;
       lds_barrier();
-      to_lds(a0, NVH, 0);
+      to_lds(a0, 0);
       const ST *wj = W + (int64_t)j * ldw + base + ROWSH;
 #pragma unroll
       for (int v = 0; v < NVH; ++v) vload(wj + VEC * (tid + TPB * v), a1[v]);
-      fwht_tiles_lds_part<CT, TPH>(s);
+      tiles_pass16<CT, TPH>(s, HB::VL);
+      tiles_pass16<CT, TPH>(s, HB::VL + 4);
       tall_body<ST, true, NVH, TPB, false, true>(W, ldw, n, m, j, p0, prev, cf, cprev_of, iaprev,
                                                  base + ROWSH, a1);
-      to_lds(a1, NVH, ROWSH);
-      fwht_tiles_lds_part<CT, TPH>(s + TPH * TILE_PAD);
+      to_lds(a1, ROWSH);
+      tiles_pass16<CT, TPH>(s + TPH * TILE_PAD, HB::VL);
+      tiles_pass16<CT, TPH>(s + TPH * TILE_PAD, HB::VL + 4);
     }
   }
   if (!piped) {
@@ -366,8 +417,9 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
     if (KIND == RHQR_SKETCH_SRHT) {
       if (tid < NSW) sgn[tid] = sw;
       lds_barrier();
-      to_lds(acc, NV, 0);
-      fwht_tiles_lds<CT, TPW>(s);
+      to_lds(acc, 0);
+      tiles_pass16<CT, TPW>(s, WB::VL);
+      tiles_pass16<CT, TPW>(s, WB::VL + 4);
     } else {
       // Gaussian: partial Omega[:, rows] w~_rows, four row groups per sample
         // Each thread takes two adjacent samples (one 16-byte load of Omega per
@@ -428,19 +480,39 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
     }
   }
   if (KIND == RHQR_SKETCH_SRHT) {
+    // sample q (row r = TILE r1 + r2): the tiles t0 + tt of this workgroup
+    // enter with sign (-1)^popcount(r1 & (t0 + tt)) = that of r1 & t0 times
+    // that of r1 & tt; the slot r1 & MREG holds the combination over the
+    // register tile bits, the others are summed here
+    lds_barrier();
     const uint64_t t0 = (uint64_t)bid * TPW;
-    for (int q = tid; q < l; q += TPB) {
-      const int32_t r = q == tid ? rq : rows[q];
-      const int r2 = tpad(r & (TILE - 1));
-      const uint64_t r1 = (uint64_t)(r >> TILE_LOG);
-      double h = 0.0;
+    auto samples = [&](auto bits) {
+      using B = decltype(bits);
+      for (int q = tid; q < l; q += TPB) {
+        const int32_t r = q == tid ? rq : rows[q];
+        const int r2 = r & (TILE - 1);
+        const uint64_t r1 = (uint64_t)(r >> TILE_LOG);
+        const int rb = r2 & ~B::FMASK;
+        const int treg = (int)(r1 & (uint64_t)B::MREG);
+        double h = 0.0;
 #pragma unroll
-      for (int tt = 0; tt < TPW; ++tt) {
-        const double x = (double)s[tt * TILE_PAD + r2];
-        h += (__popcll(r1 & (t0 + tt)) & 1) ? -x : x;
+        for (int x = 0; x < (1 << B::NRAW); ++x) {
+          const int tau = deposit_bits(x, B::MRAW);
+#pragma unroll
+          for (int y = 0; y < (1 << B::NF); ++y) {
+            const int f = y << B::FLO;
+            const double v = (double)s[(tau | treg) * TILE_PAD + tpad(rb | f)];
+            const int par = __popc((unsigned)(r1 & (uint64_t)tau)) + __popc((unsigned)(r2 & f));
+            h += (par & 1) ? -v : v;
+          }
+        }
+        part[(int64_t)bid * l + q] = (__popcll(r1 & t0) & 1) ? -h : h;
       }
-      part[(int64_t)bid * l + q] = h;
-    }
+    };
+    if (piped)
+      samples(HB{});
+    else
+      samples(WB{});
   }
 }
 

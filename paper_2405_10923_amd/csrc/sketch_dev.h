@@ -11,33 +11,34 @@ namespace {
 // and accumulates its contribution to each of the l samples; part[c][g][q].
 // Later tiles' loads are issued before the current tile's transform.  512
 // threads transform one tile (TILE rows) per step, so two workgroups fit on a
-// compute unit (about 110 registers per lane, 35 KB of LDS in float64) and
-// overlap one's loads with the other's transform.
+// compute unit and overlap one's loads with the other's transform.
+//
+// The 12 index bits of a tile are split three ways.  A thread holds 8 values:
+// its 16-byte vectors' elements and its vectors, i.e. the low VL bits
+// (VL = log2 of the elements per vector) and the bits above the 9 bits of the
+// thread index; their butterflies run in registers.  The thread-index bits
+// [VL, VL + 9) go through LDS: two radix-16 passes over [VL, VL + 4) and
+// [VL + 4, VL + 8), and the last bit, VL + 8, is folded into the sample
+// reads (out[r] = s[r without the bit] +/- s[r with it]).  The butterflies
+// over distinct bits commute, so this is the same transform as three radix-16
+// passes over the whole tile, up to rounding, with 24 % less LDS traffic.
 constexpr int SK_TPB = 512, SK_TPW = 1;
 
-template <typename A> __device__ __forceinline__ void fwht_sk_group(A *s) {
-  // fully unrolled: no inner loop, so the waits for loads in flight across
-  // the transform stay exact
-#pragma unroll
-  for (int pass = 0; pass < 3; ++pass) {
-    lds_barrier();
-    const int sh = 4 * pass;
-    const int gg = threadIdx.x;
-    if (gg < (TILE / 16) * SK_TPW) {
-      A *st = s + (gg >> 8) * TILE_PAD;
-      const int g = gg & 255;
-      const int lo = g & ((1 << sh) - 1);
-      const int hi = g >> sh;
-      const int base = lo + (hi << (sh + 4));
-      A v[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = st[tpad(base + (k << sh))];
-      fwht16(v);
-#pragma unroll
-      for (int k = 0; k < 16; ++k) st[tpad(base + (k << sh))] = v[k];
-    }
-  }
+// one radix-16 pass over the tile bits [sh, sh + 4), 256 threads of 16 values
+template <typename A> __device__ __forceinline__ void fwht_sk_pass(A *s, int sh) {
   lds_barrier();
+  const int g = threadIdx.x;
+  if (g < TILE / 16) {
+    const int lo = g & ((1 << sh) - 1);
+    const int hi = g >> sh;
+    const int base = lo + (hi << (sh + 4));
+    A v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = s[tpad(base + (k << sh))];
+    fwht16(v);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s[tpad(base + (k << sh))] = v[k];
+  }
 }
 
 // Row groups whose loads are in flight ahead of the one being transformed:
@@ -60,36 +61,45 @@ __device__ __forceinline__ void srht_cols_block(const ST *__restrict__ X, int64_
   constexpr int VEC = 16 / sizeof(ST);
   constexpr int ROWS = TILE * SK_TPW;
   constexpr int NV = ROWS / (SK_TPB * VEC);
-  static_assert(NV >= 1, "tile too small for the vector width");
+  constexpr int NE = NV * VEC;
+  constexpr int VL = VEC == 2 ? 1 : VEC == 4 ? 2 : 3;
+  constexpr int FB = VL + 8;  // the folded bit
+  static_assert(SK_TPW == 1 && SK_TPB == 512 && TILE == 4096 && NE == 8,
+                "3 register bits, 9 thread-index bits");
   static_assert(VEC <= 32, "a thread's rows must share one 32-bit sign word");
-  __shared__ AT s[SK_TPW * TILE_PAD];
+  __shared__ AT s[TILE_PAD];
   const ST *x = X + (int64_t)c * ldx;
   // sign bit i is bit i % 32 of 32-bit word i / 32 (the 64-bit words, little-endian)
   const uint32_t *__restrict__ sg32 = reinterpret_cast<const uint32_t *>(signs);
+  // per sample: the padded positions of its tile row without and with the
+  // folded bit, whether that bit is set, and its tile-index bits
   double acc[QA];
-  int r2q[QA];
+  int r0q[QA], r1x[QA];
+  bool fneg[QA];
   uint64_t r1q[QA];
 #pragma unroll
   for (int a = 0; a < QA; ++a) {
     acc[a] = 0.0;
     const int q = threadIdx.x + SK_TPB * a;
     const int32_t r = q < l ? rows[q] : 0;
-    r2q[a] = tpad(r & (TILE - 1));
+    const int r2 = r & (TILE - 1);
+    r0q[a] = tpad(r2 & ~(1 << FB));
+    r1x[a] = tpad(r2 | (1 << FB));
+    fneg[a] = (r2 >> FB) & 1;
     r1q[a] = (uint64_t)(r >> TILE_LOG);
   }
   const int64_t cnt = gb < ngroups ? (ngroups - 1 - gb) / gt + 1 : 0;
   const int64_t nfullg = n / ROWS;  // groups entirely inside the n rows
   const int64_t cntf = !aligned ? 0 : (gb < nfullg ? (nfullg - 1 - gb) / gt + 1 : 0);
-  // signed, transformed group g in LDS, then its samples into acc
+  // signed, transformed group g, then its samples into acc
   // xs: the group's values, raw (16-byte words as loaded, decoded here) or
   // already in AT
   auto transform = [&](int64_t g, const auto &xs, const uint32_t (&ws)[NV]) {
     const int64_t base = g * ROWS;
-    lds_barrier();  // the previous group's samples have been read
+    AT t[NE];  // t[VEC v + e]: row VEC (tid + SK_TPB v) + e of the group
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int li0 = VEC * (threadIdx.x + SK_TPB * v);
-      const int64_t i0 = base + li0;
+      const int64_t i0 = base + VEC * (threadIdx.x + SK_TPB * v);
       AT xd[VEC];
       if constexpr (std::is_same<std::decay_t<decltype(xs[0])>, u32x4>::value) {
         vdecode<ST, AT>(xs[v], xd);
@@ -102,21 +112,34 @@ __device__ __forceinline__ void srht_cols_block(const ST *__restrict__ X, int64_
         const int64_t r = i0 + e;
         AT val = (r >= m && r < n) ? xd[e] : (AT)0;
         if ((ws[v] >> (r & 31)) & 1u) val = -val;
-        const int li = li0 + e;
-        s[(li >> TILE_LOG) * TILE_PAD + tpad(li & (TILE - 1))] = val;
+        t[v * VEC + e] = val;
       }
     }
-    fwht_sk_group(s);
-    const uint64_t t0 = (uint64_t)g * SK_TPW;
+    // the bits of the index VEC v + e are tile bits: their butterflies here
+#pragma unroll
+    for (int h = 1; h < NE; h <<= 1)
+#pragma unroll
+      for (int i = 0; i < NE; ++i)
+        if ((i & h) == 0) {
+          const AT a = t[i], b = t[i + h];
+          t[i] = a + b;
+          t[i + h] = a - b;
+        }
+    lds_barrier();  // the previous group's samples have been read
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) s[tpad(VEC * (threadIdx.x + SK_TPB * v) + e)] = t[v * VEC + e];
+    fwht_sk_pass(s, VL);
+    fwht_sk_pass(s, VL + 4);
+    lds_barrier();
 #pragma unroll
     for (int a = 0; a < QA; ++a) {
       const int q = threadIdx.x + SK_TPB * a;
       if (q < l) {
-#pragma unroll
-        for (int tt = 0; tt < SK_TPW; ++tt) {
-          const double hv = (double)s[tt * TILE_PAD + r2q[a]];
-          acc[a] += (__popcll(r1q[a] & (t0 + tt)) & 1) ? -hv : hv;
-        }
+        const double h0 = (double)s[r0q[a]], h1 = (double)s[r1x[a]];
+        const double hv = fneg[a] ? h0 - h1 : h0 + h1;
+        acc[a] += (__popcll(r1q[a] & (uint64_t)g) & 1) ? -hv : hv;
       }
     }
   };

@@ -219,7 +219,9 @@ def test_padded_leading_dimension_f64(pad, panel, outer):
     for k in ("R", "S", "T"):
         assert rel(to_np(out[k]), ref[k]) < 1e-12, k
     assert rel(to_np(Wd), ref["U"]) < 1e-12
-    assert rel(to_np(out["Q"]), orq.thin_q(ref["U"], ref["T"], m)) < 1e-12
+    # Q is formed from U and T: its forward error grows with cond(W) (1e3
+    # here, 1e2 in the element-wise tests, whose bound is 1e-12)
+    assert rel(to_np(out["Q"]), orq.thin_q(ref["U"], ref["T"], m)) < 1e-11
 
 
 @pytest.mark.parametrize("dt", ["float32", "float16", "bfloat16"])
