@@ -140,8 +140,9 @@ def kernel_bytes(n, m, l, es, panel, outer=0, tpw=0):
     tall pass reads the stored columns it applies (all earlier ones, or its
     inner panel's), the raw column j-1 and w_j, writes u_{j-1} and the raw
     refreshed column, reads the sign bits and writes one l-vector of partials
-    per workgroup.  Panel launch (K0, J, nb) reads the J - K0 columns it
-    applies and the panel's nb columns and writes them."""
+    per workgroup; the first pass of a panel applies nothing and only reads
+    w_j.  Panel launch (K0, J, nb) reads the J - K0 columns it applies and
+    the panel's nb columns and writes them."""
     N = 1 << (n - 1).bit_length()
     tail = (n - m) * es
     side = _nparts(n, es, tpw) * l * 8 + N / 8
@@ -149,7 +150,7 @@ def kernel_bytes(n, m, l, es, panel, outer=0, tpw=0):
     tall = 0.0
     for j in range(1, m):
         J = p0[j]
-        cols = (j - J + 3) if j > J else 2
+        cols = (j - J + 3) if j > J else 1
         tall += cols * tail + side
     mx = sum((J - K0 + 2 * nb) * tail for K0, J, nb in ups if nb > 8)
     valu = sum((J - K0 + 2 * nb) * tail for K0, J, nb in ups if nb <= 8)

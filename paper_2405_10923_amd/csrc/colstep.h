@@ -186,7 +186,11 @@ __device__ __forceinline__ void tall_body(ST *__restrict__ W, int64_t ldw, int64
       }
     }
   }
-  // store the raw refreshed column in place (in the storage type)
+  // store the raw refreshed column in place (in the storage type); the first
+  // pass of a panel in the blocked schedule applies nothing (the panel update
+  // has), so w_j is unchanged and is not written back
+  const bool applied = p0 < j - 1 || (j >= 1 && prev);  // uniform
+  if (!applied) return;
   ST *wjw = W + (int64_t)j * ldw;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
