@@ -119,8 +119,10 @@ __global__ void k_zero_mat(double *A, int64_t lda, int32_t rows, int32_t cols) {
 
 // ------------------------------------------- sketch-space Householder QR
 // Householder QR of the small L x m float64 sketch Z (overwritten),
-// right-looking in panels of NB columns (16, or 8 for sketches of more than
-// 1024 rows), two launches per panel.
+// right-looking in panels of NB = 8 columns, two launches per panel.  (The
+// column steps are unrolled per panel column: panels of 16 make four times the
+// straight-line code per launch and measured 3 % slower per call at
+// 2^20 x 128, l = 512, for half the launches.)
 // k_hqr_panel (one workgroup of HQ_TPB threads) factors the panel one column
 // at a time (RHVector with Psi = I, Alg. 2: sigma, rho, gamma, alpha, beta;
 // identity reflector when rho = 0) with the panel in registers: thread t holds
@@ -141,8 +143,6 @@ constexpr int HQ_W = HQ_TPB / 64;
 constexpr int SQ_MAXL = 2048;  // L + m at most on this path (else the column engine)
 constexpr int SQ_MAXM = 1024;  // largest m (recrhqr_factor rejects larger)
 
-// panel width for an L-row sketch: 16 while the panel fits 4 rows per thread
-inline int hqr_nb(int32_t L) { return L <= 4 * HQ_TPB ? 16 : 8; }
 
 // f(integral_constant<int, I>) for I = B .. E-1, in order
 template <int B, int E, typename F> __device__ __forceinline__ void static_for(F &&f) {
@@ -585,7 +585,6 @@ int hqr_run(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, double *T,
   for (int32_t J = 0; J < m; J += NB) {
     const int32_t nb = m - J < NB ? m - J : NB;
     const int rpt = (L - J + HQ_TPB - 1) / HQ_TPB;
-    if (NB == 16 && rpt > 4) return RHQR_ERR_UNSUPPORTED;
     int rc = hqr_panel_launch<NB>(rpt, L, m, J, Zc, S, lds, T, ldt, R, ldr, status, st);
     if (rc) return rc;
     const int ntrail = m - J - nb;
@@ -624,8 +623,6 @@ int sketch_space_hqr(int32_t L, int32_t m, double *Zc, double *S, int64_t lds, d
   hipLaunchKernelGGL(k_zero_mat, dim3((m + 255) / 256, m), dim3(256), 0, st, T, ldt, m, m);
   RHQR_HIP(hipGetLastError());
   if (L + m <= SQ_MAXL) {  // the panel in registers; two launches per panel
-    if (hqr_nb(L) == 16)
-      return hqr_run<16>(L, m, Zc, S, lds, T, ldt, R, ldr, X0, X1, w.status, st);
     return hqr_run<8>(L, m, Zc, S, lds, T, ldt, R, ldr, X0, X1, w.status, st);
   }
   LoopArgs a;
