@@ -237,8 +237,11 @@ __global__ void __launch_bounds__(HQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
         dg[c] = -sigma * rho;
         flags[c] = (ident ? 1 : 0) | (!(isfinite(ss) && isfinite(yj)) ? 2 : 0);
       }
-      // H_j = I - beta s_j s_j^t on the panel's later columns (rows >= c)
-      if (c + 1 < nb) {  // uniform
+      // H_j = I - beta s_j s_j^t on the panel's later columns (rows >= c),
+      // and g_{q,c} = s_q^t s_c for the earlier ones (final since their own
+      // steps; s_c is zero above its pivot), which T_pp needs: the products
+      // with every panel column over rows >= c, reduced together
+      if (c > 0 || c + 1 < nb) {  // uniform
         double d[NB];
 #pragma unroll
         for (int q = 0; q < NB; ++q) d[q] = 0.0;
@@ -247,14 +250,14 @@ __global__ void __launch_bounds__(HQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
           const int r = tid + HQ_TPB * i;
           if (r >= c && r < rows) {
 #pragma unroll
-            for (int q = c + 1; q < NB; ++q) d[q] += P[i][c] * P[i][q];
+            for (int q = 0; q < NB; ++q)
+              if (q != c) d[q] += P[i][c] * P[i][q];
           }
         }
         // wave sums eight columns at a time: lane L holds the sum of column
         // 8 h + (L >> 3) of group h
 #pragma unroll
         for (int h = 0; h < NB / 8; ++h) {
-          if (8 * h + 7 <= c) continue;  // no later column in this group (uniform)
           double v8[8];
 #pragma unroll
           for (int k = 0; k < 8; ++k) v8[k] = d[8 * h + k];
@@ -267,6 +270,7 @@ __global__ void __launch_bounds__(HQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
         double sq = 0.0;
 #pragma unroll
         for (int k = 0; k < HQ_W; ++k) sq += red[b][k][lane & (NB - 1)];
+        if (w == 0 && lane < c) gp[lane][c] = sq;
 #pragma unroll
         for (int q = c + 1; q < NB; ++q) {
           const double g = beta * lane_read(sq, q);
@@ -303,48 +307,7 @@ __global__ void __launch_bounds__(HQ_TPB) k_hqr_panel(int32_t L, int32_t m, int3
       if (flags[c] & 2) atomicCAS(status + 1, 0, J + c + 1);
     }
   }
-  // T_pp: g_{q,c} = s_q^t s_c over rows >= c (s_c is zero above its pivot)
-  // for the NP = NB (NB - 1) / 2 pairs q < c (pair k = c (c - 1) / 2 + q),
-  // from the registers: per-thread partial sums, eight pairs per wave
-  // butterfly, then the waves in order
-  constexpr int NP = NB * (NB - 1) / 2;
-  constexpr int NP8 = (NP + 7) / 8;
-  __shared__ double gred[HQ_W][NP8 * 8];
-  static_for<0, NP8>([&](auto hh) {
-    constexpr int h = decltype(hh)::value;
-    double v8[8];
-    static_for<0, 8>([&](auto kk) {
-      constexpr int k = 8 * h + decltype(kk)::value;
-      constexpr int c = [] {
-        int cc = 1, first = 0;
-        while (first + cc <= k) first += cc++;
-        return cc;
-      }();
-      constexpr int q = k - c * (c - 1) / 2;
-      double acc = 0.0;
-      if constexpr (k < NP) {
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-          const int r = tid + HQ_TPB * i;
-          if (r >= c && r < rows) acc += P[i][q] * P[i][c];
-        }
-      }
-      v8[decltype(kk)::value] = acc;
-    });
-    const double tot = wave_sum8(v8);
-    if ((lane & 7) == 0) gred[w][8 * h + (lane >> 3)] = tot;
-  });
-  __syncthreads();
-  if (tid < NP) {
-    int cc = 1;
-    while (cc * (cc + 1) / 2 <= tid) ++cc;  // pair tid = cc (cc - 1) / 2 + qq
-    const int qq = tid - cc * (cc - 1) / 2;
-    double v = 0.0;
-#pragma unroll
-    for (int k2 = 0; k2 < HQ_W; ++k2) v += gred[k2][tid];
-    gp[qq][cc] = v;
-  }
-  __syncthreads();
+  __syncthreads();  // g_{q,c} of the last steps
   // row q of T_pp on lane q: T_qq = beta_q, T_qc = -beta_c sum_{q <= k < c} T_qk g_kc
   if (w == 0 && lane < nb) {
     const int q = lane;
