@@ -1454,11 +1454,16 @@ __global__ void __launch_bounds__(TM_WAVES * 64) k_trsm_mx(const ST *__restrict_
       // forward substitution over the diagonal block: column c (held by lane
       // group gc, register tc) is scaled by 1 / M_cc, broadcast to the row's
       // other lane groups and removed from their later columns
+      // (each lane scales its own column's value by that column's reciprocal
+      // before the broadcast, so no step waits on a load of it)
       const double *md = Mq + 16 * b * LDP + 16 * b;
       const double *iv = Mq + MC * LDP + 16 * b;
-      CT cf[4], cn[4];
+      CT cf[4], cn[4], ivr[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) cf[t] = (CT)md[Ops::di(g, t)];
+      for (int t = 0; t < 4; ++t) {
+        cf[t] = (CT)md[Ops::di(g, t)];
+        ivr[t] = (CT)iv[Ops::di(g, t)];
+      }
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
         int gc = 0, tc = 0;
@@ -1474,9 +1479,8 @@ __global__ void __launch_bounds__(TM_WAVES * 64) k_trsm_mx(const ST *__restrict_
 #pragma unroll
           for (int t = 0; t < 4; ++t) cn[t] = (CT)md[(c + 1) * LDP + Ops::di(g, t)];
         }
-        const CT icv = (CT)iv[c];
         __builtin_amdgcn_sched_barrier(0);
-        const CT xc = __shfl(x[b][tc] * icv, 16 * gc + r, 64);
+        const CT xc = __shfl(x[b][tc] * ivr[tc], 16 * gc + r, 64);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int col = Ops::di(g, t);
