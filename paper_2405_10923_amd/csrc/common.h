@@ -312,9 +312,9 @@ template <> struct PxOps<float> {
 // (U and P may be columns of one array that do not overlap).
 
 // ---------------------------------------------------------------- FWHT
-// In-place unnormalised Walsh-Hadamard transform (natural order) of TILE
-// values held in LDS at padded positions tpad(i).  Three radix-16 passes over
-// bit groups [0,4), [4,8), [8,12); each of 256 threads owns one group of 16.
+// In-place unnormalised Walsh-Hadamard transform (natural order) of 16
+// values: the radix-16 step of the tile transforms, which run it over groups
+// of 16 entries of a tile in LDS (4 index bits per pass).
 template <typename A> __device__ __forceinline__ void fwht16(A v[16]) {
 #pragma unroll
   for (int h = 1; h < 16; h <<= 1) {
@@ -327,30 +327,6 @@ template <typename A> __device__ __forceinline__ void fwht16(A v[16]) {
       }
     }
   }
-}
-
-template <typename A> __device__ void fwht_tile_lds(A *s) {
-#pragma unroll 1
-  for (int pass = 0; pass < 3; ++pass) {
-    __syncthreads();
-    const int sh = 4 * pass;
-    for (int g = threadIdx.x; g < TILE / 16; g += blockDim.x) {
-      const int lo = g & ((1 << sh) - 1);
-      const int hi = g >> sh;
-      const int base = lo + (hi << (sh + 4));
-      A v[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = s[tpad(base + (k << sh))];
-      fwht16(v);
-#pragma unroll
-      for (int k = 0; k < 16; ++k) s[tpad(base + (k << sh))] = v[k];
-    }
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ bool sign_bit(const uint64_t *signs, int64_t i) {
-  return (signs[i >> 6] >> (i & 63)) & 1ull;
 }
 
 // ---------------------------------------------------------------- host side
