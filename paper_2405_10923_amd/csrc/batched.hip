@@ -142,8 +142,13 @@ __global__ void __launch_bounds__(PTRI_WAVES * 64) kb_ptri(const ColProblem *__r
             local * PTRI_WAVES + (threadIdx.x >> 6), blockIdx.y);
 }
 
+// workgroups per compute unit kb_panel is built for: those of the matrix-core
+// update, except for 2-byte storage, whose vector-unit update of wide panels
+// would spill at that register budget
+template <typename ST> constexpr int kb_panel_min_wg() { return sizeof(ST) == 2 ? 1 : px_min_wg<ST>(); }
+
 template <typename ST>
-__global__ void __launch_bounds__(PANEL_TPB) kb_panel(const ColProblem *__restrict__ P,
+__global__ void __launch_bounds__(PANEL_TPB, kb_panel_min_wg<ST>()) kb_panel(const ColProblem *__restrict__ P,
                                                       const BlockMap *__restrict__ map, int32_t K0,
                                                       int32_t J, int32_t width) {
   const BlockMap b = map[blockIdx.x];

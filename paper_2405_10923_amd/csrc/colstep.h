@@ -1295,12 +1295,20 @@ __device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int
 // of U; element e of every lane forms one 16-row operand (rows VEC j + e).
 // The accumulators start from the panel itself (same layout, 16-byte loads)
 // and are stored back as they are.  A wave owns px_rg groups of 16 VEC rows;
-// PX_KS steps of 4 columns (U as raw 16-byte words, and -C) are loaded
+// px_ks steps of 4 columns (U as raw 16-byte words, and -C) are loaded
 // together ahead of their products.  Waves that cross row m or n take guarded
 // element accesses; rows < m are never written.  Needs 16-byte aligned
 // columns.
-constexpr int PX_KS = 4;     // 4-column steps loaded together
-constexpr int PX_WAVES = 4;  // waves per workgroup
+// Per storage type, the 4-column steps loaded together and the workgroups per
+// compute unit the kernels are built for: float32 and 2-byte data run with 4
+// waves per SIMD (accumulators in ordinary registers) and one step per batch
+// (float32, 2^22 rows, 32 columns: 0.61 against 0.64 ms per outer update; the
+// batch's 16-column updates 12 % faster); float64 keeps 4 steps per batch and
+// the register budget of 2-3 waves per SIMD (accumulators in AGPRs), which
+// measured 2.5 % faster than 4 waves in the factorization.
+template <typename ST> constexpr int px_ks() { return sizeof(ST) == 8 ? 4 : 1; }
+template <typename ST> constexpr int px_min_wg() { return sizeof(ST) == 8 ? 1 : 4; }
+constexpr int PX_WAVES = 4;   // waves per workgroup
 constexpr int PX_MIN_NB = 8; // narrower panels stay on the vector units (k_panel)
 // row groups of 16 VEC rows per wave: 64 rows (float64) or 128 rows
 __host__ __device__ constexpr int px_rg(int es) { return es == 2 ? 1 : 2; }
@@ -1358,11 +1366,12 @@ __device__ __forceinline__ void panel_mx_wave(const ST *__restrict__ U, int64_t 
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[g][e][ct][t] = x[e];
       }
-  for (int k0 = K0; k0 < K1; k0 += 4 * PX_KS) {
-    u32x4 ub[PX_KS][RG];
-    CT cf[PX_KS][NCT];
+  constexpr int KS = px_ks<ST>();
+  for (int k0 = K0; k0 < K1; k0 += 4 * KS) {
+    u32x4 ub[KS][RG];
+    CT cf[KS][NCT];
 #pragma unroll
-    for (int s = 0; s < PX_KS; ++s) {
+    for (int s = 0; s < KS; ++s) {
       const int k = k0 + 4 * s + kq;
       const bool kv = k < K1;
       const int kc = kv ? k : K1 - 1;  // clamped: every load is in bounds
@@ -1378,7 +1387,7 @@ __device__ __forceinline__ void panel_mx_wave(const ST *__restrict__ U, int64_t 
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int s = 0; s < PX_KS; ++s) {
+    for (int s = 0; s < KS; ++s) {
       // a column beyond J contributes zero coefficients; its (clamped) values
       // are zeroed too, so no non-finite entry can enter the sum
       const bool kv = k0 + 4 * s + kq < K1;

@@ -842,7 +842,7 @@ void launch_panel(ST *W, int64_t ldw, int64_t n, int32_t m, int32_t K0, int32_t 
 
 // W[m:n, J:J+nb] -= U[m:n, K0:J] C_{K0:J} on matrix cores (float64 / float32)
 template <typename ST, int NC>
-__global__ void __launch_bounds__(PX_WAVES * 64) k_panel_mx(ST *__restrict__ W, int64_t ldw,
+__global__ void __launch_bounds__(PX_WAVES * 64, px_min_wg<ST>()) k_panel_mx(ST *__restrict__ W, int64_t ldw,
                                                             int64_t n, int32_t m, int32_t K0,
                                                             int32_t J, int32_t nb, int pw,
                                                             const double *__restrict__ C) {
@@ -1004,7 +1004,7 @@ __global__ void k_a5_head(int32_t m, int32_t K, int32_t kb, int32_t J, int32_t n
 
 // W[m:n, J:J+nb] -= U[m:n, K:K+kb] C_{K:K+kb}: matrix cores, or vector units
 template <typename ST, int NC>
-__global__ void __launch_bounds__(PX_WAVES * 64) k_a5_panel_mx(ST *__restrict__ W, int64_t ldw,
+__global__ void __launch_bounds__(PX_WAVES * 64, px_min_wg<ST>()) k_a5_panel_mx(ST *__restrict__ W, int64_t ldw,
                                                                int64_t n, int32_t m, int32_t K,
                                                                int32_t kb, int32_t J, int32_t nb,
                                                                int pw,
