@@ -137,14 +137,19 @@ __device__ __forceinline__ void vload(const ST *p, CT *o) {
   u.y = uv.y;
   u.z = uv.z;
   u.w = uv.w;
+  // (the whole vector reinterpreted at once: rebuilding each value from its
+  // two words let the compiler re-load the first one with a narrower load of
+  // the same address)
   if constexpr (sizeof(ST) == 8) {
-    o[0] = (CT)__hiloint2double((int)u.y, (int)u.x);
-    o[1] = (CT)__hiloint2double((int)u.w, (int)u.z);
+    const f64x2 d = __builtin_bit_cast(f64x2, u);
+    o[0] = (CT)d.x;
+    o[1] = (CT)d.y;
   } else if constexpr (sizeof(ST) == 4) {
-    o[0] = (CT)__uint_as_float(u.x);
-    o[1] = (CT)__uint_as_float(u.y);
-    o[2] = (CT)__uint_as_float(u.z);
-    o[3] = (CT)__uint_as_float(u.w);
+    const f32x4 f = __builtin_bit_cast(f32x4, u);
+    o[0] = (CT)f.x;
+    o[1] = (CT)f.y;
+    o[2] = (CT)f.z;
+    o[3] = (CT)f.w;
   } else {
     const uint32_t w[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
@@ -165,14 +170,19 @@ __device__ __forceinline__ u32x4 vraw_nt(const void *p) {
 }
 template <typename ST, typename CT>
 __device__ __forceinline__ void vdecode(const u32x4 u, CT *o) {
+  // (the whole vector reinterpreted at once: rebuilding each value from its
+  // two words let the compiler re-load the first one with a narrower load of
+  // the same address)
   if constexpr (sizeof(ST) == 8) {
-    o[0] = (CT)__hiloint2double((int)u.y, (int)u.x);
-    o[1] = (CT)__hiloint2double((int)u.w, (int)u.z);
+    const f64x2 d = __builtin_bit_cast(f64x2, u);
+    o[0] = (CT)d.x;
+    o[1] = (CT)d.y;
   } else if constexpr (sizeof(ST) == 4) {
-    o[0] = (CT)__uint_as_float(u.x);
-    o[1] = (CT)__uint_as_float(u.y);
-    o[2] = (CT)__uint_as_float(u.z);
-    o[3] = (CT)__uint_as_float(u.w);
+    const f32x4 f = __builtin_bit_cast(f32x4, u);
+    o[0] = (CT)f.x;
+    o[1] = (CT)f.y;
+    o[2] = (CT)f.z;
+    o[3] = (CT)f.w;
   } else {
     const uint32_t w[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
