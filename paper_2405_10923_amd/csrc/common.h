@@ -100,68 +100,8 @@ inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // -------------------------------------------------------------- 16-byte I/O
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// 16-byte load decoded to CT; NT selects a non-temporal (streaming) load.
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-template <typename ST, typename CT, bool NT = false>
-__device__ __forceinline__ void vload(const ST *p, CT *o) {
-  if constexpr (sizeof(ST) == 8) {
-    f64x2 d;
-    if constexpr (NT)
-      d = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p));
-    else
-      d = *reinterpret_cast<const f64x2 *>(p);
-    o[0] = (CT)d.x;
-    o[1] = (CT)d.y;
-    return;
-  } else if constexpr (std::is_same<ST, float>::value) {
-    f32x4 f;
-    if constexpr (NT)
-      f = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
-    else
-      f = *reinterpret_cast<const f32x4 *>(p);
-    o[0] = (CT)f.x;
-    o[1] = (CT)f.y;
-    o[2] = (CT)f.z;
-    o[3] = (CT)f.w;
-    return;
-  }
-  u32x4 uv;
-  if constexpr (NT)
-    uv = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
-  else
-    uv = *reinterpret_cast<const u32x4 *>(p);
-  uint4 u;
-  u.x = uv.x;
-  u.y = uv.y;
-  u.z = uv.z;
-  u.w = uv.w;
-  // (the whole vector reinterpreted at once: rebuilding each value from its
-  // two words let the compiler re-load the first one with a narrower load of
-  // the same address)
-  if constexpr (sizeof(ST) == 8) {
-    const f64x2 d = __builtin_bit_cast(f64x2, u);
-    o[0] = (CT)d.x;
-    o[1] = (CT)d.y;
-  } else if constexpr (sizeof(ST) == 4) {
-    const f32x4 f = __builtin_bit_cast(f32x4, u);
-    o[0] = (CT)f.x;
-    o[1] = (CT)f.y;
-    o[2] = (CT)f.z;
-    o[3] = (CT)f.w;
-  } else {
-    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const unsigned short b = (unsigned short)(w[k >> 1] >> (16 * (k & 1)));
-      if constexpr (std::is_same<ST, __half>::value)
-        o[k] = (CT)__half2float(__ushort_as_half(b));
-      else
-        o[k] = (CT)__uint_as_float(((uint32_t)b) << 16);
-    }
-  }
-}
 
 // Raw 16-byte non-temporal load and its decoding, for loops that issue a batch
 // of loads before converting any of them.
@@ -194,6 +134,38 @@ __device__ __forceinline__ void vdecode(const u32x4 u, CT *o) {
         o[k] = (CT)__uint_as_float(((uint32_t)b) << 16);
     }
   }
+}
+
+// 16-byte load decoded to CT; NT selects a non-temporal (streaming) load.
+template <typename ST, typename CT, bool NT = false>
+__device__ __forceinline__ void vload(const ST *p, CT *o) {
+  if constexpr (sizeof(ST) == 8) {
+    f64x2 d;
+    if constexpr (NT)
+      d = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p));
+    else
+      d = *reinterpret_cast<const f64x2 *>(p);
+    o[0] = (CT)d.x;
+    o[1] = (CT)d.y;
+    return;
+  } else if constexpr (std::is_same<ST, float>::value) {
+    f32x4 f;
+    if constexpr (NT)
+      f = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
+    else
+      f = *reinterpret_cast<const f32x4 *>(p);
+    o[0] = (CT)f.x;
+    o[1] = (CT)f.y;
+    o[2] = (CT)f.z;
+    o[3] = (CT)f.w;
+    return;
+  }
+  u32x4 uv;  // 2-byte storage
+  if constexpr (NT)
+    uv = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+  else
+    uv = *reinterpret_cast<const u32x4 *>(p);
+  vdecode<ST, CT>(uv, o);
 }
 
 template <typename ST> __device__ __forceinline__ unsigned short enc16(float v) {
