@@ -1299,15 +1299,20 @@ __device__ __forceinline__ void panel_block(ST *__restrict__ W, int64_t ldw, int
 // together ahead of their products.  Waves that cross row m or n take guarded
 // element accesses; rows < m are never written.  Needs 16-byte aligned
 // columns.
-// Per storage type, the 4-column steps loaded together and the workgroups per
-// compute unit the kernels are built for: float32 and 2-byte data run with 4
-// waves per SIMD (accumulators in ordinary registers) and one step per batch
-// (float32, 2^22 rows, 32 columns: 0.61 against 0.64 ms per outer update; the
-// batch's 16-column updates 12 % faster); float64 keeps 4 steps per batch and
-// the register budget of 2-3 waves per SIMD (accumulators in AGPRs), which
-// measured 2.5 % faster than 4 waves in the factorization.
-template <typename ST> constexpr int px_ks() { return sizeof(ST) == 8 ? 4 : 1; }
-template <typename ST> constexpr int px_min_wg() { return sizeof(ST) == 8 ? 1 : 4; }
+// The panel updates (NC <= 32) load one 4-column step per batch and are built
+// for PX_MIN_WG workgroups per compute unit (4 waves per SIMD, accumulators
+// in ordinary registers).  Measured at 2^22 rows against 4 steps per batch at
+// 2-3 waves per SIMD (accumulators in AGPRs): float32 outer updates 0.64 ->
+// 0.61 ms, the float32 batch's 16-column updates 3.03 -> 2.43 ms per launch,
+// float64 outer updates 1.198 -> 1.185 ms.  The thin Q's 64-column tail
+// product keeps 4 steps per batch in float64, where its FP64 matrix cores
+// bound it (with one step: 13.3 ms against 9.8 ms at 2^22 x 256), and takes
+// one in float32 (the 512-problem batch's thin Q: 15.3 ms against 18.0 ms).
+template <typename ST, int NC> constexpr int px_ks() {
+  return NC > 32 && sizeof(ST) == 8 ? 4 : 1;
+}
+constexpr int PX_MIN_WG = 4;
+template <typename ST> constexpr int px_min_wg() { return PX_MIN_WG; }
 constexpr int PX_WAVES = 4;   // waves per workgroup
 constexpr int PX_MIN_NB = 8; // narrower panels stay on the vector units (k_panel)
 // row groups of 16 VEC rows per wave: 64 rows (float64) or 128 rows
@@ -1366,7 +1371,7 @@ __device__ __forceinline__ void panel_mx_wave(const ST *__restrict__ U, int64_t 
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[g][e][ct][t] = x[e];
       }
-  constexpr int KS = px_ks<ST>();
+  constexpr int KS = px_ks<ST, NC>();
   for (int k0 = K0; k0 < K1; k0 += 4 * KS) {
     u32x4 ub[KS][RG];
     CT cf[KS][NCT];
