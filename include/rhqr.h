@@ -134,7 +134,8 @@ RHQR_API int rhqr_sketch(rhqr_sketch_t h, int dtype, int64_t n, int32_t k, const
  *           column is kept.  Bits 24-27: transform tiles of 4096 rows per
  *           workgroup of the refresh + re-sketch pass, 0 (chosen from n), 1, 2
  *           or 4 (at least 2 for 2-byte storage): a tuning knob, the results
- *           differ only in the summation order of the sketch partials.
+ *           differ only in the order of the transform's butterflies over the
+ *           tile index and the summation order of the sketch partials.
  *           Bit 28: block RHQR exactly as Alg. 5 writes it, with blocks of b
  *           = bits 8-15 columns (1 <= b <= 32, outer width 0): before each
  *           block is factored (Alg. 4 over its columns, refresh coefficients
@@ -376,7 +377,9 @@ RHQR_API int rhqr_spmv_csr(int dtype, int64_t n, const int64_t *d_ptr, const int
  *     (on the batch's own stream) and the graph is launched on `stream`; later
  *     calls replay it.  Each problem's U, S, T, R equal those of rhqr_factor
  *     with the same schedule bitwise (same device code, same choice of
- *     matrix cores or vector units per panel, same reduction orders).
+ *     matrix cores or vector units per panel, same reduction orders), given
+ *     the batch's transform tiles per workgroup (1; 2 for 2-byte storage:
+ *     rhqr_factor's own choice below 2^21 rows, else opts bits 24-27).
  *   rhqr_batch_thin_q: after rhqr_batch_factor (on the same stream), the
  *     thin Q of every problem i with d_Q[i] != NULL: Q_i = [I_m; 0] -
  *     U_i T_i U_{i,1}^t (Sec. 3.2), n_i x m_i in the batch dtype, column-major

@@ -375,7 +375,8 @@ __device__ __forceinline__ void tall_block(const ColProblem &P, int32_t j, int32
   };
   // SRHT, float64, full workgroups of several tiles: two halves, the first
   // half's tiles transformed while the second half's loads of w_j are in
-  // flight (the same arithmetic per row and per tile as the one-pass order;
+  // flight (the same refresh arithmetic per row as the one-pass order; the
+  // halves' top bit joins the sample reads instead of the registers;
   // narrower types, with one or two vectors per thread and half, measured
   // slower this way)
   constexpr bool PIPE =
